@@ -1,0 +1,27 @@
+"""FP64 CPU oracle for the spline geometric Maxwell leapfrog (scheme 2).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import anything from this package.  The
+product path (``paper_2302_04979_amd``) never imports it and shares no code with
+it: the two sides meet only through the seeded input generators in
+``workloads``.
+
+The oracle is written plainly from the paper, in FP64 with NumPy/SciPy
+primitives (matrix products, dense LU), with no blocking or fusion:
+
+* ``splines``   - knot vectors, B-spline and Curry-Schoenberg bases, Gauss rules,
+                  1D incidence matrices, 1D pairing matrices G^ and M^
+                  (Section 2.3; Section 4.1).
+* ``geometry``  - maps F of the unit cube and the 2-form metric factor
+                  DF^T DF / (gamma det DF) (Section 2.3 pullbacks).
+* ``assembly``  - level 0, the plain definitions: 3D pairing matrices K1, K~1
+                  by 3D quadrature, mass matrices by element loops, sparse curls
+                  (Sections 2.4, 3.4).
+* ``scheme``    - level 1, the structured method: per-axis Kronecker solves
+                  (eq. (4.4), (4.5)), sum-factorised mass applies, the explicit
+                  leapfrog of (3.10)-(3.13) in its (e, h) Petrov-Galerkin form,
+                  energies, CFL, projections, point sources and probes.
+
+Every function pinned by tests under ``-m "not gpu"``; see the design doc for the
+pins, and for the readings taken where the paper is silent.
+"""

@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs for the spline Maxwell leapfrog workloads.
+
+This module is shared by the FP64 oracle and by the HIP path.  It only draws
+random numbers and evaluates the analytic *input* fields (cavity modes, the
+deformed-cube parameters, dipole and probe placements); it holds none of the
+discretisation's arithmetic (no bases, quadrature, Hodge or pairing matrices).
+
+Workloads follow the numerical experiments of the paper (Section 5: the unit
+cube cavity with its first curl-curl eigenfunction, whose angular frequency is
+sqrt(2)*pi) and extend them to a deformed cube with random per-element
+permittivity, point-dipole sources and point probes.
+
+Random streams: ``numpy.random.default_rng([seed, purpose_id])``, one stream
+per purpose, base seed 0.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+PURPOSE = {
+    "eps": 1,
+    "modes": 2,
+    "dipoles": 3,
+    "probes": 4,
+    "fd": 5,
+    "field": 6,
+    "eps_true": 7,
+}
+
+#: amplitude of the deformed-cube map x -> x + a*sin(pi x)sin(pi y)sin(pi z)
+DEFORMED_AMPLITUDE = 0.08
+
+
+def rng(seed: int, purpose: str) -> np.random.Generator:
+    """Independent generator for one purpose of one seeded workload."""
+    return np.random.default_rng([int(seed), PURPOSE[purpose]])
+
+
+def eps_elements(n_elem: int, seed: int = 0, lo: float = 1.0, hi: float = 4.0,
+                 purpose: str = "eps") -> np.ndarray:
+    """Per-element permittivity, uniform in [lo, hi], shape (N, N, N) indexed
+    [ez, ey, ex] (x fastest when flattened)."""
+    return rng(seed, purpose).uniform(lo, hi, size=(n_elem, n_elem, n_elem))
+
+
+def random_vector(n: int, seed: int = 0, salt: int = 0) -> np.ndarray:
+    """Standard-normal coefficient vector (operator tests)."""
+    g = np.random.default_rng([int(seed), PURPOSE["field"], int(salt)])
+    return g.standard_normal(n)
+
+
+# --------------------------------------------------------------------------
+# PEC cavity modes of the unit cube
+# --------------------------------------------------------------------------
+def _mode_indices(count: int):
+    """The `count` lowest (l, m, n) with at most one zero index, ordered by
+    l^2+m^2+n^2 and then lexicographically."""
+    cand = []
+    top = int(math.ceil(math.sqrt(count))) + 3
+    for lmn in itertools.product(range(top + 1), repeat=3):
+        if sum(1 for v in lmn if v == 0) > 1:
+            continue
+        cand.append((lmn[0] ** 2 + lmn[1] ** 2 + lmn[2] ** 2, lmn))
+    cand.sort()
+    return [lmn for _, lmn in cand[:count]]
+
+
+def cavity_modes(seed: int = 0, count: int = 10):
+    """Random smooth initial field: `count` PEC cavity modes.
+
+    Each mode is (l, m, n, a, amp): E = amp * (a_x cos(l pi x) sin(m pi y) sin(n pi z),
+    a_y sin(l pi x) cos(m pi y) sin(n pi z), a_z sin(l pi x) sin(m pi y) cos(n pi z))
+    with a a unit vector orthogonal to (l, m, n) (divergence free) and amp ~ N(0, 1).
+    When one index is zero only the component along that axis survives, so a
+    is that unit axis vector.
+    """
+    g = rng(seed, "modes")
+    modes = []
+    for lmn in _mode_indices(count):
+        k = np.array(lmn, dtype=float)
+        if (k == 0).any():
+            a = (k == 0).astype(float)
+            _ = g.standard_normal(3)  # keep the stream layout uniform
+        else:
+            v = g.standard_normal(3)
+            v -= k * (v @ k) / (k @ k)
+            a = v / np.linalg.norm(v)
+        amp = g.standard_normal()
+        modes.append((int(lmn[0]), int(lmn[1]), int(lmn[2]), a, float(amp)))
+    return modes
+
+
+def mode_110():
+    """The lowest cavity mode E = (0, 0, sin(pi x) sin(pi y)), omega = sqrt(2) pi."""
+    return [(1, 1, 0, np.array([0.0, 0.0, 1.0]), 1.0)]
+
+
+def eval_modes(modes, xyz: np.ndarray) -> np.ndarray:
+    """Electric field of a sum of cavity modes at physical points xyz (n, 3)."""
+    xyz = np.asarray(xyz, dtype=float)
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    out = np.zeros(xyz.shape, dtype=float)
+    pi = math.pi
+    for l, m, n, a, amp in modes:
+        sx, cx = np.sin(l * pi * x), np.cos(l * pi * x)
+        sy, cy = np.sin(m * pi * y), np.cos(m * pi * y)
+        sz, cz = np.sin(n * pi * z), np.cos(n * pi * z)
+        out[..., 0] += amp * a[0] * cx * sy * sz
+        out[..., 1] += amp * a[1] * sx * cy * sz
+        out[..., 2] += amp * a[2] * sx * sy * cz
+    return out
+
+
+def curl_modes(modes, xyz: np.ndarray) -> np.ndarray:
+    """curl E of a sum of cavity modes at physical points (for the exact H)."""
+    xyz = np.asarray(xyz, dtype=float)
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    out = np.zeros(xyz.shape, dtype=float)
+    pi = math.pi
+    for l, m, n, a, amp in modes:
+        kx, ky, kz = l * pi, m * pi, n * pi
+        sx, cx = np.sin(kx * x), np.cos(kx * x)
+        sy, cy = np.sin(ky * y), np.cos(ky * y)
+        sz, cz = np.sin(kz * z), np.cos(kz * z)
+        # E = (A cx sy sz, B sx cy sz, C sx sy cz)
+        A, B, C = amp * a[0], amp * a[1], amp * a[2]
+        dEz_dy = C * sx * ky * cy * cz
+        dEy_dz = B * sx * cy * kz * cz
+        dEx_dz = A * cx * sy * kz * cz
+        dEz_dx = C * kx * cx * sy * cz
+        dEy_dx = B * kx * cx * cy * sz
+        dEx_dy = A * cx * ky * cy * sz
+        out[..., 0] += dEz_dy - dEy_dz
+        out[..., 1] += dEx_dz - dEz_dx
+        out[..., 2] += dEy_dx - dEx_dy
+    return out
+
+
+def mode_omega(modes) -> np.ndarray:
+    """Angular frequency pi*sqrt(l^2+m^2+n^2) of each mode (eps = mu = 1)."""
+    return np.array([math.pi * math.sqrt(l * l + m * m + n * n) for l, m, n, _, _ in modes])
+
+
+# --------------------------------------------------------------------------
+# Point dipoles and probes
+# --------------------------------------------------------------------------
+def dipoles(count: int, seed: int = 0, dt: float = 1.0, sigma_steps: float = 20.0,
+            t0_sigmas: float = 5.0, margin: float = 0.0):
+    """`count` point dipoles: parametric positions U(margin, 1-margin)^3,
+    unit moments uniform on the sphere, Gaussian-in-time profile
+    amp*exp(-(t-t0)^2/(2 sigma^2)) with sigma = sigma_steps*dt, t0 = t0_sigmas*sigma.
+
+    Returns dict of arrays: pos (n,3), moment (n,3), t0 (n,), sigma (n,), amp (n,).
+    """
+    g = rng(seed, "dipoles")
+    pos = g.uniform(margin, 1.0 - margin, size=(count, 3))
+    v = g.standard_normal((count, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    sigma = np.full(count, sigma_steps * dt)
+    return {"pos": pos, "moment": v, "t0": t0_sigmas * sigma, "sigma": sigma,
+            "amp": np.ones(count)}
+
+
+def probes(count: int, seed: int = 0, margin: float = 0.0) -> np.ndarray:
+    """`count` probe points in parametric coordinates, U(margin, 1-margin)^3."""
+    return rng(seed, "probes").uniform(margin, 1.0 - margin, size=(count, 3))
