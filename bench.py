@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the scheme-2 spline Maxwell leapfrog on one MI355X.
+
+Workload: degree p=3, 64^3 elements, the deformed cube
+x -> x + 0.08 sin(pi x) sin(pi y) sin(pi z) on every component, per-element
+eps ~ U[1,4] (seed 0), mu = 1, initial E = sum of the 10 lowest cavity modes
+with N(0,1) amplitudes (seed 0), H = 0, dt = 0.5 CFL, FP64.
+
+A timed step is one pass of the whole hot path: fused curl + Hodge mass apply
+M^2_{1/mu} D^1 e, Kronecker solve with K~1, h update; fused dual curl + mass
+apply M~^2_{1/eps} D~^1 h, Kronecker solve with K1, e update; tracking of b
+and d; the leapfrog energy invariant.  Inputs are resident in HBM before the
+timed region.  value = DOF-updates/s = (dim e + dim h) * steps / seconds.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s per leapfrog step at p=3, 64^3 (mixed vs FP64) + adjoint grad time"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(p, N, steps, eps):
+    """The FP64 oracle on the host cores: `steps` leapfrog steps of the same
+    workload from a seeded random state (the step cost does not depend on the
+    data), timed after its one-off set-up."""
+    import numpy as np
+    import workloads as W
+    from oracle.geometry import Map
+    from oracle.scheme import Scheme
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    S = Scheme(p, N, Map("sine", W.DEFORMED_AMPLITUDE), eps=eps)
+    S.metric()
+    e = W.random_vector(S.n_e, 0, 41)
+    h = W.random_vector(S.n_h, 0, 42)
+    S.step(e, h, 1e-3, nsteps=1)  # warm caches and BLAS threads
+    t0 = time.perf_counter()
+    S.step(e, h, 1e-3, nsteps=steps)
+    dt = time.perf_counter() - t0
+    return {"value": (S.n_e + S.n_h) * steps / dt, "unit": "DOF-updates/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle leapfrog steps of the same p={p}, {N}^3 deformed-cube workload "
+                      f"from a seeded random state ({dt:.1f} s of CPU work, set-up excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only: the scheme-2 leapfrog here is a single-GPU build "
+              f"(requested --gpus {args.gpus}, WORLD_SIZE={world}); the multi-GPU slab decomposition "
+              f"is a design, not an implementation.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2302_04979_amd as K
+    import workloads as W
+
+    p, N = args.p, args.n
+    torch.cuda.set_device(0)
+    log(f"set-up p={p} N={N}")
+    G = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+    eps = W.eps_elements(N, 0)
+    G.set_materials(eps=eps)
+    xq = G.quad_points()
+    Eq = W.eval_modes(W.cavity_modes(0), xq)
+    del xq
+    dev = torch.device("cuda")
+    E = torch.zeros(2 * G.n_e, dtype=torch.float64, device=dev)
+    H = torch.zeros(2 * G.n_h, dtype=torch.float64, device=dev)
+    G.project_E(Eq, E[:G.n_e])
+    G.project_D(Eq, E[G.n_e:], tol=1e-13)
+    del Eq
+    dt = 0.5 * G.cfl(max_iter=300, tol=1e-6)
+    log(f"dt = {dt:.6e}")
+    flags = K.TRACK_DB
+    G.init_stagger(E, H, dt, flags=flags)
+    en_w = torch.zeros(max(args.warmup, 1), dtype=torch.float64, device=dev)
+    en = torch.zeros(args.steps, dtype=torch.float64, device=dev)
+    en_p = torch.zeros(args.steps, dtype=torch.float64, device=dev)
+    if args.warmup:
+        G.step(E, H, dt, nsteps=args.warmup, flags=flags, energy=en_w)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    # ---- timed region ----
+    log(f"timing {args.steps} steps")
+    t_start = args.warmup * dt
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    G.step(E, H, dt, nsteps=args.steps, t_start=t_start, flags=flags, energy=en)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+    dofs = G.n_e + G.n_h
+    value = dofs * args.steps / (ms * 1e-3)
+    energies = en.cpu().numpy()
+    drift = float(np.abs(energies / energies[0] - 1.0).max())
+
+    # ---- per-kernel durations, HIP events on the launch stream ----
+    G.profile_begin(capacity=16 * args.steps + 64)
+    G.step(E, H, dt, nsteps=args.steps, t_start=t_start + args.steps * dt, flags=flags, energy=en_p)
+    prof = G.profile_end()
+    torch.cuda.synchronize()
+    # the plain step (no b/d tracking, no energy) for reference
+    e_only, h_only = E[:G.n_e].clone(), H[:G.n_h].clone()
+    ev0.record(stream)
+    G.step(e_only, h_only, dt, nsteps=args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = ev0.elapsed_time(ev1) / args.steps
+
+    # dominant kernel: the fused curl + mass apply (two launches per step)
+    ms_mass = prof["mass_B"][0] + prof["mass_D"][0]
+    n_mass = prof["mass_B"][1] + prof["mass_D"][1]
+    avg_mass_s = ms_mass / n_mass * 1e-3
+    n_qp = G.n_qp
+    # algorithmic bytes of one mass apply: metric (6 doubles per Gauss point),
+    # per-element 1/gamma, the input 1-form and the output 2-form once each
+    bytes_B = 8.0 * (6 * n_qp + N ** 3 + G.n_e + G.n_h)
+    bytes_D = 8.0 * (6 * n_qp + N ** 3 + G.n_h + G.n_e)
+    bytes_avg = 0.5 * (bytes_B + bytes_D)
+    achieved = bytes_avg / avg_mass_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "mass_kernel (fused curl + 2-form Hodge apply)",
+                "avg_launch_us": round(avg_mass_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": int(bytes_avg)}
+    breakdown = {k: {"ms_per_launch": round(v[0] / v[1], 4) if v[1] else None, "launches": v[1]}
+                 for k, v in prof.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        cpu = cpu_baseline(p, N, args.cpu_steps, eps)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"scheme-2 leapfrog, deformed cube (a=0.08), p={p}, {N}^3 elements, "
+                               f"eps~U[1,4], 10 cavity modes, dt=0.5 CFL, FP64, b/d tracking + energy",
+                   "dofs_e_plus_h": dofs, "dt": dt, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "ms_per_step_plain": ms_plain,
+        "value_plain": dofs / (ms_plain * 1e-3),
+        "energy_rel_drift": drift,
+        "kernels": breakdown,
+        "mixed": None,
+        "adjoint_grad_s": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * kronmaxwell - explicit leapfrog of the spline geometric Maxwell scheme with
+ * Kronecker-structured pairing solves (Kapidani & Vazquez, "High order
+ * geometric methods with splines: fast solution with explicit time-stepping
+ * for Maxwell equations"), for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2-3 of the paper): Maxwell's equations in differential forms
+ * on the unit cube mapped by F, with perfect-conductor walls,
+ *     d_t D = dH - J,   d_t B = -dE,   D = eps E (via a Hodge star), B = mu H.
+ * E and B live in the primal spline complex of degrees p / p-1 with boundary
+ * conditions built in (X^1_{h,0}, X^2_{h,0}); H and D in the dual complex of
+ * degrees p-1 / p-2 (X~^1, X~^2).  The scheme of Section 3.5, eqs. (3.10)-(3.13),
+ * uses the Hodge operators of the second kind:
+ *     K1 e = M~^2_{1/eps} d,      K~1 h = M^2_{1/mu} b,
+ * so every time step applies the geometry/material mass matrices M and solves
+ * with the metric-free pairing matrices K1, K~1, whose blocks are Kronecker
+ * products of 1D matrices (eqs. (4.2)-(4.5)).
+ *
+ * Discrete unknowns and their layout in device memory (all FP64):
+ *   e  (X^1_{h,0}) and d (X~^2): n_e = 3 * n1 * n0^2 values
+ *   h  (X~^1)      and b (X^2_{h,0}): n_h = 3 * n0 * n1^2 values
+ * with n0 = N + p - 2, n1 = N + p - 1 for N elements per axis.  A vector stores
+ * its three components one after the other; inside a component the x index
+ * runs fastest.  Component c of e has n1 entries along axis c and n0 across,
+ * component c of h has n0 along axis c and n1 across.
+ *
+ * Time stepping (staggered leapfrog, Petrov-Galerkin (e, h) form of Section
+ * 3.5.2 with the tested source s = M~ j):
+ *     h^{n+1/2} = h^{n-1/2} - dt K~1^{-1} M^2_{1/mu} D^1 e^n
+ *     e^{n+1}   = e^n + dt K1^{-1} ( M~^2_{1/eps} D~^1 h^{n+1/2} - s(t_{n+1/2}) )
+ * and, when tracking is on, b^{n+1/2} = b^{n-1/2} - dt D^1 e^n and
+ * d^{n+1} = d^n + dt D~^1 h^{n+1/2}.
+ *
+ * Conventions for every call:
+ *   - Each call returns a kmx_status; nothing throws across this interface;
+ *     kmx_last_error() gives a thread-local message for the last failure.
+ *   - Pointers documented as "device" are HIP device pointers owned by the
+ *     caller; pointers documented as "host" are ordinary host memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Device work is
+ *     enqueued on it; calls that return host results synchronise it.
+ *   - The space owns all operator data and all scratch memory, sized at
+ *     creation for `max_batch` fields; kmx_step never allocates.
+ *   - Calls on one space must not overlap on different streams (they share
+ *     the space's scratch memory).
+ */
+#ifndef KRONMAXWELL_H
+#define KRONMAXWELL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kmx_space kmx_space;
+typedef struct kmx_source kmx_source;
+
+typedef enum {
+    KMX_OK = 0,
+    KMX_E_ARG = 1,       /* invalid argument (size, pointer, degree, batch) */
+    KMX_E_GEOMETRY = 2,  /* det DF <= 0 (or not finite) at a quadrature point */
+    KMX_E_MATERIAL = 3,  /* eps or mu <= 0 or not finite */
+    KMX_E_DEVICE = 4,    /* a HIP runtime call failed */
+    KMX_E_OOM = 5,       /* device allocation failed at creation */
+    KMX_E_UNSTABLE = 6,  /* non-finite value detected, or dt above the CFL limit */
+    KMX_E_STATE = 7      /* call not valid in the current state */
+} kmx_status;
+
+/* Map of the parametric cube (Section 2.3).
+ *   kind 0: identity, Omega = (0,1)^3.
+ *   kind 1: x -> x + amplitude * sin(pi x) sin(pi y) sin(pi z) on every
+ *           component (a deformed cube, identity on the boundary).
+ *   kind 2: user Jacobian: dF_qp (host) holds DF at every quadrature point,
+ *           9 doubles row-major (DF[i][j] = dF_i/dx^_j) per point, points in
+ *           the order of kmx_quad_points. */
+typedef struct {
+    int kind;
+    double amplitude;
+    const double* dF_qp;
+} kmx_map;
+
+typedef enum { KMX_FP64 = 0, KMX_MIXED = 1 } kmx_precision;
+
+/* flags for kmx_step / kmx_init_stagger */
+#define KMX_TRACK_DB 1 /* E holds [e | d] and H holds [h | b] per batch member */
+
+/* Create the discrete spaces, operators and scratch for degree p (2..4),
+ * n_elem elements per axis (1..80), map `map` (host struct), precision, and at
+ * most max_batch simultaneous fields.  Materials default to eps = mu = 1.
+ * Uses the current HIP device.  Gauss rule: p+1 points per element and axis.
+ * Errors: KMX_E_ARG, KMX_E_GEOMETRY, KMX_E_OOM, KMX_E_DEVICE. */
+kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision,
+                            int max_batch, kmx_space** out);
+
+/* Release everything the space owns (NULL is accepted). */
+void kmx_destroy_space(kmx_space* sp);
+
+/* Per-element eps and mu (host, N^3 each, element index x fastest); NULL keeps
+ * the value 1.  Errors: KMX_E_MATERIAL, KMX_E_DEVICE. */
+kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double* mu_elem);
+
+/* n_e = dim X^1_{h,0} = dim X~^2, n_h = dim X~^1 = dim X^2_{h,0}, n_qp = number
+ * of quadrature points (N^3 (p+1)^3).  Any output pointer may be NULL. */
+kmx_status kmx_sizes(const kmx_space* sp, int64_t* n_e, int64_t* n_h, int64_t* n_qp);
+
+/* Physical coordinates F(x^_q) of every quadrature point, host array of
+ * 3 * n_qp doubles, element-major: [ez][ey][ex][iqz][iqy][iqx][xyz]. */
+kmx_status kmx_quad_points(const kmx_space* sp, double* xyz_host);
+
+/* Initial electric field (Section 5.1, "projecting" the initial data):
+ * e = K1^{-1} l with l_i = int_Omega eta_i . E0 dx over the dual 2-form basis
+ * eta_i, the L^2_{1/eps} projection of D0 = eps E0 followed by the Hodge (3.11).
+ * E_qp_host: physical E0 at the quadrature points (3 * n_qp doubles, order of
+ * kmx_quad_points).  e_dev: device, n_e doubles (written).  Host computation
+ * plus one copy on `stream`. */
+kmx_status kmx_project_E(kmx_space* sp, const double* E_qp_host, double* e_dev, void* stream);
+
+/* d = M~^{-1} l (the L^2_{1/eps} projection of D0 itself, for tracking d),
+ * by preconditioned conjugate gradients on the device to relative residual
+ * `tol`.  E_qp_host as for kmx_project_E; d_dev: device, n_e doubles. */
+kmx_status kmx_project_D(kmx_space* sp, const double* E_qp_host, double* d_dev, double tol,
+                         void* stream);
+
+/* Largest stable step 2 / sqrt(lambda_max(K1^{-1} M~ D~^1 K~1^{-1} M D^1)) by
+ * power iteration on the device (seeded start vector), stopping when the
+ * eigenvalue estimate changes by less than tol (relative) or after max_iter
+ * iterations.  Synchronises. */
+kmx_status kmx_cfl(kmx_space* sp, int max_iter, double tol, double* dt_max);
+
+/* Point dipoles J = q delta(x - F(x^0)) g(t), g(t) = amp exp(-(t - t0)^2 / (2 sigma^2)).
+ * Tested source s_i = q . eta_i(x0) / eps(x0) with eta_i the physical dual
+ * 2-form basis (pushed forward).  Host arrays: pos (n x 3, parametric position
+ * in [0,1]^3), moment (n x 3), t0, sigma, amp (n each), batch_of (n, the batch
+ * member each dipole drives; NULL = member 0).  The source keeps a reference
+ * to nothing on the host; materials must be set before creating sources. */
+kmx_status kmx_create_source(kmx_space* sp, int n, const double* pos, const double* moment,
+                             const double* t0, const double* sigma, const double* amp,
+                             const int* batch_of, kmx_source** out);
+void kmx_destroy_source(kmx_source* src);
+
+/* Backward half kick from t = 0 data: h <- h + dt/2 K~1^{-1} M D^1 e, and with
+ * KMX_TRACK_DB also b <- b + dt/2 D^1 e.  E, H: device, batch members of
+ * stride n_e*(1+track) and n_h*(1+track). */
+kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt, int batch,
+                            int flags, void* stream);
+
+/* nsteps leapfrog steps (formulas above), in place.  On entry E holds e^n (and
+ * d^n) and H holds h^{n-1/2} (and b^{n-1/2}) at time t = t_start; on exit the
+ * state is advanced by nsteps.  J: NULL or a source of this space (not allowed
+ * together with KMX_TRACK_DB).  energy_dev: NULL, or device array of
+ * nsteps * batch doubles receiving the leapfrog invariant after every step
+ * (requires KMX_TRACK_DB).  Never allocates and never synchronises. */
+kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start,
+                    double dt, int nsteps, int batch, int flags, double* energy_dev, void* stream);
+
+/* Energies of tracked states (E = [e|d], H = [h|b], at e^n, d^n, h^{n-1/2},
+ * b^{n-1/2}), eq. (3.2):
+ *   out_host[2k]   = 1/2 (d.K1 e + b.K~1 h - dt (K~1 h).(D^1 e)), the invariant
+ *                    1/2 (d^n.M~ d^n + b^{n-1/2}.M b^{n+1/2}) of the leapfrog,
+ *   out_host[2k+1] = 1/2 (e^T K~2 d + h^T K2 b), the paper's energy (3.2),
+ * for batch member k.  FP64 deterministic reductions.  Synchronises. */
+kmx_status kmx_energy(kmx_space* sp, const double* E, const double* H, double dt, int batch,
+                      double* out_host, void* stream);
+
+/* ---- operator-level entry points (one step of the path each) ----------- */
+
+/* y = D^1 x (primal, which = 0: x in X^1_{h,0} -> X^2_{h,0}) or y = D~^1 x
+ * (dual, which = 1: X~^1 -> X~^2); device vectors of one field. */
+kmx_status kmx_op_curl(kmx_space* sp, int which, const double* x, double* y, void* stream);
+
+/* y = M x for which = 0: M^2_{1/mu} on X^2_{h,0}; which = 1: M~^2_{1/eps} on
+ * X~^2.  With `curl` = 1 the input is the 1-form and y = M D x (the fused
+ * curl + mass apply of the time step).  Device vectors of one field. */
+kmx_status kmx_op_mass(kmx_space* sp, int which, int curl, const double* x, double* y,
+                       void* stream);
+
+/* x = K^{-1} y (transpose = 0) or K^{-T} y (transpose = 1) with K = K1
+ * (which = 1; y in X~^2 layout, x in X^1_{h,0}) or K~1 (which = 0; y in
+ * X^2_{h,0}, x in X~^1), eqs. (4.4)-(4.5).  x and y may alias. */
+kmx_status kmx_op_solve(kmx_space* sp, int which, int transpose, const double* y, double* x,
+                        void* stream);
+
+/* y = K x with K = K1 (which = 1) or K~1 (which = 0). */
+kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, void* stream);
+
+/* ---- per-kernel timing ---------------------------------------------------
+ * Between kmx_profile_begin and kmx_profile_end every kernel the space
+ * launches (up to `capacity` launches) is bracketed by HIP events recorded on
+ * the launch stream.  kmx_profile_end waits for the last event and returns,
+ * per kernel kind, the summed elapsed milliseconds and the launch count:
+ *   0 mass apply on X^2_{h,0} (with the primal curl fused)
+ *   1 mass apply on X~^2 (with the dual curl fused)
+ *   2 patch gather + pairing solves along x and y
+ *   3 pairing solve along z + leapfrog update
+ *   4 curl (tracking of b and d)
+ *   5 energy reductions
+ * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
+#define KMX_PROFILE_KINDS 8
+kmx_status kmx_profile_begin(kmx_space* sp, int capacity);
+kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches);
+
+const char* kmx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,264 @@
+"""kronmaxwell: MI355X-native explicit leapfrog for the spline geometric Maxwell
+scheme with Kronecker-structured pairing solves (scheme 2 of Kapidani &
+Vazquez, Section 3.5 and Section 4).
+
+Thin Python binding over the C-ABI library ``libkronmaxwell.so`` (declared in
+``include/kronmaxwell.h``).  Every function here only marshals arguments:
+device vectors are torch float64 CUDA tensors passed as raw pointers, on the
+caller's current stream.  All arithmetic of the time step runs in the HIP
+kernels of the library; there is no fallback path: if the library is missing
+an ImportError-like RuntimeError is raised on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Space", "Source", "load_library", "EXPORTS", "TRACK_DB", "KMXError"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
+TRACK_DB = 1
+
+# every symbol declared in include/kronmaxwell.h
+EXPORTS = (
+    "kmx_create_space", "kmx_destroy_space", "kmx_set_materials", "kmx_sizes", "kmx_quad_points",
+    "kmx_project_E", "kmx_project_D", "kmx_cfl", "kmx_create_source", "kmx_destroy_source",
+    "kmx_init_stagger", "kmx_step", "kmx_energy", "kmx_op_curl", "kmx_op_mass", "kmx_op_solve",
+    "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_last_error",
+)
+PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy")
+
+_STATUS = {0: "KMX_OK", 1: "KMX_E_ARG", 2: "KMX_E_GEOMETRY", 3: "KMX_E_MATERIAL", 4: "KMX_E_DEVICE",
+           5: "KMX_E_OOM", 6: "KMX_E_UNSTABLE", 7: "KMX_E_STATE"}
+
+
+class KMXError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Map(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("amplitude", ctypes.c_double), ("dF_qp", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libkronmaxwell.so (built in-tree by ``paper_2302_04979_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2302_04979_amd.build`")
+    # torch ships its own HIP runtime; load it first so that the library binds
+    # to that same runtime instance (one device context, shared streams and
+    # allocations) instead of mapping a second copy from the ROCm install.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, i64p = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "kmx_create_space": ([i, i, ctypes.POINTER(_Map), i, i, ctypes.POINTER(vp)], i),
+        "kmx_destroy_space": ([vp], None),
+        "kmx_set_materials": ([vp, vp, vp], i),
+        "kmx_sizes": ([vp, i64p, i64p, i64p], i),
+        "kmx_quad_points": ([vp, vp], i),
+        "kmx_project_E": ([vp, vp, vp, vp], i),
+        "kmx_project_D": ([vp, vp, vp, d, vp], i),
+        "kmx_cfl": ([vp, i, d, ctypes.POINTER(d)], i),
+        "kmx_create_source": ([vp, i, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)], i),
+        "kmx_destroy_source": ([vp], None),
+        "kmx_init_stagger": ([vp, vp, vp, d, i, i, vp], i),
+        "kmx_step": ([vp, vp, vp, vp, d, d, i, i, i, vp, vp], i),
+        "kmx_energy": ([vp, vp, vp, d, i, vp, vp], i),
+        "kmx_op_curl": ([vp, i, vp, vp, vp], i),
+        "kmx_op_mass": ([vp, i, i, vp, vp, vp], i),
+        "kmx_op_solve": ([vp, i, i, vp, vp, vp], i),
+        "kmx_op_pairing": ([vp, i, vp, vp, vp], i),
+        "kmx_profile_begin": ([vp, i], i),
+        "kmx_profile_end": ([vp, vp, vp], i),
+        "kmx_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise KMXError(st, load_library().kmx_last_error().decode())
+
+
+def _dptr(t, n=None, name="tensor"):
+    """Raw device pointer of a contiguous float64 CUDA tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} entries, needs {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a, n=None, dtype=np.float64, name="array"):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if n is not None and a.size != n:
+        raise ValueError(f"{name} has {a.size} entries, needs {n}")
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Source:
+    """Point dipoles (see kmx_create_source)."""
+
+    def __init__(self, space: "Space", pos, moment, t0, sigma, amp, batch_of=None):
+        L = load_library()
+        n = int(np.asarray(pos).shape[0])
+        self._keep = [_hptr(pos, 3 * n), _hptr(moment, 3 * n), _hptr(t0, n), _hptr(sigma, n), _hptr(amp, n)]
+        bo = None if batch_of is None else _hptr(batch_of, n, np.int32)
+        h = ctypes.c_void_p()
+        _check(L.kmx_create_source(space._h, n, *[k[1] for k in self._keep],
+                                   None if bo is None else bo[1], ctypes.byref(h)))
+        self._h = h
+        self.space = space
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().kmx_destroy_source(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Space:
+    """Discrete spaces, operators and scratch of one problem (kmx_create_space)."""
+
+    def __init__(self, p: int, n_elem: int, map_kind: int = 0, amplitude: float = 0.0, dF_qp=None,
+                 precision: int = 0, max_batch: int = 1):
+        L = load_library()
+        self._dF = None
+        m = _Map(int(map_kind), float(amplitude), None)
+        if dF_qp is not None:
+            self._dF, ptr = _hptr(dF_qp)
+            m.dF_qp = ptr
+        h = ctypes.c_void_p()
+        _check(L.kmx_create_space(int(p), int(n_elem), ctypes.byref(m), int(precision), int(max_batch),
+                                  ctypes.byref(h)))
+        self._h = h
+        self.p, self.N, self.max_batch = p, n_elem, max_batch
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(L.kmx_sizes(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        self.n_e, self.n_h, self.n_qp = a.value, b.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().kmx_destroy_space(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- set-up -------------------------------------------------------
+    def set_materials(self, eps=None, mu=None):
+        n3 = self.N ** 3
+        e = None if eps is None else _hptr(np.asarray(eps).ravel(), n3, name="eps")
+        m = None if mu is None else _hptr(np.asarray(mu).ravel(), n3, name="mu")
+        _check(load_library().kmx_set_materials(self._h, None if e is None else e[1], None if m is None else m[1]))
+
+    def quad_points(self) -> np.ndarray:
+        out = np.empty((self.n_qp, 3))
+        _check(load_library().kmx_quad_points(self._h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def project_E(self, E_qp, e):
+        a, ptr = _hptr(E_qp, 3 * self.n_qp, name="E_qp")
+        _check(load_library().kmx_project_E(self._h, ptr, _dptr(e, self.n_e, "e"), _stream()))
+
+    def project_D(self, E_qp, d, tol=1e-13):
+        a, ptr = _hptr(E_qp, 3 * self.n_qp, name="E_qp")
+        _check(load_library().kmx_project_D(self._h, ptr, _dptr(d, self.n_e, "d"), float(tol), _stream()))
+
+    def cfl(self, max_iter=2000, tol=1e-10) -> float:
+        out = ctypes.c_double()
+        _check(load_library().kmx_cfl(self._h, int(max_iter), float(tol), ctypes.byref(out)))
+        return out.value
+
+    def source(self, pos, moment, t0, sigma, amp, batch_of=None) -> Source:
+        return Source(self, pos, moment, t0, sigma, amp, batch_of)
+
+    # ---- time stepping ------------------------------------------------
+    def init_stagger(self, E, H, dt, batch=1, flags=0):
+        k = 1 + (flags & TRACK_DB)
+        _check(load_library().kmx_init_stagger(self._h, _dptr(E, batch * k * self.n_e, "E"),
+                                               _dptr(H, batch * k * self.n_h, "H"), float(dt), int(batch),
+                                               int(flags), _stream()))
+
+    def step(self, E, H, dt, nsteps=1, J: Source | None = None, t_start=0.0, batch=1, flags=0, energy=None):
+        k = 1 + (flags & TRACK_DB)
+        en = None if energy is None else _dptr(energy, nsteps * batch, "energy")
+        _check(load_library().kmx_step(self._h, _dptr(E, batch * k * self.n_e, "E"),
+                                       _dptr(H, batch * k * self.n_h, "H"), None if J is None else J._h,
+                                       float(t_start), float(dt), int(nsteps), int(batch), int(flags), en,
+                                       _stream()))
+
+    def energy(self, E, H, dt, batch=1) -> np.ndarray:
+        out = np.empty(2 * batch)
+        _check(load_library().kmx_energy(self._h, _dptr(E, batch * 2 * self.n_e, "E"),
+                                         _dptr(H, batch * 2 * self.n_h, "H"), float(dt), int(batch),
+                                         ctypes.c_void_p(out.ctypes.data), _stream()))
+        return out.reshape(batch, 2)
+
+    # ---- single operators ---------------------------------------------
+    def op_curl(self, primal: bool, x, y):
+        n_in, n_out = (self.n_e, self.n_h) if primal else (self.n_h, self.n_e)
+        _check(load_library().kmx_op_curl(self._h, 0 if primal else 1, _dptr(x, n_in, "x"), _dptr(y, n_out, "y"),
+                                          _stream()))
+
+    def op_mass(self, which: str, x, y, curl=False):
+        """which 'B' (M^2_{1/mu}) or 'D' (M~^2_{1/eps}); curl=True applies M D."""
+        w = 0 if which == "B" else 1
+        n_out = self.n_h if w == 0 else self.n_e
+        n_in = (self.n_e if w == 0 else self.n_h) if curl else n_out
+        _check(load_library().kmx_op_mass(self._h, w, int(bool(curl)), _dptr(x, n_in, "x"), _dptr(y, n_out, "y"),
+                                          _stream()))
+
+    def op_solve(self, which: str, y, x, transpose=False):
+        """which 'K1' or 'K1t': x = K^{-1} y (or K^{-T} y)."""
+        w = 1 if which == "K1" else 0
+        n = self.n_e if w else self.n_h
+        _check(load_library().kmx_op_solve(self._h, w, int(bool(transpose)), _dptr(y, n, "y"), _dptr(x, n, "x"),
+                                           _stream()))
+
+    def profile_begin(self, capacity=100000):
+        _check(load_library().kmx_profile_begin(self._h, int(capacity)))
+
+    def profile_end(self) -> dict:
+        """{kind: (total_ms, launches)} for the launches since profile_begin."""
+        ms = np.zeros(8)
+        cnt = np.zeros(8, dtype=np.int32)
+        _check(load_library().kmx_profile_end(self._h, ctypes.c_void_p(ms.ctypes.data),
+                                              ctypes.c_void_p(cnt.ctypes.data)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_KINDS)}
+
+    def op_pairing(self, which: str, x, y):
+        w = 1 if which == "K1" else 0
+        n = self.n_e if w else self.n_h
+        _check(load_library().kmx_op_pairing(self._h, w, _dptr(x, n, "x"), _dptr(y, n, "y"), _stream()))

@@ -1,0 +1,686 @@
+// C-ABI of kronmaxwell: set-up of a space and the stream-ordered leapfrog.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "kmx_internal.hpp"
+#include "setup.hpp"
+
+using namespace kmx;
+
+namespace {
+
+thread_local std::string g_err;
+
+kmx_status fail(kmx_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(KMX_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+#define CHECK_LAUNCH()                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess) return fail(KMX_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// factor-set ids beyond the four pairing factors: 1D Gram matrices used by the
+// conjugate-gradient preconditioner of the dual 2-form mass matrix
+constexpr int F_GRAM_DV = 4, F_GRAM_DD = 5, NFAC = 6;
+
+void space_dims(const kmx_space* sp, int space, int dims[3][3], int64_t off[3]) {
+    for (int c = 0; c < 3; ++c) {
+        comp_dims(sp, space, c, dims[c]);
+        off[c] = comp_offset(sp, space, c);
+    }
+}
+
+int pair_fac(int which_K1, int transpose, int c, int a) {
+    if (which_K1) return transpose ? (a == c ? F_MT : F_GT) : (a == c ? F_M : F_G);
+    return transpose ? (a == c ? F_G : F_M) : (a == c ? F_GT : F_MT);
+}
+
+void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
+    *fac = sp->d_fac;
+    for (int k = 0; k < 8; ++k) fac_off[k] = 0;
+    for (int k = 0; k < NFAC; ++k) fac_off[k] = sp->fac_off[k];
+}
+
+// Kernel kinds reported by kmx_profile_end.
+enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5 };
+
+struct ProfScope {  // brackets one launch with events when profiling is on
+    kmx_space* sp;
+    hipStream_t s;
+    int slot = -1;
+    ProfScope(kmx_space* sp_, hipStream_t s_, int kind) : sp(sp_), s(s_) {
+        if (sp->prof_on && sp->prof_used + 2 <= int(sp->prof_ev.size())) {
+            slot = sp->prof_used;
+            sp->prof_used += 2;
+            sp->prof_kind[slot / 2] = kind;
+            (void)hipEventRecord(sp->prof_ev[slot], s);
+        }
+    }
+    ~ProfScope() {
+        if (slot >= 0) (void)hipEventRecord(sp->prof_ev[slot + 1], s);
+    }
+};
+
+// y (patches) = M x or M D x for one or more batch members
+void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t src_stride, int batch,
+              hipStream_t s) {
+    MassArgs a{};
+    a.src = src;
+    a.src_stride = src_stride;
+    a.patch = sp->d_patch;
+    a.patch_stride = sp->patch_per_field;
+    a.metric = sp->d_metric;
+    a.inv_gamma = space == SP_B ? sp->d_inv_mu : sp->d_inv_eps;
+    a.tab = sp->d_tab;
+    for (int k = 0; k < 4; ++k) a.tab_off[k] = sp->tab_off[k];
+    a.ntile = sp->ntile;
+    a.npad = sp->npad;
+    a.n0 = sp->n0;
+    a.n1 = sp->n1;
+    const int src_space = curl ? (space == SP_B ? SP_E : SP_H) : space;
+    space_dims(sp, src_space, a.src_dims, a.src_comp_off);
+    patch_size(sp->p, space, sp->ntile, a.patch_comp_off);
+    ProfScope ps(sp, s, space == SP_B ? PK_MASS_B : PK_MASS_D);
+    launch_mass(sp->p, space, curl, a, batch, s);
+}
+
+// out = (accumulate ? out : 0) + alpha * K^{-1} y, y gathered from the patches
+// (from_patch) or read from `in`; solve = 0 skips the pairing solve (plain
+// gather of the mass output).
+void run_solve(kmx_space* sp, int which_K1, int transpose, int from_patch, int gather_space, const double* in,
+               int64_t in_stride, double* out, int64_t out_stride, double alpha, int accumulate, int batch,
+               const kmx_source* J, double t_src, int solve, hipStream_t s, const int* fac_override = nullptr) {
+    XYArgs a{};
+    a.patch = sp->d_patch;
+    a.patch_stride = sp->patch_per_field;
+    patch_size(sp->p, gather_space == SP_B ? SP_B : SP_D, sp->ntile, a.patch_comp_off);
+    a.in = in;
+    a.in_stride = in_stride;
+    const int64_t nfield = std::max(sp->n_e, sp->n_h);
+    a.out = sp->d_tmp;
+    a.out_stride = nfield;
+    const int layout = which_K1 ? SP_D : SP_B;  // dims of K1 (= e, d) or K~1 (= h, b) vectors
+    space_dims(sp, layout, a.dims, a.comp_off);
+    a.ntile = sp->ntile;
+    fill_fac(sp, &a.fac, a.fac_off);
+    for (int c = 0; c < 3; ++c)
+        for (int ax = 0; ax < 3; ++ax)
+            a.fac_id[c][ax] = fac_override ? fac_override[c * 3 + ax] : pair_fac(which_K1, transpose, c, ax);
+    a.from_patch = from_patch;
+    a.gather_space = gather_space;
+    a.n_src = 0;
+    if (J) {
+        a.src_entries = J->d_entries;
+        a.src_prof = J->d_prof;
+        a.src_off = reinterpret_cast<const int*>(J->d_prof + 4 * J->n);
+        a.n_src = J->n;
+        a.entries_per = J->entries_per;
+        a.t_src = t_src;
+    }
+    a.solve = solve;
+    {
+        ProfScope ps(sp, s, PK_XY);
+        launch_xy(sp->p, a, batch, s);
+    }
+
+    ZArgs z{};
+    z.in = sp->d_tmp;
+    z.in_stride = nfield;
+    z.out = out;
+    z.out_stride = out_stride;
+    for (int c = 0; c < 3; ++c) {
+        z.comp_off[c] = a.comp_off[c];
+        for (int k = 0; k < 3; ++k) z.dims[c][k] = a.dims[c][k];
+        z.fac_id[c] = a.fac_id[c][2];
+    }
+    fill_fac(sp, &z.fac, z.fac_off);
+    z.alpha = alpha;
+    z.accumulate = accumulate;
+    z.solve = solve;
+    ProfScope ps(sp, s, PK_Z);
+    launch_z(sp->p, z, batch, s);
+}
+
+void run_curl(kmx_space* sp, int primal, const double* in, int64_t in_stride, double* out, int64_t out_stride,
+              double alpha, double beta, int batch, hipStream_t s) {
+    CurlArgs a{};
+    a.in = in;
+    a.in_stride = in_stride;
+    a.out = out;
+    a.out_stride = out_stride;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.primal = primal;
+    space_dims(sp, primal ? SP_E : SP_H, a.in_dims, a.in_comp_off);
+    space_dims(sp, primal ? SP_B : SP_D, a.out_dims, a.out_comp_off);
+    ProfScope ps(sp, s, PK_CURL);
+    launch_curl(a, primal ? sp->n_h : sp->n_e, batch, s);
+}
+
+int energy_blocks(const kmx_space* sp) {
+    const int64_t n = std::max(sp->n_e, sp->n_h);
+    return int(std::min<int64_t>(1024, (n + 255) / 256));
+}
+
+void run_energy(kmx_space* sp, const double* E, const double* H, double dt, int batch, double* out,
+                int64_t out_stride, hipStream_t s) {
+    EnergyArgs a{};
+    a.E = E;
+    a.H = H;
+    a.n_e = sp->n_e;
+    a.n_h = sp->n_h;
+    space_dims(sp, SP_E, a.e_dims, a.e_comp_off);
+    space_dims(sp, SP_B, a.h_dims, a.h_comp_off);
+    fill_fac(sp, &a.fac, a.fac_off);
+    a.partial = sp->d_red;
+    a.nblocks = energy_blocks(sp);
+    ProfScope ps(sp, s, PK_ENERGY);
+    launch_energy(sp->p, a, batch, s);
+    launch_energy_final(sp->d_red, a.nblocks, dt, batch, out, out_stride, s);
+}
+
+kmx_status upload(double** dst, const std::vector<double>& v) {
+    if (hipMalloc(dst, std::max<size_t>(v.size(), 1) * sizeof(double)) != hipSuccess)
+        return fail(KMX_E_OOM, "device allocation failed");
+    if (!v.empty()) HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    return KMX_OK;
+}
+
+kmx_status upload_materials(kmx_space* sp) {
+    const int N = sp->N, P = sp->npad;
+    for (int which = 0; which < 2; ++which) {
+        const std::vector<double>& h = which ? sp->inv_mu_host : sp->inv_eps_host;
+        std::vector<double> pad(size_t(P) * P * P, 0.0);
+        for (int z = 0; z < N; ++z)
+            for (int y = 0; y < N; ++y)
+                for (int x = 0; x < N; ++x)
+                    pad[(size_t(z) * P + y) * P + x] = h[(size_t(z) * N + y) * N + x];
+        double* d = which ? sp->d_inv_mu : sp->d_inv_eps;
+        HIP_TRY(hipMemcpy(d, pad.data(), pad.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return KMX_OK;
+}
+
+std::vector<double> gram(const Tables& tb, int tag) {
+    const int n = (tag == PV || tag == DD) ? tb.n0 : tb.n1;
+    const int K = tag_support(tb.p, tag);
+    std::vector<double> G(size_t(n) * n, 0.0);
+    for (int e = 0; e < tb.N; ++e)
+        for (int q = 0; q < tb.nq; ++q) {
+            const double* v = &tb.tab[tag][(e * tb.nq + q) * K];
+            const double w = tb.wq[e * tb.nq + q];
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) {
+                    const int gi = e + i + tag_offset(tag), gj = e + j + tag_offset(tag);
+                    if (gi < 0 || gj < 0 || gi >= n || gj >= n) continue;
+                    G[size_t(gi) * n + gj] += w * v[i] * v[j];
+                }
+        }
+    return G;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kmx_last_error(void) { return g_err.c_str(); }
+
+kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision, int max_batch,
+                            kmx_space** out) {
+    if (!out) return fail(KMX_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (p < 2 || p > 4) return fail(KMX_E_ARG, "degree p must be 2, 3 or 4");
+    // one xy-plane of a component ((N+p-1)^2 doubles) must fit the 64 KiB of
+    // dynamic LDS the solve kernel requests
+    if (n_elem < 1 || n_elem > 80) return fail(KMX_E_ARG, "n_elem must be in 1..80");
+    if (max_batch < 1) return fail(KMX_E_ARG, "max_batch must be >= 1");
+    if (precision != KMX_FP64) return fail(KMX_E_ARG, "only KMX_FP64 is available in this build");
+    if (map && (map->kind < 0 || map->kind > 2)) return fail(KMX_E_ARG, "unknown map kind");
+    if (map && map->kind == 2 && !map->dF_qp) return fail(KMX_E_ARG, "map kind 2 needs dF_qp");
+    kmx_space* sp = new kmx_space();
+    try {
+        sp->p = p;
+        sp->N = n_elem;
+        sp->nq = p + 1;
+        sp->n0 = n_elem + p - 2;
+        sp->n1 = n_elem + p - 1;
+        sp->ntile = (n_elem + TILE - 1) / TILE;
+        sp->npad = sp->ntile * TILE;
+        sp->max_batch = max_batch;
+        sp->precision = precision;
+        sp->n_e = 3LL * sp->n1 * sp->n0 * sp->n0;
+        sp->n_h = 3LL * sp->n0 * sp->n1 * sp->n1;
+        sp->n_qp = int64_t(n_elem) * n_elem * n_elem * sp->nq * sp->nq * sp->nq;
+        sp->map = map ? *map : kmx_map{0, 0.0, nullptr};
+        if (sp->map.kind == 2) {
+            sp->dF_user.assign(map->dF_qp, map->dF_qp + 9 * sp->n_qp);
+            sp->map.dF_qp = nullptr;
+        }
+        build_tables(sp->tb, p, n_elem);
+        const size_t ne3 = size_t(n_elem) * n_elem * n_elem;
+        sp->inv_eps_host.assign(ne3, 1.0);
+        sp->inv_mu_host.assign(ne3, 1.0);
+        std::vector<double> metric;
+        kmx_status st = build_metric(sp, metric);
+        if (st != KMX_OK) {
+            delete sp;
+            return fail(st, "det DF <= 0 at a quadrature point: the map is not admissible");
+        }
+        // device data
+        if ((st = upload(&sp->d_metric, metric)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        std::vector<double> tabs;
+        for (int t = 0; t < 4; ++t) {
+            sp->tab_off[t] = int64_t(tabs.size());
+            tabs.insert(tabs.end(), sp->tb.tab[t].begin(), sp->tb.tab[t].end());
+        }
+        if ((st = upload(&sp->d_tab, tabs)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        std::vector<double> facs;
+        BandLU sets[NFAC] = {sp->tb.lu[F_G], sp->tb.lu[F_M], sp->tb.lu[F_GT], sp->tb.lu[F_MT],
+                             band_lu(gram(sp->tb, DV), sp->n1, p - 1), band_lu(gram(sp->tb, DD), sp->n0, p - 1)};
+        for (int k = 0; k < NFAC; ++k) {
+            sp->fac_off[k] = int64_t(facs.size());
+            const BandLU& f = sets[k];
+            facs.insert(facs.end(), f.L.begin(), f.L.end());
+            facs.insert(facs.end(), f.U.begin(), f.U.end());
+            facs.insert(facs.end(), f.dinv.begin(), f.dinv.end());
+            facs.insert(facs.end(), f.band.begin(), f.band.end());
+        }
+        if ((st = upload(&sp->d_fac, facs)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        const size_t npad3 = size_t(sp->npad) * sp->npad * sp->npad;
+        if (hipMalloc(&sp->d_inv_eps, npad3 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_inv_mu, npad3 * sizeof(double)) != hipSuccess) {
+            kmx_destroy_space(sp);
+            return fail(KMX_E_OOM, "device allocation failed (materials)");
+        }
+        if ((st = upload_materials(sp)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        int64_t off[3];
+        sp->patch_per_field = std::max(patch_size(p, SP_B, sp->ntile, off), patch_size(p, SP_D, sp->ntile, off));
+        const int64_t nfield = std::max(sp->n_e, sp->n_h);
+        sp->red_len = int64_t(max_batch) * 1024 * 3 + 64;
+        if (hipMalloc(&sp->d_patch, size_t(sp->patch_per_field) * max_batch * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_tmp, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_tmp2, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_red, size_t(sp->red_len) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_scal, size_t(64 + 2 * max_batch) * sizeof(double)) != hipSuccess) {
+            kmx_destroy_space(sp);
+            return fail(KMX_E_OOM, "device allocation failed (scratch)");
+        }
+    } catch (const std::exception& ex) {
+        kmx_destroy_space(sp);
+        return fail(KMX_E_ARG, std::string("set-up failed: ") + ex.what());
+    }
+    *out = sp;
+    return KMX_OK;
+}
+
+kmx_status kmx_profile_begin(kmx_space* sp, int capacity) {
+    if (!sp || capacity < 1) return fail(KMX_E_ARG, "bad argument");
+    if (sp->prof_on) return fail(KMX_E_STATE, "profiling already on");
+    sp->prof_ev.assign(2 * size_t(capacity), nullptr);
+    sp->prof_kind.assign(capacity, -1);
+    for (auto& e : sp->prof_ev) HIP_TRY(hipEventCreate(&e));
+    sp->prof_used = 0;
+    sp->prof_on = true;
+    return KMX_OK;
+}
+
+kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches) {
+    if (!sp || !ms_total || !launches) return fail(KMX_E_ARG, "bad argument");
+    if (!sp->prof_on) return fail(KMX_E_STATE, "profiling is off");
+    for (int k = 0; k < KMX_PROFILE_KINDS; ++k) {
+        ms_total[k] = 0.0;
+        launches[k] = 0;
+    }
+    kmx_status st = KMX_OK;
+    if (sp->prof_used > 0 && hipEventSynchronize(sp->prof_ev[sp->prof_used - 1]) != hipSuccess)
+        st = fail(KMX_E_DEVICE, "event synchronisation failed");
+    for (int i = 0; st == KMX_OK && i < sp->prof_used / 2; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sp->prof_ev[2 * i], sp->prof_ev[2 * i + 1]) != hipSuccess) {
+            st = fail(KMX_E_DEVICE, "hipEventElapsedTime failed");
+            break;
+        }
+        ms_total[sp->prof_kind[i]] += ms;
+        launches[sp->prof_kind[i]] += 1;
+    }
+    for (auto& e : sp->prof_ev) (void)hipEventDestroy(e);
+    sp->prof_ev.clear();
+    sp->prof_kind.clear();
+    sp->prof_used = 0;
+    sp->prof_on = false;
+    return st;
+}
+
+void kmx_destroy_space(kmx_space* sp) {
+    if (!sp) return;
+    for (auto& e : sp->prof_ev) (void)hipEventDestroy(e);
+    double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
+                      sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
+    for (double* b : bufs)
+        if (b) (void)hipFree(b);
+    delete sp;
+}
+
+kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double* mu_elem) {
+    if (!sp) return fail(KMX_E_ARG, "space is NULL");
+    const size_t ne3 = size_t(sp->N) * sp->N * sp->N;
+    std::vector<double> ie(ne3, 1.0), im(ne3, 1.0);
+    for (size_t i = 0; i < ne3; ++i) {
+        if (eps_elem) {
+            if (!(eps_elem[i] > 0.0) || !std::isfinite(eps_elem[i]))
+                return fail(KMX_E_MATERIAL, "eps must be finite and > 0");
+            ie[i] = 1.0 / eps_elem[i];
+        }
+        if (mu_elem) {
+            if (!(mu_elem[i] > 0.0) || !std::isfinite(mu_elem[i]))
+                return fail(KMX_E_MATERIAL, "mu must be finite and > 0");
+            im[i] = 1.0 / mu_elem[i];
+        }
+    }
+    sp->inv_eps_host = ie;
+    sp->inv_mu_host = im;
+    return upload_materials(sp);
+}
+
+kmx_status kmx_sizes(const kmx_space* sp, int64_t* n_e, int64_t* n_h, int64_t* n_qp) {
+    if (!sp) return fail(KMX_E_ARG, "space is NULL");
+    if (n_e) *n_e = sp->n_e;
+    if (n_h) *n_h = sp->n_h;
+    if (n_qp) *n_qp = sp->n_qp;
+    return KMX_OK;
+}
+
+kmx_status kmx_quad_points(const kmx_space* sp, double* xyz_host) {
+    if (!sp || !xyz_host) return fail(KMX_E_ARG, "NULL argument");
+    quad_points(sp, xyz_host);
+    return KMX_OK;
+}
+
+kmx_status kmx_project_E(kmx_space* sp, const double* E_qp_host, double* e_dev, void* stream) {
+    if (!sp || !E_qp_host || !e_dev) return fail(KMX_E_ARG, "NULL argument");
+    std::vector<double> l;
+    load_E(sp, E_qp_host, l);
+    kron_solve_K1_host(sp, l);
+    HIP_TRY(hipMemcpyAsync(e_dev, l.data(), l.size() * sizeof(double), hipMemcpyHostToDevice,
+                           static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return KMX_OK;
+}
+
+kmx_status kmx_project_D(kmx_space* sp, const double* E_qp_host, double* d_dev, double tol, void* stream) {
+    if (!sp || !E_qp_host || !d_dev) return fail(KMX_E_ARG, "NULL argument");
+    if (!(tol > 0.0)) return fail(KMX_E_ARG, "tol must be > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<double> l;
+    load_E(sp, E_qp_host, l);
+    const int64_t n = sp->n_e;
+    double *r = nullptr, *z = nullptr, *pd = nullptr, *Ap = nullptr;
+    if (hipMalloc(&r, n * sizeof(double)) != hipSuccess || hipMalloc(&z, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&pd, n * sizeof(double)) != hipSuccess || hipMalloc(&Ap, n * sizeof(double)) != hipSuccess) {
+        hipFree(r); hipFree(z); hipFree(pd); hipFree(Ap);
+        return fail(KMX_E_OOM, "device allocation failed (CG vectors)");
+    }
+    kmx_status result = KMX_OK;
+    const int nb = energy_blocks(sp);
+    int pre[9];
+    for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < 3; ++a) pre[c * 3 + a] = (a == c) ? F_GRAM_DV : F_GRAM_DD;
+    auto dot = [&](const double* x, const double* y, int slot) {
+        launch_dot(x, y, n, n, 1, sp->d_red, nb, s);
+        launch_sum_final(sp->d_red, nb, 1, sp->d_scal + slot, s);
+    };
+    auto precond = [&](const double* in, double* outv) {  // identity-map, unit-material mass inverse
+        run_solve(sp, 1, 0, 0, SP_D, in, n, outv, n, 1.0, 0, 1, nullptr, 0.0, 1, s, pre);
+    };
+    double l2 = 0.0;
+    for (double v : l) l2 += v * v;
+    const double stop = tol * std::sqrt(l2);
+    hipMemcpyAsync(r, l.data(), n * sizeof(double), hipMemcpyHostToDevice, s);
+    hipMemsetAsync(d_dev, 0, n * sizeof(double), s);
+    precond(r, z);
+    hipMemcpyAsync(pd, z, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    dot(r, z, 0);
+    int it = 0;
+    for (; it < 2000; ++it) {
+        run_mass(sp, SP_D, false, pd, n, 1, s);
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, Ap, n, 1.0, 0, 1, nullptr, 0.0, 0, s);
+        dot(pd, Ap, 1);
+        launch_cg_update(d_dev, r, pd, Ap, nullptr, n, sp->d_scal, 0, s);
+        dot(r, r, 3);
+        double rr = 0.0;
+        hipMemcpyAsync(&rr, sp->d_scal + 3, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess) { result = fail(KMX_E_DEVICE, "CG failed"); break; }
+        if (!std::isfinite(rr)) { result = fail(KMX_E_UNSTABLE, "CG diverged"); break; }
+        if (std::sqrt(rr) <= stop) break;
+        precond(r, z);
+        dot(r, z, 2);
+        launch_cg_update(d_dev, r, pd, Ap, z, n, sp->d_scal, 1, s);
+        hipMemcpyAsync(sp->d_scal, sp->d_scal + 2, sizeof(double), hipMemcpyDeviceToDevice, s);
+    }
+    if (result == KMX_OK && it >= 2000) result = fail(KMX_E_UNSTABLE, "CG did not converge");
+    hipStreamSynchronize(s);
+    hipFree(r); hipFree(z); hipFree(pd); hipFree(Ap);
+    return result;
+}
+
+kmx_status kmx_cfl(kmx_space* sp, int max_iter, double tol, double* dt_max) {
+    if (!sp || !dt_max || max_iter < 1) return fail(KMX_E_ARG, "bad argument");
+    hipStream_t s = nullptr;
+    const int64_t ne = sp->n_e, nh = sp->n_h;
+    double *x = nullptr, *hb = nullptr;
+    if (hipMalloc(&x, ne * sizeof(double)) != hipSuccess || hipMalloc(&hb, nh * sizeof(double)) != hipSuccess) {
+        hipFree(x); hipFree(hb);
+        return fail(KMX_E_OOM, "device allocation failed (CFL vectors)");
+    }
+    std::vector<double> x0(ne);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    double nrm = 0.0;
+    for (int64_t i = 0; i < ne; ++i) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        x0[i] = double(st >> 11) / double(1ull << 53) - 0.5;
+        nrm += x0[i] * x0[i];
+    }
+    for (auto& v : x0) v /= std::sqrt(nrm);
+    hipMemcpy(x, x0.data(), ne * sizeof(double), hipMemcpyHostToDevice);
+    const int nb = energy_blocks(sp);
+    double lam = 0.0;
+    kmx_status result = KMX_OK;
+    for (int it = 0; it < max_iter; ++it) {
+        run_mass(sp, SP_B, true, x, ne, 1, s);
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, hb, nh, 1.0, 0, 1, nullptr, 0.0, 1, s);
+        run_mass(sp, SP_D, true, hb, nh, 1, s);
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, x, ne, 1.0, 0, 1, nullptr, 0.0, 1, s);
+        launch_dot(x, x, ne, ne, 1, sp->d_red, nb, s);
+        launch_sum_final(sp->d_red, nb, 1, sp->d_scal, s);
+        double yy = 0.0;
+        hipMemcpy(&yy, sp->d_scal, sizeof(double), hipMemcpyDeviceToHost);
+        const double lam_new = std::sqrt(yy);
+        if (!std::isfinite(lam_new) || lam_new <= 0.0) { result = fail(KMX_E_UNSTABLE, "power iteration failed"); break; }
+        launch_axpby(x, x, ne, 1.0 / lam_new, nullptr, 0.0, s);
+        const bool done = std::fabs(lam_new - lam) <= tol * lam_new;
+        lam = lam_new;
+        if (done) break;
+    }
+    hipDeviceSynchronize();
+    hipFree(x);
+    hipFree(hb);
+    if (result != KMX_OK) return result;
+    *dt_max = 2.0 / std::sqrt(lam);
+    return KMX_OK;
+}
+
+kmx_status kmx_create_source(kmx_space* sp, int n, const double* pos, const double* moment, const double* t0,
+                             const double* sigma, const double* amp, const int* batch_of, kmx_source** out) {
+    if (!sp || !out || n < 1 || !pos || !moment || !t0 || !sigma || !amp) return fail(KMX_E_ARG, "bad argument");
+    *out = nullptr;
+    std::vector<int> order(n);
+    for (int k = 0; k < n; ++k) {
+        order[k] = k;
+        const int b = batch_of ? batch_of[k] : 0;
+        if (b < 0 || b >= sp->max_batch) return fail(KMX_E_ARG, "dipole batch index out of range");
+        for (int a = 0; a < 3; ++a)
+            if (!(pos[3 * k + a] >= 0.0 && pos[3 * k + a] <= 1.0)) return fail(KMX_E_ARG, "dipole position outside [0,1]^3");
+        if (!(sigma[k] > 0.0)) return fail(KMX_E_ARG, "sigma must be > 0");
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
+        return (batch_of ? batch_of[i] : 0) < (batch_of ? batch_of[j] : 0);
+    });
+    const int per = 3 * sp->p * (sp->p - 1) * (sp->p - 1);
+    std::vector<double> ent(size_t(n) * per * 5, 0.0), prof(size_t(n) * 4);
+    std::vector<int> off(sp->max_batch + 1, 0);
+    int bmax = 0;
+    for (int r = 0; r < n; ++r) {
+        const int k = order[r];
+        std::vector<DipoleEntry> de;
+        dipole_entries(sp, &pos[3 * k], &moment[3 * k], de);
+        for (size_t e = 0; e < de.size() && int(e) < per; ++e) {
+            double* q = &ent[(size_t(r) * per + e) * 5];
+            q[0] = de[e].comp; q[1] = de[e].iz; q[2] = de[e].iy; q[3] = de[e].ix; q[4] = de[e].val;
+        }
+        for (size_t e = de.size(); int(e) < per; ++e) ent[(size_t(r) * per + e) * 5] = -1.0;  // no component
+        const int b = batch_of ? batch_of[k] : 0;
+        prof[4 * r] = t0[k]; prof[4 * r + 1] = sigma[k]; prof[4 * r + 2] = amp[k]; prof[4 * r + 3] = b;
+        off[b + 1]++;
+        bmax = std::max(bmax, b + 1);
+    }
+    for (int b = 0; b < sp->max_batch; ++b) off[b + 1] += off[b];
+    kmx_source* src = new kmx_source();
+    src->sp = sp;
+    src->n = n;
+    src->batch_max = bmax;
+    src->entries_per = per;
+    // offsets are stored as ints right after the profiles
+    const size_t prof_bytes = prof.size() * sizeof(double), off_bytes = off.size() * sizeof(int);
+    if (hipMalloc(&src->d_entries, ent.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&src->d_prof, prof_bytes + off_bytes + 16) != hipSuccess) {
+        kmx_destroy_source(src);
+        return fail(KMX_E_OOM, "device allocation failed (sources)");
+    }
+    HIP_TRY(hipMemcpy(src->d_entries, ent.data(), ent.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(src->d_prof, prof.data(), prof_bytes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(reinterpret_cast<char*>(src->d_prof) + prof_bytes, off.data(), off_bytes, hipMemcpyHostToDevice));
+    *out = src;
+    return KMX_OK;
+}
+
+void kmx_destroy_source(kmx_source* src) {
+    if (!src) return;
+    if (src->d_entries) (void)hipFree(src->d_entries);
+    if (src->d_prof) (void)hipFree(src->d_prof);
+    delete src;
+}
+
+kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt, int batch, int flags,
+                            void* stream) {
+    if (!sp || !E || !H) return fail(KMX_E_ARG, "NULL argument");
+    if (batch < 1 || batch > sp->max_batch) return fail(KMX_E_ARG, "batch out of range");
+    const int track = flags & KMX_TRACK_DB;
+    const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (track) run_curl(sp, 1, E, es, H + sp->n_h, hs, 0.5 * dt, 1.0, batch, s);
+    run_mass(sp, SP_B, true, E, es, batch, s);
+    run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, 0.5 * dt, 1, batch, nullptr, 0.0, 1, s);
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, double dt,
+                    int nsteps, int batch, int flags, double* energy_dev, void* stream) {
+    if (!sp || !E || !H) return fail(KMX_E_ARG, "NULL argument");
+    if (batch < 1 || batch > sp->max_batch) return fail(KMX_E_ARG, "batch out of range");
+    if (nsteps < 0) return fail(KMX_E_ARG, "nsteps < 0");
+    if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt not finite");
+    const int track = flags & KMX_TRACK_DB;
+    if (J && J->sp != sp) return fail(KMX_E_ARG, "source belongs to another space");
+    if (J && track) return fail(KMX_E_ARG, "tracking d and b needs J = NULL (d would need M~^{-1} s)");
+    if (energy_dev && !track) return fail(KMX_E_ARG, "energy output needs KMX_TRACK_DB");
+    const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int n = 0; n < nsteps; ++n) {
+        const double t_half = t_start + (n + 0.5) * dt;
+        if (track) run_curl(sp, 1, E, es, H + sp->n_h, hs, -dt, 1.0, batch, s);  // b -= dt D^1 e
+        run_mass(sp, SP_B, true, E, es, batch, s);                                 // M D^1 e
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -dt, 1, batch, nullptr, 0.0, 1, s);
+        run_mass(sp, SP_D, true, H, hs, batch, s);                                 // M~ D~^1 h
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, dt, 1, batch, J, t_half, 1, s);
+        if (track) run_curl(sp, 0, H, hs, E + sp->n_e, es, dt, 1.0, batch, s);    // d += dt D~^1 h
+        if (energy_dev) run_energy(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, 1, s);
+    }
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_energy(kmx_space* sp, const double* E, const double* H, double dt, int batch, double* out_host,
+                      void* stream) {
+    if (!sp || !E || !H || !out_host) return fail(KMX_E_ARG, "NULL argument");
+    if (batch < 1 || batch > sp->max_batch) return fail(KMX_E_ARG, "batch out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    run_energy(sp, E, H, dt, batch, sp->d_scal, 2, s);
+    CHECK_LAUNCH();
+    std::vector<double> tmp(2 * batch);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), sp->d_scal, 2 * batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < 2 * batch; ++k) out_host[k] = tmp[k];
+    for (int k = 0; k < batch; ++k)
+        if (!std::isfinite(tmp[2 * k])) return fail(KMX_E_UNSTABLE, "energy is not finite");
+    return KMX_OK;
+}
+
+kmx_status kmx_op_curl(kmx_space* sp, int which, const double* x, double* y, void* stream) {
+    if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
+    run_curl(sp, which == 0, x, 0, y, 0, 1.0, 0.0, 1, static_cast<hipStream_t>(stream));
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_op_mass(kmx_space* sp, int which, int curl, const double* x, double* y, void* stream) {
+    if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int space = which == 0 ? SP_B : SP_D;
+    run_mass(sp, space, curl != 0, x, 0, 1, s);
+    run_solve(sp, which, 0, 1, space, nullptr, 0, y, 0, 1.0, 0, 1, nullptr, 0.0, 0, s);
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_op_solve(kmx_space* sp, int which, int transpose, const double* y, double* x, void* stream) {
+    if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
+    run_solve(sp, which, transpose != 0, 0, which ? SP_D : SP_B, y, 0, x, 0, 1.0, 0, 1, nullptr, 0.0, 1,
+              static_cast<hipStream_t>(stream));
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, void* stream) {
+    if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
+    PairArgs a{};
+    a.in = x;
+    a.out = y;
+    space_dims(sp, which ? SP_D : SP_B, a.dims, a.comp_off);
+    fill_fac(sp, &a.fac, a.fac_off);
+    for (int c = 0; c < 3; ++c)
+        for (int ax = 0; ax < 3; ++ax) a.fac_id[c][ax] = pair_fac(which, 0, c, ax);
+    launch_pairing(sp->p, a, which ? sp->n_e : sp->n_h, 1, static_cast<hipStream_t>(stream));
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+}  // extern "C"

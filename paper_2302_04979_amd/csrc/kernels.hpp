@@ -1,0 +1,124 @@
+// Kernel launch interfaces (kernels.hip).
+#pragma once
+
+#include "kmx_internal.hpp"
+
+namespace kmx {
+
+// Mass apply y = M x (or M D x with the curl fused), written as per-tile
+// partial sums ("patches") that the solve kernels gather.
+struct MassArgs {
+    const double* src;          // input field of batch member 0
+    int64_t src_stride;         // distance between batch members
+    double* patch;              // patch buffer of batch member 0
+    int64_t patch_stride;
+    const double* metric;       // w_q DF^T DF / det DF, tile layout
+    const double* inv_gamma;    // [npad^3] per-element 1/eps or 1/mu, or nullptr
+    const double* tab;          // concatenated 1D tables
+    int64_t tab_off[4];
+    int ntile, npad, n0, n1;
+    int64_t src_comp_off[3];
+    int src_dims[3][3];         // [c][z, y, x] of the source space
+    int64_t patch_comp_off[3];  // per component, within one field's patches
+};
+
+// Gather patches (or read a field), subtract point sources, solve along x and y.
+struct XYArgs {
+    const double* patch;        // gather source (from_patch = 1)
+    int64_t patch_stride;
+    int64_t patch_comp_off[3];
+    const double* in;           // field source (from_patch = 0)
+    int64_t in_stride;
+    double* out;
+    int64_t out_stride;
+    int64_t comp_off[3];        // component offsets (same for in and out)
+    int dims[3][3];             // [c][z, y, x]
+    int ntile;
+    const double* fac;          // banded factor sets
+    int64_t fac_off[8];
+    int fac_id[3][3];           // [c][axis] factor id; axis 2 unused here
+    int from_patch;
+    int gather_space;           // SP_B or SP_D: layout of the patches
+    // point sources (tested dipoles); n_src = 0 when none
+    const double* src_entries;  // [n_src][entries_per][5] = comp, iz, iy, ix, value
+    const double* src_prof;     // [n_src][4] = t0, sigma, amp, batch
+    const int* src_off;         // [batch+1] dipoles of each batch member (sorted)
+    int n_src, entries_per;
+    double t_src;
+    int solve;                  // 0: gather only (copy to out), 1: solve x and y
+};
+
+// Solve along z and finish: out = (accumulate ? out : 0) + alpha * x.
+struct ZArgs {
+    const double* in;
+    int64_t in_stride;
+    double* out;
+    int64_t out_stride;
+    int64_t comp_off[3];
+    int dims[3][3];
+    const double* fac;
+    int64_t fac_off[8];
+    int fac_id[3];
+    double alpha;
+    int accumulate;
+    int solve;                  // 0: no z solve (plain axpy of in)
+};
+
+struct CurlArgs {
+    const double* in;
+    int64_t in_stride;
+    double* out;
+    int64_t out_stride;
+    int64_t in_comp_off[3], out_comp_off[3];
+    int in_dims[3][3], out_dims[3][3];
+    double alpha, beta;         // out = beta * out + alpha * curl(in)
+    int primal;
+};
+
+struct PairArgs {               // y = K x, banded Kronecker apply
+    const double* in;
+    int64_t in_stride;
+    double* out;
+    int64_t out_stride;
+    int64_t comp_off[3];
+    int dims[3][3];
+    const double* fac;
+    int64_t fac_off[8];
+    int fac_id[3][3];           // [c][axis]
+};
+
+struct EnergyArgs {
+    const double* E;            // [e | d] per batch member
+    const double* H;            // [h | b]
+    int64_t n_e, n_h;
+    int64_t e_comp_off[3], h_comp_off[3];
+    int e_dims[3][3], h_dims[3][3];
+    const double* fac;
+    int64_t fac_off[8];
+    double* partial;            // [batch][nblocks][3]
+    int nblocks;
+};
+
+void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s);
+void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s);
+void launch_z(int p, const ZArgs& a, int batch, hipStream_t s);
+void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
+void launch_pairing(int p, const PairArgs& a, int64_t n, int batch, hipStream_t s);
+void launch_energy(int p, const EnergyArgs& a, int batch, hipStream_t s);
+// out[b*out_stride] (+ step offset) from the energy partials
+void launch_energy_final(const double* partial, int nblocks, double dt, int batch, double* out,
+                         int64_t out_stride, hipStream_t s);
+// partial dot products x.y per batch member -> partial[b][nblocks]
+void launch_dot(const double* x, const double* y, int64_t n, int64_t stride, int batch,
+                double* partial, int nblocks, hipStream_t s);
+void launch_sum_final(const double* partial, int nblocks, int batch, double* out, hipStream_t s);
+// y = a*x + b*y with device scalars a = sa[0]*ka, b = kb (sa may be null => 1)
+void launch_axpby(const double* x, double* y, int64_t n, double ka, const double* sa, double kb,
+                  hipStream_t s);
+void launch_cg_update(double* x, double* r, double* pdir, const double* Ap, const double* z,
+                      int64_t n, const double* scal, int phase, hipStream_t s);
+
+int mass_threads(int p);
+int64_t patch_size(int p, int space, int ntile, int64_t comp_off[3]);
+
+}  // namespace kmx

@@ -1,0 +1,114 @@
+// Internal definitions shared by the host set-up code and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/kronmaxwell.h"
+
+namespace kmx {
+
+// Elements per tile edge of the mass-apply kernel; tiles are TILE^3 elements.
+constexpr int TILE = 4;
+
+// 1D basis tags (Section 2.3 / 4.1):
+//   PV primal value S_p(Xi) minus its two boundary functions (dim n0)
+//   PD primal derivative, Curry-Schoenberg basis of S_{p-1}(Xi') (dim n1)
+//   DV dual value, B-splines of S_{p-1}(Xi') (dim n1)
+//   DD dual derivative, Curry-Schoenberg basis of S_{p-2}(Xi'') (dim n0)
+enum Tag { PV = 0, PD = 1, DV = 2, DD = 3 };
+
+// Number of basis functions of a tag that are nonzero on one element.
+__host__ __device__ constexpr int tag_support(int p, int tag) {
+    return tag == PV ? p + 1 : (tag == DD ? p - 1 : p);
+}
+// Global index of local function j on element e is e + j + tag_offset.
+__host__ __device__ constexpr int tag_offset(int tag) { return tag == PV ? -1 : 0; }
+
+// Form spaces: component c, axis a -> tag.
+enum Space { SP_E = 0, SP_B = 1, SP_H = 2, SP_D = 3 };
+__host__ __device__ constexpr int space_tag(int space, int c, int a) {
+    return space == SP_E ? (a == c ? PD : PV)
+         : space == SP_B ? (a == c ? PV : PD)
+         : space == SP_H ? (a == c ? DD : DV)
+                         : (a == c ? DV : DD);
+}
+
+// Banded LU factors (no pivoting) of an n x n matrix with half bandwidth w,
+// stored per row: L[i*w + k] = l(i, i-1-k), U[i*w + k] = u(i, i+1+k),
+// dinv[i] = 1/u(i,i); band[i*(2w+1) + k] = a(i, i-w+k) (the matrix itself).
+struct BandLU {
+    int n = 0, w = 0;
+    std::vector<double> L, U, dinv, band;
+};
+
+// Device copy of one set of banded factors: contiguous [L | U | dinv | band].
+struct DevBand {
+    const double* L;
+    const double* U;
+    const double* dinv;
+    const double* band;
+    int n, w;
+};
+
+// 1D factor ids: G^, M^, G^T, M^T.
+enum Fac { F_G = 0, F_M = 1, F_GT = 2, F_MT = 3 };
+
+struct DipoleEntry {   // one nonzero of a tested dipole source
+    int comp, iz, iy, ix;
+    double val;
+};
+
+struct Tables {        // host-side 1D data
+    int p = 0, N = 0, nq = 0, n0 = 0, n1 = 0, npad = 0;
+    std::vector<double> xq, wq;                 // global Gauss points / weights (N*nq)
+    std::vector<double> tab[4];                 // [npad][nq][K(tag)] values at Gauss points
+    std::vector<double> G, M;                   // dense n0 x n0 and n1 x n1
+    BandLU lu[4];                               // factors of G, M, G^T, M^T
+};
+
+}  // namespace kmx
+
+struct kmx_source {
+    kmx_space* sp = nullptr;
+    int n = 0;
+    int batch_max = 0;                 // 1 + largest batch index
+    double* d_entries = nullptr;       // device: per dipole, ENTRIES x {comp,iz,iy,ix,val} as doubles
+    double* d_prof = nullptr;          // device: per dipole {t0, sigma, amp, batch}
+    int entries_per = 0;
+};
+
+struct kmx_space {
+    int p = 0, N = 0, nq = 0, n0 = 0, n1 = 0;
+    int npad = 0, ntile = 0;           // padded element count and tiles per axis
+    int max_batch = 1;
+    int precision = 0;
+    int64_t n_e = 0, n_h = 0, n_qp = 0;
+    kmx::Tables tb;
+    kmx_map map{};
+    std::vector<double> inv_eps_host, inv_mu_host;   // [N^3] x fastest
+    std::vector<double> dF_user;                      // kind 2 copy
+    // device data
+    double* d_tab = nullptr;           // 4 tag tables concatenated
+    int64_t tab_off[4] = {0, 0, 0, 0};
+    double* d_metric = nullptr;        // w_q DF^T DF / det DF, tile layout
+    double* d_inv_eps = nullptr;       // [npad^3]
+    double* d_inv_mu = nullptr;        // [npad^3]
+    double* d_fac = nullptr;           // 4 banded factor sets
+    int64_t fac_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double* d_patch = nullptr;         // mass-apply partial outputs
+    int64_t patch_per_field = 0;
+    double* d_tmp = nullptr;           // field-sized scratch [max_batch][max(n_e,n_h)]
+    double* d_tmp2 = nullptr;          // second field-sized scratch
+    double* d_red = nullptr;           // reduction partials
+    int64_t red_len = 0;
+    double* d_scal = nullptr;          // small device scalars
+    // optional per-kernel timing with HIP events (kmx_profile_begin/end)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_kind;
+    int prof_used = 0;
+};

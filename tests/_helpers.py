@@ -1,0 +1,37 @@
+"""Shared helpers for the GPU parity tests (oracle on the host, HIP path on cuda:0)."""
+import numpy as np
+
+import workloads as W
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def make_pair(p, N, deformed=True, eps=True, max_batch=1, eps_seed=0):
+    """Oracle Scheme and GPU Space on the same problem."""
+    from oracle.geometry import Map
+    from oracle.scheme import Scheme
+    import paper_2302_04979_amd as K
+    e = W.eps_elements(N, eps_seed) if eps else None
+    geo = Map("sine", W.DEFORMED_AMPLITUDE) if deformed else Map("identity")
+    S = Scheme(p, N, geo, eps=e)
+    G = K.Space(p, N, map_kind=1 if deformed else 0, amplitude=W.DEFORMED_AMPLITUDE if deformed else 0.0,
+                max_batch=max_batch)
+    if eps:
+        G.set_materials(eps=e)
+    return S, G
+
+
+def to_dev(x):
+    import torch
+    return torch.tensor(np.asarray(x, dtype=float), dtype=torch.float64, device="cuda")
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(float)

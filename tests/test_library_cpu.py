@@ -1,0 +1,52 @@
+"""The C-ABI library loads on the host and exports every declared symbol;
+argument errors are reported before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kronmaxwell.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:kmx_status|void|const char\*)\s+(kmx_\w+)\s*\(", txt, re.M)))
+
+
+def _lib():
+    import paper_2302_04979_amd as K
+    if not os.path.exists(K.LIB_PATH):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    return K, K.load_library()
+
+
+def test_header_declares_the_binding_exports():
+    import paper_2302_04979_amd as K
+    assert _declared() == sorted(K.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    K, L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_argument_errors_without_device():
+    K, L = _lib()
+    h = ctypes.c_void_p()
+    m = K._Map(0, 0.0, None)
+    for p, n, prec, mb in ((1, 4, 0, 1), (5, 4, 0, 1), (3, 0, 0, 1), (3, 4, 0, 0), (3, 4, 7, 1)):
+        st = L.kmx_create_space(p, n, ctypes.byref(m), prec, mb, ctypes.byref(h))
+        assert st == 1, (p, n, prec, mb)
+        assert L.kmx_last_error().decode()
+    bad = K._Map(9, 0.0, None)
+    assert L.kmx_create_space(3, 4, ctypes.byref(bad), 0, 1, ctypes.byref(h)) == 1
+    needs_df = K._Map(2, 0.0, None)
+    assert L.kmx_create_space(3, 4, ctypes.byref(needs_df), 0, 1, ctypes.byref(h)) == 1
+    a = ctypes.c_int64()
+    assert L.kmx_sizes(None, ctypes.byref(a), None, None) == 1
+    assert L.kmx_step(None, None, None, None, 0.0, 0.1, 1, 1, 0, None, None) == 1
+    assert L.kmx_set_materials(None, None, None) == 1
+    L.kmx_destroy_space(None)  # accepted
