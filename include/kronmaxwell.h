@@ -85,7 +85,7 @@ typedef enum { KMX_FP64 = 0, KMX_MIXED = 1 } kmx_precision;
 #define KMX_TRACK_DB 1 /* E holds [e | d] and H holds [h | b] per batch member */
 
 /* Create the discrete spaces, operators and scratch for degree p (2..4),
- * n_elem elements per axis (1..80), map `map` (host struct), precision, and at
+ * n_elem elements per axis (1..72), map `map` (host struct), precision, and at
  * most max_batch simultaneous fields.  Materials default to eps = mu = 1.
  * Uses the current HIP device.  Gauss rule: p+1 points per element and axis.
  * Errors: KMX_E_ARG, KMX_E_GEOMETRY, KMX_E_OOM, KMX_E_DEVICE. */
@@ -190,10 +190,11 @@ kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, 
  * per kernel kind, the summed elapsed milliseconds and the launch count:
  *   0 mass apply on X^2_{h,0} (with the primal curl fused)
  *   1 mass apply on X~^2 (with the dual curl fused)
- *   2 patch gather + pairing solves along x and y
+ *   2 pairing solves (or applies) along x and y
  *   3 pairing solve along z + leapfrog update
  *   4 curl (tracking of b and d)
  *   5 energy reductions
+ *   6 patch gather (sum of the overlapping tile outputs of a mass apply)
  * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
 #define KMX_PROFILE_KINDS 8
 kmx_status kmx_profile_begin(kmx_space* sp, int capacity);

@@ -29,7 +29,7 @@ EXPORTS = (
     "kmx_init_stagger", "kmx_step", "kmx_energy", "kmx_op_curl", "kmx_op_mass", "kmx_op_solve",
     "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_last_error",
 )
-PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy")
+PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather")
 
 _STATUS = {0: "KMX_OK", 1: "KMX_E_ARG", 2: "KMX_E_GEOMETRY", 3: "KMX_E_MATERIAL", 4: "KMX_E_DEVICE",
            5: "KMX_E_OOM", 6: "KMX_E_UNSTABLE", 7: "KMX_E_STATE"}

@@ -60,7 +60,7 @@ void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
 }
 
 // Kernel kinds reported by kmx_profile_end.
-enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5 };
+enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6 };
 
 struct ProfScope {  // brackets one launch with events when profiling is on
     kmx_space* sp;
@@ -81,8 +81,12 @@ struct ProfScope {  // brackets one launch with events when profiling is on
 
 // y (patches) = M x or M D x for one or more batch members
 void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t src_stride, int batch,
-              hipStream_t s) {
+              hipStream_t s, double* track = nullptr, int64_t track_stride = 0, double track_alpha = 0.0) {
     MassArgs a{};
+    a.track = curl ? track : nullptr;
+    a.track_stride = track_stride;
+    a.track_alpha = track_alpha;
+    space_dims(sp, space, a.track_dims, a.track_comp_off);
     a.src = src;
     a.src_stride = src_stride;
     a.patch = sp->d_patch;
@@ -102,30 +106,44 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
     launch_mass(sp->p, space, curl, a, batch, s);
 }
 
-// out = (accumulate ? out : 0) + alpha * K^{-1} y, y gathered from the patches
-// (from_patch) or read from `in`; solve = 0 skips the pairing solve (plain
-// gather of the mass output).
+// out = (accumulate ? out : 0) + alpha * op(y), y gathered from the patches
+// (from_patch) or read from `in`; op = K^{-1} (solve = 1), K (solve = 2, the
+// banded pairing apply) or the identity (solve = 0, plain gather of the mass
+// output).
 void run_solve(kmx_space* sp, int which_K1, int transpose, int from_patch, int gather_space, const double* in,
                int64_t in_stride, double* out, int64_t out_stride, double alpha, int accumulate, int batch,
                const kmx_source* J, double t_src, int solve, hipStream_t s, const int* fac_override = nullptr) {
+    const int64_t nfield = std::max(sp->n_e, sp->n_h);
+    const int layout = which_K1 ? SP_D : SP_B;  // dims of K1 (= e, d) or K~1 (= h, b) vectors
+    if (from_patch) {
+        // sum the overlapping tile patches of the mass apply into a field
+        GatherArgs g{};
+        g.patch = sp->d_patch;
+        g.patch_stride = sp->patch_per_field;
+        patch_size(sp->p, gather_space == SP_B ? SP_B : SP_D, sp->ntile, g.patch_comp_off);
+        space_dims(sp, layout, g.dims, g.comp_off);
+        g.ntile = sp->ntile;
+        const bool direct = solve == 0 && !accumulate && alpha == 1.0 && !J;
+        g.out = direct ? out : sp->d_tmp2;
+        g.out_stride = direct ? out_stride : nfield;
+        {
+            ProfScope ps(sp, s, PK_GATHER);
+            launch_gather(sp->p, gather_space == SP_B ? SP_B : SP_D, g, which_K1 ? sp->n_e : sp->n_h, batch, s);
+        }
+        if (direct) return;
+        in = sp->d_tmp2;
+        in_stride = nfield;
+    }
     XYArgs a{};
-    a.patch = sp->d_patch;
-    a.patch_stride = sp->patch_per_field;
-    patch_size(sp->p, gather_space == SP_B ? SP_B : SP_D, sp->ntile, a.patch_comp_off);
     a.in = in;
     a.in_stride = in_stride;
-    const int64_t nfield = std::max(sp->n_e, sp->n_h);
     a.out = sp->d_tmp;
     a.out_stride = nfield;
-    const int layout = which_K1 ? SP_D : SP_B;  // dims of K1 (= e, d) or K~1 (= h, b) vectors
     space_dims(sp, layout, a.dims, a.comp_off);
-    a.ntile = sp->ntile;
     fill_fac(sp, &a.fac, a.fac_off);
     for (int c = 0; c < 3; ++c)
         for (int ax = 0; ax < 3; ++ax)
             a.fac_id[c][ax] = fac_override ? fac_override[c * 3 + ax] : pair_fac(which_K1, transpose, c, ax);
-    a.from_patch = from_patch;
-    a.gather_space = gather_space;
     a.n_src = 0;
     if (J) {
         a.src_entries = J->d_entries;
@@ -182,6 +200,10 @@ int energy_blocks(const kmx_space* sp) {
 
 void run_energy(kmx_space* sp, const double* E, const double* H, double dt, int batch, double* out,
                 int64_t out_stride, hipStream_t s) {
+    ProfScope ps(sp, s, PK_ENERGY);  // one span for the pairing applies and the sums
+    const bool saved = sp->prof_on;
+    sp->prof_on = false;
+    const int64_t nfield = std::max(sp->n_e, sp->n_h);
     EnergyArgs a{};
     a.E = E;
     a.H = H;
@@ -189,12 +211,20 @@ void run_energy(kmx_space* sp, const double* E, const double* H, double dt, int 
     a.n_h = sp->n_h;
     space_dims(sp, SP_E, a.e_dims, a.e_comp_off);
     space_dims(sp, SP_B, a.h_dims, a.h_comp_off);
-    fill_fac(sp, &a.fac, a.fac_off);
+    a.work = sp->d_tmp2;
+    a.work_stride = nfield;
     a.partial = sp->d_red;
     a.nblocks = energy_blocks(sp);
-    ProfScope ps(sp, s, PK_ENERGY);
+    // v = K1 e, then d . v
+    run_solve(sp, 1, 0, 0, SP_D, E, 2 * sp->n_e, sp->d_tmp2, nfield, 1.0, 0, batch, nullptr, 0.0, 2, s);
+    a.mode = 0;
+    launch_energy(sp->p, a, batch, s);
+    // u = K~1 h, then b . u and u . D^1 e
+    run_solve(sp, 0, 0, 0, SP_B, H, 2 * sp->n_h, sp->d_tmp2, nfield, 1.0, 0, batch, nullptr, 0.0, 2, s);
+    a.mode = 1;
     launch_energy(sp->p, a, batch, s);
     launch_energy_final(sp->d_red, a.nblocks, dt, batch, out, out_stride, s);
+    sp->prof_on = saved;
 }
 
 kmx_status upload(double** dst, const std::vector<double>& v) {
@@ -248,9 +278,9 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
     if (!out) return fail(KMX_E_ARG, "out is NULL");
     *out = nullptr;
     if (p < 2 || p > 4) return fail(KMX_E_ARG, "degree p must be 2, 3 or 4");
-    // one xy-plane of a component ((N+p-1)^2 doubles) must fit the 64 KiB of
-    // dynamic LDS the solve kernel requests
-    if (n_elem < 1 || n_elem > 80) return fail(KMX_E_ARG, "n_elem must be in 1..80");
+    // one xy-plane of a component ((N+p-1)^2 doubles) plus two factor sets must
+    // fit the 64 KiB of dynamic LDS the solve kernel requests
+    if (n_elem < 1 || n_elem > 72) return fail(KMX_E_ARG, "n_elem must be in 1..72");
     if (max_batch < 1) return fail(KMX_E_ARG, "max_batch must be >= 1");
     if (precision != KMX_FP64) return fail(KMX_E_ARG, "only KMX_FP64 is available in this build");
     if (map && (map->kind < 0 || map->kind > 2)) return fail(KMX_E_ARG, "unknown map kind");
@@ -616,12 +646,12 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = t_start + (n + 0.5) * dt;
-        if (track) run_curl(sp, 1, E, es, H + sp->n_h, hs, -dt, 1.0, batch, s);  // b -= dt D^1 e
-        run_mass(sp, SP_B, true, E, es, batch, s);                                 // M D^1 e
+        // M D^1 e (and b -= dt D^1 e), then h -= dt K~1^{-1} (.)
+        run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -dt);
         run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -dt, 1, batch, nullptr, 0.0, 1, s);
-        run_mass(sp, SP_D, true, H, hs, batch, s);                                 // M~ D~^1 h
+        // M~ D~^1 h (and d += dt D~^1 h), then e += dt K1^{-1} (. - s)
+        run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, dt);
         run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, dt, 1, batch, J, t_half, 1, s);
-        if (track) run_curl(sp, 0, H, hs, E + sp->n_e, es, dt, 1.0, batch, s);    // d += dt D~^1 h
         if (energy_dev) run_energy(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, 1, s);
     }
     CHECK_LAUNCH();
@@ -671,14 +701,8 @@ kmx_status kmx_op_solve(kmx_space* sp, int which, int transpose, const double* y
 
 kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, void* stream) {
     if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
-    PairArgs a{};
-    a.in = x;
-    a.out = y;
-    space_dims(sp, which ? SP_D : SP_B, a.dims, a.comp_off);
-    fill_fac(sp, &a.fac, a.fac_off);
-    for (int c = 0; c < 3; ++c)
-        for (int ax = 0; ax < 3; ++ax) a.fac_id[c][ax] = pair_fac(which, 0, c, ax);
-    launch_pairing(sp->p, a, which ? sp->n_e : sp->n_h, 1, static_cast<hipStream_t>(stream));
+    run_solve(sp, which, 0, 0, which ? SP_D : SP_B, x, 0, y, 0, 1.0, 0, 1, nullptr, 0.0, 2,
+              static_cast<hipStream_t>(stream));
     CHECK_LAUNCH();
     return KMX_OK;
 }

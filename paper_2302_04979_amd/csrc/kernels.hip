@@ -11,13 +11,17 @@ namespace kmx {
 // Mass apply (Section 3.4): y_i = sum_q w^_i(q) . G(q) X(q) / gamma_e over the
 // Gauss points q of every element, with X(q) the parametric vector proxy of the
 // input 2-form (or of the curl of the input 1-form).  One workgroup owns a
-// tile of TILE^3 elements and walks its Gauss points plane by plane in z; each
-// plane is contracted with the 1D tables in three passes (z, y, x) to the
-// point values, multiplied by the 3x3 metric, and contracted back (x, y, z).
-// Outputs are accumulated in LDS over the tile's window of basis functions and
-// written as a patch; neighbouring patches overlap and are summed, in a fixed
-// order, by the solve kernel that consumes them (no atomics: bitwise
-// deterministic).
+// tile of TILE^3 elements and one thread owns one (x, y) Gauss-point column
+// of it.  Sum factorisation in three parts:
+//   1. the tile's coefficient window is contracted along y and x once (LDS),
+//      leaving each thread a register column A[cz] over the z window;
+//   2. the thread walks its column's Gauss points in z without barriers: z
+//      contraction from A, the 3x3 metric (streamed from HBM, the only large
+//      operand), and the z integral accumulated into a register column R[cz];
+//   3. the R columns are contracted back along x and y once (LDS).
+// Outputs cover the tile's window of basis functions and are written as a
+// patch; neighbouring patches overlap and are summed, in a fixed order, by the
+// solve kernel that consumes them (no atomics: bitwise deterministic).
 // ===========================================================================
 template <int P>
 struct MassCfg {
@@ -63,10 +67,10 @@ int64_t patch_size(int p, int space, int ntile, int64_t off[3]) {
 
 __device__ inline int tag_dim(int tag, int n0, int n1) { return (tag == PV || tag == DD) ? n0 : n1; }
 
-// load one component window of a field into LDS (zero outside the space)
+// value of one entry of a component window of a field (zero outside the space)
 template <int P, class L>
-__device__ inline void load_window(double* dst, const double* __restrict__ src, const int dims[3],
-                                   int tx, int ty, int tz, int n0, int n1, int i) {
+__device__ inline double window_value(const double* __restrict__ src, const int dims[3], int tx, int ty, int tz,
+                                      int n0, int n1, int i) {
     const int lx = i % L::Wx, ly = (i / L::Wx) % L::Wy, lz = i / L::plane;
     const int gx = tx * TILE + tag_offset(L::tx) + lx;
     const int gy = ty * TILE + tag_offset(L::ty) + ly;
@@ -75,7 +79,32 @@ __device__ inline void load_window(double* dst, const double* __restrict__ src, 
     if (gx >= 0 && gx < tag_dim(L::tx, n0, n1) && gy >= 0 && gy < tag_dim(L::ty, n0, n1) && gz >= 0 &&
         gz < tag_dim(L::tz, n0, n1))
         v = src[(int64_t(gz) * dims[1] + gy) * dims[2] + gx];
-    dst[i] = v;
+    return v;
+}
+
+// the three component windows of a field into LDS (contiguous, component after
+// component); every load of a thread is issued before its first LDS store
+template <int P, class L0, class L1, class L2, int NT>
+__device__ inline void load_windows(double* dst, const double* __restrict__ src, const int64_t comp_off[3],
+                                    const int dims[3][3], int tx, int ty, int tz, int n0, int n1, int tid) {
+    constexpr int TOT = L0::size + L1::size + L2::size;
+    constexpr int IT = (TOT + NT - 1) / NT;
+    double r[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int i = tid + k * NT;
+        r[k] = 0.0;
+        if (i < L0::size) r[k] = window_value<P, L0>(src + comp_off[0], dims[0], tx, ty, tz, n0, n1, i);
+        else if (i < L0::size + L1::size)
+            r[k] = window_value<P, L1>(src + comp_off[1], dims[1], tx, ty, tz, n0, n1, i - L0::size);
+        else if (i < TOT)
+            r[k] = window_value<P, L2>(src + comp_off[2], dims[2], tx, ty, tz, n0, n1, i - L0::size - L1::size);
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int i = tid + k * NT;
+        if (i < TOT) dst[i] = r[k];
+    }
 }
 
 // curl of the 1-form window into component C of the 2-form window:
@@ -99,74 +128,111 @@ __device__ inline double curl_at(const double* s0, const double* s1, const doubl
     return (sa[ia + da] - sa[ia]) - (sb[ib + db] - sb[ib]);
 }
 
-template <int P, class L>
-__device__ inline void stage_z(const double* xin, double* zpl, const double* __restrict__ t, int lez, int i) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < L::Kz; ++j) s += t[j] * xin[(lez + j) * L::plane + i];
-    zpl[i] = s;
+// The tile that owns global index g of a window along one axis: the tile t with
+// t * TILE <= g - offset < (t + 1) * TILE (the last tile also owns the tail).
+template <int TAG>
+__device__ inline int owner_tile(int g, int nt) {
+    int t = (g - tag_offset(TAG)) / TILE;
+    return t > nt - 1 ? nt - 1 : t;
 }
 
+// track[g] += alpha * window value, for the window entries this tile owns
 template <int P, class L>
-__device__ inline void stage_y(const double* zpl, double* ypl, const double* __restrict__ tab, int ty, int i) {
-    constexpr int NQ = P + 1;
-    const int lx = i % L::Wx, qy = i / L::Wx;
-    const int ley = qy / NQ, iqy = qy % NQ;
-    const double* t = tab + ((ty * TILE + ley) * NQ + iqy) * L::Ky;
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < L::Ky; ++j) s += t[j] * zpl[(ley + j) * L::Wx + lx];
-    ypl[i] = s;
+__device__ inline void track_owned(double* __restrict__ tr, const int dims[3], const double* xw, double alpha,
+                                   int tx, int ty, int tz, int nt, int i) {
+    const int lx = i % L::Wx, ly = (i / L::Wx) % L::Wy, lz = i / L::plane;
+    const int gx = tx * TILE + tag_offset(L::tx) + lx;
+    const int gy = ty * TILE + tag_offset(L::ty) + ly;
+    const int gz = tz * TILE + tag_offset(L::tz) + lz;
+    if (gx < 0 || gx >= dims[2] || gy < 0 || gy >= dims[1] || gz < 0 || gz >= dims[0]) return;
+    if (owner_tile<L::tx>(gx, nt) != tx || owner_tile<L::ty>(gy, nt) != ty || owner_tile<L::tz>(gz, nt) != tz)
+        return;
+    const int64_t k = (int64_t(gz) * dims[1] + gy) * dims[2] + gx;
+    tr[k] += alpha * xw[i];
 }
 
-template <int P, class L>
-__device__ inline double stage_x(const double* ypl, const double* __restrict__ tab, int tx, int qy, int qx) {
-    constexpr int NQ = P + 1;
-    const int lex = qx / NQ, iqx = qx % NQ;
-    const double* t = tab + ((tx * TILE + lex) * NQ + iqx) * L::Kx;
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < L::Kx; ++j) s += t[j] * ypl[qy * L::Wx + lex + j];
-    return s;
-}
+// Table slot of axis a: 0 = the tag of the component along a, 1 = the tag of
+// the two components across a.
+template <int SPACE>
+__device__ constexpr int slot_of(int c, int a) { return c == a ? 0 : 1; }
 
-template <int P, class L>
-__device__ inline void stage_xt(const double* uq, double* xt, const double* __restrict__ tab, int tx, int i) {
-    constexpr int NQ = P + 1, Q = TILE * NQ;
-    const int lx = i % L::Wx, qy = i / L::Wx;
-    double s = 0.0;
+// Per-component register columns: A (values of the input after the x and y
+// contractions, one per z-window entry) and R (z-accumulated integrals).
+template <int P, class L, int NQ, int Q>
+__device__ inline void contract_xy(const double* __restrict__ xw, double* bb, const double* tabx,
+                                   const double* taby, double (&Acol)[L::Wz], int tid, int NT, int qy, int qx,
+                                   bool active) {
+    // y contraction of every z-plane of the window: bb[cz][qy][lx]
+    for (int i = tid; i < L::Wz * Q * L::Wx; i += NT) {
+        const int cz = i / (Q * L::Wx), r = i % (Q * L::Wx);
+        const int q = r / L::Wx, lx = r % L::Wx;
+        const int le = q / NQ, iq = q % NQ;
+        const double* t = taby + (le * NQ + iq) * L::Ky;
+        const double* x = xw + (cz * L::Wy + le) * L::Wx + lx;
+        double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < L::Kx; ++j) {
-        const int lex = lx - j;
-        if (lex < 0 || lex >= TILE) continue;
-        const double* t = tab + ((tx * TILE + lex) * NQ) * L::Kx + j;
-#pragma unroll
-        for (int iq = 0; iq < NQ; ++iq) s += t[iq * L::Kx] * uq[qy * Q + lex * NQ + iq];
+        for (int j = 0; j < L::Ky; ++j) s += t[j] * x[j * L::Wx];
+        bb[i] = s;
     }
-    xt[i] = s;
-}
-
-template <int P, class L>
-__device__ inline void stage_yt(const double* xt, double* yt, const double* __restrict__ tab, int ty, int i) {
-    constexpr int NQ = P + 1;
-    const int lx = i % L::Wx, ly = i / L::Wx;
-    double s = 0.0;
+    __syncthreads();
+    // x contraction into this thread's register column
+    if (active) {
+        const int le = qx / NQ, iq = qx % NQ;
+        double phi[L::Kx];
 #pragma unroll
-    for (int j = 0; j < L::Ky; ++j) {
-        const int ley = ly - j;
-        if (ley < 0 || ley >= TILE) continue;
-        const double* t = tab + ((ty * TILE + ley) * NQ) * L::Ky + j;
+        for (int j = 0; j < L::Kx; ++j) phi[j] = tabx[(le * NQ + iq) * L::Kx + j];
 #pragma unroll
-        for (int iq = 0; iq < NQ; ++iq) s += t[iq * L::Ky] * xt[(ley * NQ + iq) * L::Wx + lx];
+        for (int cz = 0; cz < L::Wz; ++cz) {
+            const double* b = bb + (cz * Q + qy) * L::Wx + le;
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < L::Kx; ++j) s += phi[j] * b[j];
+            Acol[cz] = s;
+        }
     }
-    yt[i] = s;
+    __syncthreads();
 }
 
-template <int P, class L>
-__device__ inline void stage_zt(const double* yt, double* acc, const double* __restrict__ t, int lez, int i) {
-    const double v = yt[i];
+template <int P, class L, int NQ, int Q>
+__device__ inline void integrate_xy(const double (&Rcol)[L::Wz], double* rb, double* bb, const double* tabx,
+                                    const double* taby, double* __restrict__ out, int tid, int NT, int qy, int qx,
+                                    bool active) {
+    if (active) {
 #pragma unroll
-    for (int j = 0; j < L::Kz; ++j) acc[(lez + j) * L::plane + i] += t[j] * v;
+        for (int cz = 0; cz < L::Wz; ++cz) rb[(cz * Q + qy) * Q + qx] = Rcol[cz];
+    }
+    __syncthreads();
+    // transposed x contraction: bb[cz][qy][lx]
+    for (int i = tid; i < L::Wz * Q * L::Wx; i += NT) {
+        const int cz = i / (Q * L::Wx), r = i % (Q * L::Wx);
+        const int q = r / L::Wx, lx = r % L::Wx;
+        const double* row = rb + (cz * Q + q) * Q;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < L::Kx; ++j) {
+            const int le = lx - j;
+            if (le < 0 || le >= TILE) continue;
+#pragma unroll
+            for (int iq = 0; iq < NQ; ++iq) s += tabx[(le * NQ + iq) * L::Kx + j] * row[le * NQ + iq];
+        }
+        bb[i] = s;
+    }
+    __syncthreads();
+    // transposed y contraction straight into the tile's patch
+    for (int i = tid; i < L::size; i += NT) {
+        const int cz = i / L::plane, r = i % L::plane;
+        const int ly = r / L::Wx, lx = r % L::Wx;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < L::Ky; ++j) {
+            const int le = ly - j;
+            if (le < 0 || le >= TILE) continue;
+#pragma unroll
+            for (int iq = 0; iq < NQ; ++iq)
+                s += taby[(le * NQ + iq) * L::Ky + j] * bb[(cz * Q + le * NQ + iq) * L::Wx + lx];
+        }
+        out[i] = s;
+    }
 }
 
 template <int P, int SPACE, bool CURL>
@@ -179,39 +245,50 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
     using S0 = Lay<P, SRC, 0>;
     using S1 = Lay<P, SRC, 1>;
     using S2 = Lay<P, SRC, 2>;
-    // LDS map: input window | accumulators | 1-form window | plane scratch
-    constexpr int OX0 = 0, OX1 = OX0 + L0::size, OX2 = OX1 + L1::size, OXE = OX2 + L2::size;
-    constexpr int OA0 = OXE, OA1 = OA0 + L0::size, OA2 = OA1 + L1::size, OAE = OA2 + L2::size;
-    constexpr int OS0 = OAE, OS1 = OS0 + (CURL ? S0::size : 0), OS2 = OS1 + (CURL ? S1::size : 0),
-                  OSE = OS2 + (CURL ? S2::size : 0);
-    // z-contracted plane / y-transposed plane share storage
-    constexpr int OZ0 = OSE, OZ1 = OZ0 + L0::plane, OZ2 = OZ1 + L1::plane, OZE = OZ2 + L2::plane;
-    // y-contracted rows / x-transposed rows share storage
-    constexpr int OY0 = OZE, OY1 = OY0 + Q * L0::Wx, OY2 = OY1 + Q * L1::Wx, OYE = OY2 + Q * L2::Wx;
-    constexpr int OU0 = OYE, OU1 = OU0 + Q * Q, OU2 = OU1 + Q * Q, OUE = OU2 + Q * Q;
-    __shared__ double sm[OUE];
+    constexpr int KMAX = P + 1;
+    constexpr int TSL = TILE * NQ * KMAX;  // one table slice
+    // LDS map: tables | [1-form windows, 2-form windows] aliased later by the
+    // z-integral planes | one y/x contraction buffer
+    constexpr int SW = CURL ? S0::size + S1::size + S2::size : 0;
+    constexpr int XW = L0::size + L1::size + L2::size;
+    constexpr int WZM = L0::Wz > L1::Wz ? (L0::Wz > L2::Wz ? L0::Wz : L2::Wz) : (L1::Wz > L2::Wz ? L1::Wz : L2::Wz);
+    constexpr int RB = WZM * Q * Q;
+    constexpr int R0 = (SW + XW) > RB ? (SW + XW) : RB;
+    constexpr int BB0 = L0::Wz * Q * L0::Wx, BB1 = L1::Wz * Q * L1::Wx, BB2 = L2::Wz * Q * L2::Wx;
+    constexpr int BB = BB0 > BB1 ? (BB0 > BB2 ? BB0 : BB2) : (BB1 > BB2 ? BB1 : BB2);
+    constexpr int OT = 0, OR = OT + 6 * TSL, OB = OR + R0;
+    constexpr int OS0 = OR, OS1 = OS0 + (CURL ? S0::size : 0), OS2 = OS1 + (CURL ? S1::size : 0);
+    constexpr int OX0 = OR + SW, OX1 = OX0 + L0::size, OX2 = OX1 + L1::size;
+    __shared__ double sm[OB + BB];
 
     const int tid = threadIdx.x;
     const int tile = blockIdx.x;
     const int b = blockIdx.y;
     const int nt = A.ntile;
     const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
+    const int tcoord[3] = {tx, ty, tz};
     const double* src = A.src + int64_t(b) * A.src_stride;
+    const int qy = tid / Q, qx = tid % Q;
+    const bool active = tid < Q * Q;
+    // the first two Gauss-point planes of the metric are requested before the
+    // window set-up so that their latency overlaps it
+    const double* gm = A.metric + int64_t(tile) * Q * 6 * Q * Q + qy * Q + qx;
+    double g[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g[k] = active ? __builtin_nontemporal_load(gm + k * Q * Q) : 0.0;
 
-    // ---- input window (with the curl fused) ----
+    // ---- 1D tables of the tile: [axis][slot][element][point][function] ----
+    for (int i = tid; i < 6 * TSL; i += NT) {
+        const int a = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
+        const int tag = slot == 0 ? space_tag(SPACE, a, a) : space_tag(SPACE, (a + 1) % 3, a);
+        const int K = tag_support(P, tag);
+        if (k < TILE * NQ * K) sm[OT + i] = A.tab[A.tab_off[tag] + int64_t(tcoord[a]) * TILE * NQ * K + k];
+    }
+    // ---- input windows (curl fused) ----
     if (CURL) {
-        for (int i = tid; i < S0::size + S1::size + S2::size; i += NT) {
-            if (i < S0::size)
-                load_window<P, S0>(sm + OS0, src + A.src_comp_off[0], A.src_dims[0], tx, ty, tz, A.n0, A.n1, i);
-            else if (i < S0::size + S1::size)
-                load_window<P, S1>(sm + OS1, src + A.src_comp_off[1], A.src_dims[1], tx, ty, tz, A.n0, A.n1,
-                                   i - S0::size);
-            else
-                load_window<P, S2>(sm + OS2, src + A.src_comp_off[2], A.src_dims[2], tx, ty, tz, A.n0, A.n1,
-                                   i - S0::size - S1::size);
-        }
+        load_windows<P, S0, S1, S2, NT>(sm + OS0, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
         __syncthreads();
-        for (int i = tid; i < L0::size + L1::size + L2::size; i += NT) {
+        for (int i = tid; i < XW; i += NT) {
             if (i < L0::size)
                 sm[OX0 + i] = curl_at<P, SRC, SPACE, 0>(sm + OS0, sm + OS1, sm + OS2, i);
             else if (i < L0::size + L1::size)
@@ -220,105 +297,100 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
                 sm[OX2 + i - L0::size - L1::size] =
                     curl_at<P, SRC, SPACE, 2>(sm + OS0, sm + OS1, sm + OS2, i - L0::size - L1::size);
         }
-    } else {
-        for (int i = tid; i < L0::size + L1::size + L2::size; i += NT) {
-            if (i < L0::size)
-                load_window<P, L0>(sm + OX0, src + A.src_comp_off[0], A.src_dims[0], tx, ty, tz, A.n0, A.n1, i);
-            else if (i < L0::size + L1::size)
-                load_window<P, L1>(sm + OX1, src + A.src_comp_off[1], A.src_dims[1], tx, ty, tz, A.n0, A.n1,
-                                   i - L0::size);
-            else
-                load_window<P, L2>(sm + OX2, src + A.src_comp_off[2], A.src_dims[2], tx, ty, tz, A.n0, A.n1,
-                                   i - L0::size - L1::size);
+        if (A.track) {
+            __syncthreads();
+            double* tr = A.track + int64_t(b) * A.track_stride;
+            for (int i = tid; i < XW; i += NT) {
+                if (i < L0::size)
+                    track_owned<P, L0>(tr + A.track_comp_off[0], A.track_dims[0], sm + OX0, A.track_alpha, tx, ty,
+                                       tz, nt, i);
+                else if (i < L0::size + L1::size)
+                    track_owned<P, L1>(tr + A.track_comp_off[1], A.track_dims[1], sm + OX1, A.track_alpha, tx, ty,
+                                       tz, nt, i - L0::size);
+                else
+                    track_owned<P, L2>(tr + A.track_comp_off[2], A.track_dims[2], sm + OX2, A.track_alpha, tx, ty,
+                                       tz, nt, i - L0::size - L1::size);
+            }
         }
+    } else {
+        load_windows<P, L0, L1, L2, NT>(sm + OX0, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
     }
-    for (int i = tid; i < OAE - OA0; i += NT) sm[OA0 + i] = 0.0;
     __syncthreads();
 
-    const double* tab0x = A.tab + A.tab_off[L0::tx];
-    const double* tab0y = A.tab + A.tab_off[L0::ty];
-    const double* tab0z = A.tab + A.tab_off[L0::tz];
-    const double* tab1x = A.tab + A.tab_off[L1::tx];
-    const double* tab1y = A.tab + A.tab_off[L1::ty];
-    const double* tab1z = A.tab + A.tab_off[L1::tz];
-    const double* tab2x = A.tab + A.tab_off[L2::tx];
-    const double* tab2y = A.tab + A.tab_off[L2::ty];
-    const double* tab2z = A.tab + A.tab_off[L2::tz];
+    const double* T = sm + OT;
+    auto tab = [&](int a, int slot) { return T + (a * 2 + slot) * TSL; };
 
-    const int qy = tid / Q, qx = tid % Q;
-    const bool active = tid < Q * Q;
-    const int ex = tx * TILE + qx / NQ, ey = ty * TILE + qy / NQ;
-    const double* metric_tile = A.metric + int64_t(tile) * Q * 6 * Q * Q;
+    // ---- x and y contractions of the whole window, once per tile ----
+    double A0[L0::Wz], A1[L1::Wz], A2[L2::Wz];
+    contract_xy<P, L0, NQ, Q>(sm + OX0, sm + OB, tab(0, 0), tab(1, 1), A0, tid, NT, qy, qx, active);
+    contract_xy<P, L1, NQ, Q>(sm + OX1, sm + OB, tab(0, 1), tab(1, 0), A1, tid, NT, qy, qx, active);
+    contract_xy<P, L2, NQ, Q>(sm + OX2, sm + OB, tab(0, 1), tab(1, 1), A2, tid, NT, qy, qx, active);
 
-    for (int qz = 0; qz < Q; ++qz) {
-        const int lez = qz / NQ, iqz = qz % NQ, ez = tz * TILE + lez;
-        const double* t0z = tab0z + (ez * NQ + iqz) * L0::Kz;
-        const double* t1z = tab1z + (ez * NQ + iqz) * L1::Kz;
-        const double* t2z = tab2z + (ez * NQ + iqz) * L2::Kz;
-        // prefetch this thread's metric entries early
-        double g[6] = {0, 0, 0, 0, 0, 0};
-        double ig = 1.0;
-        if (active) {
-            const double* gm = metric_tile + int64_t(qz) * 6 * Q * Q + qy * Q + qx;
+    // ---- stream the Gauss-point planes: z contraction, metric, z integral ----
+    double R0c[L0::Wz], R1c[L1::Wz], R2c[L2::Wz];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) g[k] = gm[k * Q * Q];
-            if (A.inv_gamma) ig = A.inv_gamma[(int64_t(ez) * A.npad + ey) * A.npad + ex];
+    for (int k = 0; k < L0::Wz; ++k) R0c[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < L1::Wz; ++k) R1c[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < L2::Wz; ++k) R2c[k] = 0.0;
+    if (active) {
+        const int ex = tx * TILE + qx / NQ, ey = ty * TILE + qy / NQ;
+        double ig[TILE];
+#pragma unroll
+        for (int le = 0; le < TILE; ++le)
+            ig[le] = A.inv_gamma ? A.inv_gamma[(int64_t(tz * TILE + le) * A.npad + ey) * A.npad + ex] : 1.0;
+        const double* tz0 = tab(2, 1);  // components 0 and 1 are across z
+        const double* tz2 = tab(2, 0);  // component 2 is along z
+#pragma unroll
+        for (int le = 0; le < TILE; ++le) {
+#pragma unroll
+            for (int iq = 0; iq < NQ; ++iq) {
+                const int qz = le * NQ + iq;
+                double gn[6];  // next plane in flight while this one is used
+                if (qz + 1 < Q) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        gn[k] = __builtin_nontemporal_load(gm + int64_t(qz + 1) * 6 * Q * Q + k * Q * Q);
+                }
+                const double* t0 = tz0 + (le * NQ + iq) * L0::Kz;
+                const double* t2 = tz2 + (le * NQ + iq) * L2::Kz;
+                double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+                for (int j = 0; j < L0::Kz; ++j) v0 += t0[j] * A0[le + j];
+#pragma unroll
+                for (int j = 0; j < L1::Kz; ++j) v1 += t0[j] * A1[le + j];
+#pragma unroll
+                for (int j = 0; j < L2::Kz; ++j) v2 += t2[j] * A2[le + j];
+                const double s = ig[le];
+                const double u0 = s * (g[0] * v0 + g[3] * v1 + g[4] * v2);
+                const double u1 = s * (g[3] * v0 + g[1] * v1 + g[5] * v2);
+                const double u2 = s * (g[4] * v0 + g[5] * v1 + g[2] * v2);
+#pragma unroll
+                for (int j = 0; j < L0::Kz; ++j) R0c[le + j] += t0[j] * u0;
+#pragma unroll
+                for (int j = 0; j < L1::Kz; ++j) R1c[le + j] += t0[j] * u1;
+#pragma unroll
+                for (int j = 0; j < L2::Kz; ++j) R2c[le + j] += t2[j] * u2;
+                if (qz + 1 < Q) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) g[k] = gn[k];
+                }
+            }
         }
-        // z pass
-        for (int i = tid; i < L0::plane + L1::plane + L2::plane; i += NT) {
-            if (i < L0::plane) stage_z<P, L0>(sm + OX0, sm + OZ0, t0z, lez, i);
-            else if (i < L0::plane + L1::plane) stage_z<P, L1>(sm + OX1, sm + OZ1, t1z, lez, i - L0::plane);
-            else stage_z<P, L2>(sm + OX2, sm + OZ2, t2z, lez, i - L0::plane - L1::plane);
-        }
-        __syncthreads();
-        // y pass
-        for (int i = tid; i < Q * (L0::Wx + L1::Wx + L2::Wx); i += NT) {
-            if (i < Q * L0::Wx) stage_y<P, L0>(sm + OZ0, sm + OY0, tab0y, ty, i);
-            else if (i < Q * (L0::Wx + L1::Wx)) stage_y<P, L1>(sm + OZ1, sm + OY1, tab1y, ty, i - Q * L0::Wx);
-            else stage_y<P, L2>(sm + OZ2, sm + OY2, tab2y, ty, i - Q * (L0::Wx + L1::Wx));
-        }
-        __syncthreads();
-        // x pass, metric, store point values
-        if (active) {
-            const double v0 = stage_x<P, L0>(sm + OY0, tab0x, tx, qy, qx);
-            const double v1 = stage_x<P, L1>(sm + OY1, tab1x, tx, qy, qx);
-            const double v2 = stage_x<P, L2>(sm + OY2, tab2x, tx, qy, qx);
-            sm[OU0 + qy * Q + qx] = ig * (g[0] * v0 + g[3] * v1 + g[4] * v2);
-            sm[OU1 + qy * Q + qx] = ig * (g[3] * v0 + g[1] * v1 + g[5] * v2);
-            sm[OU2 + qy * Q + qx] = ig * (g[4] * v0 + g[5] * v1 + g[2] * v2);
-        }
-        __syncthreads();
-        // x^T pass
-        for (int i = tid; i < Q * (L0::Wx + L1::Wx + L2::Wx); i += NT) {
-            if (i < Q * L0::Wx) stage_xt<P, L0>(sm + OU0, sm + OY0, tab0x, tx, i);
-            else if (i < Q * (L0::Wx + L1::Wx)) stage_xt<P, L1>(sm + OU1, sm + OY1, tab1x, tx, i - Q * L0::Wx);
-            else stage_xt<P, L2>(sm + OU2, sm + OY2, tab2x, tx, i - Q * (L0::Wx + L1::Wx));
-        }
-        __syncthreads();
-        // y^T pass
-        for (int i = tid; i < L0::plane + L1::plane + L2::plane; i += NT) {
-            if (i < L0::plane) stage_yt<P, L0>(sm + OY0, sm + OZ0, tab0y, ty, i);
-            else if (i < L0::plane + L1::plane) stage_yt<P, L1>(sm + OY1, sm + OZ1, tab1y, ty, i - L0::plane);
-            else stage_yt<P, L2>(sm + OY2, sm + OZ2, tab2y, ty, i - L0::plane - L1::plane);
-        }
-        __syncthreads();
-        // z^T accumulation (each (c, y, x) column owned by one thread)
-        for (int i = tid; i < L0::plane + L1::plane + L2::plane; i += NT) {
-            if (i < L0::plane) stage_zt<P, L0>(sm + OZ0, sm + OA0, t0z, lez, i);
-            else if (i < L0::plane + L1::plane) stage_zt<P, L1>(sm + OZ1, sm + OA1, t1z, lez, i - L0::plane);
-            else stage_zt<P, L2>(sm + OZ2, sm + OA2, t2z, lez, i - L0::plane - L1::plane);
-        }
-        __syncthreads();
     }
-    // write the tile's patch
+    __syncthreads();  // the window region is reused for the z-integral planes
+
+    // ---- transposed x and y contractions, once per tile, into the patch ----
     double* out = A.patch + int64_t(b) * A.patch_stride;
-    for (int i = tid; i < L0::size + L1::size + L2::size; i += NT) {
-        if (i < L0::size) out[A.patch_comp_off[0] + int64_t(tile) * L0::size + i] = sm[OA0 + i];
-        else if (i < L0::size + L1::size)
-            out[A.patch_comp_off[1] + int64_t(tile) * L1::size + (i - L0::size)] = sm[OA0 + i];
-        else
-            out[A.patch_comp_off[2] + int64_t(tile) * L2::size + (i - L0::size - L1::size)] = sm[OA0 + i];
-    }
+    integrate_xy<P, L0, NQ, Q>(R0c, sm + OR, sm + OB, tab(0, 0), tab(1, 1),
+                               out + A.patch_comp_off[0] + int64_t(tile) * L0::size, tid, NT, qy, qx, active);
+    __syncthreads();
+    integrate_xy<P, L1, NQ, Q>(R1c, sm + OR, sm + OB, tab(0, 1), tab(1, 0),
+                               out + A.patch_comp_off[1] + int64_t(tile) * L1::size, tid, NT, qy, qx, active);
+    __syncthreads();
+    integrate_xy<P, L2, NQ, Q>(R2c, sm + OR, sm + OB, tab(0, 1), tab(1, 1),
+                               out + A.patch_comp_off[2] + int64_t(tile) * L2::size, tid, NT, qy, qx, active);
 }
 
 void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s) {
@@ -340,134 +412,259 @@ void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipS
 }
 
 // ===========================================================================
-// Pairing solves (eqs. (4.4), (4.5)): block c of K1 or K~1 is A_z (x) A_y (x) A_x,
-// so K^{-1} applies A_x^{-1}, A_y^{-1}, A_z^{-1} along the lines of each axis.
-// Each 1D solve is a banded forward/backward substitution with the
-// precomputed LU factors (half bandwidth W = p-1).
+// Patch gather: y_i = sum of the tile patches covering basis function i, in a
+// fixed order (tiles by increasing z, y, x).  One thread per output; the
+// windows are compile-time per component, the candidate tiles come from shifts.
 // ===========================================================================
-template <int W>
-__device__ inline void band_solve_line(double* v, int n, int stride, const double* __restrict__ L,
-                                       const double* __restrict__ U, const double* __restrict__ dinv) {
-    double prev[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) prev[k] = 0.0;
-    for (int i = 0; i < n; ++i) {
-        double s = v[i * stride];
-#pragma unroll
-        for (int k = 0; k < W; ++k) s -= L[i * W + k] * prev[k];
-#pragma unroll
-        for (int k = W - 1; k > 0; --k) prev[k] = prev[k - 1];
-        prev[0] = s;
-        v[i * stride] = s;
-    }
-#pragma unroll
-    for (int k = 0; k < W; ++k) prev[k] = 0.0;
-    for (int i = n - 1; i >= 0; --i) {
-        double s = v[i * stride];
-#pragma unroll
-        for (int k = 0; k < W; ++k) s -= U[i * W + k] * prev[k];
-        s *= dinv[i];
-#pragma unroll
-        for (int k = W - 1; k > 0; --k) prev[k] = prev[k - 1];
-        prev[0] = s;
-        v[i * stride] = s;
-    }
-}
-
-struct FacView {
-    const double *L, *U, *dinv;
-};
-template <int W>
-__device__ inline FacView fac_view(const double* fac, const int64_t* fac_off, int id, int n) {
-    const double* base = fac + fac_off[id];
-    return {base, base + int64_t(n) * W, base + int64_t(2) * n * W};
-}
-
-// patch window geometry along one axis for gathering
-template <int P>
-__device__ inline int tag_window(int tag) { return TILE + tag_support(P, tag) - 1; }
-
-template <int P, int SPACE>
-__device__ inline double gather_patch(const XYArgs& A, const double* patch, int c, int gz, int gy, int gx) {
-    const int nt = A.ntile;
-    int tg[3], W[3], g[3] = {gx, gy, gz};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        tg[a] = space_tag(SPACE, c, a);
-        W[a] = TILE + tag_support(P, tg[a]) - 1;
-    }
-    int lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int r = g[a] - tag_offset(tg[a]);  // >= 0
-        int t1 = r / TILE;
-        if (t1 > nt - 1) t1 = nt - 1;
-        int t0 = t1;
-        if (t1 - 1 >= 0 && r - (t1 - 1) * TILE < W[a]) t0 = t1 - 1;
-        lo[a] = t0;
-        hi[a] = t1;
-    }
-    const double* base = patch + A.patch_comp_off[c];
-    const int size = W[0] * W[1] * W[2];
+template <int P, int SPACE, int C>
+__device__ inline double gather_one(const double* __restrict__ patch, int nt, int gz, int gy, int gx) {
+    using L = Lay<P, SPACE, C>;
+    const int rx = gx - tag_offset(L::tx), ry = gy - tag_offset(L::ty), rz = gz - tag_offset(L::tz);
+    int hx = rx / TILE, hy = ry / TILE, hz = rz / TILE;
+    hx = hx > nt - 1 ? nt - 1 : hx;
+    hy = hy > nt - 1 ? nt - 1 : hy;
+    hz = hz > nt - 1 ? nt - 1 : hz;
     double s = 0.0;
-    for (int tz = lo[2]; tz <= hi[2]; ++tz)
-        for (int ty = lo[1]; ty <= hi[1]; ++ty)
-            for (int tx = lo[0]; tx <= hi[0]; ++tx) {
-                const int lx = g[0] - tx * TILE - tag_offset(tg[0]);
-                const int ly = g[1] - ty * TILE - tag_offset(tg[1]);
-                const int lz = g[2] - tz * TILE - tag_offset(tg[2]);
-                if (lx < 0 || lx >= W[0] || ly < 0 || ly >= W[1] || lz < 0 || lz >= W[2]) continue;
+#pragma unroll
+    for (int dz = 1; dz >= 0; --dz) {
+        const int tz = hz - dz, lz = rz - tz * TILE;
+        if (tz < 0 || lz >= L::Wz) continue;
+#pragma unroll
+        for (int dy = 1; dy >= 0; --dy) {
+            const int ty = hy - dy, ly = ry - ty * TILE;
+            if (ty < 0 || ly >= L::Wy) continue;
+#pragma unroll
+            for (int dx = 1; dx >= 0; --dx) {
+                const int tx = hx - dx, lx = rx - tx * TILE;
+                if (tx < 0 || lx >= L::Wx) continue;
                 const int64_t tile = (int64_t(tz) * nt + ty) * nt + tx;
-                s += base[tile * size + (lz * W[1] + ly) * W[0] + lx];
+                s += patch[tile * L::size + (lz * L::Wy + ly) * L::Wx + lx];
             }
+        }
+    }
     return s;
 }
 
 template <int P, int SPACE>
-__global__ void __launch_bounds__(256) xy_kernel(const XYArgs A) {
-    constexpr int W = P - 1;
-    extern __shared__ double plane[];
-    const int c = blockIdx.y, b = blockIdx.z, iz = blockIdx.x;
-    const int nz = A.dims[c][0], ny = A.dims[c][1], nx = A.dims[c][2];
-    if (iz >= nz) return;
-    const int nxp = nx | 1;  // odd row stride: x-lines hit distinct LDS banks
-    const int tid = threadIdx.x;
-    // gather
-    if (A.from_patch) {
-        const double* patch = A.patch + int64_t(b) * A.patch_stride;
-        for (int i = tid; i < nx * ny; i += blockDim.x) {
-            const int x = i % nx, y = i / nx;
-            plane[y * nxp + x] = gather_patch<P, SPACE>(A, patch, c, iz, y, x);
-        }
-    } else {
-        const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c] + int64_t(iz) * nx * ny;
-        for (int i = tid; i < nx * ny; i += blockDim.x) plane[(i / nx) * nxp + (i % nx)] = in[i];
+__global__ void __launch_bounds__(256) gather_kernel(const GatherArgs A, int64_t n) {
+    const int b = blockIdx.y;
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int c = i >= A.comp_off[2] ? 2 : (i >= A.comp_off[1] ? 1 : 0);
+    const int64_t li = i - A.comp_off[c];
+    const int nx = A.dims[c][2], ny = A.dims[c][1];
+    const int64_t row = li / nx;
+    const int x = int(li - row * nx), y = int(row % ny), z = int(row / ny);
+    const double* patch = A.patch + int64_t(b) * A.patch_stride + A.patch_comp_off[c];
+    double v;
+    if (c == 0) v = gather_one<P, SPACE, 0>(patch, A.ntile, z, y, x);
+    else if (c == 1) v = gather_one<P, SPACE, 1>(patch, A.ntile, z, y, x);
+    else v = gather_one<P, SPACE, 2>(patch, A.ntile, z, y, x);
+    A.out[int64_t(b) * A.out_stride + i] = v;
+}
+
+void launch_gather(int p, int space, const GatherArgs& a, int64_t n, int batch, hipStream_t s) {
+    dim3 grid(unsigned((n + 255) / 256), batch);
+#define LG(PP)                                                                                         \
+    if (p == PP) {                                                                                     \
+        if (space == SP_D) hipLaunchKernelGGL((gather_kernel<PP, SP_D>), grid, dim3(256), 0, s, a, n); \
+        else hipLaunchKernelGGL((gather_kernel<PP, SP_B>), grid, dim3(256), 0, s, a, n);               \
+        return;                                                                                        \
     }
-    __syncthreads();
-    // point sources: subtract g(t) s on this plane, in a fixed order
-    if (A.n_src > 0 && tid == 0) {
-        for (int k = A.src_off[b]; k < A.src_off[b + 1]; ++k) {
-            const double* pr = A.src_prof + 4 * k;
-            const double dtt = A.t_src - pr[0];
-            const double gt = pr[2] * exp(-dtt * dtt / (2.0 * pr[1] * pr[1]));
-            const double* en = A.src_entries + int64_t(k) * A.entries_per * 5;
-            for (int e = 0; e < A.entries_per; ++e) {
-                if (int(en[5 * e]) != c || int(en[5 * e + 1]) != iz) continue;
-                plane[int(en[5 * e + 2]) * nxp + int(en[5 * e + 3])] -= gt * en[5 * e + 4];
+    LG(2) LG(3) LG(4)
+#undef LG
+}
+
+// ===========================================================================
+// Pairing solves and applies (eqs. (4.2)-(4.5)): block c of K1 or K~1 is
+// A_z (x) A_y (x) A_x, so K^{-1} applies A_x^{-1}, A_y^{-1}, A_z^{-1} along the
+// lines of each axis (and K applies A_x, A_y, A_z).  Each 1D solve is a banded
+// forward/backward substitution with precomputed LU factors (half bandwidth
+// W = p-1), each 1D apply a banded product; the factors of a line are staged
+// in LDS, shared by all lines of the workgroup.
+// ===========================================================================
+// Largest line handled (N <= 72 elements, p <= 4) and the LDS size of one
+// staged factor set [L (n W) | U (n W) | dinv (n) | band (n (2W+1))].
+constexpr int KMX_LINE_MAX = 76;
+constexpr int FACTOR_MAX = 2 * KMX_LINE_MAX * 7;
+
+// Forward/backward substitution along one line.  The dependency chain runs
+// through registers only: the line values and factor coefficients of a block
+// of D steps are loaded together (one wait per block), then the D steps of the
+// chain run without touching memory except for the stores.
+template <int W>
+__device__ inline void band_solve_line(double* v, int n, int stride, const double* __restrict__ L,
+                                       const double* __restrict__ U, const double* __restrict__ dinv) {
+    constexpr int D = 8;
+    double prev[W];
+#pragma unroll
+    for (int m = 0; m < W; ++m) prev[m] = 0.0;
+    for (int i0 = 0; i0 < n; i0 += D) {
+        double xv[D], lc[D][W];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int i = i0 + k < n ? i0 + k : n - 1;
+            xv[k] = v[i * stride];
+#pragma unroll
+            for (int m = 0; m < W; ++m) lc[k][m] = L[i * W + m];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (i0 + k < n) {
+                double s = xv[k];
+#pragma unroll
+                for (int m = 0; m < W; ++m) s -= lc[k][m] * prev[m];
+#pragma unroll
+                for (int m = W - 1; m > 0; --m) prev[m] = prev[m - 1];
+                prev[0] = s;
+                v[(i0 + k) * stride] = s;
             }
         }
     }
-    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < W; ++m) prev[m] = 0.0;
+    for (int i0 = n - 1; i0 >= 0; i0 -= D) {
+        double xv[D], uc[D][W], dc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int i = i0 - k >= 0 ? i0 - k : 0;
+            xv[k] = v[i * stride];
+            dc[k] = dinv[i];
+#pragma unroll
+            for (int m = 0; m < W; ++m) uc[k][m] = U[i * W + m];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (i0 - k >= 0) {
+                double s = xv[k];
+#pragma unroll
+                for (int m = 0; m < W; ++m) s -= uc[k][m] * prev[m];
+                s *= dc[k];
+#pragma unroll
+                for (int m = W - 1; m > 0; --m) prev[m] = prev[m - 1];
+                prev[0] = s;
+                v[(i0 - k) * stride] = s;
+            }
+        }
+    }
+}
+
+// banded product of one output: sum_k band[i][k] x_{i-W+k} (the band holds
+// zeros outside the matrix, so clamped indices contribute nothing)
+template <int W>
+__device__ inline double band_row(const double* x, int n, int stride, const double* __restrict__ band, int i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2 * W + 1; ++k) {
+        int j = i - W + k;
+        j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+        s += band[i * (2 * W + 1) + k] * x[j * stride];
+    }
+    return s;
+}
+
+template <int W>
+__device__ inline void stage_factor(double* dst, const double* __restrict__ fac, int64_t off, int n, int tid,
+                                    int nt) {
+    const int len = 2 * n * (2 * W + 1);
+    for (int i = tid; i < len; i += nt) dst[i] = fac[off + i];
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) xy_kernel(const XYArgs A) {
+    constexpr int W = P - 1;
+    constexpr int SLOTS = (KMX_LINE_MAX * KMX_LINE_MAX + 255) / 256;
+    extern __shared__ double plane[];
+    __shared__ double fx[FACTOR_MAX], fy[FACTOR_MAX];
+    const int c = blockIdx.y, b = blockIdx.z, iz = blockIdx.x;
+    const int nz = A.dims[c][0], ny = A.dims[c][1], nx = A.dims[c][2];
+    if (iz >= nz) return;
+    const int nxp = nx | 1;  // odd row stride: the lines along x hit distinct LDS banks
+    const int tid = threadIdx.x;
     if (A.solve) {
-        const FacView fx = fac_view<W>(A.fac, A.fac_off, A.fac_id[c][0], nx);
-        const FacView fy = fac_view<W>(A.fac, A.fac_off, A.fac_id[c][1], ny);
-        for (int y = tid; y < ny; y += blockDim.x) band_solve_line<W>(plane + y * nxp, nx, 1, fx.L, fx.U, fx.dinv);
+        stage_factor<W>(fx, A.fac, A.fac_off[A.fac_id[c][0]], nx, tid, 256);
+        stage_factor<W>(fy, A.fac, A.fac_off[A.fac_id[c][1]], ny, tid, 256);
+    }
+    {
+        // stage the plane: rows over the 4 waves, x over the 64 lanes
+        const int lane = tid & 63, wv = tid >> 6;
+        const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c] + int64_t(iz) * nx * ny;
+        constexpr int RY = (KMX_LINE_MAX + 3) / 4;  // rows per wave
+        double r0[RY], r1[RY];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int y = wv + 4 * k;
+            r0[k] = (y < ny && lane < nx) ? in[y * nx + lane] : 0.0;
+            r1[k] = (y < ny && lane + 64 < nx) ? in[y * nx + lane + 64] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int y = wv + 4 * k;
+            if (y < ny && lane < nx) plane[y * nxp + lane] = r0[k];
+            if (y < ny && lane + 64 < nx) plane[y * nxp + lane + 64] = r1[k];
+        }
+    }
+    __syncthreads();
+    // point sources: subtract g(t) s on this plane, in a fixed order
+    if (A.n_src > 0) {
+        if (tid == 0) {
+            for (int k = A.src_off[b]; k < A.src_off[b + 1]; ++k) {
+                const double* pr = A.src_prof + 4 * k;
+                const double dtt = A.t_src - pr[0];
+                const double gt = pr[2] * exp(-dtt * dtt / (2.0 * pr[1] * pr[1]));
+                const double* en = A.src_entries + int64_t(k) * A.entries_per * 5;
+                for (int e = 0; e < A.entries_per; ++e) {
+                    if (int(en[5 * e]) != c || int(en[5 * e + 1]) != iz) continue;
+                    plane[int(en[5 * e + 2]) * nxp + int(en[5 * e + 3])] -= gt * en[5 * e + 4];
+                }
+            }
+        }
         __syncthreads();
-        for (int x = tid; x < nx; x += blockDim.x) band_solve_line<W>(plane + x, ny, nxp, fy.L, fy.U, fy.dinv);
+    }
+    if (A.solve == 1) {
+        for (int y = tid; y < ny; y += 256) band_solve_line<W>(plane + y * nxp, nx, 1, fx, fx + nx * W, fx + 2 * nx * W);
+        __syncthreads();
+        for (int x = tid; x < nx; x += 256) band_solve_line<W>(plane + x, ny, nxp, fy, fy + ny * W, fy + 2 * ny * W);
+        __syncthreads();
+    } else if (A.solve == 2) {
+        // every output of a banded product is independent: compute all of a
+        // direction into registers, then write back
+        const double* bx = fx + 2 * nx * W + nx;
+        const double* by = fy + 2 * ny * W + ny;
+        double r[SLOTS];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int i = tid + s * 256;
+            if (i < nx * ny) r[s] = band_row<W>(plane + (i / nx) * nxp, nx, 1, bx, i % nx);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int i = tid + s * 256;
+            if (i < nx * ny) plane[(i / nx) * nxp + (i % nx)] = r[s];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int i = tid + s * 256;
+            if (i < nx * ny) r[s] = band_row<W>(plane + (i % nx), ny, nxp, by, i / nx);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int i = tid + s * 256;
+            if (i < nx * ny) plane[(i / nx) * nxp + (i % nx)] = r[s];
+        }
         __syncthreads();
     }
     double* out = A.out + int64_t(b) * A.out_stride + A.comp_off[c] + int64_t(iz) * nx * ny;
-    for (int i = tid; i < nx * ny; i += blockDim.x) out[i] = plane[(i / nx) * nxp + (i % nx)];
+    {
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int y = wv; y < ny; y += 4) {
+            if (lane < nx) out[y * nx + lane] = plane[y * nxp + lane];
+            if (lane + 64 < nx) out[y * nx + lane + 64] = plane[y * nxp + lane + 64];
+        }
+    }
 }
 
 void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s) {
@@ -479,57 +676,89 @@ void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s) {
     }
     dim3 grid(nzmax, 3, batch);
     const size_t shm = size_t(smax) * sizeof(double);
-    const int space = a.gather_space;
-#define LX(PP)                                                                                         \
-    if (p == PP) {                                                                                     \
-        if (space == SP_D) hipLaunchKernelGGL((xy_kernel<PP, SP_D>), grid, dim3(256), shm, s, a);      \
-        else hipLaunchKernelGGL((xy_kernel<PP, SP_B>), grid, dim3(256), shm, s, a);                    \
-        return;                                                                                        \
+#define LX(PP)                                                                         \
+    if (p == PP) {                                                                     \
+        hipLaunchKernelGGL((xy_kernel<PP>), grid, dim3(256), shm, s, a);               \
+        return;                                                                        \
     }
     LX(2) LX(3) LX(4)
 #undef LX
 }
 
-// z solve: one thread per (x, y) column, 64 columns per workgroup staged in LDS.
+// z solve / apply: 64 (x, y) columns per workgroup staged in LDS by all 256
+// threads (coalesced rows), one thread per column for the substitution (the
+// banded apply uses all threads), then the fused update
+// out = (accumulate ? out : 0) + alpha x.
 template <int P>
-__global__ void __launch_bounds__(64) z_kernel(const ZArgs A) {
+__global__ void __launch_bounds__(256) z_kernel(const ZArgs A) {
     constexpr int W = P - 1;
+    constexpr int SLOTS = (KMX_LINE_MAX + 3) / 4;
     extern __shared__ double col[];  // [nz][64]
+    __shared__ double f[FACTOR_MAX];
     const int c = blockIdx.y, b = blockIdx.z;
     const int nz = A.dims[c][0], ny = A.dims[c][1], nx = A.dims[c][2];
     const int64_t ncol = int64_t(nx) * ny;
-    const int64_t colid = int64_t(blockIdx.x) * 64 + threadIdx.x;
-    if (int64_t(blockIdx.x) * 64 >= ncol) return;
+    const int64_t col0 = int64_t(blockIdx.x) * 64;
+    if (col0 >= ncol) return;
+    const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+    const int64_t colid = col0 + lane;
     const bool ok = colid < ncol;
+    if (A.solve) stage_factor<W>(f, A.fac, A.fac_off[A.fac_id[c]], nz, tid, 256);
     const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c];
     double* out = A.out + int64_t(b) * A.out_stride + A.comp_off[c];
-    const int t = threadIdx.x;
-    // stage the column block (loads batched so many are in flight)
-    for (int z0 = 0; z0 < nz; z0 += 8) {
-        double v[8];
+    {
+        double r[SLOTS];  // all loads of this thread in flight at once
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = (ok && z0 + k < nz) ? in[int64_t(z0 + k) * ncol + colid] : 0.0;
+        for (int s = 0; s < SLOTS; ++s) {
+            const int z = grp + 4 * s;
+            r[s] = (ok && z < nz) ? in[int64_t(z) * ncol + colid] : 0.0;
+        }
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (z0 + k < nz) col[(z0 + k) * 64 + t] = v[k];
+        for (int s = 0; s < SLOTS; ++s) {
+            const int z = grp + 4 * s;
+            if (z < nz) col[z * 64 + lane] = r[s];
+        }
     }
-    if (A.solve) {
-        const FacView fz = fac_view<W>(A.fac, A.fac_off, A.fac_id[c], nz);
-        band_solve_line<W>(col + t, nz, 64, fz.L, fz.U, fz.dinv);
+    __syncthreads();
+    if (A.solve == 1) {
+        if (grp == 0) band_solve_line<W>(col + lane, nz, 64, f, f + nz * W, f + 2 * nz * W);
+        __syncthreads();
+    } else if (A.solve == 2) {
+        const double* band = f + 2 * nz * W + nz;
+        double r[SLOTS];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int z = grp + 4 * s;
+            if (z < nz) r[s] = band_row<W>(col + lane, nz, 64, band, z);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int z = grp + 4 * s;
+            if (z < nz) col[z * 64 + lane] = r[s];
+        }
+        __syncthreads();
     }
     if (!ok) return;
     const double alpha = A.alpha;
     if (A.accumulate) {
-        for (int z0 = 0; z0 < nz; z0 += 8) {
-            double o[8];
+        double o[SLOTS];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) o[k] = (z0 + k < nz) ? out[int64_t(z0 + k) * ncol + colid] : 0.0;
+        for (int s = 0; s < SLOTS; ++s) {
+            const int z = grp + 4 * s;
+            o[s] = z < nz ? out[int64_t(z) * ncol + colid] : 0.0;
+        }
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (z0 + k < nz) out[int64_t(z0 + k) * ncol + colid] = o[k] + alpha * col[(z0 + k) * 64 + t];
+        for (int s = 0; s < SLOTS; ++s) {
+            const int z = grp + 4 * s;
+            if (z < nz) out[int64_t(z) * ncol + colid] = o[s] + alpha * col[z * 64 + lane];
         }
     } else {
-        for (int z = 0; z < nz; ++z) out[int64_t(z) * ncol + colid] = alpha * col[z * 64 + t];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int z = grp + 4 * s;
+            if (z < nz) out[int64_t(z) * ncol + colid] = alpha * col[z * 64 + lane];
+        }
     }
 }
 
@@ -545,7 +774,7 @@ void launch_z(int p, const ZArgs& a, int batch, hipStream_t s) {
     const size_t shm = size_t(nzmax) * 64 * sizeof(double);
 #define LZ(PP)                                                                \
     if (p == PP) {                                                            \
-        hipLaunchKernelGGL((z_kernel<PP>), grid, dim3(64), shm, s, a);        \
+        hipLaunchKernelGGL((z_kernel<PP>), grid, dim3(256), shm, s, a);       \
         return;                                                               \
     }
     LZ(2) LZ(3) LZ(4)
@@ -592,64 +821,10 @@ void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s) {
 }
 
 // ===========================================================================
-// Pairing apply y = K x (banded Kronecker product, for energies and tests).
-// ===========================================================================
-template <int P>
-__device__ inline double kron_band_at(const double* in, const int d[3], const double* bx, const double* by,
-                                      const double* bz, int z, int y, int x) {
-    constexpr int W = P - 1, BW = 2 * W + 1;
-    double s = 0.0;
-    for (int kz = 0; kz < BW; ++kz) {
-        const int jz = z - W + kz;
-        if (jz < 0 || jz >= d[0]) continue;
-        const double az = bz[z * BW + kz];
-        for (int ky = 0; ky < BW; ++ky) {
-            const int jy = y - W + ky;
-            if (jy < 0 || jy >= d[1]) continue;
-            const double ay = az * by[y * BW + ky];
-            const double* row = in + (int64_t(jz) * d[1] + jy) * d[2];
-            double sx = 0.0;
-            for (int kx = 0; kx < BW; ++kx) {
-                const int jx = x - W + kx;
-                if (jx < 0 || jx >= d[2]) continue;
-                sx += bx[x * BW + kx] * row[jx];
-            }
-            s += ay * sx;
-        }
-    }
-    return s;
-}
-
-template <int P>
-__global__ void pairing_kernel(const PairArgs A, int64_t n) {
-    constexpr int W = P - 1;
-    const int b = blockIdx.y;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int c = 0;
-    while (c < 2 && i >= A.comp_off[c + 1]) ++c;
-    const int64_t li = i - A.comp_off[c];
-    const int* d = A.dims[c];
-    const int x = int(li % d[2]), y = int((li / d[2]) % d[1]), z = int(li / (int64_t(d[2]) * d[1]));
-    const double* bnd[3];
-    for (int a = 0; a < 3; ++a) {
-        const int nn = d[2 - a];
-        bnd[a] = A.fac + A.fac_off[A.fac_id[c][a]] + int64_t(nn) * (2 * W + 1);  // band block
-    }
-    const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c];
-    A.out[int64_t(b) * A.out_stride + i] = kron_band_at<P>(in, d, bnd[0], bnd[1], bnd[2], z, y, x);
-}
-
-void launch_pairing(int p, const PairArgs& a, int64_t n, int batch, hipStream_t s) {
-    dim3 grid(unsigned((n + 255) / 256), batch);
-    if (p == 2) hipLaunchKernelGGL(pairing_kernel<2>, grid, dim3(256), 0, s, a, n);
-    else if (p == 3) hipLaunchKernelGGL(pairing_kernel<3>, grid, dim3(256), 0, s, a, n);
-    else hipLaunchKernelGGL(pairing_kernel<4>, grid, dim3(256), 0, s, a, n);
-}
-
-// ===========================================================================
-// Energies (3.2) and the leapfrog invariant, FP64, deterministic tree sums.
-// term0 = d . (K1 e), term1 = b . (K~1 h), term2 = (K~1 h) . (D^1 e)
+// Energies (3.2) and the leapfrog invariant, FP64, deterministic tree sums,
+// from v = K1 e and u = K~1 h (computed by the line kernels in apply mode):
+//   mode 0: term0 = d . v                over X~^2
+//   mode 1: term1 = b . u, term2 = u . (D^1 e)   over X^2_{h,0}
 // ===========================================================================
 template <int NTH>
 __device__ inline void block_sum3(double v0, double v1, double v2, double* out) {
@@ -667,59 +842,45 @@ __device__ inline void block_sum3(double v0, double v1, double v2, double* out) 
         for (int k = 0; k < 3; ++k) out[k] = s[k][0];
 }
 
-template <int P>
 __global__ void __launch_bounds__(256) energy_kernel(const EnergyArgs A) {
-    constexpr int W = P - 1;
     const int b = blockIdx.y;
     const double* e = A.E + int64_t(b) * 2 * A.n_e;
-    const double* dvec = e + A.n_e;
     const double* h = A.H + int64_t(b) * 2 * A.n_h;
-    const double* bvec = h + A.n_h;
+    const double* w = A.work + int64_t(b) * A.work_stride;
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-    const int64_t nmax = A.n_e > A.n_h ? A.n_e : A.n_h;
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nmax; i += int64_t(gridDim.x) * 256) {
-        if (i < A.n_e) {  // d-space index: (K1 e)_i d_i
-            int c = 0;
-            while (c < 2 && i >= A.e_comp_off[c + 1]) ++c;
-            const int64_t li = i - A.e_comp_off[c];
-            const int* d = A.e_dims[c];
-            const int x = int(li % d[2]), y = int((li / d[2]) % d[1]), z = int(li / (int64_t(d[2]) * d[1]));
-            // band block of a factor set sits after L, U (n*W each) and dinv (n)
-            const double* bnd[3];
-            for (int a = 0; a < 3; ++a) {
-                const int nn = d[2 - a];
-                bnd[a] = A.fac + A.fac_off[a == c ? F_M : F_G] + int64_t(nn) * (2 * W + 1);
-            }
-            const double v = kron_band_at<P>(e + A.e_comp_off[c], d, bnd[0], bnd[1], bnd[2], z, y, x);
-            t0 += v * dvec[i];
-        }
-        if (i < A.n_h) {  // b-space index: (K~1 h)_i (b_i, (D^1 e)_i)
+    if (A.mode == 0) {
+        const double* dvec = e + A.n_e;
+        for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_e; i += int64_t(gridDim.x) * 256)
+            t0 += w[i] * dvec[i];
+    } else {
+        const double* bvec = h + A.n_h;
+        for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_h; i += int64_t(gridDim.x) * 256) {
             int c = 0;
             while (c < 2 && i >= A.h_comp_off[c + 1]) ++c;
             const int64_t li = i - A.h_comp_off[c];
             const int* d = A.h_dims[c];
             const int x = int(li % d[2]), y = int((li / d[2]) % d[1]), z = int(li / (int64_t(d[2]) * d[1]));
-            const double* bnd[3];
-            for (int a = 0; a < 3; ++a) {
-                const int nn = d[2 - a];
-                bnd[a] = A.fac + A.fac_off[a == c ? F_GT : F_MT] + int64_t(nn) * (2 * W + 1);
-            }
-            const double u = kron_band_at<P>(h + A.h_comp_off[c], d, bnd[0], bnd[1], bnd[2], z, y, x);
             const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            const double w = diff1(e + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
-                             diff1(e + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
-            t1 += u * bvec[i];
-            t2 += u * w;
+            const double cu = diff1(e + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
+                              diff1(e + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
+            t1 += w[i] * bvec[i];
+            t2 += w[i] * cu;
         }
     }
-    block_sum3<256>(t0, t1, t2, A.partial + (int64_t(b) * A.nblocks + blockIdx.x) * 3);
+    __shared__ double r[3];
+    block_sum3<256>(t0, t1, t2, r);
+    if (threadIdx.x == 0) {
+        double* p = A.partial + (int64_t(b) * A.nblocks + blockIdx.x) * 3;
+        if (A.mode == 0) p[0] = r[0];
+        else {
+            p[1] = r[1];
+            p[2] = r[2];
+        }
+    }
 }
 
-void launch_energy(int p, const EnergyArgs& a, int batch, hipStream_t s) {
-    dim3 grid(a.nblocks, batch);
-    if (p == 2) hipLaunchKernelGGL(energy_kernel<2>, grid, dim3(256), 0, s, a);
-    else if (p == 3) hipLaunchKernelGGL(energy_kernel<3>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(energy_kernel<4>, grid, dim3(256), 0, s, a);
+void launch_energy(int, const EnergyArgs& a, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(energy_kernel, dim3(a.nblocks, batch), dim3(256), 0, s, a);
 }
 
 __global__ void __launch_bounds__(256) energy_final_kernel(const double* partial, int nblocks, double dt,

@@ -20,32 +20,45 @@ struct MassArgs {
     int64_t src_comp_off[3];
     int src_dims[3][3];         // [c][z, y, x] of the source space
     int64_t patch_comp_off[3];  // per component, within one field's patches
+    // optional fused tracking update of the 2-form: track += track_alpha * (curl
+    // of the input), each entry written by the one tile that owns it
+    double* track;
+    int64_t track_stride;
+    double track_alpha;
+    int64_t track_comp_off[3];
+    int track_dims[3][3];
 };
 
-// Gather patches (or read a field), subtract point sources, solve along x and y.
-struct XYArgs {
-    const double* patch;        // gather source (from_patch = 1)
+// Sum the overlapping tile patches of a mass apply into a field.
+struct GatherArgs {
+    const double* patch;
     int64_t patch_stride;
     int64_t patch_comp_off[3];
-    const double* in;           // field source (from_patch = 0)
+    double* out;
+    int64_t out_stride;
+    int64_t comp_off[3];
+    int dims[3][3];
+    int ntile;
+};
+
+// Read a field, subtract point sources, solve (or apply) along x and y.
+struct XYArgs {
+    const double* in;
     int64_t in_stride;
     double* out;
     int64_t out_stride;
     int64_t comp_off[3];        // component offsets (same for in and out)
     int dims[3][3];             // [c][z, y, x]
-    int ntile;
     const double* fac;          // banded factor sets
     int64_t fac_off[8];
     int fac_id[3][3];           // [c][axis] factor id; axis 2 unused here
-    int from_patch;
-    int gather_space;           // SP_B or SP_D: layout of the patches
     // point sources (tested dipoles); n_src = 0 when none
     const double* src_entries;  // [n_src][entries_per][5] = comp, iz, iy, ix, value
     const double* src_prof;     // [n_src][4] = t0, sigma, amp, batch
     const int* src_off;         // [batch+1] dipoles of each batch member (sorted)
     int n_src, entries_per;
     double t_src;
-    int solve;                  // 0: gather only (copy to out), 1: solve x and y
+    int solve;                  // line operation: 0 none (copy), 1 solve, 2 banded apply
 };
 
 // Solve along z and finish: out = (accumulate ? out : 0) + alpha * x.
@@ -61,7 +74,7 @@ struct ZArgs {
     int fac_id[3];
     double alpha;
     int accumulate;
-    int solve;                  // 0: no z solve (plain axpy of in)
+    int solve;                  // line operation along z: 0 none, 1 solve, 2 banded apply
 };
 
 struct CurlArgs {
@@ -75,35 +88,24 @@ struct CurlArgs {
     int primal;
 };
 
-struct PairArgs {               // y = K x, banded Kronecker apply
-    const double* in;
-    int64_t in_stride;
-    double* out;
-    int64_t out_stride;
-    int64_t comp_off[3];
-    int dims[3][3];
-    const double* fac;
-    int64_t fac_off[8];
-    int fac_id[3][3];           // [c][axis]
-};
-
 struct EnergyArgs {
     const double* E;            // [e | d] per batch member
     const double* H;            // [h | b]
     int64_t n_e, n_h;
     int64_t e_comp_off[3], h_comp_off[3];
     int e_dims[3][3], h_dims[3][3];
-    const double* fac;
-    int64_t fac_off[8];
+    const double* work;         // v = K1 e (mode 0) or u = K~1 h (mode 1)
+    int64_t work_stride;
     double* partial;            // [batch][nblocks][3]
     int nblocks;
+    int mode;
 };
 
 void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s);
+void launch_gather(int p, int space, const GatherArgs& a, int64_t n, int batch, hipStream_t s);
 void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s);
 void launch_z(int p, const ZArgs& a, int batch, hipStream_t s);
 void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
-void launch_pairing(int p, const PairArgs& a, int64_t n, int batch, hipStream_t s);
 void launch_energy(int p, const EnergyArgs& a, int batch, hipStream_t s);
 // out[b*out_stride] (+ step offset) from the energy partials
 void launch_energy_final(const double* partial, int nblocks, double dt, int batch, double* out,
