@@ -81,6 +81,12 @@ typedef struct {
 
 typedef enum { KMX_FP64 = 0, KMX_MIXED = 1 } kmx_precision;
 
+/* OR into the `precision` argument of kmx_create_space to stream the metric
+ * factor w_q DF^T DF / det DF from device memory (6 doubles per quadrature
+ * point) even for map kinds 0 and 1, whose factor is otherwise recomputed at
+ * every quadrature point inside the mass kernel.  Map kind 2 always streams. */
+#define KMX_STORED_METRIC 16
+
 /* flags for kmx_step / kmx_init_stagger */
 #define KMX_TRACK_DB 1 /* E holds [e | d] and H holds [h | b] per batch member */
 

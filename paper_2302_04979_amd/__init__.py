@@ -21,6 +21,7 @@ __all__ = ["Space", "Source", "load_library", "EXPORTS", "TRACK_DB", "KMXError"]
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
 TRACK_DB = 1
+STORED_METRIC = 16
 
 # every symbol declared in include/kronmaxwell.h
 EXPORTS = (
@@ -149,8 +150,10 @@ class Space:
     """Discrete spaces, operators and scratch of one problem (kmx_create_space)."""
 
     def __init__(self, p: int, n_elem: int, map_kind: int = 0, amplitude: float = 0.0, dF_qp=None,
-                 precision: int = 0, max_batch: int = 1):
+                 precision: int = 0, max_batch: int = 1, stored_metric: bool = False):
         L = load_library()
+        if stored_metric:
+            precision |= STORED_METRIC
         self._dF = None
         m = _Map(int(map_kind), float(amplitude), None)
         if dF_qp is not None:

@@ -92,6 +92,9 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
     a.patch = sp->d_patch;
     a.patch_stride = sp->patch_per_field;
     a.metric = sp->d_metric;
+    a.metric_mode = sp->metric_mode;
+    a.amp = sp->map.kind == 1 ? sp->map.amplitude : 0.0;
+    a.axis_tab = sp->d_axis_tab;
     a.inv_gamma = space == SP_B ? sp->d_inv_mu : sp->d_inv_eps;
     a.tab = sp->d_tab;
     for (int k = 0; k < 4; ++k) a.tab_off[k] = sp->tab_off[k];
@@ -282,7 +285,10 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
     // fit the 64 KiB of dynamic LDS the solve kernel requests
     if (n_elem < 1 || n_elem > 72) return fail(KMX_E_ARG, "n_elem must be in 1..72");
     if (max_batch < 1) return fail(KMX_E_ARG, "max_batch must be >= 1");
-    if (precision != KMX_FP64) return fail(KMX_E_ARG, "only KMX_FP64 is available in this build");
+    const int prec = precision & 0xF;
+    const bool force_stored = (precision & KMX_STORED_METRIC) != 0;
+    if (prec != KMX_FP64) return fail(KMX_E_ARG, "only KMX_FP64 is available in this build");
+    if (precision & ~(0xF | KMX_STORED_METRIC)) return fail(KMX_E_ARG, "unknown precision flag");
     if (map && (map->kind < 0 || map->kind > 2)) return fail(KMX_E_ARG, "unknown map kind");
     if (map && map->kind == 2 && !map->dF_qp) return fail(KMX_E_ARG, "map kind 2 needs dF_qp");
     kmx_space* sp = new kmx_space();
@@ -295,7 +301,7 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
         sp->ntile = (n_elem + TILE - 1) / TILE;
         sp->npad = sp->ntile * TILE;
         sp->max_batch = max_batch;
-        sp->precision = precision;
+        sp->precision = prec;
         sp->n_e = 3LL * sp->n1 * sp->n0 * sp->n0;
         sp->n_h = 3LL * sp->n0 * sp->n1 * sp->n1;
         sp->n_qp = int64_t(n_elem) * n_elem * n_elem * sp->nq * sp->nq * sp->nq;
@@ -308,14 +314,28 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
         const size_t ne3 = size_t(n_elem) * n_elem * n_elem;
         sp->inv_eps_host.assign(ne3, 1.0);
         sp->inv_mu_host.assign(ne3, 1.0);
+        sp->metric_mode = (sp->map.kind == 2 || force_stored) ? 0 : 1;
         std::vector<double> metric;
-        kmx_status st = build_metric(sp, metric);
+        kmx_status st = build_metric(sp, sp->metric_mode == 0 ? &metric : nullptr);
         if (st != KMX_OK) {
             delete sp;
             return fail(st, "det DF <= 0 at a quadrature point: the map is not admissible");
         }
         // device data
-        if ((st = upload(&sp->d_metric, metric)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        if (sp->metric_mode == 0) {
+            if ((st = upload(&sp->d_metric, metric)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+            std::vector<double>().swap(metric);
+        }
+        {
+            const int64_t npq = int64_t(sp->npad) * sp->nq, nq_all = int64_t(n_elem) * sp->nq;
+            std::vector<double> at(3 * npq, 0.0);
+            for (int64_t i = 0; i < nq_all; ++i) {
+                at[i] = std::sin(M_PI * sp->tb.xq[i]);
+                at[npq + i] = std::cos(M_PI * sp->tb.xq[i]);
+                at[2 * npq + i] = sp->tb.wq[i];
+            }
+            if ((st = upload(&sp->d_axis_tab, at)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        }
         std::vector<double> tabs;
         for (int t = 0; t < 4; ++t) {
             sp->tab_off[t] = int64_t(tabs.size());
@@ -402,7 +422,7 @@ kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches) {
 void kmx_destroy_space(kmx_space* sp) {
     if (!sp) return;
     for (auto& e : sp->prof_ev) (void)hipEventDestroy(e);
-    double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
+    double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_axis_tab, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
                       sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
     for (double* b : bufs)
         if (b) (void)hipFree(b);

@@ -235,7 +235,12 @@ __device__ inline void integrate_xy(const double (&Rcol)[L::Wz], double* rb, dou
     }
 }
 
-template <int P, int SPACE, bool CURL>
+// MET = 0: the metric w_q DF^T DF / det DF is streamed from memory (any map);
+// MET = 1: it is recomputed at each Gauss point for x -> x + a s(x) (1,1,1)
+// with s = sin(pi x) sin(pi y) sin(pi z) (a = 0: identity), from per-axis
+// tables of sin, cos and weights: DF = I + a (1,1,1)^T grad(s)^T gives
+// det DF = 1 + a (g1 + g2 + g3) and (DF^T DF)_ij = d_ij + a (g_i + g_j) + 3 a^2 g_i g_j.
+template <int P, int SPACE, bool CURL, int MET>
 __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) {
     constexpr int NQ = P + 1, Q = TILE * NQ, NT = MassCfg<P>::NT;
     constexpr int SRC = CURL ? (SPACE == SP_B ? SP_E : SP_H) : SPACE;
@@ -273,9 +278,11 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
     // the first two Gauss-point planes of the metric are requested before the
     // window set-up so that their latency overlaps it
     const double* gm = A.metric + int64_t(tile) * Q * 6 * Q * Q + qy * Q + qx;
-    double g[6];
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    if (MET == 0) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) g[k] = active ? __builtin_nontemporal_load(gm + k * Q * Q) : 0.0;
+        for (int k = 0; k < 6; ++k) g[k] = active ? __builtin_nontemporal_load(gm + k * Q * Q) : 0.0;
+    }
 
     // ---- 1D tables of the tile: [axis][slot][element][point][function] ----
     for (int i = tid; i < 6 * TSL; i += NT) {
@@ -342,16 +349,41 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
             ig[le] = A.inv_gamma ? A.inv_gamma[(int64_t(tz * TILE + le) * A.npad + ey) * A.npad + ex] : 1.0;
         const double* tz0 = tab(2, 1);  // components 0 and 1 are across z
         const double* tz2 = tab(2, 0);  // component 2 is along z
+        // analytic metric: per-thread factors of the (x, y) column
+        const int64_t npq = int64_t(A.npad) * NQ;
+        const int gxq = tx * TILE * NQ + qx, gyq = ty * TILE * NQ + qy;
+        double a1 = 0.0, a2 = 0.0, a3 = 0.0, wxy = 0.0;
+        if (MET == 1) {
+            const double sx = A.axis_tab[gxq], cx = A.axis_tab[npq + gxq], wx = A.axis_tab[2 * npq + gxq];
+            const double sy = A.axis_tab[gyq], cy = A.axis_tab[npq + gyq], wy = A.axis_tab[2 * npq + gyq];
+            a1 = M_PI * cx * sy;
+            a2 = M_PI * sx * cy;
+            a3 = M_PI * sx * sy;
+            wxy = wx * wy;
+        }
+        const double amp = A.amp, aa = 3.0 * A.amp * A.amp;
 #pragma unroll
         for (int le = 0; le < TILE; ++le) {
 #pragma unroll
             for (int iq = 0; iq < NQ; ++iq) {
                 const int qz = le * NQ + iq;
                 double gn[6];  // next plane in flight while this one is used
-                if (qz + 1 < Q) {
+                if (MET == 0 && qz + 1 < Q) {
 #pragma unroll
                     for (int k = 0; k < 6; ++k)
                         gn[k] = __builtin_nontemporal_load(gm + int64_t(qz + 1) * 6 * Q * Q + k * Q * Q);
+                }
+                if (MET == 1) {
+                    const int gzq = tz * TILE * NQ + qz;
+                    const double sz = A.axis_tab[gzq], cz = A.axis_tab[npq + gzq], wz = A.axis_tab[2 * npq + gzq];
+                    const double p1 = a1 * sz, p2 = a2 * sz, p3 = a3 * cz;
+                    const double f = wxy * wz / (1.0 + amp * (p1 + p2 + p3));
+                    g[0] = f * (1.0 + 2.0 * amp * p1 + aa * p1 * p1);
+                    g[1] = f * (1.0 + 2.0 * amp * p2 + aa * p2 * p2);
+                    g[2] = f * (1.0 + 2.0 * amp * p3 + aa * p3 * p3);
+                    g[3] = f * (amp * (p1 + p2) + aa * p1 * p2);
+                    g[4] = f * (amp * (p1 + p3) + aa * p1 * p3);
+                    g[5] = f * (amp * (p2 + p3) + aa * p2 * p3);
                 }
                 const double* t0 = tz0 + (le * NQ + iq) * L0::Kz;
                 const double* t2 = tz2 + (le * NQ + iq) * L2::Kz;
@@ -372,7 +404,7 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
                 for (int j = 0; j < L1::Kz; ++j) R1c[le + j] += t0[j] * u1;
 #pragma unroll
                 for (int j = 0; j < L2::Kz; ++j) R2c[le + j] += t2[j] * u2;
-                if (qz + 1 < Q) {
+                if (MET == 0 && qz + 1 < Q) {
 #pragma unroll
                     for (int k = 0; k < 6; ++k) g[k] = gn[k];
                 }
@@ -393,19 +425,27 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
                                out + A.patch_comp_off[2] + int64_t(tile) * L2::size, tid, NT, qy, qx, active);
 }
 
+template <int P, int SPACE, bool CURL>
+static void launch_mass_t(const MassArgs& a, dim3 grid, hipStream_t s) {
+    if (a.metric_mode == 1)
+        hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+}
+
 void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s) {
     const int nt3 = a.ntile * a.ntile * a.ntile;
     dim3 grid(nt3, batch);
-#define LM(PP)                                                                                           \
-    if (p == PP) {                                                                                       \
-        if (space == SP_B) {                                                                             \
-            if (curl) hipLaunchKernelGGL((mass_kernel<PP, SP_B, true>), grid, dim3(MassCfg<PP>::NT), 0, s, a);  \
-            else hipLaunchKernelGGL((mass_kernel<PP, SP_B, false>), grid, dim3(MassCfg<PP>::NT), 0, s, a);      \
-        } else {                                                                                         \
-            if (curl) hipLaunchKernelGGL((mass_kernel<PP, SP_D, true>), grid, dim3(MassCfg<PP>::NT), 0, s, a);  \
-            else hipLaunchKernelGGL((mass_kernel<PP, SP_D, false>), grid, dim3(MassCfg<PP>::NT), 0, s, a);      \
-        }                                                                                                \
-        return;                                                                                          \
+#define LM(PP)                                                                      \
+    if (p == PP) {                                                                  \
+        if (space == SP_B) {                                                        \
+            if (curl) launch_mass_t<PP, SP_B, true>(a, grid, s);                    \
+            else launch_mass_t<PP, SP_B, false>(a, grid, s);                        \
+        } else {                                                                    \
+            if (curl) launch_mass_t<PP, SP_D, true>(a, grid, s);                    \
+            else launch_mass_t<PP, SP_D, false>(a, grid, s);                        \
+        }                                                                           \
+        return;                                                                     \
     }
     LM(2) LM(3) LM(4)
 #undef LM

@@ -12,7 +12,10 @@ struct MassArgs {
     int64_t src_stride;         // distance between batch members
     double* patch;              // patch buffer of batch member 0
     int64_t patch_stride;
-    const double* metric;       // w_q DF^T DF / det DF, tile layout
+    const double* metric;       // w_q DF^T DF / det DF, tile layout (metric_mode 0)
+    int metric_mode;            // 0 stored metric, 1 recomputed for the sine map
+    double amp;                 // map amplitude a (metric_mode 1)
+    const double* axis_tab;     // [sin | cos | weight] at the npad*nq Gauss points of an axis
     const double* inv_gamma;    // [npad^3] per-element 1/eps or 1/mu, or nullptr
     const double* tab;          // concatenated 1D tables
     int64_t tab_off[4];

@@ -94,7 +94,9 @@ struct kmx_space {
     // device data
     double* d_tab = nullptr;           // 4 tag tables concatenated
     int64_t tab_off[4] = {0, 0, 0, 0};
-    double* d_metric = nullptr;        // w_q DF^T DF / det DF, tile layout
+    double* d_metric = nullptr;        // w_q DF^T DF / det DF, tile layout (metric_mode 0)
+    int metric_mode = 0;               // 0 stored metric, 1 recomputed in the mass kernel
+    double* d_axis_tab = nullptr;      // sin, cos, weight at the Gauss points of an axis
     double* d_inv_eps = nullptr;       // [npad^3]
     double* d_inv_mu = nullptr;        // [npad^3]
     double* d_fac = nullptr;           // 4 banded factor sets

@@ -263,10 +263,10 @@ static inline int64_t qp_index(const Tables& tb, int ez, int ey, int ex, int iz,
 // Metric factor w_q DF^T DF / det DF at every Gauss point, laid out per tile of
 // TILE^3 elements as [tile][qz][6][qy][qx] with Q = TILE*nq points per tile
 // edge; entries 0..5 = (xx, yy, zz, xy, xz, yz).  Padded elements get zeros.
-kmx_status build_metric(const kmx_space* sp, std::vector<double>& out) {
+kmx_status build_metric(const kmx_space* sp, std::vector<double>* out) {
     const Tables& tb = sp->tb;
     const int nq = tb.nq, Q = TILE * nq, nt = sp->ntile, N = tb.N;
-    out.assign(size_t(nt) * nt * nt * Q * 6 * Q * Q, 0.0);
+    if (out) out->assign(size_t(nt) * nt * nt * Q * 6 * Q * Q, 0.0);
     for (int ez = 0; ez < N; ++ez)
         for (int ey = 0; ey < N; ++ey)
             for (int ex = 0; ex < N; ++ex) {
@@ -281,6 +281,7 @@ kmx_status build_metric(const kmx_space* sp, std::vector<double>& out) {
                             map_jacobian(sp, qp_index(tb, ez, ey, ex, iz, iy, ix), xh, J);
                             const double det = det3(J);
                             if (!(det > 0.0) || !std::isfinite(det)) return KMX_E_GEOMETRY;
+                            if (!out) continue;
                             double C[6];
                             const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
                             for (int k = 0; k < 6; ++k) {
@@ -291,7 +292,7 @@ kmx_status build_metric(const kmx_space* sp, std::vector<double>& out) {
                             const int qz = (ez % TILE) * nq + iz, qy = (ey % TILE) * nq + iy,
                                       qx = (ex % TILE) * nq + ix;
                             for (int k = 0; k < 6; ++k)
-                                out[((tile * Q + qz) * 6 + k) * Q * Q + qy * Q + qx] = C[k];
+                                (*out)[((tile * Q + qz) * 6 + k) * Q * Q + qy * Q + qx] = C[k];
                         }
             }
     return KMX_OK;

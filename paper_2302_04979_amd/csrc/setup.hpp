@@ -14,7 +14,7 @@ void band_solve_host(const BandLU& f, double* x, int64_t stride);
 void build_tables(Tables& tb, int p, int N);
 void map_jacobian(const kmx_space* sp, int64_t qp_index, const double xh[3], double J[9]);
 void map_point(const kmx_space* sp, const double xh[3], double x[3]);
-kmx_status build_metric(const kmx_space* sp, std::vector<double>& out);
+kmx_status build_metric(const kmx_space* sp, std::vector<double>* out);  // out = nullptr: check det DF only
 void quad_points(const kmx_space* sp, double* xyz);
 void comp_dims(const kmx_space* sp, int space, int c, int dims[3]);
 int64_t comp_offset(const kmx_space* sp, int space, int c);
