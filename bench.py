@@ -86,6 +86,31 @@ def cpu_baseline(p, N, steps, eps):
                       f"from a seeded random state ({dt:.1f} s of CPU work, set-up excluded)"}
 
 
+def adjoint_timing(K, W, torch):
+    """Wall time of one loss + gradient evaluation (forward with checkpoints,
+    recomputation, reverse sweep) on the differentiation workload."""
+    import numpy as np
+    p, N, nsteps = 3, 32, 500
+    G = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+    G.set_materials(eps=np.full(N ** 3, 2.0))
+    dt = 0.5 * G.cfl(max_iter=200, tol=1e-6)
+    dip = W.dipoles(1, seed=0, dt=dt, margin=0.2)
+    probes = W.probes(64, seed=0)
+    zero = torch.zeros(nsteps * 192, dtype=torch.float64, device="cuda")
+    prob = K.ProbeMisfitProblem(G, dip, probes, zero, dt, nsteps, checkpoint_every=50)
+    data = prob.observe(W.eps_elements(N, 0, purpose="eps_true")).reshape(-1).clone()
+    prob = K.ProbeMisfitProblem(G, dip, probes, data, dt, nsteps, checkpoint_every=50)
+    eps0 = np.full(N ** 3, 2.0)
+    prob.loss_and_grad(eps0)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        prob.loss_and_grad(eps0)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +120,7 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -206,6 +232,13 @@ def main():
     breakdown = {k: {"ms_per_launch": round(v[0] / v[1], 4) if v[1] else None, "launches": v[1]}
                  for k, v in prof.items()}
 
+    # adjoint gradient: p=3, 32^3 deformed cube, eps = 2, one dipole, 64 probes,
+    # 500 steps, checkpoints every 50 (the differentiation workload)
+    adjoint_s = None
+    if not args.no_adjoint:
+        log("adjoint gradient")
+        adjoint_s = adjoint_timing(K, W, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
@@ -235,7 +268,7 @@ def main():
         "kernels": breakdown,
         "stored_metric": stored,
         "mixed": None,
-        "adjoint_grad_s": None,
+        "adjoint_grad_s": adjoint_s,
     }
     print(json.dumps(out), flush=True)
 

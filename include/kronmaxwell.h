@@ -54,6 +54,7 @@ extern "C" {
 
 typedef struct kmx_space kmx_space;
 typedef struct kmx_source kmx_source;
+typedef struct kmx_probes kmx_probes;
 
 typedef enum {
     KMX_OK = 0,
@@ -188,6 +189,41 @@ kmx_status kmx_op_solve(kmx_space* sp, int which, int transpose, const double* y
 
 /* y = K x with K = K1 (which = 1) or K~1 (which = 0). */
 kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, void* stream);
+
+/* ---- probes and the adjoint (gradient of a probe misfit in eps) ----------
+ * Not part of the paper, which has no inverse problem: the exact discrete
+ * adjoint of the leapfrog above. */
+
+/* Point probes of the physical electric field E_h(x) = DF^{-T} E^_h(x^) at n
+ * parametric positions (host, n x 3, in [0,1]^3).  The probe operator P
+ * (3n rows: probe, component) is precomputed on the host and kept on the
+ * device.  For map kind 2 the Jacobian of the probe's element's first
+ * quadrature point is used. */
+kmx_status kmx_create_probes(kmx_space* sp, int n, const double* pos, kmx_probes** out);
+void kmx_destroy_probes(kmx_probes* pr);
+
+/* out (device, 3n) = P e for e (device, n_e). */
+kmx_status kmx_probe_eval(kmx_space* sp, const kmx_probes* pr, const double* e, double* out, void* stream);
+
+/* From zero fields, nsteps leapfrog steps driven by J (may be NULL); obs
+ * (device, nsteps x 3n) receives P e^n for n = 1..nsteps.  Allocates two
+ * fields of working memory; synchronises. */
+kmx_status kmx_probe_forward(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, double dt, int nsteps,
+                             double* obs, void* stream);
+
+/* Loss L = 1/2 sum_n |P e^n - data_n|^2 over the run of kmx_probe_forward and
+ * its gradient with respect to the per-element eps of the space (the eps set
+ * by kmx_set_materials; create J after setting them: the tested dipole carries
+ * 1/eps at its element), by the discrete adjoint of the leapfrog:
+ *   lam = K1^{-T} ebar; hbar += dt D~^{1T} M~ lam;
+ *   g_e += -dt/eps_e^2 sum_{q in e} Lam . G (D~^1 h^{n+1/2}) (+ dt g(t) lam.s / eps at the dipole element);
+ *   ebar -= dt D^{1T} M K~1^{-T} hbar; ebar += P^T (P e^n - data_n).
+ * The forward states are recomputed from checkpoints taken every
+ * `checkpoint_every` steps.  data: device, nsteps x 3n.  loss_host: host
+ * scalar.  grad: device, N^3 (x fastest), overwritten.  Allocates its working
+ * memory (checkpoints, one segment of h, probe values); synchronises. */
+kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, const double* data, double dt,
+                       int nsteps, int checkpoint_every, double* loss_host, double* grad, void* stream);
 
 /* ---- per-kernel timing ---------------------------------------------------
  * Between kmx_profile_begin and kmx_profile_end every kernel the space

@@ -28,7 +28,8 @@ EXPORTS = (
     "kmx_create_space", "kmx_destroy_space", "kmx_set_materials", "kmx_sizes", "kmx_quad_points",
     "kmx_project_E", "kmx_project_D", "kmx_cfl", "kmx_create_source", "kmx_destroy_source",
     "kmx_init_stagger", "kmx_step", "kmx_energy", "kmx_op_curl", "kmx_op_mass", "kmx_op_solve",
-    "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_last_error",
+    "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_create_probes", "kmx_destroy_probes",
+    "kmx_probe_eval", "kmx_probe_forward", "kmx_adjoint", "kmx_last_error",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather")
 
@@ -82,6 +83,11 @@ def load_library():
         "kmx_op_pairing": ([vp, i, vp, vp, vp], i),
         "kmx_profile_begin": ([vp, i], i),
         "kmx_profile_end": ([vp, vp, vp], i),
+        "kmx_create_probes": ([vp, i, vp, ctypes.POINTER(vp)], i),
+        "kmx_destroy_probes": ([vp], None),
+        "kmx_probe_eval": ([vp, vp, vp, vp, vp], i),
+        "kmx_probe_forward": ([vp, vp, vp, d, i, vp, vp], i),
+        "kmx_adjoint": ([vp, vp, vp, vp, d, i, i, ctypes.POINTER(d), vp, vp], i),
         "kmx_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -137,6 +143,30 @@ class Source:
     def close(self):
         if getattr(self, "_h", None):
             load_library().kmx_destroy_source(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Probes:
+    """Point probes of the physical electric field (kmx_create_probes)."""
+
+    def __init__(self, space: "Space", pos):
+        n = int(np.asarray(pos).shape[0])
+        self._pos = _hptr(pos, 3 * n)
+        h = ctypes.c_void_p()
+        _check(load_library().kmx_create_probes(space._h, n, self._pos[1], ctypes.byref(h)))
+        self._h = h
+        self.space = space
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().kmx_destroy_probes(self._h)
             self._h = None
 
     def __del__(self):
@@ -250,6 +280,26 @@ class Space:
         _check(load_library().kmx_op_solve(self._h, w, int(bool(transpose)), _dptr(y, n, "y"), _dptr(x, n, "x"),
                                            _stream()))
 
+    # ---- probes and the adjoint ------------------------------------------
+    def probes(self, pos) -> Probes:
+        return Probes(self, pos)
+
+    def probe_eval(self, pr: Probes, e, out):
+        _check(load_library().kmx_probe_eval(self._h, pr._h, _dptr(e, self.n_e, "e"),
+                                             _dptr(out, 3 * pr.n, "out"), _stream()))
+
+    def probe_forward(self, pr: Probes, J: "Source | None", dt, nsteps, obs):
+        _check(load_library().kmx_probe_forward(self._h, pr._h, None if J is None else J._h, float(dt), int(nsteps),
+                                                _dptr(obs, nsteps * 3 * pr.n, "obs"), _stream()))
+
+    def adjoint(self, pr: Probes, J: "Source | None", data, dt, nsteps, checkpoint_every, grad) -> float:
+        loss = ctypes.c_double()
+        _check(load_library().kmx_adjoint(self._h, pr._h, None if J is None else J._h,
+                                          _dptr(data, nsteps * 3 * pr.n, "data"), float(dt), int(nsteps),
+                                          int(checkpoint_every), ctypes.byref(loss),
+                                          _dptr(grad, self.N ** 3, "grad"), _stream()))
+        return loss.value
+
     def profile_begin(self, capacity=100000):
         _check(load_library().kmx_profile_begin(self._h, int(capacity)))
 
@@ -265,3 +315,63 @@ class Space:
         w = 1 if which == "K1" else 0
         n = self.n_e if w else self.n_h
         _check(load_library().kmx_op_pairing(self._h, w, _dptr(x, n, "x"), _dptr(y, n, "y"), _stream()))
+
+
+class ProbeMisfitProblem:
+    """Probe-misfit inverse problem in the per-element permittivity: zero initial
+    fields, point dipoles (dict of arrays pos, moment, t0, sigma, amp), probes at
+    parametric points, observed data (device tensor, nsteps x n_probes x 3)."""
+
+    def __init__(self, space: Space, dipoles: dict, probe_pos, data, dt, nsteps, checkpoint_every=50, mu=None):
+        self.space, self.dip, self.data = space, dipoles, data
+        self.dt, self.nsteps, self.ckpt = float(dt), int(nsteps), int(checkpoint_every)
+        self.mu = mu
+        self.probes = space.probes(probe_pos)
+
+    def _source(self):
+        d = self.dip
+        return self.space.source(d["pos"], d["moment"], d["t0"], d["sigma"], d["amp"])
+
+    def loss_and_grad(self, eps):
+        """(loss, dL/deps as a device tensor of shape (N, N, N))."""
+        import torch
+        N = self.space.N
+        self.space.set_materials(eps=np.asarray(eps, dtype=float).reshape(-1), mu=self.mu)
+        J = self._source()
+        grad = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+        loss = self.space.adjoint(self.probes, J, self.data, self.dt, self.nsteps, self.ckpt, grad)
+        return loss, grad.reshape(N, N, N)
+
+    def observe(self, eps):
+        """Probe values of a forward run with the given eps (device tensor)."""
+        import torch
+        self.space.set_materials(eps=np.asarray(eps, dtype=float).reshape(-1), mu=self.mu)
+        obs = torch.zeros(self.nsteps, self.probes.n, 3, dtype=torch.float64, device="cuda")
+        self.space.probe_forward(self.probes, self._source(), self.dt, self.nsteps, obs)
+        return obs
+
+
+def _misfit_function():
+    import torch
+
+    class ProbeMisfit(torch.autograd.Function):
+        """loss = ProbeMisfit.apply(eps, problem): forward and adjoint run on the
+        device through kmx_adjoint (checkpointed); backward returns dL/deps."""
+
+        @staticmethod
+        def forward(ctx, eps, problem):
+            loss, grad = problem.loss_and_grad(eps.detach().cpu().numpy())
+            ctx.save_for_backward(grad.to(eps.device))
+            return torch.tensor(loss, dtype=torch.float64, device=eps.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (grad,) = ctx.saved_tensors
+            return grad_out * grad, None
+
+    return ProbeMisfit
+
+
+def probe_misfit(eps, problem: ProbeMisfitProblem):
+    """Differentiable probe misfit (torch.autograd.Function over the adjoint)."""
+    return _misfit_function().apply(eps, problem)

@@ -196,6 +196,19 @@ void run_curl(kmx_space* sp, int primal, const double* in, int64_t in_stride, do
     launch_curl(a, primal ? sp->n_h : sp->n_e, batch, s);
 }
 
+// out += alpha * (D^1)^T y (primal: X^2_{h,0} -> X^1_{h,0}) or (D~^1)^T y (X~^2 -> X~^1)
+void run_curlT(kmx_space* sp, int primal, const double* y, double* out, double alpha, hipStream_t s) {
+    CurlArgs a{};
+    a.in = y;
+    a.out = out;
+    a.alpha = alpha;
+    a.beta = 1.0;
+    a.primal = primal;
+    space_dims(sp, primal ? SP_B : SP_D, a.in_dims, a.in_comp_off);
+    space_dims(sp, primal ? SP_E : SP_H, a.out_dims, a.out_comp_off);
+    launch_curlT(a, primal ? sp->n_e : sp->n_h, 1, s);
+}
+
 int energy_blocks(const kmx_space* sp) {
     const int64_t n = std::max(sp->n_e, sp->n_h);
     return int(std::min<int64_t>(1024, (n + 255) / 256));
@@ -612,6 +625,16 @@ kmx_status kmx_create_source(kmx_space* sp, int n, const double* pos, const doub
         bmax = std::max(bmax, b + 1);
     }
     for (int b = 0; b < sp->max_batch; ++b) off[b + 1] += off[b];
+    std::vector<int> elem(n);
+    std::vector<double> src_ie(n);
+    for (int r = 0; r < n; ++r) {
+        const int k = order[r];
+        int el[3];
+        for (int a = 0; a < 3; ++a)
+            el[a] = std::min(std::max(int(std::floor(pos[3 * k + a] * sp->N)), 0), sp->N - 1);
+        elem[r] = (el[2] * sp->N + el[1]) * sp->N + el[0];
+        src_ie[r] = sp->inv_eps_host[elem[r]];
+    }
     kmx_source* src = new kmx_source();
     src->sp = sp;
     src->n = n;
@@ -627,6 +650,20 @@ kmx_status kmx_create_source(kmx_space* sp, int n, const double* pos, const doub
     HIP_TRY(hipMemcpy(src->d_entries, ent.data(), ent.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(src->d_prof, prof.data(), prof_bytes, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(reinterpret_cast<char*>(src->d_prof) + prof_bytes, off.data(), off_bytes, hipMemcpyHostToDevice));
+    int dims[3][3];
+    int64_t coff[3];
+    space_dims(sp, SP_D, dims, coff);
+    if (hipMalloc(&src->d_elem, n * sizeof(int)) != hipSuccess ||
+        hipMalloc(&src->d_inv_eps, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&src->d_comp_off, 3 * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&src->d_dims, 9 * sizeof(int)) != hipSuccess) {
+        kmx_destroy_source(src);
+        return fail(KMX_E_OOM, "device allocation failed (sources)");
+    }
+    HIP_TRY(hipMemcpy(src->d_elem, elem.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(src->d_inv_eps, src_ie.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(src->d_comp_off, coff, 3 * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(src->d_dims, &dims[0][0], 9 * sizeof(int), hipMemcpyHostToDevice));
     *out = src;
     return KMX_OK;
 }
@@ -635,7 +672,261 @@ void kmx_destroy_source(kmx_source* src) {
     if (!src) return;
     if (src->d_entries) (void)hipFree(src->d_entries);
     if (src->d_prof) (void)hipFree(src->d_prof);
+    if (src->d_elem) (void)hipFree(src->d_elem);
+    if (src->d_inv_eps) (void)hipFree(src->d_inv_eps);
+    if (src->d_comp_off) (void)hipFree(src->d_comp_off);
+    if (src->d_dims) (void)hipFree(src->d_dims);
     delete src;
+}
+
+kmx_status kmx_create_probes(kmx_space* sp, int n, const double* pos, kmx_probes** out) {
+    if (!sp || !pos || !out || n < 1) return fail(KMX_E_ARG, "bad argument");
+    *out = nullptr;
+    const Tables& tb = sp->tb;
+    const int N = sp->N, p = sp->p;
+    struct Ent { int row; int col; double val; };
+    std::vector<Ent> ents;
+    for (int k = 0; k < n; ++k) {
+        const double* xh = pos + 3 * k;
+        int el[3];
+        for (int a = 0; a < 3; ++a) {
+            if (!(xh[a] >= 0.0 && xh[a] <= 1.0)) return fail(KMX_E_ARG, "probe position outside [0,1]^3");
+            el[a] = std::min(std::max(int(std::floor(xh[a] * N)), 0), N - 1);
+        }
+        double J[9];
+        map_jacobian(sp, sp->map.kind == 2 ? (((int64_t(el[2]) * N + el[1]) * N + el[0]) * sp->nq * sp->nq * sp->nq)
+                                           : -1, xh, J);
+        // inverse transpose of DF: E = DF^{-T} E^ (covariant pullback of 1-forms)
+        const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                           J[2] * (J[3] * J[7] - J[4] * J[6]);
+        double C[9];  // cofactor matrix: DF^{-T} = C / det
+        C[0] = J[4] * J[8] - J[5] * J[7]; C[1] = -(J[3] * J[8] - J[5] * J[6]); C[2] = J[3] * J[7] - J[4] * J[6];
+        C[3] = -(J[1] * J[8] - J[2] * J[7]); C[4] = J[0] * J[8] - J[2] * J[6]; C[5] = -(J[0] * J[7] - J[1] * J[6]);
+        C[6] = J[1] * J[5] - J[2] * J[4]; C[7] = -(J[0] * J[5] - J[2] * J[3]); C[8] = J[0] * J[4] - J[1] * J[3];
+        for (int j = 0; j < 3; ++j) {
+            int d[3];
+            comp_dims(sp, SP_E, j, d);
+            const int64_t off = comp_offset(sp, SP_E, j);
+            double bv[3][8];
+            int K[3], tg[3];
+            for (int a = 0; a < 3; ++a) {
+                tg[a] = space_tag(SP_E, j, a);
+                K[a] = tag_support(p, tg[a]);
+                eval_tag_on_element(tb, tg[a], el[a], xh[a], bv[a]);
+            }
+            for (int jz = 0; jz < K[2]; ++jz)
+                for (int jy = 0; jy < K[1]; ++jy)
+                    for (int jx = 0; jx < K[0]; ++jx) {
+                        const int gx = el[0] + jx + tag_offset(tg[0]), gy = el[1] + jy + tag_offset(tg[1]),
+                                  gz = el[2] + jz + tag_offset(tg[2]);
+                        if (gx < 0 || gy < 0 || gz < 0 || gx >= d[2] || gy >= d[1] || gz >= d[0]) continue;
+                        const double w = bv[2][jz] * bv[1][jy] * bv[0][jx];
+                        if (w == 0.0) continue;
+                        const int col = int(off + (int64_t(gz) * d[1] + gy) * d[2] + gx);
+                        for (int c = 0; c < 3; ++c) ents.push_back({3 * k + c, col, C[3 * c + j] / det * w});
+                    }
+        }
+    }
+    // P in CSR (rows in order, entries in construction order)
+    std::vector<int> rowptr(3 * n + 1, 0), col;
+    std::vector<double> val;
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.row < b.row; });
+    for (const Ent& e : ents) { rowptr[e.row + 1]++; col.push_back(e.col); val.push_back(e.val); }
+    for (int r = 0; r < 3 * n; ++r) rowptr[r + 1] += rowptr[r];
+    // P^T over the touched dofs
+    std::vector<Ent> tents(ents);
+    std::stable_sort(tents.begin(), tents.end(), [](const Ent& a, const Ent& b) {
+        return a.col < b.col || (a.col == b.col && a.row < b.row);
+    });
+    std::vector<int> trowptr(1, 0), tcol, tidx;
+    std::vector<double> tval;
+    for (size_t i = 0; i < tents.size(); ++i) {
+        if (i == 0 || tents[i].col != tents[i - 1].col) {
+            tidx.push_back(tents[i].col);
+            if (i) trowptr.push_back(int(i));
+        }
+        tcol.push_back(tents[i].row);
+        tval.push_back(tents[i].val);
+    }
+    trowptr.push_back(int(tents.size()));
+    kmx_probes* pr = new kmx_probes();
+    pr->sp = sp;
+    pr->n = n;
+    pr->ntrows = int(tidx.size());
+    auto up_i = [&](int** d, const std::vector<int>& v) {
+        return hipMalloc(d, std::max<size_t>(v.size(), 1) * sizeof(int)) == hipSuccess &&
+               (v.empty() || hipMemcpy(*d, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess);
+    };
+    auto up_d = [&](double** d, const std::vector<double>& v) {
+        return hipMalloc(d, std::max<size_t>(v.size(), 1) * sizeof(double)) == hipSuccess &&
+               (v.empty() || hipMemcpy(*d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess);
+    };
+    if (!up_i(&pr->d_rowptr, rowptr) || !up_i(&pr->d_col, col) || !up_d(&pr->d_val, val) ||
+        !up_i(&pr->d_trowptr, trowptr) || !up_i(&pr->d_tcol, tcol) || !up_i(&pr->d_tidx, tidx) ||
+        !up_d(&pr->d_tval, tval)) {
+        kmx_destroy_probes(pr);
+        return fail(KMX_E_OOM, "device allocation failed (probes)");
+    }
+    *out = pr;
+    return KMX_OK;
+}
+
+void kmx_destroy_probes(kmx_probes* pr) {
+    if (!pr) return;
+    int* ib[] = {pr->d_rowptr, pr->d_col, pr->d_trowptr, pr->d_tcol, pr->d_tidx};
+    for (int* b : ib)
+        if (b) (void)hipFree(b);
+    if (pr->d_val) (void)hipFree(pr->d_val);
+    if (pr->d_tval) (void)hipFree(pr->d_tval);
+    delete pr;
+}
+
+kmx_status kmx_probe_eval(kmx_space* sp, const kmx_probes* pr, const double* e, double* out, void* stream) {
+    if (!sp || !pr || !e || !out || pr->sp != sp) return fail(KMX_E_ARG, "bad argument");
+    launch_csr(pr->d_rowptr, pr->d_col, pr->d_val, e, out, nullptr, 3 * pr->n, 1.0, 0.0,
+               static_cast<hipStream_t>(stream));
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_probe_forward(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, double dt, int nsteps,
+                             double* obs, void* stream) {
+    if (!sp || !pr || !obs || nsteps < 1 || pr->sp != sp || (J && J->sp != sp)) return fail(KMX_E_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *e = nullptr, *h = nullptr;
+    if (hipMalloc(&e, sp->n_e * sizeof(double)) != hipSuccess || hipMalloc(&h, sp->n_h * sizeof(double)) != hipSuccess) {
+        hipFree(e); hipFree(h);
+        return fail(KMX_E_OOM, "device allocation failed");
+    }
+    hipMemsetAsync(e, 0, sp->n_e * sizeof(double), s);
+    hipMemsetAsync(h, 0, sp->n_h * sizeof(double), s);
+    kmx_status st = KMX_OK;
+    for (int n = 0; n < nsteps && st == KMX_OK; ++n) {
+        st = kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
+        launch_csr(pr->d_rowptr, pr->d_col, pr->d_val, e, obs + int64_t(n) * 3 * pr->n, nullptr, 3 * pr->n, 1.0,
+                   0.0, s);
+    }
+    hipStreamSynchronize(s);
+    hipFree(e);
+    hipFree(h);
+    if (st != KMX_OK) return st;
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, const double* data, double dt,
+                       int nsteps, int checkpoint_every, double* loss_host, double* grad, void* stream) {
+    if (!sp || !pr || !data || !loss_host || !grad || nsteps < 1 || checkpoint_every < 1 || pr->sp != sp ||
+        (J && J->sp != sp))
+        return fail(KMX_E_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t ne = sp->n_e, nh = sp->n_h, nobs = int64_t(3) * pr->n, NS = nsteps;
+    const int K = std::min(checkpoint_every, nsteps), nseg = (nsteps + K - 1) / K;
+    // working memory (this call allocates; the time step itself never does)
+    std::vector<double*> bufs;
+    auto alloc = [&](int64_t count) -> double* {
+        double* p = nullptr;
+        if (hipMalloc(&p, std::max<int64_t>(count, 1) * sizeof(double)) != hipSuccess) return nullptr;
+        bufs.push_back(p);
+        return p;
+    };
+    double* ck_e = alloc(nseg * ne);
+    double* ck_h = alloc(nseg * nh);
+    double* seg_h = alloc(int64_t(K) * nh);
+    double* e = alloc(ne);
+    double* h = alloc(nh);
+    double* obs = alloc(NS * nobs);
+    double* res = alloc(NS * nobs);
+    double* ebar = alloc(ne);
+    double* hbar = alloc(nh);
+    double* lam = alloc(ne);
+    double* u = alloc(nh);
+    double* w = alloc(std::max(ne, nh));
+    kmx_status st = KMX_OK;
+    for (double* b : bufs)
+        if (!b) st = fail(KMX_E_OOM, "device allocation failed (adjoint working memory)");
+    if (bufs.size() != 12) st = fail(KMX_E_OOM, "device allocation failed (adjoint working memory)");
+    if (st == KMX_OK) {
+        // ---- forward run with checkpoints of (e^n, h^{n-1/2}) every K steps ----
+        hipMemsetAsync(e, 0, ne * sizeof(double), s);
+        hipMemsetAsync(h, 0, nh * sizeof(double), s);
+        for (int n = 0; n < nsteps; ++n) {
+            if (n % K == 0) {
+                hipMemcpyAsync(ck_e + int64_t(n / K) * ne, e, ne * sizeof(double), hipMemcpyDeviceToDevice, s);
+                hipMemcpyAsync(ck_h + int64_t(n / K) * nh, h, nh * sizeof(double), hipMemcpyDeviceToDevice, s);
+            }
+            kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
+            launch_csr(pr->d_rowptr, pr->d_col, pr->d_val, e, obs + n * nobs, nullptr, int(nobs), 1.0, 0.0, s);
+        }
+        // ---- misfit ----
+        const int nb = int(std::min<int64_t>(1024, (NS * nobs + 255) / 256));
+        launch_residual(obs, data, res, NS * nobs, sp->d_red, nb, s);
+        launch_sum_final(sp->d_red, nb, 1, sp->d_scal, s);
+        // ---- reverse sweep ----
+        hipMemsetAsync(grad, 0, int64_t(sp->N) * sp->N * sp->N * sizeof(double), s);
+        hipMemsetAsync(ebar, 0, ne * sizeof(double), s);
+        hipMemsetAsync(hbar, 0, nh * sizeof(double), s);
+        launch_csr(pr->d_trowptr, pr->d_tcol, pr->d_tval, res + (NS - 1) * nobs, ebar, pr->d_tidx, pr->ntrows, 1.0,
+                   1.0, s);
+        PairGradArgs g{};
+        space_dims(sp, SP_D, g.lam_dims, g.lam_comp_off);
+        space_dims(sp, SP_H, g.h_dims, g.h_comp_off);
+        g.metric = sp->d_metric;
+        g.metric_mode = sp->metric_mode;
+        g.amp = sp->map.kind == 1 ? sp->map.amplitude : 0.0;
+        g.axis_tab = sp->d_axis_tab;
+        g.inv_eps = sp->d_inv_eps;
+        g.tab = sp->d_tab;
+        for (int k = 0; k < 4; ++k) g.tab_off[k] = sp->tab_off[k];
+        g.ntile = sp->ntile;
+        g.npad = sp->npad;
+        g.n0 = sp->n0;
+        g.n1 = sp->n1;
+        g.N = sp->N;
+        g.coef = -dt;
+        g.grad = grad;
+        g.lam = lam;
+        for (int seg = nseg - 1; seg >= 0; --seg) {
+            const int n0 = seg * K, n1 = std::min(nsteps, n0 + K);
+            hipMemcpyAsync(e, ck_e + int64_t(seg) * ne, ne * sizeof(double), hipMemcpyDeviceToDevice, s);
+            hipMemcpyAsync(h, ck_h + int64_t(seg) * nh, nh * sizeof(double), hipMemcpyDeviceToDevice, s);
+            for (int n = n0; n < n1; ++n) {  // recompute the segment, keeping h^{n+1/2}
+                kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
+                hipMemcpyAsync(seg_h + int64_t(n - n0) * nh, h, nh * sizeof(double), hipMemcpyDeviceToDevice, s);
+            }
+            for (int n = n1 - 1; n >= n0; --n) {
+                const double t = (n + 0.5) * dt;
+                // lam = K1^{-T} ebar
+                run_solve(sp, 1, 1, 0, SP_D, ebar, ne, lam, ne, 1.0, 0, 1, nullptr, 0.0, 1, s);
+                // hbar += dt D~^{1T} M~ lam
+                run_mass(sp, SP_D, false, lam, ne, 1, s);
+                run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, w, ne, 1.0, 0, 1, nullptr, 0.0, 0, s);
+                run_curlT(sp, 0, w, hbar, dt, s);
+                // gradient: -dt / eps_e^2 sum_e Lam . G V   and the dipole terms
+                g.h = seg_h + int64_t(n - n0) * nh;
+                launch_pair_grad(sp->p, g, s);
+                if (J)
+                    launch_source_grad(J->d_entries, J->d_prof, J->d_elem, J->n, J->entries_per, lam, J->d_comp_off,
+                                       J->d_dims, J->d_inv_eps, t, dt, grad, s);
+                // ebar -= dt D^{1T} M K~1^{-T} hbar
+                run_solve(sp, 0, 1, 0, SP_B, hbar, nh, u, nh, 1.0, 0, 1, nullptr, 0.0, 1, s);
+                run_mass(sp, SP_B, false, u, nh, 1, s);
+                run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, w, nh, 1.0, 0, 1, nullptr, 0.0, 0, s);
+                run_curlT(sp, 1, w, ebar, -dt, s);
+                if (n >= 1)
+                    launch_csr(pr->d_trowptr, pr->d_tcol, pr->d_tval, res + int64_t(n - 1) * nobs, ebar, pr->d_tidx,
+                               pr->ntrows, 1.0, 1.0, s);
+            }
+        }
+        double sumsq = 0.0;
+        hipMemcpyAsync(&sumsq, sp->d_scal, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(KMX_E_DEVICE, "adjoint run failed");
+        *loss_host = 0.5 * sumsq;
+        if (st == KMX_OK && hipGetLastError() != hipSuccess) st = fail(KMX_E_DEVICE, "kernel launch failed");
+    }
+    hipStreamSynchronize(s);
+    for (double* b : bufs) hipFree(b);
+    return st;
 }
 
 kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt, int batch, int flags,

@@ -948,6 +948,269 @@ void launch_energy_final(const double* partial, int nblocks, double dt, int batc
 }
 
 // ===========================================================================
+// Adjoint support: transposed curls, probes, per-element permittivity gradient
+// ===========================================================================
+
+// out_j = beta out_j + alpha ((D^T y)_j),  (D^T y)_j = d_{j+2}^T y_{j+1} - d_{j+1}^T y_{j+2};
+// primal d^T: (d^T u)[c] = u[c] - u[c+1]; dual d~^T: (d~^T u)[j] = u[j-1] - u[j]
+__device__ inline double diffT1(const double* u, const int d[3], int primal, int axis, int z, int y, int x) {
+    int i[3] = {x, y, z};
+    const int n = d[2 - axis];  // length of u along the axis
+    auto at = [&](int k) -> double {
+        if (k < 0 || k >= n) return 0.0;
+        int j[3] = {i[0], i[1], i[2]};
+        j[axis] = k;
+        return u[(int64_t(j[2]) * d[1] + j[1]) * d[2] + j[0]];
+    };
+    const int k = i[axis];
+    return primal ? at(k) - at(k + 1) : at(k - 1) - at(k);
+}
+
+__global__ void curlT_kernel(const CurlArgs A, int64_t n_out) {
+    const int b = blockIdx.y;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_out) return;
+    int j = 0;
+    while (j < 2 && i >= A.out_comp_off[j + 1]) ++j;
+    const int64_t li = i - A.out_comp_off[j];
+    const int* od = A.out_dims[j];
+    const int x = int(li % od[2]), y = int((li / od[2]) % od[1]), z = int(li / (int64_t(od[2]) * od[1]));
+    const int c1 = (j + 1) % 3, c2 = (j + 2) % 3;
+    const double* in = A.in + int64_t(b) * A.in_stride;
+    const double v = diffT1(in + A.in_comp_off[c1], A.in_dims[c1], A.primal, c2, z, y, x) -
+                     diffT1(in + A.in_comp_off[c2], A.in_dims[c2], A.primal, c1, z, y, x);
+    double* out = A.out + int64_t(b) * A.out_stride;
+    out[i] = (A.beta == 0.0 ? 0.0 : A.beta * out[i]) + A.alpha * v;
+}
+
+void launch_curlT(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s) {
+    dim3 grid(unsigned((n_out + 255) / 256), batch);
+    hipLaunchKernelGGL(curlT_kernel, grid, dim3(256), 0, s, a, n_out);
+}
+
+// CSR product out[r] = alpha sum_k val[k] x[col[k]] (+ beta out[r]), one thread per row
+__global__ void csr_kernel(const int* rowptr, const int* col, const double* val, const double* x, double* out,
+                           const int* out_index, int nrows, double alpha, double beta) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double s = 0.0;
+    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) s += val[k] * x[col[k]];
+    const int o = out_index ? out_index[r] : r;
+    out[o] = (beta == 0.0 ? 0.0 : beta * out[o]) + alpha * s;
+}
+
+void launch_csr(const int* rowptr, const int* col, const double* val, const double* x, double* out,
+                const int* out_index, int nrows, double alpha, double beta, hipStream_t s) {
+    hipLaunchKernelGGL(csr_kernel, dim3((nrows + 255) / 256), dim3(256), 0, s, rowptr, col, val, x, out, out_index,
+                       nrows, alpha, beta);
+}
+
+// r = obs - data (n values) and the block partial sums of r^2
+__global__ void __launch_bounds__(256) residual_kernel(const double* obs, const double* data, double* r, int64_t n,
+                                                        double* partial) {
+    double s = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const double v = obs[i] - data[i];
+        r[i] = v;
+        s += v * v;
+    }
+    __shared__ double red[3];
+    block_sum3<256>(s, 0.0, 0.0, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+void launch_residual(const double* obs, const double* data, double* r, int64_t n, double* partial, int nblocks,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(nblocks), dim3(256), 0, s, obs, data, r, n, partial);
+}
+
+// dipole terms of the gradient: grad[e0] += coef g(t) (lam . s) / eps_e0, one
+// thread, dipoles in a fixed order (after the element kernel, stream-ordered)
+__global__ void source_grad_kernel(const double* entries, const double* prof, const int* elem, int n_src,
+                                   int entries_per, const double* lam, const int64_t* comp_off, const int* dims,
+                                   const double* src_inv_eps, double t, double coef, double* grad) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int k = 0; k < n_src; ++k) {
+        if (int(prof[4 * k + 3]) != 0) continue;  // batch member 0 only
+        const double dtt = t - prof[4 * k];
+        const double gt = prof[4 * k + 2] * exp(-dtt * dtt / (2.0 * prof[4 * k + 1] * prof[4 * k + 1]));
+        const double* en = entries + int64_t(k) * entries_per * 5;
+        double s = 0.0;
+        for (int e = 0; e < entries_per; ++e) {
+            const int c = int(en[5 * e]);
+            if (c < 0) continue;
+            const int iz = int(en[5 * e + 1]), iy = int(en[5 * e + 2]), ix = int(en[5 * e + 3]);
+            s += lam[comp_off[c] + (int64_t(iz) * dims[3 * c + 1] + iy) * dims[3 * c + 2] + ix] * en[5 * e + 4];
+        }
+        grad[elem[k]] += coef * gt * s * src_inv_eps[k];
+    }
+}
+
+void launch_source_grad(const double* entries, const double* prof, const int* elem, int n_src, int entries_per,
+                        const double* lam, const int64_t* comp_off_dev, const int* dims_dev,
+                        const double* src_inv_eps, double t, double coef, double* grad, hipStream_t s) {
+    hipLaunchKernelGGL(source_grad_kernel, dim3(1), dim3(64), 0, s, entries, prof, elem, n_src, entries_per, lam,
+                       comp_off_dev, dims_dev, src_inv_eps, t, coef, grad);
+}
+
+// Per-element pairing of two dual 2-forms through the metric,
+//   grad_e += coef inv_eps_e^2 sum_{q in e} Lam(q) . G(q) V(q),
+// with Lam interpolated from lam and V from the dual curl of the 1-form h.
+// Same tiling and sum factorisation as the mass kernel; the element sums are
+// reduced over the tile's threads in a fixed order and each tile writes only
+// its own elements.
+template <int P, int MET>
+__global__ void __launch_bounds__(MassCfg<P>::NT) pair_grad_kernel(const PairGradArgs A) {
+    constexpr int NQ = P + 1, Q = TILE * NQ, NT = MassCfg<P>::NT;
+    using L0 = Lay<P, SP_D, 0>;
+    using L1 = Lay<P, SP_D, 1>;
+    using L2 = Lay<P, SP_D, 2>;
+    using S0 = Lay<P, SP_H, 0>;
+    using S1 = Lay<P, SP_H, 1>;
+    using S2 = Lay<P, SP_H, 2>;
+    constexpr int KMAX = P + 1;
+    constexpr int TSL = TILE * NQ * KMAX;
+    constexpr int XW = L0::size + L1::size + L2::size;
+    constexpr int SW = S0::size + S1::size + S2::size;
+    constexpr int BB0 = L0::Wz * Q * L0::Wx, BB1 = L1::Wz * Q * L1::Wx, BB2 = L2::Wz * Q * L2::Wx;
+    constexpr int BB = BB0 > BB1 ? (BB0 > BB2 ? BB0 : BB2) : (BB1 > BB2 ? BB1 : BB2);
+    constexpr int RED = TILE * Q * Q;
+    constexpr int OT = 0, OL = OT + 6 * TSL, OS = OL + XW, OV = OS + SW, OB = OV + XW, OR = OB + BB;
+    __shared__ double sm[OR + RED];
+
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int nt = A.ntile;
+    const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
+    const int tcoord[3] = {tx, ty, tz};
+    const int qy = tid / Q, qx = tid % Q;
+    const bool active = tid < Q * Q;
+
+    for (int i = tid; i < 6 * TSL; i += NT) {
+        const int a = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
+        const int tag = slot == 0 ? space_tag(SP_D, a, a) : space_tag(SP_D, (a + 1) % 3, a);
+        const int K = tag_support(P, tag);
+        if (k < TILE * NQ * K) sm[OT + i] = A.tab[A.tab_off[tag] + int64_t(tcoord[a]) * TILE * NQ * K + k];
+    }
+    load_windows<P, L0, L1, L2, NT>(sm + OL, A.lam, A.lam_comp_off, A.lam_dims, tx, ty, tz, A.n0, A.n1, tid);
+    load_windows<P, S0, S1, S2, NT>(sm + OS, A.h, A.h_comp_off, A.h_dims, tx, ty, tz, A.n0, A.n1, tid);
+    __syncthreads();
+    for (int i = tid; i < XW; i += NT) {
+        if (i < L0::size)
+            sm[OV + i] = curl_at<P, SP_H, SP_D, 0>(sm + OS, sm + OS + S0::size, sm + OS + S0::size + S1::size, i);
+        else if (i < L0::size + L1::size)
+            sm[OV + i] = curl_at<P, SP_H, SP_D, 1>(sm + OS, sm + OS + S0::size, sm + OS + S0::size + S1::size,
+                                                  i - L0::size);
+        else
+            sm[OV + i] = curl_at<P, SP_H, SP_D, 2>(sm + OS, sm + OS + S0::size, sm + OS + S0::size + S1::size,
+                                                  i - L0::size - L1::size);
+    }
+    __syncthreads();
+    const double* T = sm + OT;
+    auto tab = [&](int a, int slot) { return T + (a * 2 + slot) * TSL; };
+    double A0[L0::Wz], A1[L1::Wz], A2[L2::Wz], V0[L0::Wz], V1[L1::Wz], V2[L2::Wz];
+    contract_xy<P, L0, NQ, Q>(sm + OL, sm + OB, tab(0, 0), tab(1, 1), A0, tid, NT, qy, qx, active);
+    contract_xy<P, L1, NQ, Q>(sm + OL + L0::size, sm + OB, tab(0, 1), tab(1, 0), A1, tid, NT, qy, qx, active);
+    contract_xy<P, L2, NQ, Q>(sm + OL + L0::size + L1::size, sm + OB, tab(0, 1), tab(1, 1), A2, tid, NT, qy, qx,
+                              active);
+    contract_xy<P, L0, NQ, Q>(sm + OV, sm + OB, tab(0, 0), tab(1, 1), V0, tid, NT, qy, qx, active);
+    contract_xy<P, L1, NQ, Q>(sm + OV + L0::size, sm + OB, tab(0, 1), tab(1, 0), V1, tid, NT, qy, qx, active);
+    contract_xy<P, L2, NQ, Q>(sm + OV + L0::size + L1::size, sm + OB, tab(0, 1), tab(1, 1), V2, tid, NT, qy, qx,
+                              active);
+    double acc[TILE];
+#pragma unroll
+    for (int le = 0; le < TILE; ++le) acc[le] = 0.0;
+    if (active) {
+        const double* gm = A.metric + int64_t(tile) * Q * 6 * Q * Q + qy * Q + qx;
+        const double* tz0 = tab(2, 1);
+        const double* tz2 = tab(2, 0);
+        const int64_t npq = int64_t(A.npad) * NQ;
+        const int gxq = tx * TILE * NQ + qx, gyq = ty * TILE * NQ + qy;
+        double a1 = 0.0, a2 = 0.0, a3 = 0.0, wxy = 0.0;
+        if (MET == 1) {
+            const double sx = A.axis_tab[gxq], cx = A.axis_tab[npq + gxq], wx = A.axis_tab[2 * npq + gxq];
+            const double sy = A.axis_tab[gyq], cy = A.axis_tab[npq + gyq], wy = A.axis_tab[2 * npq + gyq];
+            a1 = M_PI * cx * sy;
+            a2 = M_PI * sx * cy;
+            a3 = M_PI * sx * sy;
+            wxy = wx * wy;
+        }
+        const double amp = A.amp, aa = 3.0 * A.amp * A.amp;
+#pragma unroll
+        for (int le = 0; le < TILE; ++le) {
+#pragma unroll
+            for (int iq = 0; iq < NQ; ++iq) {
+                const int qz = le * NQ + iq;
+                double g[6];
+                if (MET == 1) {
+                    const int gzq = tz * TILE * NQ + qz;
+                    const double sz = A.axis_tab[gzq], cz = A.axis_tab[npq + gzq], wz = A.axis_tab[2 * npq + gzq];
+                    const double p1 = a1 * sz, p2 = a2 * sz, p3 = a3 * cz;
+                    const double f = wxy * wz / (1.0 + amp * (p1 + p2 + p3));
+                    g[0] = f * (1.0 + 2.0 * amp * p1 + aa * p1 * p1);
+                    g[1] = f * (1.0 + 2.0 * amp * p2 + aa * p2 * p2);
+                    g[2] = f * (1.0 + 2.0 * amp * p3 + aa * p3 * p3);
+                    g[3] = f * (amp * (p1 + p2) + aa * p1 * p2);
+                    g[4] = f * (amp * (p1 + p3) + aa * p1 * p3);
+                    g[5] = f * (amp * (p2 + p3) + aa * p2 * p3);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) g[k] = gm[int64_t(qz) * 6 * Q * Q + k * Q * Q];
+                }
+                const double* t0 = tz0 + (le * NQ + iq) * L0::Kz;
+                const double* t2 = tz2 + (le * NQ + iq) * L2::Kz;
+                double l0 = 0.0, l1 = 0.0, l2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+                for (int j = 0; j < L0::Kz; ++j) {
+                    l0 += t0[j] * A0[le + j];
+                    v0 += t0[j] * V0[le + j];
+                }
+#pragma unroll
+                for (int j = 0; j < L1::Kz; ++j) {
+                    l1 += t0[j] * A1[le + j];
+                    v1 += t0[j] * V1[le + j];
+                }
+#pragma unroll
+                for (int j = 0; j < L2::Kz; ++j) {
+                    l2 += t2[j] * A2[le + j];
+                    v2 += t2[j] * V2[le + j];
+                }
+                acc[le] += l0 * (g[0] * v0 + g[3] * v1 + g[4] * v2) + l1 * (g[3] * v0 + g[1] * v1 + g[5] * v2) +
+                           l2 * (g[4] * v0 + g[5] * v1 + g[2] * v2);
+            }
+        }
+#pragma unroll
+        for (int le = 0; le < TILE; ++le) sm[OR + (le * Q + qy) * Q + qx] = acc[le];
+    }
+    __syncthreads();
+    if (tid < TILE * TILE * TILE) {
+        const int lex = tid % TILE, ley = (tid / TILE) % TILE, lez = tid / (TILE * TILE);
+        const int ex = tx * TILE + lex, ey = ty * TILE + ley, ez = tz * TILE + lez;
+        if (ex < A.N && ey < A.N && ez < A.N) {
+            double s = 0.0;
+            for (int iy = 0; iy < NQ; ++iy)
+                for (int ix = 0; ix < NQ; ++ix) s += sm[OR + (lez * Q + ley * NQ + iy) * Q + lex * NQ + ix];
+            const double ie = A.inv_eps[(int64_t(ez) * A.npad + ey) * A.npad + ex];
+            A.grad[(int64_t(ez) * A.N + ey) * A.N + ex] += A.coef * ie * ie * s;
+        }
+    }
+}
+
+void launch_pair_grad(int p, const PairGradArgs& a, hipStream_t s) {
+    const int nt3 = a.ntile * a.ntile * a.ntile;
+#define LP(PP)                                                                                            \
+    if (p == PP) {                                                                                        \
+        if (a.metric_mode == 1)                                                                           \
+            hipLaunchKernelGGL((pair_grad_kernel<PP, 1>), dim3(nt3), dim3(MassCfg<PP>::NT), 0, s, a);     \
+        else                                                                                              \
+            hipLaunchKernelGGL((pair_grad_kernel<PP, 0>), dim3(nt3), dim3(MassCfg<PP>::NT), 0, s, a);     \
+        return;                                                                                           \
+    }
+    LP(2) LP(3) LP(4)
+#undef LP
+}
+
+// ===========================================================================
 // Dot products and vector updates (CFL power iteration, CG).
 // ===========================================================================
 __global__ void __launch_bounds__(256) dot_kernel(const double* x, const double* y, int64_t n, int64_t stride,

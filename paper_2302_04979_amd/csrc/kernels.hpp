@@ -104,7 +104,35 @@ struct EnergyArgs {
     int mode;
 };
 
+struct PairGradArgs {           // per-element metric pairing of lam and D~^1 h
+    const double* lam;
+    int64_t lam_comp_off[3];
+    int lam_dims[3][3];
+    const double* h;
+    int64_t h_comp_off[3];
+    int h_dims[3][3];
+    const double* metric;
+    int metric_mode;
+    double amp;
+    const double* axis_tab;
+    const double* inv_eps;      // [npad^3]
+    const double* tab;
+    int64_t tab_off[4];
+    int ntile, npad, n0, n1, N;
+    double coef;
+    double* grad;               // [N^3], x fastest
+};
+
 void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s);
+void launch_curlT(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
+void launch_csr(const int* rowptr, const int* col, const double* val, const double* x, double* out,
+                const int* out_index, int nrows, double alpha, double beta, hipStream_t s);
+void launch_residual(const double* obs, const double* data, double* r, int64_t n, double* partial, int nblocks,
+                     hipStream_t s);
+void launch_source_grad(const double* entries, const double* prof, const int* elem, int n_src, int entries_per,
+                        const double* lam, const int64_t* comp_off_dev, const int* dims_dev,
+                        const double* src_inv_eps, double t, double coef, double* grad, hipStream_t s);
+void launch_pair_grad(int p, const PairGradArgs& a, hipStream_t s);
 void launch_gather(int p, int space, const GatherArgs& a, int64_t n, int batch, hipStream_t s);
 void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s);
 void launch_z(int p, const ZArgs& a, int batch, hipStream_t s);

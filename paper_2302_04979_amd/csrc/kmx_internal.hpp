@@ -77,8 +77,22 @@ struct kmx_source {
     int n = 0;
     int batch_max = 0;                 // 1 + largest batch index
     double* d_entries = nullptr;       // device: per dipole, ENTRIES x {comp,iz,iy,ix,val} as doubles
-    double* d_prof = nullptr;          // device: per dipole {t0, sigma, amp, batch}
+    double* d_prof = nullptr;          // device: per dipole {t0, sigma, amp, batch}, then batch offsets
     int entries_per = 0;
+    int* d_elem = nullptr;             // device: element (x fastest, N^3) holding each dipole
+    double* d_inv_eps = nullptr;       // device: 1/eps of that element at creation
+    int64_t* d_comp_off = nullptr;     // device: component offsets of the dual 2-form space
+    int* d_dims = nullptr;             // device: [3][3] dims of the dual 2-form space
+};
+
+struct kmx_probes {
+    kmx_space* sp = nullptr;
+    int n = 0;                         // probes; rows of P = 3 n
+    int *d_rowptr = nullptr, *d_col = nullptr;
+    double* d_val = nullptr;           // P (rows: probe, physical component; columns: e dofs)
+    int ntrows = 0;
+    int *d_trowptr = nullptr, *d_tcol = nullptr, *d_tidx = nullptr;
+    double* d_tval = nullptr;          // P^T restricted to the e dofs it touches
 };
 
 struct kmx_space {
