@@ -55,6 +55,7 @@ extern "C" {
 typedef struct kmx_space kmx_space;
 typedef struct kmx_source kmx_source;
 typedef struct kmx_probes kmx_probes;
+typedef struct kmx_graph kmx_graph;
 
 typedef enum {
     KMX_OK = 0,
@@ -159,6 +160,21 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
  * (requires KMX_TRACK_DB).  Never allocates and never synchronises. */
 kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start,
                     double dt, int nsteps, int batch, int flags, double* energy_dev, void* stream);
+
+/* ---- graph-captured stepping (one graph launch for a chunk of steps) -----
+ * kmx_graph_create captures nsteps leapfrog steps (arguments as kmx_step)
+ * into a HIP graph on a stream owned by the space.  The source time of the
+ * captured steps is read from the space's device clock, which every replay
+ * advances by nsteps*dt, so replaying the graph marches in time; E, H, J and
+ * energy_dev are bound at capture and must stay valid.  The graph contains
+ * kernel nodes only.  kmx_set_time / kmx_get_time set and read the clock
+ * (synchronising). */
+kmx_status kmx_graph_create(kmx_space* sp, double* E, double* H, const kmx_source* J, double dt, int nsteps,
+                            int batch, int flags, double* energy_dev, kmx_graph** out);
+kmx_status kmx_graph_launch(kmx_graph* g, void* stream);
+void kmx_graph_destroy(kmx_graph* g);
+kmx_status kmx_set_time(kmx_space* sp, double t, void* stream);
+kmx_status kmx_get_time(kmx_space* sp, double* t, void* stream);
 
 /* Energies of tracked states (E = [e|d], H = [h|b], at e^n, d^n, h^{n-1/2},
  * b^{n-1/2}), eq. (3.2):

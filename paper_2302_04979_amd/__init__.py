@@ -29,7 +29,8 @@ EXPORTS = (
     "kmx_project_E", "kmx_project_D", "kmx_cfl", "kmx_create_source", "kmx_destroy_source",
     "kmx_init_stagger", "kmx_step", "kmx_energy", "kmx_op_curl", "kmx_op_mass", "kmx_op_solve",
     "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_create_probes", "kmx_destroy_probes",
-    "kmx_probe_eval", "kmx_probe_forward", "kmx_adjoint", "kmx_last_error",
+    "kmx_probe_eval", "kmx_probe_forward", "kmx_adjoint", "kmx_graph_create", "kmx_graph_launch",
+    "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather")
 
@@ -88,6 +89,11 @@ def load_library():
         "kmx_probe_eval": ([vp, vp, vp, vp, vp], i),
         "kmx_probe_forward": ([vp, vp, vp, d, i, vp, vp], i),
         "kmx_adjoint": ([vp, vp, vp, vp, d, i, i, ctypes.POINTER(d), vp, vp], i),
+        "kmx_graph_create": ([vp, vp, vp, vp, d, i, i, i, vp, ctypes.POINTER(vp)], i),
+        "kmx_graph_launch": ([vp, vp], i),
+        "kmx_graph_destroy": ([vp], None),
+        "kmx_set_time": ([vp, d, vp], i),
+        "kmx_get_time": ([vp, ctypes.POINTER(d), vp], i),
         "kmx_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -143,6 +149,36 @@ class Source:
     def close(self):
         if getattr(self, "_h", None):
             load_library().kmx_destroy_source(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured chunk of leapfrog steps (kmx_graph_create); launch() replays it."""
+
+    def __init__(self, space: "Space", E, H, dt, nsteps, J=None, batch=1, flags=0, energy=None):
+        k = 1 + (flags & TRACK_DB)
+        en = None if energy is None else _dptr(energy, nsteps * batch, "energy")
+        h = ctypes.c_void_p()
+        _check(load_library().kmx_graph_create(space._h, _dptr(E, batch * k * space.n_e, "E"),
+                                               _dptr(H, batch * k * space.n_h, "H"), None if J is None else J._h,
+                                               float(dt), int(nsteps), int(batch), int(flags), en, ctypes.byref(h)))
+        self._h = h
+        self._keep = (E, H, J, energy)  # bound at capture
+        self.space = space
+        self.nsteps = nsteps
+
+    def launch(self):
+        _check(load_library().kmx_graph_launch(self._h, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().kmx_graph_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -279,6 +315,18 @@ class Space:
         n = self.n_e if w else self.n_h
         _check(load_library().kmx_op_solve(self._h, w, int(bool(transpose)), _dptr(y, n, "y"), _dptr(x, n, "x"),
                                            _stream()))
+
+    # ---- graph-captured stepping --------------------------------------------
+    def graph(self, E, H, dt, nsteps, J=None, batch=1, flags=0, energy=None) -> Graph:
+        return Graph(self, E, H, dt, nsteps, J, batch, flags, energy)
+
+    def set_time(self, t):
+        _check(load_library().kmx_set_time(self._h, float(t), _stream()))
+
+    def get_time(self) -> float:
+        t = ctypes.c_double()
+        _check(load_library().kmx_get_time(self._h, ctypes.byref(t), _stream()))
+        return t.value
 
     # ---- probes and the adjoint ------------------------------------------
     def probes(self, pos) -> Probes:

@@ -115,7 +115,8 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
 // output).
 void run_solve(kmx_space* sp, int which_K1, int transpose, int from_patch, int gather_space, const double* in,
                int64_t in_stride, double* out, int64_t out_stride, double alpha, int accumulate, int batch,
-               const kmx_source* J, double t_src, int solve, hipStream_t s, const int* fac_override = nullptr) {
+               const kmx_source* J, double t_src, int solve, hipStream_t s, const int* fac_override = nullptr,
+               const double* t_dev = nullptr) {
     const int64_t nfield = std::max(sp->n_e, sp->n_h);
     const int layout = which_K1 ? SP_D : SP_B;  // dims of K1 (= e, d) or K~1 (= h, b) vectors
     if (from_patch) {
@@ -155,6 +156,7 @@ void run_solve(kmx_space* sp, int which_K1, int transpose, int from_patch, int g
         a.n_src = J->n;
         a.entries_per = J->entries_per;
         a.t_src = t_src;
+        a.t_dev = t_dev;
     }
     a.solve = solve;
     {
@@ -382,7 +384,8 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             hipMalloc(&sp->d_tmp, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_tmp2, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_red, size_t(sp->red_len) * sizeof(double)) != hipSuccess ||
-            hipMalloc(&sp->d_scal, size_t(64 + 2 * max_batch) * sizeof(double)) != hipSuccess) {
+            hipMalloc(&sp->d_scal, size_t(64 + 2 * max_batch) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_time, sizeof(double)) != hipSuccess) {
             kmx_destroy_space(sp);
             return fail(KMX_E_OOM, "device allocation failed (scratch)");
         }
@@ -435,6 +438,8 @@ kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches) {
 void kmx_destroy_space(kmx_space* sp) {
     if (!sp) return;
     for (auto& e : sp->prof_ev) (void)hipEventDestroy(e);
+    if (sp->capture_stream) (void)hipStreamDestroy(sp->capture_stream);
+    if (sp->d_time) (void)hipFree(sp->d_time);
     double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_axis_tab, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
                       sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
     for (double* b : bufs)
@@ -943,8 +948,10 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
     return KMX_OK;
 }
 
-kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, double dt,
-                    int nsteps, int batch, int flags, double* energy_dev, void* stream) {
+// The leapfrog loop.  With t_dev the source time of step n is *t_dev +
+// (n + 1/2) dt (graph replay), otherwise t_start + (n + 1/2) dt.
+kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, const double* t_dev,
+                     double dt, int nsteps, int batch, int flags, double* energy_dev, hipStream_t s) {
     if (!sp || !E || !H) return fail(KMX_E_ARG, "NULL argument");
     if (batch < 1 || batch > sp->max_batch) return fail(KMX_E_ARG, "batch out of range");
     if (nsteps < 0) return fail(KMX_E_ARG, "nsteps < 0");
@@ -954,19 +961,84 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
     if (J && track) return fail(KMX_E_ARG, "tracking d and b needs J = NULL (d would need M~^{-1} s)");
     if (energy_dev && !track) return fail(KMX_E_ARG, "energy output needs KMX_TRACK_DB");
     const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     for (int n = 0; n < nsteps; ++n) {
-        const double t_half = t_start + (n + 0.5) * dt;
+        const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
         // M D^1 e (and b -= dt D^1 e), then h -= dt K~1^{-1} (.)
         run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -dt);
         run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -dt, 1, batch, nullptr, 0.0, 1, s);
         // M~ D~^1 h (and d += dt D~^1 h), then e += dt K1^{-1} (. - s)
         run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, dt);
-        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, dt, 1, batch, J, t_half, 1, s);
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, dt, 1, batch, J, t_half, 1, s, nullptr, t_dev);
         if (energy_dev) run_energy(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, 1, s);
     }
+    if (t_dev) launch_advance_time(const_cast<double*>(t_dev), nsteps * dt, s);
     CHECK_LAUNCH();
     return KMX_OK;
+}
+
+kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, double dt,
+                    int nsteps, int batch, int flags, double* energy_dev, void* stream) {
+    return step_loop(sp, E, H, J, t_start, nullptr, dt, nsteps, batch, flags, energy_dev,
+                     static_cast<hipStream_t>(stream));
+}
+
+kmx_status kmx_set_time(kmx_space* sp, double t, void* stream) {
+    if (!sp) return fail(KMX_E_ARG, "space is NULL");
+    HIP_TRY(hipMemcpyAsync(sp->d_time, &t, sizeof(double), hipMemcpyHostToDevice, static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return KMX_OK;
+}
+
+kmx_status kmx_get_time(kmx_space* sp, double* t, void* stream) {
+    if (!sp || !t) return fail(KMX_E_ARG, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(t, sp->d_time, sizeof(double), hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return KMX_OK;
+}
+
+kmx_status kmx_graph_create(kmx_space* sp, double* E, double* H, const kmx_source* J, double dt, int nsteps,
+                            int batch, int flags, double* energy_dev, kmx_graph** out) {
+    if (!sp || !out || nsteps < 1) return fail(KMX_E_ARG, "bad argument");
+    if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on; graphs are captured without timing events");
+    *out = nullptr;
+    if (!sp->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&sp->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = sp->capture_stream;
+    HIP_TRY(hipStreamSynchronize(cs));
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    kmx_status st = step_loop(sp, E, H, J, 0.0, sp->d_time, dt, nsteps, batch, flags, energy_dev, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (st != KMX_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (ec != hipSuccess) return fail(KMX_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        hipGraphDestroy(graph);
+        return fail(KMX_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    kmx_graph* g = new kmx_graph();
+    g->sp = sp;
+    g->graph = graph;
+    g->exec = exec;
+    g->nsteps = nsteps;
+    *out = g;
+    return KMX_OK;
+}
+
+kmx_status kmx_graph_launch(kmx_graph* g, void* stream) {
+    if (!g) return fail(KMX_E_ARG, "graph is NULL");
+    HIP_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return KMX_OK;
+}
+
+void kmx_graph_destroy(kmx_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 kmx_status kmx_energy(kmx_space* sp, const double* E, const double* H, double dt, int batch, double* out_host,

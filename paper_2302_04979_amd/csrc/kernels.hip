@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(256) xy_kernel(const XYArgs A) {
         if (tid == 0) {
             for (int k = A.src_off[b]; k < A.src_off[b + 1]; ++k) {
                 const double* pr = A.src_prof + 4 * k;
-                const double dtt = A.t_src - pr[0];
+                const double dtt = (A.t_dev ? *A.t_dev : 0.0) + A.t_src - pr[0];
                 const double gt = pr[2] * exp(-dtt * dtt / (2.0 * pr[1] * pr[1]));
                 const double* en = A.src_entries + int64_t(k) * A.entries_per * 5;
                 for (int e = 0; e < A.entries_per; ++e) {
@@ -1249,6 +1249,14 @@ __global__ void axpby_kernel(const double* x, double* y, int64_t n, double ka, c
     if (i >= n) return;
     const double a = sa ? sa[0] * ka : ka;
     y[i] = a * x[i] + (kb == 0.0 ? 0.0 : kb * y[i]);
+}
+
+__global__ void advance_time_kernel(double* t, double dt) {
+    if (threadIdx.x == 0) t[0] += dt;
+}
+
+void launch_advance_time(double* t, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(advance_time_kernel, dim3(1), dim3(64), 0, s, t, dt);
 }
 
 void launch_axpby(const double* x, double* y, int64_t n, double ka, const double* sa, double kb, hipStream_t s) {

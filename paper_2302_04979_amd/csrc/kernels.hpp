@@ -60,7 +60,8 @@ struct XYArgs {
     const double* src_prof;     // [n_src][4] = t0, sigma, amp, batch
     const int* src_off;         // [batch+1] dipoles of each batch member (sorted)
     int n_src, entries_per;
-    double t_src;
+    double t_src;               // source time = (t_dev ? *t_dev : 0) + t_src
+    const double* t_dev;
     int solve;                  // line operation: 0 none (copy), 1 solve, 2 banded apply
 };
 
@@ -150,6 +151,8 @@ void launch_axpby(const double* x, double* y, int64_t n, double ka, const double
                   hipStream_t s);
 void launch_cg_update(double* x, double* r, double* pdir, const double* Ap, const double* z,
                       int64_t n, const double* scal, int phase, hipStream_t s);
+
+void launch_advance_time(double* t, double dt, hipStream_t s);
 
 int mass_threads(int p);
 int64_t patch_size(int p, int space, int ntile, int64_t comp_off[3]);

@@ -85,6 +85,13 @@ struct kmx_source {
     int* d_dims = nullptr;             // device: [3][3] dims of the dual 2-form space
 };
 
+struct kmx_graph {
+    kmx_space* sp = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int nsteps = 0;
+};
+
 struct kmx_probes {
     kmx_space* sp = nullptr;
     int n = 0;                         // probes; rows of P = 3 n
@@ -122,6 +129,8 @@ struct kmx_space {
     double* d_red = nullptr;           // reduction partials
     int64_t red_len = 0;
     double* d_scal = nullptr;          // small device scalars
+    double* d_time = nullptr;          // device time read by graph-captured steps
+    hipStream_t capture_stream = nullptr;
     // optional per-kernel timing with HIP events (kmx_profile_begin/end)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
