@@ -161,6 +161,43 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
 kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start,
                     double dt, int nsteps, int batch, int flags, double* energy_dev, void* stream);
 
+/* ---- execution plans and the autotuner -----------------------------------
+ * A space runs kmx_step (and the steps captured by kmx_graph_create) with one
+ * of two plans:
+ *   KMX_PLAN_TILED      any map and materials: per half step a fused curl +
+ *                       sum-factorised mass apply over 4^3-element tiles,
+ *                       then the per-axis banded pairing solves (Section 4).
+ *   KMX_PLAN_SEPARABLE  identity map with eps and mu the same in every
+ *                       element: the Hodge matrices are then Kronecker
+ *                       products of 1D Gram matrices like the pairings
+ *                       (eqs. (4.2)-(4.3)), so each half step is a curl and
+ *                       banded mode products along x, y, z.  One persistent
+ *                       workgroup per batch member advances it by all nsteps
+ *                       with its component tensors in LDS (lines up to 28,
+ *                       components up to the device's LDS per workgroup,
+ *                       e.g. p = 3, N <= 25).  No per-step energy output.
+ * KMX_PLAN_AUTO (the default) takes the separable plan when it applies and
+ * batch >= 32, the tiled plan otherwise.  `threads` is the separable kernel's
+ * workgroup size (64..768, multiple of 64).  Forcing KMX_PLAN_SEPARABLE on a
+ * call it cannot serve fails with KMX_E_STATE.  Both plans compute the same
+ * operators; results differ by rounding only. */
+#define KMX_PLAN_AUTO (-1)
+#define KMX_PLAN_TILED 0
+#define KMX_PLAN_SEPARABLE 1
+kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads);
+kmx_status kmx_get_plan(const kmx_space* sp, int* kind, int* threads);
+
+/* Times the candidate plans on `batch` members (zero fields of its own, J
+ * driving them if not NULL, time step dt) over probe_steps steps each after
+ * one warm-up step, and keeps the fastest as the space's plan.  Candidates:
+ * 0 tiled; 1..5 separable with 256, 384, 512, 640, 768 threads.  ms_out:
+ * NULL or host array of KMX_TUNE_CANDIDATES entries receiving the mean ms per
+ * step (-1 where a candidate does not apply).  Allocates two fields of
+ * working memory; synchronises. */
+#define KMX_TUNE_CANDIDATES 6
+kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source* J, double dt, double* ms_out,
+                    void* stream);
+
 /* ---- graph-captured stepping (one graph launch for a chunk of steps) -----
  * kmx_graph_create captures nsteps leapfrog steps (arguments as kmx_step)
  * into a HIP graph on a stream owned by the space.  The source time of the
@@ -253,6 +290,7 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
  *   4 curl (tracking of b and d)
  *   5 energy reductions
  *   6 patch gather (sum of the overlapping tile outputs of a mass apply)
+ *   7 separable persistent kernel (one launch for all steps of a call)
  * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
 #define KMX_PROFILE_KINDS 8
 kmx_status kmx_profile_begin(kmx_space* sp, int capacity);

@@ -22,6 +22,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
 TRACK_DB = 1
 STORED_METRIC = 16
+PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE = -1, 0, 1
+TUNE_CANDIDATES = 6
+TUNE_LABELS = ("tiled", "separable/256", "separable/384", "separable/512", "separable/640", "separable/768")
 
 # every symbol declared in include/kronmaxwell.h
 EXPORTS = (
@@ -29,10 +32,11 @@ EXPORTS = (
     "kmx_project_E", "kmx_project_D", "kmx_cfl", "kmx_create_source", "kmx_destroy_source",
     "kmx_init_stagger", "kmx_step", "kmx_energy", "kmx_op_curl", "kmx_op_mass", "kmx_op_solve",
     "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_create_probes", "kmx_destroy_probes",
-    "kmx_probe_eval", "kmx_probe_forward", "kmx_adjoint", "kmx_graph_create", "kmx_graph_launch",
+    "kmx_probe_eval", "kmx_probe_forward", "kmx_adjoint", "kmx_set_plan", "kmx_get_plan", "kmx_tune",
+    "kmx_graph_create", "kmx_graph_launch",
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
 )
-PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather")
+PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable")
 
 _STATUS = {0: "KMX_OK", 1: "KMX_E_ARG", 2: "KMX_E_GEOMETRY", 3: "KMX_E_MATERIAL", 4: "KMX_E_DEVICE",
            5: "KMX_E_OOM", 6: "KMX_E_UNSTABLE", 7: "KMX_E_STATE"}
@@ -89,6 +93,9 @@ def load_library():
         "kmx_probe_eval": ([vp, vp, vp, vp, vp], i),
         "kmx_probe_forward": ([vp, vp, vp, d, i, vp, vp], i),
         "kmx_adjoint": ([vp, vp, vp, vp, d, i, i, ctypes.POINTER(d), vp, vp], i),
+        "kmx_set_plan": ([vp, i, i], i),
+        "kmx_get_plan": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+        "kmx_tune": ([vp, i, i, vp, d, vp, vp], i),
         "kmx_graph_create": ([vp, vp, vp, vp, d, i, i, i, vp, ctypes.POINTER(vp)], i),
         "kmx_graph_launch": ([vp, vp], i),
         "kmx_graph_destroy": ([vp], None),
@@ -315,6 +322,23 @@ class Space:
         n = self.n_e if w else self.n_h
         _check(load_library().kmx_op_solve(self._h, w, int(bool(transpose)), _dptr(y, n, "y"), _dptr(x, n, "x"),
                                            _stream()))
+
+    # ---- execution plans --------------------------------------------------
+    def set_plan(self, kind: int, threads: int = 768):
+        _check(load_library().kmx_set_plan(self._h, int(kind), int(threads)))
+
+    def plan(self):
+        k, t = ctypes.c_int(), ctypes.c_int()
+        _check(load_library().kmx_get_plan(self._h, ctypes.byref(k), ctypes.byref(t)))
+        return k.value, t.value
+
+    def tune(self, batch: int, dt: float, probe_steps: int = 5, J: "Source | None" = None):
+        """Time the candidate plans and keep the fastest; returns the mean ms
+        per step of each candidate (None where it does not apply)."""
+        ms = np.zeros(TUNE_CANDIDATES)
+        _check(load_library().kmx_tune(self._h, int(batch), int(probe_steps), None if J is None else J._h,
+                                       float(dt), ctypes.c_void_p(ms.ctypes.data), _stream()))
+        return [None if m < 0 else float(m) for m in ms]
 
     # ---- graph-captured stepping --------------------------------------------
     def graph(self, E, H, dt, nsteps, J=None, batch=1, flags=0, energy=None) -> Graph:

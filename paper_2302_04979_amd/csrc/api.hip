@@ -60,7 +60,7 @@ void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
 }
 
 // Kernel kinds reported by kmx_profile_end.
-enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6 };
+enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6, PK_SEP = 7 };
 
 struct ProfScope {  // brackets one launch with events when profiling is on
     kmx_space* sp;
@@ -267,6 +267,17 @@ kmx_status upload_materials(kmx_space* sp) {
     return KMX_OK;
 }
 
+// whether eps and mu are the same in every element (a separable space needs both)
+void note_uniform(kmx_space* sp) {
+    sp->uniform_eps = sp->uniform_mu = true;
+    for (size_t i = 1; i < sp->inv_eps_host.size(); ++i) {
+        if (sp->inv_eps_host[i] != sp->inv_eps_host[0]) sp->uniform_eps = false;
+        if (sp->inv_mu_host[i] != sp->inv_mu_host[0]) sp->uniform_mu = false;
+    }
+    sp->eps_value = sp->inv_eps_host.empty() ? 1.0 : sp->inv_eps_host[0];
+    sp->mu_value = sp->inv_mu_host.empty() ? 1.0 : sp->inv_mu_host[0];
+}
+
 std::vector<double> gram(const Tables& tb, int tag) {
     const int n = (tag == PV || tag == DD) ? tb.n0 : tb.n1;
     const int K = tag_support(tb.p, tag);
@@ -369,6 +380,33 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             facs.insert(facs.end(), f.band.begin(), f.band.end());
         }
         if ((st = upload(&sp->d_fac, facs)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        {
+            // 1D Gram matrices of the four tags as bands of half width p (the
+            // separable plan's Hodge factors)
+            std::vector<double> gb;
+            const int B = 2 * p + 1;
+            for (int t = 0; t < 4; ++t) {
+                sp->gram_off[t] = int64_t(gb.size());
+                const int n = (t == PV || t == DD) ? sp->n0 : sp->n1;
+                const std::vector<double> G = gram(sp->tb, t);
+                for (int i = 0; i < n; ++i)
+                    for (int k = 0; k < B; ++k) {
+                        const int j = i - p + k;
+                        gb.push_back(j >= 0 && j < n ? G[size_t(i) * n + j] : 0.0);
+                    }
+            }
+            if ((st = upload(&sp->d_gram, gb)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+            int dev = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&sp->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            int ed[3][3], hd[3][3];
+            int64_t o[3];
+            space_dims(sp, SP_E, ed, o);
+            space_dims(sp, SP_H, hd, o);
+            const size_t shm = sep_lds_bytes(ed, hd);
+            const int lmax = sep_line_max(std::max(sp->n0, sp->n1));
+            if (lmax > 0 && shm <= size_t(sp->max_lds)) HIP_TRY(sep_prepare(p, lmax, shm));
+        }
         const size_t npad3 = size_t(sp->npad) * sp->npad * sp->npad;
         if (hipMalloc(&sp->d_inv_eps, npad3 * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_inv_mu, npad3 * sizeof(double)) != hipSuccess) {
@@ -441,7 +479,7 @@ void kmx_destroy_space(kmx_space* sp) {
     if (sp->capture_stream) (void)hipStreamDestroy(sp->capture_stream);
     if (sp->d_time) (void)hipFree(sp->d_time);
     double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_axis_tab, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
-                      sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
+                      sp->d_gram, sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     delete sp;
@@ -465,6 +503,7 @@ kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double
     }
     sp->inv_eps_host = ie;
     sp->inv_mu_host = im;
+    note_uniform(sp);
     return upload_materials(sp);
 }
 
@@ -950,6 +989,57 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
 
 // The leapfrog loop.  With t_dev the source time of step n is *t_dev +
 // (n + 1/2) dt (graph replay), otherwise t_start + (n + 1/2) dt.
+// Whether the separable persistent kernel can run a step call: identity map,
+// eps and mu the same in every element, no per-step energy output, lines that
+// fit the kernel's registers and component tensors that fit one workgroup's LDS.
+bool sep_eligible(const kmx_space* sp, const double* energy_dev) {
+    if (sp->map.kind != 0 || !sp->uniform_eps || !sp->uniform_mu || energy_dev) return false;
+    if (sep_line_max(std::max(sp->n0, sp->n1)) == 0) return false;
+    int ed[3][3], hd[3][3];
+    int64_t o[3];
+    space_dims(sp, SP_E, ed, o);
+    space_dims(sp, SP_H, hd, o);
+    return sep_lds_bytes(ed, hd) <= size_t(sp->max_lds);
+}
+
+// Batches from this size up take the separable kernel when no plan is set
+// (one workgroup per member; small batches leave most compute units idle).
+constexpr int SEP_AUTO_MIN_BATCH = 32;
+
+kmx_status run_sep(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, const double* t_dev,
+                   double dt, int nsteps, int batch, int track, hipStream_t s) {
+    SepArgs a{};
+    a.n_e = sp->n_e;
+    a.n_h = sp->n_h;
+    a.track = track;
+    a.e_stride = sp->n_e * (1 + track);
+    a.h_stride = sp->n_h * (1 + track);
+    space_dims(sp, SP_E, a.edims, a.e_off);
+    space_dims(sp, SP_H, a.hdims, a.h_off);
+    for (int k = 0; k < 4; ++k) {
+        a.gram_off[k] = sp->gram_off[k];
+        a.fac_off[k] = sp->fac_off[k];
+    }
+    a.inv_mu = sp->mu_value;
+    a.inv_eps = sp->eps_value;
+    a.dt = dt;
+    a.nsteps = nsteps;
+    a.t_start = t_start;
+    a.t_dev = t_dev;
+    if (J) {
+        a.src_entries = J->d_entries;
+        a.src_prof = J->d_prof;
+        a.src_off = reinterpret_cast<const int*>(J->d_prof + 4 * J->n);
+        a.n_src = J->n;
+        a.entries_per = J->entries_per;
+    }
+    ProfScope ps(sp, s, PK_SEP);
+    const hipError_t err = launch_sep(sp->p, sep_line_max(std::max(sp->n0, sp->n1)), E, H, sp->d_gram, sp->d_fac,
+                                      a, batch, sp->plan_threads, s);
+    if (err != hipSuccess) return fail(KMX_E_DEVICE, std::string("separable kernel: ") + hipGetErrorString(err));
+    return KMX_OK;
+}
+
 kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, const double* t_dev,
                      double dt, int nsteps, int batch, int flags, double* energy_dev, hipStream_t s) {
     if (!sp || !E || !H) return fail(KMX_E_ARG, "NULL argument");
@@ -960,6 +1050,21 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     if (J && J->sp != sp) return fail(KMX_E_ARG, "source belongs to another space");
     if (J && track) return fail(KMX_E_ARG, "tracking d and b needs J = NULL (d would need M~^{-1} s)");
     if (energy_dev && !track) return fail(KMX_E_ARG, "energy output needs KMX_TRACK_DB");
+    const bool sep_ok = sep_eligible(sp, energy_dev);
+    int kind = sp->plan_kind;
+    if (kind == KMX_PLAN_SEPARABLE && !sep_ok)
+        return fail(KMX_E_STATE, "separable plan needs the identity map, uniform eps and mu, no energy output "
+                                 "and component tensors that fit one workgroup's LDS");
+    if (kind == KMX_PLAN_AUTO) kind = (sep_ok && batch >= SEP_AUTO_MIN_BATCH) ? KMX_PLAN_SEPARABLE : KMX_PLAN_TILED;
+    if (kind == KMX_PLAN_SEPARABLE) {
+        if (nsteps > 0) {
+            const kmx_status st = run_sep(sp, E, H, J, t_start, t_dev, dt, nsteps, batch, track, s);
+            if (st != KMX_OK) return st;
+        }
+        if (t_dev) launch_advance_time(const_cast<double*>(t_dev), nsteps * dt, s);
+        CHECK_LAUNCH();
+        return KMX_OK;
+    }
     const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
@@ -993,6 +1098,82 @@ kmx_status kmx_get_time(kmx_space* sp, double* t, void* stream) {
     if (!sp || !t) return fail(KMX_E_ARG, "NULL argument");
     HIP_TRY(hipMemcpyAsync(t, sp->d_time, sizeof(double), hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)));
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return KMX_OK;
+}
+
+kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads) {
+    if (!sp) return fail(KMX_E_ARG, "space is NULL");
+    if (kind != KMX_PLAN_AUTO && kind != KMX_PLAN_TILED && kind != KMX_PLAN_SEPARABLE)
+        return fail(KMX_E_ARG, "unknown plan kind");
+    if (threads < 64 || threads > 768 || threads % 64) return fail(KMX_E_ARG, "threads must be 64..768, a multiple of 64");
+    sp->plan_kind = kind;
+    sp->plan_threads = threads;
+    return KMX_OK;
+}
+
+kmx_status kmx_get_plan(const kmx_space* sp, int* kind, int* threads) {
+    if (!sp || !kind || !threads) return fail(KMX_E_ARG, "NULL argument");
+    *kind = sp->plan_kind;
+    *threads = sp->plan_threads;
+    return KMX_OK;
+}
+
+kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source* J, double dt, double* ms_out,
+                    void* stream) {
+    if (!sp || batch < 1 || batch > sp->max_batch || probe_steps < 1) return fail(KMX_E_ARG, "bad argument");
+    if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 256, 384, 512, 640, 768};
+    const bool sep_ok = sep_eligible(sp, nullptr);
+    double* E = nullptr;
+    double* H = nullptr;
+    if (hipMalloc(&E, size_t(batch) * sp->n_e * sizeof(double)) != hipSuccess ||
+        hipMalloc(&H, size_t(batch) * sp->n_h * sizeof(double)) != hipSuccess) {
+        if (E) (void)hipFree(E);
+        return fail(KMX_E_OOM, "device allocation failed (tuning fields)");
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const int saved_kind = sp->plan_kind, saved_threads = sp->plan_threads;
+    kmx_status st = KMX_OK;
+    double best = 1e300;
+    int best_k = 0;
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) st = fail(KMX_E_DEVICE, "events");
+    (void)hipMemsetAsync(E, 0, size_t(batch) * sp->n_e * sizeof(double), s);
+    (void)hipMemsetAsync(H, 0, size_t(batch) * sp->n_h * sizeof(double), s);
+    for (int k = 0; k < KMX_TUNE_CANDIDATES && st == KMX_OK; ++k) {
+        double ms = -1.0;
+        if (k == 0 || sep_ok) {
+            sp->plan_kind = k == 0 ? KMX_PLAN_TILED : KMX_PLAN_SEPARABLE;
+            sp->plan_threads = k == 0 ? saved_threads : cand_threads[k];
+            st = step_loop(sp, E, H, J, 0.0, nullptr, dt, 1, batch, 0, nullptr, s);  // warm-up
+            if (st == KMX_OK) (void)hipEventRecord(ev[0], s);
+            if (st == KMX_OK) st = step_loop(sp, E, H, J, 0.0, nullptr, dt, probe_steps, batch, 0, nullptr, s);
+            if (st == KMX_OK) (void)hipEventRecord(ev[1], s);
+            float f = 0.0f;
+            if (st == KMX_OK && (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&f, ev[0], ev[1]) != hipSuccess))
+                st = fail(KMX_E_DEVICE, "tuning run failed");
+            if (st == KMX_OK) {
+                ms = double(f) / probe_steps;
+                if (ms < best) {
+                    best = ms;
+                    best_k = k;
+                }
+            }
+        }
+        if (ms_out) ms_out[k] = ms;
+    }
+    (void)hipStreamSynchronize(s);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    (void)hipFree(E);
+    (void)hipFree(H);
+    if (st != KMX_OK) {
+        sp->plan_kind = saved_kind;
+        sp->plan_threads = saved_threads;
+        return st;
+    }
+    sp->plan_kind = best_k == 0 ? KMX_PLAN_TILED : KMX_PLAN_SEPARABLE;
+    sp->plan_threads = best_k == 0 ? saved_threads : cand_threads[best_k];
     return KMX_OK;
 }
 

@@ -124,6 +124,33 @@ struct PairGradArgs {           // per-element metric pairing of lam and D~^1 h
     double* grad;               // [N^3], x fastest
 };
 
+// Persistent leapfrog of separable spaces (identity map, uniform eps and mu):
+// one workgroup per batch member runs all nsteps with the component tensors
+// in LDS.  Fields are passed as kernel arguments of their own.
+constexpr int SEP_LINE_MAX = 28;   // longest line (n0, n1) the kernel holds in registers
+struct SepArgs {
+    int64_t e_stride, h_stride;    // distance between batch members (doubled with tracking)
+    int64_t n_e, n_h;              // offset of d inside E and of b inside H
+    int track;
+    int64_t e_off[3], h_off[3];    // component offsets of the e/d and h/b spaces
+    int edims[3][3], hdims[3][3];  // [c][z, y, x]
+    int64_t gram_off[4];           // per tag: n rows of 2p+1 band entries (half width p)
+    int64_t fac_off[4];            // banded LU of G^, M^, G^T, M^T: [L | U | dinv | band]
+    double inv_mu, inv_eps, dt;
+    int nsteps;
+    double t_start;                // source time of step n: (t_dev ? *t_dev : t_start) + (n + 1/2) dt
+    const double* t_dev;
+    const double* src_entries;     // as XYArgs
+    const double* src_prof;
+    const int* src_off;
+    int n_src, entries_per;
+};
+size_t sep_lds_bytes(const int edims[3][3], const int hdims[3][3]);
+int sep_line_max(int n_max);       // register line length for lines up to n_max, 0 if too long
+hipError_t sep_prepare(int p, int lmax, size_t shm);   // grant the kernel its LDS (outside graph capture)
+hipError_t launch_sep(int p, int lmax, double* E, double* H, const double* gram, const double* fac,
+                      const SepArgs& a, int batch, int threads, hipStream_t s);
+
 void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s);
 void launch_curlT(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
 void launch_csr(const int* rowptr, const int* col, const double* val, const double* x, double* out,

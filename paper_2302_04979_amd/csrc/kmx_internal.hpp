@@ -130,6 +130,14 @@ struct kmx_space {
     int64_t red_len = 0;
     double* d_scal = nullptr;          // small device scalars
     double* d_time = nullptr;          // device time read by graph-captured steps
+    // separable plan (identity map, uniform materials): 1D Gram bands per tag
+    double* d_gram = nullptr;          // per tag: n rows x (2p+1), half width p
+    int64_t gram_off[4] = {0, 0, 0, 0};
+    bool uniform_eps = true, uniform_mu = true;
+    double eps_value = 1.0, mu_value = 1.0;   // 1/eps and 1/mu when uniform
+    int max_lds = 0;                   // device limit of LDS bytes per workgroup
+    int plan_kind = -1;                // -1 automatic, KMX_PLAN_TILED, KMX_PLAN_SEPARABLE
+    int plan_threads = 768;            // workgroup size of the separable kernel
     hipStream_t capture_stream = nullptr;
     // optional per-kernel timing with HIP events (kmx_profile_begin/end)
     bool prof_on = false;

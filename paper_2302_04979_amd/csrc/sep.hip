@@ -1,0 +1,273 @@
+// Persistent leapfrog for separable spaces: identity map and uniform eps, mu.
+//
+// With F = id the 2-form metric is the identity, so the Hodge matrices of
+// Section 3.5 are Kronecker products of 1D Gram matrices (scaled by 1/mu and
+// 1/eps), exactly as the pairings K1, K~1 are Kronecker products of the 1D
+// G^, M^ (eqs. (4.2)-(4.3)).  One half step of component c is then
+//     curl -> three banded Gram products -> (source) -> three banded solves,
+// a chain of mode-n products along x, y and z of one component tensor.  At
+// the sizes where the tensor fits one workgroup's LDS (p = 3: N <= 25), the
+// whole chain runs there and each batch member is owned by one workgroup for
+// all of its steps: one launch advances every member by nsteps, with only
+// workgroup barriers (members never exchange data).
+//
+// Each mode product is a per-thread pass over the lines of that axis: the
+// line is loaded from LDS into registers, the banded Gram product and the
+// banded LU substitution run in registers, and the line is written back.
+#include "kernels.hpp"
+
+namespace kmx {
+
+namespace {
+
+// (d v)[k] = v[k] - v[k-1] (primal, zero outside) or v[k+1] - v[k] (dual) of
+// component array u (dims [z, y, x]) along `axis`, at the output position.
+__device__ inline double sep_diff(const double* u, const int d[3], int primal, int axis, int z, int y, int x) {
+    const int sx = 1, sy = d[2], sz = d[1] * d[2];
+    const int idx = z * sz + y * sy + x * sx;
+    const int st = axis == 0 ? sx : (axis == 1 ? sy : sz);
+    const int k = axis == 0 ? x : (axis == 1 ? y : z);
+    const int n = d[2 - axis];
+    if (primal) {
+        const double a = k < n ? u[idx] : 0.0;
+        const double b = k >= 1 ? u[idx - st] : 0.0;
+        return a - b;
+    }
+    return u[idx + st] - u[idx];
+}
+
+// y = scale * (band x) in registers; band rows hold 2P+1 entries of half
+// width P (zeros outside the matrix); entries i >= n stay zero.
+template <int P, int LMAX>
+__device__ inline void gram_regs(double (&r)[LMAX], int n, const double* __restrict__ band, double scale) {
+    constexpr int B = 2 * P + 1;
+    double win[P];  // the P original entries before i
+#pragma unroll
+    for (int m = 0; m < P; ++m) win[m] = 0.0;
+#pragma unroll
+    for (int i = 0; i < LMAX; ++i) {
+        double s = 0.0;
+        if (i < n) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int j = i - P + k;
+                const double v = k < P ? win[k] : (j < LMAX ? r[j] : 0.0);
+                s += band[i * B + k] * v;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m + 1 < P; ++m) win[m] = win[m + 1];
+        win[P - 1] = r[i];
+        r[i] = s * scale;
+    }
+}
+
+// x = (LU)^{-1} r in registers, banded factors of half width W = P-1.
+template <int P, int LMAX>
+__device__ inline void lu_regs(double (&r)[LMAX], int n, const double* __restrict__ L, const double* __restrict__ U,
+                               const double* __restrict__ dinv) {
+    constexpr int W = P - 1;
+#pragma unroll
+    for (int i = 1; i < LMAX; ++i) {
+        if (i < n) {
+            double s = r[i];
+#pragma unroll
+            for (int m = 0; m < W; ++m)
+                if (i - 1 - m >= 0) s -= L[i * W + m] * r[i - 1 - m];
+            r[i] = s;
+        }
+    }
+#pragma unroll
+    for (int i = LMAX - 1; i >= 0; --i) {
+        if (i < n) {
+            double s = r[i];
+#pragma unroll
+            for (int m = 0; m < W; ++m)
+                if (i + 1 + m < LMAX) s -= U[i * W + m] * r[i + 1 + m];
+            r[i] = s * dinv[i];
+        }
+    }
+}
+
+enum { OP_GRAM = 1, OP_SOLVE = 2 };
+
+// One mode product over all lines of `axis` of the LDS tensor (dims [z, y, x],
+// row pitch `pitch`): Gram product (scaled), banded solve, or both.
+template <int P, int LMAX, int OPS>
+__device__ inline void sep_pass(double* buf, int axis, const int d[3], int pitch, const double* __restrict__ band,
+                                double scale, const double* __restrict__ fac, int tid, int nthr) {
+    const int nz = d[0], ny = d[1], nx = d[2];
+    const int n = d[2 - axis];
+    const int stride = axis == 0 ? 1 : (axis == 1 ? pitch : ny * pitch);
+    const int nlines = axis == 0 ? nz * ny : (axis == 1 ? nz * nx : ny * nx);
+    const double* L = fac;
+    const double* U = fac + n * (P - 1);
+    const double* dinv = fac + 2 * n * (P - 1);
+    // one line per thread: the launch gives at least as many threads as lines
+    // (a loop here would let the compiler hoist every row's coefficients)
+    const int l = tid;
+    if (l < nlines) {
+        int base;
+        if (axis == 0) base = l * pitch;                              // l = z*ny + y
+        else if (axis == 1) base = (l / nx) * ny * pitch + (l % nx);  // l = z*nx + x
+        else base = (l / nx) * pitch + (l % nx);                      // l = y*nx + x
+        double r[LMAX];
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i) r[i] = i < n ? buf[base + i * stride] : 0.0;
+        if (OPS & OP_GRAM) gram_regs<P, LMAX>(r, n, band, scale);
+        if (OPS & OP_SOLVE) lu_regs<P, LMAX>(r, n, L, U, dinv);
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i)
+            if (i < n) buf[base + i * stride] = r[i];
+    }
+}
+
+__host__ __device__ constexpr int pair_lu(int which_K1, int c, int a) {
+    return which_K1 ? (a == c ? F_M : F_G) : (a == c ? F_GT : F_MT);
+}
+
+template <int P, int LMAX>
+__global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double* __restrict__ H,
+                                                   const double* __restrict__ gram,
+                                                   const double* __restrict__ fac, const SepArgs A) {
+    extern __shared__ double buf[];
+    const int b = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+    double* e = E + int64_t(b) * A.e_stride;
+    double* h = H + int64_t(b) * A.h_stride;
+    const double t0 = A.t_dev ? *A.t_dev : A.t_start;
+#pragma unroll 1
+    for (int step = 0; step < A.nsteps; ++step) {
+        // ---- h^{n+1/2} = h^{n-1/2} - dt K~1^{-1} M D^1 e^n   [b -= dt D^1 e] ----
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            const int* od = A.hdims[c];
+            const int ny = od[1], nx = od[2], pitch = nx | 1, cnt = od[0] * ny * nx;
+            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+            for (int i = tid; i < cnt; i += nthr) {
+                const int x = i % nx, q = i / nx, y = q % ny, z = q / ny;
+                const double u = sep_diff(e + A.e_off[a2], A.edims[a2], 1, a1, z, y, x) -
+                                 sep_diff(e + A.e_off[a1], A.edims[a1], 1, a2, z, y, x);
+                buf[(z * ny + y) * pitch + x] = u;
+                if (A.track) h[A.n_h + A.h_off[c] + i] -= A.dt * u;
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int a = 0; a < 3; ++a) {
+                sep_pass<P, LMAX, OP_GRAM | OP_SOLVE>(buf, a, od, pitch, gram + A.gram_off[space_tag(SP_B, c, a)],
+                                                      1.0, fac + A.fac_off[pair_lu(0, c, a)], tid, nthr);
+                __syncthreads();
+            }
+            const double alpha = -A.dt * A.inv_mu;
+            for (int i = tid; i < cnt; i += nthr) {
+                const int x = i % nx, q = i / nx;
+                h[A.h_off[c] + i] += alpha * buf[q * pitch + x];
+            }
+            __syncthreads();
+        }
+        // ---- e^{n+1} = e^n + dt K1^{-1} (M~ D~^1 h^{n+1/2} - s(t_{n+1/2}))   [d += dt D~^1 h] ----
+        const double th = t0 + (step + 0.5) * A.dt;
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            const int* od = A.edims[c];
+            const int ny = od[1], nx = od[2], pitch = nx | 1, cnt = od[0] * ny * nx;
+            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+            for (int i = tid; i < cnt; i += nthr) {
+                const int x = i % nx, q = i / nx, y = q % ny, z = q / ny;
+                const double v = sep_diff(h + A.h_off[a2], A.hdims[a2], 0, a1, z, y, x) -
+                                 sep_diff(h + A.h_off[a1], A.hdims[a1], 0, a2, z, y, x);
+                buf[(z * ny + y) * pitch + x] = v;
+                if (A.track) e[A.n_e + A.e_off[c] + i] += A.dt * v;
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int a = 0; a < 3; ++a) {
+                sep_pass<P, LMAX, OP_GRAM>(buf, a, od, pitch, gram + A.gram_off[space_tag(SP_D, c, a)],
+                                           a == 2 ? A.inv_eps : 1.0, fac, tid, nthr);
+                __syncthreads();
+            }
+            // tested point sources, subtracted between the Gram products and the solves
+            for (int k = A.n_src > 0 ? A.src_off[b] : 0; k < (A.n_src > 0 ? A.src_off[b + 1] : 0); ++k) {
+                const double* pr = A.src_prof + 4 * k;
+                const double dtt = th - pr[0];
+                const double gt = pr[2] * exp(-dtt * dtt / (2.0 * pr[1] * pr[1]));
+                const double* en = A.src_entries + int64_t(k) * A.entries_per * 5;
+                for (int q = tid; q < A.entries_per; q += nthr)
+                    if (int(en[5 * q]) == c)
+                        buf[(int(en[5 * q + 1]) * ny + int(en[5 * q + 2])) * pitch + int(en[5 * q + 3])] -=
+                            gt * en[5 * q + 4];
+                __syncthreads();
+            }
+#pragma unroll 1
+            for (int a = 2; a >= 0; --a) {
+                sep_pass<P, LMAX, OP_SOLVE>(buf, a, od, pitch, gram, 1.0, fac + A.fac_off[pair_lu(1, c, a)], tid,
+                                            nthr);
+                __syncthreads();
+            }
+            for (int i = tid; i < cnt; i += nthr) {
+                const int x = i % nx, q = i / nx;
+                e[A.e_off[c] + i] += A.dt * buf[q * pitch + x];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+// LDS bytes the separable kernel needs: the largest component tensor of the
+// e/d and h/b grids with odd row pitch.
+size_t sep_lds_bytes(const int edims[3][3], const int hdims[3][3]) {
+    size_t m = 0;
+    for (int c = 0; c < 3; ++c) {
+        const size_t se = size_t(edims[c][0]) * edims[c][1] * (edims[c][2] | 1);
+        const size_t sh = size_t(hdims[c][0]) * hdims[c][1] * (hdims[c][2] | 1);
+        m = se > m ? se : m;
+        m = sh > m ? sh : m;
+    }
+    return m * sizeof(double);
+}
+
+int sep_line_max(int n_max) { return n_max <= 16 ? 16 : (n_max <= SEP_LINE_MAX ? SEP_LINE_MAX : 0); }
+
+namespace {
+template <int PP, int LL>
+hipError_t sep_raise_lds(size_t shm) {
+    static size_t done = 0;  // per instantiation: the limit already granted
+    if (done >= shm) return hipSuccess;
+    const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(sep_kernel<PP, LL>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+    if (err == hipSuccess) done = shm;
+    return err;
+}
+}  // namespace
+
+#define SEP_DISPATCH(CALL)                                                                       \
+    if (p == 2 && lmax == 16) CALL(2, 16)                                                        \
+    if (p == 3 && lmax == 16) CALL(3, 16)                                                        \
+    if (p == 4 && lmax == 16) CALL(4, 16)                                                        \
+    if (p == 2 && lmax == SEP_LINE_MAX) CALL(2, SEP_LINE_MAX)                                    \
+    if (p == 3 && lmax == SEP_LINE_MAX) CALL(3, SEP_LINE_MAX)                                    \
+    if (p == 4 && lmax == SEP_LINE_MAX) CALL(4, SEP_LINE_MAX)                                    \
+    return hipErrorInvalidValue;
+
+hipError_t sep_prepare(int p, int lmax, size_t shm) {
+#define PREP(PP, LL) return sep_raise_lds<PP, LL>(shm);
+    SEP_DISPATCH(PREP)
+#undef PREP
+}
+
+hipError_t launch_sep(int p, int lmax, double* E, double* H, const double* gram, const double* fac,
+                      const SepArgs& a, int batch, int threads, hipStream_t s) {
+    const size_t shm = sep_lds_bytes(a.edims, a.hdims);
+#define LAUNCH(PP, LL)                                                                                    \
+    {                                                                                                     \
+        const hipError_t err = sep_raise_lds<PP, LL>(shm);                                                \
+        if (err != hipSuccess) return err;                                                                \
+        hipLaunchKernelGGL((sep_kernel<PP, LL>), dim3(batch), dim3(threads), shm, s, E, H, gram, fac, a); \
+        return hipGetLastError();                                                                         \
+    }
+    SEP_DISPATCH(LAUNCH)
+#undef LAUNCH
+}
+
+}  // namespace kmx
