@@ -81,6 +81,15 @@ typedef struct {
     const double* dF_qp;
 } kmx_map;
 
+/* KMX_FP64: every operation in FP64.
+ * KMX_MIXED: the pairing solves x = K^{-1} y of the time step (eqs.
+ * (4.4)-(4.5)) use dense inverses of the 1D factors, rounded to FP32 and
+ * applied as mode-n products on the matrix cores with FP32 accumulation; the
+ * result is corrected by iterative refinement x += K^{-1}_32 (y - K x) whose
+ * residual uses the FP64 banded factors (kmx_set_refinement sets the number of
+ * corrections, default 2).  Hodge applies, curls, updates, the 1D
+ * factorisations and the energy sums stay FP64.  Mixed spaces always run the
+ * tiled plan. */
 typedef enum { KMX_FP64 = 0, KMX_MIXED = 1 } kmx_precision;
 
 /* OR into the `precision` argument of kmx_create_space to stream the metric
@@ -181,6 +190,9 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
  * workgroup size (64..768, multiple of 64).  Forcing KMX_PLAN_SEPARABLE on a
  * call it cannot serve fails with KMX_E_STATE.  Both plans compute the same
  * operators; results differ by rounding only. */
+/* Number of FP64-residual corrections of a mixed-precision solve (0..8). */
+kmx_status kmx_set_refinement(kmx_space* sp, int steps);
+
 #define KMX_PLAN_AUTO (-1)
 #define KMX_PLAN_TILED 0
 #define KMX_PLAN_SEPARABLE 1
@@ -291,8 +303,9 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
  *   5 energy reductions
  *   6 patch gather (sum of the overlapping tile outputs of a mass apply)
  *   7 separable persistent kernel (one launch for all steps of a call)
+ *   8 FP32 dense mode products of the mixed-precision solves
  * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
-#define KMX_PROFILE_KINDS 8
+#define KMX_PROFILE_KINDS 9
 kmx_status kmx_profile_begin(kmx_space* sp, int capacity);
 kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches);
 

@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
 TRACK_DB = 1
 STORED_METRIC = 16
+FP64, MIXED = 0, 1
 PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE = -1, 0, 1
 TUNE_CANDIDATES = 6
 TUNE_LABELS = ("tiled", "separable/256", "separable/384", "separable/512", "separable/640", "separable/768")
@@ -33,10 +34,12 @@ EXPORTS = (
     "kmx_init_stagger", "kmx_step", "kmx_energy", "kmx_op_curl", "kmx_op_mass", "kmx_op_solve",
     "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_create_probes", "kmx_destroy_probes",
     "kmx_probe_eval", "kmx_probe_forward", "kmx_adjoint", "kmx_set_plan", "kmx_get_plan", "kmx_tune",
+    "kmx_set_refinement",
     "kmx_graph_create", "kmx_graph_launch",
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
 )
-PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable")
+PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
+                 "mode_fp32")
 
 _STATUS = {0: "KMX_OK", 1: "KMX_E_ARG", 2: "KMX_E_GEOMETRY", 3: "KMX_E_MATERIAL", 4: "KMX_E_DEVICE",
            5: "KMX_E_OOM", 6: "KMX_E_UNSTABLE", 7: "KMX_E_STATE"}
@@ -94,6 +97,7 @@ def load_library():
         "kmx_probe_forward": ([vp, vp, vp, d, i, vp, vp], i),
         "kmx_adjoint": ([vp, vp, vp, vp, d, i, i, ctypes.POINTER(d), vp, vp], i),
         "kmx_set_plan": ([vp, i, i], i),
+        "kmx_set_refinement": ([vp, i], i),
         "kmx_get_plan": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
         "kmx_tune": ([vp, i, i, vp, d, vp, vp], i),
         "kmx_graph_create": ([vp, vp, vp, vp, d, i, i, i, vp, ctypes.POINTER(vp)], i),
@@ -323,6 +327,10 @@ class Space:
         _check(load_library().kmx_op_solve(self._h, w, int(bool(transpose)), _dptr(y, n, "y"), _dptr(x, n, "x"),
                                            _stream()))
 
+    def set_refinement(self, steps: int):
+        """Number of FP64-residual corrections of mixed-precision solves."""
+        _check(load_library().kmx_set_refinement(self._h, int(steps)))
+
     # ---- execution plans --------------------------------------------------
     def set_plan(self, kind: int, threads: int = 768):
         _check(load_library().kmx_set_plan(self._h, int(kind), int(threads)))
@@ -377,8 +385,8 @@ class Space:
 
     def profile_end(self) -> dict:
         """{kind: (total_ms, launches)} for the launches since profile_begin."""
-        ms = np.zeros(8)
-        cnt = np.zeros(8, dtype=np.int32)
+        ms = np.zeros(len(PROFILE_KINDS))
+        cnt = np.zeros(len(PROFILE_KINDS), dtype=np.int32)
         _check(load_library().kmx_profile_end(self._h, ctypes.c_void_p(ms.ctypes.data),
                                               ctypes.c_void_p(cnt.ctypes.data)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_KINDS)}

@@ -60,7 +60,8 @@ void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
 }
 
 // Kernel kinds reported by kmx_profile_end.
-enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6, PK_SEP = 7 };
+enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6, PK_SEP = 7,
+       PK_MODE = 8 };
 
 struct ProfScope {  // brackets one launch with events when profiling is on
     kmx_space* sp;
@@ -267,6 +268,39 @@ kmx_status upload_materials(kmx_space* sp) {
     return KMX_OK;
 }
 
+// Inverse of a dense n x n matrix (row-major) by Gauss-Jordan elimination with
+// partial pivoting, FP64.
+std::vector<double> dense_inverse(const std::vector<double>& A, int n) {
+    std::vector<double> a(A), inv(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[size_t(i) * n + i] = 1.0;
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::abs(a[size_t(i) * n + k]) > std::abs(a[size_t(piv) * n + k])) piv = i;
+        if (a[size_t(piv) * n + k] == 0.0) throw std::runtime_error("singular pairing factor");
+        if (piv != k)
+            for (int j = 0; j < n; ++j) {
+                std::swap(a[size_t(k) * n + j], a[size_t(piv) * n + j]);
+                std::swap(inv[size_t(k) * n + j], inv[size_t(piv) * n + j]);
+            }
+        const double d = 1.0 / a[size_t(k) * n + k];
+        for (int j = 0; j < n; ++j) {
+            a[size_t(k) * n + j] *= d;
+            inv[size_t(k) * n + j] *= d;
+        }
+        for (int i = 0; i < n; ++i) {
+            if (i == k) continue;
+            const double f = a[size_t(i) * n + k];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                a[size_t(i) * n + j] -= f * a[size_t(k) * n + j];
+                inv[size_t(i) * n + j] -= f * inv[size_t(k) * n + j];
+            }
+        }
+    }
+    return inv;
+}
+
 // whether eps and mu are the same in every element (a separable space needs both)
 void note_uniform(kmx_space* sp) {
     sp->uniform_eps = sp->uniform_mu = true;
@@ -313,7 +347,7 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
     if (max_batch < 1) return fail(KMX_E_ARG, "max_batch must be >= 1");
     const int prec = precision & 0xF;
     const bool force_stored = (precision & KMX_STORED_METRIC) != 0;
-    if (prec != KMX_FP64) return fail(KMX_E_ARG, "only KMX_FP64 is available in this build");
+    if (prec != KMX_FP64 && prec != KMX_MIXED) return fail(KMX_E_ARG, "precision must be KMX_FP64 or KMX_MIXED");
     if (precision & ~(0xF | KMX_STORED_METRIC)) return fail(KMX_E_ARG, "unknown precision flag");
     if (map && (map->kind < 0 || map->kind > 2)) return fail(KMX_E_ARG, "unknown map kind");
     if (map && map->kind == 2 && !map->dF_qp) return fail(KMX_E_ARG, "map kind 2 needs dF_qp");
@@ -407,6 +441,35 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             const int lmax = sep_line_max(std::max(sp->n0, sp->n1));
             if (lmax > 0 && shm <= size_t(sp->max_lds)) HIP_TRY(sep_prepare(p, lmax, shm));
         }
+        if (prec == KMX_MIXED) {
+            if (std::max(sp->n0, sp->n1) > mode_line_max()) {
+                kmx_destroy_space(sp);
+                return fail(KMX_E_ARG, "mixed precision supports lines of at most 80 entries");
+            }
+            // dense inverses of G^, M^, G^T, M^T in FP64, rounded to FP32
+            std::vector<float> inv;
+            const std::vector<double>* mats[2] = {&sp->tb.G, &sp->tb.M};
+            for (int k = 0; k < 4; ++k) {
+                const int n = (k == F_G || k == F_GT) ? sp->n0 : sp->n1;
+                const std::vector<double>& A = *mats[(k == F_G || k == F_GT) ? 0 : 1];
+                const std::vector<double> Ai = dense_inverse(A, n);
+                sp->inv32_off[k] = int64_t(inv.size());
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j)
+                        inv.push_back(float((k == F_GT || k == F_MT) ? Ai[size_t(j) * n + i] : Ai[size_t(i) * n + j]));
+            }
+            const int64_t nf = std::max(sp->n_e, sp->n_h) * int64_t(max_batch);
+            if (hipMalloc(&sp->d_inv32, inv.size() * sizeof(float)) != hipSuccess ||
+                hipMalloc(&sp->d_mx, nf * sizeof(double)) != hipSuccess ||
+                hipMalloc(&sp->d_mr, nf * sizeof(double)) != hipSuccess ||
+                hipMalloc(&sp->d_my, nf * sizeof(double)) != hipSuccess ||
+                hipMalloc(&sp->d_m32a, nf * sizeof(float)) != hipSuccess ||
+                hipMalloc(&sp->d_m32b, nf * sizeof(float)) != hipSuccess) {
+                kmx_destroy_space(sp);
+                return fail(KMX_E_OOM, "device allocation failed (mixed precision)");
+            }
+            HIP_TRY(hipMemcpy(sp->d_inv32, inv.data(), inv.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
         const size_t npad3 = size_t(sp->npad) * sp->npad * sp->npad;
         if (hipMalloc(&sp->d_inv_eps, npad3 * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_inv_mu, npad3 * sizeof(double)) != hipSuccess) {
@@ -481,6 +544,9 @@ void kmx_destroy_space(kmx_space* sp) {
     double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_axis_tab, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
                       sp->d_gram, sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
     for (double* b : bufs)
+        if (b) (void)hipFree(b);
+    void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b};
+    for (void* b : more)
         if (b) (void)hipFree(b);
     delete sp;
 }
@@ -989,11 +1055,56 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
 
 // The leapfrog loop.  With t_dev the source time of step n is *t_dev +
 // (n + 1/2) dt (graph replay), otherwise t_start + (n + 1/2) dt.
+// x = K^{-1} y (or K^{-T} y) in mixed precision: three FP32 mode products with
+// the dense inverse factors, then `refine_steps` corrections with the FP64
+// banded residual; out = (accumulate ? out : 0) + alpha * x.  y: FP64 field of
+// the K layout with stride nfield (left unchanged); out may not alias y.
+void mixed_solve(kmx_space* sp, int which_K1, int transpose, const double* y, double* out, int64_t out_stride,
+                 double alpha, int accumulate, int batch, hipStream_t s) {
+    const int64_t nf = std::max(sp->n_e, sp->n_h);
+    const int layout = which_K1 ? SP_D : SP_B;
+    ModeArgs m{};
+    space_dims(sp, layout, m.dims, m.comp_off);
+    m.in_stride = m.out_stride = nf;
+    m.A = sp->d_inv32;
+    m.alpha = 1.0;
+    auto apply3 = [&](const double* in, double* dst, int kind) {
+        ProfScope ps(sp, s, PK_MODE);
+        for (int ax = 0; ax < 3; ++ax) {
+            for (int c = 0; c < 3; ++c) m.A_off[c] = sp->inv32_off[pair_fac(which_K1, transpose, c, ax)];
+            m.axis = ax;
+            m.in = ax == 0 ? static_cast<const void*>(in) : (ax == 1 ? sp->d_m32a : sp->d_m32b);
+            m.in_f64 = ax == 0;
+            m.out = ax == 0 ? static_cast<void*>(sp->d_m32a) : (ax == 1 ? static_cast<void*>(sp->d_m32b) : dst);
+            m.out_kind = ax < 2 ? 0 : kind;
+            launch_mode(m, batch, s);
+        }
+    };
+    apply3(y, sp->d_mx, 1);
+    for (int it = 0; it < sp->refine_steps; ++it) {
+        (void)hipMemcpy2DAsync(sp->d_mr, nf * sizeof(double), y, nf * sizeof(double),
+                               size_t(which_K1 ? sp->n_e : sp->n_h) * sizeof(double), batch,
+                               hipMemcpyDeviceToDevice, s);
+        run_solve(sp, which_K1, transpose, 0, layout, sp->d_mx, nf, sp->d_mr, nf, -1.0, 1, batch, nullptr, 0.0, 2, s);
+        apply3(sp->d_mr, sp->d_mx, 2);
+    }
+    const int64_t n = which_K1 ? sp->n_e : sp->n_h;
+    if (accumulate) {
+        launch_strided_axpy(sp->d_mx, nf, out, out_stride, n, alpha, batch, s);
+    } else {
+        for (int b = 0; b < batch; ++b)
+            (void)hipMemcpyAsync(out + b * out_stride, sp->d_mx + b * nf, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                 s);
+        if (alpha != 1.0) launch_strided_axpy(sp->d_mx, nf, out, out_stride, n, alpha - 1.0, batch, s);
+    }
+}
+
 // Whether the separable persistent kernel can run a step call: identity map,
 // eps and mu the same in every element, no per-step energy output, lines that
 // fit the kernel's registers and component tensors that fit one workgroup's LDS.
 bool sep_eligible(const kmx_space* sp, const double* energy_dev) {
     if (sp->map.kind != 0 || !sp->uniform_eps || !sp->uniform_mu || energy_dev) return false;
+    if (sp->precision == KMX_MIXED) return false;
     if (sep_line_max(std::max(sp->n0, sp->n1)) == 0) return false;
     int ed[3][3], hd[3][3];
     int64_t o[3];
@@ -1066,14 +1177,26 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
         return KMX_OK;
     }
     const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
+    const bool mixed = sp->precision == KMX_MIXED;
+    const int64_t nf = std::max(sp->n_e, sp->n_h);
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
         // M D^1 e (and b -= dt D^1 e), then h -= dt K~1^{-1} (.)
         run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -dt);
-        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -dt, 1, batch, nullptr, 0.0, 1, s);
+        if (mixed) {
+            run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+            mixed_solve(sp, 0, 0, sp->d_my, H, hs, -dt, 1, batch, s);
+        } else {
+            run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -dt, 1, batch, nullptr, 0.0, 1, s);
+        }
         // M~ D~^1 h (and d += dt D~^1 h), then e += dt K1^{-1} (. - s)
         run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, dt);
-        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, dt, 1, batch, J, t_half, 1, s, nullptr, t_dev);
+        if (mixed) {
+            run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev);
+            mixed_solve(sp, 1, 0, sp->d_my, E, es, dt, 1, batch, s);
+        } else {
+            run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, dt, 1, batch, J, t_half, 1, s, nullptr, t_dev);
+        }
         if (energy_dev) run_energy(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, 1, s);
     }
     if (t_dev) launch_advance_time(const_cast<double*>(t_dev), nsteps * dt, s);
@@ -1098,6 +1221,12 @@ kmx_status kmx_get_time(kmx_space* sp, double* t, void* stream) {
     if (!sp || !t) return fail(KMX_E_ARG, "NULL argument");
     HIP_TRY(hipMemcpyAsync(t, sp->d_time, sizeof(double), hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)));
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return KMX_OK;
+}
+
+kmx_status kmx_set_refinement(kmx_space* sp, int steps) {
+    if (!sp || steps < 0 || steps > 8) return fail(KMX_E_ARG, "refinement steps must be 0..8");
+    sp->refine_steps = steps;
     return KMX_OK;
 }
 
@@ -1257,8 +1386,11 @@ kmx_status kmx_op_mass(kmx_space* sp, int which, int curl, const double* x, doub
 
 kmx_status kmx_op_solve(kmx_space* sp, int which, int transpose, const double* y, double* x, void* stream) {
     if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
-    run_solve(sp, which, transpose != 0, 0, which ? SP_D : SP_B, y, 0, x, 0, 1.0, 0, 1, nullptr, 0.0, 1,
-              static_cast<hipStream_t>(stream));
+    if (sp->precision == KMX_MIXED)
+        mixed_solve(sp, which, transpose != 0, y, x, 0, 1.0, 0, 1, static_cast<hipStream_t>(stream));
+    else
+        run_solve(sp, which, transpose != 0, 0, which ? SP_D : SP_B, y, 0, x, 0, 1.0, 0, 1, nullptr, 0.0, 1,
+                  static_cast<hipStream_t>(stream));
     CHECK_LAUNCH();
     return KMX_OK;
 }

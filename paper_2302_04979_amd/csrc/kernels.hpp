@@ -151,6 +151,27 @@ hipError_t sep_prepare(int p, int lmax, size_t shm);   // grant the kernel its L
 hipError_t launch_sep(int p, int lmax, double* E, double* H, const double* gram, const double* fac,
                       const SepArgs& a, int batch, int threads, hipStream_t s);
 
+// Mode-n product of every component of a field with a dense FP32 factor on
+// the matrix cores (mixed-precision solves).
+struct ModeArgs {
+    const void* in;             // FP64 (in_f64) or FP32 field, batch member 0
+    int in_f64;
+    int64_t in_stride;
+    void* out;
+    int out_kind;               // 0 FP32 store, 1 FP64 store, 2 FP64 out += alpha * result
+    int64_t out_stride;
+    double alpha;
+    int64_t comp_off[3];        // same layout for in and out
+    int dims[3][3];             // [c][z, y, x]
+    const float* A;             // dense n x n factors, row-major
+    int64_t A_off[3];           // factor of each component along `axis`
+    int axis;
+};
+int mode_line_max();
+void launch_mode(const ModeArgs& a, int batch, hipStream_t s);
+void launch_strided_axpy(const double* x, int64_t xs, double* y, int64_t ys, int64_t n, double alpha, int batch,
+                         hipStream_t s);
+
 void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s);
 void launch_curlT(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
 void launch_csr(const int* rowptr, const int* col, const double* val, const double* x, double* out,

@@ -138,6 +138,13 @@ struct kmx_space {
     int max_lds = 0;                   // device limit of LDS bytes per workgroup
     int plan_kind = -1;                // -1 automatic, KMX_PLAN_TILED, KMX_PLAN_SEPARABLE
     int plan_threads = 768;            // workgroup size of the separable kernel
+    // mixed-precision solves (precision & KMX_MIXED): dense FP32 inverses of
+    // the four 1D pairing factors and working fields
+    float* d_inv32 = nullptr;          // [G^-1 | M^-1 | G^-T | M^-T], row-major
+    int64_t inv32_off[4] = {0, 0, 0, 0};
+    double *d_mx = nullptr, *d_mr = nullptr, *d_my = nullptr;   // FP64 [max_batch][nfield]
+    float *d_m32a = nullptr, *d_m32b = nullptr;                  // FP32 [max_batch][nfield]
+    int refine_steps = 2;              // refinement corrections after the first FP32 solve
     hipStream_t capture_stream = nullptr;
     // optional per-kernel timing with HIP events (kmx_profile_begin/end)
     bool prof_on = false;

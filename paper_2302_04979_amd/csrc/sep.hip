@@ -20,20 +20,79 @@ namespace kmx {
 
 namespace {
 
-// (d v)[k] = v[k] - v[k-1] (primal, zero outside) or v[k+1] - v[k] (dual) of
-// component array u (dims [z, y, x]) along `axis`, at the output position.
-__device__ inline double sep_diff(const double* u, const int d[3], int primal, int axis, int z, int y, int x) {
-    const int sx = 1, sy = d[2], sz = d[1] * d[2];
-    const int idx = z * sz + y * sy + x * sx;
-    const int st = axis == 0 ? sx : (axis == 1 ? sy : sz);
+// The two values whose difference is (d v)[k] = v[k] - v[k-1] (primal, zero
+// outside) or v[k+1] - v[k] (dual) of component array u (dims [z, y, x])
+// along `axis`, at the output position (z, y, x).
+__device__ inline void diff_pair(const double* u, const int d[3], int primal, int axis, int z, int y, int x,
+                                 double& hi, double& lo) {
+    const int sy = d[2], sz = d[1] * d[2];
+    const int idx = z * sz + y * sy + x;
+    const int st = axis == 0 ? 1 : (axis == 1 ? sy : sz);
     const int k = axis == 0 ? x : (axis == 1 ? y : z);
-    const int n = d[2 - axis];
     if (primal) {
-        const double a = k < n ? u[idx] : 0.0;
-        const double b = k >= 1 ? u[idx - st] : 0.0;
-        return a - b;
+        hi = k < d[2 - axis] ? u[idx] : 0.0;
+        lo = k >= 1 ? u[idx - st] : 0.0;
+    } else {
+        hi = u[idx + st];
+        lo = u[idx];
     }
-    return u[idx + st] - u[idx];
+}
+
+// Curl of component c of the 1-form `src` (primal or dual) into the LDS
+// tensor of the 2-form grid od, with the optional tracking update
+// trk += talpha * curl.  U elements per thread are loaded before any is used,
+// so that each thread keeps several global loads in flight.
+template <int U>
+__device__ inline void curl_to_lds(double* buf, const double* src, const int64_t soff[3], const int sdims[3][3],
+                                   int primal, int c, const int od[3], double* trk, double talpha, int tid,
+                                   int nthr) {
+    const int ny = od[1], nx = od[2], pitch = nx | 1, cnt = od[0] * ny * nx;
+    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+    for (int i0 = tid; i0 < cnt; i0 += U * nthr) {
+        double p0[U], p1[U], q0[U], q1[U], tv[U];
+        int li[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nthr;
+            li[u] = -1;
+            p0[u] = p1[u] = q0[u] = q1[u] = tv[u] = 0.0;
+            if (i < cnt) {
+                const int x = i % nx, q = i / nx, y = q % ny, z = q / ny;
+                li[u] = q * pitch + x;
+                diff_pair(src + soff[a2], sdims[a2], primal, a1, z, y, x, p0[u], p1[u]);
+                diff_pair(src + soff[a1], sdims[a1], primal, a2, z, y, x, q0[u], q1[u]);
+                if (trk) tv[u] = trk[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (li[u] >= 0) {
+                const double v = (p0[u] - p1[u]) - (q0[u] - q1[u]);
+                buf[li[u]] = v;
+                if (trk) trk[i0 + u * nthr] = tv[u] + talpha * v;
+            }
+        }
+    }
+}
+
+// dst += alpha * (LDS tensor), U elements per thread in flight.
+template <int U>
+__device__ inline void update_from_lds(double* dst, const double* buf, const int od[3], double alpha, int tid,
+                                       int nthr) {
+    const int nx = od[2], pitch = nx | 1, cnt = od[0] * od[1] * nx;
+    for (int i0 = tid; i0 < cnt; i0 += U * nthr) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nthr;
+            v[u] = i < cnt ? dst[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nthr;
+            if (i < cnt) dst[i] = v[u] + alpha * buf[(i / nx) * pitch + (i % nx)];
+        }
+    }
 }
 
 // y = scale * (band x) in registers; band rows hold 2P+1 entries of half
@@ -141,15 +200,9 @@ __global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
             const int* od = A.hdims[c];
-            const int ny = od[1], nx = od[2], pitch = nx | 1, cnt = od[0] * ny * nx;
-            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            for (int i = tid; i < cnt; i += nthr) {
-                const int x = i % nx, q = i / nx, y = q % ny, z = q / ny;
-                const double u = sep_diff(e + A.e_off[a2], A.edims[a2], 1, a1, z, y, x) -
-                                 sep_diff(e + A.e_off[a1], A.edims[a1], 1, a2, z, y, x);
-                buf[(z * ny + y) * pitch + x] = u;
-                if (A.track) h[A.n_h + A.h_off[c] + i] -= A.dt * u;
-            }
+            const int pitch = od[2] | 1;
+            curl_to_lds<4>(buf, e, A.e_off, A.edims, 1, c, od, A.track ? h + A.n_h + A.h_off[c] : nullptr, -A.dt,
+                           tid, nthr);
             __syncthreads();
 #pragma unroll 1
             for (int a = 0; a < 3; ++a) {
@@ -157,11 +210,7 @@ __global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double
                                                       1.0, fac + A.fac_off[pair_lu(0, c, a)], tid, nthr);
                 __syncthreads();
             }
-            const double alpha = -A.dt * A.inv_mu;
-            for (int i = tid; i < cnt; i += nthr) {
-                const int x = i % nx, q = i / nx;
-                h[A.h_off[c] + i] += alpha * buf[q * pitch + x];
-            }
+            update_from_lds<8>(h + A.h_off[c], buf, od, -A.dt * A.inv_mu, tid, nthr);
             __syncthreads();
         }
         // ---- e^{n+1} = e^n + dt K1^{-1} (M~ D~^1 h^{n+1/2} - s(t_{n+1/2}))   [d += dt D~^1 h] ----
@@ -169,15 +218,9 @@ __global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
             const int* od = A.edims[c];
-            const int ny = od[1], nx = od[2], pitch = nx | 1, cnt = od[0] * ny * nx;
-            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            for (int i = tid; i < cnt; i += nthr) {
-                const int x = i % nx, q = i / nx, y = q % ny, z = q / ny;
-                const double v = sep_diff(h + A.h_off[a2], A.hdims[a2], 0, a1, z, y, x) -
-                                 sep_diff(h + A.h_off[a1], A.hdims[a1], 0, a2, z, y, x);
-                buf[(z * ny + y) * pitch + x] = v;
-                if (A.track) e[A.n_e + A.e_off[c] + i] += A.dt * v;
-            }
+            const int ny = od[1], pitch = od[2] | 1;
+            curl_to_lds<4>(buf, h, A.h_off, A.hdims, 0, c, od, A.track ? e + A.n_e + A.e_off[c] : nullptr, A.dt,
+                           tid, nthr);
             __syncthreads();
 #pragma unroll 1
             for (int a = 0; a < 3; ++a) {
@@ -203,10 +246,7 @@ __global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double
                                             nthr);
                 __syncthreads();
             }
-            for (int i = tid; i < cnt; i += nthr) {
-                const int x = i % nx, q = i / nx;
-                e[A.e_off[c] + i] += A.dt * buf[q * pitch + x];
-            }
+            update_from_lds<8>(e + A.e_off[c], buf, od, A.dt, tid, nthr);
             __syncthreads();
         }
     }
