@@ -111,6 +111,92 @@ def adjoint_timing(K, W, torch):
     return (time.perf_counter() - t0) / reps
 
 
+def _state(K, W, torch, G, N):
+    """e^0, d^0 from the 10 seeded cavity modes, h = b = 0, staggered to -dt/2."""
+    xq = G.quad_points()
+    Eq = W.eval_modes(W.cavity_modes(0), xq)
+    del xq
+    E = torch.zeros(2 * G.n_e, dtype=torch.float64, device="cuda")
+    H = torch.zeros(2 * G.n_h, dtype=torch.float64, device="cuda")
+    G.project_E(Eq, E[:G.n_e])
+    G.project_D(Eq, E[G.n_e:], tol=1e-13)
+    return E, H
+
+
+def _rel(a, b):
+    return float(torch_norm(a - b) / torch_norm(b))
+
+
+def torch_norm(x):
+    return x.double().norm()
+
+
+def mixed_vs_fp64(K, W, torch, p, N, steps, eps, dt=None, E0=None, H0=None, G64=None):
+    """The same run (deformed cube, eps, tracking + energy) with FP64 and with
+    mixed-precision solves from the same state: ms per step of each and the
+    relative difference of every field and of the energy after `steps`."""
+    dev = "cuda"
+    if G64 is None:
+        G64 = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+        G64.set_materials(eps=eps)
+    Gm = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE, precision=K.MIXED)
+    Gm.set_materials(eps=eps)
+    if E0 is None:
+        E0, H0 = _state(K, W, torch, G64, N)
+        dt = 0.5 * G64.cfl(max_iter=300, tol=1e-6)
+        G64.init_stagger(E0, H0, dt, flags=K.TRACK_DB)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, G in (("fp64", G64), ("mixed", Gm)):
+        E, H = E0.clone(), H0.clone()
+        en = torch.zeros(steps, dtype=torch.float64, device=dev)
+        G.step(E, H, dt, nsteps=2, flags=K.TRACK_DB, energy=en)  # warm-up on a scratch copy
+        E, H = E0.clone(), H0.clone()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        G.step(E, H, dt, nsteps=steps, flags=K.TRACK_DB, energy=en)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = (ev0.elapsed_time(ev1) / steps, E, H, en)
+    ne, nh = G64.n_e, G64.n_h
+    E64, H64, en64 = res["fp64"][1], res["fp64"][2], res["fp64"][3]
+    Em, Hm, enm = res["mixed"][1], res["mixed"][2], res["mixed"][3]
+    dofs = ne + nh
+    return {"workload": f"p={p}, {N}^3 deformed cube (a=0.08), eps~U[1,4], 10 cavity modes, dt=0.5 CFL, "
+                        f"b/d tracking + energy, {steps} steps",
+            "ms_per_step_fp64": res["fp64"][0], "ms_per_step_mixed": res["mixed"][0],
+            "value_fp64": dofs / (res["fp64"][0] * 1e-3), "value_mixed": dofs / (res["mixed"][0] * 1e-3),
+            "speedup_mixed_over_fp64": res["fp64"][0] / res["mixed"][0],
+            "refinement_corrections": 2,
+            "rel_err_vs_fp64": {"e": _rel(Em[:ne], E64[:ne]), "d": _rel(Em[ne:], E64[ne:]),
+                                "h": _rel(Hm[:nh], H64[:nh]), "b": _rel(Hm[nh:], H64[nh:]),
+                                "energy": float((enm[-1] - en64[-1]).abs() / en64[-1].abs())},
+            "energy_rel_drift_mixed": float(((enm / enm[0]) - 1).abs().max())}
+
+
+def profile_run(K, W, torch, p, N, steps):
+    """A short run for the profiler: a device copy of known size (512 MiB read,
+    512 MiB written: the reference for the HBM byte counters), then `steps`
+    steps of the metric workload's kernels from a seeded random state."""
+    import numpy as np
+    n = 64 * 1024 * 1024  # doubles: 512 MiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    G = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+    G.set_materials(eps=W.eps_elements(N, 0))
+    E = torch.tensor(W.random_vector(2 * G.n_e, 0, 41), dtype=torch.float64, device="cuda")
+    H = torch.tensor(W.random_vector(2 * G.n_h, 0, 42), dtype=torch.float64, device="cuda")
+    en = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    G.step(E, H, 1e-3, nsteps=steps, flags=K.TRACK_DB, energy=en)
+    torch.cuda.synchronize()
+    return {"profile_run": {"copy_bytes_each_way": n * 8, "copies": 3, "steps": steps, "p": p, "N": N}}
+
+
 def batched_timing(K, W, torch, steps=400):
     """Batched form: p=3, 24^3 elements, identity map, eps = mu = 1, zero
     initial fields, 256 members each driven by its own Gaussian point dipole
@@ -170,10 +256,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--n", type=int, default=64)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--only-mixed", action="store_true")
+    ap.add_argument("--profile-run", action="store_true")
     ap.add_argument("--only-batched", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -190,8 +279,15 @@ def main():
 
     p, N = args.p, args.n
     torch.cuda.set_device(0)
+    if args.profile_run:
+        print(json.dumps(profile_run(K, W, torch, p, N, 10)), flush=True)
+        return
     if args.only_batched:
         print(json.dumps({"batched": batched_timing(K, W, torch)}), flush=True)
+        return
+    if args.only_mixed:
+        print(json.dumps({"mixed": mixed_vs_fp64(K, W, torch, p, N, args.steps, W.eps_elements(N, 0)),
+                          "p4": mixed_vs_fp64(K, W, torch, 4, 64, 500, W.eps_elements(64, 0))}), flush=True)
         return
     log(f"set-up p={p} N={N}")
     G = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
@@ -218,6 +314,7 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
+    E_start, H_start = E.clone(), H.clone()
     # ---- timed region ----
     log(f"timing {args.steps} steps")
     t_start = args.warmup * dt
@@ -301,6 +398,14 @@ def main():
         log("batched form")
         batched = batched_timing(K, W, torch)
 
+    mixed = None
+    if not args.no_mixed:
+        log("mixed precision, metric workload")
+        mixed = mixed_vs_fp64(K, W, torch, p, N, args.steps, eps, dt, E_start, H_start, G)
+        del E_start, H_start
+        log("mixed precision, p=4 64^3, 500 steps")
+        mixed["p4_n64_500_steps"] = mixed_vs_fp64(K, W, torch, 4, 64, 500, W.eps_elements(64, 0))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
@@ -329,7 +434,7 @@ def main():
         "energy_rel_drift": drift,
         "kernels": breakdown,
         "stored_metric": stored,
-        "mixed": None,
+        "mixed": mixed,
         "adjoint_grad_s": adjoint_s,
         "batched": batched,
     }
