@@ -187,7 +187,7 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
  *                       e.g. p = 3, N <= 25).  No per-step energy output.
  * KMX_PLAN_AUTO (the default) takes the separable plan when it applies and
  * batch >= 32, the tiled plan otherwise.  `threads` is the separable kernel's
- * workgroup size (64..768, multiple of 64).  Forcing KMX_PLAN_SEPARABLE on a
+ * workgroup size (64..512, multiple of 64).  Forcing KMX_PLAN_SEPARABLE on a
  * call it cannot serve fails with KMX_E_STATE.  Both plans compute the same
  * operators; results differ by rounding only. */
 /* Number of FP64-residual corrections of a mixed-precision solve (0..8). */
@@ -202,7 +202,7 @@ kmx_status kmx_get_plan(const kmx_space* sp, int* kind, int* threads);
 /* Times the candidate plans on `batch` members (zero fields of its own, J
  * driving them if not NULL, time step dt) over probe_steps steps each after
  * one warm-up step, and keeps the fastest as the space's plan.  Candidates:
- * 0 tiled; 1..5 separable with 256, 384, 512, 640, 768 threads.  ms_out:
+ * 0 tiled; 1..5 separable with 256, 320, 384, 448, 512 threads.  ms_out:
  * NULL or host array of KMX_TUNE_CANDIDATES entries receiving the mean ms per
  * step (-1 where a candidate does not apply).  Allocates two fields of
  * working memory; synchronises. */

@@ -25,7 +25,7 @@ STORED_METRIC = 16
 FP64, MIXED = 0, 1
 PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE = -1, 0, 1
 TUNE_CANDIDATES = 6
-TUNE_LABELS = ("tiled", "separable/256", "separable/384", "separable/512", "separable/640", "separable/768")
+TUNE_LABELS = ("tiled", "separable/256", "separable/320", "separable/384", "separable/448", "separable/512")
 
 # every symbol declared in include/kronmaxwell.h
 EXPORTS = (
@@ -332,7 +332,7 @@ class Space:
         _check(load_library().kmx_set_refinement(self._h, int(steps)))
 
     # ---- execution plans --------------------------------------------------
-    def set_plan(self, kind: int, threads: int = 768):
+    def set_plan(self, kind: int, threads: int = 512):
         _check(load_library().kmx_set_plan(self._h, int(kind), int(threads)))
 
     def plan(self):

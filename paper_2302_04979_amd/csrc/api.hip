@@ -1234,7 +1234,8 @@ kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads) {
     if (!sp) return fail(KMX_E_ARG, "space is NULL");
     if (kind != KMX_PLAN_AUTO && kind != KMX_PLAN_TILED && kind != KMX_PLAN_SEPARABLE)
         return fail(KMX_E_ARG, "unknown plan kind");
-    if (threads < 64 || threads > 768 || threads % 64) return fail(KMX_E_ARG, "threads must be 64..768, a multiple of 64");
+    if (threads < 64 || threads > SEP_MAX_THREADS || threads % 64)
+        return fail(KMX_E_ARG, "threads must be 64..512, a multiple of 64");
     sp->plan_kind = kind;
     sp->plan_threads = threads;
     return KMX_OK;
@@ -1252,7 +1253,7 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     if (!sp || batch < 1 || batch > sp->max_batch || probe_steps < 1) return fail(KMX_E_ARG, "bad argument");
     if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 256, 384, 512, 640, 768};
+    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 256, 320, 384, 448, 512};
     const bool sep_ok = sep_eligible(sp, nullptr);
     double* E = nullptr;
     double* H = nullptr;

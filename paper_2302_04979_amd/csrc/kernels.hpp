@@ -128,6 +128,7 @@ struct PairGradArgs {           // per-element metric pairing of lam and D~^1 h
 // one workgroup per batch member runs all nsteps with the component tensors
 // in LDS.  Fields are passed as kernel arguments of their own.
 constexpr int SEP_LINE_MAX = 28;   // longest line (n0, n1) the kernel holds in registers
+constexpr int SEP_MAX_THREADS = 512;  // launch bound of the separable kernel
 struct SepArgs {
     int64_t e_stride, h_stride;    // distance between batch members (doubled with tracking)
     int64_t n_e, n_h;              // offset of d inside E and of b inside H

@@ -38,63 +38,6 @@ __device__ inline void diff_pair(const double* u, const int d[3], int primal, in
     }
 }
 
-// Curl of component c of the 1-form `src` (primal or dual) into the LDS
-// tensor of the 2-form grid od, with the optional tracking update
-// trk += talpha * curl.  U elements per thread are loaded before any is used,
-// so that each thread keeps several global loads in flight.
-template <int U>
-__device__ inline void curl_to_lds(double* buf, const double* src, const int64_t soff[3], const int sdims[3][3],
-                                   int primal, int c, const int od[3], double* trk, double talpha, int tid,
-                                   int nthr) {
-    const int ny = od[1], nx = od[2], pitch = nx | 1, cnt = od[0] * ny * nx;
-    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-    for (int i0 = tid; i0 < cnt; i0 += U * nthr) {
-        double p0[U], p1[U], q0[U], q1[U], tv[U];
-        int li[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nthr;
-            li[u] = -1;
-            p0[u] = p1[u] = q0[u] = q1[u] = tv[u] = 0.0;
-            if (i < cnt) {
-                const int x = i % nx, q = i / nx, y = q % ny, z = q / ny;
-                li[u] = q * pitch + x;
-                diff_pair(src + soff[a2], sdims[a2], primal, a1, z, y, x, p0[u], p1[u]);
-                diff_pair(src + soff[a1], sdims[a1], primal, a2, z, y, x, q0[u], q1[u]);
-                if (trk) tv[u] = trk[i];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (li[u] >= 0) {
-                const double v = (p0[u] - p1[u]) - (q0[u] - q1[u]);
-                buf[li[u]] = v;
-                if (trk) trk[i0 + u * nthr] = tv[u] + talpha * v;
-            }
-        }
-    }
-}
-
-// dst += alpha * (LDS tensor), U elements per thread in flight.
-template <int U>
-__device__ inline void update_from_lds(double* dst, const double* buf, const int od[3], double alpha, int tid,
-                                       int nthr) {
-    const int nx = od[2], pitch = nx | 1, cnt = od[0] * od[1] * nx;
-    for (int i0 = tid; i0 < cnt; i0 += U * nthr) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nthr;
-            v[u] = i < cnt ? dst[i] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nthr;
-            if (i < cnt) dst[i] = v[u] + alpha * buf[(i / nx) * pitch + (i % nx)];
-        }
-    }
-}
-
 // y = scale * (band x) in registers; band rows hold 2P+1 entries of half
 // width P (zeros outside the matrix); entries i >= n stay zero.
 template <int P, int LMAX>
@@ -149,35 +92,167 @@ __device__ inline void lu_regs(double (&r)[LMAX], int n, const double* __restric
 }
 
 enum { OP_GRAM = 1, OP_SOLVE = 2 };
+constexpr int CH = 4;  // entries per chunk of global loads (divides every LMAX)
 
-// One mode product over all lines of `axis` of the LDS tensor (dims [z, y, x],
-// row pitch `pitch`): Gram product (scaled), banded solve, or both.
+// Line view of the LDS tensor (dims [z, y, x], row pitch `pitch`): line l of
+// `axis` starts at base and steps by stride.
+__device__ inline void line_of(int axis, int l, const int d[3], int pitch, int& base, int& stride) {
+    const int ny = d[1], nx = d[2];
+    if (axis == 0) {          // l = z*ny + y
+        base = l * pitch;
+        stride = 1;
+    } else if (axis == 1) {   // l = z*nx + x
+        base = (l / nx) * ny * pitch + (l % nx);
+        stride = pitch;
+    } else {                  // l = y*nx + x
+        base = (l / nx) * pitch + (l % nx);
+        stride = ny * pitch;
+    }
+}
+
+template <int P, int LMAX>
+__device__ inline void line_ops(double (&r)[LMAX], int n, int ops, const double* __restrict__ band, double scale,
+                                const double* __restrict__ fac) {
+    if (ops & OP_GRAM) gram_regs<P, LMAX>(r, n, band, scale);
+    if (ops & OP_SOLVE) lu_regs<P, LMAX>(r, n, fac, fac + n * (P - 1), fac + 2 * n * (P - 1));
+}
+
+// One mode product over all lines of `axis`, LDS to LDS.
 template <int P, int LMAX, int OPS>
-__device__ inline void sep_pass(double* buf, int axis, const int d[3], int pitch, const double* __restrict__ band,
+__device__ inline void lds_pass(double* buf, int axis, const int d[3], int pitch, const double* __restrict__ band,
                                 double scale, const double* __restrict__ fac, int tid, int nthr) {
-    const int nz = d[0], ny = d[1], nx = d[2];
     const int n = d[2 - axis];
-    const int stride = axis == 0 ? 1 : (axis == 1 ? pitch : ny * pitch);
-    const int nlines = axis == 0 ? nz * ny : (axis == 1 ? nz * nx : ny * nx);
-    const double* L = fac;
-    const double* U = fac + n * (P - 1);
-    const double* dinv = fac + 2 * n * (P - 1);
-    // one line per thread: the launch gives at least as many threads as lines
-    // (a loop here would let the compiler hoist every row's coefficients)
-    const int l = tid;
-    if (l < nlines) {
-        int base;
-        if (axis == 0) base = l * pitch;                              // l = z*ny + y
-        else if (axis == 1) base = (l / nx) * ny * pitch + (l % nx);  // l = z*nx + x
-        else base = (l / nx) * pitch + (l % nx);                      // l = y*nx + x
+    const int nlines = d[0] * d[1] * d[2] / n;
+    for (int l = tid; l < nlines; l += nthr) {
+        int base, stride;
+        line_of(axis, l, d, pitch, base, stride);
         double r[LMAX];
 #pragma unroll
         for (int i = 0; i < LMAX; ++i) r[i] = i < n ? buf[base + i * stride] : 0.0;
-        if (OPS & OP_GRAM) gram_regs<P, LMAX>(r, n, band, scale);
-        if (OPS & OP_SOLVE) lu_regs<P, LMAX>(r, n, L, U, dinv);
+        line_ops<P, LMAX>(r, n, OPS, band, scale, fac);
 #pragma unroll
         for (int i = 0; i < LMAX; ++i)
             if (i < n) buf[base + i * stride] = r[i];
+    }
+}
+
+// First pass of a half step: the curl of the 1-form `src` along each z-line
+// of the 2-form component grid od, computed from global memory straight into
+// registers (lanes over x: coalesced), the optional tracking update
+// trk += talpha * curl, then the z-line operations, into LDS.
+template <int P, int LMAX>
+__device__ inline void curl_z_pass(double* buf, const double* src, const int64_t soff[3], const int sdims[3][3],
+                                   int primal, int c, const int od[3], int pitch, double* trk, double talpha,
+                                   int ops, const double* __restrict__ band, double scale,
+                                   const double* __restrict__ fac, int tid, int nthr) {
+    const int nz = od[0], ny = od[1], nx = od[2];
+    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+    for (int l = tid; l < ny * nx; l += nthr) {
+        const int y = l / nx, x = l % nx;
+        double r[LMAX];
+        // chunks of CH entries: their loads are issued together, and the
+        // scheduling barrier keeps the compiler from hoisting every chunk's
+        // loads at once (which would spill)
+#pragma unroll
+        for (int z0 = 0; z0 < LMAX; z0 += CH) {
+            double p0[CH], p1[CH], q0[CH], q1[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                p0[j] = p1[j] = q0[j] = q1[j] = 0.0;
+                if (z0 + j < nz) {
+                    diff_pair(src + soff[a2], sdims[a2], primal, a1, z0 + j, y, x, p0[j], p1[j]);
+                    diff_pair(src + soff[a1], sdims[a1], primal, a2, z0 + j, y, x, q0[j], q1[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) r[z0 + j] = (p0[j] - p1[j]) - (q0[j] - q1[j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (trk) {
+#pragma unroll
+            for (int z0 = 0; z0 < LMAX; z0 += CH) {
+                double t[CH];
+#pragma unroll
+                for (int j = 0; j < CH; ++j) t[j] = z0 + j < nz ? trk[((z0 + j) * ny + y) * nx + x] : 0.0;
+#pragma unroll
+                for (int j = 0; j < CH; ++j)
+                    if (z0 + j < nz) trk[((z0 + j) * ny + y) * nx + x] = t[j] + talpha * r[z0 + j];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        line_ops<P, LMAX>(r, nz, ops, band, scale, fac);
+#pragma unroll
+        for (int z = 0; z < LMAX; ++z)
+            if (z < nz) buf[(z * ny + y) * pitch + x] = r[z];
+    }
+}
+
+// Last pass of a half step: the line operations along `axis` (1 or 2: lanes
+// over x, coalesced) and dst += alpha * result straight from registers.
+template <int P, int LMAX>
+__device__ inline void final_pass(const double* buf, int axis, const int d[3], int pitch, double* dst, double alpha,
+                                  int ops, const double* __restrict__ band, double scale,
+                                  const double* __restrict__ fac, int tid, int nthr) {
+    const int ny = d[1], nx = d[2];
+    const int n = d[2 - axis];
+    const int nlines = d[0] * ny * nx / n;
+    const int gstride = axis == 1 ? nx : ny * nx;
+    for (int l = tid; l < nlines; l += nthr) {
+        int base, stride;
+        line_of(axis, l, d, pitch, base, stride);
+        const int gbase = axis == 1 ? (l / nx) * ny * nx + (l % nx) : l;
+        double r[LMAX];
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i) r[i] = i < n ? buf[base + i * stride] : 0.0;
+        line_ops<P, LMAX>(r, n, ops, band, scale, fac);
+#pragma unroll
+        for (int i0 = 0; i0 < LMAX; i0 += CH) {
+            double o[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) o[j] = i0 + j < n ? dst[gbase + (i0 + j) * gstride] : 0.0;
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (i0 + j < n) dst[gbase + (i0 + j) * gstride] = o[j] + alpha * r[i0 + j];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The y-pass of the e half step: Gram product along y, the tested point
+// sources of this line (entries with the line's z and x), solve along y.
+template <int P, int LMAX>
+__device__ inline void y_source_pass(double* buf, const int d[3], int pitch, const double* __restrict__ band,
+                                     const double* __restrict__ fac, int c, const SepArgs& A, int b, double th,
+                                     int tid, int nthr) {
+    const int ny = d[1], nx = d[2];
+    const int nlines = d[0] * nx;
+    const int k0 = A.n_src > 0 ? A.src_off[b] : 0, k1 = A.n_src > 0 ? A.src_off[b + 1] : 0;
+    for (int l = tid; l < nlines; l += nthr) {
+        int base, stride;
+        line_of(1, l, d, pitch, base, stride);
+        const int z = l / nx, x = l % nx;
+        double r[LMAX];
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i) r[i] = i < ny ? buf[base + i * stride] : 0.0;
+        gram_regs<P, LMAX>(r, ny, band, 1.0);
+        for (int k = k0; k < k1; ++k) {
+            const double* pr = A.src_prof + 4 * k;
+            const double dtt = th - pr[0];
+            const double gt = pr[2] * exp(-dtt * dtt / (2.0 * pr[1] * pr[1]));
+            const double* en = A.src_entries + int64_t(k) * A.entries_per * 5;
+            for (int q = 0; q < A.entries_per; ++q) {
+                if (int(en[5 * q]) != c || int(en[5 * q + 1]) != z || int(en[5 * q + 3]) != x) continue;
+                const int iy = int(en[5 * q + 2]);
+                const double v = gt * en[5 * q + 4];
+#pragma unroll
+                for (int i = 0; i < LMAX; ++i)
+                    if (i == iy) r[i] -= v;
+            }
+        }
+        lu_regs<P, LMAX>(r, ny, fac, fac + ny * (P - 1), fac + 2 * ny * (P - 1));
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i)
+            if (i < ny) buf[base + i * stride] = r[i];
     }
 }
 
@@ -185,10 +260,16 @@ __host__ __device__ constexpr int pair_lu(int which_K1, int c, int a) {
     return which_K1 ? (a == c ? F_M : F_G) : (a == c ? F_GT : F_MT);
 }
 
+// Per half step and component c:
+//   h:  z (curl from e, [b -= dt u], G_z, K_z^{-1}) | x (G_x, K_x^{-1}) | y (G_y, K_y^{-1}, h += -dt/mu .)
+//   e:  z (curl from h, [d += dt v], G_z / eps) | x (G_x) | y (G_y, - s, K_y^{-1}) | x (K_x^{-1})
+//       | z (K_z^{-1}, e += dt .)
+// The factors along different axes commute (Kronecker products), so every
+// Gram product precedes the source and every solve follows it.
 template <int P, int LMAX>
-__global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double* __restrict__ H,
-                                                   const double* __restrict__ gram,
-                                                   const double* __restrict__ fac, const SepArgs A) {
+__global__ void __launch_bounds__(512) sep_kernel(double* __restrict__ E, double* __restrict__ H,
+                                                  const double* __restrict__ gram,
+                                                  const double* __restrict__ fac, const SepArgs A) {
     extern __shared__ double buf[];
     const int b = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
     double* e = E + int64_t(b) * A.e_stride;
@@ -201,16 +282,17 @@ __global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double
         for (int c = 0; c < 3; ++c) {
             const int* od = A.hdims[c];
             const int pitch = od[2] | 1;
-            curl_to_lds<4>(buf, e, A.e_off, A.edims, 1, c, od, A.track ? h + A.n_h + A.h_off[c] : nullptr, -A.dt,
-                           tid, nthr);
+            curl_z_pass<P, LMAX>(buf, e, A.e_off, A.edims, 1, c, od, pitch,
+                                 A.track ? h + A.n_h + A.h_off[c] : nullptr, -A.dt, OP_GRAM | OP_SOLVE,
+                                 gram + A.gram_off[space_tag(SP_B, c, 2)], 1.0, fac + A.fac_off[pair_lu(0, c, 2)],
+                                 tid, nthr);
             __syncthreads();
-#pragma unroll 1
-            for (int a = 0; a < 3; ++a) {
-                sep_pass<P, LMAX, OP_GRAM | OP_SOLVE>(buf, a, od, pitch, gram + A.gram_off[space_tag(SP_B, c, a)],
-                                                      1.0, fac + A.fac_off[pair_lu(0, c, a)], tid, nthr);
-                __syncthreads();
-            }
-            update_from_lds<8>(h + A.h_off[c], buf, od, -A.dt * A.inv_mu, tid, nthr);
+            lds_pass<P, LMAX, OP_GRAM | OP_SOLVE>(buf, 0, od, pitch, gram + A.gram_off[space_tag(SP_B, c, 0)], 1.0,
+                                                  fac + A.fac_off[pair_lu(0, c, 0)], tid, nthr);
+            __syncthreads();
+            final_pass<P, LMAX>(buf, 1, od, pitch, h + A.h_off[c], -A.dt * A.inv_mu, OP_GRAM | OP_SOLVE,
+                                gram + A.gram_off[space_tag(SP_B, c, 1)], 1.0, fac + A.fac_off[pair_lu(0, c, 1)],
+                                tid, nthr);
             __syncthreads();
         }
         // ---- e^{n+1} = e^n + dt K1^{-1} (M~ D~^1 h^{n+1/2} - s(t_{n+1/2}))   [d += dt D~^1 h] ----
@@ -218,35 +300,21 @@ __global__ void __launch_bounds__(768) sep_kernel(double* __restrict__ E, double
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
             const int* od = A.edims[c];
-            const int ny = od[1], pitch = od[2] | 1;
-            curl_to_lds<4>(buf, h, A.h_off, A.hdims, 0, c, od, A.track ? e + A.n_e + A.e_off[c] : nullptr, A.dt,
-                           tid, nthr);
+            const int pitch = od[2] | 1;
+            curl_z_pass<P, LMAX>(buf, h, A.h_off, A.hdims, 0, c, od, pitch,
+                                 A.track ? e + A.n_e + A.e_off[c] : nullptr, A.dt, OP_GRAM,
+                                 gram + A.gram_off[space_tag(SP_D, c, 2)], A.inv_eps, fac, tid, nthr);
             __syncthreads();
-#pragma unroll 1
-            for (int a = 0; a < 3; ++a) {
-                sep_pass<P, LMAX, OP_GRAM>(buf, a, od, pitch, gram + A.gram_off[space_tag(SP_D, c, a)],
-                                           a == 2 ? A.inv_eps : 1.0, fac, tid, nthr);
-                __syncthreads();
-            }
-            // tested point sources, subtracted between the Gram products and the solves
-            for (int k = A.n_src > 0 ? A.src_off[b] : 0; k < (A.n_src > 0 ? A.src_off[b + 1] : 0); ++k) {
-                const double* pr = A.src_prof + 4 * k;
-                const double dtt = th - pr[0];
-                const double gt = pr[2] * exp(-dtt * dtt / (2.0 * pr[1] * pr[1]));
-                const double* en = A.src_entries + int64_t(k) * A.entries_per * 5;
-                for (int q = tid; q < A.entries_per; q += nthr)
-                    if (int(en[5 * q]) == c)
-                        buf[(int(en[5 * q + 1]) * ny + int(en[5 * q + 2])) * pitch + int(en[5 * q + 3])] -=
-                            gt * en[5 * q + 4];
-                __syncthreads();
-            }
-#pragma unroll 1
-            for (int a = 2; a >= 0; --a) {
-                sep_pass<P, LMAX, OP_SOLVE>(buf, a, od, pitch, gram, 1.0, fac + A.fac_off[pair_lu(1, c, a)], tid,
-                                            nthr);
-                __syncthreads();
-            }
-            update_from_lds<8>(e + A.e_off[c], buf, od, A.dt, tid, nthr);
+            lds_pass<P, LMAX, OP_GRAM>(buf, 0, od, pitch, gram + A.gram_off[space_tag(SP_D, c, 0)], 1.0, fac, tid,
+                                       nthr);
+            __syncthreads();
+            y_source_pass<P, LMAX>(buf, od, pitch, gram + A.gram_off[space_tag(SP_D, c, 1)],
+                                   fac + A.fac_off[pair_lu(1, c, 1)], c, A, b, th, tid, nthr);
+            __syncthreads();
+            lds_pass<P, LMAX, OP_SOLVE>(buf, 0, od, pitch, gram, 1.0, fac + A.fac_off[pair_lu(1, c, 0)], tid, nthr);
+            __syncthreads();
+            final_pass<P, LMAX>(buf, 2, od, pitch, e + A.e_off[c], A.dt, OP_SOLVE, gram, 1.0,
+                                fac + A.fac_off[pair_lu(1, c, 2)], tid, nthr);
             __syncthreads();
         }
     }

@@ -92,6 +92,25 @@ def test_separable_plan_matches_oracle(p, N):
     assert rel(out[K.PLAN_SEPARABLE][1], out[K.PLAN_TILED][1]) < 1e-13
 
 
+def test_separable_thread_counts_agree_at_full_lines():
+    """p=3, 24^3 (676 lines per pass, more than any workgroup has threads):
+    every workgroup size gives the same bits, and the tiled plan agrees."""
+    import paper_2302_04979_amd as K
+    p, N, dt = 3, 24, 2e-3
+    out = []
+    for plan, threads in ((K.PLAN_SEPARABLE, 64), (K.PLAN_SEPARABLE, 256), (K.PLAN_SEPARABLE, 320),
+                          (K.PLAN_SEPARABLE, 512), (K.PLAN_TILED, 512)):
+        G = K.Space(p, N)
+        G.set_plan(plan, threads)
+        E = to_dev(W.random_vector(G.n_e, 61))
+        H = to_dev(W.random_vector(G.n_h, 62))
+        G.step(E, H, dt, nsteps=3)
+        out.append((to_host(E), to_host(H)))
+    for k in range(1, 4):
+        assert np.array_equal(out[k][0], out[0][0]) and np.array_equal(out[k][1], out[0][1])
+    assert rel(out[0][0], out[4][0]) < 1e-13 and rel(out[0][1], out[4][1]) < 1e-13
+
+
 def test_separable_plan_tracking_matches_oracle():
     import paper_2302_04979_amd as K
     from oracle.scheme import Scheme
@@ -173,7 +192,7 @@ def test_batched_256_sources_p3_n24():
     ms = G.tune(B, dt, probe_steps=3, J=J)
     print(f"\ntuning (ms/step): {ms} -> plan {G.plan()}", flush=True)
     assert ms[0] is not None and all(m is not None for m in ms[1:])
-    G.set_plan(K.PLAN_SEPARABLE, G.plan()[1] if G.plan()[0] == K.PLAN_SEPARABLE else 768)
+    G.set_plan(K.PLAN_SEPARABLE, G.plan()[1] if G.plan()[0] == K.PLAN_SEPARABLE else 512)
     threads = G.plan()[1]
     E = torch.zeros(B * G.n_e, dtype=torch.float64, device="cuda")
     H = torch.zeros(B * G.n_h, dtype=torch.float64, device="cuda")
