@@ -55,6 +55,25 @@ def mass_flops(p, N, space):
     return 2.0 * tiles * (fma_xy + per_qp * Q ** 3)
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/hbm_traffic.json, FETCH_SIZE + WRITE_SIZE scaled by the copy
+    calibration), or None when that file is missing or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        src = os.path.join(ROOT, "paper_2302_04979_amd", "csrc", t["source"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+                return None
+        return t["kernels"][kernel_key]["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -229,10 +248,10 @@ def batched_timing(K, W, torch, steps=400):
     out = {"workload": f"batched sources: p={p}, {N}^3, identity map, eps=mu=1, {B} Gaussian point dipoles "
                        f"(one per member), zero initial fields, dt=0.5 CFL, {steps} steps in one graph launch, FP64",
            "dofs_e_plus_h": dofs, "ms_per_step": ms / steps, "value": dofs * steps / (ms * 1e-3),
-           "unit": "DOF-updates/s", "plan": {"kind": ["tiled", "separable"][plan[0]] if plan[0] >= 0 else "auto",
+           "unit": "DOF-updates/s", "plan": {"kind": ["tiled", "separable", "separable-fused"][plan[0]] if plan[0] >= 0 else "auto",
                                              "threads": plan[1]},
            "tuner_ms_per_step": dict(zip(K.TUNE_LABELS, tune_ms))}
-    if plan[0] == K.PLAN_SEPARABLE:
+    if plan[0] in (K.PLAN_SEPARABLE, K.PLAN_SEPARABLE_FUSED):
         # kernel duration with HIP events on the launch stream (eager call, same launch)
         G.profile_begin(capacity=8)
         G.step(E, H, dt, nsteps=steps, J=J, batch=B)
@@ -350,8 +369,10 @@ def main():
     avg_mass_s = ms_mass / n_mass * 1e-3
     flops = 0.5 * (mass_flops(p, N, "B") + mass_flops(p, N, "D"))
     achieved = flops / avg_mass_s / 1e12
+    tb, td = measured_traffic("mass_B"), measured_traffic("mass_D")
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": None if tb is None or td is None else 0.5 * (tb + td),
                 "kernel": "mass_kernel (fused curl + 2-form Hodge apply, metric recomputed per Gauss point)",
                 "avg_launch_us": round(avg_mass_s * 1e6, 2),
                 "algorithmic_flops_per_launch": int(flops)}

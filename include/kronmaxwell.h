@@ -98,6 +98,9 @@ typedef enum { KMX_FP64 = 0, KMX_MIXED = 1 } kmx_precision;
  * every quadrature point inside the mass kernel.  Map kind 2 always streams. */
 #define KMX_STORED_METRIC 16
 
+/* Number of FP64-residual corrections of a mixed-precision solve (0..8). */
+kmx_status kmx_set_refinement(kmx_space* sp, int steps);
+
 /* flags for kmx_step / kmx_init_stagger */
 #define KMX_TRACK_DB 1 /* E holds [e | d] and H holds [h | b] per batch member */
 
@@ -185,24 +188,27 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
  *                       with its component tensors in LDS (lines up to 28,
  *                       components up to the device's LDS per workgroup,
  *                       e.g. p = 3, N <= 25).  No per-step energy output.
+ *                       Phases: curl over all entries, one pass per mode
+ *                       product, update over all entries.
+ *   KMX_PLAN_SEPARABLE_FUSED  the same operators with the curl fused into
+ *                       the first (z) pass and the update into the last pass.
  * KMX_PLAN_AUTO (the default) takes the separable plan when it applies and
- * batch >= 32, the tiled plan otherwise.  `threads` is the separable kernel's
- * workgroup size (64..512, multiple of 64).  Forcing KMX_PLAN_SEPARABLE on a
- * call it cannot serve fails with KMX_E_STATE.  Both plans compute the same
+ * batch >= 32, the tiled plan otherwise.  `threads` is the separable kernels'
+ * workgroup size (64..768, multiple of 64).  Forcing a separable plan on a
+ * call it cannot serve fails with KMX_E_STATE.  All plans compute the same
  * operators; results differ by rounding only. */
-/* Number of FP64-residual corrections of a mixed-precision solve (0..8). */
-kmx_status kmx_set_refinement(kmx_space* sp, int steps);
-
 #define KMX_PLAN_AUTO (-1)
 #define KMX_PLAN_TILED 0
 #define KMX_PLAN_SEPARABLE 1
+#define KMX_PLAN_SEPARABLE_FUSED 2
 kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads);
 kmx_status kmx_get_plan(const kmx_space* sp, int* kind, int* threads);
 
 /* Times the candidate plans on `batch` members (zero fields of its own, J
  * driving them if not NULL, time step dt) over probe_steps steps each after
  * one warm-up step, and keeps the fastest as the space's plan.  Candidates:
- * 0 tiled; 1..5 separable with 256, 320, 384, 448, 512 threads.  ms_out:
+ * 0 tiled; 1..3 separable with 384, 512, 768 threads; 4..5 separable-fused
+ * with 512, 768 threads.  ms_out:
  * NULL or host array of KMX_TUNE_CANDIDATES entries receiving the mean ms per
  * step (-1 where a candidate does not apply).  Allocates two fields of
  * working memory; synchronises. */

@@ -23,9 +23,10 @@ LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
 TRACK_DB = 1
 STORED_METRIC = 16
 FP64, MIXED = 0, 1
-PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE = -1, 0, 1
+PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE, PLAN_SEPARABLE_FUSED = -1, 0, 1, 2
 TUNE_CANDIDATES = 6
-TUNE_LABELS = ("tiled", "separable/256", "separable/320", "separable/384", "separable/448", "separable/512")
+TUNE_LABELS = ("tiled", "separable/384", "separable/512", "separable/768", "separable-fused/512",
+               "separable-fused/768")
 
 # every symbol declared in include/kronmaxwell.h
 EXPORTS = (
@@ -332,7 +333,7 @@ class Space:
         _check(load_library().kmx_set_refinement(self._h, int(steps)))
 
     # ---- execution plans --------------------------------------------------
-    def set_plan(self, kind: int, threads: int = 512):
+    def set_plan(self, kind: int, threads: int = 768):
         _check(load_library().kmx_set_plan(self._h, int(kind), int(threads)))
 
     def plan(self):

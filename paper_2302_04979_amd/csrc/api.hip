@@ -212,6 +212,7 @@ void run_curlT(kmx_space* sp, int primal, const double* y, double* out, double a
     launch_curlT(a, primal ? sp->n_e : sp->n_h, 1, s);
 }
 
+// blocks of the dot-product and CG reductions (per batch member)
 int energy_blocks(const kmx_space* sp) {
     const int64_t n = std::max(sp->n_e, sp->n_h);
     return int(std::min<int64_t>(1024, (n + 255) / 256));
@@ -219,31 +220,25 @@ int energy_blocks(const kmx_space* sp) {
 
 void run_energy(kmx_space* sp, const double* E, const double* H, double dt, int batch, double* out,
                 int64_t out_stride, hipStream_t s) {
-    ProfScope ps(sp, s, PK_ENERGY);  // one span for the pairing applies and the sums
-    const bool saved = sp->prof_on;
-    sp->prof_on = false;
-    const int64_t nfield = std::max(sp->n_e, sp->n_h);
-    EnergyArgs a{};
+    ProfScope ps(sp, s, PK_ENERGY);
+    EnergyFusedArgs a{};
     a.E = E;
     a.H = H;
     a.n_e = sp->n_e;
     a.n_h = sp->n_h;
     space_dims(sp, SP_E, a.e_dims, a.e_comp_off);
     space_dims(sp, SP_B, a.h_dims, a.h_comp_off);
-    a.work = sp->d_tmp2;
-    a.work_stride = nfield;
+    fill_fac(sp, &a.fac, a.fac_off);
+    for (int c = 0; c < 3; ++c)
+        for (int ax = 0; ax < 3; ++ax) {
+            a.fac_id[0][c][ax] = pair_fac(1, 0, c, ax);
+            a.fac_id[1][c][ax] = pair_fac(0, 0, c, ax);
+        }
+    a.nb[0] = energy_fused_blocks(a.e_dims, a.cb[0]);
+    a.nb[1] = energy_fused_blocks(a.h_dims, a.cb[1]);
     a.partial = sp->d_red;
-    a.nblocks = energy_blocks(sp);
-    // v = K1 e, then d . v
-    run_solve(sp, 1, 0, 0, SP_D, E, 2 * sp->n_e, sp->d_tmp2, nfield, 1.0, 0, batch, nullptr, 0.0, 2, s);
-    a.mode = 0;
-    launch_energy(sp->p, a, batch, s);
-    // u = K~1 h, then b . u and u . D^1 e
-    run_solve(sp, 0, 0, 0, SP_B, H, 2 * sp->n_h, sp->d_tmp2, nfield, 1.0, 0, batch, nullptr, 0.0, 2, s);
-    a.mode = 1;
-    launch_energy(sp->p, a, batch, s);
-    launch_energy_final(sp->d_red, a.nblocks, dt, batch, out, out_stride, s);
-    sp->prof_on = saved;
+    launch_energy_fused(sp->p, a, batch, s);
+    launch_energy_final(sp->d_red, a.nb[0] + a.nb[1], dt, batch, out, out_stride, s);
 }
 
 kmx_status upload(double** dst, const std::vector<double>& v) {
@@ -480,7 +475,16 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
         int64_t off[3];
         sp->patch_per_field = std::max(patch_size(p, SP_B, sp->ntile, off), patch_size(p, SP_D, sp->ntile, off));
         const int64_t nfield = std::max(sp->n_e, sp->n_h);
-        sp->red_len = int64_t(max_batch) * 1024 * 3 + 64;
+        {
+            // reduction partials: the CG and dot kernels use up to 1024 blocks per
+            // member, the fused energy kernel one per (component, plane, row block)
+            int ed[3][3], hd[3][3], cb[3];
+            int64_t o[3];
+            space_dims(sp, SP_E, ed, o);
+            space_dims(sp, SP_B, hd, o);
+            const int64_t nbe = energy_fused_blocks(ed, cb) + energy_fused_blocks(hd, cb);
+            sp->red_len = int64_t(max_batch) * std::max<int64_t>(1024, nbe) * 3 + 64;
+        }
         if (hipMalloc(&sp->d_patch, size_t(sp->patch_per_field) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_tmp, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_tmp2, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
@@ -1145,7 +1149,8 @@ kmx_status run_sep(kmx_space* sp, double* E, double* H, const kmx_source* J, dou
         a.entries_per = J->entries_per;
     }
     ProfScope ps(sp, s, PK_SEP);
-    const hipError_t err = launch_sep(sp->p, sep_line_max(std::max(sp->n0, sp->n1)), E, H, sp->d_gram, sp->d_fac,
+    const hipError_t err = launch_sep(sp->p, sep_line_max(std::max(sp->n0, sp->n1)),
+                                      sp->plan_kind == KMX_PLAN_SEPARABLE_FUSED ? 1 : 0, E, H, sp->d_gram, sp->d_fac,
                                       a, batch, sp->plan_threads, s);
     if (err != hipSuccess) return fail(KMX_E_DEVICE, std::string("separable kernel: ") + hipGetErrorString(err));
     return KMX_OK;
@@ -1163,11 +1168,11 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     if (energy_dev && !track) return fail(KMX_E_ARG, "energy output needs KMX_TRACK_DB");
     const bool sep_ok = sep_eligible(sp, energy_dev);
     int kind = sp->plan_kind;
-    if (kind == KMX_PLAN_SEPARABLE && !sep_ok)
+    if ((kind == KMX_PLAN_SEPARABLE || kind == KMX_PLAN_SEPARABLE_FUSED) && !sep_ok)
         return fail(KMX_E_STATE, "separable plan needs the identity map, uniform eps and mu, no energy output "
                                  "and component tensors that fit one workgroup's LDS");
     if (kind == KMX_PLAN_AUTO) kind = (sep_ok && batch >= SEP_AUTO_MIN_BATCH) ? KMX_PLAN_SEPARABLE : KMX_PLAN_TILED;
-    if (kind == KMX_PLAN_SEPARABLE) {
+    if (kind == KMX_PLAN_SEPARABLE || kind == KMX_PLAN_SEPARABLE_FUSED) {
         if (nsteps > 0) {
             const kmx_status st = run_sep(sp, E, H, J, t_start, t_dev, dt, nsteps, batch, track, s);
             if (st != KMX_OK) return st;
@@ -1232,10 +1237,11 @@ kmx_status kmx_set_refinement(kmx_space* sp, int steps) {
 
 kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads) {
     if (!sp) return fail(KMX_E_ARG, "space is NULL");
-    if (kind != KMX_PLAN_AUTO && kind != KMX_PLAN_TILED && kind != KMX_PLAN_SEPARABLE)
+    if (kind != KMX_PLAN_AUTO && kind != KMX_PLAN_TILED && kind != KMX_PLAN_SEPARABLE &&
+        kind != KMX_PLAN_SEPARABLE_FUSED)
         return fail(KMX_E_ARG, "unknown plan kind");
     if (threads < 64 || threads > SEP_MAX_THREADS || threads % 64)
-        return fail(KMX_E_ARG, "threads must be 64..512, a multiple of 64");
+        return fail(KMX_E_ARG, "threads must be 64..768, a multiple of 64");
     sp->plan_kind = kind;
     sp->plan_threads = threads;
     return KMX_OK;
@@ -1253,7 +1259,10 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     if (!sp || batch < 1 || batch > sp->max_batch || probe_steps < 1) return fail(KMX_E_ARG, "bad argument");
     if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 256, 320, 384, 448, 512};
+    static const int cand_kind[KMX_TUNE_CANDIDATES] = {KMX_PLAN_TILED,          KMX_PLAN_SEPARABLE,
+                                                       KMX_PLAN_SEPARABLE,      KMX_PLAN_SEPARABLE,
+                                                       KMX_PLAN_SEPARABLE_FUSED, KMX_PLAN_SEPARABLE_FUSED};
+    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 384, 512, 768, 512, 768};
     const bool sep_ok = sep_eligible(sp, nullptr);
     double* E = nullptr;
     double* H = nullptr;
@@ -1273,7 +1282,7 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     for (int k = 0; k < KMX_TUNE_CANDIDATES && st == KMX_OK; ++k) {
         double ms = -1.0;
         if (k == 0 || sep_ok) {
-            sp->plan_kind = k == 0 ? KMX_PLAN_TILED : KMX_PLAN_SEPARABLE;
+            sp->plan_kind = cand_kind[k];
             sp->plan_threads = k == 0 ? saved_threads : cand_threads[k];
             st = step_loop(sp, E, H, J, 0.0, nullptr, dt, 1, batch, 0, nullptr, s);  // warm-up
             if (st == KMX_OK) (void)hipEventRecord(ev[0], s);
@@ -1302,7 +1311,7 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
         sp->plan_threads = saved_threads;
         return st;
     }
-    sp->plan_kind = best_k == 0 ? KMX_PLAN_TILED : KMX_PLAN_SEPARABLE;
+    sp->plan_kind = cand_kind[best_k];
     sp->plan_threads = best_k == 0 ? saved_threads : cand_threads[best_k];
     return KMX_OK;
 }

@@ -23,6 +23,16 @@ namespace kmx {
 // patch; neighbouring patches overlap and are summed, in a fixed order, by the
 // solve kernel that consumes them (no atomics: bitwise deterministic).
 // ===========================================================================
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// block index; block i is given tile (i mod 8) * (T/8) + i / 8 so that every
+// XCD walks one contiguous range of tiles (whole z layers at 64^3) and the
+// windows that neighbouring tiles share stay in that XCD's L2.
+__device__ inline int xcd_tile(int block, int ntiles) {
+    constexpr int XCD = 8;
+    const int per = ntiles / XCD;
+    return block < per * XCD ? (block % XCD) * per + block / XCD : block;
+}
+
 template <int P>
 struct MassCfg {
     static constexpr int NQ = P + 1;
@@ -267,9 +277,9 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
     __shared__ double sm[OB + BB];
 
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x;
-    const int b = blockIdx.y;
     const int nt = A.ntile;
+    const int tile = xcd_tile(blockIdx.x, nt * nt * nt);
+    const int b = blockIdx.y;
     const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
     const int tcoord[3] = {tx, ty, tz};
     const double* src = A.src + int64_t(b) * A.src_stride;
@@ -861,10 +871,9 @@ void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s) {
 }
 
 // ===========================================================================
-// Energies (3.2) and the leapfrog invariant, FP64, deterministic tree sums,
-// from v = K1 e and u = K~1 h (computed by the line kernels in apply mode):
-//   mode 0: term0 = d . v                over X~^2
-//   mode 1: term1 = b . u, term2 = u . (D^1 e)   over X^2_{h,0}
+// Energies (3.2) and the leapfrog invariant, FP64, deterministic tree sums:
+//   term0 = d . (K1 e)  over X~^2
+//   term1 = b . (K~1 h), term2 = (K~1 h) . (D^1 e)  over X^2_{h,0}
 // ===========================================================================
 template <int NTH>
 __device__ inline void block_sum3(double v0, double v1, double v2, double* out) {
@@ -882,45 +891,128 @@ __device__ inline void block_sum3(double v0, double v1, double v2, double* out) 
         for (int k = 0; k < 3; ++k) out[k] = s[k][0];
 }
 
-__global__ void __launch_bounds__(256) energy_kernel(const EnergyArgs A) {
-    const int b = blockIdx.y;
-    const double* e = A.E + int64_t(b) * 2 * A.n_e;
-    const double* h = A.H + int64_t(b) * 2 * A.n_h;
-    const double* w = A.work + int64_t(b) * A.work_stride;
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-    if (A.mode == 0) {
-        const double* dvec = e + A.n_e;
-        for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_e; i += int64_t(gridDim.x) * 256)
-            t0 += w[i] * dvec[i];
-    } else {
-        const double* bvec = h + A.n_h;
-        for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_h; i += int64_t(gridDim.x) * 256) {
-            int c = 0;
-            while (c < 2 && i >= A.h_comp_off[c + 1]) ++c;
-            const int64_t li = i - A.h_comp_off[c];
-            const int* d = A.h_dims[c];
-            const int x = int(li % d[2]), y = int((li / d[2]) % d[1]), z = int(li / (int64_t(d[2]) * d[1]));
+// Fused energy terms: one workgroup per (component, z plane, block of EROWS
+// rows) forms w = K v on its rows (K1 e for the first term, K~1 h for the
+// other two) by the Kronecker structure: the z band combines 2W+1 planes,
+// then the x and y bands run in LDS; the dot products with d (first term), b
+// and D^1 e (second and third) follow in the same pass.  Blocks [0, nb0) do
+// the first term, [nb0, nb0 + nb1) the others; each writes its three partial
+// sums (zeros for terms it does not own) for the fixed-order final sum.
+constexpr int EROWS = 16;
+
+template <int P>
+__global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs A) {
+    constexpr int W = P - 1, B = 2 * W + 1;
+    constexpr int TR = EROWS + 2 * W;  // staged rows (with the y halo)
+    __shared__ double tile[TR * KMX_LINE_MAX];
+    __shared__ double band[3][KMX_LINE_MAX * B];
+    const int tid = threadIdx.x, bm = blockIdx.y;
+    const int blk = blockIdx.x;
+    const int mode = blk < A.nb[0] ? 0 : 1;
+    int rem = mode == 0 ? blk : blk - A.nb[0];
+    int c = 0;
+    while (c < 2 && rem >= A.cb[mode][c]) rem -= A.cb[mode][c++];
+    const int* d = mode == 0 ? A.e_dims[c] : A.h_dims[c];
+    const int nz = d[0], ny = d[1], nx = d[2];
+    const int nyb = (ny + EROWS - 1) / EROWS;
+    const int z = rem / nyb, y0 = (rem % nyb) * EROWS;
+    const double* E = A.E + int64_t(bm) * 2 * A.n_e;
+    const double* H = A.H + int64_t(bm) * 2 * A.n_h;
+    const double* v = (mode == 0 ? E + A.e_comp_off[c] : H + A.h_comp_off[c]);
+    // bands of the three axes (the factor sets' stored matrix)
+    for (int a = 0; a < 3; ++a) {
+        const int n = d[2 - a];
+        const double* src = A.fac + A.fac_off[A.fac_id[mode][c][a]] + 2 * int64_t(n) * W + n;
+        for (int i = tid; i < n * B; i += 256) band[a][i] = src[i];
+    }
+    __syncthreads();
+    // z band: tile[r][x] = sum_k Kz(z, z+k) v[z+k][y0-W+r][x]
+    for (int i = tid; i < TR * nx; i += 256) {
+        const int r = i / nx, x = i % nx, y = y0 - W + r;
+        double s = 0.0;
+        if (y >= 0 && y < ny) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int zz = z - W + k;
+                if (zz >= 0 && zz < nz) s += band[2][z * B + k] * v[(int64_t(zz) * ny + y) * nx + x];
+            }
+        }
+        tile[r * KMX_LINE_MAX + x] = s;
+    }
+    __syncthreads();
+    // x band, row by row (outputs to registers first: the rows are updated in place)
+    constexpr int SL = (TR * KMX_LINE_MAX + 255) / 256;
+    double t[SL];
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+        const int i = tid + q * 256;
+        t[q] = 0.0;
+        if (i < TR * nx) {
+            const int r = i / nx, x = i % nx;
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int xx = x - W + k;
+                if (xx >= 0 && xx < nx) t[q] += band[0][x * B + k] * tile[r * KMX_LINE_MAX + xx];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+        const int i = tid + q * 256;
+        if (i < TR * nx) tile[(i / nx) * KMX_LINE_MAX + (i % nx)] = t[q];
+    }
+    __syncthreads();
+    // y band on the owned rows, then the dot products
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const int rows = ny - y0 < EROWS ? ny - y0 : EROWS;
+    for (int i = tid; i < rows * nx; i += 256) {
+        const int ry = i / nx, x = i % nx, y = y0 + ry;
+        double w = 0.0;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int yy = y - W + k;
+            if (yy >= 0 && yy < ny) w += band[1][y * B + k] * tile[(ry + k) * KMX_LINE_MAX + x];
+        }
+        const int64_t at = (int64_t(z) * ny + y) * nx + x;
+        if (mode == 0) {
+            s0 += w * E[A.n_e + A.e_comp_off[c] + at];
+        } else {
             const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            const double cu = diff1(e + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
-                              diff1(e + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
-            t1 += w[i] * bvec[i];
-            t2 += w[i] * cu;
+            const double cu = diff1(E + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
+                              diff1(E + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
+            s1 += w * H[A.n_h + A.h_comp_off[c] + at];
+            s2 += w * cu;
         }
     }
     __shared__ double r[3];
-    block_sum3<256>(t0, t1, t2, r);
-    if (threadIdx.x == 0) {
-        double* p = A.partial + (int64_t(b) * A.nblocks + blockIdx.x) * 3;
-        if (A.mode == 0) p[0] = r[0];
-        else {
-            p[1] = r[1];
-            p[2] = r[2];
-        }
+    block_sum3<256>(s0, s1, s2, r);
+    if (tid == 0) {
+        double* o = A.partial + (int64_t(bm) * (A.nb[0] + A.nb[1]) + blk) * 3;
+        o[0] = r[0];
+        o[1] = r[1];
+        o[2] = r[2];
     }
 }
 
-void launch_energy(int, const EnergyArgs& a, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(energy_kernel, dim3(a.nblocks, batch), dim3(256), 0, s, a);
+void launch_energy_fused(int p, const EnergyFusedArgs& a, int batch, hipStream_t s) {
+    dim3 grid(a.nb[0] + a.nb[1], batch);
+#define LE(PP)                                                                      \
+    if (p == PP) {                                                                  \
+        hipLaunchKernelGGL((energy_fused_kernel<PP>), grid, dim3(256), 0, s, a);    \
+        return;                                                                     \
+    }
+    LE(2) LE(3) LE(4)
+#undef LE
+}
+
+int energy_fused_blocks(const int dims[3][3], int cb[3]) {
+    int tot = 0;
+    for (int c = 0; c < 3; ++c) {
+        cb[c] = dims[c][0] * ((dims[c][1] + EROWS - 1) / EROWS);
+        tot += cb[c];
+    }
+    return tot;
 }
 
 __global__ void __launch_bounds__(256) energy_final_kernel(const double* partial, int nblocks, double dt,

@@ -92,17 +92,19 @@ struct CurlArgs {
     int primal;
 };
 
-struct EnergyArgs {
+// All three energy terms in one launch (K v formed plane-block by plane-block).
+struct EnergyFusedArgs {
     const double* E;            // [e | d] per batch member
     const double* H;            // [h | b]
     int64_t n_e, n_h;
     int64_t e_comp_off[3], h_comp_off[3];
     int e_dims[3][3], h_dims[3][3];
-    const double* work;         // v = K1 e (mode 0) or u = K~1 h (mode 1)
-    int64_t work_stride;
-    double* partial;            // [batch][nblocks][3]
-    int nblocks;
-    int mode;
+    const double* fac;          // banded factor sets (their stored matrices are used)
+    int64_t fac_off[8];
+    int fac_id[2][3][3];        // [term group][c][axis]: K1 factors, K~1 factors
+    int nb[2];                  // blocks of the first term and of the other two
+    int cb[2][3];               // blocks per component
+    double* partial;            // [batch][nb0 + nb1][3]
 };
 
 struct PairGradArgs {           // per-element metric pairing of lam and D~^1 h
@@ -128,7 +130,7 @@ struct PairGradArgs {           // per-element metric pairing of lam and D~^1 h
 // one workgroup per batch member runs all nsteps with the component tensors
 // in LDS.  Fields are passed as kernel arguments of their own.
 constexpr int SEP_LINE_MAX = 28;   // longest line (n0, n1) the kernel holds in registers
-constexpr int SEP_MAX_THREADS = 512;  // launch bound of the separable kernel
+constexpr int SEP_MAX_THREADS = 768;  // launch bound of the separable kernel
 struct SepArgs {
     int64_t e_stride, h_stride;    // distance between batch members (doubled with tracking)
     int64_t n_e, n_h;              // offset of d inside E and of b inside H
@@ -149,7 +151,7 @@ struct SepArgs {
 size_t sep_lds_bytes(const int edims[3][3], const int hdims[3][3]);
 int sep_line_max(int n_max);       // register line length for lines up to n_max, 0 if too long
 hipError_t sep_prepare(int p, int lmax, size_t shm);   // grant the kernel its LDS (outside graph capture)
-hipError_t launch_sep(int p, int lmax, double* E, double* H, const double* gram, const double* fac,
+hipError_t launch_sep(int p, int lmax, int variant, double* E, double* H, const double* gram, const double* fac,
                       const SepArgs& a, int batch, int threads, hipStream_t s);
 
 // Mode-n product of every component of a field with a dense FP32 factor on
@@ -187,7 +189,8 @@ void launch_gather(int p, int space, const GatherArgs& a, int64_t n, int batch, 
 void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s);
 void launch_z(int p, const ZArgs& a, int batch, hipStream_t s);
 void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
-void launch_energy(int p, const EnergyArgs& a, int batch, hipStream_t s);
+void launch_energy_fused(int p, const EnergyFusedArgs& a, int batch, hipStream_t s);
+int energy_fused_blocks(const int dims[3][3], int cb[3]);
 // out[b*out_stride] (+ step offset) from the energy partials
 void launch_energy_final(const double* partial, int nblocks, double dt, int batch, double* out,
                          int64_t out_stride, hipStream_t s);

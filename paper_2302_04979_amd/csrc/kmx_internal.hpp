@@ -137,7 +137,7 @@ struct kmx_space {
     double eps_value = 1.0, mu_value = 1.0;   // 1/eps and 1/mu when uniform
     int max_lds = 0;                   // device limit of LDS bytes per workgroup
     int plan_kind = -1;                // -1 automatic, KMX_PLAN_TILED, KMX_PLAN_SEPARABLE
-    int plan_threads = 512;            // workgroup size of the separable kernel
+    int plan_threads = 768;            // workgroup size of the separable kernel
     // mixed-precision solves (precision & KMX_MIXED): dense FP32 inverses of
     // the four 1D pairing factors and working fields
     float* d_inv32 = nullptr;          // [G^-1 | M^-1 | G^-T | M^-T], row-major

@@ -74,7 +74,7 @@ def test_separable_plan_matches_oracle(p, N):
     E0 = W.random_vector(2 * S.n_e, 21) * 0.1
     H0 = W.random_vector(2 * S.n_h, 22) * 0.1
     out = {}
-    for plan in (K.PLAN_SEPARABLE, K.PLAN_TILED):
+    for plan in (K.PLAN_SEPARABLE, K.PLAN_SEPARABLE_FUSED, K.PLAN_TILED):
         G = K.Space(p, N, max_batch=2)
         G.set_materials(eps=np.full(n3, 2.5), mu=np.full(n3, 1.5))
         G.set_plan(plan, 256)
@@ -85,11 +85,13 @@ def test_separable_plan_matches_oracle(p, N):
     for k in range(2):
         e, h = _oracle_member(S, dip, k, E0[k * S.n_e:(k + 1) * S.n_e], H0[k * S.n_h:(k + 1) * S.n_h], dt, nsteps,
                               t_start)
-        Es, Hs = out[K.PLAN_SEPARABLE]
-        assert rel(Es[k * S.n_e:(k + 1) * S.n_e], e) < 1e-12
-        assert rel(Hs[k * S.n_h:(k + 1) * S.n_h], h) < 1e-12
-    assert rel(out[K.PLAN_SEPARABLE][0], out[K.PLAN_TILED][0]) < 1e-13
-    assert rel(out[K.PLAN_SEPARABLE][1], out[K.PLAN_TILED][1]) < 1e-13
+        for plan in (K.PLAN_SEPARABLE, K.PLAN_SEPARABLE_FUSED):
+            Es, Hs = out[plan]
+            assert rel(Es[k * S.n_e:(k + 1) * S.n_e], e) < 1e-12
+            assert rel(Hs[k * S.n_h:(k + 1) * S.n_h], h) < 1e-12
+    for plan in (K.PLAN_SEPARABLE, K.PLAN_SEPARABLE_FUSED):
+        assert rel(out[plan][0], out[K.PLAN_TILED][0]) < 1e-13
+        assert rel(out[plan][1], out[K.PLAN_TILED][1]) < 1e-13
 
 
 def test_separable_thread_counts_agree_at_full_lines():
@@ -98,26 +100,31 @@ def test_separable_thread_counts_agree_at_full_lines():
     import paper_2302_04979_amd as K
     p, N, dt = 3, 24, 2e-3
     out = []
-    for plan, threads in ((K.PLAN_SEPARABLE, 64), (K.PLAN_SEPARABLE, 256), (K.PLAN_SEPARABLE, 320),
-                          (K.PLAN_SEPARABLE, 512), (K.PLAN_TILED, 512)):
+    for plan, threads in ((K.PLAN_SEPARABLE, 64), (K.PLAN_SEPARABLE, 256), (K.PLAN_SEPARABLE, 384),
+                          (K.PLAN_SEPARABLE, 768), (K.PLAN_TILED, 768), (K.PLAN_SEPARABLE_FUSED, 64),
+                          (K.PLAN_SEPARABLE_FUSED, 384), (K.PLAN_SEPARABLE_FUSED, 768)):
         G = K.Space(p, N)
         G.set_plan(plan, threads)
         E = to_dev(W.random_vector(G.n_e, 61))
         H = to_dev(W.random_vector(G.n_h, 62))
         G.step(E, H, dt, nsteps=3)
         out.append((to_host(E), to_host(H)))
-    for k in range(1, 4):
+    for k in (1, 2, 3):
         assert np.array_equal(out[k][0], out[0][0]) and np.array_equal(out[k][1], out[0][1])
-    assert rel(out[0][0], out[4][0]) < 1e-13 and rel(out[0][1], out[4][1]) < 1e-13
+    for k in (6, 7):
+        assert np.array_equal(out[k][0], out[5][0]) and np.array_equal(out[k][1], out[5][1])
+    for k in (4, 5):
+        assert rel(out[0][0], out[k][0]) < 1e-13 and rel(out[0][1], out[k][1]) < 1e-13
 
 
-def test_separable_plan_tracking_matches_oracle():
+@pytest.mark.parametrize("fused", [False, True])
+def test_separable_plan_tracking_matches_oracle(fused):
     import paper_2302_04979_amd as K
     from oracle.scheme import Scheme
     p, N, dt, nsteps = 3, 7, 0.01, 12
     S = Scheme(p, N)
     G = K.Space(p, N)
-    G.set_plan(K.PLAN_SEPARABLE, 384)
+    G.set_plan(K.PLAN_SEPARABLE_FUSED if fused else K.PLAN_SEPARABLE, 384)
     e0, h0 = W.random_vector(S.n_e, 31), W.random_vector(S.n_h, 32)
     d0, b0 = W.random_vector(S.n_e, 33), W.random_vector(S.n_h, 34)
     E, H = to_dev(np.concatenate([e0, d0])), to_dev(np.concatenate([h0, b0]))
@@ -146,12 +153,13 @@ def test_separable_plan_refuses_what_it_cannot_run():
         G2.set_plan(K.PLAN_SEPARABLE, 100)  # not a multiple of 64
 
 
-def test_separable_graph_replays_equal_eager_steps():
+@pytest.mark.parametrize("fused", [False, True])
+def test_separable_graph_replays_equal_eager_steps(fused):
     import torch
     import paper_2302_04979_amd as K
     p, N, B, Kst = 3, 6, 4, 9
     G = K.Space(p, N, max_batch=B)
-    G.set_plan(K.PLAN_SEPARABLE, 512)
+    G.set_plan(K.PLAN_SEPARABLE_FUSED if fused else K.PLAN_SEPARABLE, 512)
     dt = 0.01
     dip = W.dipoles(B, seed=8, dt=dt)
     dip["t0"] = np.full(B, 10 * dt)
@@ -192,8 +200,9 @@ def test_batched_256_sources_p3_n24():
     ms = G.tune(B, dt, probe_steps=3, J=J)
     print(f"\ntuning (ms/step): {ms} -> plan {G.plan()}", flush=True)
     assert ms[0] is not None and all(m is not None for m in ms[1:])
-    G.set_plan(K.PLAN_SEPARABLE, G.plan()[1] if G.plan()[0] == K.PLAN_SEPARABLE else 512)
-    threads = G.plan()[1]
+    if G.plan()[0] == K.PLAN_TILED:
+        G.set_plan(K.PLAN_SEPARABLE, 768)
+    kind, threads = G.plan()
     E = torch.zeros(B * G.n_e, dtype=torch.float64, device="cuda")
     H = torch.zeros(B * G.n_h, dtype=torch.float64, device="cuda")
     gr = G.graph(E, H, dt, nsteps, J=J, batch=B)
@@ -203,13 +212,13 @@ def test_batched_256_sources_p3_n24():
     gr.launch()
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    print(f"batched 256 x 400 steps (separable, {threads} threads): {el * 1e3:.1f} ms, "
+    print(f"batched 256 x 400 steps (plan {kind}, {threads} threads): {el * 1e3:.1f} ms, "
           f"{(G.n_e + G.n_h) * B * nsteps / el:.3e} DOF-updates/s", flush=True)
     Eb = to_host(E)
     assert np.isfinite(Eb).all() and np.abs(Eb).max() > 0
     for k in (0, 97, 255):
         G1 = K.Space(p, N)
-        G1.set_plan(K.PLAN_SEPARABLE, threads)
+        G1.set_plan(kind, threads)
         J1 = G1.source(dip["pos"][k:k + 1], dip["moment"][k:k + 1], dip["t0"][k:k + 1], dip["sigma"][k:k + 1],
                        dip["amp"][k:k + 1])
         E1 = torch.zeros(G1.n_e, dtype=torch.float64, device="cuda")
@@ -220,7 +229,7 @@ def test_batched_256_sources_p3_n24():
     S = Scheme(p, N)
     e, h = _oracle_member(S, dip, k, np.zeros(S.n_e), np.zeros(S.n_h), dt, n_or)
     G1 = K.Space(p, N)
-    G1.set_plan(K.PLAN_SEPARABLE, threads)
+    G1.set_plan(kind, threads)
     J1 = G1.source(dip["pos"][k:k + 1], dip["moment"][k:k + 1], dip["t0"][k:k + 1], dip["sigma"][k:k + 1],
                    dip["amp"][k:k + 1])
     E1 = torch.zeros(G1.n_e, dtype=torch.float64, device="cuda")
