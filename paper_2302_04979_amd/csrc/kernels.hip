@@ -394,17 +394,16 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
                     for (int k = 0; k < 6; ++k)
                         gn[k] = __builtin_nontemporal_load(gm + int64_t(qz + 1) * 6 * Q * Q + k * Q * Q);
                 }
+                // analytic metric: G = f (I + a (p 1^T + 1 p^T) + 3 a^2 p p^T) with p = grad s,
+                // applied below as a rank-2 update of the identity
+                double p1 = 0.0, p2 = 0.0, p3 = 0.0, f = 0.0;
                 if (MET == 1) {
                     const int gzq = tz * TILE * NQ + qz;
                     const double sz = A.axis_tab[gzq], cz = A.axis_tab[npq + gzq], wz = A.axis_tab[2 * npq + gzq];
-                    const double p1 = a1 * sz, p2 = a2 * sz, p3 = a3 * cz;
-                    const double f = wxy * wz * recip_nr(1.0 + amp * (p1 + p2 + p3));
-                    g[0] = f * (1.0 + 2.0 * amp * p1 + aa * p1 * p1);
-                    g[1] = f * (1.0 + 2.0 * amp * p2 + aa * p2 * p2);
-                    g[2] = f * (1.0 + 2.0 * amp * p3 + aa * p3 * p3);
-                    g[3] = f * (amp * (p1 + p2) + aa * p1 * p2);
-                    g[4] = f * (amp * (p1 + p3) + aa * p1 * p3);
-                    g[5] = f * (amp * (p2 + p3) + aa * p2 * p3);
+                    p1 = a1 * sz;
+                    p2 = a2 * sz;
+                    p3 = a3 * cz;
+                    f = wxy * wz * recip_nr(1.0 + amp * (p1 + p2 + p3));
                 }
                 const double* t0 = tz0 + (le * NQ + iq) * L0::Kz;
                 const double* t2 = tz2 + (le * NQ + iq) * L2::Kz;
@@ -416,9 +415,19 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
 #pragma unroll
                 for (int j = 0; j < L2::Kz; ++j) v2 += t2[j] * A2[le + j];
                 const double s = ig[le];
-                const double u0 = s * (g[0] * v0 + g[3] * v1 + g[4] * v2);
-                const double u1 = s * (g[3] * v0 + g[1] * v1 + g[5] * v2);
-                const double u2 = s * (g[4] * v0 + g[5] * v1 + g[2] * v2);
+                double u0, u1, u2;
+                if (MET == 1) {
+                    // G v = f (v + (a S + 3 a^2 P) p + a P 1), S = sum v, P = p . v
+                    const double S = v0 + v1 + v2, Pv = p1 * v0 + p2 * v1 + p3 * v2;
+                    const double al = amp * S + aa * Pv, be = amp * Pv, sf = s * f;
+                    u0 = sf * (v0 + fma(al, p1, be));
+                    u1 = sf * (v1 + fma(al, p2, be));
+                    u2 = sf * (v2 + fma(al, p3, be));
+                } else {
+                    u0 = s * (g[0] * v0 + g[3] * v1 + g[4] * v2);
+                    u1 = s * (g[3] * v0 + g[1] * v1 + g[5] * v2);
+                    u2 = s * (g[4] * v0 + g[5] * v1 + g[2] * v2);
+                }
 #pragma unroll
                 for (int j = 0; j < L0::Kz; ++j) R0c[le + j] += t0[j] * u0;
 #pragma unroll
@@ -1245,17 +1254,16 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) pair_grad_kernel(const PairGra
             for (int iq = 0; iq < NQ; ++iq) {
                 const int qz = le * NQ + iq;
                 double g[6];
+                // analytic metric: G = f (I + a (p 1^T + 1 p^T) + 3 a^2 p p^T) with p = grad s,
+                // applied below as a rank-2 update of the identity
+                double p1 = 0.0, p2 = 0.0, p3 = 0.0, f = 0.0;
                 if (MET == 1) {
                     const int gzq = tz * TILE * NQ + qz;
                     const double sz = A.axis_tab[gzq], cz = A.axis_tab[npq + gzq], wz = A.axis_tab[2 * npq + gzq];
-                    const double p1 = a1 * sz, p2 = a2 * sz, p3 = a3 * cz;
-                    const double f = wxy * wz * recip_nr(1.0 + amp * (p1 + p2 + p3));
-                    g[0] = f * (1.0 + 2.0 * amp * p1 + aa * p1 * p1);
-                    g[1] = f * (1.0 + 2.0 * amp * p2 + aa * p2 * p2);
-                    g[2] = f * (1.0 + 2.0 * amp * p3 + aa * p3 * p3);
-                    g[3] = f * (amp * (p1 + p2) + aa * p1 * p2);
-                    g[4] = f * (amp * (p1 + p3) + aa * p1 * p3);
-                    g[5] = f * (amp * (p2 + p3) + aa * p2 * p3);
+                    p1 = a1 * sz;
+                    p2 = a2 * sz;
+                    p3 = a3 * cz;
+                    f = wxy * wz * recip_nr(1.0 + amp * (p1 + p2 + p3));
                 } else {
 #pragma unroll
                     for (int k = 0; k < 6; ++k) g[k] = gm[int64_t(qz) * 6 * Q * Q + k * Q * Q];
