@@ -946,22 +946,34 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
         for (int i = tid; i < n * B; i += 256) band[a][i] = src[i];
     }
     __syncthreads();
-    // z band: tile[r][x] = sum_k Kz(z, z+k) v[z+k][y0-W+r][x]
-    for (int i = tid; i < TR * nx; i += 256) {
-        const int r = i / nx, x = i % nx, y = y0 - W + r;
-        double s = 0.0;
-        if (y >= 0 && y < ny) {
+    // z band: tile[r][x] = sum_k Kz(z, z+k) v[z+k][y0-W+r][x]; every load of a
+    // thread is issued before the first is used
+    constexpr int SL = (TR * KMX_LINE_MAX + 255) / 256;
+    {
+        double vz[SL][B];
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+            const int i = tid + q * 256, r = i / nx, x = i % nx, y = y0 - W + r;
 #pragma unroll
             for (int k = 0; k < B; ++k) {
                 const int zz = z - W + k;
-                if (zz >= 0 && zz < nz) s += band[2][z * B + k] * v[(int64_t(zz) * ny + y) * nx + x];
+                vz[q][k] = (i < TR * nx && y >= 0 && y < ny && zz >= 0 && zz < nz)
+                               ? v[(int64_t(zz) * ny + y) * nx + x] : 0.0;
             }
         }
-        tile[r * KMX_LINE_MAX + x] = s;
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+            const int i = tid + q * 256;
+            if (i < TR * nx) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < B; ++k) s += band[2][z * B + k] * vz[q][k];
+                tile[(i / nx) * KMX_LINE_MAX + (i % nx)] = s;
+            }
+        }
     }
     __syncthreads();
     // x band, row by row (outputs to registers first: the rows are updated in place)
-    constexpr int SL = (TR * KMX_LINE_MAX + 255) / 256;
     double t[SL];
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
@@ -983,26 +995,45 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
         if (i < TR * nx) tile[(i / nx) * KMX_LINE_MAX + (i % nx)] = t[q];
     }
     __syncthreads();
-    // y band on the owned rows, then the dot products
+    // y band on the owned rows, then the dot products (partner loads first)
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int rows = ny - y0 < EROWS ? ny - y0 : EROWS;
-    for (int i = tid; i < rows * nx; i += 256) {
-        const int ry = i / nx, x = i % nx, y = y0 + ry;
-        double w = 0.0;
+    constexpr int SO = (EROWS * KMX_LINE_MAX + 255) / 256;
+    double pb[SO], pc[SO];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int yy = y - W + k;
-            if (yy >= 0 && yy < ny) w += band[1][y * B + k] * tile[(ry + k) * KMX_LINE_MAX + x];
+    for (int q = 0; q < SO; ++q) {
+        const int i = tid + q * 256;
+        pb[q] = pc[q] = 0.0;
+        if (i < rows * nx) {
+            const int y = y0 + i / nx, x = i % nx;
+            const int64_t at = (int64_t(z) * ny + y) * nx + x;
+            if (mode == 0) {
+                pb[q] = E[A.n_e + A.e_comp_off[c] + at];
+            } else {
+                const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+                pb[q] = H[A.n_h + A.h_comp_off[c] + at];
+                pc[q] = diff1(E + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
+                        diff1(E + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
+            }
         }
-        const int64_t at = (int64_t(z) * ny + y) * nx + x;
-        if (mode == 0) {
-            s0 += w * E[A.n_e + A.e_comp_off[c] + at];
-        } else {
-            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            const double cu = diff1(E + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
-                              diff1(E + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
-            s1 += w * H[A.n_h + A.h_comp_off[c] + at];
-            s2 += w * cu;
+    }
+#pragma unroll
+    for (int q = 0; q < SO; ++q) {
+        const int i = tid + q * 256;
+        if (i < rows * nx) {
+            const int ry = i / nx, x = i % nx, y = y0 + ry;
+            double w = 0.0;
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int yy = y - W + k;
+                if (yy >= 0 && yy < ny) w += band[1][y * B + k] * tile[(ry + k) * KMX_LINE_MAX + x];
+            }
+            if (mode == 0) {
+                s0 += w * pb[q];
+            } else {
+                s1 += w * pb[q];
+                s2 += w * pc[q];
+            }
         }
     }
     __shared__ double r[3];
@@ -1254,16 +1285,17 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) pair_grad_kernel(const PairGra
             for (int iq = 0; iq < NQ; ++iq) {
                 const int qz = le * NQ + iq;
                 double g[6];
-                // analytic metric: G = f (I + a (p 1^T + 1 p^T) + 3 a^2 p p^T) with p = grad s,
-                // applied below as a rank-2 update of the identity
-                double p1 = 0.0, p2 = 0.0, p3 = 0.0, f = 0.0;
                 if (MET == 1) {
                     const int gzq = tz * TILE * NQ + qz;
                     const double sz = A.axis_tab[gzq], cz = A.axis_tab[npq + gzq], wz = A.axis_tab[2 * npq + gzq];
-                    p1 = a1 * sz;
-                    p2 = a2 * sz;
-                    p3 = a3 * cz;
-                    f = wxy * wz * recip_nr(1.0 + amp * (p1 + p2 + p3));
+                    const double p1 = a1 * sz, p2 = a2 * sz, p3 = a3 * cz;
+                    const double f = wxy * wz * recip_nr(1.0 + amp * (p1 + p2 + p3));
+                    g[0] = f * (1.0 + 2.0 * amp * p1 + aa * p1 * p1);
+                    g[1] = f * (1.0 + 2.0 * amp * p2 + aa * p2 * p2);
+                    g[2] = f * (1.0 + 2.0 * amp * p3 + aa * p3 * p3);
+                    g[3] = f * (amp * (p1 + p2) + aa * p1 * p2);
+                    g[4] = f * (amp * (p1 + p3) + aa * p1 * p3);
+                    g[5] = f * (amp * (p2 + p3) + aa * p2 * p3);
                 } else {
 #pragma unroll
                     for (int k = 0; k < 6; ++k) g[k] = gm[int64_t(qz) * 6 * Q * Q + k * Q * Q];
