@@ -100,10 +100,26 @@ def cpu_baseline(p, N, steps, eps):
     t0 = time.perf_counter()
     S.step(e, h, 1e-3, nsteps=steps)
     dt = time.perf_counter() - t0
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            S.step(e, h, 1e-3, nsteps=2)
+            single = (S.n_e + S.n_h) * 2 / (time.perf_counter() - t1)
+    except Exception:
+        pass
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": (S.n_e + S.n_h) * steps / dt, "unit": "DOF-updates/s", "cores": int(cores),
             "kind": "oracle",
             "sample": f"{steps} FP64 oracle leapfrog steps of the same p={p}, {N}^3 deformed-cube workload "
-                      f"from a seeded random state ({dt:.1f} s of CPU work, set-up excluded)"}
+                      f"from a seeded random state ({dt:.1f} s of CPU work, set-up excluded)",
+            "value_single_thread": single, "host_cpu": model, "nproc": os.cpu_count()}
 
 
 def adjoint_timing(K, W, torch):
@@ -249,7 +265,7 @@ def batched_timing(K, W, torch, steps=400):
     out = {"workload": f"batched sources: p={p}, {N}^3, identity map, eps=mu=1, {B} Gaussian point dipoles "
                        f"(one per member), zero initial fields, dt=0.5 CFL, {steps} steps in one graph launch, FP64",
            "dofs_e_plus_h": dofs, "ms_per_step": ms / steps, "value": dofs * steps / (ms * 1e-3),
-           "unit": "DOF-updates/s", "plan": {"kind": ["tiled", "separable", "separable-fused"][plan[0]] if plan[0] >= 0 else "auto",
+           "unit": "DOF-updates/s", "plan": {"kind": K.PLAN_NAMES[plan[0]],
                                              "threads": plan[1]},
            "tuner_ms_per_step": dict(zip(K.TUNE_LABELS, tune_ms))}
     if plan[0] in (K.PLAN_SEPARABLE, K.PLAN_SEPARABLE_FUSED):
@@ -326,6 +342,10 @@ def main():
     log(f"dt = {dt:.6e}")
     flags = K.TRACK_DB
     G.init_stagger(E, H, dt, flags=flags)
+    # the library's tuner picks the plan (tiled with banded or dense solves here)
+    tune_ms = G.tune(1, dt, probe_steps=10)
+    plan = G.plan()
+    log(f"plan {K.PLAN_NAMES[plan[0]]}: {dict(zip(K.TUNE_LABELS, tune_ms))}")
     en_w = torch.zeros(max(args.warmup, 1), dtype=torch.float64, device=dev)
     en = torch.zeros(args.steps, dtype=torch.float64, device=dev)
     en_p = torch.zeros(args.steps, dtype=torch.float64, device=dev)
@@ -448,7 +468,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"scheme-2 leapfrog, deformed cube (a=0.08), p={p}, {N}^3 elements, "
                                f"eps~U[1,4], 10 cavity modes, dt=0.5 CFL, FP64, b/d tracking + energy",
-                   "dofs_e_plus_h": dofs, "dt": dt, "parallelism": "single GPU"},
+                   "dofs_e_plus_h": dofs, "dt": dt, "parallelism": "single GPU",
+                   "plan": K.PLAN_NAMES[plan[0]],
+                   "tuner_ms_per_step": {k: v for k, v in zip(K.TUNE_LABELS, tune_ms) if v is not None}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ms_per_step_plain": ms_plain,

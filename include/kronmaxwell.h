@@ -192,6 +192,10 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
  *                       product, update over all entries.
  *   KMX_PLAN_SEPARABLE_FUSED  the same operators with the curl fused into
  *                       the first (z) pass and the update into the last pass.
+ *   KMX_PLAN_TILED_DENSE  the tiled plan with the pairing solves applied as
+ *                       three FP64 mode products with the dense inverses of
+ *                       the 1D factors (computed once on the host in FP64) on
+ *                       the matrix cores, instead of banded substitutions.
  * KMX_PLAN_AUTO (the default) takes the separable plan when it applies and
  * batch >= 32, the tiled plan otherwise.  `threads` is the separable kernels'
  * workgroup size (64..768, multiple of 64).  Forcing a separable plan on a
@@ -201,18 +205,19 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
 #define KMX_PLAN_TILED 0
 #define KMX_PLAN_SEPARABLE 1
 #define KMX_PLAN_SEPARABLE_FUSED 2
+#define KMX_PLAN_TILED_DENSE 3
 kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads);
 kmx_status kmx_get_plan(const kmx_space* sp, int* kind, int* threads);
 
 /* Times the candidate plans on `batch` members (zero fields of its own, J
  * driving them if not NULL, time step dt) over probe_steps steps each after
  * one warm-up step, and keeps the fastest as the space's plan.  Candidates:
- * 0 tiled; 1..3 separable with 384, 512, 768 threads; 4..5 separable-fused
- * with 512, 768 threads.  ms_out:
+ * 0 tiled; 1 tiled-dense; 2..4 separable with 384, 512, 768 threads; 5..6
+ * separable-fused with 512, 768 threads.  ms_out:
  * NULL or host array of KMX_TUNE_CANDIDATES entries receiving the mean ms per
  * step (-1 where a candidate does not apply).  Allocates two fields of
  * working memory; synchronises. */
-#define KMX_TUNE_CANDIDATES 6
+#define KMX_TUNE_CANDIDATES 7
 kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source* J, double dt, double* ms_out,
                     void* stream);
 
@@ -310,8 +315,9 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
  *   6 patch gather (sum of the overlapping tile outputs of a mass apply)
  *   7 separable persistent kernel (one launch for all steps of a call)
  *   8 FP32 dense mode products of the mixed-precision solves
+ *   9 FP64 dense mode products of the tiled-dense plan (one span per solve)
  * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
-#define KMX_PROFILE_KINDS 9
+#define KMX_PROFILE_KINDS 10
 kmx_status kmx_profile_begin(kmx_space* sp, int capacity);
 kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches);
 

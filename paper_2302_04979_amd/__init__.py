@@ -23,10 +23,12 @@ LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
 TRACK_DB = 1
 STORED_METRIC = 16
 FP64, MIXED = 0, 1
-PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE, PLAN_SEPARABLE_FUSED = -1, 0, 1, 2
-TUNE_CANDIDATES = 6
-TUNE_LABELS = ("tiled", "separable/384", "separable/512", "separable/768", "separable-fused/512",
-               "separable-fused/768")
+PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE, PLAN_SEPARABLE_FUSED, PLAN_TILED_DENSE = -1, 0, 1, 2, 3
+TUNE_CANDIDATES = 7
+TUNE_LABELS = ("tiled", "tiled-dense", "separable/384", "separable/512", "separable/768",
+               "separable-fused/512", "separable-fused/768")
+PLAN_NAMES = {PLAN_AUTO: "auto", PLAN_TILED: "tiled", PLAN_SEPARABLE: "separable",
+              PLAN_SEPARABLE_FUSED: "separable-fused", PLAN_TILED_DENSE: "tiled-dense"}
 
 # every symbol declared in include/kronmaxwell.h
 EXPORTS = (
@@ -40,7 +42,7 @@ EXPORTS = (
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
-                 "mode_fp32")
+                 "mode_fp32", "mode_fp64")
 
 _STATUS = {0: "KMX_OK", 1: "KMX_E_ARG", 2: "KMX_E_GEOMETRY", 3: "KMX_E_MATERIAL", 4: "KMX_E_DEVICE",
            5: "KMX_E_OOM", 6: "KMX_E_UNSTABLE", 7: "KMX_E_STATE"}

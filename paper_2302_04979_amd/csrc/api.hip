@@ -61,7 +61,7 @@ void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
 
 // Kernel kinds reported by kmx_profile_end.
 enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6, PK_SEP = 7,
-       PK_MODE = 8 };
+       PK_MODE = 8, PK_MODE64 = 9 };
 
 struct ProfScope {  // brackets one launch with events when profiling is on
     kmx_space* sp;
@@ -436,6 +436,21 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             const int lmax = sep_line_max(std::max(sp->n0, sp->n1));
             if (lmax > 0 && shm <= size_t(sp->max_lds)) HIP_TRY(sep_prepare(p, lmax, shm));
         }
+        {
+            // dense FP64 inverses of G^, M^, G^T, M^T (row-major) for the
+            // tiled-dense plan
+            std::vector<double> inv;
+            for (int k = 0; k < 4; ++k) {
+                const int n = (k == F_G || k == F_GT) ? sp->n0 : sp->n1;
+                const std::vector<double>& A = (k == F_G || k == F_GT) ? sp->tb.G : sp->tb.M;
+                const std::vector<double> Ai = dense_inverse(A, n);
+                sp->inv64_off[k] = int64_t(inv.size());
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j)
+                        inv.push_back((k == F_GT || k == F_MT) ? Ai[size_t(j) * n + i] : Ai[size_t(i) * n + j]);
+            }
+            if ((st = upload(&sp->d_inv64, inv)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+        }
         if (prec == KMX_MIXED) {
             if (std::max(sp->n0, sp->n1) > mode_line_max()) {
                 kmx_destroy_space(sp);
@@ -549,7 +564,7 @@ void kmx_destroy_space(kmx_space* sp) {
                       sp->d_gram, sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
-    void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b};
+    void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_inv64};
     for (void* b : more)
         if (b) (void)hipFree(b);
     delete sp;
@@ -1103,6 +1118,29 @@ void mixed_solve(kmx_space* sp, int which_K1, int transpose, const double* y, do
     }
 }
 
+// out += alpha * K^{-1} y by three FP64 mode products with the dense inverse
+// factors on the matrix cores.  y: d_tmp2 layout (stride nfield); d_tmp2 and
+// d_tmp are overwritten.
+void dense_solve(kmx_space* sp, int which_K1, double* y, double* out, int64_t out_stride, double alpha, int batch,
+                 hipStream_t s) {
+    const int64_t nf = std::max(sp->n_e, sp->n_h);
+    ModeArgs m{};
+    space_dims(sp, which_K1 ? SP_D : SP_B, m.dims, m.comp_off);
+    m.A64 = sp->d_inv64;
+    ProfScope ps(sp, s, PK_MODE64);
+    for (int ax = 0; ax < 3; ++ax) {
+        for (int c = 0; c < 3; ++c) m.A_off[c] = sp->inv64_off[pair_fac(which_K1, 0, c, ax)];
+        m.axis = ax;
+        m.in = ax == 1 ? sp->d_tmp : y;
+        m.in_stride = nf;
+        m.out = ax == 0 ? sp->d_tmp : (ax == 1 ? y : out);
+        m.out_stride = ax == 2 ? out_stride : nf;
+        m.out_kind = ax == 2 ? 2 : 1;
+        m.alpha = alpha;
+        launch_mode64(m, batch, s);
+    }
+}
+
 // Whether the separable persistent kernel can run a step call: identity map,
 // eps and mu the same in every element, no per-step energy output, lines that
 // fit the kernel's registers and component tensors that fit one workgroup's LDS.
@@ -1183,12 +1221,16 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     }
     const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
     const bool mixed = sp->precision == KMX_MIXED;
+    const bool dense = kind == KMX_PLAN_TILED_DENSE;
     const int64_t nf = std::max(sp->n_e, sp->n_h);
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
         // M D^1 e (and b -= dt D^1 e), then h -= dt K~1^{-1} (.)
         run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -dt);
-        if (mixed) {
+        if (dense && !mixed) {
+            run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+            dense_solve(sp, 0, sp->d_tmp2, H, hs, -dt, batch, s);
+        } else if (mixed) {
             run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
             mixed_solve(sp, 0, 0, sp->d_my, H, hs, -dt, 1, batch, s);
         } else {
@@ -1196,7 +1238,14 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
         }
         // M~ D~^1 h (and d += dt D~^1 h), then e += dt K1^{-1} (. - s)
         run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, dt);
-        if (mixed) {
+        if (dense && !mixed) {
+            run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+            if (J)
+                launch_source_sub(sp->d_tmp2, nf, J->d_entries, J->d_prof,
+                                  reinterpret_cast<const int*>(J->d_prof + 4 * J->n), J->entries_per, J->d_comp_off,
+                                  J->d_dims, t_half, t_dev, batch, s);
+            dense_solve(sp, 1, sp->d_tmp2, E, es, dt, batch, s);
+        } else if (mixed) {
             run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev);
             mixed_solve(sp, 1, 0, sp->d_my, E, es, dt, 1, batch, s);
         } else {
@@ -1238,7 +1287,7 @@ kmx_status kmx_set_refinement(kmx_space* sp, int steps) {
 kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads) {
     if (!sp) return fail(KMX_E_ARG, "space is NULL");
     if (kind != KMX_PLAN_AUTO && kind != KMX_PLAN_TILED && kind != KMX_PLAN_SEPARABLE &&
-        kind != KMX_PLAN_SEPARABLE_FUSED)
+        kind != KMX_PLAN_SEPARABLE_FUSED && kind != KMX_PLAN_TILED_DENSE)
         return fail(KMX_E_ARG, "unknown plan kind");
     if (threads < 64 || threads > SEP_MAX_THREADS || threads % 64)
         return fail(KMX_E_ARG, "threads must be 64..768, a multiple of 64");
@@ -1259,10 +1308,10 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     if (!sp || batch < 1 || batch > sp->max_batch || probe_steps < 1) return fail(KMX_E_ARG, "bad argument");
     if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    static const int cand_kind[KMX_TUNE_CANDIDATES] = {KMX_PLAN_TILED,          KMX_PLAN_SEPARABLE,
-                                                       KMX_PLAN_SEPARABLE,      KMX_PLAN_SEPARABLE,
-                                                       KMX_PLAN_SEPARABLE_FUSED, KMX_PLAN_SEPARABLE_FUSED};
-    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 384, 512, 768, 512, 768};
+    static const int cand_kind[KMX_TUNE_CANDIDATES] = {
+        KMX_PLAN_TILED,     KMX_PLAN_TILED_DENSE, KMX_PLAN_SEPARABLE,      KMX_PLAN_SEPARABLE,
+        KMX_PLAN_SEPARABLE, KMX_PLAN_SEPARABLE_FUSED, KMX_PLAN_SEPARABLE_FUSED};
+    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 0, 384, 512, 768, 512, 768};
     const bool sep_ok = sep_eligible(sp, nullptr);
     double* E = nullptr;
     double* H = nullptr;
@@ -1281,9 +1330,9 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     (void)hipMemsetAsync(H, 0, size_t(batch) * sp->n_h * sizeof(double), s);
     for (int k = 0; k < KMX_TUNE_CANDIDATES && st == KMX_OK; ++k) {
         double ms = -1.0;
-        if (k == 0 || sep_ok) {
+        if (k < 2 || sep_ok) {
             sp->plan_kind = cand_kind[k];
-            sp->plan_threads = k == 0 ? saved_threads : cand_threads[k];
+            sp->plan_threads = k < 2 ? saved_threads : cand_threads[k];
             st = step_loop(sp, E, H, J, 0.0, nullptr, dt, 1, batch, 0, nullptr, s);  // warm-up
             if (st == KMX_OK) (void)hipEventRecord(ev[0], s);
             if (st == KMX_OK) st = step_loop(sp, E, H, J, 0.0, nullptr, dt, probe_steps, batch, 0, nullptr, s);
@@ -1312,7 +1361,7 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
         return st;
     }
     sp->plan_kind = cand_kind[best_k];
-    sp->plan_threads = best_k == 0 ? saved_threads : cand_threads[best_k];
+    sp->plan_threads = best_k < 2 ? saved_threads : cand_threads[best_k];
     return KMX_OK;
 }
 

@@ -166,12 +166,19 @@ struct ModeArgs {
     double alpha;
     int64_t comp_off[3];        // same layout for in and out
     int dims[3][3];             // [c][z, y, x]
-    const float* A;             // dense n x n factors, row-major
+    const float* A;             // dense n x n FP32 factors, row-major
+    const double* A64;          // dense n x n FP64 factors (launch_mode64)
     int64_t A_off[3];           // factor of each component along `axis`
     int axis;
 };
 int mode_line_max();
 void launch_mode(const ModeArgs& a, int batch, hipStream_t s);
+// FP64 mode product (in and out FP64; out_kind 1 store, 2 accumulate)
+void launch_mode64(const ModeArgs& a, int batch, hipStream_t s);
+// y -= g(t) s for the point sources of every batch member (device comp_off / dims)
+void launch_source_sub(double* y, int64_t y_stride, const double* entries, const double* prof, const int* off,
+                       int entries_per, const int64_t* comp_off_dev, const int* dims_dev, double t_src,
+                       const double* t_dev, int batch, hipStream_t s);
 void launch_strided_axpy(const double* x, int64_t xs, double* y, int64_t ys, int64_t n, double alpha, int batch,
                          hipStream_t s);
 
