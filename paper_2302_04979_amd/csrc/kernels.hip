@@ -306,11 +306,25 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
     }
 
     // ---- 1D tables of the tile: [axis][slot][element][point][function] ----
-    for (int i = tid; i < 6 * TSL; i += NT) {
-        const int a = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
-        const int tag = slot == 0 ? space_tag(SPACE, a, a) : space_tag(SPACE, (a + 1) % 3, a);
-        const int K = tag_support(P, tag);
-        if (k < TILE * NQ * K) sm[OT + i] = A.tab[A.tab_off[tag] + int64_t(tcoord[a]) * TILE * NQ * K + k];
+    {
+        constexpr int ST = (6 * TSL + NT - 1) / NT;
+        double r[ST];
+#pragma unroll
+        for (int q = 0; q < ST; ++q) {
+            const int i = tid + NT * q;
+            const int a = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
+            const int tag = slot == 0 ? space_tag(SPACE, a % 3, a % 3) : space_tag(SPACE, (a + 1) % 3, a % 3);
+            const int K = tag_support(P, tag);
+            r[q] = (i < 6 * TSL && k < TILE * NQ * K)
+                       ? A.tab[A.tab_off[tag] + int64_t(tcoord[a % 3]) * TILE * NQ * K + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < ST; ++q) {
+            const int i = tid + NT * q;
+            const int a = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
+            const int tag = slot == 0 ? space_tag(SPACE, a % 3, a % 3) : space_tag(SPACE, (a + 1) % 3, a % 3);
+            if (i < 6 * TSL && k < TILE * NQ * tag_support(P, tag)) sm[OT + i] = r[q];
+        }
     }
     // ---- input windows (curl fused) ----
     if (CURL) {
@@ -633,11 +647,24 @@ __device__ inline double band_row(const double* x, int n, int stride, const doub
     return s;
 }
 
+// One factor set [L | U | dinv | band] (2n(2W+1) doubles) into LDS by a
+// workgroup of 256 threads: every load of a thread is issued before its first
+// store (one memory latency instead of one per element).
 template <int W>
-__device__ inline void stage_factor(double* dst, const double* __restrict__ fac, int64_t off, int n, int tid,
-                                    int nt) {
+__device__ inline void stage_factor(double* dst, const double* __restrict__ fac, int64_t off, int n, int tid) {
+    constexpr int S = (FACTOR_MAX + 255) / 256;
     const int len = 2 * n * (2 * W + 1);
-    for (int i = tid; i < len; i += nt) dst[i] = fac[off + i];
+    double r[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        const int i = tid + 256 * q;
+        r[q] = i < len ? fac[off + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        const int i = tid + 256 * q;
+        if (i < len) dst[i] = r[q];
+    }
 }
 
 template <int P>
@@ -652,8 +679,8 @@ __global__ void __launch_bounds__(256) xy_kernel(const XYArgs A) {
     const int nxp = nx | 1;  // odd row stride: the lines along x hit distinct LDS banks
     const int tid = threadIdx.x;
     if (A.solve) {
-        stage_factor<W>(fx, A.fac, A.fac_off[A.fac_id[c][0]], nx, tid, 256);
-        stage_factor<W>(fy, A.fac, A.fac_off[A.fac_id[c][1]], ny, tid, 256);
+        stage_factor<W>(fx, A.fac, A.fac_off[A.fac_id[c][0]], nx, tid);
+        stage_factor<W>(fy, A.fac, A.fac_off[A.fac_id[c][1]], ny, tid);
     }
     {
         // stage the plane: rows over the 4 waves, x over the 64 lanes
@@ -773,7 +800,7 @@ __global__ void __launch_bounds__(256) z_kernel(const ZArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
     const int64_t colid = col0 + lane;
     const bool ok = colid < ncol;
-    if (A.solve) stage_factor<W>(f, A.fac, A.fac_off[A.fac_id[c]], nz, tid, 256);
+    if (A.solve) stage_factor<W>(f, A.fac, A.fac_off[A.fac_id[c]], nz, tid);
     const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c];
     double* out = A.out + int64_t(b) * A.out_stride + A.comp_off[c];
     {
@@ -939,11 +966,29 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
     const double* E = A.E + int64_t(bm) * 2 * A.n_e;
     const double* H = A.H + int64_t(bm) * 2 * A.n_h;
     const double* v = (mode == 0 ? E + A.e_comp_off[c] : H + A.h_comp_off[c]);
-    // bands of the three axes (the factor sets' stored matrix)
-    for (int a = 0; a < 3; ++a) {
-        const int n = d[2 - a];
-        const double* src = A.fac + A.fac_off[A.fac_id[mode][c][a]] + 2 * int64_t(n) * W + n;
-        for (int i = tid; i < n * B; i += 256) band[a][i] = src[i];
+    // bands of the three axes (the factor sets' stored matrix), all loads first
+    {
+        constexpr int SB = (KMX_LINE_MAX * B + 255) / 256;
+        double r[3][SB];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int n = d[2 - a];
+            const double* src = A.fac + A.fac_off[A.fac_id[mode][c][a]] + 2 * int64_t(n) * W + n;
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+                const int i = tid + 256 * q;
+                r[a][q] = i < n * B ? src[i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int n = d[2 - a];
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+                const int i = tid + 256 * q;
+                if (i < n * B) band[a][i] = r[a][q];
+            }
+        }
     }
     __syncthreads();
     // z band: tile[r][x] = sum_k Kz(z, z+k) v[z+k][y0-W+r][x]; every load of a
