@@ -38,7 +38,7 @@ def mass_flops(p, N, space):
     coefficient window and their transposes, and per Gauss point the z
     contraction, the z integral, and the metric applied as a rank-2 update of
     the identity (grad s, 1/det DF by a refined reciprocal, the two dot
-    products and the update: about 21 FMA-equivalents); times the tiles."""
+    products and the update: about 20 FMA-equivalents); times the tiles."""
     T, nq = 4, p + 1
     Q = T * nq
     K = {"Pv": p + 1, "Pd": p, "Dv": p, "Dd": p - 1}
@@ -51,7 +51,7 @@ def mass_flops(p, N, space):
         wx, wy, wz = (T + k - 1 for k in (kx, ky, kz))
         fma_xy += 2 * (wz * Q * wx * ky + wz * Q * Q * kx)  # forward and transposed
         kz_sum += kz
-    per_qp = 2 * kz_sum + 21
+    per_qp = 2 * kz_sum + 20
     tiles = ((N + T - 1) // T) ** 3
     return 2.0 * tiles * (fma_xy + per_qp * Q ** 3)
 

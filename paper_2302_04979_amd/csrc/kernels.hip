@@ -220,14 +220,14 @@ __device__ inline void integrate_xy(const double (&Rcol)[L::Wz], double* rb, dou
                                     bool active) {
     if (active) {
 #pragma unroll
-        for (int cz = 0; cz < L::Wz; ++cz) rb[(cz * Q + qy) * Q + qx] = Rcol[cz];
+        for (int cz = 0; cz < L::Wz; ++cz) rb[(cz * Q + qy) * (Q + 1) + qx] = Rcol[cz];
     }
     __syncthreads();
     // transposed x contraction: bb[cz][qy][lx]
     for (int i = tid; i < L::Wz * Q * L::Wx; i += NT) {
         const int cz = i / (Q * L::Wx), r = i % (Q * L::Wx);
         const int q = r / L::Wx, lx = r % L::Wx;
-        const double* row = rb + (cz * Q + q) * Q;
+        const double* row = rb + (cz * Q + q) * (Q + 1);  // odd pitch: rows spread over the banks
         double s = 0.0;
 #pragma unroll
         for (int j = 0; j < L::Kx; ++j) {
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
     constexpr int SW = CURL ? S0::size + S1::size + S2::size : 0;
     constexpr int XW = L0::size + L1::size + L2::size;
     constexpr int WZM = L0::Wz > L1::Wz ? (L0::Wz > L2::Wz ? L0::Wz : L2::Wz) : (L1::Wz > L2::Wz ? L1::Wz : L2::Wz);
-    constexpr int RB = WZM * Q * Q;
+    constexpr int RB = WZM * Q * (Q + 1);
     constexpr int R0 = (SW + XW) > RB ? (SW + XW) : RB;
     constexpr int BB0 = L0::Wz * Q * L0::Wx, BB1 = L1::Wz * Q * L1::Wx, BB2 = L2::Wz * Q * L2::Wx;
     constexpr int BB = BB0 > BB1 ? (BB0 > BB2 ? BB0 : BB2) : (BB1 > BB2 ? BB1 : BB2);
@@ -387,16 +387,16 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
         // analytic metric: per-thread factors of the (x, y) column
         const int64_t npq = int64_t(A.npad) * NQ;
         const int gxq = tx * TILE * NQ + qx, gyq = ty * TILE * NQ + qy;
+        // analytic metric, per (x, y) column: q = a grad s = (a1 s_z, a2 s_z, a3 c_z)
         double a1 = 0.0, a2 = 0.0, a3 = 0.0, wxy = 0.0;
         if (MET == 1) {
             const double sx = A.axis_tab[gxq], cx = A.axis_tab[npq + gxq], wx = A.axis_tab[2 * npq + gxq];
             const double sy = A.axis_tab[gyq], cy = A.axis_tab[npq + gyq], wy = A.axis_tab[2 * npq + gyq];
-            a1 = M_PI * cx * sy;
-            a2 = M_PI * sx * cy;
-            a3 = M_PI * sx * sy;
+            a1 = A.amp * M_PI * cx * sy;
+            a2 = A.amp * M_PI * sx * cy;
+            a3 = A.amp * M_PI * sx * sy;
             wxy = wx * wy;
         }
-        const double amp = A.amp, aa = 3.0 * A.amp * A.amp;
 #pragma unroll
         for (int le = 0; le < TILE; ++le) {
 #pragma unroll
@@ -408,16 +408,17 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
                     for (int k = 0; k < 6; ++k)
                         gn[k] = __builtin_nontemporal_load(gm + int64_t(qz + 1) * 6 * Q * Q + k * Q * Q);
                 }
-                // analytic metric: G = f (I + a (p 1^T + 1 p^T) + 3 a^2 p p^T) with p = grad s,
+                // analytic metric: with q = a grad s, DF = I + 1 q^T, det DF = 1 + q.1 and
+                // w DF^T DF / det DF = f (I + q 1^T + 1 q^T + 3 q q^T), f = w / det DF,
                 // applied below as a rank-2 update of the identity
-                double p1 = 0.0, p2 = 0.0, p3 = 0.0, f = 0.0;
+                double q1 = 0.0, q2 = 0.0, q3 = 0.0, f = 0.0;
                 if (MET == 1) {
                     const int gzq = tz * TILE * NQ + qz;
                     const double sz = A.axis_tab[gzq], cz = A.axis_tab[npq + gzq], wz = A.axis_tab[2 * npq + gzq];
-                    p1 = a1 * sz;
-                    p2 = a2 * sz;
-                    p3 = a3 * cz;
-                    f = wxy * wz * recip_nr(1.0 + amp * (p1 + p2 + p3));
+                    q1 = a1 * sz;
+                    q2 = a2 * sz;
+                    q3 = a3 * cz;
+                    f = wxy * wz * recip_nr(1.0 + (q1 + q2 + q3));
                 }
                 const double* t0 = tz0 + (le * NQ + iq) * L0::Kz;
                 const double* t2 = tz2 + (le * NQ + iq) * L2::Kz;
@@ -431,12 +432,12 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
                 const double s = ig[le];
                 double u0, u1, u2;
                 if (MET == 1) {
-                    // G v = f (v + (a S + 3 a^2 P) p + a P 1), S = sum v, P = p . v
-                    const double S = v0 + v1 + v2, Pv = p1 * v0 + p2 * v1 + p3 * v2;
-                    const double al = amp * S + aa * Pv, be = amp * Pv, sf = s * f;
-                    u0 = sf * (v0 + fma(al, p1, be));
-                    u1 = sf * (v1 + fma(al, p2, be));
-                    u2 = sf * (v2 + fma(al, p3, be));
+                    // G v = f (v + (S + 3 Q) q + Q 1), S = sum v, Q = q . v
+                    const double Qv = q1 * v0 + q2 * v1 + q3 * v2;
+                    const double cq = fma(3.0, Qv, v0 + v1 + v2), sf = s * f;
+                    u0 = sf * (v0 + fma(cq, q1, Qv));
+                    u1 = sf * (v1 + fma(cq, q2, Qv));
+                    u2 = sf * (v2 + fma(cq, q3, Qv));
                 } else {
                     u0 = s * (g[0] * v0 + g[3] * v1 + g[4] * v2);
                     u1 = s * (g[3] * v0 + g[1] * v1 + g[5] * v2);
