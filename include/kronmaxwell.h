@@ -192,6 +192,9 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
  *                       product, update over all entries.
  *   KMX_PLAN_SEPARABLE_FUSED  the same operators with the curl fused into
  *                       the first (z) pass and the update into the last pass.
+ *   KMX_PLAN_TILED_W4   the tiled plan with the mass kernel compiled for four
+ *                       resident waves per SIMD (registers capped at 128;
+ *                       p <= 3, otherwise as KMX_PLAN_TILED).
  *   KMX_PLAN_TILED_DENSE  the tiled plan with the pairing solves applied as
  *                       three FP64 mode products with the dense inverses of
  *                       the 1D factors (computed once on the host in FP64) on
@@ -206,18 +209,19 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
 #define KMX_PLAN_SEPARABLE 1
 #define KMX_PLAN_SEPARABLE_FUSED 2
 #define KMX_PLAN_TILED_DENSE 3
+#define KMX_PLAN_TILED_W4 4
 kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads);
 kmx_status kmx_get_plan(const kmx_space* sp, int* kind, int* threads);
 
 /* Times the candidate plans on `batch` members (zero fields of its own, J
  * driving them if not NULL, time step dt) over probe_steps steps each after
  * one warm-up step, and keeps the fastest as the space's plan.  Candidates:
- * 0 tiled; 1 tiled-dense; 2..4 separable with 384, 512, 768 threads; 5..6
- * separable-fused with 512, 768 threads.  ms_out:
+ * 0 tiled; 1 tiled-w4; 2 tiled-dense; 3..5 separable with 384, 512, 768
+ * threads; 6..7 separable-fused with 512, 768 threads.  ms_out:
  * NULL or host array of KMX_TUNE_CANDIDATES entries receiving the mean ms per
  * step (-1 where a candidate does not apply).  Allocates two fields of
  * working memory; synchronises. */
-#define KMX_TUNE_CANDIDATES 7
+#define KMX_TUNE_CANDIDATES 8
 kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source* J, double dt, double* ms_out,
                     void* stream);
 

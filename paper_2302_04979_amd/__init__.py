@@ -23,12 +23,12 @@ LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
 TRACK_DB = 1
 STORED_METRIC = 16
 FP64, MIXED = 0, 1
-PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE, PLAN_SEPARABLE_FUSED, PLAN_TILED_DENSE = -1, 0, 1, 2, 3
-TUNE_CANDIDATES = 7
-TUNE_LABELS = ("tiled", "tiled-dense", "separable/384", "separable/512", "separable/768",
+PLAN_AUTO, PLAN_TILED, PLAN_SEPARABLE, PLAN_SEPARABLE_FUSED, PLAN_TILED_DENSE, PLAN_TILED_W4 = -1, 0, 1, 2, 3, 4
+TUNE_CANDIDATES = 8
+TUNE_LABELS = ("tiled", "tiled-w4", "tiled-dense", "separable/384", "separable/512", "separable/768",
                "separable-fused/512", "separable-fused/768")
 PLAN_NAMES = {PLAN_AUTO: "auto", PLAN_TILED: "tiled", PLAN_SEPARABLE: "separable",
-              PLAN_SEPARABLE_FUSED: "separable-fused", PLAN_TILED_DENSE: "tiled-dense"}
+              PLAN_SEPARABLE_FUSED: "separable-fused", PLAN_TILED_DENSE: "tiled-dense", PLAN_TILED_W4: "tiled-w4"}
 
 # every symbol declared in include/kronmaxwell.h
 EXPORTS = (

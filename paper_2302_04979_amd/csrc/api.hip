@@ -106,6 +106,7 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
     const int src_space = curl ? (space == SP_B ? SP_E : SP_H) : space;
     space_dims(sp, src_space, a.src_dims, a.src_comp_off);
     patch_size(sp->p, space, sp->ntile, a.patch_comp_off);
+    a.waves4 = sp->mass_waves4;
     ProfScope ps(sp, s, space == SP_B ? PK_MASS_B : PK_MASS_D);
     launch_mass(sp->p, space, curl, a, batch, s);
 }
@@ -1222,6 +1223,7 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
     const bool mixed = sp->precision == KMX_MIXED;
     const bool dense = kind == KMX_PLAN_TILED_DENSE;
+    sp->mass_waves4 = kind == KMX_PLAN_TILED_W4 ? 1 : 0;
     const int64_t nf = std::max(sp->n_e, sp->n_h);
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
@@ -1287,7 +1289,7 @@ kmx_status kmx_set_refinement(kmx_space* sp, int steps) {
 kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads) {
     if (!sp) return fail(KMX_E_ARG, "space is NULL");
     if (kind != KMX_PLAN_AUTO && kind != KMX_PLAN_TILED && kind != KMX_PLAN_SEPARABLE &&
-        kind != KMX_PLAN_SEPARABLE_FUSED && kind != KMX_PLAN_TILED_DENSE)
+        kind != KMX_PLAN_SEPARABLE_FUSED && kind != KMX_PLAN_TILED_DENSE && kind != KMX_PLAN_TILED_W4)
         return fail(KMX_E_ARG, "unknown plan kind");
     if (threads < 64 || threads > SEP_MAX_THREADS || threads % 64)
         return fail(KMX_E_ARG, "threads must be 64..768, a multiple of 64");
@@ -1309,9 +1311,9 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on");
     hipStream_t s = static_cast<hipStream_t>(stream);
     static const int cand_kind[KMX_TUNE_CANDIDATES] = {
-        KMX_PLAN_TILED,     KMX_PLAN_TILED_DENSE, KMX_PLAN_SEPARABLE,      KMX_PLAN_SEPARABLE,
-        KMX_PLAN_SEPARABLE, KMX_PLAN_SEPARABLE_FUSED, KMX_PLAN_SEPARABLE_FUSED};
-    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 0, 384, 512, 768, 512, 768};
+        KMX_PLAN_TILED,     KMX_PLAN_TILED_W4,  KMX_PLAN_TILED_DENSE,     KMX_PLAN_SEPARABLE,
+        KMX_PLAN_SEPARABLE, KMX_PLAN_SEPARABLE, KMX_PLAN_SEPARABLE_FUSED, KMX_PLAN_SEPARABLE_FUSED};
+    static const int cand_threads[KMX_TUNE_CANDIDATES] = {0, 0, 0, 384, 512, 768, 512, 768};
     const bool sep_ok = sep_eligible(sp, nullptr);
     double* E = nullptr;
     double* H = nullptr;
@@ -1330,9 +1332,9 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     (void)hipMemsetAsync(H, 0, size_t(batch) * sp->n_h * sizeof(double), s);
     for (int k = 0; k < KMX_TUNE_CANDIDATES && st == KMX_OK; ++k) {
         double ms = -1.0;
-        if (k < 2 || sep_ok) {
+        if (k < 3 || sep_ok) {
             sp->plan_kind = cand_kind[k];
-            sp->plan_threads = k < 2 ? saved_threads : cand_threads[k];
+            sp->plan_threads = k < 3 ? saved_threads : cand_threads[k];
             st = step_loop(sp, E, H, J, 0.0, nullptr, dt, 1, batch, 0, nullptr, s);  // warm-up
             if (st == KMX_OK) (void)hipEventRecord(ev[0], s);
             if (st == KMX_OK) st = step_loop(sp, E, H, J, 0.0, nullptr, dt, probe_steps, batch, 0, nullptr, s);
@@ -1361,7 +1363,7 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
         return st;
     }
     sp->plan_kind = cand_kind[best_k];
-    sp->plan_threads = best_k < 2 ? saved_threads : cand_threads[best_k];
+    sp->plan_threads = best_k < 3 ? saved_threads : cand_threads[best_k];
     return KMX_OK;
 }
 

@@ -261,8 +261,11 @@ __device__ inline void integrate_xy(const double (&Rcol)[L::Wz], double* rb, dou
 // with s = sin(pi x) sin(pi y) sin(pi z) (a = 0: identity), from per-axis
 // tables of sin, cos and weights: DF = I + a (1,1,1)^T grad(s)^T gives
 // det DF = 1 + a (g1 + g2 + g3) and (DF^T DF)_ij = d_ij + a (g_i + g_j) + 3 a^2 g_i g_j.
-template <int P, int SPACE, bool CURL, int MET>
-__global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) {
+// WPE: minimum waves per SIMD the compiler must allow (1: its own choice; 4:
+// registers capped at 128 for a fourth resident workgroup per CU).
+template <int P, int SPACE, bool CURL, int MET, int WPE>
+__global__ void __launch_bounds__(MassCfg<P>::NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+mass_kernel(const MassArgs A) {
     constexpr int NQ = P + 1, Q = TILE * NQ, NT = MassCfg<P>::NT;
     constexpr int SRC = CURL ? (SPACE == SP_B ? SP_E : SP_H) : SPACE;
     using L0 = Lay<P, SPACE, 0>;
@@ -472,10 +475,15 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) mass_kernel(const MassArgs A) 
 
 template <int P, int SPACE, bool CURL>
 static void launch_mass_t(const MassArgs& a, dim3 grid, hipStream_t s) {
-    if (a.metric_mode == 1)
-        hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+    // the four-wave variant exists for p <= 3 (p = 4 would spill)
+    const bool w4 = a.waves4 && P <= 3;
+    if (a.metric_mode == 1) {
+        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+    } else {
+        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+    }
 }
 
 void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipStream_t s) {

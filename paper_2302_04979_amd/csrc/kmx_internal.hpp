@@ -138,6 +138,7 @@ struct kmx_space {
     int max_lds = 0;                   // device limit of LDS bytes per workgroup
     int plan_kind = -1;                // -1 automatic, KMX_PLAN_TILED, KMX_PLAN_SEPARABLE
     int plan_threads = 768;            // workgroup size of the separable kernel
+    int mass_waves4 = 0;               // tiled plans: mass kernel variant for four waves per SIMD
     // mixed-precision solves (precision & KMX_MIXED): dense FP32 inverses of
     // the four 1D pairing factors and working fields
     float* d_inv32 = nullptr;          // [G^-1 | M^-1 | G^-T | M^-T], row-major

@@ -1,5 +1,5 @@
-"""Tiled plan with dense FP64 mode-product solves (matrix cores) against the
-FP64 oracle and against the banded solves."""
+"""Tiled plan variants: dense FP64 mode-product solves (matrix cores) and the
+four-wave mass kernel, against the FP64 oracle and the default tiled plan."""
 import math
 
 import numpy as np
@@ -26,7 +26,7 @@ def test_dense_plan_matches_oracle(p, N):
     E0 = W.random_vector(2 * S.n_e, 71) * 0.1
     H0 = W.random_vector(2 * S.n_h, 72) * 0.1
     out = {}
-    for plan in (K.PLAN_TILED_DENSE, K.PLAN_TILED):
+    for plan in (K.PLAN_TILED_DENSE, K.PLAN_TILED, K.PLAN_TILED_W4):
         G.set_plan(plan)
         E, H = to_dev(E0), to_dev(H0)
         G.step(E, H, dt, nsteps=nsteps, J=J, t_start=0.02, batch=2)
@@ -40,6 +40,9 @@ def test_dense_plan_matches_oracle(p, N):
         assert rel(Ed[k * S.n_e:(k + 1) * S.n_e], e) < 1e-12
         assert rel(Hd[k * S.n_h:(k + 1) * S.n_h], h) < 1e-12
     assert rel(Ed, out[K.PLAN_TILED][0]) < 1e-13 and rel(Hd, out[K.PLAN_TILED][1]) < 1e-13
+    # the four-wave mass kernel variant performs the same operations: same bits
+    assert np.array_equal(out[K.PLAN_TILED_W4][0], out[K.PLAN_TILED][0])
+    assert np.array_equal(out[K.PLAN_TILED_W4][1], out[K.PLAN_TILED][1])
 
 
 def test_dense_plan_tracking_and_energy():
