@@ -38,31 +38,55 @@ __device__ inline void diff_pair(const double* u, const int d[3], int primal, in
     }
 }
 
+// Position (x, y, z) of the thread's m-th entry tid + m * nthr of a [z][y][x]
+// grid, advanced by carries instead of integer divisions (which the GPU
+// emulates in software) per entry.
+struct GridWalk {
+    int x, y, z, dx, dy, dz, nx, ny;
+    __device__ GridWalk(int tid, int nthr, int nx_, int ny_) : nx(nx_), ny(ny_) {
+        x = tid % nx;
+        y = (tid / nx) % ny;
+        z = tid / (nx * ny);
+        dx = nthr % nx;
+        dy = (nthr / nx) % ny;
+        dz = nthr / (nx * ny);
+    }
+    __device__ void next() {
+        x += dx;
+        const int cx = x >= nx;
+        x -= cx ? nx : 0;
+        y += dy + cx;
+        const int cy = y >= ny;
+        y -= cy ? ny : 0;
+        z += dz + cy;
+    }
+};
+
 // Curl of component c of the 1-form `src` (primal or dual) into the LDS
 // tensor of the 2-form grid od, with the optional tracking update
-// trk += talpha * curl.  U elements per thread are loaded before any is used,
+// trk += talpha * curl.  U entries per thread are loaded before any is used,
 // so that each thread keeps several global loads in flight.
 template <int U>
 __device__ inline void curl_to_lds(double* buf, const double* src, const int64_t soff[3], const int sdims[3][3],
                                    int primal, int c, const int od[3], double* trk, double talpha, int tid,
                                    int nthr) {
-    const int ny = od[1], nx = od[2], pitch = nx | 1, cnt = od[0] * ny * nx;
+    const int nz = od[0], ny = od[1], nx = od[2], pitch = nx | 1;
     const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-    for (int i0 = tid; i0 < cnt; i0 += U * nthr) {
+    GridWalk g(tid, nthr, nx, ny);
+    for (int i0 = tid; i0 < nz * ny * nx; i0 += U * nthr) {
         double p0[U], p1[U], q0[U], q1[U], tv[U];
         int li[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nthr;
             li[u] = -1;
             p0[u] = p1[u] = q0[u] = q1[u] = tv[u] = 0.0;
-            if (i < cnt) {
-                const int x = i % nx, q = i / nx, y = q % ny, z = q / ny;
-                li[u] = q * pitch + x;
-                diff_pair(src + soff[a2], sdims[a2], primal, a1, z, y, x, p0[u], p1[u]);
-                diff_pair(src + soff[a1], sdims[a1], primal, a2, z, y, x, q0[u], q1[u]);
-                if (trk) tv[u] = trk[i];
+            if (g.z < nz) {
+                li[u] = (g.z * ny + g.y) * pitch + g.x;
+                diff_pair(src + soff[a2], sdims[a2], primal, a1, g.z, g.y, g.x, p0[u], p1[u]);
+                diff_pair(src + soff[a1], sdims[a1], primal, a2, g.z, g.y, g.x, q0[u], q1[u]);
+                if (trk) tv[u] = trk[i0 + u * nthr];
             }
+            g.next();
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -75,22 +99,26 @@ __device__ inline void curl_to_lds(double* buf, const double* src, const int64_t
     }
 }
 
-// dst += alpha * (LDS tensor), U elements per thread in flight.
+// dst += alpha * (LDS tensor), U entries per thread in flight.
 template <int U>
 __device__ inline void update_from_lds(double* dst, const double* buf, const int od[3], double alpha, int tid,
                                        int nthr) {
-    const int nx = od[2], pitch = nx | 1, cnt = od[0] * od[1] * nx;
+    const int nx = od[2], pitch = nx | 1, rows = od[0] * od[1], cnt = rows * nx;
+    GridWalk g(tid, nthr, nx, rows);  // (x, row) walk; z stays 0
     for (int i0 = tid; i0 < cnt; i0 += U * nthr) {
         double v[U];
+        int li[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u * nthr;
-            v[u] = i < cnt ? dst[i] : 0.0;
+            li[u] = g.z == 0 ? g.y * pitch + g.x : -1;
+            v[u] = (i < cnt) ? dst[i] : 0.0;
+            g.next();
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u * nthr;
-            if (i < cnt) dst[i] = v[u] + alpha * buf[(i / nx) * pitch + (i % nx)];
+            if (i < cnt) dst[i] = v[u] + alpha * buf[li[u]];
         }
     }
 }
