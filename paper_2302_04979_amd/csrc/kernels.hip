@@ -538,16 +538,36 @@ __device__ inline double gather_one(const double* __restrict__ patch, int nt, in
     return s;
 }
 
+// q = n / d and r = n % d for 0 <= n < 2^24, d > 0, without the software
+// integer division: the hardware reciprocal, refined by one Newton step, gives
+// a quotient that is off by at most one, which one comparison corrects.
+__device__ inline int fast_divmod(int n, int d, int& r) {
+    const double dd = double(d);
+    double inv = __builtin_amdgcn_rcp(dd);
+    inv = fma(inv, fma(-dd, inv, 1.0), inv);
+    int q = int(double(n) * inv);
+    r = n - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    return q;
+}
+
 template <int P, int SPACE>
 __global__ void __launch_bounds__(256) gather_kernel(const GatherArgs A, int64_t n) {
     const int b = blockIdx.y;
-    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int i = blockIdx.x * 256 + threadIdx.x;  // fields hold fewer than 2^24 entries
     if (i >= n) return;
     const int c = i >= A.comp_off[2] ? 2 : (i >= A.comp_off[1] ? 1 : 0);
-    const int64_t li = i - A.comp_off[c];
+    const int li = i - int(A.comp_off[c]);
     const int nx = A.dims[c][2], ny = A.dims[c][1];
-    const int64_t row = li / nx;
-    const int x = int(li - row * nx), y = int(row % ny), z = int(row / ny);
+    int x, y;
+    const int row = fast_divmod(li, nx, x);
+    const int z = fast_divmod(row, ny, y);
     const double* patch = A.patch + int64_t(b) * A.patch_stride + A.patch_comp_off[c];
     double v;
     if (c == 0) v = gather_one<P, SPACE, 0>(patch, A.ntile, z, y, x);
@@ -947,27 +967,21 @@ __device__ inline void block_sum3(double v0, double v1, double v2, double* out) 
         for (int k = 0; k < 3; ++k) out[k] = s[k][0];
 }
 
-// Fused energy terms: one workgroup per (component, block of EROWS rows,
-// chunk of EZ planes) forms w = K v on its rows and planes (K1 e for the first
-// term, K~1 h for the other two) by the Kronecker structure, walking the input
-// planes of the chunk (plus W on each side) once: each input plane is staged
-// with its y halo, banded along x and y in LDS into a ring of 2W+1 planes, and
-// every output plane is the z band of the ring.  The next input plane and the
-// dot partners (d for the first term, b and D^1 e for the others) are loaded
-// into registers while the current plane is processed.  Blocks [0, nb0) do the
-// first term, [nb0, nb0 + nb1) the others; each writes its three partial sums
-// (zeros for terms it does not own) for the fixed-order final sum.
+// Fused energy terms: one workgroup per (component, z plane, block of EROWS
+// rows) forms w = K v on its rows (K1 e for the first term, K~1 h for the
+// other two) by the Kronecker structure: the z band combines 2W+1 planes,
+// then the x and y bands run in LDS; the dot products with d (first term), b
+// and D^1 e (second and third) follow in the same pass.  Blocks [0, nb0) do
+// the first term, [nb0, nb0 + nb1) the others; each writes its three partial
+// sums (zeros for terms it does not own) for the fixed-order final sum.
 constexpr int EROWS = 16;
-constexpr int EZ = 8;
 
 template <int P>
 __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs A) {
     constexpr int W = P - 1, B = 2 * W + 1;
     constexpr int TR = EROWS + 2 * W;  // staged rows (with the y halo)
-    constexpr int LM = KMX_LINE_MAX;
-    __shared__ double tile[TR * LM];
-    __shared__ double ring[B][EROWS * LM];
-    __shared__ double band[3][LM * B];
+    __shared__ double tile[TR * KMX_LINE_MAX];
+    __shared__ double band[3][KMX_LINE_MAX * B];
     const int tid = threadIdx.x, bm = blockIdx.y;
     const int blk = blockIdx.x;
     const int mode = blk < A.nb[0] ? 0 : 1;
@@ -977,15 +991,13 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
     const int* d = mode == 0 ? A.e_dims[c] : A.h_dims[c];
     const int nz = d[0], ny = d[1], nx = d[2];
     const int nyb = (ny + EROWS - 1) / EROWS;
-    const int z0 = (rem / nyb) * EZ, y0 = (rem % nyb) * EROWS;
-    const int rows = ny - y0 < EROWS ? ny - y0 : EROWS;
+    const int z = rem / nyb, y0 = (rem % nyb) * EROWS;
     const double* E = A.E + int64_t(bm) * 2 * A.n_e;
     const double* H = A.H + int64_t(bm) * 2 * A.n_h;
     const double* v = (mode == 0 ? E + A.e_comp_off[c] : H + A.h_comp_off[c]);
-    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
     // bands of the three axes (the factor sets' stored matrix), all loads first
     {
-        constexpr int SB = (LM * B + 255) / 256;
+        constexpr int SB = (KMX_LINE_MAX * B + 255) / 256;
         double r[3][SB];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1007,118 +1019,94 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
             }
         }
     }
-    constexpr int SL = (TR * LM + 255) / 256;      // staged entries per thread
-    constexpr int SO = (EROWS * LM + 255) / 256;   // owned entries per thread
-    // the (row, x) of every entry a thread handles, computed once (the integer
-    // divisions would otherwise be repeated for every plane)
-    int sr[SL], sx[SL], orow[SO], ox[SO];
+    __syncthreads();
+    // z band: tile[r][x] = sum_k Kz(z, z+k) v[z+k][y0-W+r][x]; every load of a
+    // thread is issued before the first is used
+    constexpr int SL = (TR * KMX_LINE_MAX + 255) / 256;
+    {
+        double vz[SL][B];
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+            const int i = tid + q * 256, r = i / nx, x = i % nx, y = y0 - W + r;
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int zz = z - W + k;
+                vz[q][k] = (i < TR * nx && y >= 0 && y < ny && zz >= 0 && zz < nz)
+                               ? v[(int64_t(zz) * ny + y) * nx + x] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+            const int i = tid + q * 256;
+            if (i < TR * nx) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < B; ++k) s += band[2][z * B + k] * vz[q][k];
+                tile[(i / nx) * KMX_LINE_MAX + (i % nx)] = s;
+            }
+        }
+    }
+    __syncthreads();
+    // x band, row by row (outputs to registers first: the rows are updated in place)
+    double t[SL];
 #pragma unroll
     for (int q = 0; q < SL; ++q) {
         const int i = tid + q * 256;
-        sr[q] = i < TR * nx ? i / nx : -1;
-        sx[q] = i % nx;
+        t[q] = 0.0;
+        if (i < TR * nx) {
+            const int r = i / nx, x = i % nx;
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int xx = x - W + k;
+                if (xx >= 0 && xx < nx) t[q] += band[0][x * B + k] * tile[r * KMX_LINE_MAX + xx];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+        const int i = tid + q * 256;
+        if (i < TR * nx) tile[(i / nx) * KMX_LINE_MAX + (i % nx)] = t[q];
+    }
+    __syncthreads();
+    // y band on the owned rows, then the dot products (partner loads first)
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const int rows = ny - y0 < EROWS ? ny - y0 : EROWS;
+    constexpr int SO = (EROWS * KMX_LINE_MAX + 255) / 256;
+    double pb[SO], pc[SO];
+#pragma unroll
+    for (int q = 0; q < SO; ++q) {
+        const int i = tid + q * 256;
+        pb[q] = pc[q] = 0.0;
+        if (i < rows * nx) {
+            const int y = y0 + i / nx, x = i % nx;
+            const int64_t at = (int64_t(z) * ny + y) * nx + x;
+            if (mode == 0) {
+                pb[q] = E[A.n_e + A.e_comp_off[c] + at];
+            } else {
+                const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+                pb[q] = H[A.n_h + A.h_comp_off[c] + at];
+                pc[q] = diff1(E + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
+                        diff1(E + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
+            }
+        }
     }
 #pragma unroll
     for (int q = 0; q < SO; ++q) {
         const int i = tid + q * 256;
-        orow[q] = i < rows * nx ? i / nx : -1;
-        ox[q] = i % nx;
-    }
-    // loads of input plane zi (zero outside the tensor)
-    auto load_plane = [&](int zi, double (&pf)[SL]) {
+        if (i < rows * nx) {
+            const int ry = i / nx, x = i % nx, y = y0 + ry;
+            double w = 0.0;
 #pragma unroll
-        for (int q = 0; q < SL; ++q) {
-            const int y = y0 - W + sr[q];
-            pf[q] = (sr[q] >= 0 && zi >= 0 && zi < nz && y >= 0 && y < ny) ? v[(int64_t(zi) * ny + y) * nx + sx[q]]
-                                                                            : 0.0;
-        }
-    };
-    // dot partners of output plane zo
-    auto load_partners = [&](int zo, double (&pb)[SO], double (&pc)[SO]) {
-#pragma unroll
-        for (int q = 0; q < SO; ++q) {
-            pb[q] = pc[q] = 0.0;
-            if (orow[q] >= 0 && zo >= 0 && zo < nz) {
-                const int y = y0 + orow[q], x = ox[q];
-                const int64_t at = (int64_t(zo) * ny + y) * nx + x;
-                if (mode == 0) {
-                    pb[q] = E[A.n_e + A.e_comp_off[c] + at];
-                } else {
-                    pb[q] = H[A.n_h + A.h_comp_off[c] + at];
-                    pc[q] = diff1(E + A.e_comp_off[a2], A.e_dims[a2], 1, a1, zo, y, x) -
-                            diff1(E + A.e_comp_off[a1], A.e_dims[a1], 1, a2, zo, y, x);
-                }
+            for (int k = 0; k < B; ++k) {
+                const int yy = y - W + k;
+                if (yy >= 0 && yy < ny) w += band[1][y * B + k] * tile[(ry + k) * KMX_LINE_MAX + x];
             }
-        }
-    };
-    double pf[SL], pb[SO], pc[SO];
-    load_plane(z0 - W, pf);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    const int zend = z0 + EZ + W;  // one past the last input plane
-    for (int zi = z0 - W; zi < zend; ++zi) {
-        // stage the plane, then start the loads of the next plane and of the
-        // partners of the output plane finished in this iteration
-#pragma unroll
-        for (int q = 0; q < SL; ++q)
-            if (sr[q] >= 0) tile[sr[q] * LM + sx[q]] = pf[q];
-        const int zo = zi - W;
-        const bool emit = zo >= z0 && zo < nz;
-        if (zi + 1 < zend) load_plane(zi + 1, pf);
-        if (emit) load_partners(zo, pb, pc);
-        __syncthreads();
-        // x band, row by row (outputs to registers first: the rows are updated in place)
-        double t[SL];
-#pragma unroll
-        for (int q = 0; q < SL; ++q) {
-            t[q] = 0.0;
-            if (sr[q] >= 0) {
-#pragma unroll
-                for (int k = 0; k < B; ++k) {
-                    const int xx = sx[q] - W + k;
-                    if (xx >= 0 && xx < nx) t[q] += band[0][sx[q] * B + k] * tile[sr[q] * LM + xx];
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < SL; ++q)
-            if (sr[q] >= 0) tile[sr[q] * LM + sx[q]] = t[q];
-        __syncthreads();
-        // y band of the owned rows into the ring slot of this plane
-        double* slot = ring[((zi % B) + B) % B];
-#pragma unroll
-        for (int q = 0; q < SO; ++q) {
-            if (orow[q] >= 0) {
-                const int ry = orow[q], x = ox[q], y = y0 + ry;
-                double w = 0.0;
-#pragma unroll
-                for (int k = 0; k < B; ++k) {
-                    const int yy = y - W + k;
-                    if (yy >= 0 && yy < ny) w += band[1][y * B + k] * tile[(ry + k) * LM + x];
-                }
-                slot[ry * LM + x] = w;
-            }
-        }
-        __syncthreads();
-        // z band of the ring for output plane zo, and the dot products
-        if (emit) {
-#pragma unroll
-            for (int q = 0; q < SO; ++q) {
-                if (orow[q] >= 0) {
-                    const int at = orow[q] * LM + ox[q];
-                    double w = 0.0;
-#pragma unroll
-                    for (int k = 0; k < B; ++k) {
-                        const int zz = zo - W + k;
-                        if (zz >= 0 && zz < nz) w += band[2][zo * B + k] * ring[((zz % B) + B) % B][at];
-                    }
-                    if (mode == 0) {
-                        s0 += w * pb[q];
-                    } else {
-                        s1 += w * pb[q];
-                        s2 += w * pc[q];
-                    }
-                }
+            if (mode == 0) {
+                s0 += w * pb[q];
+            } else {
+                s1 += w * pb[q];
+                s2 += w * pc[q];
             }
         }
     }
@@ -1146,7 +1134,7 @@ void launch_energy_fused(int p, const EnergyFusedArgs& a, int batch, hipStream_t
 int energy_fused_blocks(const int dims[3][3], int cb[3]) {
     int tot = 0;
     for (int c = 0; c < 3; ++c) {
-        cb[c] = ((dims[c][0] + EZ - 1) / EZ) * ((dims[c][1] + EROWS - 1) / EROWS);
+        cb[c] = dims[c][0] * ((dims[c][1] + EROWS - 1) / EROWS);
         tot += cb[c];
     }
     return tot;
