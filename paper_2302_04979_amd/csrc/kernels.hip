@@ -601,40 +601,65 @@ void launch_gather(int p, int space, const GatherArgs& a, int64_t n, int batch, 
 constexpr int KMX_LINE_MAX = 76;
 constexpr int FACTOR_MAX = 2 * KMX_LINE_MAX * 7;
 
-// Forward/backward substitution of one line held in registers (n <= LMAX):
-// the line is read from LDS once, the chain runs in registers with the factor
-// coefficients read as uniform (scalar) loads, and each step puts one FMA
-// (forward) or one FMA and one multiply (backward) on the dependency chain:
-// the terms of the older entries are subtracted first.
-template <int W, int LMAX>
-__device__ inline void band_solve_regs(double* v, int n, int stride, const double* __restrict__ L,
+// Forward/backward substitution along one line.  The dependency chain runs
+// through registers only: the line values and factor coefficients of a block
+// of D steps are loaded together (one wait per block), then the D steps of the
+// chain run without touching memory except for the stores.
+template <int W>
+__device__ inline void band_solve_line(double* v, int n, int stride, const double* __restrict__ L,
                                        const double* __restrict__ U, const double* __restrict__ dinv) {
-    double r[LMAX];
+    constexpr int D = 8;
+    double prev[W];
 #pragma unroll
-    for (int i = 0; i < LMAX; ++i) r[i] = i < n ? v[i * stride] : 0.0;
+    for (int m = 0; m < W; ++m) prev[m] = 0.0;
+    for (int i0 = 0; i0 < n; i0 += D) {
+        double xv[D], lc[D][W];
 #pragma unroll
-    for (int i = 1; i < LMAX; ++i) {
-        if (i < n) {
-            double s = r[i];
+        for (int k = 0; k < D; ++k) {
+            const int i = i0 + k < n ? i0 + k : n - 1;
+            xv[k] = v[i * stride];
 #pragma unroll
-            for (int m = W - 1; m >= 0; --m)
-                if (i - 1 - m >= 0) s -= L[i * W + m] * r[i - 1 - m];
-            r[i] = s;
+            for (int m = 0; m < W; ++m) lc[k][m] = L[i * W + m];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (i0 + k < n) {
+                double s = xv[k];
+#pragma unroll
+                for (int m = 0; m < W; ++m) s -= lc[k][m] * prev[m];
+#pragma unroll
+                for (int m = W - 1; m > 0; --m) prev[m] = prev[m - 1];
+                prev[0] = s;
+                v[(i0 + k) * stride] = s;
+            }
         }
     }
 #pragma unroll
-    for (int i = LMAX - 1; i >= 0; --i) {
-        if (i < n) {
-            double s = r[i];
+    for (int m = 0; m < W; ++m) prev[m] = 0.0;
+    for (int i0 = n - 1; i0 >= 0; i0 -= D) {
+        double xv[D], uc[D][W], dc[D];
 #pragma unroll
-            for (int m = W - 1; m >= 0; --m)
-                if (i + 1 + m < LMAX) s -= U[i * W + m] * r[i + 1 + m];
-            r[i] = s * dinv[i];
+        for (int k = 0; k < D; ++k) {
+            const int i = i0 - k >= 0 ? i0 - k : 0;
+            xv[k] = v[i * stride];
+            dc[k] = dinv[i];
+#pragma unroll
+            for (int m = 0; m < W; ++m) uc[k][m] = U[i * W + m];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (i0 - k >= 0) {
+                double s = xv[k];
+#pragma unroll
+                for (int m = 0; m < W; ++m) s -= uc[k][m] * prev[m];
+                s *= dc[k];
+#pragma unroll
+                for (int m = W - 1; m > 0; --m) prev[m] = prev[m - 1];
+                prev[0] = s;
+                v[(i0 - k) * stride] = s;
+            }
         }
     }
-#pragma unroll
-    for (int i = 0; i < LMAX; ++i)
-        if (i < n) v[i * stride] = r[i];
 }
 
 // banded product of one output: sum_k band[i][k] x_{i-W+k} (the band holds
@@ -682,7 +707,7 @@ __global__ void __launch_bounds__(256) xy_kernel(const XYArgs A) {
     if (iz >= nz) return;
     const int nxp = nx | 1;  // odd row stride: the lines along x hit distinct LDS banks
     const int tid = threadIdx.x;
-    if (A.solve == 2) {
+    if (A.solve) {
         stage_factor<W>(fx, A.fac, A.fac_off[A.fac_id[c][0]], nx, tid);
         stage_factor<W>(fy, A.fac, A.fac_off[A.fac_id[c][1]], ny, tid);
     }
@@ -723,13 +748,9 @@ __global__ void __launch_bounds__(256) xy_kernel(const XYArgs A) {
         __syncthreads();
     }
     if (A.solve == 1) {
-        const double* gx = A.fac + A.fac_off[A.fac_id[c][0]];
-        const double* gy = A.fac + A.fac_off[A.fac_id[c][1]];
-        for (int y = tid; y < ny; y += 256)
-            band_solve_regs<W, KMX_LINE_MAX>(plane + y * nxp, nx, 1, gx, gx + nx * W, gx + 2 * nx * W);
+        for (int y = tid; y < ny; y += 256) band_solve_line<W>(plane + y * nxp, nx, 1, fx, fx + nx * W, fx + 2 * nx * W);
         __syncthreads();
-        for (int x = tid; x < nx; x += 256)
-            band_solve_regs<W, KMX_LINE_MAX>(plane + x, ny, nxp, gy, gy + ny * W, gy + 2 * ny * W);
+        for (int x = tid; x < nx; x += 256) band_solve_line<W>(plane + x, ny, nxp, fy, fy + ny * W, fy + 2 * ny * W);
         __syncthreads();
     } else if (A.solve == 2) {
         // every output of a banded product is independent: compute all of a
@@ -808,7 +829,7 @@ __global__ void __launch_bounds__(256) z_kernel(const ZArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
     const int64_t colid = col0 + lane;
     const bool ok = colid < ncol;
-    if (A.solve == 2) stage_factor<W>(f, A.fac, A.fac_off[A.fac_id[c]], nz, tid);
+    if (A.solve) stage_factor<W>(f, A.fac, A.fac_off[A.fac_id[c]], nz, tid);
     const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c];
     double* out = A.out + int64_t(b) * A.out_stride + A.comp_off[c];
     {
@@ -826,8 +847,7 @@ __global__ void __launch_bounds__(256) z_kernel(const ZArgs A) {
     }
     __syncthreads();
     if (A.solve == 1) {
-        const double* g = A.fac + A.fac_off[A.fac_id[c]];
-        if (grp == 0) band_solve_regs<W, KMX_LINE_MAX>(col + lane, nz, 64, g, g + nz * W, g + 2 * nz * W);
+        if (grp == 0) band_solve_line<W>(col + lane, nz, 64, f, f + nz * W, f + 2 * nz * W);
         __syncthreads();
     } else if (A.solve == 2) {
         const double* band = f + 2 * nz * W + nz;
