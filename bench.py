@@ -214,7 +214,8 @@ def mixed_vs_fp64(K, W, torch, p, N, steps, eps, dt=None, E0=None, H0=None, G64=
 def profile_run(K, W, torch, p, N, steps):
     """A short run for the profiler: a device copy of known size (512 MiB read,
     512 MiB written: the reference for the HBM byte counters), then `steps`
-    steps of the metric workload's kernels from a seeded random state."""
+    steps of the metric workload's kernels from a seeded random state under
+    each of the two tiled plans whose mass kernels differ."""
     import numpy as np
     n = 64 * 1024 * 1024  # doubles: 512 MiB
     src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -228,7 +229,10 @@ def profile_run(K, W, torch, p, N, steps):
     E = torch.tensor(W.random_vector(2 * G.n_e, 0, 41), dtype=torch.float64, device="cuda")
     H = torch.tensor(W.random_vector(2 * G.n_h, 0, 42), dtype=torch.float64, device="cuda")
     en = torch.zeros(steps, dtype=torch.float64, device="cuda")
-    G.step(E, H, 1e-3, nsteps=steps, flags=K.TRACK_DB, energy=en)
+    # the tiled plan, then the tiled plan with the four-wave mass kernel
+    for plan in (K.PLAN_TILED, K.PLAN_TILED_W4):
+        G.set_plan(plan)
+        G.step(E, H, 1e-3, nsteps=steps, flags=K.TRACK_DB, energy=en)
     torch.cuda.synchronize()
     return {"profile_run": {"copy_bytes_each_way": n * 8, "copies": 3, "steps": steps, "p": p, "N": N}}
 
@@ -410,7 +414,8 @@ def main():
     avg_mass_s = ms_mass / n_mass * 1e-3
     flops = 0.5 * (mass_flops(p, N, "B") + mass_flops(p, N, "D"))
     achieved = flops / avg_mass_s / 1e12
-    tb, td = measured_traffic("mass_B"), measured_traffic("mass_D")
+    sfx = "_w4" if plan[0] == K.PLAN_TILED_W4 else ""
+    tb, td = measured_traffic("mass_B" + sfx), measured_traffic("mass_D" + sfx)
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": None if tb is None or td is None else 0.5 * (tb + td),
