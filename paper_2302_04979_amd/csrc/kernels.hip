@@ -133,20 +133,24 @@ __device__ inline void load_windows(double* dst, const double* __restrict__ src,
 // window is one entry longer, and both the primal (v[k] - v[k-1]) and the dual
 // (v[r+1] - v[r]) incidence become local[l+1] - local[l].
 template <int P, int SRC, int SPACE, int C>
-__device__ inline double curl_at(const double* s0, const double* s1, const double* s2, int i) {
-    using L = Lay<P, SPACE, C>;
+__device__ inline double curl_xyz(const double* s0, const double* s1, const double* s2, int lx, int ly, int lz) {
     constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
     using LA = Lay<P, SRC, A2>;  // differentiated along A1
     using LB = Lay<P, SRC, A1>;  // differentiated along A2
     const double* sa = (A2 == 0) ? s0 : (A2 == 1 ? s1 : s2);
     const double* sb = (A1 == 0) ? s0 : (A1 == 1 ? s1 : s2);
-    const int lx = i % L::Wx, ly = (i / L::Wx) % L::Wy, lz = i / L::plane;
-    int l[3] = {lx, ly, lz};
-    const int ia = (l[2] * LA::Wy + l[1]) * LA::Wx + l[0];
-    const int da = A1 == 0 ? 1 : (A1 == 1 ? LA::Wx : LA::plane);
-    const int ib = (l[2] * LB::Wy + l[1]) * LB::Wx + l[0];
-    const int db = A2 == 0 ? 1 : (A2 == 1 ? LB::Wx : LB::plane);
+    const int ia = (lz * LA::Wy + ly) * LA::Wx + lx;
+    constexpr int da = A1 == 0 ? 1 : (A1 == 1 ? LA::Wx : LA::plane);
+    const int ib = (lz * LB::Wy + ly) * LB::Wx + lx;
+    constexpr int db = A2 == 0 ? 1 : (A2 == 1 ? LB::Wx : LB::plane);
     return (sa[ia + da] - sa[ia]) - (sb[ib + db] - sb[ib]);
+}
+
+// the same at entry i of the 2-form window of component C
+template <int P, int SRC, int SPACE, int C>
+__device__ inline double curl_at(const double* s0, const double* s1, const double* s2, int i) {
+    using L = Lay<P, SPACE, C>;
+    return curl_xyz<P, SRC, SPACE, C>(s0, s1, s2, i % L::Wx, (i / L::Wx) % L::Wy, i / L::plane);
 }
 
 // The tile that owns global index g of a window along one axis: the tile t with
@@ -157,11 +161,11 @@ __device__ inline int owner_tile(int g, int nt) {
     return t > nt - 1 ? nt - 1 : t;
 }
 
-// track[g] += alpha * window value, for the window entries this tile owns
-template <int P, class L>
-__device__ inline void track_owned(double* __restrict__ tr, const int dims[3], const double* xw, double alpha,
-                                   int tx, int ty, int tz, int nt, int i) {
-    const int lx = i % L::Wx, ly = (i / L::Wx) % L::Wy, lz = i / L::plane;
+// track[g] += alpha * v for the window entry (lx, ly, lz) of value v, if this
+// tile owns it
+template <class L>
+__device__ inline void track_at(double* __restrict__ tr, const int dims[3], double v, double alpha, int tx, int ty,
+                                int tz, int nt, int lx, int ly, int lz) {
     const int gx = tx * TILE + tag_offset(L::tx) + lx;
     const int gy = ty * TILE + tag_offset(L::ty) + ly;
     const int gz = tz * TILE + tag_offset(L::tz) + lz;
@@ -169,7 +173,7 @@ __device__ inline void track_owned(double* __restrict__ tr, const int dims[3], c
     if (owner_tile<L::tx>(gx, nt) != tx || owner_tile<L::ty>(gy, nt) != ty || owner_tile<L::tz>(gz, nt) != tz)
         return;
     const int64_t k = (int64_t(gz) * dims[1] + gy) * dims[2] + gx;
-    tr[k] += alpha * xw[i];
+    tr[k] += alpha * v;
 }
 
 // Table slot of axis a: 0 = the tag of the component along a, 1 = the tag of
@@ -256,6 +260,133 @@ __device__ inline void integrate_xy(const double (&Rcol)[L::Wz], double* rb, dou
     }
 }
 
+// ---- pieces of the mass kernel ---------------------------------------------
+// The 1D tables are the same for every lane of a workgroup except along x.
+// The y tables and the x tables of the integrals are read from global memory
+// with uniform addresses (the scalar cache); the x tables of the contraction
+// (indexed by lane) and the z tables (used in the register-heavy Gauss-point
+// walk, where scalar registers run short) are staged in LDS.
+
+// table of axis a and slot (0: the tag of the component along a, 1: the tag of
+// the components across a) for the tile coordinate `coord` along a:
+// [element][point][function]
+template <int P, int SPACE, int AX, int SLOT>
+__device__ inline const double* axis_table(const double* __restrict__ tab, const int64_t* tab_off, int coord) {
+    constexpr int tag = SLOT == 0 ? space_tag(SPACE, AX, AX) : space_tag(SPACE, (AX + 1) % 3, AX);
+    return tab + tab_off[tag] + int64_t(coord) * (TILE * (P + 1) * tag_support(P, tag));
+}
+
+// LDS pitches of one component: the y-contracted window yc[cz][qy][lx], whose
+// z planes are padded so that consecutive planes start Wx entries apart modulo
+// 16 doubles (the planes one wave writes then fall on distinct banks), and
+// the x-integrated rows xi[cz][lx][qy] (odd row pitch), which reuse its space.
+template <class L, int Q>
+struct MassPitch {
+    static constexpr int bz = Q * L::Wx + ((L::Wx - Q * L::Wx) % 16 + 16) % 16;
+    static constexpr int yc = L::Wz * bz;
+    static constexpr int xi = L::Wz * L::Wx * (Q + 1);
+    static constexpr int size = yc > xi ? yc : xi;
+};
+
+// Part 1a, one wave per component: lane (cz, lx) takes the y column of the
+// component's window at (lx, cz) -- formed from the 1-form windows when the
+// curl is fused -- adds the entries this tile owns to the tracked 2-form, and
+// contracts the column along y: yc[cz][qy][lx] = sum_j T_y[qy][j] x[le(qy) + j].
+template <int P, int SRC, int SPACE, int C, bool CURL, int NQ, int Q>
+__device__ inline void forward_y(const double* s0, const double* s1, const double* s2, const double* xw,
+                                 double* yc, const double* __restrict__ tyt, int lane, double* __restrict__ tr,
+                                 const MassArgs& A, int tx, int ty, int tz, int nt) {
+    using L = Lay<P, SPACE, C>;
+    using PT = MassPitch<L, Q>;
+    if (lane >= L::Wz * L::Wx) return;
+    const int cz = lane / L::Wx, lx = lane - cz * L::Wx;
+    double x[L::Wy];
+#pragma unroll
+    for (int ly = 0; ly < L::Wy; ++ly)
+        x[ly] = CURL ? curl_xyz<P, SRC, SPACE, C>(s0, s1, s2, lx, ly, cz) : xw[(cz * L::Wy + ly) * L::Wx + lx];
+    if (CURL && tr) {
+#pragma unroll
+        for (int ly = 0; ly < L::Wy; ++ly)
+            track_at<L>(tr + A.track_comp_off[C], A.track_dims[C], x[ly], A.track_alpha, tx, ty, tz, nt, lx, ly, cz);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int le = q / NQ;
+        const double* t = tyt + q * L::Ky;
+        double s = t[0] * x[le];
+#pragma unroll
+        for (int j = 1; j < L::Ky; ++j) s = fma(t[j], x[le + j], s);
+        yc[cz * PT::bz + q * L::Wx + lx] = s;
+    }
+}
+
+// Part 1b: thread (qy, qx) contracts along x into its register column,
+// A[cz] = sum_j T_x[qx][j] yc[cz][qy][le(qx) + j].
+template <class L, int NQ, int Q>
+__device__ inline void forward_x(const double* yc, const double* txl, double (&Acol)[L::Wz], int qy, int qx) {
+    using PT = MassPitch<L, Q>;
+    const int le = qx / NQ;
+    double phi[L::Kx];
+#pragma unroll
+    for (int j = 0; j < L::Kx; ++j) phi[j] = txl[qx * L::Kx + j];
+#pragma unroll
+    for (int cz = 0; cz < L::Wz; ++cz) {
+        const double* b = yc + cz * PT::bz + qy * L::Wx + le;
+        double s = phi[0] * b[0];
+#pragma unroll
+        for (int j = 1; j < L::Kx; ++j) s = fma(phi[j], b[j], s);
+        Acol[cz] = s;
+    }
+}
+
+// Part 3a: thread t = (cz, qy) integrates one x row of the z integrals R
+// against the x table: xi[cz][lx][qy] = sum over (qx, j) with le(qx) + j = lx
+// of T_x[qx][j] R[cz][qy][qx].
+template <class L, int NQ, int Q>
+__device__ inline void integrate_x_row(const double* rb, double* xi, const double* __restrict__ txt, int t) {
+    if (t >= L::Wz * Q) return;
+    const int cz = t / Q, qy = t - cz * Q;
+    const double* row = rb + t * (Q + 1);
+    double r[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) r[k] = row[k];
+    double c[L::Wx];
+#pragma unroll
+    for (int lx = 0; lx < L::Wx; ++lx) c[lx] = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int le = q / NQ;
+#pragma unroll
+        for (int j = 0; j < L::Kx; ++j) c[le + j] = fma(txt[q * L::Kx + j], r[q], c[le + j]);
+    }
+#pragma unroll
+    for (int lx = 0; lx < L::Wx; ++lx) xi[(cz * L::Wx + lx) * (Q + 1) + qy] = c[lx];
+}
+
+// Part 3b, one wave per component: lane (cz, lx) integrates its xi row along y
+// against the y table and writes the column of the tile's patch.
+template <class L, int NQ, int Q>
+__device__ inline void integrate_y_col(const double* xi, double* __restrict__ out, const double* __restrict__ tyt,
+                                       int lane) {
+    if (lane >= L::Wz * L::Wx) return;
+    const int cz = lane / L::Wx, lx = lane - cz * L::Wx;
+    const double* col = xi + lane * (Q + 1);
+    double c[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) c[k] = col[k];
+    double o[L::Wy];
+#pragma unroll
+    for (int ly = 0; ly < L::Wy; ++ly) o[ly] = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int le = q / NQ;
+#pragma unroll
+        for (int j = 0; j < L::Ky; ++j) o[le + j] = fma(tyt[q * L::Ky + j], c[q], o[le + j]);
+    }
+#pragma unroll
+    for (int ly = 0; ly < L::Wy; ++ly) out[(cz * L::Wy + ly) * L::Wx + lx] = o[ly];
+}
+
 // MET = 0: the metric w_q DF^T DF / det DF is streamed from memory (any map);
 // MET = 1: it is recomputed at each Gauss point for x -> x + a s(x) (1,1,1)
 // with s = sin(pi x) sin(pi y) sin(pi z) (a = 0: identity), from per-axis
@@ -263,9 +394,11 @@ __device__ inline void integrate_xy(const double (&Rcol)[L::Wz], double* rb, dou
 // det DF = 1 + a (g1 + g2 + g3) and (DF^T DF)_ij = d_ij + a (g_i + g_j) + 3 a^2 g_i g_j.
 // WPE: minimum waves per SIMD the compiler must allow (1: its own choice; 4:
 // registers capped at 128 for a fourth resident workgroup per CU).
+// `tabg` and `axt` are A.tab and A.axis_tab, passed again as restrict
+// parameters so that their uniform reads go through the scalar cache.
 template <int P, int SPACE, bool CURL, int MET, int WPE>
 __global__ void __launch_bounds__(MassCfg<P>::NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-mass_kernel(const MassArgs A) {
+mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __restrict__ axt) {
     constexpr int NQ = P + 1, Q = TILE * NQ, NT = MassCfg<P>::NT;
     constexpr int SRC = CURL ? (SPACE == SP_B ? SP_E : SP_H) : SPACE;
     using L0 = Lay<P, SPACE, 0>;
@@ -274,33 +407,37 @@ mass_kernel(const MassArgs A) {
     using S0 = Lay<P, SRC, 0>;
     using S1 = Lay<P, SRC, 1>;
     using S2 = Lay<P, SRC, 2>;
+    using P0 = MassPitch<L0, Q>;
+    using P1 = MassPitch<L1, Q>;
+    using P2 = MassPitch<L2, Q>;
+    static_assert(NT >= 3 * 64, "parts 1a and 3b take one wave per component");
+    static_assert(L0::Wz * L0::Wx <= 64 && L1::Wz * L1::Wx <= 64 && L2::Wz * L2::Wx <= 64,
+                  "a component's (z, x) columns fit one wave");
+    static_assert(L0::Wz * Q <= NT && L1::Wz * Q <= NT && L2::Wz * Q <= NT, "one x row per thread");
     constexpr int KMAX = P + 1;
     constexpr int TSL = TILE * NQ * KMAX;  // one table slice
-    // LDS map: tables | [1-form windows, 2-form windows] aliased later by the
-    // z-integral planes | one y/x contraction buffer
-    constexpr int SW = CURL ? S0::size + S1::size + S2::size : 0;
-    constexpr int XW = L0::size + L1::size + L2::size;
+    // LDS map: x and z tables (two slots each) | input windows, later the
+    // z-integral planes of one component | per component: y-contracted window,
+    // later x-integrated rows
+    constexpr int SW = CURL ? S0::size + S1::size + S2::size : L0::size + L1::size + L2::size;
     constexpr int WZM = L0::Wz > L1::Wz ? (L0::Wz > L2::Wz ? L0::Wz : L2::Wz) : (L1::Wz > L2::Wz ? L1::Wz : L2::Wz);
     constexpr int RB = WZM * Q * (Q + 1);
-    constexpr int R0 = (SW + XW) > RB ? (SW + XW) : RB;
-    constexpr int BB0 = L0::Wz * Q * L0::Wx, BB1 = L1::Wz * Q * L1::Wx, BB2 = L2::Wz * Q * L2::Wx;
-    constexpr int BB = BB0 > BB1 ? (BB0 > BB2 ? BB0 : BB2) : (BB1 > BB2 ? BB1 : BB2);
-    constexpr int OT = 0, OR = OT + 6 * TSL, OB = OR + R0;
-    constexpr int OS0 = OR, OS1 = OS0 + (CURL ? S0::size : 0), OS2 = OS1 + (CURL ? S1::size : 0);
-    constexpr int OX0 = OR + SW, OX1 = OX0 + L0::size, OX2 = OX1 + L1::size;
-    __shared__ double sm[OB + BB];
+    constexpr int R0 = SW > RB ? SW : RB;
+    constexpr int OT = 0, OR = OT + 4 * TSL;
+    constexpr int OY0 = OR + R0, OY1 = OY0 + P0::size, OY2 = OY1 + P1::size, OEND = OY2 + P2::size;
+    __shared__ double sm[OEND];
 
     const int tid = threadIdx.x;
     const int nt = A.ntile;
     const int tile = xcd_tile(blockIdx.x, nt * nt * nt);
     const int b = blockIdx.y;
     const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
-    const int tcoord[3] = {tx, ty, tz};
     const double* src = A.src + int64_t(b) * A.src_stride;
     const int qy = tid / Q, qx = tid % Q;
     const bool active = tid < Q * Q;
-    // the first two Gauss-point planes of the metric are requested before the
-    // window set-up so that their latency overlaps it
+    const int wave = tid / 64, lane = tid % 64;
+    // the first Gauss-point plane of the metric is requested before the window
+    // set-up so that its latency overlaps it
     const double* gm = A.metric + int64_t(tile) * Q * 6 * Q * Q + qy * Q + qx;
     double g[6] = {0, 0, 0, 0, 0, 0};
     if (MET == 0) {
@@ -308,70 +445,92 @@ mass_kernel(const MassArgs A) {
         for (int k = 0; k < 6; ++k) g[k] = active ? __builtin_nontemporal_load(gm + k * Q * Q) : 0.0;
     }
 
-    // ---- 1D tables of the tile: [axis][slot][element][point][function] ----
+    // ---- per (x, y) column: 1/gamma of its four elements and, for the analytic
+    // metric, q = a grad s = (a1 s_z, a2 s_z, a3 c_z) up to the z factors; read
+    // here, before the column registers fill up ----
+    double ig[TILE];
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0, wxy = 0.0;
+    if (active) {
+        const int ex = tx * TILE + qx / NQ, ey = ty * TILE + qy / NQ;
+#pragma unroll
+        for (int le = 0; le < TILE; ++le)
+            ig[le] = A.inv_gamma ? A.inv_gamma[(int64_t(tz * TILE + le) * A.npad + ey) * A.npad + ex] : 1.0;
+        if (MET == 1) {
+            const int64_t npq = int64_t(A.npad) * NQ;
+            const int gxq = tx * TILE * NQ + qx, gyq = ty * TILE * NQ + qy;
+            const double sx = axt[gxq], cx = axt[npq + gxq], wx = axt[2 * npq + gxq];
+            const double sy = axt[gyq], cy = axt[npq + gyq], wy = axt[2 * npq + gyq];
+            a1 = A.amp * M_PI * cx * sy;
+            a2 = A.amp * M_PI * sx * cy;
+            a3 = A.amp * M_PI * sx * sy;
+            wxy = wx * wy;
+        }
+    }
+
+    // ---- x and z tables of the tile: [axis x, z][slot][element][point][function] ----
     {
-        constexpr int ST = (6 * TSL + NT - 1) / NT;
+        constexpr int ST = (4 * TSL + NT - 1) / NT;
         double r[ST];
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
             const int i = tid + NT * q;
-            const int a = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
-            const int tag = slot == 0 ? space_tag(SPACE, a % 3, a % 3) : space_tag(SPACE, (a + 1) % 3, a % 3);
+            const int az = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
+            const int tag = az == 0 ? (slot == 0 ? space_tag(SPACE, 0, 0) : space_tag(SPACE, 1, 0))
+                                    : (slot == 0 ? space_tag(SPACE, 2, 2) : space_tag(SPACE, 0, 2));
             const int K = tag_support(P, tag);
-            r[q] = (i < 6 * TSL && k < TILE * NQ * K)
-                       ? A.tab[A.tab_off[tag] + int64_t(tcoord[a % 3]) * TILE * NQ * K + k] : 0.0;
+            const int coord = az == 0 ? tx : tz;
+            r[q] = (i < 4 * TSL && k < TILE * NQ * K) ? tabg[A.tab_off[tag] + int64_t(coord) * TILE * NQ * K + k]
+                                                      : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
             const int i = tid + NT * q;
-            const int a = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
-            const int tag = slot == 0 ? space_tag(SPACE, a % 3, a % 3) : space_tag(SPACE, (a + 1) % 3, a % 3);
-            if (i < 6 * TSL && k < TILE * NQ * tag_support(P, tag)) sm[OT + i] = r[q];
+            if (i < 4 * TSL) sm[OT + i] = r[q];
         }
     }
-    // ---- input windows (curl fused) ----
-    if (CURL) {
-        load_windows<P, S0, S1, S2, NT>(sm + OS0, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
-        __syncthreads();
-        for (int i = tid; i < XW; i += NT) {
-            if (i < L0::size)
-                sm[OX0 + i] = curl_at<P, SRC, SPACE, 0>(sm + OS0, sm + OS1, sm + OS2, i);
-            else if (i < L0::size + L1::size)
-                sm[OX1 + i - L0::size] = curl_at<P, SRC, SPACE, 1>(sm + OS0, sm + OS1, sm + OS2, i - L0::size);
-            else
-                sm[OX2 + i - L0::size - L1::size] =
-                    curl_at<P, SRC, SPACE, 2>(sm + OS0, sm + OS1, sm + OS2, i - L0::size - L1::size);
-        }
-        if (A.track) {
-            __syncthreads();
-            double* tr = A.track + int64_t(b) * A.track_stride;
-            for (int i = tid; i < XW; i += NT) {
-                if (i < L0::size)
-                    track_owned<P, L0>(tr + A.track_comp_off[0], A.track_dims[0], sm + OX0, A.track_alpha, tx, ty,
-                                       tz, nt, i);
-                else if (i < L0::size + L1::size)
-                    track_owned<P, L1>(tr + A.track_comp_off[1], A.track_dims[1], sm + OX1, A.track_alpha, tx, ty,
-                                       tz, nt, i - L0::size);
-                else
-                    track_owned<P, L2>(tr + A.track_comp_off[2], A.track_dims[2], sm + OX2, A.track_alpha, tx, ty,
-                                       tz, nt, i - L0::size - L1::size);
-            }
-        }
-    } else {
-        load_windows<P, L0, L1, L2, NT>(sm + OX0, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
+    // ---- input windows: the 1-form (curl fused) or the 2-form ----
+    if (CURL) load_windows<P, S0, S1, S2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
+    else load_windows<P, L0, L1, L2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
+    __syncthreads();
+
+    // ---- part 1a: y contraction of the windows, one wave per component ----
+    {
+        double* tr = (CURL && A.track) ? A.track + int64_t(b) * A.track_stride : nullptr;
+        const double* s0 = sm + OR;
+        const double* s1 = s0 + S0::size;
+        const double* s2 = s1 + S1::size;
+        const double* x0 = sm + OR;
+        const double* x1 = x0 + L0::size;
+        const double* x2 = x1 + L1::size;
+        if (wave == 0)
+            forward_y<P, SRC, SPACE, 0, CURL, NQ, Q>(s0, s1, s2, x0, sm + OY0,
+                                                     axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane, tr, A,
+                                                     tx, ty, tz, nt);
+        else if (wave == 1)
+            forward_y<P, SRC, SPACE, 1, CURL, NQ, Q>(s0, s1, s2, x1, sm + OY1,
+                                                     axis_table<P, SPACE, 1, 0>(tabg, A.tab_off, ty), lane, tr, A,
+                                                     tx, ty, tz, nt);
+        else if (wave == 2)
+            forward_y<P, SRC, SPACE, 2, CURL, NQ, Q>(s0, s1, s2, x2, sm + OY2,
+                                                     axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane, tr, A,
+                                                     tx, ty, tz, nt);
     }
     __syncthreads();
 
-    const double* T = sm + OT;
-    auto tab = [&](int a, int slot) { return T + (a * 2 + slot) * TSL; };
-
-    // ---- x and y contractions of the whole window, once per tile ----
+    // ---- part 1b: x contraction into the register columns ----
     double A0[L0::Wz], A1[L1::Wz], A2[L2::Wz];
-    contract_xy<P, L0, NQ, Q>(sm + OX0, sm + OB, tab(0, 0), tab(1, 1), A0, tid, NT, qy, qx, active);
-    contract_xy<P, L1, NQ, Q>(sm + OX1, sm + OB, tab(0, 1), tab(1, 0), A1, tid, NT, qy, qx, active);
-    contract_xy<P, L2, NQ, Q>(sm + OX2, sm + OB, tab(0, 1), tab(1, 1), A2, tid, NT, qy, qx, active);
+    if (active) {
+        // one component at a time: the scheduler would otherwise hoist all
+        // three components' LDS reads and run out of registers
+        forward_x<L0, NQ, Q>(sm + OY0, sm + OT, A0, qy, qx);
+        __builtin_amdgcn_sched_barrier(0);
+        forward_x<L1, NQ, Q>(sm + OY1, sm + OT + TSL, A1, qy, qx);
+        __builtin_amdgcn_sched_barrier(0);
+        forward_x<L2, NQ, Q>(sm + OY2, sm + OT + TSL, A2, qy, qx);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 
-    // ---- stream the Gauss-point planes: z contraction, metric, z integral ----
+    // ---- part 2: stream the Gauss-point planes: z contraction, metric, z integral ----
     double R0c[L0::Wz], R1c[L1::Wz], R2c[L2::Wz];
 #pragma unroll
     for (int k = 0; k < L0::Wz; ++k) R0c[k] = 0.0;
@@ -380,26 +539,9 @@ mass_kernel(const MassArgs A) {
 #pragma unroll
     for (int k = 0; k < L2::Wz; ++k) R2c[k] = 0.0;
     if (active) {
-        const int ex = tx * TILE + qx / NQ, ey = ty * TILE + qy / NQ;
-        double ig[TILE];
-#pragma unroll
-        for (int le = 0; le < TILE; ++le)
-            ig[le] = A.inv_gamma ? A.inv_gamma[(int64_t(tz * TILE + le) * A.npad + ey) * A.npad + ex] : 1.0;
-        const double* tz0 = tab(2, 1);  // components 0 and 1 are across z
-        const double* tz2 = tab(2, 0);  // component 2 is along z
-        // analytic metric: per-thread factors of the (x, y) column
+        const double* tz0 = sm + OT + 3 * TSL;  // components 0 and 1 are across z
+        const double* tz2 = sm + OT + 2 * TSL;  // component 2 is along z
         const int64_t npq = int64_t(A.npad) * NQ;
-        const int gxq = tx * TILE * NQ + qx, gyq = ty * TILE * NQ + qy;
-        // analytic metric, per (x, y) column: q = a grad s = (a1 s_z, a2 s_z, a3 c_z)
-        double a1 = 0.0, a2 = 0.0, a3 = 0.0, wxy = 0.0;
-        if (MET == 1) {
-            const double sx = A.axis_tab[gxq], cx = A.axis_tab[npq + gxq], wx = A.axis_tab[2 * npq + gxq];
-            const double sy = A.axis_tab[gyq], cy = A.axis_tab[npq + gyq], wy = A.axis_tab[2 * npq + gyq];
-            a1 = A.amp * M_PI * cx * sy;
-            a2 = A.amp * M_PI * sx * cy;
-            a3 = A.amp * M_PI * sx * sy;
-            wxy = wx * wy;
-        }
 #pragma unroll
         for (int le = 0; le < TILE; ++le) {
 #pragma unroll
@@ -417,14 +559,14 @@ mass_kernel(const MassArgs A) {
                 double q1 = 0.0, q2 = 0.0, q3 = 0.0, f = 0.0;
                 if (MET == 1) {
                     const int gzq = tz * TILE * NQ + qz;
-                    const double sz = A.axis_tab[gzq], cz = A.axis_tab[npq + gzq], wz = A.axis_tab[2 * npq + gzq];
+                    const double sz = axt[gzq], cz = axt[npq + gzq], wz = axt[2 * npq + gzq];
                     q1 = a1 * sz;
                     q2 = a2 * sz;
                     q3 = a3 * cz;
                     f = wxy * wz * recip_nr(1.0 + (q1 + q2 + q3));
                 }
-                const double* t0 = tz0 + (le * NQ + iq) * L0::Kz;
-                const double* t2 = tz2 + (le * NQ + iq) * L2::Kz;
+                const double* t0 = tz0 + qz * L0::Kz;
+                const double* t2 = tz2 + qz * L2::Kz;
                 double v0 = 0.0, v1 = 0.0, v2 = 0.0;
 #pragma unroll
                 for (int j = 0; j < L0::Kz; ++j) v0 += t0[j] * A0[le + j];
@@ -459,18 +601,41 @@ mass_kernel(const MassArgs A) {
             }
         }
     }
-    __syncthreads();  // the window region is reused for the z-integral planes
 
-    // ---- transposed x and y contractions, once per tile, into the patch ----
+    // ---- part 3: x integrals row by row (R planes in the window region, last
+    // read in part 1a), then y integrals, one wave per component ----
+    double* rb = sm + OR;
+    if (active) {
+#pragma unroll
+        for (int cz = 0; cz < L0::Wz; ++cz) rb[(cz * Q + qy) * (Q + 1) + qx] = R0c[cz];
+    }
+    __syncthreads();
+    integrate_x_row<L0, NQ, Q>(rb, sm + OY0, axis_table<P, SPACE, 0, 0>(tabg, A.tab_off, tx), tid);
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int cz = 0; cz < L1::Wz; ++cz) rb[(cz * Q + qy) * (Q + 1) + qx] = R1c[cz];
+    }
+    __syncthreads();
+    integrate_x_row<L1, NQ, Q>(rb, sm + OY1, axis_table<P, SPACE, 0, 1>(tabg, A.tab_off, tx), tid);
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int cz = 0; cz < L2::Wz; ++cz) rb[(cz * Q + qy) * (Q + 1) + qx] = R2c[cz];
+    }
+    __syncthreads();
+    integrate_x_row<L2, NQ, Q>(rb, sm + OY2, axis_table<P, SPACE, 0, 1>(tabg, A.tab_off, tx), tid);
+    __syncthreads();
     double* out = A.patch + int64_t(b) * A.patch_stride;
-    integrate_xy<P, L0, NQ, Q>(R0c, sm + OR, sm + OB, tab(0, 0), tab(1, 1),
-                               out + A.patch_comp_off[0] + int64_t(tile) * L0::size, tid, NT, qy, qx, active);
-    __syncthreads();
-    integrate_xy<P, L1, NQ, Q>(R1c, sm + OR, sm + OB, tab(0, 1), tab(1, 0),
-                               out + A.patch_comp_off[1] + int64_t(tile) * L1::size, tid, NT, qy, qx, active);
-    __syncthreads();
-    integrate_xy<P, L2, NQ, Q>(R2c, sm + OR, sm + OB, tab(0, 1), tab(1, 1),
-                               out + A.patch_comp_off[2] + int64_t(tile) * L2::size, tid, NT, qy, qx, active);
+    if (wave == 0)
+        integrate_y_col<L0, NQ, Q>(sm + OY0, out + A.patch_comp_off[0] + int64_t(tile) * L0::size,
+                                   axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane);
+    else if (wave == 1)
+        integrate_y_col<L1, NQ, Q>(sm + OY1, out + A.patch_comp_off[1] + int64_t(tile) * L1::size,
+                                   axis_table<P, SPACE, 1, 0>(tabg, A.tab_off, ty), lane);
+    else if (wave == 2)
+        integrate_y_col<L2, NQ, Q>(sm + OY2, out + A.patch_comp_off[2] + int64_t(tile) * L2::size,
+                                   axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane);
 }
 
 template <int P, int SPACE, bool CURL>
@@ -478,11 +643,13 @@ static void launch_mass_t(const MassArgs& a, dim3 grid, hipStream_t s) {
     // the four-wave variant exists for p <= 3 (p = 4 would spill)
     const bool w4 = a.waves4 && P <= 3;
     if (a.metric_mode == 1) {
-        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a);
-        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a,
+                                   a.tab, a.axis_tab);
+        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a, a.tab, a.axis_tab);
     } else {
-        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a);
-        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a);
+        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a,
+                                   a.tab, a.axis_tab);
+        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a, a.tab, a.axis_tab);
     }
 }
 
