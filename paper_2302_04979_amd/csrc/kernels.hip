@@ -128,6 +128,56 @@ __device__ inline void load_windows(double* dst, const double* __restrict__ src,
     }
 }
 
+// Component window rows for the mass kernel: lane (g, ly, lx) = (tid / 64,
+// (tid / 8) % 8, tid % 8) holds the entries (lx, ly, g + k G) of the window
+// (G = NT / 64 z-groups), so the index arithmetic and the x, y bounds tests
+// are done once per thread and the eight lanes of an x row read contiguous
+// memory.
+template <int P, class L, int G, int I>
+__device__ inline void window_rows(double (&r)[I], const double* __restrict__ src, const int dims[3], int tx, int ty,
+                                   int tz, int n0, int n1, int lx, int ly, int g) {
+    static_assert(L::Wx <= 8 && L::Wy <= 8, "an (x, y) plane of a window fits 64 lanes");
+    const int gx = tx * TILE + tag_offset(L::tx) + lx;
+    const int gy = ty * TILE + tag_offset(L::ty) + ly;
+    const bool okxy = lx < L::Wx && ly < L::Wy && gx >= 0 && gx < tag_dim(L::tx, n0, n1) && gy >= 0 &&
+                      gy < tag_dim(L::ty, n0, n1);
+    const int nz = tag_dim(L::tz, n0, n1);
+    const int gz0 = tz * TILE + tag_offset(L::tz) + g;
+    const int64_t zs = int64_t(dims[1]) * dims[2];
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const int lz = g + k * G, gz = gz0 + k * G;
+        r[k] = (okxy && lz < L::Wz && gz >= 0 && gz < nz) ? src[int64_t(gz) * zs + int64_t(gy) * dims[2] + gx] : 0.0;
+    }
+}
+
+template <class L, int G, int I>
+__device__ inline void store_rows(double* dst, const double (&r)[I], int lx, int ly, int g) {
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const int lz = g + k * G;
+        if (lx < L::Wx && ly < L::Wy && lz < L::Wz) dst[(lz * L::Wy + ly) * L::Wx + lx] = r[k];
+    }
+}
+
+// the three component windows of a field into LDS (contiguous, component after
+// component); every load of a thread is issued before its first LDS store
+template <int P, class L0, class L1, class L2, int NT>
+__device__ inline void load_windows_rows(double* dst, const double* __restrict__ src, const int64_t comp_off[3],
+                                         const int dims[3][3], int tx, int ty, int tz, int n0, int n1, int tid) {
+    static_assert(NT % 64 == 0, "whole waves");
+    constexpr int G = NT / 64;
+    constexpr int I0 = (L0::Wz + G - 1) / G, I1 = (L1::Wz + G - 1) / G, I2 = (L2::Wz + G - 1) / G;
+    const int lx = tid & 7, ly = (tid >> 3) & 7, g = tid >> 6;
+    double r0[I0], r1[I1], r2[I2];
+    window_rows<P, L0, G, I0>(r0, src + comp_off[0], dims[0], tx, ty, tz, n0, n1, lx, ly, g);
+    window_rows<P, L1, G, I1>(r1, src + comp_off[1], dims[1], tx, ty, tz, n0, n1, lx, ly, g);
+    window_rows<P, L2, G, I2>(r2, src + comp_off[2], dims[2], tx, ty, tz, n0, n1, lx, ly, g);
+    store_rows<L0, G, I0>(dst, r0, lx, ly, g);
+    store_rows<L1, G, I1>(dst + L0::size, r1, lx, ly, g);
+    store_rows<L2, G, I2>(dst + L0::size + L1::size, r2, lx, ly, g);
+}
+
 // curl of the 1-form window into component C of the 2-form window:
 // (d_{C+1} u_{C+2} - d_{C+2} u_{C+1}); along the differentiated axis the 1-form
 // window is one entry longer, and both the primal (v[k] - v[k-1]) and the dual
@@ -489,8 +539,10 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
         }
     }
     // ---- input windows: the 1-form (curl fused) or the 2-form ----
-    if (CURL) load_windows<P, S0, S1, S2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
-    else load_windows<P, L0, L1, L2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
+    if (CURL)
+        load_windows_rows<P, S0, S1, S2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
+    else
+        load_windows_rows<P, L0, L1, L2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
     __syncthreads();
 
     // ---- part 1a: y contraction of the windows, one wave per component ----
