@@ -195,10 +195,12 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
  *   KMX_PLAN_TILED_W4   the tiled plan with the mass kernel compiled for four
  *                       resident waves per SIMD (registers capped at 128;
  *                       p <= 3, otherwise as KMX_PLAN_TILED).
- *   KMX_PLAN_TILED_DENSE  the tiled plan with the pairing solves applied as
- *                       three FP64 mode products with the dense inverses of
- *                       the 1D factors (computed once on the host in FP64) on
- *                       the matrix cores, instead of banded substitutions.
+ *   KMX_PLAN_TILED_DENSE  the tiled plan with the pairing solves applied
+ *                       with the dense inverses of the 1D factors (computed
+ *                       once on the host in FP64) on the FP64 matrix cores:
+ *                       per z plane B_y X B_x^T, then B_z along z, instead of
+ *                       banded substitutions.  Lines of at most 80 entries;
+ *                       kmx_set_plan fails with KMX_E_ARG otherwise.
  * KMX_PLAN_AUTO (the default) takes the separable plan when it applies and
  * batch >= 32, the tiled plan otherwise.  `threads` is the separable kernels'
  * workgroup size (64..768, multiple of 64).  Forcing a separable plan on a
@@ -319,7 +321,8 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
  *   6 patch gather (sum of the overlapping tile outputs of a mass apply)
  *   7 separable persistent kernel (one launch for all steps of a call)
  *   8 FP32 dense mode products of the mixed-precision solves
- *   9 FP64 dense mode products of the tiled-dense plan (one span per solve)
+ *   9 FP64 dense solves of the tiled-dense plan (plane pass and z pass, one
+ *     span per solve)
  * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
 #define KMX_PROFILE_KINDS 10
 kmx_status kmx_profile_begin(kmx_space* sp, int capacity);

@@ -42,7 +42,7 @@ EXPORTS = (
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
-                 "mode_fp32", "mode_fp64")
+                 "mode_fp32", "dense_fp64")
 
 _STATUS = {0: "KMX_OK", 1: "KMX_E_ARG", 2: "KMX_E_GEOMETRY", 3: "KMX_E_MATERIAL", 4: "KMX_E_DEVICE",
            5: "KMX_E_OOM", 6: "KMX_E_UNSTABLE", 7: "KMX_E_STATE"}

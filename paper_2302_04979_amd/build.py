@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkronmaxwell.so")
-SOURCES = ["setup.hip", "kernels.hip", "sep.hip", "mixed.hip", "api.hip"]
+SOURCES = ["setup.hip", "kernels.hip", "sep.hip", "mixed.hip", "dense.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -24,9 +24,18 @@ FLAGS = [
 ]
 
 
+# Matrix-core sources: MFMA accumulators in ordinary VGPRs.  With the default
+# (accumulation registers) the compiler copies every loop-carried accumulator
+# into and out of them around each product, serialising the products.
+FILE_FLAGS = {
+    "dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "mixed.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

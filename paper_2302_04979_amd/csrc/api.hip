@@ -61,7 +61,7 @@ void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
 
 // Kernel kinds reported by kmx_profile_end.
 enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6, PK_SEP = 7,
-       PK_MODE = 8, PK_MODE64 = 9 };
+       PK_MODE = 8, PK_DENSE = 9 };
 
 struct ProfScope {  // brackets one launch with events when profiling is on
     kmx_space* sp;
@@ -437,20 +437,32 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             const int lmax = sep_line_max(std::max(sp->n0, sp->n1));
             if (lmax > 0 && shm <= size_t(sp->max_lds)) HIP_TRY(sep_prepare(p, lmax, shm));
         }
-        {
-            // dense FP64 inverses of G^, M^, G^T, M^T (row-major) for the
-            // tiled-dense plan
-            std::vector<double> inv;
+        if (std::max(sp->n0, sp->n1) <= DENSE_NMAX) {
+            // dense FP64 inverses of G^, M^, G^T, M^T for the tiled-dense
+            // plan, in the matrix cores' operand order
+            std::vector<double> frag;
             for (int k = 0; k < 4; ++k) {
                 const int n = (k == F_G || k == F_GT) ? sp->n0 : sp->n1;
                 const std::vector<double>& A = (k == F_G || k == F_GT) ? sp->tb.G : sp->tb.M;
                 const std::vector<double> Ai = dense_inverse(A, n);
-                sp->inv64_off[k] = int64_t(inv.size());
+                std::vector<double> B(size_t(n) * n);
                 for (int i = 0; i < n; ++i)
                     for (int j = 0; j < n; ++j)
-                        inv.push_back((k == F_GT || k == F_MT) ? Ai[size_t(j) * n + i] : Ai[size_t(i) * n + j]);
+                        B[size_t(i) * n + j] = (k == F_GT || k == F_MT) ? Ai[size_t(j) * n + i] : Ai[size_t(i) * n + j];
+                sp->frag64_off[k] = int64_t(frag.size());
+                frag.resize(frag.size() + size_t(dense_frag_doubles(n)));
+                dense_fragments(B.data(), n, frag.data() + sp->frag64_off[k]);
             }
-            if ((st = upload(&sp->d_inv64, inv)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+            if ((st = upload(&sp->d_frag64, frag)) != KMX_OK) { kmx_destroy_space(sp); return st; }
+            int db[3][3], dd[3][3];
+            int64_t o[3];
+            space_dims(sp, SP_B, db, o);
+            space_dims(sp, SP_D, dd, o);
+            const size_t shm = std::max(dense_lds_bytes(db), dense_lds_bytes(dd));
+            if (shm <= size_t(sp->max_lds)) {
+                HIP_TRY(dense_prepare(shm));
+                sp->dense_ok = 1;
+            }
         }
         if (prec == KMX_MIXED) {
             if (std::max(sp->n0, sp->n1) > mode_line_max()) {
@@ -565,7 +577,7 @@ void kmx_destroy_space(kmx_space* sp) {
                       sp->d_gram, sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
-    void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_inv64};
+    void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_frag64};
     for (void* b : more)
         if (b) (void)hipFree(b);
     delete sp;
@@ -1122,24 +1134,36 @@ void mixed_solve(kmx_space* sp, int which_K1, int transpose, const double* y, do
 // out += alpha * K^{-1} y by three FP64 mode products with the dense inverse
 // factors on the matrix cores.  y: d_tmp2 layout (stride nfield); d_tmp2 and
 // d_tmp are overwritten.
-void dense_solve(kmx_space* sp, int which_K1, double* y, double* out, int64_t out_stride, double alpha, int batch,
-                 hipStream_t s) {
+void dense_solve(kmx_space* sp, int which_K1, const double* y, double* out, int64_t out_stride, double alpha,
+                 int batch, const kmx_source* J, double t_src, const double* t_dev, hipStream_t s) {
     const int64_t nf = std::max(sp->n_e, sp->n_h);
-    ModeArgs m{};
-    space_dims(sp, which_K1 ? SP_D : SP_B, m.dims, m.comp_off);
-    m.A64 = sp->d_inv64;
-    ProfScope ps(sp, s, PK_MODE64);
-    for (int ax = 0; ax < 3; ++ax) {
-        for (int c = 0; c < 3; ++c) m.A_off[c] = sp->inv64_off[pair_fac(which_K1, 0, c, ax)];
-        m.axis = ax;
-        m.in = ax == 1 ? sp->d_tmp : y;
-        m.in_stride = nf;
-        m.out = ax == 0 ? sp->d_tmp : (ax == 1 ? y : out);
-        m.out_stride = ax == 2 ? out_stride : nf;
-        m.out_kind = ax == 2 ? 2 : 1;
-        m.alpha = alpha;
-        launch_mode64(m, batch, s);
+    DenseArgs a{};
+    space_dims(sp, which_K1 ? SP_D : SP_B, a.dims, a.comp_off);
+    a.frag = sp->d_frag64;
+    for (int c = 0; c < 3; ++c)
+        for (int ax = 0; ax < 3; ++ax) a.frag_off[c][ax] = sp->frag64_off[pair_fac(which_K1, 0, c, ax)];
+    if (J) {
+        a.src_entries = J->d_entries;
+        a.src_prof = J->d_prof;
+        a.src_off = reinterpret_cast<const int*>(J->d_prof + 4 * J->n);
+        a.n_src = J->n;
+        a.entries_per = J->entries_per;
+        a.t_src = t_src;
+        a.t_dev = t_dev;
     }
+    ProfScope ps(sp, s, PK_DENSE);
+    a.in = y;
+    a.in_stride = nf;
+    a.out = sp->d_tmp;
+    a.out_stride = nf;
+    launch_dense_xy(a, batch, s);
+    a.in = sp->d_tmp;
+    a.out = out;
+    a.out_stride = out_stride;
+    a.alpha = alpha;
+    a.accumulate = 1;
+    a.n_src = 0;
+    launch_dense_z(a, batch, s);
 }
 
 // Whether the separable persistent kernel can run a step call: identity map,
@@ -1231,7 +1255,7 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
         run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -dt);
         if (dense && !mixed) {
             run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
-            dense_solve(sp, 0, sp->d_tmp2, H, hs, -dt, batch, s);
+            dense_solve(sp, 0, sp->d_tmp2, H, hs, -dt, batch, nullptr, 0.0, nullptr, s);
         } else if (mixed) {
             run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
             mixed_solve(sp, 0, 0, sp->d_my, H, hs, -dt, 1, batch, s);
@@ -1242,11 +1266,7 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
         run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, dt);
         if (dense && !mixed) {
             run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
-            if (J)
-                launch_source_sub(sp->d_tmp2, nf, J->d_entries, J->d_prof,
-                                  reinterpret_cast<const int*>(J->d_prof + 4 * J->n), J->entries_per, J->d_comp_off,
-                                  J->d_dims, t_half, t_dev, batch, s);
-            dense_solve(sp, 1, sp->d_tmp2, E, es, dt, batch, s);
+            dense_solve(sp, 1, sp->d_tmp2, E, es, dt, batch, J, t_half, t_dev, s);
         } else if (mixed) {
             run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev);
             mixed_solve(sp, 1, 0, sp->d_my, E, es, dt, 1, batch, s);
@@ -1293,6 +1313,8 @@ kmx_status kmx_set_plan(kmx_space* sp, int kind, int threads) {
         return fail(KMX_E_ARG, "unknown plan kind");
     if (threads < 64 || threads > SEP_MAX_THREADS || threads % 64)
         return fail(KMX_E_ARG, "threads must be 64..768, a multiple of 64");
+    if (kind == KMX_PLAN_TILED_DENSE && !sp->dense_ok)
+        return fail(KMX_E_ARG, "the tiled-dense plan needs lines of at most 80 entries and its LDS on the device");
     sp->plan_kind = kind;
     sp->plan_threads = threads;
     return KMX_OK;
@@ -1332,7 +1354,7 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
     (void)hipMemsetAsync(H, 0, size_t(batch) * sp->n_h * sizeof(double), s);
     for (int k = 0; k < KMX_TUNE_CANDIDATES && st == KMX_OK; ++k) {
         double ms = -1.0;
-        if (k < 3 || sep_ok) {
+        if ((k < 3 && (cand_kind[k] != KMX_PLAN_TILED_DENSE || sp->dense_ok)) || (k >= 3 && sep_ok)) {
             sp->plan_kind = cand_kind[k];
             sp->plan_threads = k < 3 ? saved_threads : cand_threads[k];
             st = step_loop(sp, E, H, J, 0.0, nullptr, dt, 1, batch, 0, nullptr, s);  // warm-up

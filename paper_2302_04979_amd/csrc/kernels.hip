@@ -1202,7 +1202,9 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
     __shared__ double tile[TR * KMX_LINE_MAX];
     __shared__ double band[3][KMX_LINE_MAX * B];
     const int tid = threadIdx.x, bm = blockIdx.y;
-    const int blk = blockIdx.x;
+    // XCD-aware order: each XCD takes a contiguous range of (component, plane,
+    // row block), so the 2W+1 planes that neighbouring blocks share stay in its L2
+    const int blk = xcd_tile(blockIdx.x, A.nb[0] + A.nb[1]);
     const int mode = blk < A.nb[0] ? 0 : 1;
     int rem = mode == 0 ? blk : blk - A.nb[0];
     int c = 0;

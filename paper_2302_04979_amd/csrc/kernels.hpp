@@ -168,14 +168,40 @@ struct ModeArgs {
     int64_t comp_off[3];        // same layout for in and out
     int dims[3][3];             // [c][z, y, x]
     const float* A;             // dense n x n FP32 factors, row-major
-    const double* A64;          // dense n x n FP64 factors (launch_mode64)
     int64_t A_off[3];           // factor of each component along `axis`
     int axis;
 };
 int mode_line_max();
 void launch_mode(const ModeArgs& a, int batch, hipStream_t s);
-// FP64 mode product (in and out FP64; out_kind 1 store, 2 accumulate)
-void launch_mode64(const ModeArgs& a, int batch, hipStream_t s);
+
+// Dense FP64 solves with the inverse 1D factors on the matrix cores: the plane
+// pass Y = B_y X B_x^T (less the point sources) and the z pass
+// out = (accumulate ? out : 0) + alpha B_z X.
+constexpr int DENSE_NMAX = 80;  // longest line
+struct DenseArgs {
+    const double* in;
+    int64_t in_stride;
+    double* out;
+    int64_t out_stride;
+    int64_t comp_off[3];        // same layout for in and out
+    int dims[3][3];             // [c][z, y, x]
+    const double* frag;         // inverse factors in MFMA operand order
+    int64_t frag_off[3][3];     // [c][axis]
+    double alpha;               // z pass
+    int accumulate;
+    const double* src_entries;  // point sources, plane pass (as XYArgs)
+    const double* src_prof;
+    const int* src_off;
+    int n_src, entries_per;
+    double t_src;
+    const double* t_dev;
+};
+int64_t dense_frag_doubles(int n);                           // size of one operand-order factor
+void dense_fragments(const double* B, int n, double* frag);  // row-major n x n -> operand order
+size_t dense_lds_bytes(const int dims[3][3]);                // LDS of the larger of the two kernels
+hipError_t dense_prepare(size_t shm);                        // grant the kernels their LDS (outside capture)
+void launch_dense_xy(const DenseArgs& a, int batch, hipStream_t s);
+void launch_dense_z(const DenseArgs& a, int batch, hipStream_t s);
 // y -= g(t) s for the point sources of every batch member (device comp_off / dims)
 void launch_source_sub(double* y, int64_t y_stride, const double* entries, const double* prof, const int* off,
                        int entries_per, const int64_t* comp_off_dev, const int* dims_dev, double t_src,

@@ -147,8 +147,9 @@ struct kmx_space {
     float *d_m32a = nullptr, *d_m32b = nullptr;                  // FP32 [max_batch][nfield]
     int refine_steps = 2;              // refinement corrections after the first FP32 solve
     // dense FP64 inverses of the four 1D pairing factors (tiled-dense plan)
-    double* d_inv64 = nullptr;
-    int64_t inv64_off[4] = {0, 0, 0, 0};
+    double* d_frag64 = nullptr;        // FP64 inverse factors in MFMA operand order (tiled-dense plan)
+    int64_t frag64_off[4] = {0, 0, 0, 0};
+    int dense_ok = 0;                  // the dense kernels' LDS fits the device
     hipStream_t capture_stream = nullptr;
     // optional per-kernel timing with HIP events (kmx_profile_begin/end)
     bool prof_on = false;

@@ -113,94 +113,6 @@ __global__ void __launch_bounds__(256) mode_kernel(const ModeArgs M) {
     }
 }
 
-// FP64 variant (v_mfma_f64_16x16x4f64): the dense inverses applied in FP64,
-// 32 lines per workgroup (the FP64 factor takes 52 KB of LDS); each wave takes
-// every fourth (row tile, 16-line group) pair.
-constexpr int MODE64_LINES = 32;
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__global__ void __launch_bounds__(256) mode64_kernel(const ModeArgs M) {
-    __shared__ double As[MODE_NMAX][MODE_NMAX + 1];
-    __shared__ double Xs[MODE_NMAX][MODE64_LINES + 1];
-    const int c = blockIdx.y, b = blockIdx.z, tid = threadIdx.x;
-    const int* d = M.dims[c];
-    const int ny = d[1], nx = d[2];
-    const int n = d[2 - M.axis];
-    const int nlines = d[0] * ny * nx / n;
-    const int l0 = blockIdx.x * MODE64_LINES;
-    if (l0 >= nlines) return;  // uniform over the workgroup
-    const int64_t sj = M.axis == 0 ? 1 : (M.axis == 1 ? nx : int64_t(ny) * nx);
-    constexpr int NA = MODE_NMAX * MODE_NMAX / 256, NX = MODE_NMAX * MODE64_LINES / 256;
-    const double* A = M.A64 + M.A_off[c];
-    const double* in = static_cast<const double*>(M.in) + int64_t(b) * M.in_stride + M.comp_off[c];
-    double ra[NA], rx[NX];
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-        const int i = tid + q * 256, r = i / MODE_NMAX, k = i % MODE_NMAX;
-        ra[q] = (r < n && k < n) ? A[r * n + k] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < NX; ++q) {
-        const int i = tid + q * 256;
-        const int j = M.axis == 0 ? i % MODE_NMAX : i / MODE64_LINES;
-        const int l = M.axis == 0 ? i / MODE_NMAX : i % MODE64_LINES;
-        const int lg = l0 + l;
-        rx[q] = (j < n && lg < nlines) ? in[line_base(M.axis, lg, ny, nx) + j * sj] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-        const int i = tid + q * 256;
-        As[i / MODE_NMAX][i % MODE_NMAX] = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < NX; ++q) {
-        const int i = tid + q * 256;
-        const int j = M.axis == 0 ? i % MODE_NMAX : i / MODE64_LINES;
-        const int l = M.axis == 0 ? i / MODE_NMAX : i % MODE64_LINES;
-        Xs[j][l] = rx[q];
-    }
-    __syncthreads();
-    const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-    const int ntile = (n + 15) / 16;
-    constexpr int GROUPS = MODE64_LINES / 16;
-    constexpr int MAXIT = (MODE_NMAX / 16 * GROUPS + 3) / 4;  // items per wave
-    v4d acc[MAXIT];
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) acc[it] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int items = ntile * GROUPS;
-    for (int k0 = 0; k0 < n; k0 += 4) {
-#pragma unroll
-        for (int it = 0; it < MAXIT; ++it) {
-            const int item = w + 4 * it;
-            if (item < items) {
-                const int t = item / GROUPS, g = item % GROUPS;
-                acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[16 * t + lr][k0 + lk], Xs[k0 + lk][16 * g + lr],
-                                                               acc[it], 0, 0, 0);
-            }
-        }
-    }
-    double* out = static_cast<double*>(M.out) + int64_t(b) * M.out_stride + M.comp_off[c];
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-        const int item = w + 4 * it;
-        if (item >= items) continue;
-        const int t = item / GROUPS, g = item % GROUPS;
-        const int lg = l0 + 16 * g + lr;
-        if (lg >= nlines) continue;
-        const int64_t ob = line_base(M.axis, lg, ny, nx);
-        // the FP64 instruction interleaves its result rows: register r of
-        // lane (lk, lr) holds row lk + 4 r (the FP32 one holds 4 lk + r)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = 16 * t + lk + 4 * r;
-            if (i < n) {
-                if (M.out_kind == 2) out[ob + i * sj] += M.alpha * acc[it][r];
-                else out[ob + i * sj] = acc[it][r];
-            }
-        }
-    }
-}
-
 // y -= g(t) s for the tested point sources of each batch member (one
 // workgroup per member; dipoles in order, entries of one dipole in parallel).
 __global__ void __launch_bounds__(256) source_sub_kernel(double* y, int64_t y_stride, const double* entries,
@@ -245,16 +157,6 @@ void launch_mode(const ModeArgs& a, int batch, hipStream_t s) {
     }
     dim3 grid((lines + MODE_LINES - 1) / MODE_LINES, 3, batch);
     hipLaunchKernelGGL(mode_kernel, grid, dim3(256), 0, s, a);
-}
-
-void launch_mode64(const ModeArgs& a, int batch, hipStream_t s) {
-    int lines = 0;
-    for (int c = 0; c < 3; ++c) {
-        const int l = a.dims[c][0] * a.dims[c][1] * a.dims[c][2] / a.dims[c][2 - a.axis];
-        lines = l > lines ? l : lines;
-    }
-    dim3 grid((lines + MODE64_LINES - 1) / MODE64_LINES, 3, batch);
-    hipLaunchKernelGGL(mode64_kernel, grid, dim3(256), 0, s, a);
 }
 
 void launch_source_sub(double* y, int64_t y_stride, const double* entries, const double* prof, const int* off,
