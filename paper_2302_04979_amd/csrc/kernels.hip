@@ -68,6 +68,14 @@ int mass_threads(int p) {
     }
 }
 
+// Patch layout of one component: [tz][ty][lz][ly][tx][lx], the x rows of the
+// tiles along x side by side, so that a row of outputs gathers from
+// contiguous memory.
+template <class L>
+__host__ __device__ inline int64_t patch_at(int nt, int tx, int ty, int tz, int lx, int ly, int lz) {
+    return ((((int64_t(tz) * nt + ty) * L::Wz + lz) * L::Wy + ly) * nt + tx) * L::Wx + lx;
+}
+
 template <int P, int SPACE>
 static int64_t patch_size_t(int ntile, int64_t off[3]) {
     const int64_t nt3 = int64_t(ntile) * ntile * ntile;
@@ -417,7 +425,7 @@ __device__ inline void integrate_x_row(const double* rb, double* xi, const doubl
 // against the y table and writes the column of the tile's patch.
 template <class L, int NQ, int Q>
 __device__ inline void integrate_y_col(const double* xi, double* __restrict__ out, const double* __restrict__ tyt,
-                                       int lane) {
+                                       int lane, int nt, int tx, int ty, int tz) {
     if (lane >= L::Wz * L::Wx) return;
     const int cz = lane / L::Wx, lx = lane - cz * L::Wx;
     const double* col = xi + lane * (Q + 1);
@@ -434,7 +442,7 @@ __device__ inline void integrate_y_col(const double* xi, double* __restrict__ ou
         for (int j = 0; j < L::Ky; ++j) o[le + j] = fma(tyt[q * L::Ky + j], c[q], o[le + j]);
     }
 #pragma unroll
-    for (int ly = 0; ly < L::Wy; ++ly) out[(cz * L::Wy + ly) * L::Wx + lx] = o[ly];
+    for (int ly = 0; ly < L::Wy; ++ly) out[patch_at<L>(nt, tx, ty, tz, lx, ly, cz)] = o[ly];
 }
 
 // MET = 0: the metric w_q DF^T DF / det DF is streamed from memory (any map);
@@ -498,8 +506,9 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
     // ---- per (x, y) column: 1/gamma of its four elements and, for the analytic
     // metric, q = a grad s = (a1 s_z, a2 s_z, a3 c_z) up to the z factors; read
     // here, before the column registers fill up ----
+    // (analytic metric: ig[le] holds w_x w_y / gamma_e, and a12 = a1 + a2)
     double ig[TILE];
-    double a1 = 0.0, a2 = 0.0, a3 = 0.0, wxy = 0.0;
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0, a12 = 0.0;
     if (active) {
         const int ex = tx * TILE + qx / NQ, ey = ty * TILE + qy / NQ;
 #pragma unroll
@@ -513,7 +522,10 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
             a1 = A.amp * M_PI * cx * sy;
             a2 = A.amp * M_PI * sx * cy;
             a3 = A.amp * M_PI * sx * sy;
-            wxy = wx * wy;
+            a12 = a1 + a2;
+            const double wxy = wx * wy;
+#pragma unroll
+            for (int le = 0; le < TILE; ++le) ig[le] *= wxy;
         }
     }
 
@@ -608,14 +620,15 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
                 // analytic metric: with q = a grad s, DF = I + 1 q^T, det DF = 1 + q.1 and
                 // w DF^T DF / det DF = f (I + q 1^T + 1 q^T + 3 q q^T), f = w / det DF,
                 // applied below as a rank-2 update of the identity
-                double q1 = 0.0, q2 = 0.0, q3 = 0.0, f = 0.0;
+                double q1 = 0.0, q2 = 0.0, q3 = 0.0, sf = 0.0;
                 if (MET == 1) {
                     const int gzq = tz * TILE * NQ + qz;
                     const double sz = axt[gzq], cz = axt[npq + gzq], wz = axt[2 * npq + gzq];
                     q1 = a1 * sz;
                     q2 = a2 * sz;
                     q3 = a3 * cz;
-                    f = wxy * wz * recip_nr(1.0 + (q1 + q2 + q3));
+                    // s f = (w / gamma_e) / det DF, det DF = 1 + (a1 + a2) s_z + a3 c_z
+                    sf = (ig[le] * wz) * recip_nr(fma(a12, sz, fma(a3, cz, 1.0)));
                 }
                 const double* t0 = tz0 + qz * L0::Kz;
                 const double* t2 = tz2 + qz * L2::Kz;
@@ -626,16 +639,17 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
                 for (int j = 0; j < L1::Kz; ++j) v1 += t0[j] * A1[le + j];
 #pragma unroll
                 for (int j = 0; j < L2::Kz; ++j) v2 += t2[j] * A2[le + j];
-                const double s = ig[le];
                 double u0, u1, u2;
                 if (MET == 1) {
-                    // G v = f (v + (S + 3 Q) q + Q 1), S = sum v, Q = q . v
-                    const double Qv = q1 * v0 + q2 * v1 + q3 * v2;
-                    const double cq = fma(3.0, Qv, v0 + v1 + v2), sf = s * f;
-                    u0 = sf * (v0 + fma(cq, q1, Qv));
-                    u1 = sf * (v1 + fma(cq, q2, Qv));
-                    u2 = sf * (v2 + fma(cq, q3, Qv));
+                    // G v = f (v + (S + 3 Q) q + Q 1), S = sum v, Q = q . v, as
+                    // u = sf v + (sf (S + 3 Q)) q + sf Q 1
+                    const double Qv = fma(q1, v0, fma(q2, v1, q3 * v2));
+                    const double cq = sf * fma(3.0, Qv, v0 + v1 + v2), bq = sf * Qv;
+                    u0 = fma(sf, v0, fma(cq, q1, bq));
+                    u1 = fma(sf, v1, fma(cq, q2, bq));
+                    u2 = fma(sf, v2, fma(cq, q3, bq));
                 } else {
+                    const double s = ig[le];
                     u0 = s * (g[0] * v0 + g[3] * v1 + g[4] * v2);
                     u1 = s * (g[3] * v0 + g[1] * v1 + g[5] * v2);
                     u2 = s * (g[4] * v0 + g[5] * v1 + g[2] * v2);
@@ -680,14 +694,14 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
     __syncthreads();
     double* out = A.patch + int64_t(b) * A.patch_stride;
     if (wave == 0)
-        integrate_y_col<L0, NQ, Q>(sm + OY0, out + A.patch_comp_off[0] + int64_t(tile) * L0::size,
-                                   axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane);
+        integrate_y_col<L0, NQ, Q>(sm + OY0, out + A.patch_comp_off[0], axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty),
+                                   lane, nt, tx, ty, tz);
     else if (wave == 1)
-        integrate_y_col<L1, NQ, Q>(sm + OY1, out + A.patch_comp_off[1] + int64_t(tile) * L1::size,
-                                   axis_table<P, SPACE, 1, 0>(tabg, A.tab_off, ty), lane);
+        integrate_y_col<L1, NQ, Q>(sm + OY1, out + A.patch_comp_off[1], axis_table<P, SPACE, 1, 0>(tabg, A.tab_off, ty),
+                                   lane, nt, tx, ty, tz);
     else if (wave == 2)
-        integrate_y_col<L2, NQ, Q>(sm + OY2, out + A.patch_comp_off[2] + int64_t(tile) * L2::size,
-                                   axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane);
+        integrate_y_col<L2, NQ, Q>(sm + OY2, out + A.patch_comp_off[2], axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty),
+                                   lane, nt, tx, ty, tz);
 }
 
 template <int P, int SPACE, bool CURL>
@@ -749,8 +763,7 @@ __device__ inline double gather_one(const double* __restrict__ patch, int nt, in
             for (int dx = 1; dx >= 0; --dx) {
                 const int tx = hx - dx, lx = rx - tx * TILE;
                 if (tx < 0 || lx >= L::Wx) continue;
-                const int64_t tile = (int64_t(tz) * nt + ty) * nt + tx;
-                s += patch[tile * L::size + (lz * L::Wy + ly) * L::Wx + lx];
+                s += patch[patch_at<L>(nt, tx, ty, tz, lx, ly, lz)];
             }
         }
     }
