@@ -219,19 +219,32 @@ __device__ inline int owner_tile(int g, int nt) {
     return t > nt - 1 ? nt - 1 : t;
 }
 
-// track[g] += alpha * v for the window entry (lx, ly, lz) of value v, if this
-// tile owns it
-template <class L>
-__device__ inline void track_at(double* __restrict__ tr, const int dims[3], double v, double alpha, int tx, int ty,
-                                int tz, int nt, int lx, int ly, int lz) {
+// The entries of the y column (lx, ., lz) of a component window that this tile
+// owns: their offsets in the tracked component (-1 where not owned) and their
+// current values, requested at the start of the tile so that the update in
+// the y pass does not wait for them.
+template <class L, int NY>
+__device__ inline void track_column_load(const double* __restrict__ tr, const int dims[3], int tx, int ty, int tz,
+                                         int nt, int lane, int (&k)[NY], double (&v)[NY]) {
+#pragma unroll
+    for (int ly = 0; ly < NY; ++ly) {
+        k[ly] = -1;
+        v[ly] = 0.0;
+    }
+    if (lane >= L::Wz * L::Wx) return;
+    const int lz = lane / L::Wx, lx = lane - lz * L::Wx;
     const int gx = tx * TILE + tag_offset(L::tx) + lx;
-    const int gy = ty * TILE + tag_offset(L::ty) + ly;
     const int gz = tz * TILE + tag_offset(L::tz) + lz;
-    if (gx < 0 || gx >= dims[2] || gy < 0 || gy >= dims[1] || gz < 0 || gz >= dims[0]) return;
-    if (owner_tile<L::tx>(gx, nt) != tx || owner_tile<L::ty>(gy, nt) != ty || owner_tile<L::tz>(gz, nt) != tz)
-        return;
-    const int64_t k = (int64_t(gz) * dims[1] + gy) * dims[2] + gx;
-    tr[k] += alpha * v;
+    if (gx < 0 || gx >= dims[2] || gz < 0 || gz >= dims[0]) return;
+    if (owner_tile<L::tx>(gx, nt) != tx || owner_tile<L::tz>(gz, nt) != tz) return;
+#pragma unroll
+    for (int ly = 0; ly < L::Wy; ++ly) {
+        const int gy = ty * TILE + tag_offset(L::ty) + ly;
+        if (gy >= 0 && gy < dims[1] && owner_tile<L::ty>(gy, nt) == ty) {
+            k[ly] = (gz * dims[1] + gy) * dims[2] + gx;
+            v[ly] = tr[k[ly]];
+        }
+    }
 }
 
 // Table slot of axis a: 0 = the tag of the component along a, 1 = the tag of
@@ -350,10 +363,10 @@ struct MassPitch {
 // component's window at (lx, cz) -- formed from the 1-form windows when the
 // curl is fused -- adds the entries this tile owns to the tracked 2-form, and
 // contracts the column along y: yc[cz][qy][lx] = sum_j T_y[qy][j] x[le(qy) + j].
-template <int P, int SRC, int SPACE, int C, bool CURL, int NQ, int Q>
+template <int P, int SRC, int SPACE, int C, bool CURL, int NQ, int Q, int NY>
 __device__ inline void forward_y(const double* s0, const double* s1, const double* s2, const double* xw,
                                  double* yc, const double* __restrict__ tyt, int lane, double* __restrict__ tr,
-                                 const MassArgs& A, int tx, int ty, int tz, int nt) {
+                                 const MassArgs& A, const int (&tk)[NY], const double (&tv)[NY]) {
     using L = Lay<P, SPACE, C>;
     using PT = MassPitch<L, Q>;
     if (lane >= L::Wz * L::Wx) return;
@@ -363,9 +376,10 @@ __device__ inline void forward_y(const double* s0, const double* s1, const doubl
     for (int ly = 0; ly < L::Wy; ++ly)
         x[ly] = CURL ? curl_xyz<P, SRC, SPACE, C>(s0, s1, s2, lx, ly, cz) : xw[(cz * L::Wy + ly) * L::Wx + lx];
     if (CURL && tr) {
+        double* t = tr + A.track_comp_off[C];
 #pragma unroll
         for (int ly = 0; ly < L::Wy; ++ly)
-            track_at<L>(tr + A.track_comp_off[C], A.track_dims[C], x[ly], A.track_alpha, tx, ty, tz, nt, lx, ly, cz);
+            if (tk[ly] >= 0) t[tk[ly]] = tv[ly] + A.track_alpha * x[ly];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -529,6 +543,18 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
         }
     }
 
+    // ---- tracked 2-form entries owned by this tile, one wave per component ----
+    constexpr int WYM = L0::Wy > L1::Wy ? (L0::Wy > L2::Wy ? L0::Wy : L2::Wy) : (L1::Wy > L2::Wy ? L1::Wy : L2::Wy);
+    double* tr = (CURL && A.track) ? A.track + int64_t(b) * A.track_stride : nullptr;
+    int tk[WYM];
+    double tv[WYM];
+    if (tr && wave == 0)
+        track_column_load<L0, WYM>(tr + A.track_comp_off[0], A.track_dims[0], tx, ty, tz, nt, lane, tk, tv);
+    else if (tr && wave == 1)
+        track_column_load<L1, WYM>(tr + A.track_comp_off[1], A.track_dims[1], tx, ty, tz, nt, lane, tk, tv);
+    else if (tr && wave == 2)
+        track_column_load<L2, WYM>(tr + A.track_comp_off[2], A.track_dims[2], tx, ty, tz, nt, lane, tk, tv);
+
     // ---- x and z tables of the tile: [axis x, z][slot][element][point][function] ----
     {
         constexpr int ST = (4 * TSL + NT - 1) / NT;
@@ -559,7 +585,6 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
 
     // ---- part 1a: y contraction of the windows, one wave per component ----
     {
-        double* tr = (CURL && A.track) ? A.track + int64_t(b) * A.track_stride : nullptr;
         const double* s0 = sm + OR;
         const double* s1 = s0 + S0::size;
         const double* s2 = s1 + S1::size;
@@ -569,15 +594,15 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
         if (wave == 0)
             forward_y<P, SRC, SPACE, 0, CURL, NQ, Q>(s0, s1, s2, x0, sm + OY0,
                                                      axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane, tr, A,
-                                                     tx, ty, tz, nt);
+                                                     tk, tv);
         else if (wave == 1)
             forward_y<P, SRC, SPACE, 1, CURL, NQ, Q>(s0, s1, s2, x1, sm + OY1,
                                                      axis_table<P, SPACE, 1, 0>(tabg, A.tab_off, ty), lane, tr, A,
-                                                     tx, ty, tz, nt);
+                                                     tk, tv);
         else if (wave == 2)
             forward_y<P, SRC, SPACE, 2, CURL, NQ, Q>(s0, s1, s2, x2, sm + OY2,
                                                      axis_table<P, SPACE, 1, 1>(tabg, A.tab_off, ty), lane, tr, A,
-                                                     tx, ty, tz, nt);
+                                                     tk, tv);
     }
     __syncthreads();
 
