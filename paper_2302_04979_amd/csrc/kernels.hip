@@ -1264,8 +1264,10 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
             const double* src = A.fac + A.fac_off[A.fac_id[mode][c][a]] + 2 * int64_t(n) * W + n;
 #pragma unroll
             for (int q = 0; q < SB; ++q) {
+                // branch-free: load from an index inside the array, then select
                 const int i = tid + 256 * q;
-                r[a][q] = i < n * B ? src[i] : 0.0;
+                const double t = src[i < n * B ? i : 0];
+                r[a][q] = i < n * B ? t : 0.0;
             }
         }
 #pragma unroll
@@ -1290,8 +1292,9 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
 #pragma unroll
             for (int k = 0; k < B; ++k) {
                 const int zz = z - W + k;
-                vz[q][k] = (i < TR * nx && y >= 0 && y < ny && zz >= 0 && zz < nz)
-                               ? v[(int64_t(zz) * ny + y) * nx + x] : 0.0;
+                const bool ok = i < TR * nx && y >= 0 && y < ny && zz >= 0 && zz < nz;
+                const double t = v[ok ? (zz * ny + y) * nx + x : 0];
+                vz[q][k] = ok ? t : 0.0;
             }
         }
 #pragma unroll
@@ -1316,8 +1319,10 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
             const int r = i / nx, x = i % nx;
 #pragma unroll
             for (int k = 0; k < B; ++k) {
-                const int xx = x - W + k;
-                if (xx >= 0 && xx < nx) t[q] += band[0][x * B + k] * tile[r * KMX_LINE_MAX + xx];
+                // the band is zero outside the matrix: a clamped index adds nothing
+                int xx = x - W + k;
+                xx = xx < 0 ? 0 : (xx > nx - 1 ? nx - 1 : xx);
+                t[q] += band[0][x * B + k] * tile[r * KMX_LINE_MAX + xx];
             }
         }
     }
@@ -1358,8 +1363,9 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
             double w = 0.0;
 #pragma unroll
             for (int k = 0; k < B; ++k) {
-                const int yy = y - W + k;
-                if (yy >= 0 && yy < ny) w += band[1][y * B + k] * tile[(ry + k) * KMX_LINE_MAX + x];
+                // rows of the tile outside the field hold finite values and
+                // meet zero band entries
+                w += band[1][y * B + k] * tile[(ry + k) * KMX_LINE_MAX + x];
             }
             if (mode == 0) {
                 s0 += w * pb[q];
