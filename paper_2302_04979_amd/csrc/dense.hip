@@ -56,14 +56,24 @@ struct Staged {
 };
 
 // One workgroup per (z plane, component, batch member): Y = B_y X B_x^T with
-// X the plane less the point sources on it.  Output tiles (16 x 16) are dealt
-// to the four waves, NJ per wave (the largest component's count); a wave's
-// tiles past its component's count repeat its last tile and are not stored,
-// so the products run without branches and the accumulators stay in the
-// matrix registers.  T = X B_x^T overwrites X in LDS.
-template <int NJ>
+// X the plane less the point sources on it, for planes of up to T = 5 tiles
+// of 16 per axis (KB = 4-wide k steps: the largest component's count; a
+// smaller component adds zero rows and columns).  The 16 x 16 output tiles
+// are dealt so that each wave needs only two tiles of the factor, which it
+// keeps in registers for the whole product:
+//   T = X B_x^T: wave w owns output column tile w (every row tile) and, with
+//       T = 5, row tile w of column tile 4 (wave 0 also row tile 4);
+//   Y = B_y T:   wave w owns output row tile w (every column tile) and, with
+//       T = 5, column tile w of row tile 4 (wave 0 also column tile 4).
+// Per k step a wave reads one LDS operand per row (column) tile plus one,
+// and no factor from LDS.  T = X B_x^T overwrites X in LDS.
+template <int KB>
 __global__ void __launch_bounds__(256) dense_xy_kernel(const DenseArgs A) {
-    extern __shared__ double smem[];
+    constexpr int T = (KB + 3) / 4;
+    constexpr int SH = T == 5 ? 1 : 0;  // the fifth tile row / column, shared by the waves
+    static_assert(T <= 5, "planes of at most 80 x 80");
+    constexpr int R = 16 * T, P = 16 * T + 1;  // plane rows and (odd) pitch in LDS
+    extern __shared__ double X[];
     const int c = blockIdx.y, b = blockIdx.z, iz = blockIdx.x;
     const int nz = A.dims[c][0], ny = A.dims[c][1], nx = A.dims[c][2];
     if (iz >= nz) return;
@@ -71,15 +81,17 @@ __global__ void __launch_bounds__(256) dense_xy_kernel(const DenseArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lk = lane >> 4;
     const int tyn = (ny + 15) / 16, txn = (nx + 15) / 16, kbx = (nx + 3) / 4, kby = (ny + 3) / 4;
-    const int P = dense_xy_pitch(nx), R = dense_xy_rows(ny);
-    double* X = smem;
-    double* Fx = X + R * P;
-    double* Fy = Fx + dense_frag_size(nx);
+    // factor tiles of this wave (indices clamped inside the factor; their
+    // products with the zero padding add nothing)
+    const int own_x = wv < txn ? wv : txn - 1, own_y = wv < tyn ? wv : tyn - 1;
+    const double* Fx = A.frag + A.frag_off[c][0];
+    const double* Fy = A.frag + A.frag_off[c][1];
+    double bx[1 + SH][KB], by[1 + SH][KB];
     {
         // the plane (zero padded to R rows and P columns; rows over the waves)
-        // and both factors, all loads in flight together
+        // and the factor tiles, all loads in flight together
         const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c] + int64_t(iz) * nx * ny;
-        constexpr int RB = DENSE_NMAX / 4;
+        constexpr int RB = R / 4;
         double r0[RB], r1[RB];
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
@@ -87,19 +99,22 @@ __global__ void __launch_bounds__(256) dense_xy_kernel(const DenseArgs A) {
             r0[k] = (y < ny && lane < nx) ? in[y * nx + lane] : 0.0;
             r1[k] = (y < ny && lane + 64 < nx) ? in[y * nx + lane + 64] : 0.0;
         }
-        Staged<FRAG_SLOTS> fx, fy;
-        fx.load(A.frag + A.frag_off[c][0], dense_frag_size(nx), tid);
-        fy.load(A.frag + A.frag_off[c][1], dense_frag_size(ny), tid);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const int kx = kb < kbx ? kb : kbx - 1, ky = kb < kby ? kb : kby - 1;
+            bx[0][kb] = Fx[(own_x * kbx + kx) * 64 + lane];
+            by[0][kb] = Fy[(own_y * kby + ky) * 64 + lane];
+            if (SH) {
+                bx[SH][kb] = Fx[((txn - 1) * kbx + kx) * 64 + lane];
+                by[SH][kb] = Fy[((tyn - 1) * kby + ky) * 64 + lane];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
             const int y = wv + 4 * k;
-            if (y < R) {
-                if (lane < P) X[y * P + lane] = r0[k];
-                if (lane + 64 < P) X[y * P + lane + 64] = r1[k];
-            }
+            if (lane < P) X[y * P + lane] = r0[k];
+            if (lane + 64 < P) X[y * P + lane + 64] = r1[k];
         }
-        fx.store(Fx, dense_frag_size(nx), tid);
-        fy.store(Fy, dense_frag_size(ny), tid);
     }
     __syncthreads();
     if (A.n_src > 0) {
@@ -118,48 +133,88 @@ __global__ void __launch_bounds__(256) dense_xy_kernel(const DenseArgs A) {
         }
         __syncthreads();
     }
-    const int items = tyn * txn;
-    int tr[NJ], tc[NJ];
+    // validity of the shared tiles for this component (a smaller component
+    // may have fewer than five)
+    const bool sh_x = SH && txn == T, sh_y = SH && tyn == T;
+    v4d acc[T], acs, ace;  // own tiles, the shared tile, wave 0's corner tile
+    // ---- T = X B_x^T: T[y][i] = sum_x X[y][x] B_x[i][x] ----
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        int it = wv + 4 * j;
-        it = it < items ? it : (items - 1 - ((items - 1 - wv) & 3));  // this wave's last tile
-        tr[j] = it / txn;
-        tc[j] = it - tr[j] * txn;
-    }
-    v4d acc[NJ];
+    for (int t = 0; t < T; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    acs = ace = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-    // T = X B_x^T: T[y][i] = sum_x X[y][x] B_x[i][x]
-    for (int kb = 0; kb < kbx; ++kb) {
+    for (int kb = 0; kb < KB; ++kb) {
+        double xa[T];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            acc[j] = mfma64(X[(16 * tr[j] + lr) * P + 4 * kb + lk], Fx[(tc[j] * kbx + kb) * 64 + lane], acc[j]);
+        for (int t = 0; t < T; ++t) xa[t] = X[(16 * t + lr) * P + 4 * kb + lk];
+        const double xw = X[(16 * wv + lr) * P + 4 * kb + lk];
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = mfma64(xa[t], bx[0][kb], acc[t]);
+        if (SH) {
+            acs = mfma64(xw, bx[SH][kb], acs);
+            if (wv == 0) ace = mfma64(xa[T - 1], bx[SH][kb], ace);
+        }
     }
     __syncthreads();  // every wave is done with X
+    if (wv < txn) {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        // a repeated tile stores the same values again: harmless
+        for (int t = 0; t < T; ++t)
+            if (t < tyn) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) X[(16 * tr[j] + lk + 4 * r) * P + 16 * tc[j] + lr] = acc[j][r];
-        acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+                for (int r = 0; r < 4; ++r) X[(16 * t + lk + 4 * r) * P + 16 * wv + lr] = acc[t][r];
+            }
+    }
+    if (SH && sh_x && wv < tyn) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[(16 * wv + lk + 4 * r) * P + 16 * (T - 1) + lr] = acs[r];
+    }
+    if (SH && sh_x && sh_y && wv == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[(16 * (T - 1) + lk + 4 * r) * P + 16 * (T - 1) + lr] = ace[r];
     }
     __syncthreads();
-    // Y = B_y T: Y[o][i] = sum_y B_y[o][y] T[y][i]  (rows of T past ny are zero)
-    for (int kb = 0; kb < kby; ++kb) {
+    // ---- Y = B_y T: Y[o][i] = sum_y B_y[o][y] T[y][i] (rows of T past ny are zero) ----
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            acc[j] = mfma64(Fy[(tr[j] * kby + kb) * 64 + lane], X[(4 * kb + lk) * P + 16 * tc[j] + lr], acc[j]);
+    for (int t = 0; t < T; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    acs = ace = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        double ta[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) ta[t] = X[(4 * kb + lk) * P + 16 * t + lr];
+        const double tw = X[(4 * kb + lk) * P + 16 * wv + lr];
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = mfma64(by[0][kb], ta[t], acc[t]);
+        if (SH) {
+            acs = mfma64(by[SH][kb], tw, acs);
+            if (wv == 0) ace = mfma64(by[SH][kb], ta[T - 1], ace);
+        }
     }
     double* out = A.out + int64_t(b) * A.out_stride + A.comp_off[c] + int64_t(iz) * nx * ny;
+    if (wv < tyn) {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        if (wv + 4 * j >= items) continue;
-        const int i = 16 * tc[j] + lr;
+        for (int t = 0; t < T; ++t) {
+            const int i = 16 * t + lr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = 16 * wv + lk + 4 * r;
+                if (t < txn && o < ny && i < nx) out[o * nx + i] = acc[t][r];
+            }
+        }
+    }
+    if (SH && sh_y && wv < txn) {
+        const int i = 16 * wv + lr;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int o = 16 * tr[j] + lk + 4 * r;
-            if (o < ny && i < nx) out[o * nx + i] = acc[j][r];
+            const int o = 16 * (T - 1) + lk + 4 * r;
+            if (o < ny && i < nx) out[o * nx + i] = acs[r];
+        }
+    }
+    if (SH && sh_x && sh_y && wv == 0) {
+        const int i = 16 * (T - 1) + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 16 * (T - 1) + lk + 4 * r;
+            if (o < ny && i < nx) out[o * nx + i] = ace[r];
         }
     }
 }
@@ -240,14 +295,20 @@ __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
     }
 }
 
+// k steps and plane LDS of the plane kernel for a field's components
+int xy_kb(const int dims[3][3]) {
+    int kb = 0;
+    for (int c = 0; c < 3; ++c)
+        for (int a = 1; a <= 2; ++a) {
+            const int k = (dims[c][a] + 3) / 4;
+            kb = k > kb ? k : kb;
+        }
+    return kb;
+}
+
 size_t xy_lds(const int dims[3][3]) {
-    size_t m = 0;
-    for (int c = 0; c < 3; ++c) {
-        const int ny = dims[c][1], nx = dims[c][2];
-        const size_t s = size_t(dense_xy_rows(ny)) * dense_xy_pitch(nx) + dense_frag_size(nx) + dense_frag_size(ny);
-        m = s > m ? s : m;
-    }
-    return m * sizeof(double);
+    const int t = (xy_kb(dims) + 3) / 4;
+    return size_t(16 * t) * (16 * t + 1) * sizeof(double);
 }
 
 size_t z_lds(const int dims[3][3]) {
@@ -279,11 +340,14 @@ size_t dense_lds_bytes(const int dims[3][3]) {
     return a > b ? a : b;
 }
 
-template <int NJ>
+template <int KB>
 hipError_t raise_xy(size_t shm) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_xy_kernel<NJ>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_xy_kernel<KB>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
 }
+
+#define DENSE_KB_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 
 template <int TZ>
 hipError_t raise_z(size_t shm) {
@@ -292,31 +356,28 @@ hipError_t raise_z(size_t shm) {
 }
 
 hipError_t dense_prepare(size_t shm) {
-    const hipError_t e[] = {raise_xy<1>(shm), raise_xy<2>(shm), raise_xy<3>(shm), raise_xy<4>(shm),
-                            raise_xy<5>(shm), raise_xy<6>(shm), raise_xy<7>(shm), raise_z<1>(shm),
-                            raise_z<2>(shm),  raise_z<3>(shm),  raise_z<4>(shm),  raise_z<5>(shm)};
-    for (hipError_t x : e)
-        if (x != hipSuccess) return x;
-    return hipSuccess;
+    hipError_t e = hipSuccess;
+#define RAISE(K) \
+    if (e == hipSuccess) e = raise_xy<K>(shm);
+    DENSE_KB_CASES(RAISE)
+#undef RAISE
+    const hipError_t ez[] = {raise_z<1>(shm), raise_z<2>(shm), raise_z<3>(shm), raise_z<4>(shm), raise_z<5>(shm)};
+    for (hipError_t x : ez)
+        if (e == hipSuccess) e = x;
+    return e;
 }
 
 void launch_dense_xy(const DenseArgs& a, int batch, hipStream_t s) {
-    int nzmax = 0, items = 0;
-    for (int c = 0; c < 3; ++c) {
-        nzmax = a.dims[c][0] > nzmax ? a.dims[c][0] : nzmax;
-        const int it = ((a.dims[c][1] + 15) / 16) * ((a.dims[c][2] + 15) / 16);
-        items = it > items ? it : items;
-    }
+    int nzmax = 0;
+    for (int c = 0; c < 3; ++c) nzmax = a.dims[c][0] > nzmax ? a.dims[c][0] : nzmax;
     const dim3 grid(nzmax, 3, batch);
     const size_t shm = xy_lds(a.dims);
-    switch ((items + 3) / 4) {
-        case 1: hipLaunchKernelGGL(dense_xy_kernel<1>, grid, dim3(256), shm, s, a); break;
-        case 2: hipLaunchKernelGGL(dense_xy_kernel<2>, grid, dim3(256), shm, s, a); break;
-        case 3: hipLaunchKernelGGL(dense_xy_kernel<3>, grid, dim3(256), shm, s, a); break;
-        case 4: hipLaunchKernelGGL(dense_xy_kernel<4>, grid, dim3(256), shm, s, a); break;
-        case 5: hipLaunchKernelGGL(dense_xy_kernel<5>, grid, dim3(256), shm, s, a); break;
-        case 6: hipLaunchKernelGGL(dense_xy_kernel<6>, grid, dim3(256), shm, s, a); break;
-        default: hipLaunchKernelGGL(dense_xy_kernel<7>, grid, dim3(256), shm, s, a); break;
+    switch (xy_kb(a.dims)) {
+#define LAUNCH(K) \
+    case K: hipLaunchKernelGGL(dense_xy_kernel<K>, grid, dim3(256), shm, s, a); break;
+        DENSE_KB_CASES(LAUNCH)
+#undef LAUNCH
+        default: break;
     }
 }
 
