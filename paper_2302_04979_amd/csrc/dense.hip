@@ -20,7 +20,6 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int DMAX_T = DENSE_NMAX / 16;  // output tiles per axis
 
 __device__ inline v4d mfma64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -30,30 +29,6 @@ __device__ inline v4d mfma64(double a, double b, v4d c) {
 __host__ __device__ inline int dense_xy_pitch(int nx) { return 16 * ((nx + 15) / 16) + 1; }
 __host__ __device__ inline int dense_xy_rows(int ny) { return 16 * ((ny + 15) / 16); }
 __host__ __device__ inline int dense_frag_size(int n) { return ((n + 15) / 16) * ((n + 3) / 4) * 64; }
-
-// Staging global -> LDS in one round: the loads of every slot (up to S per
-// thread) are issued before the first store, so a workgroup pays one memory
-// latency for all of its operands.
-constexpr int FRAG_SLOTS = (DMAX_T * (DENSE_NMAX / 4) * 64 + 255) / 256;  // one factor, per thread
-
-template <int S>
-struct Staged {
-    double r[S];
-    __device__ inline void load(const double* __restrict__ src, int n, int tid) {
-#pragma unroll
-        for (int u = 0; u < S; ++u) {
-            const int i = u * 256 + tid;
-            r[u] = i < n ? src[i] : 0.0;
-        }
-    }
-    __device__ inline void store(double* dst, int n, int tid) const {
-#pragma unroll
-        for (int u = 0; u < S; ++u) {
-            const int i = u * 256 + tid;
-            if (i < n) dst[i] = r[u];
-        }
-    }
-};
 
 // One workgroup per (z plane, component, batch member): Y = B_y X B_x^T with
 // X the plane less the point sources on it, for planes of up to T = 5 tiles
@@ -220,13 +195,17 @@ __global__ void __launch_bounds__(256) dense_xy_kernel(const DenseArgs A) {
 }
 
 // One workgroup per 64 (x, y) columns of a component: out = (accumulate ? out
-// : 0) + alpha B_z X over the columns.  Wave w owns the 16 columns 16 w ..
-// 16 w + 15 and the TZ 16-row tiles of the output (the largest component's
-// count; a component with fewer repeats its last tile without storing it), so
-// each operand of X it reads serves all of its tiles.
-template <int TZ>
+// : 0) + alpha B_z X over the columns, KB k steps (the largest component's;
+// rows past a component's nz are zero).  Wave w owns the 16 columns 16 w ..
+// 16 w + 15 and every 16-row tile of the output; the B_z tiles (the left
+// operands) stay in its registers, read from L2 together with the columns and
+// the accumulated output, so a k step reads one operand from LDS for TZ
+// products.
+template <int KB>
 __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
-    extern __shared__ double smem[];
+    constexpr int TZ = (KB + 3) / 4;
+    constexpr int P = 65;
+    extern __shared__ double X[];  // [4 KB][P]
     const int c = blockIdx.y, b = blockIdx.z;
     const int nz = A.dims[c][0], ny = A.dims[c][1], nx = A.dims[c][2];
     const int64_t ncol = int64_t(nx) * ny;
@@ -235,52 +214,46 @@ __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 15, lk = lane >> 4;
     const int tzn = (nz + 15) / 16, kbz = (nz + 3) / 4;
-    constexpr int P = 65;
-    double* X = smem;                 // [4 kbz][P]
-    double* Fz = X + 4 * kbz * P;
     double* out = A.out + int64_t(b) * A.out_stride + A.comp_off[c];
     const int64_t col = col0 + 16 * wv + lr;
-    // the accumulated output is requested first: it is not needed until the end
-    double o[TZ][4];
-#pragma unroll
-    for (int t = 0; t < TZ; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int z = 16 * t + lk + 4 * r;
-            o[t][r] = (A.accumulate && col < ncol && z < nz) ? out[int64_t(z) * ncol + col] : 0.0;
-        }
+    const double* Fz = A.frag + A.frag_off[c][2];
+    double o[TZ][4], fa[TZ][KB];
     {
-        // the columns (rows z over the waves) and the factor, all loads in flight together
+        // the accumulated output, the factor tiles and the columns (rows z over
+        // the waves), all loads in flight together
+#pragma unroll
+        for (int t = 0; t < TZ; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int z = 16 * t + lk + 4 * r;
+                o[t][r] = (A.accumulate && col < ncol && z < nz) ? out[int64_t(z) * ncol + col] : 0.0;
+            }
+#pragma unroll
+        for (int t = 0; t < TZ; ++t) {
+            const int tc = t < tzn ? t : tzn - 1;  // inside the factor; the zero rows meet it
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) fa[t][kb] = Fz[(tc * kbz + (kb < kbz ? kb : kbz - 1)) * 64 + lane];
+        }
         const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c];
         const bool ok = col0 + lane < ncol;
-        constexpr int RB = DENSE_NMAX / 4;
-        double r[RB];
+        double r[KB];
 #pragma unroll
-        for (int k = 0; k < RB; ++k) {
+        for (int k = 0; k < KB; ++k) {
             const int z = wv + 4 * k;
             r[k] = (ok && z < nz) ? in[int64_t(z) * ncol + col0 + lane] : 0.0;
         }
-        Staged<FRAG_SLOTS> fz;
-        fz.load(A.frag + A.frag_off[c][2], dense_frag_size(nz), tid);
 #pragma unroll
-        for (int k = 0; k < RB; ++k) {
-            const int z = wv + 4 * k;
-            if (z < 4 * kbz) X[z * P + lane] = r[k];
-        }
-        fz.store(Fz, dense_frag_size(nz), tid);
+        for (int k = 0; k < KB; ++k) X[(wv + 4 * k) * P + lane] = r[k];
     }
     __syncthreads();
     v4d acc[TZ];
-    int tt[TZ];
 #pragma unroll
-    for (int t = 0; t < TZ; ++t) {
-        acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-        tt[t] = t < tzn ? t : tzn - 1;
-    }
-    for (int kb = 0; kb < kbz; ++kb) {
+    for (int t = 0; t < TZ; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
         const double xb = X[(4 * kb + lk) * P + 16 * wv + lr];
 #pragma unroll
-        for (int t = 0; t < TZ; ++t) acc[t] = mfma64(Fz[(tt[t] * kbz + kb) * 64 + lane], xb, acc[t]);
+        for (int t = 0; t < TZ; ++t) acc[t] = mfma64(fa[t][kb], xb, acc[t]);
     }
     if (col >= ncol) return;
     const double alpha = A.alpha;
@@ -311,15 +284,16 @@ size_t xy_lds(const int dims[3][3]) {
     return size_t(16 * t) * (16 * t + 1) * sizeof(double);
 }
 
-size_t z_lds(const int dims[3][3]) {
-    size_t m = 0;
+int z_kb(const int dims[3][3]) {
+    int kb = 0;
     for (int c = 0; c < 3; ++c) {
-        const int nz = dims[c][0];
-        const size_t s = size_t(4 * ((nz + 3) / 4)) * 65 + dense_frag_size(nz);
-        m = s > m ? s : m;
+        const int k = (dims[c][0] + 3) / 4;
+        kb = k > kb ? k : kb;
     }
-    return m * sizeof(double);
+    return kb;
 }
+
+size_t z_lds(const int dims[3][3]) { return size_t(4 * z_kb(dims)) * 65 * sizeof(double); }
 
 }  // namespace
 
@@ -349,21 +323,19 @@ hipError_t raise_xy(size_t shm) {
 #define DENSE_KB_CASES(X) \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 
-template <int TZ>
+template <int KB>
 hipError_t raise_z(size_t shm) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_z_kernel<TZ>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_z_kernel<KB>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
 }
 
 hipError_t dense_prepare(size_t shm) {
     hipError_t e = hipSuccess;
 #define RAISE(K) \
-    if (e == hipSuccess) e = raise_xy<K>(shm);
+    if (e == hipSuccess) e = raise_xy<K>(shm); \
+    if (e == hipSuccess) e = raise_z<K>(shm);
     DENSE_KB_CASES(RAISE)
 #undef RAISE
-    const hipError_t ez[] = {raise_z<1>(shm), raise_z<2>(shm), raise_z<3>(shm), raise_z<4>(shm), raise_z<5>(shm)};
-    for (hipError_t x : ez)
-        if (e == hipSuccess) e = x;
     return e;
 }
 
@@ -383,21 +355,18 @@ void launch_dense_xy(const DenseArgs& a, int batch, hipStream_t s) {
 
 void launch_dense_z(const DenseArgs& a, int batch, hipStream_t s) {
     int64_t cmax = 0;
-    int tz = 0;
     for (int c = 0; c < 3; ++c) {
         const int64_t n = int64_t(a.dims[c][1]) * a.dims[c][2];
         cmax = n > cmax ? n : cmax;
-        const int t = (a.dims[c][0] + 15) / 16;
-        tz = t > tz ? t : tz;
     }
     const dim3 grid(unsigned((cmax + 63) / 64), 3, batch);
     const size_t shm = z_lds(a.dims);
-    switch (tz) {
-        case 1: hipLaunchKernelGGL(dense_z_kernel<1>, grid, dim3(256), shm, s, a); break;
-        case 2: hipLaunchKernelGGL(dense_z_kernel<2>, grid, dim3(256), shm, s, a); break;
-        case 3: hipLaunchKernelGGL(dense_z_kernel<3>, grid, dim3(256), shm, s, a); break;
-        case 4: hipLaunchKernelGGL(dense_z_kernel<4>, grid, dim3(256), shm, s, a); break;
-        default: hipLaunchKernelGGL(dense_z_kernel<5>, grid, dim3(256), shm, s, a); break;
+    switch (z_kb(a.dims)) {
+#define LAUNCH(K) \
+    case K: hipLaunchKernelGGL(dense_z_kernel<K>, grid, dim3(256), shm, s, a); break;
+        DENSE_KB_CASES(LAUNCH)
+#undef LAUNCH
+        default: break;
     }
 }
 
