@@ -202,10 +202,6 @@ size_t dense_lds_bytes(const int dims[3][3]);                // LDS of the large
 hipError_t dense_prepare(size_t shm);                        // grant the kernels their LDS (outside capture)
 void launch_dense_xy(const DenseArgs& a, int batch, hipStream_t s);
 void launch_dense_z(const DenseArgs& a, int batch, hipStream_t s);
-// y -= g(t) s for the point sources of every batch member (device comp_off / dims)
-void launch_source_sub(double* y, int64_t y_stride, const double* entries, const double* prof, const int* off,
-                       int entries_per, const int64_t* comp_off_dev, const int* dims_dev, double t_src,
-                       const double* t_dev, int batch, hipStream_t s);
 void launch_strided_axpy(const double* x, int64_t xs, double* y, int64_t ys, int64_t n, double alpha, int batch,
                          hipStream_t s);
 

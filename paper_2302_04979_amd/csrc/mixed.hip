@@ -113,31 +113,6 @@ __global__ void __launch_bounds__(256) mode_kernel(const ModeArgs M) {
     }
 }
 
-// y -= g(t) s for the tested point sources of each batch member (one
-// workgroup per member; dipoles in order, entries of one dipole in parallel).
-__global__ void __launch_bounds__(256) source_sub_kernel(double* y, int64_t y_stride, const double* entries,
-                                                         const double* prof, const int* off, int entries_per,
-                                                         const int64_t comp_off[3], const int dims[3][3],
-                                                         double t_src, const double* t_dev) {
-    const int b = blockIdx.x;
-    double* yb = y + int64_t(b) * y_stride;
-    const double t = (t_dev ? *t_dev : 0.0) + t_src;
-    for (int k = off[b]; k < off[b + 1]; ++k) {
-        const double* pr = prof + 4 * k;
-        const double dtt = t - pr[0];
-        const double gt = pr[2] * exp(-dtt * dtt / (2.0 * pr[1] * pr[1]));
-        const double* en = entries + int64_t(k) * entries_per * 5;
-        for (int q = threadIdx.x; q < entries_per; q += 256) {
-            const int c = int(en[5 * q]);
-            if (c < 0) continue;
-            const int* dd = dims[c];
-            yb[comp_off[c] + (int64_t(en[5 * q + 1]) * dd[1] + int64_t(en[5 * q + 2])) * dd[2] + int64_t(en[5 * q + 3])] -=
-                gt * en[5 * q + 4];
-        }
-        __syncthreads();
-    }
-}
-
 __global__ void strided_axpy_kernel(const double* __restrict__ x, int64_t xs, double* __restrict__ y, int64_t ys,
                                     int64_t n, double alpha) {
     const int b = blockIdx.y;
@@ -157,13 +132,6 @@ void launch_mode(const ModeArgs& a, int batch, hipStream_t s) {
     }
     dim3 grid((lines + MODE_LINES - 1) / MODE_LINES, 3, batch);
     hipLaunchKernelGGL(mode_kernel, grid, dim3(256), 0, s, a);
-}
-
-void launch_source_sub(double* y, int64_t y_stride, const double* entries, const double* prof, const int* off,
-                       int entries_per, const int64_t* comp_off_dev, const int* dims_dev, double t_src,
-                       const double* t_dev, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(source_sub_kernel, dim3(batch), dim3(256), 0, s, y, y_stride, entries, prof, off, entries_per,
-                       comp_off_dev, reinterpret_cast<const int(*)[3]>(dims_dev), t_src, t_dev);
 }
 
 void launch_strided_axpy(const double* x, int64_t xs, double* y, int64_t ys, int64_t n, double alpha, int batch,
