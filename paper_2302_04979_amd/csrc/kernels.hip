@@ -1168,6 +1168,20 @@ void launch_z(int p, const ZArgs& a, int batch, hipStream_t s) {
 // Curl (incidence matrices, Section 2.4): out = beta out + alpha (d_{c+1} u_{c+2}
 // - d_{c+2} u_{c+1}); primal d: v[k] - v[k-1] (zero outside), dual d~: v[r+1] - v[r].
 // ===========================================================================
+// the same for the primal difference, branch-free: every load comes from an
+// index clamped inside the component and out-of-range taps are selected away
+__device__ inline double diff1_primal(const double* u, const int d[3], int axis, int z, int y, int x) {
+    const int n = d[2 - axis];
+    const int k = axis == 0 ? x : (axis == 1 ? y : z);
+    const int stride = axis == 0 ? 1 : (axis == 1 ? d[2] : d[1] * d[2]);
+    const int base = (z * d[1] + y) * d[2] + x;
+    const int k1 = k < n - 1 ? k : n - 1;
+    const int k0 = k - 1 < 0 ? 0 : (k - 1 < n - 1 ? k - 1 : n - 1);
+    const double a = u[base + (k1 - k) * stride];
+    const double c = u[base + (k0 - k) * stride];
+    return (k < n ? a : 0.0) - (k - 1 >= 0 && k - 1 < n ? c : 0.0);
+}
+
 __device__ inline double diff1(const double* u, const int d[3], int primal, int axis, int z, int y, int x) {
     int i[3] = {x, y, z};
     const int n = d[2 - axis];
@@ -1208,20 +1222,38 @@ void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s) {
 //   term0 = d . (K1 e)  over X~^2
 //   term1 = b . (K~1 h), term2 = (K~1 h) . (D^1 e)  over X^2_{h,0}
 // ===========================================================================
+// Sum of three values over a workgroup of NTH threads in a fixed order: a
+// butterfly within each wave, then the wave partials in wave order (one
+// barrier).  out is written by thread 0.
 template <int NTH>
 __device__ inline void block_sum3(double v0, double v1, double v2, double* out) {
-    __shared__ double s[3][NTH];
-    s[0][threadIdx.x] = v0;
-    s[1][threadIdx.x] = v1;
-    s[2][threadIdx.x] = v2;
-    __syncthreads();
-    for (int h = NTH / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
-            for (int k = 0; k < 3; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
-        __syncthreads();
+    constexpr int NW = NTH / 64;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        v0 += __shfl_xor(v0, m, 64);
+        v1 += __shfl_xor(v1, m, 64);
+        v2 += __shfl_xor(v2, m, 64);
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) out[k] = s[k][0];
+    __shared__ double s[3][NW];
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s[0][w] = v0;
+        s[1][w] = v1;
+        s[2][w] = v2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = s[0][0], t1 = s[1][0], t2 = s[2][0];
+#pragma unroll
+        for (int k = 1; k < NW; ++k) {
+            t0 += s[0][k];
+            t1 += s[1][k];
+            t2 += s[2][k];
+        }
+        out[0] = t0;
+        out[1] = t1;
+        out[2] = t2;
+    }
 }
 
 // Fused energy terms: one workgroup per (component, z plane, block of EROWS
@@ -1350,8 +1382,8 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
             } else {
                 const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
                 pb[q] = H[A.n_h + A.h_comp_off[c] + at];
-                pc[q] = diff1(E + A.e_comp_off[a2], A.e_dims[a2], 1, a1, z, y, x) -
-                        diff1(E + A.e_comp_off[a1], A.e_dims[a1], 1, a2, z, y, x);
+                pc[q] = diff1_primal(E + A.e_comp_off[a2], A.e_dims[a2], a1, z, y, x) -
+                        diff1_primal(E + A.e_comp_off[a1], A.e_dims[a1], a2, z, y, x);
             }
         }
     }
@@ -1409,14 +1441,26 @@ __global__ void __launch_bounds__(256) energy_final_kernel(const double* partial
                                                            double* out, int64_t out_stride) {
     const int b = blockIdx.x;
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-    for (int k = threadIdx.x; k < nblocks; k += 256) {
-        const double* p = partial + (int64_t(b) * nblocks + k) * 3;
-        t0 += p[0];
-        t1 += p[1];
-        t2 += p[2];
+    constexpr int U = 8;  // partials per thread and round, all requested together
+    for (int k0 = 0; k0 < nblocks; k0 += 256 * U) {
+        double v[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * 256 + threadIdx.x;
+            const double* p = partial + (int64_t(b) * nblocks + (k < nblocks ? k : 0)) * 3;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) v[u][j] = k < nblocks ? p[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            t0 += v[u][0];
+            t1 += v[u][1];
+            t2 += v[u][2];
+        }
     }
     __shared__ double r[3];
     block_sum3<256>(t0, t1, t2, r);
+    __syncthreads();
     if (threadIdx.x == 0) {
         const double paper = 0.5 * (r[0] + r[1]);
         out[int64_t(b) * out_stride] = paper - 0.5 * dt * r[2];
