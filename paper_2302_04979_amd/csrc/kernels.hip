@@ -775,22 +775,35 @@ __device__ inline double gather_one(const double* __restrict__ patch, int nt, in
     hx = hx > nt - 1 ? nt - 1 : hx;
     hy = hy > nt - 1 ? nt - 1 : hy;
     hz = hz > nt - 1 ? nt - 1 : hz;
+    // the candidate tiles h - 1 and h per axis, in a fixed order; a candidate
+    // that does not cover the entry is read at a clamped (valid) position and
+    // contributes zero, so the eight reads are issued without branches
+    bool vx[2], vy[2], vz[2];
+    int tx[2], ty[2], tz[2], lx[2], ly[2], lz[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const int ax = hx - 1 + d, ay = hy - 1 + d, az = hz - 1 + d;
+        vx[d] = ax >= 0 && rx - ax * TILE < L::Wx;
+        vy[d] = ay >= 0 && ry - ay * TILE < L::Wy;
+        vz[d] = az >= 0 && rz - az * TILE < L::Wz;
+        tx[d] = vx[d] ? ax : hx;
+        ty[d] = vy[d] ? ay : hy;
+        tz[d] = vz[d] ? az : hz;
+        lx[d] = vx[d] ? rx - tx[d] * TILE : 0;
+        ly[d] = vy[d] ? ry - ty[d] * TILE : 0;
+        lz[d] = vz[d] ? rz - tz[d] * TILE : 0;
+    }
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int dz = k >> 2, dy = (k >> 1) & 1, dx = k & 1;
+        v[k] = patch[patch_at<L>(nt, tx[dx], ty[dy], tz[dz], lx[dx], ly[dy], lz[dz])];
+    }
     double s = 0.0;
 #pragma unroll
-    for (int dz = 1; dz >= 0; --dz) {
-        const int tz = hz - dz, lz = rz - tz * TILE;
-        if (tz < 0 || lz >= L::Wz) continue;
-#pragma unroll
-        for (int dy = 1; dy >= 0; --dy) {
-            const int ty = hy - dy, ly = ry - ty * TILE;
-            if (ty < 0 || ly >= L::Wy) continue;
-#pragma unroll
-            for (int dx = 1; dx >= 0; --dx) {
-                const int tx = hx - dx, lx = rx - tx * TILE;
-                if (tx < 0 || lx >= L::Wx) continue;
-                s += patch[patch_at<L>(nt, tx, ty, tz, lx, ly, lz)];
-            }
-        }
+    for (int k = 0; k < 8; ++k) {
+        const int dz = k >> 2, dy = (k >> 1) & 1, dx = k & 1;
+        s += (vz[dz] && vy[dy] && vx[dx]) ? v[k] : 0.0;
     }
     return s;
 }
