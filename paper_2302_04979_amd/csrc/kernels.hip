@@ -154,8 +154,11 @@ __device__ inline void window_rows(double (&r)[I], const double* __restrict__ sr
     const int64_t zs = int64_t(dims[1]) * dims[2];
 #pragma unroll
     for (int k = 0; k < I; ++k) {
+        // branch-free: the load comes from index 0 where the entry is outside
         const int lz = g + k * G, gz = gz0 + k * G;
-        r[k] = (okxy && lz < L::Wz && gz >= 0 && gz < nz) ? src[int64_t(gz) * zs + int64_t(gy) * dims[2] + gx] : 0.0;
+        const bool ok = okxy && lz < L::Wz && gz >= 0 && gz < nz;
+        const double t = src[ok ? int64_t(gz) * zs + int64_t(gy) * dims[2] + gx : 0];
+        r[k] = ok ? t : 0.0;
     }
 }
 
@@ -567,8 +570,9 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
                                     : (slot == 0 ? space_tag(SPACE, 2, 2) : space_tag(SPACE, 0, 2));
             const int K = tag_support(P, tag);
             const int coord = az == 0 ? tx : tz;
-            r[q] = (i < 4 * TSL && k < TILE * NQ * K) ? tabg[A.tab_off[tag] + int64_t(coord) * TILE * NQ * K + k]
-                                                      : 0.0;
+            const bool ok = i < 4 * TSL && k < TILE * NQ * K;
+            const double t = tabg[ok ? A.tab_off[tag] + int64_t(coord) * TILE * NQ * K + k : 0];
+            r[q] = ok ? t : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
