@@ -171,24 +171,6 @@ __device__ inline void store_rows(double* dst, const double (&r)[I], int lx, int
     }
 }
 
-// the three component windows of a field into LDS (contiguous, component after
-// component); every load of a thread is issued before its first LDS store
-template <int P, class L0, class L1, class L2, int NT>
-__device__ inline void load_windows_rows(double* dst, const double* __restrict__ src, const int64_t comp_off[3],
-                                         const int dims[3][3], int tx, int ty, int tz, int n0, int n1, int tid) {
-    static_assert(NT % 64 == 0, "whole waves");
-    constexpr int G = NT / 64;
-    constexpr int I0 = (L0::Wz + G - 1) / G, I1 = (L1::Wz + G - 1) / G, I2 = (L2::Wz + G - 1) / G;
-    const int lx = tid & 7, ly = (tid >> 3) & 7, g = tid >> 6;
-    double r0[I0], r1[I1], r2[I2];
-    window_rows<P, L0, G, I0>(r0, src + comp_off[0], dims[0], tx, ty, tz, n0, n1, lx, ly, g);
-    window_rows<P, L1, G, I1>(r1, src + comp_off[1], dims[1], tx, ty, tz, n0, n1, lx, ly, g);
-    window_rows<P, L2, G, I2>(r2, src + comp_off[2], dims[2], tx, ty, tz, n0, n1, lx, ly, g);
-    store_rows<L0, G, I0>(dst, r0, lx, ly, g);
-    store_rows<L1, G, I1>(dst + L0::size, r1, lx, ly, g);
-    store_rows<L2, G, I2>(dst + L0::size + L1::size, r2, lx, ly, g);
-}
-
 // curl of the 1-form window into component C of the 2-form window:
 // (d_{C+1} u_{C+2} - d_{C+2} u_{C+1}); along the differentiated axis the 1-form
 // window is one entry longer, and both the primal (v[k] - v[k-1]) and the dual
@@ -520,33 +502,8 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
         for (int k = 0; k < 6; ++k) g[k] = active ? __builtin_nontemporal_load(gm + k * Q * Q) : 0.0;
     }
 
-    // ---- per (x, y) column: 1/gamma of its four elements and, for the analytic
-    // metric, q = a grad s = (a1 s_z, a2 s_z, a3 c_z) up to the z factors; read
-    // here, before the column registers fill up ----
-    // (analytic metric: ig[le] holds w_x w_y / gamma_e, and a12 = a1 + a2)
-    double ig[TILE];
-    double a1 = 0.0, a2 = 0.0, a3 = 0.0, a12 = 0.0;
-    if (active) {
-        const int ex = tx * TILE + qx / NQ, ey = ty * TILE + qy / NQ;
-#pragma unroll
-        for (int le = 0; le < TILE; ++le)
-            ig[le] = A.inv_gamma ? A.inv_gamma[(int64_t(tz * TILE + le) * A.npad + ey) * A.npad + ex] : 1.0;
-        if (MET == 1) {
-            const int64_t npq = int64_t(A.npad) * NQ;
-            const int gxq = tx * TILE * NQ + qx, gyq = ty * TILE * NQ + qy;
-            const double sx = axt[gxq], cx = axt[npq + gxq], wx = axt[2 * npq + gxq];
-            const double sy = axt[gyq], cy = axt[npq + gyq], wy = axt[2 * npq + gyq];
-            a1 = A.amp * M_PI * cx * sy;
-            a2 = A.amp * M_PI * sx * cy;
-            a3 = A.amp * M_PI * sx * sy;
-            a12 = a1 + a2;
-            const double wxy = wx * wy;
-#pragma unroll
-            for (int le = 0; le < TILE; ++le) ig[le] *= wxy;
-        }
-    }
-
-    // ---- tracked 2-form entries owned by this tile, one wave per component ----
+    // ---- tracked 2-form entries owned by this tile, one wave per component
+    // (requested first: the per-wave branches must not wait for other loads) ----
     constexpr int WYM = L0::Wy > L1::Wy ? (L0::Wy > L2::Wy ? L0::Wy : L2::Wy) : (L1::Wy > L2::Wy ? L1::Wy : L2::Wy);
     double* tr = (CURL && A.track) ? A.track + int64_t(b) * A.track_stride : nullptr;
     int tk[WYM];
@@ -558,33 +515,86 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
     else if (tr && wave == 2)
         track_column_load<L2, WYM>(tr + A.track_comp_off[2], A.track_dims[2], tx, ty, tz, nt, lane, tk, tv);
 
+    // ---- per (x, y) column: 1/gamma of its four elements and, for the analytic
+    // metric, q = a grad s = (a1 s_z, a2 s_z, a3 c_z) up to the z factors; read
+    // here, before the column registers fill up ----
+    // (analytic metric: ig[le] holds w_x w_y / gamma_e, and a12 = a1 + a2)
+    // (only the loads here: the factors are formed after the windows are
+    // stored, so that no wait for these loads precedes the other requests)
+    double ig[TILE], ax[6] = {0, 0, 0, 0, 0, 0};
+    if (active) {
+        const int ex = tx * TILE + qx / NQ, ey = ty * TILE + qy / NQ;
+#pragma unroll
+        for (int le = 0; le < TILE; ++le)
+            ig[le] = A.inv_gamma ? A.inv_gamma[(int64_t(tz * TILE + le) * A.npad + ey) * A.npad + ex] : 1.0;
+        if (MET == 1) {
+            const int64_t npq = int64_t(A.npad) * NQ;
+            const int gxq = tx * TILE * NQ + qx, gyq = ty * TILE * NQ + qy;
+            ax[0] = axt[gxq];
+            ax[1] = axt[npq + gxq];
+            ax[2] = axt[2 * npq + gxq];
+            ax[3] = axt[gyq];
+            ax[4] = axt[npq + gyq];
+            ax[5] = axt[2 * npq + gyq];
+        }
+    }
+
     // ---- x and z tables of the tile: [axis x, z][slot][element][point][function] ----
     {
         constexpr int ST = (4 * TSL + NT - 1) / NT;
+        // the four (axis, slot) tags are compile-time: their table offsets are
+        // scalars, selected per lane (a lane-indexed read of the argument array
+        // would be a vector load and a wait for every earlier request)
+        constexpr int T0 = space_tag(SPACE, 0, 0), T1 = space_tag(SPACE, 1, 0);
+        constexpr int T2 = space_tag(SPACE, 2, 2), T3 = space_tag(SPACE, 0, 2);
+        constexpr int K0 = tag_support(P, T0), K1 = tag_support(P, T1), K2 = tag_support(P, T2), K3 = tag_support(P, T3);
+        const int64_t b0 = A.tab_off[T0] + int64_t(tx) * TILE * NQ * K0, b1 = A.tab_off[T1] + int64_t(tx) * TILE * NQ * K1;
+        const int64_t b2 = A.tab_off[T2] + int64_t(tz) * TILE * NQ * K2, b3 = A.tab_off[T3] + int64_t(tz) * TILE * NQ * K3;
         double r[ST];
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
             const int i = tid + NT * q;
-            const int az = i / (2 * TSL), slot = (i / TSL) % 2, k = i % TSL;
-            const int tag = az == 0 ? (slot == 0 ? space_tag(SPACE, 0, 0) : space_tag(SPACE, 1, 0))
-                                    : (slot == 0 ? space_tag(SPACE, 2, 2) : space_tag(SPACE, 0, 2));
-            const int K = tag_support(P, tag);
-            const int coord = az == 0 ? tx : tz;
+            const int sel = i / TSL, k = i % TSL;  // sel = 2 az + slot
+            const int K = sel == 0 ? K0 : (sel == 1 ? K1 : (sel == 2 ? K2 : K3));
+            const int64_t base = sel == 0 ? b0 : (sel == 1 ? b1 : (sel == 2 ? b2 : b3));
             const bool ok = i < 4 * TSL && k < TILE * NQ * K;
-            const double t = tabg[ok ? A.tab_off[tag] + int64_t(coord) * TILE * NQ * K + k : 0];
+            const double t = tabg[ok ? base + k : 0];
             r[q] = ok ? t : 0.0;
         }
+        // ---- input windows (the 1-form when the curl is fused, else the
+        // 2-form), requested before any of the LDS stores waits for a load ----
+        using W0 = typename std::conditional<CURL, S0, L0>::type;
+        using W1 = typename std::conditional<CURL, S1, L1>::type;
+        using W2 = typename std::conditional<CURL, S2, L2>::type;
+        constexpr int WG = NT / 64;
+        constexpr int I0 = (W0::Wz + WG - 1) / WG, I1 = (W1::Wz + WG - 1) / WG, I2 = (W2::Wz + WG - 1) / WG;
+        const int wlx = tid & 7, wly = (tid >> 3) & 7, wg = tid >> 6;
+        double w0[I0], w1[I1], w2[I2];
+        window_rows<P, W0, WG, I0>(w0, src + A.src_comp_off[0], A.src_dims[0], tx, ty, tz, A.n0, A.n1, wlx, wly, wg);
+        window_rows<P, W1, WG, I1>(w1, src + A.src_comp_off[1], A.src_dims[1], tx, ty, tz, A.n0, A.n1, wlx, wly, wg);
+        window_rows<P, W2, WG, I2>(w2, src + A.src_comp_off[2], A.src_dims[2], tx, ty, tz, A.n0, A.n1, wlx, wly, wg);
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
             const int i = tid + NT * q;
             if (i < 4 * TSL) sm[OT + i] = r[q];
         }
+        store_rows<W0, WG, I0>(sm + OR, w0, wlx, wly, wg);
+        store_rows<W1, WG, I1>(sm + OR + W0::size, w1, wlx, wly, wg);
+        store_rows<W2, WG, I2>(sm + OR + W0::size + W1::size, w2, wlx, wly, wg);
     }
-    // ---- input windows: the 1-form (curl fused) or the 2-form ----
-    if (CURL)
-        load_windows_rows<P, S0, S1, S2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
-    else
-        load_windows_rows<P, L0, L1, L2, NT>(sm + OR, src, A.src_comp_off, A.src_dims, tx, ty, tz, A.n0, A.n1, tid);
+    // analytic metric, per (x, y) column: q = a grad s = (a1 s_z, a2 s_z, a3 c_z)
+    // up to the z factors, a12 = a1 + a2, and ig[le] = w_x w_y / gamma_e
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0, a12 = 0.0;
+    if (MET == 1 && active) {
+        const double sx = ax[0], cx = ax[1], wx = ax[2], sy = ax[3], cy = ax[4], wy = ax[5];
+        a1 = A.amp * M_PI * cx * sy;
+        a2 = A.amp * M_PI * sx * cy;
+        a3 = A.amp * M_PI * sx * sy;
+        a12 = a1 + a2;
+        const double wxy = wx * wy;
+#pragma unroll
+        for (int le = 0; le < TILE; ++le) ig[le] *= wxy;
+    }
     __syncthreads();
 
     // ---- part 1a: y contraction of the windows, one wave per component ----
