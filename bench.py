@@ -215,7 +215,7 @@ def profile_run(K, W, torch, p, N, steps):
     """A short run for the profiler: a device copy of known size (512 MiB read,
     512 MiB written: the reference for the HBM byte counters), then `steps`
     steps of the metric workload's kernels from a seeded random state under
-    each of the two tiled plans whose mass kernels differ."""
+    each of the three tiled plans."""
     import numpy as np
     n = 64 * 1024 * 1024  # doubles: 512 MiB
     src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -229,8 +229,9 @@ def profile_run(K, W, torch, p, N, steps):
     E = torch.tensor(W.random_vector(2 * G.n_e, 0, 41), dtype=torch.float64, device="cuda")
     H = torch.tensor(W.random_vector(2 * G.n_h, 0, 42), dtype=torch.float64, device="cuda")
     en = torch.zeros(steps, dtype=torch.float64, device="cuda")
-    # the tiled plan, then the tiled plan with the four-wave mass kernel
-    for plan in (K.PLAN_TILED, K.PLAN_TILED_W4):
+    # the tiled plan, the tiled plan with the four-wave mass kernel, and the
+    # tiled plan with dense solves
+    for plan in (K.PLAN_TILED, K.PLAN_TILED_W4, K.PLAN_TILED_DENSE):
         G.set_plan(plan)
         G.step(E, H, 1e-3, nsteps=steps, flags=K.TRACK_DB, energy=en)
     torch.cuda.synchronize()
