@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for the spline geometric Maxwell leapfrog (scheme 2).
+"""FP64 CPU oracle for the spline geometric Maxwell leapfrog (schemes 2 and 1).
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import anything from this package.  The
@@ -21,6 +21,11 @@ primitives (matrix products, dense LU), with no blocking or fusion:
                   (eq. (4.4), (4.5)), sum-factorised mass applies, the explicit
                   leapfrog of (3.10)-(3.13) in its (e, h) Petrov-Galerkin form,
                   energies, CFL, projections, point sources and probes.
+* ``scheme1``   - the first scheme (Section 3.3): 1-form mass matrices with
+                  the covariant factor det DF (DF^T DF)^{-1}, conjugate-gradient
+                  mass solves, the (e, h) leapfrog with the transposed pairings,
+                  its energies and CFL.
+* ``adjoint``   - the discrete adjoint of the scheme-2 leapfrog.
 
 Every function pinned by tests under ``-m "not gpu"``; see the design doc for the
 pins, and for the readings taken where the paper is silent.

@@ -12,7 +12,9 @@ Test infrastructure only (see ``oracle/__init__``).  Meant for tiny meshes
   basis functions - not from the Kronecker factorisation (4.2)/(4.3), which the
   tests check against this.
 * Mass matrices M^2_{1/mu} (primal 2-forms) and M~^2_{1/eps} (dual 2-forms),
-  Section 3.4: entries int w^_i . G w^_j with the 2-form metric factor G.
+  Section 3.4: entries int w^_i . G w^_j with the 2-form metric factor G; and
+  for scheme 1 (Section 3.3) M^1_eps (primal 1-forms) and M~^1_mu (dual
+  1-forms) with the 1-form factor G1 and the material as a factor.
 * Incidence matrices D^1 (primal curl, e -> b) and D~^1 (dual curl,
   h -> d-space) as explicit +-1 matrices (Section 2.4).
 """
@@ -105,6 +107,13 @@ def mass_2form(axis: Axis, space: str, G: np.ndarray, inv_gamma_elem: np.ndarray
                         Wij = w[q] * G[q, ci, cj] * g
                         M[o[ci]:o[ci + 1], o[cj]:o[cj + 1]] += Phi[ci].T @ (Wij[:, None] * Phi[cj])
     return M
+
+
+def mass_1form(axis: Axis, space: str, G1: np.ndarray, gamma_elem: np.ndarray | None):
+    """Mass matrix of the 1-form space `space` ('E' with gamma = eps, 'H' with
+    gamma = mu) by the same element loop: G1 = det DF (DF^T DF)^{-1} at the
+    Gauss points, the material multiplying (not dividing) the integrand."""
+    return mass_2form(axis, space, G1, gamma_elem)
 
 
 def curl_matrix(axis: Axis, primal: bool) -> np.ndarray:

@@ -11,7 +11,10 @@ L^2 product of two 2-forms becomes, in parametric coordinates,
 
 The paper only refers to the pullbacks; this factor is derived here.  For a
 1-form the pullback is covariant (E = DF^{-T} E^), used for probes and for the
-initial projection.
+initial projection; it gives the 1-form factor of the mass matrices of scheme
+1 (Section 3.3),
+
+    (E, E')_{L^2_gamma} = int E^ . G1 E'^ dx^,   G1 = gamma det DF (DF^T DF)^{-1}.
 """
 from __future__ import annotations
 
@@ -59,3 +62,11 @@ def metric_2form(DF: np.ndarray) -> np.ndarray:
     if np.any(det <= 0):
         raise ValueError("map is not orientation preserving (det DF <= 0)")
     return np.einsum("...ki,...kj->...ij", DF, DF) / det[..., None, None]
+
+
+def metric_1form(DF: np.ndarray) -> np.ndarray:
+    """det DF (DF^T DF)^{-1} at each point (gamma = 1), shape (..., 3, 3)."""
+    det = np.linalg.det(DF)
+    if np.any(det <= 0):
+        raise ValueError("map is not orientation preserving (det DF <= 0)")
+    return det[..., None, None] * np.linalg.inv(np.einsum("...ki,...kj->...ij", DF, DF))
