@@ -272,6 +272,50 @@ kmx_status kmx_op_solve(kmx_space* sp, int which, int transpose, const double* y
 /* y = K x with K = K1 (which = 1) or K~1 (which = 0). */
 kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, void* stream);
 
+/* ---- the first scheme: Hodge stars with 1-form mass matrices -------------
+ * Section 3.3, eqs. (3.5)-(3.8): M^1_eps e = K~2 d and M~^1_mu h = K2 b, with
+ * K~2 = K1^T and K2 = K~1^T (the pairing-transpose property of Section 2.4),
+ * advanced in the (e, h) form of Section 3.3.2 by the same leapfrog:
+ *     h^{n+1/2} = h^{n-1/2} - dt (M~^1_mu)^{-1} K~1^T D^1 e^n
+ *     e^{n+1}   = e^n + dt (M^1_eps)^{-1} K1^T D~^1 h^{n+1/2}
+ * (source free).  M^1_eps (on X^1_{h,0}, n_e unknowns) and M~^1_mu (on X~^1,
+ * n_h unknowns) have entries int eta^_i . G1 eta^_j gamma over the parametric
+ * cube, G1 = det DF (DF^T DF)^{-1} the covariant pullback factor, gamma = eps or
+ * mu per element.  Their systems are solved by conjugate gradients
+ * preconditioned with the identity-map, unit-material mass (Kronecker products
+ * of 1D Gram matrices, inverted exactly), stopped at |y - M x| <= tol |y|.
+ * These calls need an FP64 space (KMX_E_STATE for KMX_MIXED) and allocate, at
+ * their first use, eps and mu on the tiles, eight field-sized work vectors
+ * and (streamed-metric spaces) the 1-form metric factor; they synchronise the
+ * stream while solving (the residual norm is read back) and are not
+ * graph-capturable.  One field per call (no batch). */
+
+/* y = M^1_eps x (which = 0, X^1_{h,0}) or y = M~^1_mu x (which = 1, X~^1);
+ * device vectors of one field. */
+kmx_status kmx_op_mass1(kmx_space* sp, int which, const double* x, double* y, void* stream);
+
+/* x = M^{-1} y for the mass of kmx_op_mass1 (which as there), starting from
+ * the guess held in x (device, overwritten; must not alias y).  iters (host,
+ * may be NULL) receives the CG iterations.  KMX_E_UNSTABLE when the tolerance
+ * is not reached within max_iter iterations or a value is not finite. */
+kmx_status kmx_solve_mass1(kmx_space* sp, int which, const double* y, double* x, double tol, int max_iter,
+                           int* iters, void* stream);
+
+/* One half step of the first scheme:
+ *   which = 1: out += alpha (M~^1_mu)^{-1} K~1^T D^1 x   (x = e, out = h)
+ *   which = 0: out += alpha (M^1_eps)^{-1} K1^T D~^1 x   (x = h, out = e)
+ * The solve starts from the space's previous solution of the same kind (a
+ * warm start).  With which = 1 and alpha = dt/2 it gives the staggered start
+ * h^{-1/2} = h^0 + dt/2 (M~^1_mu)^{-1} K~1^T D^1 e^0.  iters as above. */
+kmx_status kmx_half_step_scheme1(kmx_space* sp, int which, const double* x, double* out, double alpha, double tol,
+                                 int max_iter, int* iters, void* stream);
+
+/* nsteps leapfrog steps of the first scheme on (e^n, h^{n-1/2}) (device, n_e
+ * and n_h values).  iters (host, 2 ints, may be NULL) receives the summed CG
+ * iterations of the e solves and of the h solves. */
+kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, double tol, int max_iter,
+                            int* iters, void* stream);
+
 /* ---- probes and the adjoint (gradient of a probe misfit in eps) ----------
  * Not part of the paper, which has no inverse problem: the exact discrete
  * adjoint of the leapfrog above. */
@@ -322,9 +366,11 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
  *   7 separable persistent kernel (one launch for all steps of a call)
  *   8 FP32 dense mode products of the mixed-precision solves
  *   9 FP64 dense solves of the tiled-dense plan (plane pass and z pass, one
- *     span per solve)
+ *     span per solve), and the dense Kronecker applies of the first scheme
+ *  10 mass apply on a 1-form space (first scheme)
+ *  11 vector updates and dot products of the first scheme's CG
  * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
-#define KMX_PROFILE_KINDS 10
+#define KMX_PROFILE_KINDS 12
 kmx_status kmx_profile_begin(kmx_space* sp, int capacity);
 kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches);
 

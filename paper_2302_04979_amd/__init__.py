@@ -40,9 +40,10 @@ EXPORTS = (
     "kmx_set_refinement",
     "kmx_graph_create", "kmx_graph_launch",
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
+    "kmx_op_mass1", "kmx_solve_mass1", "kmx_half_step_scheme1", "kmx_step_scheme1",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
-                 "mode_fp32", "dense_fp64")
+                 "mode_fp32", "dense_fp64", "mass_1form", "cg_vector")
 
 _STATUS = {0: "KMX_OK", 1: "KMX_E_ARG", 2: "KMX_E_GEOMETRY", 3: "KMX_E_MATERIAL", 4: "KMX_E_DEVICE",
            5: "KMX_E_OOM", 6: "KMX_E_UNSTABLE", 7: "KMX_E_STATE"}
@@ -109,6 +110,10 @@ def load_library():
         "kmx_set_time": ([vp, d, vp], i),
         "kmx_get_time": ([vp, ctypes.POINTER(d), vp], i),
         "kmx_last_error": ([], ctypes.c_char_p),
+        "kmx_op_mass1": ([vp, i, vp, vp, vp], i),
+        "kmx_solve_mass1": ([vp, i, vp, vp, d, i, ctypes.POINTER(i), vp], i),
+        "kmx_half_step_scheme1": ([vp, i, vp, vp, d, d, i, ctypes.POINTER(i), vp], i),
+        "kmx_step_scheme1": ([vp, vp, vp, d, i, d, i, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -329,6 +334,41 @@ class Space:
         n = self.n_e if w else self.n_h
         _check(load_library().kmx_op_solve(self._h, w, int(bool(transpose)), _dptr(y, n, "y"), _dptr(x, n, "x"),
                                            _stream()))
+
+    # ---- the first scheme (1-form mass solves) ---------------------------
+    def op_mass1(self, which: str, x, y):
+        """which 'E' (M^1_eps on X^1_{h,0}) or 'H' (M~^1_mu on X~^1)."""
+        w = 0 if which == "E" else 1
+        n = self.n_e if w == 0 else self.n_h
+        _check(load_library().kmx_op_mass1(self._h, w, _dptr(x, n, "x"), _dptr(y, n, "y"), _stream()))
+
+    def solve_mass1(self, which: str, y, x, tol=1e-13, max_iter=500) -> int:
+        """x = M^{-1} y from the guess in x; returns the CG iterations."""
+        w = 0 if which == "E" else 1
+        n = self.n_e if w == 0 else self.n_h
+        it = ctypes.c_int(0)
+        _check(load_library().kmx_solve_mass1(self._h, w, _dptr(y, n, "y"), _dptr(x, n, "x"), float(tol),
+                                              int(max_iter), ctypes.byref(it), _stream()))
+        return it.value
+
+    def half_step_scheme1(self, which: str, x, out, alpha, tol=1e-13, max_iter=500) -> int:
+        """which 'H': out += alpha M~^{-1} K~1^T D^1 x; which 'E': out += alpha M^{-1} K1^T D~^1 x."""
+        w = 0 if which == "E" else 1
+        n_x, n_o = (self.n_h, self.n_e) if w == 0 else (self.n_e, self.n_h)
+        it = ctypes.c_int(0)
+        _check(load_library().kmx_half_step_scheme1(self._h, w, _dptr(x, n_x, "x"), _dptr(out, n_o, "out"),
+                                                    float(alpha), float(tol), int(max_iter), ctypes.byref(it),
+                                                    _stream()))
+        return it.value
+
+    def step_scheme1(self, e, h, dt, nsteps=1, tol=1e-13, max_iter=500):
+        """nsteps leapfrog steps of the first scheme; returns the summed CG
+        iterations (e solves, h solves)."""
+        it = (ctypes.c_int * 2)()
+        _check(load_library().kmx_step_scheme1(self._h, _dptr(e, self.n_e, "e"), _dptr(h, self.n_h, "h"),
+                                               float(dt), int(nsteps), float(tol), int(max_iter),
+                                               ctypes.cast(it, ctypes.c_void_p), _stream()))
+        return int(it[0]), int(it[1])
 
     def set_refinement(self, steps: int):
         """Number of FP64-residual corrections of mixed-precision solves."""

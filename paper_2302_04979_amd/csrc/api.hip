@@ -40,6 +40,9 @@ kmx_status fail(kmx_status st, const std::string& msg) {
 // factor-set ids beyond the four pairing factors: 1D Gram matrices used by the
 // conjugate-gradient preconditioner of the dual 2-form mass matrix
 constexpr int F_GRAM_DV = 4, F_GRAM_DD = 5, NFAC = 6;
+// slots of the dense operand-order factors beyond the four inverses: inverse
+// Gram matrices by tag, then the pairing factors G^, M^, G^T, M^T
+constexpr int FR_GRAM_INV = 4, FR_PAIR = 8;
 
 void space_dims(const kmx_space* sp, int space, int dims[3][3], int64_t off[3]) {
     for (int c = 0; c < 3; ++c) {
@@ -61,7 +64,7 @@ void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
 
 // Kernel kinds reported by kmx_profile_end.
 enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6, PK_SEP = 7,
-       PK_MODE = 8, PK_DENSE = 9 };
+       PK_MODE = 8, PK_DENSE = 9, PK_MASS_1 = 10, PK_VEC = 11 };
 
 struct ProfScope {  // brackets one launch with events when profiling is on
     kmx_space* sp;
@@ -96,7 +99,10 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
     a.metric_mode = sp->metric_mode;
     a.amp = sp->map.kind == 1 ? sp->map.amplitude : 0.0;
     a.axis_tab = sp->d_axis_tab;
-    a.inv_gamma = space == SP_B ? sp->d_inv_mu : sp->d_inv_eps;
+    // 2-forms read 1/mu (B) or 1/eps (D); the 1-form masses of the first
+    // scheme read eps (E) or mu (H) and their own metric factor
+    a.inv_gamma = space == SP_B ? sp->d_inv_mu : space == SP_D ? sp->d_inv_eps : space == SP_E ? sp->d_eps : sp->d_mu;
+    if (space == SP_E || space == SP_H) a.metric = sp->d_metric1;
     a.tab = sp->d_tab;
     for (int k = 0; k < 4; ++k) a.tab_off[k] = sp->tab_off[k];
     a.ntile = sp->ntile;
@@ -107,7 +113,7 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
     space_dims(sp, src_space, a.src_dims, a.src_comp_off);
     patch_size(sp->p, space, sp->ntile, a.patch_comp_off);
     a.waves4 = sp->mass_waves4;
-    ProfScope ps(sp, s, space == SP_B ? PK_MASS_B : PK_MASS_D);
+    ProfScope ps(sp, s, space == SP_B ? PK_MASS_B : space == SP_D ? PK_MASS_D : PK_MASS_1);
     launch_mass(sp->p, space, curl, a, batch, s);
 }
 
@@ -441,17 +447,28 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             // dense FP64 inverses of G^, M^, G^T, M^T for the tiled-dense
             // plan, in the matrix cores' operand order
             std::vector<double> frag;
+            auto add_frag = [&](int slot, const std::vector<double>& B, int n) {
+                sp->frag64_off[slot] = int64_t(frag.size());
+                frag.resize(frag.size() + size_t(dense_frag_doubles(n)));
+                dense_fragments(B.data(), n, frag.data() + sp->frag64_off[slot]);
+            };
             for (int k = 0; k < 4; ++k) {
                 const int n = (k == F_G || k == F_GT) ? sp->n0 : sp->n1;
                 const std::vector<double>& A = (k == F_G || k == F_GT) ? sp->tb.G : sp->tb.M;
                 const std::vector<double> Ai = dense_inverse(A, n);
-                std::vector<double> B(size_t(n) * n);
+                std::vector<double> B(size_t(n) * n), Bf(size_t(n) * n);
                 for (int i = 0; i < n; ++i)
-                    for (int j = 0; j < n; ++j)
-                        B[size_t(i) * n + j] = (k == F_GT || k == F_MT) ? Ai[size_t(j) * n + i] : Ai[size_t(i) * n + j];
-                sp->frag64_off[k] = int64_t(frag.size());
-                frag.resize(frag.size() + size_t(dense_frag_doubles(n)));
-                dense_fragments(B.data(), n, frag.data() + sp->frag64_off[k]);
+                    for (int j = 0; j < n; ++j) {
+                        const bool tr = k == F_GT || k == F_MT;
+                        B[size_t(i) * n + j] = tr ? Ai[size_t(j) * n + i] : Ai[size_t(i) * n + j];
+                        Bf[size_t(i) * n + j] = tr ? A[size_t(j) * n + i] : A[size_t(i) * n + j];
+                    }
+                add_frag(k, B, n);
+                add_frag(FR_PAIR + k, Bf, n);
+            }
+            for (int t = 0; t < 4; ++t) {
+                const int n = (t == PV || t == DD) ? sp->n0 : sp->n1;
+                add_frag(FR_GRAM_INV + t, dense_inverse(gram(sp->tb, t), n), n);
             }
             if ((st = upload(&sp->d_frag64, frag)) != KMX_OK) { kmx_destroy_space(sp); return st; }
             int db[3][3], dd[3][3];
@@ -501,7 +518,9 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
         }
         if ((st = upload_materials(sp)) != KMX_OK) { kmx_destroy_space(sp); return st; }
         int64_t off[3];
-        sp->patch_per_field = std::max(patch_size(p, SP_B, sp->ntile, off), patch_size(p, SP_D, sp->ntile, off));
+        sp->patch_per_field = 0;
+        for (int space = 0; space < 4; ++space)
+            sp->patch_per_field = std::max(sp->patch_per_field, patch_size(p, space, sp->ntile, off));
         const int64_t nfield = std::max(sp->n_e, sp->n_h);
         {
             // reduction partials: the CG and dot kernels use up to 1024 blocks per
@@ -577,7 +596,8 @@ void kmx_destroy_space(kmx_space* sp) {
                       sp->d_gram, sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
-    void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_frag64};
+    void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_frag64,
+                    sp->d_eps, sp->d_mu, sp->d_metric1, sp->d_s1};
     for (void* b : more)
         if (b) (void)hipFree(b);
     delete sp;
@@ -601,6 +621,11 @@ kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double
     }
     sp->inv_eps_host = ie;
     sp->inv_mu_host = im;
+    if (eps_elem) sp->eps_host.assign(eps_elem, eps_elem + ne3);
+    else sp->eps_host.clear();
+    if (mu_elem) sp->mu_host.assign(mu_elem, mu_elem + ne3);
+    else sp->mu_host.clear();
+    sp->s1_ready = 0;
     note_uniform(sp);
     return upload_materials(sp);
 }
@@ -1482,6 +1507,285 @@ kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, 
     if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
     run_solve(sp, which, 0, 0, which ? SP_D : SP_B, x, 0, y, 0, 1.0, 0, 1, nullptr, 0.0, 2,
               static_cast<hipStream_t>(stream));
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// The first scheme (Section 3.3): Hodge stars with the 1-form mass matrices,
+//   M^1_eps d_t e = K1^T D~^1 h,   M~^1_mu d_t h = - K~1^T D^1 e,
+// each mass system solved by preconditioned conjugate gradients.  The
+// preconditioner is the mass matrix of the identity map with unit material,
+// whose blocks are Kronecker products of 1D Gram matrices: its inverse is
+// applied with the dense inverse Gram factors on the matrix cores, as are the
+// transposed pairing matrices (the same dense plane and z passes as the
+// tiled-dense plan's solves).
+// ===========================================================================
+namespace {
+
+// work vectors of the first scheme, each max(n_e, n_h) long
+enum { S1_Y = 0, S1_R, S1_Z, S1_P, S1_AP, S1_CU, S1_XE, S1_XH, S1_VECS };
+
+double* s1_vec(kmx_space* sp, int k) { return sp->d_s1 + int64_t(k) * std::max(sp->n_e, sp->n_h); }
+
+kmx_status s1_upload_padded(kmx_space* sp, double** dst, const std::vector<double>& v) {
+    const int N = sp->N, P = sp->npad;
+    std::vector<double> pad(size_t(P) * P * P, 0.0);
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x)
+                pad[(size_t(z) * P + y) * P + x] = v.empty() ? 1.0 : v[(size_t(z) * N + y) * N + x];
+    if (!*dst && hipMalloc(dst, pad.size() * sizeof(double)) != hipSuccess)
+        return fail(KMX_E_OOM, "device allocation failed (first-scheme materials)");
+    HIP_TRY(hipMemcpy(*dst, pad.data(), pad.size() * sizeof(double), hipMemcpyHostToDevice));
+    return KMX_OK;
+}
+
+// Set-up at the first use (and after kmx_set_materials): eps and mu padded to
+// the tiles, the 1-form metric factor when the metric is streamed, and the
+// work vectors.  Synchronous; not for use under graph capture.
+kmx_status s1_prepare(kmx_space* sp) {
+    if (!sp->dense_ok) return fail(KMX_E_STATE, "the first scheme needs the dense FP64 kernels (LDS too small)");
+    if (sp->max_batch < 1) return fail(KMX_E_STATE, "no batch capacity");
+    kmx_status st;
+    if (!sp->s1_ready) {
+        if ((st = s1_upload_padded(sp, &sp->d_eps, sp->eps_host)) != KMX_OK) return st;
+        if ((st = s1_upload_padded(sp, &sp->d_mu, sp->mu_host)) != KMX_OK) return st;
+        sp->s1_ready = 1;
+    }
+    if (sp->metric_mode == 0 && !sp->d_metric1) {
+        std::vector<double> m1;
+        if ((st = build_metric(sp, &m1, 1)) != KMX_OK) return fail(st, "det DF <= 0 at a quadrature point");
+        if ((st = upload(&sp->d_metric1, m1)) != KMX_OK) return st;
+    }
+    if (!sp->d_s1) {
+        const size_t n = size_t(S1_VECS) * size_t(std::max(sp->n_e, sp->n_h));
+        if (hipMalloc(&sp->d_s1, n * sizeof(double)) != hipSuccess)
+            return fail(KMX_E_OOM, "device allocation failed (first-scheme vectors)");
+        HIP_TRY(hipMemset(sp->d_s1, 0, n * sizeof(double)));
+    }
+    return KMX_OK;
+}
+
+// out = (accumulate ? out : 0) + alpha * (F_z (x) F_y (x) F_x) in, component by
+// component, with the dense factors in fragment slots frag[c][axis]; `layout`
+// names a space with the dims of in and out.  Uses d_tmp (in must differ).
+void dense_kron(kmx_space* sp, int layout, const int frag[3][3], const double* in, double* out, double alpha,
+                int accumulate, hipStream_t s) {
+    const int64_t nf = std::max(sp->n_e, sp->n_h);
+    DenseArgs a{};
+    space_dims(sp, layout, a.dims, a.comp_off);
+    a.frag = sp->d_frag64;
+    for (int c = 0; c < 3; ++c)
+        for (int ax = 0; ax < 3; ++ax) a.frag_off[c][ax] = sp->frag64_off[frag[c][ax]];
+    ProfScope ps(sp, s, PK_DENSE);
+    a.in = in;
+    a.in_stride = nf;
+    a.out = sp->d_tmp;
+    a.out_stride = nf;
+    launch_dense_xy(a, 1, s);
+    a.in = sp->d_tmp;
+    a.out = out;
+    a.out_stride = nf;
+    a.alpha = alpha;
+    a.accumulate = accumulate;
+    launch_dense_z(a, 1, s);
+}
+
+// y = M x for a 1-form space (SP_E: M^1_eps, SP_H: M~^1_mu)
+void run_mass1(kmx_space* sp, int space, const double* x, double* y, hipStream_t s) {
+    run_mass(sp, space, false, x, 0, 1, s);
+    GatherArgs g{};
+    g.patch = sp->d_patch;
+    g.patch_stride = sp->patch_per_field;
+    patch_size(sp->p, space, sp->ntile, g.patch_comp_off);
+    space_dims(sp, space, g.dims, g.comp_off);
+    g.ntile = sp->ntile;
+    g.out = y;
+    g.out_stride = 0;
+    ProfScope ps(sp, s, PK_GATHER);
+    launch_gather(sp->p, space, g, space == SP_E ? sp->n_e : sp->n_h, 1, s);
+}
+
+// z = P^{-1} r with P the identity-map, unit-material 1-form mass
+void s1_precond(kmx_space* sp, int space, const double* r, double* z, hipStream_t s) {
+    int f[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < 3; ++a) f[c][a] = FR_GRAM_INV + space_tag(space, c, a);
+    dense_kron(sp, space, f, r, z, 1.0, 0, s);
+}
+
+// y = K~1^T D^1 e (space SP_H) or K1^T D~^1 h (space SP_E): the right-hand
+// sides of the (e, h) form, K~1^T block c = G^ along c (x) M^ across and
+// K1^T block c = M^T along c (x) G^T across
+void s1_rhs(kmx_space* sp, int space, const double* x, double* y, hipStream_t s) {
+    double* cu = s1_vec(sp, S1_CU);
+    run_curl(sp, space == SP_H, x, 0, cu, 0, 1.0, 0.0, 1, s);
+    int f[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < 3; ++a)
+            f[c][a] = FR_PAIR + (space == SP_H ? (a == c ? F_G : F_M) : (a == c ? F_MT : F_GT));
+    dense_kron(sp, space, f, cu, y, 1.0, 0, s);
+}
+
+// d_scal[slot] = x . y (deterministic two-level sum)
+void s1_dot(kmx_space* sp, const double* x, const double* y, int64_t n, int slot, hipStream_t s) {
+    const int nb = energy_blocks(sp);
+    ProfScope ps(sp, s, PK_VEC);
+    launch_dot(x, y, n, n, 1, sp->d_red, nb, s);
+    launch_sum_final(sp->d_red, nb, 1, sp->d_scal + slot, s);
+}
+
+// x = M^{-1} y by preconditioned CG from the initial guess in x, to
+// |r| <= tol |y|.  The residual norm is read back at every iteration from
+// `expect` - 1 on (expect = iterations of the previous solve of this space),
+// so a warm-started sequence of solves synchronises about twice per solve.
+kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double tol, int max_iter, int expect,
+                  int* iters, hipStream_t s) {
+    const int64_t n = space == SP_E ? sp->n_e : sp->n_h;
+    double *r = s1_vec(sp, S1_R), *z = s1_vec(sp, S1_Z), *pd = s1_vec(sp, S1_P), *Ap = s1_vec(sp, S1_AP);
+    double* sc = sp->d_scal;  // [0] r.z  [1] p.Ap  [2] new r.z  [3] r.r  [4] y.y
+    run_mass1(sp, space, x, Ap, s);
+    HIP_TRY(hipMemcpyAsync(r, y, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    {
+        ProfScope ps(sp, s, PK_VEC);
+        launch_axpby(Ap, r, n, -1.0, nullptr, 1.0, s);
+    }
+    s1_dot(sp, y, y, n, 4, s);
+    s1_dot(sp, r, r, n, 3, s);
+    double h2[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(h2, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *iters = 0;
+    if (!std::isfinite(h2[0]) || !std::isfinite(h2[1])) return fail(KMX_E_UNSTABLE, "mass solve: non-finite input");
+    if (h2[1] == 0.0) {  // y = 0: x = 0
+        HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), s));
+        return KMX_OK;
+    }
+    const double stop = tol * tol * h2[1];
+    if (h2[0] <= stop) return KMX_OK;
+    s1_precond(sp, space, r, z, s);
+    HIP_TRY(hipMemcpyAsync(pd, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    s1_dot(sp, r, z, n, 0, s);
+    int it = 0;
+    while (true) {
+        run_mass1(sp, space, pd, Ap, s);
+        s1_dot(sp, pd, Ap, n, 1, s);
+        {
+            ProfScope ps(sp, s, PK_VEC);
+            launch_cg_update(x, r, pd, Ap, nullptr, n, sc, 0, s);
+        }
+        ++it;
+        s1_dot(sp, r, r, n, 3, s);
+        if (it >= expect - 1 || it >= max_iter) {
+            double rr = 0.0;
+            HIP_TRY(hipMemcpyAsync(&rr, sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (!std::isfinite(rr)) return fail(KMX_E_UNSTABLE, "mass solve diverged");
+            if (rr <= stop) break;
+            if (it >= max_iter) {
+                *iters = it;
+                return fail(KMX_E_UNSTABLE, "mass solve did not reach the tolerance within max_iter iterations");
+            }
+        }
+        s1_precond(sp, space, r, z, s);
+        s1_dot(sp, r, z, n, 2, s);
+        {
+            ProfScope ps(sp, s, PK_VEC);
+            launch_cg_update(x, r, pd, Ap, z, n, sc, 1, s);
+        }
+        HIP_TRY(hipMemcpyAsync(sc, sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    *iters = it;
+    return KMX_OK;
+}
+
+// out += alpha * M^{-1} rhs(x) for one half step; the solve starts from the
+// previous solution of the same space
+kmx_status s1_half(kmx_space* sp, int space, const double* x, double* out, double alpha, double tol, int max_iter,
+                   int* iters, hipStream_t s) {
+    const int64_t n = space == SP_E ? sp->n_e : sp->n_h;
+    double* y = s1_vec(sp, S1_Y);
+    double* sol = s1_vec(sp, space == SP_E ? S1_XE : S1_XH);
+    s1_rhs(sp, space, x, y, s);
+    int it = 0;
+    kmx_status st = s1_pcg(sp, space, y, sol, tol, max_iter, sp->s1_expect[space == SP_E ? 0 : 1], &it, s);
+    *iters += it;
+    if (st != KMX_OK) return st;
+    sp->s1_expect[space == SP_E ? 0 : 1] = it;
+    ProfScope ps(sp, s, PK_VEC);
+    launch_axpby(sol, out, n, alpha, nullptr, 1.0, s);
+    return KMX_OK;
+}
+
+kmx_status s1_check(kmx_space* sp, double tol, int max_iter) {
+    if (!sp) return fail(KMX_E_ARG, "space is NULL");
+    if (!(tol > 0.0) || !(tol < 1.0)) return fail(KMX_E_ARG, "tol must be in (0, 1)");
+    if (max_iter < 1) return fail(KMX_E_ARG, "max_iter must be >= 1");
+    if (sp->precision == KMX_MIXED) return fail(KMX_E_STATE, "the first scheme runs in FP64 spaces only");
+    return s1_prepare(sp);
+}
+
+}  // namespace
+
+extern "C" {
+
+kmx_status kmx_op_mass1(kmx_space* sp, int which, const double* x, double* y, void* stream) {
+    if (!sp || !x || !y || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
+    kmx_status st = s1_prepare(sp);
+    if (st != KMX_OK) return st;
+    run_mass1(sp, which == 0 ? SP_E : SP_H, x, y, static_cast<hipStream_t>(stream));
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_solve_mass1(kmx_space* sp, int which, const double* y, double* x, double tol, int max_iter,
+                           int* iters, void* stream) {
+    if (!y || !x || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
+    kmx_status st = s1_check(sp, tol, max_iter);
+    if (st != KMX_OK) return st;
+    if (x == y) return fail(KMX_E_ARG, "x and y must not alias");
+    int it = 0;
+    st = s1_pcg(sp, which == 0 ? SP_E : SP_H, y, x, tol, max_iter, 0, &it, static_cast<hipStream_t>(stream));
+    if (iters) *iters = it;
+    if (st != KMX_OK) return st;
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_half_step_scheme1(kmx_space* sp, int which, const double* x, double* out, double alpha, double tol,
+                                 int max_iter, int* iters, void* stream) {
+    if (!x || !out || (which != 0 && which != 1)) return fail(KMX_E_ARG, "bad argument");
+    kmx_status st = s1_check(sp, tol, max_iter);
+    if (st != KMX_OK) return st;
+    int it = 0;
+    st = s1_half(sp, which == 0 ? SP_E : SP_H, x, out, alpha, tol, max_iter, &it, static_cast<hipStream_t>(stream));
+    if (iters) *iters = it;
+    if (st != KMX_OK) return st;
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, double tol, int max_iter,
+                            int* iters, void* stream) {
+    if (!e || !h) return fail(KMX_E_ARG, "NULL field");
+    if (nsteps < 0) return fail(KMX_E_ARG, "nsteps must be >= 0");
+    if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt must be finite");
+    kmx_status st = s1_check(sp, tol, max_iter);
+    if (st != KMX_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int it[2] = {0, 0};
+    for (int n = 0; n < nsteps && st == KMX_OK; ++n) {
+        st = s1_half(sp, SP_H, e, h, -dt, tol, max_iter, &it[1], s);
+        if (st == KMX_OK) st = s1_half(sp, SP_E, h, e, dt, tol, max_iter, &it[0], s);
+    }
+    if (iters) {
+        iters[0] = it[0];
+        iters[1] = it[1];
+    }
+    if (st != KMX_OK) return st;
     CHECK_LAUNCH();
     return KMX_OK;
 }

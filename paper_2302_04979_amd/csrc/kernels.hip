@@ -10,7 +10,11 @@ namespace kmx {
 // ===========================================================================
 // Mass apply (Section 3.4): y_i = sum_q w^_i(q) . G(q) X(q) / gamma_e over the
 // Gauss points q of every element, with X(q) the parametric vector proxy of the
-// input 2-form (or of the curl of the input 1-form).  One workgroup owns a
+// input 2-form (or of the curl of the input 1-form).  The same kernel applies
+// the 1-form masses of the first scheme (Section 3.3): there G(q) is the
+// covariant factor det DF (DF^T DF)^{-1} and the material multiplies,
+// y_i = sum_q w^_i(q) . G(q) X(q) gamma_e; the per-element array the kernel
+// reads holds 1/gamma for 2-forms and gamma for 1-forms.  One workgroup owns a
 // tile of TILE^3 elements and one thread owns one (x, y) Gauss-point column
 // of it.  Sum factorisation in three parts:
 //   1. the tile's coefficient window is contracted along y and x once (LDS),
@@ -87,8 +91,10 @@ static int64_t patch_size_t(int ntile, int64_t off[3]) {
 
 int64_t patch_size(int p, int space, int ntile, int64_t off[3]) {
 #define PS(PP)                                                                          \
-    if (p == PP) return space == SP_B ? patch_size_t<PP, SP_B>(ntile, off)              \
-                                      : patch_size_t<PP, SP_D>(ntile, off);
+    if (p == PP) return space == SP_B   ? patch_size_t<PP, SP_B>(ntile, off)            \
+                      : space == SP_D   ? patch_size_t<PP, SP_D>(ntile, off)            \
+                      : space == SP_E   ? patch_size_t<PP, SP_E>(ntile, off)            \
+                                        : patch_size_t<PP, SP_H>(ntile, off);
     PS(2) PS(3) PS(4)
 #undef PS
     return 0;
@@ -458,6 +464,11 @@ __global__ void __launch_bounds__(MassCfg<P>::NT) __attribute__((amdgpu_waves_pe
 mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __restrict__ axt) {
     constexpr int NQ = P + 1, Q = TILE * NQ, NT = MassCfg<P>::NT;
     constexpr int SRC = CURL ? (SPACE == SP_B ? SP_E : SP_H) : SPACE;
+    // 1-form spaces (the mass matrices of the first scheme): the covariant
+    // factor det DF (DF^T DF)^{-1} and the material as a factor; 2-form spaces:
+    // DF^T DF / det DF and the material's inverse
+    constexpr bool FORM1 = SPACE == SP_E || SPACE == SP_H;
+    static_assert(!(FORM1 && CURL), "the curl is fused only into the 2-form masses");
     using L0 = Lay<P, SPACE, 0>;
     using L1 = Lay<P, SPACE, 1>;
     using L2 = Lay<P, SPACE, 2>;
@@ -515,7 +526,7 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
     else if (tr && wave == 2)
         track_column_load<L2, WYM>(tr + A.track_comp_off[2], A.track_dims[2], tx, ty, tz, nt, lane, tk, tv);
 
-    // ---- per (x, y) column: 1/gamma of its four elements and, for the analytic
+    // ---- per (x, y) column: 1/gamma (1-forms: gamma) of its four elements and, for the analytic
     // metric, q = a grad s = (a1 s_z, a2 s_z, a3 c_z) up to the z factors; read
     // here, before the column registers fill up ----
     // (analytic metric: ig[le] holds w_x w_y / gamma_e, and a12 = a1 + a2)
@@ -659,15 +670,18 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
                 // analytic metric: with q = a grad s, DF = I + 1 q^T, det DF = 1 + q.1 and
                 // w DF^T DF / det DF = f (I + q 1^T + 1 q^T + 3 q q^T), f = w / det DF,
                 // applied below as a rank-2 update of the identity
-                double q1 = 0.0, q2 = 0.0, q3 = 0.0, sf = 0.0;
+                double q1 = 0.0, q2 = 0.0, q3 = 0.0, sf = 0.0, dd = 1.0, rd = 1.0;
                 if (MET == 1) {
                     const int gzq = tz * TILE * NQ + qz;
                     const double sz = axt[gzq], cz = axt[npq + gzq], wz = axt[2 * npq + gzq];
                     q1 = a1 * sz;
                     q2 = a2 * sz;
                     q3 = a3 * cz;
-                    // s f = (w / gamma_e) / det DF, det DF = 1 + (a1 + a2) s_z + a3 c_z
-                    sf = (ig[le] * wz) * recip_nr(fma(a12, sz, fma(a3, cz, 1.0)));
+                    // det DF = 1 + (a1 + a2) s_z + a3 c_z
+                    dd = fma(a12, sz, fma(a3, cz, 1.0));
+                    rd = recip_nr(dd);
+                    // 2-form: s f = (w / gamma_e) / det DF; 1-form: w gamma_e
+                    sf = FORM1 ? ig[le] * wz : (ig[le] * wz) * rd;
                 }
                 const double* t0 = tz0 + qz * L0::Kz;
                 const double* t2 = tz2 + qz * L2::Kz;
@@ -679,7 +693,17 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
 #pragma unroll
                 for (int j = 0; j < L2::Kz; ++j) v2 += t2[j] * A2[le + j];
                 double u0, u1, u2;
-                if (MET == 1) {
+                if (MET == 1 && FORM1) {
+                    // DF^{-1} = I - 1 q^T / d (d = det DF), so
+                    // det DF (DF^T DF)^{-1} v = d v - S q + (|q|^2 S / d - Q) 1,
+                    // S = sum v, Q = q . v, scaled by sf = w gamma_e
+                    const double Sv = v0 + v1 + v2, Qv = fma(q1, v0, fma(q2, v1, q3 * v2));
+                    const double qq = fma(q1, q1, fma(q2, q2, q3 * q3));
+                    const double sd = sf * dd, ss = -sf * Sv, c1 = sf * fma(qq * Sv, rd, -Qv);
+                    u0 = fma(sd, v0, fma(ss, q1, c1));
+                    u1 = fma(sd, v1, fma(ss, q2, c1));
+                    u2 = fma(sd, v2, fma(ss, q3, c1));
+                } else if (MET == 1) {
                     // G v = f (v + (S + 3 Q) q + Q 1), S = sum v, Q = q . v, as
                     // u = sf v + (sf (S + 3 Q)) q + sf Q 1
                     const double Qv = fma(q1, v0, fma(q2, v1, q3 * v2));
@@ -766,9 +790,13 @@ void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipS
         if (space == SP_B) {                                                        \
             if (curl) launch_mass_t<PP, SP_B, true>(a, grid, s);                    \
             else launch_mass_t<PP, SP_B, false>(a, grid, s);                        \
-        } else {                                                                    \
+        } else if (space == SP_D) {                                                 \
             if (curl) launch_mass_t<PP, SP_D, true>(a, grid, s);                    \
             else launch_mass_t<PP, SP_D, false>(a, grid, s);                        \
+        } else if (space == SP_E) {                                                 \
+            launch_mass_t<PP, SP_E, false>(a, grid, s);                             \
+        } else {                                                                    \
+            launch_mass_t<PP, SP_H, false>(a, grid, s);                             \
         }                                                                           \
         return;                                                                     \
     }
@@ -865,7 +893,9 @@ void launch_gather(int p, int space, const GatherArgs& a, int64_t n, int batch, 
 #define LG(PP)                                                                                         \
     if (p == PP) {                                                                                     \
         if (space == SP_D) hipLaunchKernelGGL((gather_kernel<PP, SP_D>), grid, dim3(256), 0, s, a, n); \
-        else hipLaunchKernelGGL((gather_kernel<PP, SP_B>), grid, dim3(256), 0, s, a, n);               \
+        else if (space == SP_B) hipLaunchKernelGGL((gather_kernel<PP, SP_B>), grid, dim3(256), 0, s, a, n); \
+        else if (space == SP_E) hipLaunchKernelGGL((gather_kernel<PP, SP_E>), grid, dim3(256), 0, s, a, n); \
+        else hipLaunchKernelGGL((gather_kernel<PP, SP_H>), grid, dim3(256), 0, s, a, n);               \
         return;                                                                                        \
     }
     LG(2) LG(3) LG(4)

@@ -260,10 +260,11 @@ static inline int64_t qp_index(const Tables& tb, int ez, int ey, int ex, int iz,
     return ((((ez * N + ey) * N + ex) * nq + iz) * nq + iy) * nq + ix;
 }
 
-// Metric factor w_q DF^T DF / det DF at every Gauss point, laid out per tile of
+// Metric factor w_q DF^T DF / det DF (2-forms) or w_q det DF (DF^T DF)^{-1}
+// (1-forms, the covariant pullback) at every Gauss point, laid out per tile of
 // TILE^3 elements as [tile][qz][6][qy][qx] with Q = TILE*nq points per tile
 // edge; entries 0..5 = (xx, yy, zz, xy, xz, yz).  Padded elements get zeros.
-kmx_status build_metric(const kmx_space* sp, std::vector<double>* out) {
+kmx_status build_metric(const kmx_space* sp, std::vector<double>* out, int form) {
     const Tables& tb = sp->tb;
     const int nq = tb.nq, Q = TILE * nq, nt = sp->ntile, N = tb.N;
     if (out) out->assign(size_t(nt) * nt * nt * Q * 6 * Q * Q, 0.0);
@@ -284,10 +285,23 @@ kmx_status build_metric(const kmx_space* sp, std::vector<double>* out) {
                             if (!out) continue;
                             double C[6];
                             const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
-                            for (int k = 0; k < 6; ++k) {
-                                double s = 0.0;
-                                for (int r = 0; r < 3; ++r) s += J[3 * r + ii[k]] * J[3 * r + jj[k]];
-                                C[k] = w * s / det;
+                            double S[3][3];
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j) {
+                                    double s = 0.0;
+                                    for (int r = 0; r < 3; ++r) s += J[3 * r + i] * J[3 * r + j];
+                                    S[i][j] = s;
+                                }
+                            if (form == 2) {
+                                for (int k = 0; k < 6; ++k) C[k] = w * S[ii[k]][jj[k]] / det;
+                            } else {
+                                // det (S^{-1}) = det * adj(S) / det(S), det(S) = det^2
+                                for (int k = 0; k < 6; ++k) {
+                                    const int i = ii[k], j = jj[k];
+                                    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                                    const double cof = S[j1][i1] * S[j2][i2] - S[j1][i2] * S[j2][i1];
+                                    C[k] = w * cof / det;
+                                }
                             }
                             const int qz = (ez % TILE) * nq + iz, qy = (ey % TILE) * nq + iy,
                                       qx = (ex % TILE) * nq + ix;

@@ -14,7 +14,8 @@ void band_solve_host(const BandLU& f, double* x, int64_t stride);
 void build_tables(Tables& tb, int p, int N);
 void map_jacobian(const kmx_space* sp, int64_t qp_index, const double xh[3], double J[9]);
 void map_point(const kmx_space* sp, const double xh[3], double x[3]);
-kmx_status build_metric(const kmx_space* sp, std::vector<double>* out);  // out = nullptr: check det DF only
+// form 2: w DF^T DF / det DF; form 1: w det DF (DF^T DF)^{-1}.  out = nullptr: check det DF only
+kmx_status build_metric(const kmx_space* sp, std::vector<double>* out, int form = 2);
 void quad_points(const kmx_space* sp, double* xyz);
 void comp_dims(const kmx_space* sp, int space, int c, int dims[3]);
 int64_t comp_offset(const kmx_space* sp, int space, int c);

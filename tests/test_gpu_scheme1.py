@@ -1,0 +1,137 @@
+"""GPU parity of the first scheme (Section 3.3: 1-form mass matrices solved by
+preconditioned CG) against the FP64 oracle: the 1-form mass applies, the mass
+solves, one half step, several leapfrog steps, and the leapfrog invariant.
+
+Tolerances.  The applies are sums of the same products in another order
+(1e-13).  The solves stop at |y - M x| <= tol |y| (tol = 1e-14 here); the
+oracle's CG goes to 1e-15.  The solution error is then bounded by
+cond(M) * 1e-14; cond(M) of these bases is below 1e3 for p <= 4 (measured by
+the oracle's dense matrices at N = 3), so solutions and steps are compared at
+1e-10 relative, the true residual at 1e-12.  The invariant drifts by the
+solve error only: 1e-10 over the run."""
+import numpy as np
+import pytest
+
+import workloads as W
+from _helpers import rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-14
+CASES = [(2, 3, True, False), (3, 5, True, False), (3, 8, True, False), (4, 6, True, False),
+         (3, 4, False, False), (3, 5, True, True)]
+
+
+def _make(p, N, deformed, stored):
+    from oracle.geometry import Map
+    from oracle.scheme1 import Scheme1
+    import paper_2302_04979_amd as K
+    eps, mu = W.eps_elements(N, 0), W.eps_elements(N, 1, 1.0, 2.0)
+    geo = Map("sine", W.DEFORMED_AMPLITUDE) if deformed else Map("identity")
+    S = Scheme1(p, N, geo, eps=eps, mu=mu)
+    G = K.Space(p, N, map_kind=1 if deformed else 0, amplitude=W.DEFORMED_AMPLITUDE if deformed else 0.0,
+                stored_metric=stored)
+    G.set_materials(eps=eps, mu=mu)
+    return S, G
+
+
+@pytest.fixture(scope="module", params=CASES,
+                ids=lambda c: f"p{c[0]}N{c[1]}{'def' if c[2] else 'id'}{'-stored' if c[3] else ''}")
+def pair(request):
+    p, N, deformed, stored = request.param
+    print(f"\n[case] scheme 1 p={p} N={N} deformed={deformed} stored={stored}", flush=True)
+    return _make(p, N, deformed, stored)
+
+
+@pytest.mark.parametrize("space", ["E", "H"])
+def test_mass1_apply(pair, space):
+    S, G = pair
+    import torch
+    n = S.n_e if space == "E" else S.n_h
+    x = W.random_vector(n, 3)
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    G.op_mass1(space, to_dev(x), y)
+    assert rel(to_host(y), S.mass1_apply(space, x)) < 1e-13
+
+
+@pytest.mark.parametrize("space", ["E", "H"])
+def test_mass1_solve(pair, space):
+    S, G = pair
+    import torch
+    n = S.n_e if space == "E" else S.n_h
+    y = W.random_vector(n, 5)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    it = G.solve_mass1(space, to_dev(y), x, tol=TOL, max_iter=400)
+    xg = to_host(x)
+    ref, _ = S.mass1_solve(space, y)
+    assert 0 < it < 400
+    assert rel(xg, ref) < 1e-10
+    assert np.linalg.norm(y - S.mass1_apply(space, xg)) < 1e-12 * np.linalg.norm(y)
+    # a second solve from the solution as the guess stops at once
+    it2 = G.solve_mass1(space, to_dev(y), x, tol=1e-10, max_iter=400)
+    assert it2 <= 1 and rel(to_host(x), ref) < 1e-10
+
+
+def test_half_steps(pair):
+    S, G = pair
+    import torch
+    e = W.random_vector(S.n_e, 6)
+    h0 = W.random_vector(S.n_h, 7)
+    h = to_dev(h0)
+    G.half_step_scheme1("H", to_dev(e), h, -0.3, tol=TOL)
+    ref = h0 - 0.3 * S.mass1_solve("H", S.rhs_h(e))[0]
+    assert rel(to_host(h) - h0, ref - h0) < 1e-10
+    e0 = W.random_vector(S.n_e, 8)
+    eg = to_dev(e0)
+    G.half_step_scheme1("E", to_dev(h0), eg, 0.25, tol=TOL)
+    ref = e0 + 0.25 * S.mass1_solve("E", S.rhs_e(h0))[0]
+    assert rel(to_host(eg) - e0, ref - e0) < 1e-10
+
+
+def test_leapfrog_parity_and_invariant(pair):
+    S, G = pair
+    import torch
+    dt, nsteps = 0.1 / S.N, 12
+    e0 = W.random_vector(S.n_e, 9)
+    # staggered start from h^0 = 0 on both sides
+    h_o, _ = S.init_stagger1(e0, np.zeros(S.n_h), dt)
+    e_g, h_g = to_dev(e0), torch.zeros(S.n_h, dtype=torch.float64, device="cuda")
+    G.half_step_scheme1("H", e_g, h_g, 0.5 * dt, tol=TOL)
+    assert rel(to_host(h_g), h_o) < 1e-10
+
+    def invariant(e, h):
+        hh = h.clone()
+        G.half_step_scheme1("H", e, hh, -dt, tol=TOL)
+        Me = torch.empty_like(e)
+        Mh = torch.empty_like(h)
+        G.op_mass1("E", e, Me)
+        G.op_mass1("H", hh, Mh)
+        return 0.5 * float(e @ Me + h @ Mh)
+
+    E0 = invariant(e_g, h_g)
+    its = G.step_scheme1(e_g, h_g, dt, nsteps, tol=TOL)
+    e_o, h_o, _, _ = S.step1(e0, h_o, dt, nsteps)
+    assert rel(to_host(e_g), e_o) < 1e-10
+    assert rel(to_host(h_g), h_o) < 1e-10
+    assert its[0] > 0 and its[1] > 0
+    E1 = invariant(e_g, h_g)
+    assert abs(E1 / E0 - 1) < 1e-10
+    # the oracle's invariant of its own run agrees
+    Eo = S.energy1_modified(e_o, h_o, h_o - dt * S.mass1_solve("H", S.rhs_h(e_o))[0])
+    assert abs(E1 / Eo - 1) < 1e-10
+
+
+def test_zero_rhs_and_errors():
+    import torch
+    import paper_2302_04979_amd as K
+    G = K.Space(3, 4, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+    n = G.n_h
+    x = to_dev(W.random_vector(n, 1))
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    assert G.solve_mass1("H", y, x, tol=1e-12) == 0
+    assert float(x.abs().max()) == 0.0
+    with pytest.raises(K.KMXError):
+        G.solve_mass1("H", y, x, tol=0.0)
+    with pytest.raises(K.KMXError):
+        G.solve_mass1("E", to_dev(W.random_vector(G.n_e, 2)), torch.zeros(G.n_e, dtype=torch.float64,
+                                                                          device="cuda"), tol=1e-14, max_iter=1)
