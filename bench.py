@@ -42,7 +42,7 @@ def mass_flops(p, N, space):
     T, nq = 4, p + 1
     Q = T * nq
     K = {"Pv": p + 1, "Pd": p, "Dv": p, "Dd": p - 1}
-    along, across = ("Pv", "Pd") if space == "B" else ("Dv", "Dd")
+    along, across = {"B": ("Pv", "Pd"), "D": ("Dv", "Dd"), "E": ("Pd", "Pv"), "H": ("Dd", "Dv")}[space]
     fma_xy = 0
     kz_sum = 0
     for c in range(3):
@@ -211,11 +211,52 @@ def mixed_vs_fp64(K, W, torch, p, N, steps, eps, dt=None, E0=None, H0=None, G64=
             "energy_rel_drift_mixed": float(((enm / enm[0]) - 1).abs().max())}
 
 
+def scheme1_timing(K, W, torch, G, e0, dt2, ms_step2, steps=20, tol=1e-12):
+    """The first scheme (1-form mass solves by PCG) on the same space and
+    initial e as the headline run: its CFL next to scheme 2's, ms per step at
+    dt = 0.5 CFL with the solves to |r| <= tol |y|, CG iterations per solve, the
+    1-form mass kernel's launch time and FLOP rate, and the per-step and
+    per-simulated-time ratios to scheme 2."""
+    p, N = G.p, G.N
+    cfl1 = G.cfl_scheme1(max_iter=300, tol=1e-6, cg_tol=1e-10)
+    dt1 = 0.5 * cfl1
+    e = e0.clone()
+    h = torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+    G.half_step_scheme1("H", e, h, 0.5 * dt1, tol=tol)
+    G.step_scheme1(e, h, dt1, 3, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = G.step_scheme1(e, h, dt1, steps, tol=tol)
+    torch.cuda.synchronize()
+    ms1 = (time.perf_counter() - t0) * 1e3 / steps
+    G.profile_begin(capacity=4096)
+    G.step_scheme1(e, h, dt1, 4, tol=tol)
+    prof = G.profile_end()
+    m = prof["mass_1form"]
+    avg = m[0] / m[1] * 1e-3
+    flops = 0.5 * (mass_flops(p, N, "E") + mass_flops(p, N, "H"))
+    share = {k: round(v[0] / sum(x[0] for x in prof.values()), 3) for k, v in prof.items() if v[1]}
+    cfl2 = 2.0 * dt2
+    te, th = measured_traffic("mass_E"), measured_traffic("mass_H")
+    return {"workload": f"first scheme (1-form mass solves), same space, e^0 and eps as the headline, mu = 1, "
+                        f"dt = 0.5 CFL1, PCG to |r| <= {tol:g} |y|, warm-started",
+            "ms_per_step": ms1, "steps": steps, "dt": dt1,
+            "cg_iters_per_solve": {"e": its[0] / steps, "h": its[1] / steps},
+            "cfl": cfl1, "cfl_scheme2": cfl2, "cfl_ratio": cfl1 / cfl2,
+            "per_step_ratio_vs_scheme2": ms1 / ms_step2,
+            "per_simulated_time_ratio_vs_scheme2": (ms1 / dt1) / (ms_step2 / dt2),
+            "mass_1form_kernel": {"avg_launch_us": round(avg * 1e6, 2),
+                                  "tflops": round(flops / avg / 1e12, 2),
+                                  "frac_fp64_peak": round(flops / avg / 1e12 / FP64_PEAK_TFLOPS, 4),
+                                  "traffic": None if te is None or th is None else 0.5 * (te + th)},
+            "time_share": share}
+
+
 def profile_run(K, W, torch, p, N, steps):
     """A short run for the profiler: a device copy of known size (512 MiB read,
     512 MiB written: the reference for the HBM byte counters), then `steps`
     steps of the metric workload's kernels from a seeded random state under
-    each of the three tiled plans."""
+    each of the three tiled plans, then two steps of the first scheme."""
     import numpy as np
     n = 64 * 1024 * 1024  # doubles: 512 MiB
     src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -234,6 +275,8 @@ def profile_run(K, W, torch, p, N, steps):
     for plan in (K.PLAN_TILED, K.PLAN_TILED_W4, K.PLAN_TILED_DENSE):
         G.set_plan(plan)
         G.step(E, H, 1e-3, nsteps=steps, flags=K.TRACK_DB, energy=en)
+    # two steps of the first scheme (1-form mass kernels, PCG)
+    G.step_scheme1(E[:G.n_e], H[:G.n_h], 1e-3, 2, tol=1e-10)
     torch.cuda.synchronize()
     return {"profile_run": {"copy_bytes_each_way": n * 8, "copies": 3, "steps": steps, "p": p, "N": N}}
 
@@ -305,6 +348,8 @@ def main():
     ap.add_argument("--only-mixed", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
     ap.add_argument("--only-batched", action="store_true")
+    ap.add_argument("--no-scheme1", action="store_true")
+    ap.add_argument("--only-scheme1", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -346,6 +391,19 @@ def main():
     dt = 0.5 * G.cfl(max_iter=300, tol=1e-6)
     log(f"dt = {dt:.6e}")
     flags = K.TRACK_DB
+    if args.only_scheme1:
+        # scheme 2 on the same state for the ratio (plain step, eager), then scheme 1
+        e2, h2 = E[:G.n_e].clone(), torch.zeros(G.n_h, dtype=torch.float64, device=dev)
+        G.init_stagger(e2, h2, dt)
+        G.step(e2, h2, dt, nsteps=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.step(e2, h2, dt, nsteps=args.steps)
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t0) * 1e3 / args.steps
+        print(json.dumps({"scheme2_ms_per_step_plain": ms2,
+                          "scheme1": scheme1_timing(K, W, torch, G, E[:G.n_e].clone(), dt, ms2)}), flush=True)
+        return
     G.init_stagger(E, H, dt, flags=flags)
     # the library's tuner picks the plan (tiled with banded or dense solves here)
     tune_ms = G.tune(1, dt, probe_steps=10)
@@ -474,6 +532,11 @@ def main():
         log("mixed precision, p=4 64^3, 500 steps")
         mixed["p4_n64_500_steps"] = mixed_vs_fp64(K, W, torch, 4, 64, 500, W.eps_elements(64, 0))
 
+    scheme1 = None
+    if not args.no_scheme1:
+        log("first scheme")
+        scheme1 = scheme1_timing(K, W, torch, G, e_only, dt, ms_per_step)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
@@ -509,6 +572,7 @@ def main():
         "mixed": mixed,
         "adjoint_grad_s": adjoint_s,
         "batched": batched,
+        "scheme1": scheme1,
     }
     print(json.dumps(out), flush=True)
 
