@@ -272,6 +272,31 @@ kmx_status kmx_op_solve(kmx_space* sp, int which, int transpose, const double* y
 /* y = K x with K = K1 (which = 1) or K~1 (which = 0). */
 kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, void* stream);
 
+/* ---- higher-order symplectic time stepping -------------------------------
+ * Symmetric compositions of the leapfrog (kick-drift-kick) of order 2, 4, 6:
+ * step weights c_1..c_m with m = 1, 3, 9, from the triple jump
+ * c <- (z1 c, z0 c, z1 c), z1 = 1 / (2 - 2^(1/(2k+1))), z0 = 1 - 2 z1 (Yoshida
+ * 1990); the paper names higher-order symplectic integrators as the way past
+ * the time-error plateau of the leapfrog (Section 6).  The state is (e^n, h^)
+ * with h^ = h^n + (c_1 dt / 2) K~1^{-1} M D^1 e^n (for order 2 the leapfrog's
+ * h^{n-1/2}); one step runs m substeps
+ *     h^ -= a_j dt K~1^{-1} M D^1 e;   e += c_j dt K1^{-1} M~ D~^1 h^
+ * with a_1 = c_1 and a_j = (c_{j-1} + c_j) / 2, so order 2 is kmx_step.
+ * Tracked b and d (KMX_TRACK_DB) follow the same kicks.  No sources, no
+ * energy output; the tiled plans only (KMX_E_STATE for a separable plan;
+ * KMX_PLAN_AUTO runs the tiled plan).  The stable step shrinks with the
+ * largest |c_j| (1.70 at order 4, 2.30 at order 6). */
+
+/* The staggered start of a composed run: h^ = h^0 + (c_1 dt / 2) K~1^{-1} M D^1 e^0
+ * (kmx_init_stagger with c_1 dt).  order: 2, 4 or 6. */
+kmx_status kmx_init_split(kmx_space* sp, const double* E, double* H, double dt, int order, int batch,
+                          int flags, void* stream);
+
+/* nsteps composed steps of the given order (2, 4, 6) on (E, H) as kmx_step
+ * lays them out. */
+kmx_status kmx_step_split(kmx_space* sp, double* E, double* H, double dt, int nsteps, int order, int batch,
+                          int flags, void* stream);
+
 /* ---- the first scheme: Hodge stars with 1-form mass matrices -------------
  * Section 3.3, eqs. (3.5)-(3.8): M^1_eps e = K~2 d and M~^1_mu h = K2 b, with
  * K~2 = K1^T and K2 = K~1^T (the pairing-transpose property of Section 2.4),
@@ -315,6 +340,12 @@ kmx_status kmx_half_step_scheme1(kmx_space* sp, int which, const double* x, doub
  * iterations of the e solves and of the h solves. */
 kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, double tol, int max_iter,
                             int* iters, void* stream);
+
+/* Largest stable time step of the first scheme, 2 / sqrt(lambda_max) of
+ * (M^1_eps)^{-1} K1^T D~^1 (M~^1_mu)^{-1} K~1^T D^1 by power iteration from the
+ * same seeded start as kmx_cfl (stops when lambda changes by at most tol
+ * relative), each mass solve to cg_tol.  Allocates two fields; synchronises. */
+kmx_status kmx_cfl_scheme1(kmx_space* sp, int max_iter, double tol, double cg_tol, double* dt_max);
 
 /* ---- probes and the adjoint (gradient of a probe misfit in eps) ----------
  * Not part of the paper, which has no inverse problem: the exact discrete

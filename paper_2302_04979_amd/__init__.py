@@ -40,7 +40,8 @@ EXPORTS = (
     "kmx_set_refinement",
     "kmx_graph_create", "kmx_graph_launch",
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
-    "kmx_op_mass1", "kmx_solve_mass1", "kmx_half_step_scheme1", "kmx_step_scheme1",
+    "kmx_op_mass1", "kmx_solve_mass1", "kmx_half_step_scheme1", "kmx_step_scheme1", "kmx_cfl_scheme1",
+    "kmx_init_split", "kmx_step_split",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
                  "mode_fp32", "dense_fp64", "mass_1form", "cg_vector")
@@ -114,6 +115,9 @@ def load_library():
         "kmx_solve_mass1": ([vp, i, vp, vp, d, i, ctypes.POINTER(i), vp], i),
         "kmx_half_step_scheme1": ([vp, i, vp, vp, d, d, i, ctypes.POINTER(i), vp], i),
         "kmx_step_scheme1": ([vp, vp, vp, d, i, d, i, vp, vp], i),
+        "kmx_cfl_scheme1": ([vp, i, d, d, ctypes.POINTER(d)], i),
+        "kmx_init_split": ([vp, vp, vp, d, i, i, i, vp], i),
+        "kmx_step_split": ([vp, vp, vp, d, i, i, i, i, vp], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -307,6 +311,20 @@ class Space:
                                        float(t_start), float(dt), int(nsteps), int(batch), int(flags), en,
                                        _stream()))
 
+    def init_split(self, E, H, dt, order, batch=1, flags=0):
+        """Staggered start of a composed run of the given order (2, 4, 6)."""
+        k = 1 + (flags & TRACK_DB)
+        _check(load_library().kmx_init_split(self._h, _dptr(E, batch * k * self.n_e, "E"),
+                                             _dptr(H, batch * k * self.n_h, "H"), float(dt), int(order),
+                                             int(batch), int(flags), _stream()))
+
+    def step_split(self, E, H, dt, nsteps, order, batch=1, flags=0):
+        """nsteps symmetric-composition steps of order 2, 4 or 6 (source free)."""
+        k = 1 + (flags & TRACK_DB)
+        _check(load_library().kmx_step_split(self._h, _dptr(E, batch * k * self.n_e, "E"),
+                                             _dptr(H, batch * k * self.n_h, "H"), float(dt), int(nsteps),
+                                             int(order), int(batch), int(flags), _stream()))
+
     def energy(self, E, H, dt, batch=1) -> np.ndarray:
         out = np.empty(2 * batch)
         _check(load_library().kmx_energy(self._h, _dptr(E, batch * 2 * self.n_e, "E"),
@@ -369,6 +387,12 @@ class Space:
                                                float(dt), int(nsteps), float(tol), int(max_iter),
                                                ctypes.cast(it, ctypes.c_void_p), _stream()))
         return int(it[0]), int(it[1])
+
+    def cfl_scheme1(self, max_iter=2000, tol=1e-10, cg_tol=1e-12) -> float:
+        out = ctypes.c_double()
+        _check(load_library().kmx_cfl_scheme1(self._h, int(max_iter), float(tol), float(cg_tol),
+                                              ctypes.byref(out)))
+        return out.value
 
     def set_refinement(self, steps: int):
         """Number of FP64-residual corrections of mixed-precision solves."""

@@ -1244,6 +1244,38 @@ kmx_status run_sep(kmx_space* sp, double* E, double* H, const kmx_source* J, dou
     return KMX_OK;
 }
 
+// One kick-drift substep of the tiled plans:
+//   h -= ka K~1^{-1} M D^1 e   (b -= ka D^1 e when tracking)
+//   e += kb K1^{-1} (M~ D~^1 h - s(t_half))   (d += kb D~^1 h)
+// the leapfrog step with ka = kb = dt, a substep of a composition otherwise.
+static void tiled_substep(kmx_space* sp, double* E, double* H, int64_t es, int64_t hs, double ka, double kb, int batch,
+                   int track, bool dense, bool mixed, const kmx_source* J, double t_half, const double* t_dev,
+                   hipStream_t s) {
+    const int64_t nf = std::max(sp->n_e, sp->n_h);
+    // M D^1 e (and b -= ka D^1 e), then h -= ka K~1^{-1} (.)
+    run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -ka);
+    if (dense && !mixed) {
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+        dense_solve(sp, 0, sp->d_tmp2, H, hs, -ka, batch, nullptr, 0.0, nullptr, s);
+    } else if (mixed) {
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+        mixed_solve(sp, 0, 0, sp->d_my, H, hs, -ka, 1, batch, s);
+    } else {
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -ka, 1, batch, nullptr, 0.0, 1, s);
+    }
+    // M~ D~^1 h (and d += kb D~^1 h), then e += kb K1^{-1} (. - s)
+    run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, kb);
+    if (dense && !mixed) {
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+        dense_solve(sp, 1, sp->d_tmp2, E, es, kb, batch, J, t_half, t_dev, s);
+    } else if (mixed) {
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev);
+        mixed_solve(sp, 1, 0, sp->d_my, E, es, kb, 1, batch, s);
+    } else {
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, kb, 1, batch, J, t_half, 1, s, nullptr, t_dev);
+    }
+}
+
 kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, const double* t_dev,
                      double dt, int nsteps, int batch, int flags, double* energy_dev, hipStream_t s) {
     if (!sp || !E || !H) return fail(KMX_E_ARG, "NULL argument");
@@ -1273,31 +1305,9 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     const bool mixed = sp->precision == KMX_MIXED;
     const bool dense = kind == KMX_PLAN_TILED_DENSE;
     sp->mass_waves4 = kind == KMX_PLAN_TILED_W4 ? 1 : 0;
-    const int64_t nf = std::max(sp->n_e, sp->n_h);
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
-        // M D^1 e (and b -= dt D^1 e), then h -= dt K~1^{-1} (.)
-        run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -dt);
-        if (dense && !mixed) {
-            run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
-            dense_solve(sp, 0, sp->d_tmp2, H, hs, -dt, batch, nullptr, 0.0, nullptr, s);
-        } else if (mixed) {
-            run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
-            mixed_solve(sp, 0, 0, sp->d_my, H, hs, -dt, 1, batch, s);
-        } else {
-            run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -dt, 1, batch, nullptr, 0.0, 1, s);
-        }
-        // M~ D~^1 h (and d += dt D~^1 h), then e += dt K1^{-1} (. - s)
-        run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, dt);
-        if (dense && !mixed) {
-            run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
-            dense_solve(sp, 1, sp->d_tmp2, E, es, dt, batch, J, t_half, t_dev, s);
-        } else if (mixed) {
-            run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev);
-            mixed_solve(sp, 1, 0, sp->d_my, E, es, dt, 1, batch, s);
-        } else {
-            run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, dt, 1, batch, J, t_half, 1, s, nullptr, t_dev);
-        }
+        tiled_substep(sp, E, H, es, hs, dt, dt, batch, track, dense, mixed, J, t_half, t_dev, s);
         if (energy_dev) run_energy(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, 1, s);
     }
     if (t_dev) launch_advance_time(const_cast<double*>(t_dev), nsteps * dt, s);
@@ -1309,6 +1319,55 @@ kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, do
                     int nsteps, int batch, int flags, double* energy_dev, void* stream) {
     return step_loop(sp, E, H, J, t_start, nullptr, dt, nsteps, batch, flags, energy_dev,
                      static_cast<hipStream_t>(stream));
+}
+
+// Weights c_1..c_m of the symmetric triple-jump composition of the leapfrog
+// of the given even order (2: the leapfrog; 2k+2: z1, z0, z1 times the order-2k
+// weights, z1 = 1 / (2 - 2^(1/(2k+1))), z0 = 1 - 2 z1).
+static std::vector<double> composition_weights(int order) {
+    std::vector<double> c{1.0};
+    for (int k = 1; k < order / 2; ++k) {
+        const double z1 = 1.0 / (2.0 - std::pow(2.0, 1.0 / (2 * k + 1))), z0 = 1.0 - 2.0 * z1;
+        std::vector<double> n;
+        for (double z : {z1, z0, z1})
+            for (double w : c) n.push_back(w * z);
+        c.swap(n);
+    }
+    return c;
+}
+
+kmx_status kmx_init_split(kmx_space* sp, const double* E, double* H, double dt, int order, int batch, int flags,
+                          void* stream) {
+    if (order != 2 && order != 4 && order != 6) return fail(KMX_E_ARG, "order must be 2, 4 or 6");
+    return kmx_init_stagger(sp, E, H, composition_weights(order)[0] * dt, batch, flags, stream);
+}
+
+kmx_status kmx_step_split(kmx_space* sp, double* E, double* H, double dt, int nsteps, int order, int batch,
+                          int flags, void* stream) {
+    if (!sp || !E || !H) return fail(KMX_E_ARG, "NULL argument");
+    if (order != 2 && order != 4 && order != 6) return fail(KMX_E_ARG, "order must be 2, 4 or 6");
+    if (batch < 1 || batch > sp->max_batch) return fail(KMX_E_ARG, "batch out of range");
+    if (nsteps < 0) return fail(KMX_E_ARG, "nsteps < 0");
+    if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt not finite");
+    int kind = sp->plan_kind;
+    if (kind == KMX_PLAN_SEPARABLE || kind == KMX_PLAN_SEPARABLE_FUSED)
+        return fail(KMX_E_STATE, "composed steps run the tiled plans only");
+    if (kind == KMX_PLAN_AUTO) kind = KMX_PLAN_TILED;
+    const int track = flags & KMX_TRACK_DB;
+    const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
+    const bool mixed = sp->precision == KMX_MIXED;
+    const bool dense = kind == KMX_PLAN_TILED_DENSE;
+    sp->mass_waves4 = kind == KMX_PLAN_TILED_W4 ? 1 : 0;
+    const std::vector<double> c = composition_weights(order);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int n = 0; n < nsteps; ++n)
+        for (size_t j = 0; j < c.size(); ++j) {
+            // the first kick also carries the previous step's last half kick (c_m = c_1)
+            const double a = j == 0 ? c[0] : 0.5 * (c[j - 1] + c[j]);
+            tiled_substep(sp, E, H, es, hs, a * dt, c[j] * dt, batch, track, dense, mixed, nullptr, 0.0, nullptr, s);
+        }
+    CHECK_LAUNCH();
+    return KMX_OK;
 }
 
 kmx_status kmx_set_time(kmx_space* sp, double t, void* stream) {
@@ -1548,7 +1607,6 @@ kmx_status s1_upload_padded(kmx_space* sp, double** dst, const std::vector<doubl
 // work vectors.  Synchronous; not for use under graph capture.
 kmx_status s1_prepare(kmx_space* sp) {
     if (!sp->dense_ok) return fail(KMX_E_STATE, "the first scheme needs the dense FP64 kernels (LDS too small)");
-    if (sp->max_batch < 1) return fail(KMX_E_STATE, "no batch capacity");
     kmx_status st;
     if (!sp->s1_ready) {
         if ((st = s1_upload_padded(sp, &sp->d_eps, sp->eps_host)) != KMX_OK) return st;
@@ -1646,7 +1704,7 @@ kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double t
                   int* iters, hipStream_t s) {
     const int64_t n = space == SP_E ? sp->n_e : sp->n_h;
     double *r = s1_vec(sp, S1_R), *z = s1_vec(sp, S1_Z), *pd = s1_vec(sp, S1_P), *Ap = s1_vec(sp, S1_AP);
-    double* sc = sp->d_scal;  // [0] r.z  [1] p.Ap  [2] new r.z  [3] r.r  [4] y.y
+    double* sc = sp->d_scal;  // [0], [2] r.z (alternating)  [1] p.Ap  [3] r.r  [4] y.y
     run_mass1(sp, space, x, Ap, s);
     HIP_TRY(hipMemcpyAsync(r, y, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     {
@@ -1669,16 +1727,24 @@ kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double t
     s1_precond(sp, space, r, z, s);
     HIP_TRY(hipMemcpyAsync(pd, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     s1_dot(sp, r, z, n, 0, s);
+    // r.z alternates between slots 0 and 2 so that no copy is needed
+    const int nb = energy_blocks(sp);
+    int cur = 0;
     int it = 0;
     while (true) {
         run_mass1(sp, space, pd, Ap, s);
         s1_dot(sp, pd, Ap, n, 1, s);
+        const int nxt = 2 - cur;
         {
             ProfScope ps(sp, s, PK_VEC);
-            launch_cg_update(x, r, pd, Ap, nullptr, n, sc, 0, s);
+            launch_cg2(x, r, pd, Ap, nullptr, n, sc + cur, sc + 1, 0, s);
         }
         ++it;
-        s1_dot(sp, r, r, n, 3, s);
+        s1_precond(sp, space, r, z, s);
+        {
+            ProfScope ps(sp, s, PK_VEC);
+            launch_dot2(r, z, n, sp->d_red, nb, sc + 3, sc + nxt, s);
+        }
         if (it >= expect - 1 || it >= max_iter) {
             double rr = 0.0;
             HIP_TRY(hipMemcpyAsync(&rr, sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1690,13 +1756,11 @@ kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double t
                 return fail(KMX_E_UNSTABLE, "mass solve did not reach the tolerance within max_iter iterations");
             }
         }
-        s1_precond(sp, space, r, z, s);
-        s1_dot(sp, r, z, n, 2, s);
         {
             ProfScope ps(sp, s, PK_VEC);
-            launch_cg_update(x, r, pd, Ap, z, n, sc, 1, s);
+            launch_cg2(x, r, pd, Ap, z, n, sc + nxt, sc + cur, 1, s);
         }
-        HIP_TRY(hipMemcpyAsync(sc, sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
+        cur = nxt;
     }
     *iters = it;
     return KMX_OK;
@@ -1787,6 +1851,58 @@ kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int 
     }
     if (st != KMX_OK) return st;
     CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_cfl_scheme1(kmx_space* sp, int max_iter, double tol, double cg_tol, double* dt_max) {
+    if (!dt_max || max_iter < 1) return fail(KMX_E_ARG, "bad argument");
+    kmx_status st = s1_check(sp, cg_tol, 1000);
+    if (st != KMX_OK) return st;
+    hipStream_t s = nullptr;
+    const int64_t ne = sp->n_e, nh = sp->n_h;
+    double *x = nullptr, *hb = nullptr;
+    if (hipMalloc(&x, ne * sizeof(double)) != hipSuccess || hipMalloc(&hb, nh * sizeof(double)) != hipSuccess) {
+        hipFree(x); hipFree(hb);
+        return fail(KMX_E_OOM, "device allocation failed (CFL vectors)");
+    }
+    // the same seeded start vector as kmx_cfl
+    std::vector<double> x0(ne);
+    uint64_t rs = 0x9E3779B97F4A7C15ull;
+    double nrm = 0.0;
+    for (int64_t i = 0; i < ne; ++i) {
+        rs = rs * 6364136223846793005ull + 1442695040888963407ull;
+        x0[i] = double(rs >> 11) / double(1ull << 53) - 0.5;
+        nrm += x0[i] * x0[i];
+    }
+    for (auto& v : x0) v /= std::sqrt(nrm);
+    hipMemcpy(x, x0.data(), ne * sizeof(double), hipMemcpyHostToDevice);
+    const int nb = energy_blocks(sp);
+    double lam = 0.0;
+    int it_cg = 0;
+    for (int it = 0; it < max_iter && st == KMX_OK; ++it) {
+        // x <- A1 x = M^{-1} K1^T D~^1 M~^{-1} K~1^T D^1 x, then normalised
+        hipMemsetAsync(hb, 0, nh * sizeof(double), s);
+        st = s1_half(sp, SP_H, x, hb, 1.0, cg_tol, 1000, &it_cg, s);
+        if (st != KMX_OK) break;
+        hipMemsetAsync(x, 0, ne * sizeof(double), s);
+        st = s1_half(sp, SP_E, hb, x, 1.0, cg_tol, 1000, &it_cg, s);
+        if (st != KMX_OK) break;
+        launch_dot(x, x, ne, ne, 1, sp->d_red, nb, s);
+        launch_sum_final(sp->d_red, nb, 1, sp->d_scal + 8, s);
+        double yy = 0.0;
+        hipMemcpy(&yy, sp->d_scal + 8, sizeof(double), hipMemcpyDeviceToHost);
+        const double lam_new = std::sqrt(yy);
+        if (!std::isfinite(lam_new) || lam_new <= 0.0) { st = fail(KMX_E_UNSTABLE, "power iteration failed"); break; }
+        launch_axpby(x, x, ne, 1.0 / lam_new, nullptr, 0.0, s);
+        const bool done = std::fabs(lam_new - lam) <= tol * lam_new;
+        lam = lam_new;
+        if (done) break;
+    }
+    hipDeviceSynchronize();
+    hipFree(x);
+    hipFree(hb);
+    if (st != KMX_OK) return st;
+    *dt_max = 2.0 / std::sqrt(lam);
     return KMX_OK;
 }
 

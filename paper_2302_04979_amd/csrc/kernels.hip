@@ -1864,6 +1864,67 @@ __global__ void cg_kernel(double* x, double* r, double* pdir, const double* Ap, 
     }
 }
 
+// r.r and r.z in one pass: per-block partials [block][2], then one
+// fixed-order final sum writing the two results to separate scalars.
+__global__ void __launch_bounds__(256) dot2_kernel(const double* r, const double* z, int64_t n, double* partial) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const double a = r[i];
+        s0 += a * a;
+        s1 += a * z[i];
+    }
+    __shared__ double red[3];
+    block_sum3<256>(s0, s1, 0.0, red);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = red[0];
+        partial[2 * blockIdx.x + 1] = red[1];
+    }
+}
+
+__global__ void __launch_bounds__(256) sum2_final_kernel(const double* partial, int nblocks, double* out0,
+                                                         double* out1) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += 256) {
+        s0 += partial[2 * k];
+        s1 += partial[2 * k + 1];
+    }
+    __shared__ double red[3];
+    block_sum3<256>(s0, s1, 0.0, red);
+    if (threadIdx.x == 0) {
+        out0[0] = red[0];
+        out1[0] = red[1];
+    }
+}
+
+void launch_dot2(const double* r, const double* z, int64_t n, double* partial, int nblocks, double* out0,
+                 double* out1, hipStream_t s) {
+    hipLaunchKernelGGL(dot2_kernel, dim3(nblocks), dim3(256), 0, s, r, z, n, partial);
+    hipLaunchKernelGGL(sum2_final_kernel, dim3(1), dim3(256), 0, s, partial, nblocks, out0, out1);
+}
+
+// CG updates with the step scalars addressed explicitly (alternating slots
+// for r.z, so no copies between iterations):
+//   phase 0: x += a p, r -= a Ap   (a = num / den)
+//   phase 1: p = z + b p           (b = num / den)
+__global__ void cg2_kernel(double* x, double* r, double* pdir, const double* Ap, const double* z, int64_t n,
+                           const double* num, const double* den, int phase) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double c = num[0] / den[0];
+    if (phase == 0) {
+        x[i] += c * pdir[i];
+        r[i] -= c * Ap[i];
+    } else {
+        pdir[i] = z[i] + c * pdir[i];
+    }
+}
+
+void launch_cg2(double* x, double* r, double* pdir, const double* Ap, const double* z, int64_t n, const double* num,
+                const double* den, int phase, hipStream_t s) {
+    hipLaunchKernelGGL(cg2_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, x, r, pdir, Ap, z, n, num, den,
+                       phase);
+}
+
 void launch_cg_update(double* x, double* r, double* pdir, const double* Ap, const double* z, int64_t n,
                       const double* scal, int phase, hipStream_t s) {
     hipLaunchKernelGGL(cg_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, x, r, pdir, Ap, z, n, scal,

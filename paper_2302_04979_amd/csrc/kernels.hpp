@@ -231,6 +231,12 @@ void launch_sum_final(const double* partial, int nblocks, int batch, double* out
 // y = a*x + b*y with device scalars a = sa[0]*ka, b = kb (sa may be null => 1)
 void launch_axpby(const double* x, double* y, int64_t n, double ka, const double* sa, double kb,
                   hipStream_t s);
+// partial[2 * nblocks] scratch; out0 = r.r, out1 = r.z (device scalars)
+void launch_dot2(const double* r, const double* z, int64_t n, double* partial, int nblocks, double* out0,
+                 double* out1, hipStream_t s);
+// phase 0: x += (num/den) p, r -= (num/den) Ap; phase 1: p = z + (num/den) p
+void launch_cg2(double* x, double* r, double* pdir, const double* Ap, const double* z, int64_t n, const double* num,
+                const double* den, int phase, hipStream_t s);
 void launch_cg_update(double* x, double* r, double* pdir, const double* Ap, const double* z,
                       int64_t n, const double* scal, int phase, hipStream_t s);
 
