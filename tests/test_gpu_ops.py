@@ -9,7 +9,8 @@ from _helpers import make_pair, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(2, 3, True), (2, 9, True), (3, 4, False), (3, 5, True), (3, 8, True), (4, 6, True)]
+CASES = [(2, 1, True), (3, 2, True), (2, 3, True), (2, 9, True), (3, 4, False), (3, 5, True), (3, 8, True),
+         (4, 6, True)]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=lambda c: f"p{c[0]}N{c[1]}{'def' if c[2] else 'id'}")

@@ -20,8 +20,8 @@ from _helpers import rel, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-14
-CASES = [(2, 3, True, False), (3, 5, True, False), (3, 8, True, False), (4, 6, True, False),
-         (3, 4, False, False), (3, 5, True, True)]
+CASES = [(2, 1, True, False), (4, 2, True, False), (2, 3, True, False), (3, 5, True, False),
+         (3, 8, True, False), (4, 6, True, False), (3, 4, False, False), (3, 5, True, True)]
 
 
 def _make(p, N, deformed, stored):
@@ -121,6 +121,19 @@ def test_leapfrog_parity_and_invariant(pair):
     # the oracle's invariant of its own run agrees
     Eo = S.energy1_modified(e_o, h_o, h_o - dt * S.mass1_solve("H", S.rhs_h(e_o))[0])
     assert abs(E1 / Eo - 1) < 1e-10
+
+
+def test_zero_steps_change_nothing():
+    import torch
+    import paper_2302_04979_amd as K
+    G = K.Space(3, 4, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+    e0, h0 = to_dev(W.random_vector(G.n_e, 1)), to_dev(W.random_vector(G.n_h, 2))
+    e, h = e0.clone(), h0.clone()
+    assert G.step_scheme1(e, h, 0.01, 0) == (0, 0)
+    G.step_split(e, h, 0.01, 0, 4)
+    G.step(e, h, 0.01, nsteps=0)
+    torch.cuda.synchronize()
+    assert torch.equal(e, e0) and torch.equal(h, h0)
 
 
 def test_zero_rhs_and_errors():
