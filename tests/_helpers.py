@@ -35,3 +35,14 @@ def to_host(t):
     import torch
     torch.cuda.synchronize()
     return t.detach().cpu().numpy().astype(float)
+
+
+def qp_param_points(p, N):
+    """Parametric Gauss points in the element-major order of the library
+    ([ez][ey][ex][iqz][iqy][iqx]), p+1 Gauss-Legendre points per element."""
+    g, _ = np.polynomial.legendre.leggauss(p + 1)
+    x = (np.arange(N)[:, None] + 0.5 * (g[None, :] + 1.0)) / N  # [e][iq]
+    X = np.broadcast_to(x[None, None, :, None, None, :], (N, N, N, p + 1, p + 1, p + 1))
+    Y = np.broadcast_to(x[None, :, None, None, :, None], (N, N, N, p + 1, p + 1, p + 1))
+    Z = np.broadcast_to(x[:, None, None, :, None, None], (N, N, N, p + 1, p + 1, p + 1))
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)

@@ -167,3 +167,33 @@ def dipoles(count: int, seed: int = 0, dt: float = 1.0, sigma_steps: float = 20.
 def probes(count: int, seed: int = 0, margin: float = 0.0) -> np.ndarray:
     """`count` probe points in parametric coordinates, U(margin, 1-margin)^3."""
     return rng(seed, "probes").uniform(margin, 1.0 - margin, size=(count, 3))
+
+
+# --------------------------------------------------------------------------
+# Quarter of a coaxial cable: 1 < x^2 + y^2 < 2, 0 < z < 1 (Section 5), as a
+# degree-2 NURBS map of the unit cube (geometry input of the curved workload)
+# --------------------------------------------------------------------------
+def quarter_annulus_jacobian(xh: np.ndarray):
+    """Map x^ = (u, v, w) -> (rho(u) C(v), w) with rho(u) = 1 + (sqrt(2) - 1) u
+    (radius from 1 to sqrt(2)) and C the quarter unit circle from (1, 0) to
+    (0, 1) as a rational quadratic Bezier curve (control points (1,0), (1,1),
+    (0,1), weights 1, 1/sqrt(2), 1).  Returns the mapped points (..., 3) and
+    the Jacobians DF[i, j] = dF_i / dx^_j (..., 3, 3)."""
+    xh = np.asarray(xh, dtype=float)
+    u, v, w = xh[..., 0], xh[..., 1], xh[..., 2]
+    wt = 1.0 / math.sqrt(2.0)
+    b0, b1, b2 = (1 - v) ** 2, 2 * v * (1 - v) * wt, v ** 2
+    db0, db1, db2 = -2 * (1 - v), 2 * wt * (1 - 2 * v), 2 * v
+    den = b0 + b1 + b2
+    dden = db0 + db1 + db2
+    cx, cy = (b0 + b1) / den, (b1 + b2) / den
+    dcx = ((db0 + db1) * den - (b0 + b1) * dden) / den ** 2
+    dcy = ((db1 + db2) * den - (b1 + b2) * dden) / den ** 2
+    rho = 1.0 + (math.sqrt(2.0) - 1.0) * u
+    drho = math.sqrt(2.0) - 1.0
+    F = np.stack([rho * cx, rho * cy, w], axis=-1)
+    J = np.zeros(xh.shape[:-1] + (3, 3))
+    J[..., 0, 0], J[..., 0, 1] = drho * cx, rho * dcx
+    J[..., 1, 0], J[..., 1, 1] = drho * cy, rho * dcy
+    J[..., 2, 2] = 1.0
+    return F, J
