@@ -252,6 +252,46 @@ def scheme1_timing(K, W, torch, G, e0, dt2, ms_step2, steps=20, tol=1e-12):
             "time_share": share}
 
 
+def schemes_vs_degree(K, W, torch, N=32, degrees=(2, 3, 4), steps=10, tol=1e-12):
+    """Both schemes on the deformed cube (eps ~ U[1,4], mu = 1) at N^3 for
+    p = 2, 3, 4: the CFL limits of each (power iteration on the device), the
+    time per step of each (scheme 2: the plain step under the tuner's plan;
+    scheme 1: PCG to tol), and the ratios per step and per unit of simulated
+    time (Section 5.2: the CFL of the mass-solve scheme decays more slowly in
+    p, its steps cost far more)."""
+    out = {"workload": f"deformed cube (a=0.08), {N}^3, eps~U[1,4], mu=1, random e^0, h^0 = 0; "
+                       f"scheme 1 PCG to |r| <= {tol:g} |y|", "p": {}}
+    for p in degrees:
+        G = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+        G.set_materials(eps=W.eps_elements(N, 0))
+        cfl2 = G.cfl(max_iter=300, tol=1e-6)
+        cfl1 = G.cfl_scheme1(max_iter=300, tol=1e-6, cg_tol=1e-10)
+        e0 = torch.tensor(W.random_vector(G.n_e, 0, 51), dtype=torch.float64, device="cuda")
+        G.tune(1, 0.5 * cfl2, probe_steps=5)
+        e, h = e0.clone(), torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+        G.init_stagger(e, h, 0.5 * cfl2)
+        G.step(e, h, 0.5 * cfl2, nsteps=5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.step(e, h, 0.5 * cfl2, nsteps=10 * steps)
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t0) * 1e3 / (10 * steps)
+        e, h = e0.clone(), torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+        G.half_step_scheme1("H", e, h, 0.25 * cfl1, tol=tol)
+        G.step_scheme1(e, h, 0.5 * cfl1, 2, tol=tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = G.step_scheme1(e, h, 0.5 * cfl1, steps, tol=tol)
+        torch.cuda.synchronize()
+        ms1 = (time.perf_counter() - t0) * 1e3 / steps
+        out["p"][str(p)] = {"cfl_scheme2": cfl2, "cfl_scheme1": cfl1, "cfl_ratio": cfl1 / cfl2,
+                            "ms_per_step_scheme2": ms2, "ms_per_step_scheme1": ms1,
+                            "cg_iters_per_solve": {"e": its[0] / steps, "h": its[1] / steps},
+                            "per_step_ratio": ms1 / ms2, "per_simulated_time_ratio": (ms1 / cfl1) / (ms2 / cfl2)}
+        G.close()
+    return out
+
+
 def time_order_comparison(K, W, torch, G, e0, dt, steps=100):
     """Time-discretisation error of the leapfrog and of its order-4 and
     order-6 symmetric compositions on the headline space: from (e0, h = 0) to
@@ -573,6 +613,8 @@ def main():
     if not args.no_scheme1:
         log("first scheme")
         scheme1 = scheme1_timing(K, W, torch, G, e_only, dt, ms_per_step)
+        log("both schemes against the degree, 32^3")
+        scheme1["vs_degree"] = schemes_vs_degree(K, W, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
