@@ -1313,24 +1313,27 @@ __device__ inline void block_sum3(double v0, double v1, double v2, double* out) 
     }
 }
 
-// Fused energy terms: one workgroup per (component, z plane, block of EROWS
-// rows) forms w = K v on its rows (K1 e for the first term, K~1 h for the
-// other two) by the Kronecker structure: the z band combines 2W+1 planes,
-// then the x and y bands run in LDS; the dot products with d (first term), b
-// and D^1 e (second and third) follow in the same pass.  Blocks [0, nb0) do
-// the first term, [nb0, nb0 + nb1) the others; each writes its three partial
-// sums (zeros for terms it does not own) for the fixed-order final sum.
+// Fused energy terms: one workgroup per (component, pair of z planes, block
+// of EROWS rows) forms w = K v on its rows (K1 e for the first term, K~1 h for
+// the other two) by the Kronecker structure: the z band combines 2W+1 planes
+// (the 2W+2 planes staged once serve both output planes), then the x and y
+// bands run in LDS; the dot products with d (first term), b and D^1 e (second
+// and third) follow in the same pass.  Blocks [0, nb0) do the first term,
+// [nb0, nb0 + nb1) the others; each writes its three partial sums (zeros for
+// terms it does not own) for the fixed-order final sum.
 constexpr int EROWS = 16;
+constexpr int EPLANES = 2;  // output planes per workgroup
 
 template <int P>
 __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs A) {
     constexpr int W = P - 1, B = 2 * W + 1;
     constexpr int TR = EROWS + 2 * W;  // staged rows (with the y halo)
-    __shared__ double tile[TR * KMX_LINE_MAX];
+    constexpr int ZL = B + EPLANES - 1;  // staged planes
+    __shared__ double tile[EPLANES][TR * KMX_LINE_MAX];
     __shared__ double band[3][KMX_LINE_MAX * B];
     const int tid = threadIdx.x, bm = blockIdx.y;
-    // XCD-aware order: each XCD takes a contiguous range of (component, plane,
-    // row block), so the 2W+1 planes that neighbouring blocks share stay in its L2
+    // XCD-aware order: each XCD takes a contiguous range of (component, plane
+    // pair, row block), so the planes that neighbouring blocks share stay in its L2
     const int blk = xcd_tile(blockIdx.x, A.nb[0] + A.nb[1]);
     const int mode = blk < A.nb[0] ? 0 : 1;
     int rem = mode == 0 ? blk : blk - A.nb[0];
@@ -1339,7 +1342,7 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
     const int* d = mode == 0 ? A.e_dims[c] : A.h_dims[c];
     const int nz = d[0], ny = d[1], nx = d[2];
     const int nyb = (ny + EROWS - 1) / EROWS;
-    const int z = rem / nyb, y0 = (rem % nyb) * EROWS;
+    const int z0 = (rem / nyb) * EPLANES, y0 = (rem % nyb) * EROWS;
     const double* E = A.E + int64_t(bm) * 2 * A.n_e;
     const double* H = A.H + int64_t(bm) * 2 * A.n_h;
     const double* v = (mode == 0 ? E + A.e_comp_off[c] : H + A.h_comp_off[c]);
@@ -1370,100 +1373,114 @@ __global__ void __launch_bounds__(256) energy_fused_kernel(const EnergyFusedArgs
         }
     }
     __syncthreads();
-    // z band: tile[r][x] = sum_k Kz(z, z+k) v[z+k][y0-W+r][x]; every load of a
-    // thread is issued before the first is used
+    // z band: tile[j][r][x] = sum_k Kz(z0+j, z0+j-W+k) v[z0+j-W+k][y0-W+r][x];
+    // every load of a thread is issued before the first is used
     constexpr int SL = (TR * KMX_LINE_MAX + 255) / 256;
     {
-        double vz[SL][B];
+        double vz[SL][ZL];
 #pragma unroll
         for (int q = 0; q < SL; ++q) {
             const int i = tid + q * 256, r = i / nx, x = i % nx, y = y0 - W + r;
 #pragma unroll
-            for (int k = 0; k < B; ++k) {
-                const int zz = z - W + k;
+            for (int k = 0; k < ZL; ++k) {
+                const int zz = z0 - W + k;
                 const bool ok = i < TR * nx && y >= 0 && y < ny && zz >= 0 && zz < nz;
                 const double t = v[ok ? (zz * ny + y) * nx + x : 0];
                 vz[q][k] = ok ? t : 0.0;
             }
         }
 #pragma unroll
-        for (int q = 0; q < SL; ++q) {
-            const int i = tid + q * 256;
-            if (i < TR * nx) {
-                double s = 0.0;
+        for (int j = 0; j < EPLANES; ++j) {
+            // a plane past the field has a zero band row (its outputs are not used)
+            const int zj = z0 + j < nz ? z0 + j : nz - 1;
+            const double bw = z0 + j < nz ? 1.0 : 0.0;
 #pragma unroll
-                for (int k = 0; k < B; ++k) s += band[2][z * B + k] * vz[q][k];
-                tile[(i / nx) * KMX_LINE_MAX + (i % nx)] = s;
+            for (int q = 0; q < SL; ++q) {
+                const int i = tid + q * 256;
+                if (i < TR * nx) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < B; ++k) s += band[2][zj * B + k] * vz[q][k + j];
+                    tile[j][(i / nx) * KMX_LINE_MAX + (i % nx)] = bw * s;
+                }
             }
         }
     }
     __syncthreads();
     // x band, row by row (outputs to registers first: the rows are updated in place)
-    double t[SL];
+    double t[EPLANES][SL];
 #pragma unroll
-    for (int q = 0; q < SL; ++q) {
-        const int i = tid + q * 256;
-        t[q] = 0.0;
-        if (i < TR * nx) {
-            const int r = i / nx, x = i % nx;
+    for (int j = 0; j < EPLANES; ++j)
 #pragma unroll
-            for (int k = 0; k < B; ++k) {
-                // the band is zero outside the matrix: a clamped index adds nothing
-                int xx = x - W + k;
-                xx = xx < 0 ? 0 : (xx > nx - 1 ? nx - 1 : xx);
-                t[q] += band[0][x * B + k] * tile[r * KMX_LINE_MAX + xx];
+        for (int q = 0; q < SL; ++q) {
+            const int i = tid + q * 256;
+            t[j][q] = 0.0;
+            if (i < TR * nx) {
+                const int r = i / nx, x = i % nx;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    // the band is zero outside the matrix: a clamped index adds nothing
+                    int xx = x - W + k;
+                    xx = xx < 0 ? 0 : (xx > nx - 1 ? nx - 1 : xx);
+                    t[j][q] += band[0][x * B + k] * tile[j][r * KMX_LINE_MAX + xx];
+                }
             }
         }
-    }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < SL; ++q) {
-        const int i = tid + q * 256;
-        if (i < TR * nx) tile[(i / nx) * KMX_LINE_MAX + (i % nx)] = t[q];
-    }
+    for (int j = 0; j < EPLANES; ++j)
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+            const int i = tid + q * 256;
+            if (i < TR * nx) tile[j][(i / nx) * KMX_LINE_MAX + (i % nx)] = t[j][q];
+        }
     __syncthreads();
     // y band on the owned rows, then the dot products (partner loads first)
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int rows = ny - y0 < EROWS ? ny - y0 : EROWS;
     constexpr int SO = (EROWS * KMX_LINE_MAX + 255) / 256;
-    double pb[SO], pc[SO];
+    double pb[EPLANES][SO], pc[EPLANES][SO];
 #pragma unroll
-    for (int q = 0; q < SO; ++q) {
-        const int i = tid + q * 256;
-        pb[q] = pc[q] = 0.0;
-        if (i < rows * nx) {
-            const int y = y0 + i / nx, x = i % nx;
-            const int64_t at = (int64_t(z) * ny + y) * nx + x;
-            if (mode == 0) {
-                pb[q] = E[A.n_e + A.e_comp_off[c] + at];
-            } else {
-                const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-                pb[q] = H[A.n_h + A.h_comp_off[c] + at];
-                pc[q] = diff1_primal(E + A.e_comp_off[a2], A.e_dims[a2], a1, z, y, x) -
-                        diff1_primal(E + A.e_comp_off[a1], A.e_dims[a1], a2, z, y, x);
+    for (int j = 0; j < EPLANES; ++j)
+#pragma unroll
+        for (int q = 0; q < SO; ++q) {
+            const int i = tid + q * 256, z = z0 + j;
+            pb[j][q] = pc[j][q] = 0.0;
+            if (i < rows * nx && z < nz) {
+                const int y = y0 + i / nx, x = i % nx;
+                const int64_t at = (int64_t(z) * ny + y) * nx + x;
+                if (mode == 0) {
+                    pb[j][q] = E[A.n_e + A.e_comp_off[c] + at];
+                } else {
+                    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+                    pb[j][q] = H[A.n_h + A.h_comp_off[c] + at];
+                    pc[j][q] = diff1_primal(E + A.e_comp_off[a2], A.e_dims[a2], a1, z, y, x) -
+                               diff1_primal(E + A.e_comp_off[a1], A.e_dims[a1], a2, z, y, x);
+                }
             }
         }
-    }
 #pragma unroll
-    for (int q = 0; q < SO; ++q) {
-        const int i = tid + q * 256;
-        if (i < rows * nx) {
-            const int ry = i / nx, x = i % nx, y = y0 + ry;
-            double w = 0.0;
+    for (int j = 0; j < EPLANES; ++j)
 #pragma unroll
-            for (int k = 0; k < B; ++k) {
-                // rows of the tile outside the field hold finite values and
-                // meet zero band entries
-                w += band[1][y * B + k] * tile[(ry + k) * KMX_LINE_MAX + x];
-            }
-            if (mode == 0) {
-                s0 += w * pb[q];
-            } else {
-                s1 += w * pb[q];
-                s2 += w * pc[q];
+        for (int q = 0; q < SO; ++q) {
+            const int i = tid + q * 256;
+            if (i < rows * nx && z0 + j < nz) {
+                const int ry = i / nx, x = i % nx, y = y0 + ry;
+                double w = 0.0;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    // rows of the tile outside the field hold finite values and
+                    // meet zero band entries
+                    w += band[1][y * B + k] * tile[j][(ry + k) * KMX_LINE_MAX + x];
+                }
+                if (mode == 0) {
+                    s0 += w * pb[j][q];
+                } else {
+                    s1 += w * pb[j][q];
+                    s2 += w * pc[j][q];
+                }
             }
         }
-    }
     __shared__ double r[3];
     block_sum3<256>(s0, s1, s2, r);
     if (tid == 0) {
@@ -1488,7 +1505,7 @@ void launch_energy_fused(int p, const EnergyFusedArgs& a, int batch, hipStream_t
 int energy_fused_blocks(const int dims[3][3], int cb[3]) {
     int tot = 0;
     for (int c = 0; c < 3; ++c) {
-        cb[c] = dims[c][0] * ((dims[c][1] + EROWS - 1) / EROWS);
+        cb[c] = ((dims[c][0] + EPLANES - 1) / EPLANES) * ((dims[c][1] + EROWS - 1) / EROWS);
         tot += cb[c];
     }
     return tot;
