@@ -148,6 +148,22 @@ class Scheme1(Scheme):
         """b with M~^1_mu h = K~1^T b (eq. (3.8))."""
         return self.kron_solve("K1t", self.mass1_apply("H", h), transpose=True)
 
+    def project_E1(self, efield, tol: float = 1e-15) -> np.ndarray:
+        """e^0 = M^{-1} l, l_i = (E0, eta_i)_{L^2_eps} over the primal 1-form
+        basis eta_i = DF^{-T} eta^_i: in parametric coordinates
+        l_i = int eta^_i . (eps det DF DF^{-1} E0(F(x^))) dx^ (the L^2_eps
+        projection of E0 onto X^1_{h,0}, the initial value of the Galerkin
+        scheme of Section 3.3.2)."""
+        xh = self.quad_points()
+        E = efield(self.geo.F(xh))
+        DF = self.geo.DF(xh)
+        det = np.linalg.det(DF)
+        Eh = det[..., None] * np.linalg.solve(DF, E[..., None])[..., 0]
+        W = self.wq[:, None, None] * self.wq[None, :, None] * self.wq[None, None, :]
+        g = 1.0 if self.eps is None else self._elem_to_q(self.eps)
+        l = self.integrate("E", [Eh[..., c] * W * g for c in range(3)])
+        return self.mass1_solve("E", l, tol=tol)[0]
+
     # ------------------------------------------------------------------
     # energies
     # ------------------------------------------------------------------

@@ -183,3 +183,48 @@ def test_cfl_scheme1_exceeds_scheme2():
         l2 = np.abs(np.linalg.eigvals(np.stack([S2.apply_A(c) for c in np.eye(S2.n_e)], 1))).max()
         ratios.append(np.sqrt(l2 / l1))
     assert ratios[0] > 1.0 and ratios[0] < ratios[1] < ratios[2]
+
+
+def test_projection_is_exact_on_discrete_fields():
+    """project_E1 reproduces a field that lies in X^1_{h,0} (deformed map)."""
+    S = _deformed(2, 3)
+    e = W.random_vector(S.n_e, 13)
+
+    def field(X):
+        # the physical field of e at the mapped Gauss points, in the order
+        # project_E1 evaluates them
+        return S.field_at_quad("E", e)
+
+    assert np.linalg.norm(S.project_E1(field) - e) < 1e-11 * np.linalg.norm(e)
+
+
+def _cavity_errors1(p, N, T, dt):
+    import math
+    S = Scheme1(p, N)
+    modes = W.mode_110()
+    omega = W.mode_omega(modes)[0]
+    e = S.project_E1(lambda xyz: W.eval_modes(modes, xyz))
+    h, _ = S.init_stagger1(e, np.zeros(S.n_h), dt, tol=1e-14)
+    xq = S.quad_points()
+    E0, C0 = W.eval_modes(modes, xq), W.curl_modes(modes, xq)
+    errE = nrmE = errH = nrmH = 0.0
+    for n in range(1, int(round(T / dt)) + 1):
+        e, h, _, _ = S.step1(e, h, dt, tol=1e-14)
+        Eex = E0 * math.cos(omega * n * dt)
+        Hex = -C0 * math.sin(omega * (n - 0.5) * dt) / omega
+        errE += S.l2_norm_sq_quad(S.field_at_quad("E", e) - Eex)
+        nrmE += S.l2_norm_sq_quad(Eex)
+        errH += S.l2_norm_sq_quad(S.field_at_quad("H", h) - Hex)
+        nrmH += S.l2_norm_sq_quad(Hex)
+    return math.sqrt(errE / nrmE), math.sqrt(errH / nrmH)
+
+
+def test_cavity_convergence_orders_scheme1():
+    """Section 5.1, Fig. 2: the first scheme converges at the same rates as the
+    second, h^p for E and h^(p-1) for H in L^2(0,T;L^2) (p = 3, cube cavity,
+    first mode)."""
+    import math
+    p, T, dt = 3, 0.5, 2.5e-3
+    errs = [_cavity_errors1(p, N, T, dt) for N in (2, 4)]
+    assert math.log2(errs[0][0] / errs[1][0]) > p - 0.3, errs
+    assert math.log2(errs[0][1] / errs[1][1]) > p - 1 - 0.3, errs
