@@ -335,6 +335,13 @@ kmx_status kmx_solve_mass1(kmx_space* sp, int which, const double* y, double* x,
 kmx_status kmx_half_step_scheme1(kmx_space* sp, int which, const double* x, double* out, double alpha, double tol,
                                  int max_iter, int* iters, void* stream);
 
+/* Initial value of the first scheme: e^0 (device, n_e) = the L^2_eps projection
+ * of a physical field E0 onto X^1_{h,0}, M^1_eps e^0 = l with
+ * l_i = int eps E0 . eta_i dx (eta_i = DF^{-T} eta^_i the primal 1-form basis),
+ * solved by the same PCG to tol.  E_qp_host as for kmx_project_E (3 doubles per
+ * quadrature point, in the order of kmx_quad_points).  Synchronises. */
+kmx_status kmx_project_E1(kmx_space* sp, const double* E_qp_host, double* e_dev, double tol, void* stream);
+
 /* nsteps leapfrog steps of the first scheme on (e^n, h^{n-1/2}) (device, n_e
  * and n_h values).  iters (host, 2 ints, may be NULL) receives the summed CG
  * iterations of the e solves and of the h solves. */

@@ -41,7 +41,7 @@ EXPORTS = (
     "kmx_graph_create", "kmx_graph_launch",
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
     "kmx_op_mass1", "kmx_solve_mass1", "kmx_half_step_scheme1", "kmx_step_scheme1", "kmx_cfl_scheme1",
-    "kmx_init_split", "kmx_step_split",
+    "kmx_init_split", "kmx_step_split", "kmx_project_E1",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
                  "mode_fp32", "dense_fp64", "mass_1form", "cg_vector")
@@ -117,6 +117,7 @@ def load_library():
         "kmx_step_scheme1": ([vp, vp, vp, d, i, d, i, vp, vp], i),
         "kmx_cfl_scheme1": ([vp, i, d, d, ctypes.POINTER(d)], i),
         "kmx_init_split": ([vp, vp, vp, d, i, i, i, vp], i),
+        "kmx_project_E1": ([vp, vp, vp, d, vp], i),
         "kmx_step_split": ([vp, vp, vp, d, i, i, i, i, vp], i),
     }
     for name, (args, res) in sig.items():
@@ -387,6 +388,12 @@ class Space:
                                                float(dt), int(nsteps), float(tol), int(max_iter),
                                                ctypes.cast(it, ctypes.c_void_p), _stream()))
         return int(it[0]), int(it[1])
+
+    def project_E1(self, E_qp, e, tol=1e-13):
+        """e^0 = L^2_eps projection of E0 (physical field at the quadrature
+        points, (n_qp, 3) host array) onto X^1_{h,0}."""
+        keep, ptr = _hptr(E_qp, 3 * self.n_qp)
+        _check(load_library().kmx_project_E1(self._h, ptr, _dptr(e, self.n_e, "e"), float(tol), _stream()))
 
     def cfl_scheme1(self, max_iter=2000, tol=1e-10, cg_tol=1e-12) -> float:
         out = ctypes.c_double()

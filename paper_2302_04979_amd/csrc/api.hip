@@ -1832,6 +1832,23 @@ kmx_status kmx_half_step_scheme1(kmx_space* sp, int which, const double* x, doub
     return KMX_OK;
 }
 
+kmx_status kmx_project_E1(kmx_space* sp, const double* E_qp_host, double* e_dev, double tol, void* stream) {
+    if (!E_qp_host || !e_dev) return fail(KMX_E_ARG, "NULL argument");
+    kmx_status st = s1_check(sp, tol, 2000);
+    if (st != KMX_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<double> l;
+    load_E(sp, E_qp_host, l, 1);
+    double* y = s1_vec(sp, S1_Y);
+    HIP_TRY(hipMemcpyAsync(y, l.data(), l.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(e_dev, 0, l.size() * sizeof(double), s));
+    int it = 0;
+    st = s1_pcg(sp, SP_E, y, e_dev, tol, 2000, 0, &it, s);
+    if (st != KMX_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    return KMX_OK;
+}
+
 kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, double tol, int max_iter,
                             int* iters, void* stream) {
     if (!e || !h) return fail(KMX_E_ARG, "NULL field");

@@ -344,10 +344,13 @@ int64_t comp_offset(const kmx_space* sp, int space, int c) {
     return o;
 }
 
-// l_i = sum_q w_q eta^_i(q) . (DF^T E0)(q) over the dual 2-form basis.
-void load_E(const kmx_space* sp, const double* E_qp, std::vector<double>& l) {
+// form 2: l_i = sum_q w_q eta^_i(q) . (DF^T E0)(q) over the dual 2-form basis;
+// form 1: l_i = sum_q w_q eps_e eta^_i(q) . (det DF DF^{-1} E0)(q) over the
+// primal 1-form basis (the L^2_eps load vector of the first scheme).
+void load_E(const kmx_space* sp, const double* E_qp, std::vector<double>& l, int form) {
     const Tables& tb = sp->tb;
     const int nq = tb.nq, N = tb.N, p = tb.p;
+    const int space = form == 1 ? SP_E : SP_D;
     l.assign(sp->n_e, 0.0);
     std::vector<double> F(size_t(nq) * nq * nq * 3);
     for (int ez = 0; ez < N; ++ez)
@@ -361,18 +364,37 @@ void load_E(const kmx_space* sp, const double* E_qp, std::vector<double>& l) {
                             const double w = tb.wq[ex * nq + ix] * tb.wq[ey * nq + iy] * tb.wq[ez * nq + iz];
                             double J[9];
                             map_jacobian(sp, q, xh, J);
-                            for (int c = 0; c < 3; ++c) {
-                                double s = 0.0;
-                                for (int r = 0; r < 3; ++r) s += J[3 * r + c] * E_qp[3 * q + r];
-                                F[((iz * nq + iy) * nq + ix) * 3 + c] = w * s;
+                            if (form == 1) {
+                                // det DF DF^{-1} = adj(DF): row c of the adjugate is the
+                                // cross product of the columns c+1 and c+2 of DF
+                                const double eps = sp->eps_host.empty()
+                                                       ? 1.0
+                                                       : sp->eps_host[(size_t(ez) * N + ey) * N + ex];
+                                for (int c = 0; c < 3; ++c) {
+                                    const int a = (c + 1) % 3, b = (c + 2) % 3;
+                                    double s = 0.0;
+                                    for (int r = 0; r < 3; ++r) {
+                                        const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
+                                        const double adj = J[3 * r1 + a] * J[3 * r2 + b] - J[3 * r2 + a] * J[3 * r1 + b];
+                                        s += adj * E_qp[3 * q + r];
+                                    }
+                                    F[((iz * nq + iy) * nq + ix) * 3 + c] = w * eps * s;
+                                }
+                            } else {
+                                for (int c = 0; c < 3; ++c) {
+                                    double s = 0.0;
+                                    for (int r = 0; r < 3; ++r) s += J[3 * r + c] * E_qp[3 * q + r];
+                                    F[((iz * nq + iy) * nq + ix) * 3 + c] = w * s;
+                                }
                             }
                         }
                 for (int c = 0; c < 3; ++c) {
-                    const int tgx = space_tag(SP_D, c, 0), tgy = space_tag(SP_D, c, 1), tgz = space_tag(SP_D, c, 2);
+                    const int tgx = space_tag(space, c, 0), tgy = space_tag(space, c, 1), tgz = space_tag(space, c, 2);
                     const int Kx = tag_support(p, tgx), Ky = tag_support(p, tgy), Kz = tag_support(p, tgz);
+                    const int ox = tag_offset(tgx), oy = tag_offset(tgy), oz = tag_offset(tgz);
                     int d[3];
-                    comp_dims(sp, SP_D, c, d);
-                    const int64_t off = comp_offset(sp, SP_D, c);
+                    comp_dims(sp, space, c, d);
+                    const int64_t off = comp_offset(sp, space, c);
                     for (int iz = 0; iz < nq; ++iz)
                         for (int iy = 0; iy < nq; ++iy)
                             for (int ix = 0; ix < nq; ++ix) {
@@ -383,7 +405,10 @@ void load_E(const kmx_space* sp, const double* E_qp, std::vector<double>& l) {
                                 for (int jz = 0; jz < Kz; ++jz)
                                     for (int jy = 0; jy < Ky; ++jy)
                                         for (int jx = 0; jx < Kx; ++jx) {
-                                            const int gz = ez + jz, gy = ey + jy, gx = ex + jx;
+                                            // boundary functions of the primal space are not unknowns
+                                            const int gz = ez + jz + oz, gy = ey + jy + oy, gx = ex + jx + ox;
+                                            if (gz < 0 || gy < 0 || gx < 0 || gz >= d[0] || gy >= d[1] || gx >= d[2])
+                                                continue;
                                             l[off + (int64_t(gz) * d[1] + gy) * d[2] + gx] += bz[jz] * by[jy] * bx[jx] * f;
                                         }
                             }

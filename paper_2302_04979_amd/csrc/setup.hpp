@@ -19,7 +19,7 @@ kmx_status build_metric(const kmx_space* sp, std::vector<double>* out, int form 
 void quad_points(const kmx_space* sp, double* xyz);
 void comp_dims(const kmx_space* sp, int space, int c, int dims[3]);
 int64_t comp_offset(const kmx_space* sp, int space, int c);
-void load_E(const kmx_space* sp, const double* E_qp, std::vector<double>& l);
+void load_E(const kmx_space* sp, const double* E_qp, std::vector<double>& l, int form = 2);
 void kron_solve_K1_host(const kmx_space* sp, std::vector<double>& y);
 void dipole_entries(const kmx_space* sp, const double pos[3], const double q[3],
                     std::vector<DipoleEntry>& out);

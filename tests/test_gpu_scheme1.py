@@ -199,3 +199,17 @@ def test_full_size_invariant_and_residual():
     E0 = invariant()
     G.step_scheme1(e, h, dt, 10, tol=1e-13)
     assert abs(invariant() / E0 - 1) < 1e-10
+
+
+@pytest.mark.parametrize("p,N,deformed", [(2, 3, True), (3, 5, True), (3, 4, False)])
+def test_project_E1_matches_oracle(p, N, deformed):
+    """The L^2_eps projection of ten cavity modes onto X^1_{h,0} (host load
+    vector, PCG on the device) against the oracle's projection."""
+    import torch
+    S, G = _make(p, N, deformed, False)
+    modes = W.cavity_modes(0)
+    Eq = W.eval_modes(modes, G.quad_points())
+    e = torch.zeros(G.n_e, dtype=torch.float64, device="cuda")
+    G.project_E1(Eq, e, tol=1e-14)
+    ref = S.project_E1(lambda xyz: W.eval_modes(modes, xyz.reshape(-1, 3)).reshape(xyz.shape))
+    assert rel(to_host(e), ref) < 1e-10
