@@ -335,12 +335,7 @@ def convergence_both_schemes(K, W, torch, p=3, Ns=(4, 8, 16), T=0.5, dt=1e-3, n_
     return out
 
 
-def coax_timing(K, W, torch, p=3, N=32, steps=100):
-    """The curved workload: the quarter coaxial cable (Section 5) as a
-    degree-2 NURBS map given by its Jacobians at the Gauss points (the metric
-    factor streamed from HBM), eps ~ U[1,4], PEC walls, random e^0 with a
-    consistent d^0, dt = 0.5 CFL, tracking and energy; ms per step under the
-    tuner's plan and the streamed mass kernel's HBM rate."""
+def _coax_space(K, W, p, N):
     import numpy as np
     g, _ = np.polynomial.legendre.leggauss(p + 1)
     x = (np.arange(N)[:, None] + 0.5 * (g[None, :] + 1.0)) / N
@@ -349,8 +344,51 @@ def coax_timing(K, W, torch, p=3, N=32, steps=100):
     Y = np.broadcast_to(x[None, :, None, None, :, None], sh)
     Z = np.broadcast_to(x[:, None, None, :, None, None], sh)
     _, DF = W.quarter_annulus_jacobian(np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
-    G = K.Space(p, N, map_kind=2, dF_qp=DF.reshape(-1))
-    del DF, X, Y, Z
+    return K.Space(p, N, map_kind=2, dF_qp=DF.reshape(-1))
+
+
+def coax_schemes(K, W, torch, p=4, N=16, steps=20, tol=1e-12):
+    """Both schemes on the quarter coax, p = 4 and 16^3 elements (the paper's
+    finest coax mesh, where it quotes its per-step and total-time ratios,
+    Section 6): CFL limits, ms per step (scheme 2: plain step under the tuner's
+    plan; scheme 1: PCG to tol) and the ratios, eps = mu = 1."""
+    G = _coax_space(K, W, p, N)
+    cfl2 = G.cfl(max_iter=300, tol=1e-6)
+    cfl1 = G.cfl_scheme1(max_iter=300, tol=1e-6, cg_tol=1e-10)
+    G.tune(1, 0.5 * cfl2, probe_steps=5)
+    e0 = torch.tensor(W.random_vector(G.n_e, 0, 81), dtype=torch.float64, device="cuda")
+    e, h = e0.clone(), torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+    G.init_stagger(e, h, 0.5 * cfl2)
+    G.step(e, h, 0.5 * cfl2, nsteps=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G.step(e, h, 0.5 * cfl2, nsteps=20 * steps)
+    torch.cuda.synchronize()
+    ms2 = (time.perf_counter() - t0) * 1e3 / (20 * steps)
+    e, h = e0.clone(), torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+    G.half_step_scheme1("H", e, h, 0.25 * cfl1, tol=tol)
+    G.step_scheme1(e, h, 0.5 * cfl1, 2, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = G.step_scheme1(e, h, 0.5 * cfl1, steps, tol=tol)
+    torch.cuda.synchronize()
+    ms1 = (time.perf_counter() - t0) * 1e3 / steps
+    G.close()
+    return {"workload": f"quarter coax (NURBS map), p={p}, {N}^3, eps=mu=1, random e^0; scheme 1 PCG to {tol:g}",
+            "cfl_scheme2": cfl2, "cfl_scheme1": cfl1, "cfl_ratio": cfl1 / cfl2,
+            "ms_per_step_scheme2": ms2, "ms_per_step_scheme1": ms1,
+            "cg_iters_per_solve": {"e": its[0] / steps, "h": its[1] / steps},
+            "per_step_ratio": ms1 / ms2, "per_simulated_time_ratio": (ms1 / cfl1) / (ms2 / cfl2)}
+
+
+def coax_timing(K, W, torch, p=3, N=32, steps=100):
+    """The curved workload: the quarter coaxial cable (Section 5) as a
+    degree-2 NURBS map given by its Jacobians at the Gauss points (the metric
+    factor streamed from HBM), eps ~ U[1,4], PEC walls, random e^0 with a
+    consistent d^0, dt = 0.5 CFL, tracking and energy; ms per step under the
+    tuner's plan and the streamed mass kernel's HBM rate."""
+    import numpy as np
+    G = _coax_space(K, W, p, N)
     G.set_materials(eps=W.eps_elements(N, 0))
     dev = torch.device("cuda")
     E = torch.zeros(2 * G.n_e, dtype=torch.float64, device=dev)
@@ -719,6 +757,8 @@ def main():
         scheme1["vs_degree"] = schemes_vs_degree(K, W, torch)
         log("cavity convergence of both schemes")
         scheme1["convergence"] = convergence_both_schemes(K, W, torch)
+        log("both schemes on the quarter coax, p=4, 16^3")
+        scheme1["coax_p4_n16"] = coax_schemes(K, W, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
