@@ -306,9 +306,12 @@ kmx_status kmx_step_split(kmx_space* sp, double* E, double* H, double dt, int ns
  * (source free).  M^1_eps (on X^1_{h,0}, n_e unknowns) and M~^1_mu (on X~^1,
  * n_h unknowns) have entries int eta^_i . G1 eta^_j gamma over the parametric
  * cube, G1 = det DF (DF^T DF)^{-1} the covariant pullback factor, gamma = eps or
- * mu per element.  Their systems are solved by conjugate gradients
- * preconditioned with the identity-map, unit-material mass (Kronecker products
- * of 1D Gram matrices, inverted exactly), stopped at |y - M x| <= tol |y|.
+ * mu per element.  Their systems are solved by conjugate gradients stopped at
+ * |y - M x| <= tol |y|, preconditioned with a Kronecker-product approximation
+ * of the mass: per component, 1D Gram matrices weighted by the best separable
+ * (log-additive) fit of gamma (G1)_cc, inverted exactly.  It is the mass
+ * matrix itself when the map is the identity or another orthogonal product
+ * map (such as the quarter annulus) and the material is uniform.
  * These calls need an FP64 space (KMX_E_STATE for KMX_MIXED) and allocate, at
  * their first use, eps and mu on the tiles, eight field-sized work vectors
  * and (streamed-metric spaces) the 1-form metric factor; they synchronise the

@@ -40,9 +40,9 @@ kmx_status fail(kmx_status st, const std::string& msg) {
 // factor-set ids beyond the four pairing factors: 1D Gram matrices used by the
 // conjugate-gradient preconditioner of the dual 2-form mass matrix
 constexpr int F_GRAM_DV = 4, F_GRAM_DD = 5, NFAC = 6;
-// slots of the dense operand-order factors beyond the four inverses: inverse
-// Gram matrices by tag, then the pairing factors G^, M^, G^T, M^T
-constexpr int FR_GRAM_INV = 4, FR_PAIR = 8;
+// slots of the dense operand-order factors beyond the four inverses: the
+// pairing factors G^, M^, G^T, M^T themselves
+constexpr int FR_PAIR = 4;
 
 void space_dims(const kmx_space* sp, int space, int dims[3][3], int64_t off[3]) {
     for (int c = 0; c < 3; ++c) {
@@ -466,10 +466,6 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
                 add_frag(k, B, n);
                 add_frag(FR_PAIR + k, Bf, n);
             }
-            for (int t = 0; t < 4; ++t) {
-                const int n = (t == PV || t == DD) ? sp->n0 : sp->n1;
-                add_frag(FR_GRAM_INV + t, dense_inverse(gram(sp->tb, t), n), n);
-            }
             if ((st = upload(&sp->d_frag64, frag)) != KMX_OK) { kmx_destroy_space(sp); return st; }
             int db[3][3], dd[3][3];
             int64_t o[3];
@@ -597,7 +593,7 @@ void kmx_destroy_space(kmx_space* sp) {
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_frag64,
-                    sp->d_eps, sp->d_mu, sp->d_metric1, sp->d_s1};
+                    sp->d_eps, sp->d_mu, sp->d_metric1, sp->d_s1, sp->d_frag_pre};
     for (void* b : more)
         if (b) (void)hipFree(b);
     delete sp;
@@ -1576,11 +1572,11 @@ kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, 
 // The first scheme (Section 3.3): Hodge stars with the 1-form mass matrices,
 //   M^1_eps d_t e = K1^T D~^1 h,   M~^1_mu d_t h = - K~1^T D^1 e,
 // each mass system solved by preconditioned conjugate gradients.  The
-// preconditioner is the mass matrix of the identity map with unit material,
-// whose blocks are Kronecker products of 1D Gram matrices: its inverse is
-// applied with the dense inverse Gram factors on the matrix cores, as are the
-// transposed pairing matrices (the same dense plane and z passes as the
-// tiled-dense plan's solves).
+// preconditioner is a Kronecker-product approximation of the mass matrix (1D
+// Gram matrices weighted by a separable fit of the metric and the material,
+// s1_build_precond): its inverse is applied with dense inverse factors on the
+// matrix cores, as are the transposed pairing matrices (the same dense plane
+// and z passes as the tiled-dense plan's solves).
 // ===========================================================================
 namespace {
 
@@ -1602,6 +1598,94 @@ kmx_status s1_upload_padded(kmx_space* sp, double** dst, const std::vector<doubl
     return KMX_OK;
 }
 
+// 1D Gram matrix of one tag with a weight per global Gauss point of the axis
+std::vector<double> gram_weighted(const Tables& tb, int tag, const std::vector<double>& f) {
+    const int n = (tag == PV || tag == DD) ? tb.n0 : tb.n1;
+    const int K = tag_support(tb.p, tag);
+    std::vector<double> G(size_t(n) * n, 0.0);
+    for (int e = 0; e < tb.N; ++e)
+        for (int q = 0; q < tb.nq; ++q) {
+            const double* v = &tb.tab[tag][(e * tb.nq + q) * K];
+            const double w = tb.wq[e * tb.nq + q] * f[e * tb.nq + q];
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) {
+                    const int gi = e + i + tag_offset(tag), gj = e + j + tag_offset(tag);
+                    if (gi < 0 || gj < 0 || gi >= n || gj >= n) continue;
+                    G[size_t(gi) * n + gj] += w * v[i] * v[j];
+                }
+        }
+    return G;
+}
+
+// The preconditioner of the 1-form mass solves: for each space (E with eps, H
+// with mu) and component c, the diagonal entry gamma_e (G1)_cc of the weighted
+// metric is fitted by a separable product fx(x) fy(y) fz(z) (the best additive
+// fit of its logarithm: the mean over the other two axes, less two thirds of
+// the overall mean); block c of the preconditioner is then the Kronecker
+// product of the 1D Gram matrices weighted by fx, fy, fz, inverted exactly.
+// For the identity map and uniform materials it is the mass matrix itself.
+kmx_status s1_build_precond(kmx_space* sp) {
+    const Tables& tb = sp->tb;
+    const int N = tb.N, nq = tb.nq, M = N * nq;
+    std::vector<double> lm[2][3][3];
+    double tot[2][3] = {};
+    for (int s = 0; s < 2; ++s)
+        for (int c = 0; c < 3; ++c)
+            for (int a = 0; a < 3; ++a) lm[s][c][a].assign(M, 0.0);
+    for (int ez = 0; ez < N; ++ez)
+        for (int ey = 0; ey < N; ++ey)
+            for (int ex = 0; ex < N; ++ex) {
+                const size_t el = (size_t(ez) * N + ey) * N + ex;
+                const double gam[2] = {sp->eps_host.empty() ? 1.0 : sp->eps_host[el],
+                                       sp->mu_host.empty() ? 1.0 : sp->mu_host[el]};
+                for (int iz = 0; iz < nq; ++iz)
+                    for (int iy = 0; iy < nq; ++iy)
+                        for (int ix = 0; ix < nq; ++ix) {
+                            const int64_t q = ((((int64_t(ez) * N + ey) * N + ex) * nq + iz) * nq + iy) * nq + ix;
+                            const double xh[3] = {tb.xq[ex * nq + ix], tb.xq[ey * nq + iy], tb.xq[ez * nq + iz]};
+                            double J[9], S[3][3];
+                            map_jacobian(sp, q, xh, J);
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j)
+                                    S[i][j] = J[i] * J[j] + J[3 + i] * J[3 + j] + J[6 + i] * J[6 + j];
+                            const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                                               J[2] * (J[3] * J[7] - J[4] * J[6]);
+                            const int g3[3] = {ex * nq + ix, ey * nq + iy, ez * nq + iz};
+                            for (int c = 0; c < 3; ++c) {
+                                // (det DF (DF^T DF)^{-1})_cc = cofactor_cc(S) / det DF
+                                const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+                                const double g1 = (S[c1][c1] * S[c2][c2] - S[c1][c2] * S[c2][c1]) / det;
+                                for (int s = 0; s < 2; ++s) {
+                                    const double lg = std::log(gam[s] * g1);
+                                    tot[s][c] += lg;
+                                    for (int a = 0; a < 3; ++a) lm[s][c][a][g3[a]] += lg;
+                                }
+                            }
+                        }
+            }
+    std::vector<double> frag;
+    const double m2 = double(M) * M, m3 = m2 * M;
+    for (int s = 0; s < 2; ++s) {
+        const int space = s == 0 ? SP_E : SP_H;
+        for (int c = 0; c < 3; ++c)
+            for (int a = 0; a < 3; ++a) {
+                std::vector<double> f(M);
+                for (int i = 0; i < M; ++i) f[i] = std::exp(lm[s][c][a][i] / m2 - (2.0 / 3.0) * tot[s][c] / m3);
+                const int tag = space_tag(space, c, a);
+                const int n = (tag == PV || tag == DD) ? sp->n0 : sp->n1;
+                const std::vector<double> inv = dense_inverse(gram_weighted(tb, tag, f), n);
+                sp->frag_pre_off[s][c][a] = int64_t(frag.size());
+                frag.resize(frag.size() + size_t(dense_frag_doubles(n)));
+                dense_fragments(inv.data(), n, frag.data() + sp->frag_pre_off[s][c][a]);
+            }
+    }
+    if (sp->d_frag_pre) {
+        HIP_TRY(hipFree(sp->d_frag_pre));
+        sp->d_frag_pre = nullptr;
+    }
+    return upload(&sp->d_frag_pre, frag);
+}
+
 // Set-up at the first use (and after kmx_set_materials): eps and mu padded to
 // the tiles, the 1-form metric factor when the metric is streamed, and the
 // work vectors.  Synchronous; not for use under graph capture.
@@ -1611,6 +1695,7 @@ kmx_status s1_prepare(kmx_space* sp) {
     if (!sp->s1_ready) {
         if ((st = s1_upload_padded(sp, &sp->d_eps, sp->eps_host)) != KMX_OK) return st;
         if ((st = s1_upload_padded(sp, &sp->d_mu, sp->mu_host)) != KMX_OK) return st;
+        if ((st = s1_build_precond(sp)) != KMX_OK) return st;
         sp->s1_ready = 1;
     }
     if (sp->metric_mode == 0 && !sp->d_metric1) {
@@ -1628,16 +1713,16 @@ kmx_status s1_prepare(kmx_space* sp) {
 }
 
 // out = (accumulate ? out : 0) + alpha * (F_z (x) F_y (x) F_x) in, component by
-// component, with the dense factors in fragment slots frag[c][axis]; `layout`
+// component, with the dense factors at base + off[c][axis]; `layout`
 // names a space with the dims of in and out.  Uses d_tmp (in must differ).
-void dense_kron(kmx_space* sp, int layout, const int frag[3][3], const double* in, double* out, double alpha,
-                int accumulate, hipStream_t s) {
+void dense_kron(kmx_space* sp, int layout, const double* base, const int64_t off[3][3], const double* in,
+                double* out, double alpha, int accumulate, hipStream_t s) {
     const int64_t nf = std::max(sp->n_e, sp->n_h);
     DenseArgs a{};
     space_dims(sp, layout, a.dims, a.comp_off);
-    a.frag = sp->d_frag64;
+    a.frag = base;
     for (int c = 0; c < 3; ++c)
-        for (int ax = 0; ax < 3; ++ax) a.frag_off[c][ax] = sp->frag64_off[frag[c][ax]];
+        for (int ax = 0; ax < 3; ++ax) a.frag_off[c][ax] = off[c][ax];
     ProfScope ps(sp, s, PK_DENSE);
     a.in = in;
     a.in_stride = nf;
@@ -1667,12 +1752,9 @@ void run_mass1(kmx_space* sp, int space, const double* x, double* y, hipStream_t
     launch_gather(sp->p, space, g, space == SP_E ? sp->n_e : sp->n_h, 1, s);
 }
 
-// z = P^{-1} r with P the identity-map, unit-material 1-form mass
+// z = P^{-1} r with P the separable (Kronecker) approximation of the 1-form mass
 void s1_precond(kmx_space* sp, int space, const double* r, double* z, hipStream_t s) {
-    int f[3][3];
-    for (int c = 0; c < 3; ++c)
-        for (int a = 0; a < 3; ++a) f[c][a] = FR_GRAM_INV + space_tag(space, c, a);
-    dense_kron(sp, space, f, r, z, 1.0, 0, s);
+    dense_kron(sp, space, sp->d_frag_pre, sp->frag_pre_off[space == SP_E ? 0 : 1], r, z, 1.0, 0, s);
 }
 
 // y = K~1^T D^1 e (space SP_H) or K1^T D~^1 h (space SP_E): the right-hand
@@ -1681,11 +1763,11 @@ void s1_precond(kmx_space* sp, int space, const double* r, double* z, hipStream_
 void s1_rhs(kmx_space* sp, int space, const double* x, double* y, hipStream_t s) {
     double* cu = s1_vec(sp, S1_CU);
     run_curl(sp, space == SP_H, x, 0, cu, 0, 1.0, 0.0, 1, s);
-    int f[3][3];
+    int64_t off[3][3];
     for (int c = 0; c < 3; ++c)
         for (int a = 0; a < 3; ++a)
-            f[c][a] = FR_PAIR + (space == SP_H ? (a == c ? F_G : F_M) : (a == c ? F_MT : F_GT));
-    dense_kron(sp, space, f, cu, y, 1.0, 0, s);
+            off[c][a] = sp->frag64_off[FR_PAIR + (space == SP_H ? (a == c ? F_G : F_M) : (a == c ? F_MT : F_GT))];
+    dense_kron(sp, space, sp->d_frag64, off, cu, y, 1.0, 0, s);
 }
 
 // d_scal[slot] = x . y (deterministic two-level sum)

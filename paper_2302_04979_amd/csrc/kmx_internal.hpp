@@ -148,10 +148,9 @@ struct kmx_space {
     int refine_steps = 2;              // refinement corrections after the first FP32 solve
     // dense FP64 inverses of the four 1D pairing factors (tiled-dense plan)
     double* d_frag64 = nullptr;        // FP64 inverse factors in MFMA operand order (tiled-dense plan)
-    // [0..3] inverses of G^, M^, G^T, M^T; [4..7] inverse 1D Gram matrices of
-    // the tags PV, PD, DV, DD (first-scheme preconditioner); [8..11] G^, M^,
-    // G^T, M^T themselves (first-scheme pairing applies)
-    int64_t frag64_off[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // [0..3] inverses of G^, M^, G^T, M^T; [4..7] G^, M^, G^T, M^T themselves
+    // (first-scheme pairing applies)
+    int64_t frag64_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int dense_ok = 0;                  // the dense kernels' LDS fits the device
     // first scheme (1-form mass solves), set up at its first use
     std::vector<double> eps_host, mu_host;   // [N^3] eps and mu as given (empty: 1)
@@ -159,6 +158,8 @@ struct kmx_space {
     double* d_mu = nullptr;            // [npad^3] mu
     double* d_metric1 = nullptr;       // w_q det DF (DF^T DF)^{-1}, tile layout (metric_mode 0)
     double* d_s1 = nullptr;            // scheme-1 work vectors, S1_VECS x max(n_e, n_h)
+    double* d_frag_pre = nullptr;      // scheme-1 preconditioner: inverse weighted 1D Grams, operand order
+    int64_t frag_pre_off[2][3][3] = {};  // [E, H][component][axis]
     int s1_ready = 0;                  // d_eps / d_mu hold the current materials
     int s1_expect[2] = {0, 0};         // iterations of the last E and H solves
     hipStream_t capture_stream = nullptr;
