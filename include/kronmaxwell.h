@@ -276,8 +276,8 @@ kmx_status kmx_op_pairing(kmx_space* sp, int which, const double* x, double* y, 
  * Symmetric compositions of the leapfrog (kick-drift-kick) of order 2, 4, 6:
  * step weights c_1..c_m with m = 1, 3, 9, from the triple jump
  * c <- (z1 c, z0 c, z1 c), z1 = 1 / (2 - 2^(1/(2k+1))), z0 = 1 - 2 z1 (Yoshida
- * 1990); the paper names higher-order symplectic integrators as the way past
- * the time-error plateau of the leapfrog (Section 6).  The state is (e^n, h^)
+ * 1990); the paper names pairing the scheme with higher-order symplectic
+ * integrators as future work (Section 6).  The state is (e^n, h^)
  * with h^ = h^n + (c_1 dt / 2) K~1^{-1} M D^1 e^n (for order 2 the leapfrog's
  * h^{n-1/2}); one step runs m substeps
  *     h^ -= a_j dt K~1^{-1} M D^1 e;   e += c_j dt K1^{-1} M~ D~^1 h^

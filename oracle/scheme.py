@@ -49,8 +49,8 @@ def composition_weights(order: int):
     (kick-drift-kick) that has the given even order: order 2 is the leapfrog,
     order 2k+2 composes three order-2k methods with the triple-jump weights
     z1 = 1 / (2 - 2^(1/(2k+1))), z0 = 1 - 2 z1 (Yoshida 1990; the paper names
-    higher-order symplectic integrators as the way past the time-error
-    plateau, Section 6)."""
+    pairing the scheme with higher-order symplectic integrators as future
+    work, Section 6)."""
     if order not in (2, 4, 6):
         raise ValueError("order must be 2, 4 or 6")
     c = [1.0]

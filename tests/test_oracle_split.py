@@ -1,6 +1,6 @@
 """Pins of the oracle's higher-order symplectic time stepping (compositions of
-the leapfrog; the paper names them as the way past the time-error plateau,
-Section 6)."""
+the leapfrog; the paper names pairing the scheme with higher-order symplectic
+integrators as future work, Section 6)."""
 import numpy as np
 import pytest
 
