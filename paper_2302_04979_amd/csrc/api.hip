@@ -576,6 +576,9 @@ kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches) {
         launches[sp->prof_kind[i]] += 1;
     }
     for (auto& e : sp->prof_ev) (void)hipEventDestroy(e);
+    for (auto& e : sp->s1_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (sp->h_rr) (void)hipHostFree(sp->h_rr);
     sp->prof_ev.clear();
     sp->prof_kind.clear();
     sp->prof_used = 0;
@@ -586,6 +589,9 @@ kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches) {
 void kmx_destroy_space(kmx_space* sp) {
     if (!sp) return;
     for (auto& e : sp->prof_ev) (void)hipEventDestroy(e);
+    for (auto& e : sp->s1_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (sp->h_rr) (void)hipHostFree(sp->h_rr);
     if (sp->capture_stream) (void)hipStreamDestroy(sp->capture_stream);
     if (sp->d_time) (void)hipFree(sp->d_time);
     double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_axis_tab, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
@@ -1703,6 +1709,10 @@ kmx_status s1_prepare(kmx_space* sp) {
         if ((st = build_metric(sp, &m1, 1)) != KMX_OK) return fail(st, "det DF <= 0 at a quadrature point");
         if ((st = upload(&sp->d_metric1, m1)) != KMX_OK) return st;
     }
+    if (!sp->h_rr) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&sp->h_rr), 2 * sizeof(double), hipHostMallocDefault));
+        for (int k = 0; k < 2; ++k) HIP_TRY(hipEventCreateWithFlags(&sp->s1_ev[k], hipEventDisableTiming));
+    }
     if (!sp->d_s1) {
         const size_t n = size_t(S1_VECS) * size_t(std::max(sp->n_e, sp->n_h));
         if (hipMalloc(&sp->d_s1, n * sizeof(double)) != hipSuccess)
@@ -1779,10 +1789,11 @@ void s1_dot(kmx_space* sp, const double* x, const double* y, int64_t n, int slot
 }
 
 // x = M^{-1} y by preconditioned CG from the initial guess in x, to
-// |r| <= tol |y|.  The residual norm is read back at every iteration from
-// `expect` - 1 on (expect = iterations of the previous solve of this space),
-// so a warm-started sequence of solves synchronises about twice per solve.
-kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double tol, int max_iter, int expect,
+// |r| <= tol |y|.  The residual norm of every iteration is copied to pinned
+// host memory behind an event; the host tests iteration k's norm after it has
+// enqueued iteration k + 1, so the device never waits for the host and at most
+// one iteration more than needed is run (it only improves x).
+kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double tol, int max_iter,
                   int* iters, hipStream_t s) {
     const int64_t n = space == SP_E ? sp->n_e : sp->n_h;
     double *r = s1_vec(sp, S1_R), *z = s1_vec(sp, S1_Z), *pd = s1_vec(sp, S1_P), *Ap = s1_vec(sp, S1_AP);
@@ -1813,6 +1824,15 @@ kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double t
     const int nb = energy_blocks(sp);
     int cur = 0;
     int it = 0;
+    // the residual norm of iteration k lands in h_rr[k % 2], marked by s1_ev[k % 2]
+    auto converged = [&](int k, bool* done) -> kmx_status {
+        HIP_TRY(hipEventSynchronize(sp->s1_ev[k & 1]));
+        const double rr = sp->h_rr[k & 1];
+        if (!std::isfinite(rr)) return fail(KMX_E_UNSTABLE, "mass solve diverged");
+        *done = rr <= stop;
+        return KMX_OK;
+    };
+    bool done = false;
     while (true) {
         run_mass1(sp, space, pd, Ap, s);
         s1_dot(sp, pd, Ap, n, 1, s);
@@ -1827,22 +1847,26 @@ kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double t
             ProfScope ps(sp, s, PK_VEC);
             launch_dot2(r, z, n, sp->d_red, nb, sc + 3, sc + nxt, s);
         }
-        if (it >= expect - 1 || it >= max_iter) {
-            double rr = 0.0;
-            HIP_TRY(hipMemcpyAsync(&rr, sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (!std::isfinite(rr)) return fail(KMX_E_UNSTABLE, "mass solve diverged");
-            if (rr <= stop) break;
-            if (it >= max_iter) {
-                *iters = it;
-                return fail(KMX_E_UNSTABLE, "mass solve did not reach the tolerance within max_iter iterations");
-            }
-        }
+        HIP_TRY(hipMemcpyAsync(sp->h_rr + (it & 1), sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(sp->s1_ev[it & 1], s));
         {
             ProfScope ps(sp, s, PK_VEC);
             launch_cg2(x, r, pd, Ap, z, n, sc + nxt, sc + cur, 1, s);
         }
         cur = nxt;
+        // test the previous iteration while this one runs
+        if (it >= 2) {
+            kmx_status st = converged(it - 1, &done);
+            if (st != KMX_OK) return st;
+            if (done) break;
+        }
+        if (it >= max_iter) {
+            kmx_status st = converged(it, &done);
+            if (st != KMX_OK) return st;
+            if (done) break;
+            *iters = it;
+            return fail(KMX_E_UNSTABLE, "mass solve did not reach the tolerance within max_iter iterations");
+        }
     }
     *iters = it;
     return KMX_OK;
@@ -1857,10 +1881,9 @@ kmx_status s1_half(kmx_space* sp, int space, const double* x, double* out, doubl
     double* sol = s1_vec(sp, space == SP_E ? S1_XE : S1_XH);
     s1_rhs(sp, space, x, y, s);
     int it = 0;
-    kmx_status st = s1_pcg(sp, space, y, sol, tol, max_iter, sp->s1_expect[space == SP_E ? 0 : 1], &it, s);
+    kmx_status st = s1_pcg(sp, space, y, sol, tol, max_iter, &it, s);
     *iters += it;
     if (st != KMX_OK) return st;
-    sp->s1_expect[space == SP_E ? 0 : 1] = it;
     ProfScope ps(sp, s, PK_VEC);
     launch_axpby(sol, out, n, alpha, nullptr, 1.0, s);
     return KMX_OK;
@@ -1894,7 +1917,7 @@ kmx_status kmx_solve_mass1(kmx_space* sp, int which, const double* y, double* x,
     if (st != KMX_OK) return st;
     if (x == y) return fail(KMX_E_ARG, "x and y must not alias");
     int it = 0;
-    st = s1_pcg(sp, which == 0 ? SP_E : SP_H, y, x, tol, max_iter, 0, &it, static_cast<hipStream_t>(stream));
+    st = s1_pcg(sp, which == 0 ? SP_E : SP_H, y, x, tol, max_iter, &it, static_cast<hipStream_t>(stream));
     if (iters) *iters = it;
     if (st != KMX_OK) return st;
     CHECK_LAUNCH();
@@ -1925,7 +1948,7 @@ kmx_status kmx_project_E1(kmx_space* sp, const double* E_qp_host, double* e_dev,
     HIP_TRY(hipMemcpyAsync(y, l.data(), l.size() * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(e_dev, 0, l.size() * sizeof(double), s));
     int it = 0;
-    st = s1_pcg(sp, SP_E, y, e_dev, tol, 2000, 0, &it, s);
+    st = s1_pcg(sp, SP_E, y, e_dev, tol, 2000, &it, s);
     if (st != KMX_OK) return st;
     HIP_TRY(hipStreamSynchronize(s));
     return KMX_OK;

@@ -161,7 +161,8 @@ struct kmx_space {
     double* d_frag_pre = nullptr;      // scheme-1 preconditioner: inverse weighted 1D Grams, operand order
     int64_t frag_pre_off[2][3][3] = {};  // [E, H][component][axis]
     int s1_ready = 0;                  // d_eps / d_mu hold the current materials
-    int s1_expect[2] = {0, 0};         // iterations of the last E and H solves
+    double* h_rr = nullptr;            // pinned host copies of the CG residual norms (ring of 2)
+    hipEvent_t s1_ev[2] = {nullptr, nullptr};  // marks the copies
     hipStream_t capture_stream = nullptr;
     // optional per-kernel timing with HIP events (kmx_profile_begin/end)
     bool prof_on = false;
