@@ -98,3 +98,21 @@ def test_full_size_composed_steps():
     G.op_pairing("K1", E[:n_e].contiguous(), Ke)
     G.op_mass("D", E[n_e:].contiguous(), Md)
     assert float(torch.linalg.norm(Ke - Md) / torch.linalg.norm(Md)) < 1e-12
+
+
+def test_full_size_order4_step_matches_oracle():
+    """p=3, 64^3 deformed cube with random eps under the dense plan: one
+    order-4 composed step (three substeps) from a random state against the
+    oracle's composition."""
+    import paper_2302_04979_amd as K
+    S, G = make_pair(3, 64)
+    print("\n[case] composed order 4 vs oracle, p=3 N=64", flush=True)
+    G.set_plan(K.PLAN_TILED_DENSE)
+    e0 = W.random_vector(S.n_e, 8, 31)
+    h0 = W.random_vector(S.n_h, 8, 32)
+    dt = 1e-3
+    e, h, _, _ = S.step_split(e0, h0, dt, 1, 4)
+    E, H = to_dev(e0), to_dev(h0)
+    G.step_split(E, H, dt, 1, 4)
+    assert rel(to_host(E) - e0, e - e0) < 1e-12
+    assert rel(to_host(H) - h0, h - h0) < 1e-12
