@@ -197,15 +197,18 @@ __global__ void __launch_bounds__(256) dense_xy_kernel(const DenseArgs A) {
 // One workgroup per 64 (x, y) columns of a component: out = (accumulate ? out
 // : 0) + alpha B_z X over the columns, KB k steps (the largest component's;
 // rows past a component's nz are zero).  Wave w owns the 16 columns 16 w ..
-// 16 w + 15 and every 16-row tile of the output; the B_z tiles (the left
-// operands) stay in its registers, read from L2 together with the columns and
-// the accumulated output, so a k step reads one operand from LDS for TZ
-// products.
+// 16 w + 15 and every 16-row tile of the output.  The B_z tiles (the left
+// operands, the same for every wave) and the columns are read once per
+// workgroup into LDS, together with the accumulated output; a k step then
+// reads TZ + 1 operands from LDS for TZ products.
 template <int KB>
 __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
     constexpr int TZ = (KB + 3) / 4;
     constexpr int P = 65;
-    extern __shared__ double X[];  // [4 KB][P]
+    constexpr int NF = TZ * KB * 64;           // factor operands
+    constexpr int LF = (NF + 255) / 256;       // factor loads per thread
+    extern __shared__ double X[];  // [4 KB][P] columns, then [TZ][KB][64] factor operands
+    double* F = X + 4 * KB * P;
     const int c = blockIdx.y, b = blockIdx.z;
     const int nz = A.dims[c][0], ny = A.dims[c][1], nx = A.dims[c][2];
     const int64_t ncol = int64_t(nx) * ny;
@@ -217,10 +220,10 @@ __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
     double* out = A.out + int64_t(b) * A.out_stride + A.comp_off[c];
     const int64_t col = col0 + 16 * wv + lr;
     const double* Fz = A.frag + A.frag_off[c][2];
-    double o[TZ][4], fa[TZ][KB];
+    double o[TZ][4], fr[LF];
     {
-        // the accumulated output, the factor tiles and the columns (rows z over
-        // the waves), all loads in flight together
+        // the accumulated output, the factor operands and the columns (rows z
+        // over the waves), all loads in flight together
 #pragma unroll
         for (int t = 0; t < TZ; ++t)
 #pragma unroll
@@ -229,10 +232,14 @@ __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
                 o[t][r] = (A.accumulate && col < ncol && z < nz) ? out[int64_t(z) * ncol + col] : 0.0;
             }
 #pragma unroll
-        for (int t = 0; t < TZ; ++t) {
-            const int tc = t < tzn ? t : tzn - 1;  // inside the factor; the zero rows meet it
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) fa[t][kb] = Fz[(tc * kbz + (kb < kbz ? kb : kbz - 1)) * 64 + lane];
+        for (int q = 0; q < LF; ++q) {
+            // operand (t, kb, l) of the padded factor; indices clamped inside the
+            // stored factor (its products with the zero rows of X add nothing)
+            const int i = tid + 256 * q;
+            const int t = i / (KB * 64), kb = (i / 64) % KB, l = i % 64;
+            const int tc = t < tzn ? t : tzn - 1, kc = kb < kbz ? kb : kbz - 1;
+            const double v = Fz[i < NF ? (tc * kbz + kc) * 64 + l : 0];
+            fr[q] = i < NF ? v : 0.0;
         }
         const double* in = A.in + int64_t(b) * A.in_stride + A.comp_off[c];
         const bool ok = col0 + lane < ncol;
@@ -241,6 +248,11 @@ __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
         for (int k = 0; k < KB; ++k) {
             const int z = wv + 4 * k;
             r[k] = (ok && z < nz) ? in[int64_t(z) * ncol + col0 + lane] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < LF; ++q) {
+            const int i = tid + 256 * q;
+            if (i < NF) F[i] = fr[q];
         }
 #pragma unroll
         for (int k = 0; k < KB; ++k) X[(wv + 4 * k) * P + lane] = r[k];
@@ -253,7 +265,7 @@ __global__ void __launch_bounds__(256) dense_z_kernel(const DenseArgs A) {
     for (int kb = 0; kb < KB; ++kb) {
         const double xb = X[(4 * kb + lk) * P + 16 * wv + lr];
 #pragma unroll
-        for (int t = 0; t < TZ; ++t) acc[t] = mfma64(fa[t][kb], xb, acc[t]);
+        for (int t = 0; t < TZ; ++t) acc[t] = mfma64(F[(t * KB + kb) * 64 + lane], xb, acc[t]);
     }
     if (col >= ncol) return;
     const double alpha = A.alpha;
@@ -293,7 +305,10 @@ int z_kb(const int dims[3][3]) {
     return kb;
 }
 
-size_t z_lds(const int dims[3][3]) { return size_t(4 * z_kb(dims)) * 65 * sizeof(double); }
+size_t z_lds(const int dims[3][3]) {
+    const int kb = z_kb(dims), tz = (kb + 3) / 4;
+    return (size_t(4 * kb) * 65 + size_t(tz) * kb * 64) * sizeof(double);
+}
 
 }  // namespace
 
