@@ -12,15 +12,18 @@ primitives (matrix products, dense LU), with no blocking or fusion:
 * ``splines``   - knot vectors, B-spline and Curry-Schoenberg bases, Gauss rules,
                   1D incidence matrices, 1D pairing matrices G^ and M^
                   (Section 2.3; Section 4.1).
-* ``geometry``  - maps F of the unit cube and the 2-form metric factor
-                  DF^T DF / (gamma det DF) (Section 2.3 pullbacks).
+* ``geometry``  - maps F of the unit cube (identity, the deformed cube, the
+                  quarter coax of Section 5 as a degree-2 NURBS map) and the
+                  2-form and 1-form metric factors DF^T DF / det DF and
+                  det DF (DF^T DF)^{-1} (Section 2.3 pullbacks).
 * ``assembly``  - level 0, the plain definitions: 3D pairing matrices K1, K~1
                   by 3D quadrature, mass matrices by element loops, sparse curls
                   (Sections 2.4, 3.4).
 * ``scheme``    - level 1, the structured method: per-axis Kronecker solves
                   (eq. (4.4), (4.5)), sum-factorised mass applies, the explicit
                   leapfrog of (3.10)-(3.13) in its (e, h) Petrov-Galerkin form,
-                  energies, CFL, projections, point sources and probes.
+                  energies, CFL, projections, point sources and probes;
+                  symmetric triple-jump compositions of the leapfrog.
 * ``scheme1``   - the first scheme (Section 3.3): 1-form mass matrices with
                   the covariant factor det DF (DF^T DF)^{-1}, conjugate-gradient
                   mass solves, the (e, h) leapfrog with the transposed pairings,
