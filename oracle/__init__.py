@@ -30,6 +30,7 @@ primitives (matrix products, dense LU), with no blocking or fusion:
                   its energies and CFL.
 * ``adjoint``   - the discrete adjoint of the scheme-2 leapfrog.
 
-Every function pinned by tests under ``-m "not gpu"``; see the design doc for the
-pins, and for the readings taken where the paper is silent.
+Every function is pinned by the CPU tests ``tests/test_oracle_*.py`` against
+closed forms, invariants, dense level-0 assembly and brute force on tiny
+meshes.
 """
