@@ -351,6 +351,17 @@ kmx_status kmx_project_E1(kmx_space* sp, const double* E_qp_host, double* e_dev,
 kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, double tol, int max_iter,
                             int* iters, void* stream);
 
+/* nsteps steps of the first scheme on the device arrays e, h captured once as
+ * a HIP graph (replayed with kmx_graph_launch, released with
+ * kmx_graph_destroy): every mass solve runs a fixed number of preconditioned CG
+ * iterations (iters_e, iters_h >= 1; choose them from the counts a tolerance-
+ * driven kmx_step_scheme1 reports) with no read-back of the residual, from the
+ * warm start of the previous solve.  The space's first-scheme set-up (its
+ * allocations) is done before the capture.  The captured graph holds kernel
+ * and device-to-device copy nodes only. */
+kmx_status kmx_graph_create_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, int iters_e,
+                                    int iters_h, kmx_graph** out);
+
 /* Largest stable time step of the first scheme, 2 / sqrt(lambda_max) of
  * (M^1_eps)^{-1} K1^T D~^1 (M~^1_mu)^{-1} K~1^T D^1 by power iteration from the
  * same seeded start as kmx_cfl (stops when lambda changes by at most tol

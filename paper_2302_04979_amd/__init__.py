@@ -41,7 +41,7 @@ EXPORTS = (
     "kmx_graph_create", "kmx_graph_launch",
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
     "kmx_op_mass1", "kmx_solve_mass1", "kmx_half_step_scheme1", "kmx_step_scheme1", "kmx_cfl_scheme1",
-    "kmx_init_split", "kmx_step_split", "kmx_project_E1",
+    "kmx_init_split", "kmx_step_split", "kmx_project_E1", "kmx_graph_create_scheme1",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
                  "mode_fp32", "dense_fp64", "mass_1form", "cg_vector")
@@ -118,6 +118,7 @@ def load_library():
         "kmx_cfl_scheme1": ([vp, i, d, d, ctypes.POINTER(d)], i),
         "kmx_init_split": ([vp, vp, vp, d, i, i, i, vp], i),
         "kmx_project_E1": ([vp, vp, vp, d, vp], i),
+        "kmx_graph_create_scheme1": ([vp, vp, vp, d, i, i, i, ctypes.POINTER(vp)], i),
         "kmx_step_split": ([vp, vp, vp, d, i, i, i, i, vp], i),
     }
     for name, (args, res) in sig.items():
@@ -234,6 +235,21 @@ class Probes:
             self.close()
         except Exception:
             pass
+
+
+class GraphScheme1(Graph):
+    """nsteps first-scheme steps with fixed CG iteration counts, captured as a
+    HIP graph (kmx_graph_create_scheme1); launch() replays it."""
+
+    def __init__(self, space: "Space", e, h, dt, nsteps, iters_e, iters_h):
+        g = ctypes.c_void_p()
+        _check(load_library().kmx_graph_create_scheme1(space._h, _dptr(e, space.n_e, "e"),
+                                                       _dptr(h, space.n_h, "h"), float(dt), int(nsteps),
+                                                       int(iters_e), int(iters_h), ctypes.byref(g)))
+        self._h = g
+        self._keep = (e, h)  # bound at capture
+        self.space = space
+        self.nsteps = nsteps
 
 
 class Space:
@@ -394,6 +410,10 @@ class Space:
         points, (n_qp, 3) host array) onto X^1_{h,0}."""
         keep, ptr = _hptr(E_qp, 3 * self.n_qp)
         _check(load_library().kmx_project_E1(self._h, ptr, _dptr(e, self.n_e, "e"), float(tol), _stream()))
+
+    def graph_scheme1(self, e, h, dt, nsteps, iters_e, iters_h) -> GraphScheme1:
+        """Capture nsteps first-scheme steps with fixed CG iteration counts."""
+        return GraphScheme1(self, e, h, dt, nsteps, iters_e, iters_h)
 
     def cfl_scheme1(self, max_iter=2000, tol=1e-10, cg_tol=1e-12) -> float:
         out = ctypes.c_double()

@@ -1872,6 +1872,32 @@ kmx_status s1_pcg(kmx_space* sp, int space, const double* y, double* x, double t
     return KMX_OK;
 }
 
+// The same CG with a fixed number of iterations and no read-back (graph
+// capture): x = M^{-1} y after `iters` iterations from the guess in x.
+void s1_pcg_fixed(kmx_space* sp, int space, const double* y, double* x, int iters, hipStream_t s) {
+    const int64_t n = space == SP_E ? sp->n_e : sp->n_h;
+    double *r = s1_vec(sp, S1_R), *z = s1_vec(sp, S1_Z), *pd = s1_vec(sp, S1_P), *Ap = s1_vec(sp, S1_AP);
+    double* sc = sp->d_scal;
+    const int nb = energy_blocks(sp);
+    run_mass1(sp, space, x, Ap, s);
+    (void)hipMemcpyAsync(r, y, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    launch_axpby(Ap, r, n, -1.0, nullptr, 1.0, s);
+    s1_precond(sp, space, r, z, s);
+    (void)hipMemcpyAsync(pd, z, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    s1_dot(sp, r, z, n, 0, s);
+    int cur = 0;
+    for (int it = 0; it < iters; ++it) {
+        run_mass1(sp, space, pd, Ap, s);
+        s1_dot(sp, pd, Ap, n, 1, s);
+        const int nxt = 2 - cur;
+        launch_cg2(x, r, pd, Ap, nullptr, n, sc + cur, sc + 1, 0, s);
+        s1_precond(sp, space, r, z, s);
+        launch_dot2(r, z, n, sp->d_red, nb, sc + 3, sc + nxt, s);
+        launch_cg2(x, r, pd, Ap, z, n, sc + nxt, sc + cur, 1, s);
+        cur = nxt;
+    }
+}
+
 // out += alpha * M^{-1} rhs(x) for one half step; the solve starts from the
 // previous solution of the same space
 kmx_status s1_half(kmx_space* sp, int space, const double* x, double* out, double alpha, double tol, int max_iter,
@@ -1973,6 +1999,46 @@ kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int 
     }
     if (st != KMX_OK) return st;
     CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_graph_create_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, int iters_e,
+                                    int iters_h, kmx_graph** out) {
+    if (!e || !h || !out || nsteps < 1 || iters_e < 1 || iters_h < 1) return fail(KMX_E_ARG, "bad argument");
+    if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt must be finite");
+    kmx_status st = s1_check(sp, 0.5, 1);  // set-up (allocations) before the capture
+    if (st != KMX_OK) return st;
+    if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on; graphs are captured without timing events");
+    *out = nullptr;
+    if (!sp->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&sp->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = sp->capture_stream;
+    HIP_TRY(hipStreamSynchronize(cs));
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    double* y = s1_vec(sp, S1_Y);
+    for (int n = 0; n < nsteps; ++n) {
+        // h -= dt M~^{-1} K~1^T D^1 e, then e += dt M^{-1} K1^T D~^1 h
+        s1_rhs(sp, SP_H, e, y, cs);
+        s1_pcg_fixed(sp, SP_H, y, s1_vec(sp, S1_XH), iters_h, cs);
+        launch_axpby(s1_vec(sp, S1_XH), h, sp->n_h, -dt, nullptr, 1.0, cs);
+        s1_rhs(sp, SP_E, h, y, cs);
+        s1_pcg_fixed(sp, SP_E, y, s1_vec(sp, S1_XE), iters_e, cs);
+        launch_axpby(s1_vec(sp, S1_XE), e, sp->n_e, dt, nullptr, 1.0, cs);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (ec != hipSuccess) return fail(KMX_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        hipGraphDestroy(graph);
+        return fail(KMX_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    kmx_graph* g = new kmx_graph();
+    g->sp = sp;
+    g->graph = graph;
+    g->exec = exec;
+    g->nsteps = nsteps;
+    *out = g;
     return KMX_OK;
 }
 

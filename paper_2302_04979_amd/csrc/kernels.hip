@@ -1927,7 +1927,9 @@ __global__ void cg2_kernel(double* x, double* r, double* pdir, const double* Ap,
                            const double* num, const double* den, int phase) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double c = num[0] / den[0];
+    // a zero denominator (a zero right-hand side, or a residual already zero
+    // in a fixed-count solve) makes the step a no-op
+    const double c = den[0] != 0.0 ? num[0] / den[0] : 0.0;
     if (phase == 0) {
         x[i] += c * pdir[i];
         r[i] -= c * Ap[i];

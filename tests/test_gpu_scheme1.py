@@ -213,3 +213,31 @@ def test_project_E1_matches_oracle(p, N, deformed):
     G.project_E1(Eq, e, tol=1e-14)
     ref = S.project_E1(lambda xyz: W.eval_modes(modes, xyz.reshape(-1, 3)).reshape(xyz.shape))
     assert rel(to_host(e), ref) < 1e-10
+
+
+def test_graph_captured_fixed_iteration_steps():
+    """Steps captured as a HIP graph with fixed CG iteration counts: replays
+    from the same state (with eager work and host reads in between) agree to
+    rounding (each replay's solves start from the previous replay's solutions,
+    the warm start), and match the oracle's steps to the solve tolerance."""
+    import torch
+    S, G = _make(3, 5, True, False)
+    dt, nsteps = 0.02, 4
+    e0 = W.random_vector(S.n_e, 21)
+    h0, _ = S.init_stagger1(e0, np.zeros(S.n_h), dt)
+    e, h = to_dev(e0), to_dev(h0)
+    gr = G.graph_scheme1(e, h, dt, nsteps, 60, 40)
+    outs = []
+    for _ in range(3):
+        e.copy_(to_dev(e0))
+        h.copy_(to_dev(h0))
+        torch.cuda.synchronize()
+        gr.launch()
+        torch.cuda.synchronize()
+        outs.append((to_host(e), to_host(h)))
+        G.op_mass1("E", e, torch.empty_like(e))  # eager work between replays
+    gr.close()
+    for eo, ho in outs[1:]:
+        assert rel(eo, outs[0][0]) < 1e-13 and rel(ho, outs[0][1]) < 1e-13
+    e_o, h_o, _, _ = S.step1(e0, h0, dt, nsteps)
+    assert rel(outs[0][0], e_o) < 1e-10 and rel(outs[0][1], h_o) < 1e-10
