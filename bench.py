@@ -229,6 +229,18 @@ def scheme1_timing(K, W, torch, G, e0, dt2, ms_step2, steps=20, tol=1e-12):
     its = G.step_scheme1(e, h, dt1, steps, tol=tol)
     torch.cuda.synchronize()
     ms1 = (time.perf_counter() - t0) * 1e3 / steps
+    # the same steps captured as one HIP graph with fixed iteration counts (the
+    # tolerance-driven counts, rounded up, plus one)
+    it_e, it_h = int(math.ceil(its[0] / steps)) + 1, int(math.ceil(its[1] / steps)) + 1
+    gsteps = 10
+    gr = G.graph_scheme1(e, h, dt1, gsteps, it_e, it_h)
+    gr.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr.launch()
+    torch.cuda.synchronize()
+    ms1_graph = (time.perf_counter() - t0) * 1e3 / gsteps
+    gr.close()
     G.profile_begin(capacity=4096)
     G.step_scheme1(e, h, dt1, 4, tol=tol)
     prof = G.profile_end()
@@ -241,6 +253,8 @@ def scheme1_timing(K, W, torch, G, e0, dt2, ms_step2, steps=20, tol=1e-12):
     return {"workload": f"first scheme (1-form mass solves), same space, e^0 and eps as the headline, mu = 1, "
                         f"dt = 0.5 CFL1, PCG to |r| <= {tol:g} |y|, warm-started",
             "ms_per_step": ms1, "steps": steps, "dt": dt1,
+            "graph_fixed_iterations": {"iters_e": it_e, "iters_h": it_h, "ms_per_step": ms1_graph,
+                                       "per_step_ratio_vs_scheme2": ms1_graph / ms_step2},
             "cg_iters_per_solve": {"e": its[0] / steps, "h": its[1] / steps},
             "cfl": cfl1, "cfl_scheme2": cfl2, "cfl_ratio": cfl1 / cfl2,
             "per_step_ratio_vs_scheme2": ms1 / ms_step2,
