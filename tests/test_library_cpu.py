@@ -50,3 +50,20 @@ def test_argument_errors_without_device():
     assert L.kmx_step(None, None, None, None, 0.0, 0.1, 1, 1, 0, None, None) == 1
     assert L.kmx_set_materials(None, None, None) == 1
     L.kmx_destroy_space(None)  # accepted
+
+
+def test_argument_errors_of_the_added_entry_points():
+    """The first scheme, the composed steps and their graphs refuse NULL or
+    out-of-range arguments before any device work."""
+    K, L = _lib()
+    d = ctypes.c_double
+    assert L.kmx_op_mass1(None, 0, None, None, None) == 1
+    assert L.kmx_solve_mass1(None, 0, None, None, d(1e-12), 10, None, None) == 1
+    assert L.kmx_half_step_scheme1(None, 1, None, None, d(0.1), d(1e-12), 10, None, None) == 1
+    assert L.kmx_step_scheme1(None, None, None, d(0.1), 1, d(1e-12), 10, None, None) == 1
+    assert L.kmx_project_E1(None, None, None, d(1e-12), None) == 1
+    assert L.kmx_cfl_scheme1(None, 10, d(1e-6), d(1e-10), None) == 1
+    assert L.kmx_graph_create_scheme1(None, None, None, d(0.1), 1, 5, 5, None) == 1
+    assert L.kmx_step_split(None, None, None, d(0.1), 1, 4, 1, 0, None) == 1
+    assert L.kmx_init_split(None, None, None, d(0.1), 3, 1, 0, None) == 1  # order 3 does not exist
+    assert L.kmx_last_error().decode()
