@@ -4,7 +4,7 @@ by the discrete adjoint of the (e, h) leapfrog (oracle, FP64, plain NumPy).
 Test infrastructure only (see ``oracle/__init__``).
 
 The paper has no adjoint; this is the exact reverse-mode derivative of the
-time-discrete scheme it defines (Section 3.5.2 form, see ``oracle.scheme``):
+time-discrete scheme it defines (Section 3.4.2 form, see ``oracle.scheme``):
 
   forward, from e^0 = 0, h^{-1/2} = 0:
       h^{n+1/2} = h^{n-1/2} - dt K~1^{-1} M D^1 e^n

@@ -2,12 +2,12 @@
 
 Test infrastructure only (see ``oracle/__init__``).
 
-What is computed (paper, Section 3.5 and Section 4):
+What is computed (paper, Section 3.4 and Section 4):
 
   semi-discrete scheme (3.10)-(3.13)
       d_t d = D~^1 h - j,   K1 e = M~^2_{1/eps} d,
       d_t b = - D^1 e,      K~1 h = M^2_{1/mu} b,
-  in the equivalent Petrov-Galerkin (e, h) form of Section 3.5.2
+  in the equivalent Petrov-Galerkin (e, h) form of Section 3.4.2
       K~1 d_t h = - M^2_{1/mu} D^1 e,   K1 d_t e = M~^2_{1/eps} D~^1 h - s,
   with s = M~ j the tested source, advanced by the staggered leapfrog
       h^{n+1/2} = h^{n-1/2} - dt K~1^{-1} M D^1 e^n

@@ -1,6 +1,6 @@
 """kronmaxwell: MI355X-native explicit leapfrog for the spline geometric Maxwell
 scheme with Kronecker-structured pairing solves (scheme 2 of Kapidani &
-Vazquez, Section 3.5 and Section 4).
+Vazquez, Section 3.4 and Section 4).
 
 Thin Python binding over the C-ABI library ``libkronmaxwell.so`` (declared in
 ``include/kronmaxwell.h``).  Every function here only marshals arguments:

@@ -1,7 +1,7 @@
 // Persistent leapfrog for separable spaces: identity map and uniform eps, mu.
 //
 // With F = id the 2-form metric is the identity, so the Hodge matrices of
-// Section 3.5 are Kronecker products of 1D Gram matrices (scaled by 1/mu and
+// Section 3.4 are Kronecker products of 1D Gram matrices (scaled by 1/mu and
 // 1/eps), exactly as the pairings K1, K~1 are Kronecker products of the 1D
 // G^, M^ (eqs. (4.2)-(4.3)).  One half step of component c is then
 //     curl -> three banded Gram products -> (source) -> three banded solves,

@@ -1,4 +1,4 @@
-"""Pins of the oracle's leapfrog for scheme 2 (Sections 3.5, 4, 5)."""
+"""Pins of the oracle's leapfrog for scheme 2 (Sections 3.4, 4, 5)."""
 import math
 
 import numpy as np
