@@ -29,6 +29,10 @@ primitives (matrix products, dense LU), with no blocking or fusion:
                   mass solves, the (e, h) leapfrog with the transposed pairings,
                   its energies and CFL.
 * ``adjoint``   - the discrete adjoint of the scheme-2 leapfrog.
+* ``lifting``   - non-homogeneous tangential data for E (Section 3.5): the
+                  whole primal spaces, the least-squares trace fit of the
+                  lifting, the lifted leapfrog with separable-in-time data
+                  (the coaxial cable's TEM mode, Section 5.1.2).
 
 Every function is pinned by the CPU tests ``tests/test_oracle_*.py`` against
 closed forms, invariants, dense level-0 assembly and brute force on tiny

@@ -170,3 +170,69 @@ def div_matrix(axis: Axis, primal: bool) -> np.ndarray:
                         j[a] = k
                         D[row, os_[a] + (j[2] * sh[1] + j[1]) * sh[2] + j[0]] += coef
     return D
+
+
+# ---------------------------------------------------------------------------
+# whole primal spaces (non-homogeneous boundary data, Section 3.5)
+# ---------------------------------------------------------------------------
+def pairing_K1_full(axis: Axis) -> np.ndarray:
+    """The pairing of X~^2 (rows) with the whole X^1_h (columns), by 3D
+    quadrature: [(K1)_0 (K1)_b] up to the ordering of the columns."""
+    pts, w = quad_points_3d(axis)
+    K = np.zeros((space_size(axis, "D"), space_size(axis, "Ef")))
+    od, oe = _offsets(axis, "D"), _offsets(axis, "Ef")
+    for c in range(3):
+        Pd = basis_3d(axis, "D", c, pts)
+        Pe = basis_3d(axis, "Ef", c, pts)
+        K[od[c]:od[c + 1], oe[c]:oe[c + 1]] = Pd.T @ (w[:, None] * Pe)
+    return K
+
+
+def mass_2form_trial_full(axis: Axis, G: np.ndarray, inv_mu_elem: np.ndarray | None = None):
+    """M^2_{1/mu} with test functions in X^2_{h,0} (rows) and trial functions
+    in the whole X^2_h (columns), by the element loop of ``mass_2form``."""
+    N, nq = axis.N, axis.p + 1
+    pts, w = quad_points_3d(axis)
+    Q = N * nq
+    ot, of = _offsets(axis, "B"), _offsets(axis, "Bf")
+    M = np.zeros((ot[3], of[3]))
+    qidx = np.arange(Q ** 3).reshape(Q, Q, Q)
+    for ez in range(N):
+        for ey in range(N):
+            for ex in range(N):
+                q = qidx[ez * nq:(ez + 1) * nq, ey * nq:(ey + 1) * nq, ex * nq:(ex + 1) * nq].ravel()
+                g = 1.0 if inv_mu_elem is None else inv_mu_elem[ez, ey, ex]
+                Pt = [basis_3d(axis, "B", c, pts[q]) for c in range(3)]
+                Pf = [basis_3d(axis, "Bf", c, pts[q]) for c in range(3)]
+                for ci in range(3):
+                    for cj in range(3):
+                        Wij = w[q] * G[q, ci, cj] * g
+                        M[ot[ci]:ot[ci + 1], of[cj]:of[cj + 1]] += Pt[ci].T @ (Wij[:, None] * Pf[cj])
+    return M
+
+
+def curl_matrix_full(axis: Axis) -> np.ndarray:
+    """D^1 from the whole X^1_h to the whole X^2_h: the +-1 matrix with the
+    full primal incidence d_full (Pf' = Pd d_full) along each axis."""
+    d1 = axis.d_full()
+    os_, od = _offsets(axis, "Ef"), _offsets(axis, "Bf")
+    D = np.zeros((od[3], os_[3]))
+    for c in range(3):
+        sh_dst = comp_shape(axis, "Bf", c)
+        for sign, a, s in ((+1.0, (c + 1) % 3, (c + 2) % 3), (-1.0, (c + 2) % 3, (c + 1) % 3)):
+            sh_src = comp_shape(axis, "Ef", s)
+            for iz in range(sh_dst[0]):
+                for iy in range(sh_dst[1]):
+                    for ix in range(sh_dst[2]):
+                        row = od[c] + (iz * sh_dst[1] + iy) * sh_dst[2] + ix
+                        dst_idx = [ix, iy, iz]
+                        for k in range(d1.shape[1]):
+                            coef = d1[dst_idx[a], k]
+                            if coef == 0.0:
+                                continue
+                            src_idx = list(dst_idx)
+                            src_idx[a] = k
+                            jx, jy, jz = src_idx
+                            D[row, os_[s] + (jz * sh_src[1] + jy) * sh_src[2] + jx] += sign * coef
+    return D
+

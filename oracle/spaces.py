@@ -9,6 +9,9 @@ unknowns are
   b in X^2_{h,0} (primal 2-form)   component c: Pv along axis c, Pd across
   h in X~^1      (dual 1-form)     component c: Dd along axis c, Dv across
   d in X~^2      (dual 2-form)     component c: Dv along axis c, Dd across
+and, for non-homogeneous boundary data (Section 3.5), the whole primal spaces
+  X^1_h ('Ef')                     component c: Pd along axis c, Pf across
+  X^2_h ('Bf')                     component c: Pf along axis c, Pd across
 
 A vector stores its three components one after the other; inside a component
 the x index runs fastest (the vec convention of Section 4.2), i.e. a component
@@ -25,6 +28,10 @@ SPACE_TAGS = {
     "B": lambda c, a: "Pv" if a == c else "Pd",
     "H": lambda c, a: "Dd" if a == c else "Dv",
     "D": lambda c, a: "Dv" if a == c else "Dd",
+    # the whole primal spaces X^1_h and X^2_h, boundary functions kept
+    # (non-homogeneous boundary data, Section 3.5)
+    "Ef": lambda c, a: "Pd" if a == c else "Pf",
+    "Bf": lambda c, a: "Pf" if a == c else "Pd",
 }
 
 

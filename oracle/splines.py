@@ -15,6 +15,8 @@ The four 1D bases, by tag:
   Pd  primal derivative  Curry-Schoenberg basis of S_{p-1}(Xi')       dim n1 = N+p-1
   Dv  dual value         standard B-splines of S_{p-1}(Xi')            dim n1
   Dd  dual derivative    Curry-Schoenberg basis of S_{p-2}(Xi'')       dim n0
+  Pf  primal value, full S_p(Xi) with its boundary functions           dim n0+2
+      (only for non-homogeneous boundary data, Section 3.5)
 """
 from __future__ import annotations
 
@@ -76,7 +78,7 @@ class Axis:
         self.xi2 = self.xi[2:-2]
         self.n0 = n_elem + p - 2
         self.n1 = n_elem + p - 1
-        self.dims = {"Pv": self.n0, "Pd": self.n1, "Dv": self.n1, "Dd": self.n0}
+        self.dims = {"Pv": self.n0, "Pd": self.n1, "Dv": self.n1, "Dd": self.n0, "Pf": self.n0 + 2}
 
     # ---- bases ----------------------------------------------------------
     def eval(self, tag: str, x) -> np.ndarray:
@@ -84,6 +86,8 @@ class Axis:
         p = self.p
         if tag == "Pv":
             return bspline_basis(self.xi, p, x)[:, 1:-1]
+        if tag == "Pf":
+            return bspline_basis(self.xi, p, x)
         if tag == "Pd":
             B = bspline_basis(self.xi1, p - 1, x)
             j = np.arange(B.shape[1])
@@ -114,6 +118,16 @@ class Axis:
         for c in range(self.n0):
             d[c, c] = 1.0
             d[c + 1, c] = -1.0
+        return d
+
+    def d_full(self) -> np.ndarray:
+        """n1 x (n0+2) matrix with Pf' = Pd d_full: the derivative of the full
+        primal basis, d_full[k, k+1] = +1, d_full[k, k] = -1 (it equals d on
+        the interior columns)."""
+        d = np.zeros((self.n1, self.n0 + 2))
+        for k in range(self.n1):
+            d[k, k] = -1.0
+            d[k, k + 1] = 1.0
         return d
 
     def d_dual(self) -> np.ndarray:

@@ -197,3 +197,45 @@ def quarter_annulus_jacobian(xh: np.ndarray):
     J[..., 1, 0], J[..., 1, 1] = drho * cy, rho * dcy
     J[..., 2, 2] = 1.0
     return F, J
+
+
+# --------------------------------------------------------------------------
+# TEM standing wave of the quarter coaxial cable (Section 5.1.2)
+# --------------------------------------------------------------------------
+def tem_coax_E(xyz: np.ndarray, t: float = 0.0) -> np.ndarray:
+    """E = (1/r) sin(pi z) cos(pi t) r^ (eps = mu = 1): the TEM mode between
+    the cylinders r = 1, sqrt 2 with the shorting planes z = 0, 1; its
+    tangential trace vanishes on those four faces and not on the planes y = 0
+    and x = 0 (the Dirichlet data there)."""
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    r2 = x * x + y * y
+    f = np.sin(np.pi * z) * np.cos(np.pi * t) / r2
+    return np.stack([f * x, f * y, np.zeros_like(z)], axis=-1)
+
+
+def tem_coax_H(xyz: np.ndarray, t: float = 0.0) -> np.ndarray:
+    """H = -(1/r) cos(pi z) sin(pi t) phi^, the magnetic field of the same mode."""
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    r2 = x * x + y * y
+    f = -np.cos(np.pi * z) * np.sin(np.pi * t) / r2
+    return np.stack([-f * y, f * x, np.zeros_like(z)], axis=-1)
+
+
+def face_gauss_points(p: int, n_elem: int) -> np.ndarray:
+    """Parametric Gauss points of the six faces of the unit cube (p + 1
+    Gauss-Legendre points per element and axis), shape (6, Q, Q, 3): face
+    f = 2 a + s is x^_a = s, indexed [i_v][i_u] over its two other axes u < v
+    (u fastest)."""
+    g, _ = np.polynomial.legendre.leggauss(p + 1)
+    x = ((np.arange(n_elem)[:, None] + 0.5 * (g[None, :] + 1.0)) / n_elem).ravel()
+    Q = x.size
+    out = np.zeros((6, Q, Q, 3))
+    for a in range(3):
+        u, v = [k for k in range(3) if k != a]
+        for s in range(2):
+            f = out[2 * a + s]
+            f[..., a] = float(s)
+            f[..., u] = x[None, :]
+            f[..., v] = x[:, None]
+    return out
+
