@@ -9,7 +9,7 @@
  *     d_t D = dH - J,   d_t B = -dE,   D = eps E (via a Hodge star), B = mu H.
  * E and B live in the primal spline complex of degrees p / p-1 with boundary
  * conditions built in (X^1_{h,0}, X^2_{h,0}); H and D in the dual complex of
- * degrees p-1 / p-2 (X~^1, X~^2).  The scheme of Section 3.5, eqs. (3.10)-(3.13),
+ * degrees p-1 / p-2 (X~^1, X~^2).  The scheme of Section 3.4, eqs. (3.10)-(3.13),
  * uses the Hodge operators of the second kind:
  *     K1 e = M~^2_{1/eps} d,      K~1 h = M^2_{1/mu} b,
  * so every time step applies the geometry/material mass matrices M and solves
@@ -25,7 +25,7 @@
  * component c of h has n0 along axis c and n1 across.
  *
  * Time stepping (staggered leapfrog, Petrov-Galerkin (e, h) form of Section
- * 3.5.2 with the tested source s = M~ j):
+ * 3.4.2 with the tested source s = M~ j):
  *     h^{n+1/2} = h^{n-1/2} - dt K~1^{-1} M^2_{1/mu} D^1 e^n
  *     e^{n+1}   = e^n + dt K1^{-1} ( M~^2_{1/eps} D~^1 h^{n+1/2} - s(t_{n+1/2}) )
  * and, when tracking is on, b^{n+1/2} = b^{n-1/2} - dt D^1 e^n and
@@ -64,7 +64,8 @@ typedef enum {
     KMX_E_MATERIAL = 3,  /* eps or mu <= 0 or not finite */
     KMX_E_DEVICE = 4,    /* a HIP runtime call failed */
     KMX_E_OOM = 5,       /* device allocation failed at creation */
-    KMX_E_UNSTABLE = 6,  /* non-finite value detected, or dt above the CFL limit */
+    KMX_E_UNSTABLE = 6,  /* non-finite value detected, or |dt| above the stable step that
+                            kmx_cfl (kmx_cfl_scheme1) last computed for the space */
     KMX_E_STATE = 7      /* call not valid in the current state */
 } kmx_status;
 
@@ -116,7 +117,10 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
 void kmx_destroy_space(kmx_space* sp);
 
 /* Per-element eps and mu (host, N^3 each, element index x fastest); NULL keeps
- * the value 1.  Errors: KMX_E_MATERIAL, KMX_E_DEVICE. */
+ * the value 1.  Forgets the stable steps computed by kmx_cfl and
+ * kmx_cfl_scheme1 (they depend on the materials).  Errors: KMX_E_MATERIAL,
+ * KMX_E_DEVICE; KMX_E_STATE while graphs captured on the space exist (a
+ * graph holds the material state it was captured with: destroy it first). */
 kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double* mu_elem);
 
 /* n_e = dim X^1_{h,0} = dim X~^2, n_h = dim X~^1 = dim X^2_{h,0}, n_qp = number
@@ -124,7 +128,9 @@ kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double
 kmx_status kmx_sizes(const kmx_space* sp, int64_t* n_e, int64_t* n_h, int64_t* n_qp);
 
 /* Physical coordinates F(x^_q) of every quadrature point, host array of
- * 3 * n_qp doubles, element-major: [ez][ey][ex][iqz][iqy][iqx][xyz]. */
+ * 3 * n_qp doubles, element-major: [ez][ey][ex][iqz][iqy][iqx][xyz].  For map
+ * kind 2 only the Jacobians are known: the parametric coordinates x^_q are
+ * returned (the caller maps them). */
 kmx_status kmx_quad_points(const kmx_space* sp, double* xyz_host);
 
 /* Initial electric field (Section 5.1, "projecting" the initial data):
@@ -144,7 +150,11 @@ kmx_status kmx_project_D(kmx_space* sp, const double* E_qp_host, double* d_dev, 
 /* Largest stable step 2 / sqrt(lambda_max(K1^{-1} M~ D~^1 K~1^{-1} M D^1)) by
  * power iteration on the device (seeded start vector), stopping when the
  * eigenvalue estimate changes by less than tol (relative) or after max_iter
- * iterations.  Synchronises. */
+ * iterations.  Synchronises.  The space keeps the result: until the next
+ * kmx_set_materials, kmx_step and kmx_graph_create refuse |dt| above it, and
+ * kmx_step_split a largest substep max_j |c_j dt| above it, with
+ * KMX_E_UNSTABLE (before any device work).  Without a kmx_cfl call no step is
+ * checked. */
 kmx_status kmx_cfl(kmx_space* sp, int max_iter, double tol, double* dt_max);
 
 /* Point dipoles J = q delta(x - F(x^0)) g(t), g(t) = amp exp(-(t - t0)^2 / (2 sigma^2)).
@@ -169,7 +179,8 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
  * state is advanced by nsteps.  J: NULL or a source of this space (not allowed
  * together with KMX_TRACK_DB).  energy_dev: NULL, or device array of
  * nsteps * batch doubles receiving the leapfrog invariant after every step
- * (requires KMX_TRACK_DB).  Never allocates and never synchronises. */
+ * (requires KMX_TRACK_DB).  Never allocates and never synchronises.
+ * KMX_E_UNSTABLE when |dt| exceeds the last kmx_cfl result of the space. */
 kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start,
                     double dt, int nsteps, int batch, int flags, double* energy_dev, void* stream);
 
@@ -233,7 +244,10 @@ kmx_status kmx_tune(kmx_space* sp, int batch, int probe_steps, const kmx_source*
  * captured steps is read from the space's device clock, which every replay
  * advances by nsteps*dt, so replaying the graph marches in time; E, H, J and
  * energy_dev are bound at capture and must stay valid.  The graph contains
- * kernel nodes only.  kmx_set_time / kmx_get_time set and read the clock
+ * kernel nodes only.  It also holds the material state of the capture (the
+ * separable plan bakes uniform eps and mu into its launch), so
+ * kmx_set_materials is refused while graphs of the space exist.  A graph may
+ * be destroyed after its space.  kmx_set_time / kmx_get_time set and read the clock
  * (synchronising). */
 kmx_status kmx_graph_create(kmx_space* sp, double* E, double* H, const kmx_source* J, double dt, int nsteps,
                             int batch, int flags, double* energy_dev, kmx_graph** out);
@@ -297,6 +311,53 @@ kmx_status kmx_init_split(kmx_space* sp, const double* E, double* H, double dt, 
 kmx_status kmx_step_split(kmx_space* sp, double* E, double* H, double dt, int nsteps, int order, int batch,
                           int flags, void* stream);
 
+/* ---- non-homogeneous tangential data for E (Section 3.5) ----------------
+ * E_h = E_{h,0} + E_{h,b}: the unknowns e are E_{h,0} in X^1_{h,0}; the lifting
+ * E_{h,b} lives in the whole primal 1-form space X^1_h (the boundary functions
+ * of the full B-spline basis kept: component c has n1 entries along axis c and
+ * n0 + 2 across, x fastest; n_ef = 3 n1 (n0 + 2)^2 entries), carried by its
+ * boundary coefficients.  With the lifting the second scheme solves
+ * (K1)_0 e_0 = M~ d - (K1)_b e_b, with D^1 from X^1_h to X^2_h and the mass of
+ * the Hodge K~1 h = M^2_{1/mu} b taking trial functions in the whole X^2_h. */
+
+/* n_ef, the size of a coefficient vector of X^1_h. */
+kmx_status kmx_sizes_full(const kmx_space* sp, int64_t* n_ef);
+
+/* Boundary coefficients of the lifting from tangential data (the projection
+ * on the trace space that Section 3.5 asks for; reading: one least-squares
+ * fit over the six faces of the parametric cube, in the parametric L^2 norm, so
+ * that a coefficient on an edge is fitted to both of its faces; exact when
+ * the data is the trace of a field of X^1_h).  Eh_faces (host): the pulled-back
+ * field E^ = DF^T (E o F) (three parametric components; the caller knows the
+ * map on the boundary) at the Gauss points of the faces x^_a = s, face
+ * f = 2 a + s, over the two other axes u < v with u fastest:
+ * Eh_faces[((f * Q + i_v) * Q + i_u) * 3 + comp], Q = N (p + 1) points per axis
+ * at the positions of kmx_quad_points; only the tangential components are
+ * used.  eb_full (host, n_ef): the fitted coefficients, zero at the interior
+ * functions.  iters (may be NULL): conjugate-gradient iterations of the fit.
+ * Synchronous host computation. */
+kmx_status kmx_lift_boundary(kmx_space* sp, const double* Eh_faces, double* eb_full, int* iters);
+
+/* Boundary data E_b(x, t) = sum_j g_j(t) E_b^j(x) with g_j(t) = amp_j
+ * cos(omega_j t + phase_j) and E_b^j given by its boundary coefficients
+ * (eb_full: host, nterms x n_ef; interior entries ignored), nterms <= 8
+ * (0 removes the lifting).  Forms, once and in FP64 on the host,
+ * v_h^j = K~1^{-1} M_{0,f} D^1_f e_b^j and v_e^j = (K1)_0^{-1} (K1)_b e_b^j and
+ * keeps them on the device; then (for every batch member)
+ *   kmx_step:         h -= dt g_j(t_n) v_h^j after the h update and
+ *                     e -= (g_j(t_{n+1}) - g_j(t_n)) v_e^j after the e update,
+ *                     t_n the time at the start of the step (graph replays:
+ *                     the space's device clock);
+ *   kmx_init_stagger: h += dt/2 g_j(0) v_h^j;
+ *   kmx_project_E:    e = K1^{-1} l - g_j(0) v_e^j (the Hodge with the lifting
+ *                     at t = 0).
+ * The lifting depends on mu, so kmx_set_materials removes it.  Not with
+ * KMX_TRACK_DB (KMX_E_ARG), composed steps, the first scheme, the adjoint or
+ * a forced separable plan (KMX_E_STATE); KMX_E_STATE while graphs of the space
+ * exist.  Allocates its two device arrays (nterms fields each). */
+kmx_status kmx_set_lifting(kmx_space* sp, int nterms, const double* eb_full, const double* amp,
+                           const double* omega, const double* phase);
+
 /* ---- the first scheme: Hodge stars with 1-form mass matrices -------------
  * Section 3.3, eqs. (3.5)-(3.8): M^1_eps e = K~2 d and M~^1_mu h = K2 b, with
  * K~2 = K1^T and K2 = K~1^T (the pairing-transpose property of Section 2.4),
@@ -347,7 +408,9 @@ kmx_status kmx_project_E1(kmx_space* sp, const double* E_qp_host, double* e_dev,
 
 /* nsteps leapfrog steps of the first scheme on (e^n, h^{n-1/2}) (device, n_e
  * and n_h values).  iters (host, 2 ints, may be NULL) receives the summed CG
- * iterations of the e solves and of the h solves. */
+ * iterations of the e solves and of the h solves.  KMX_E_UNSTABLE when |dt|
+ * exceeds the last kmx_cfl_scheme1 result (also for
+ * kmx_graph_create_scheme1). */
 kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int nsteps, double tol, int max_iter,
                             int* iters, void* stream);
 
@@ -365,7 +428,8 @@ kmx_status kmx_graph_create_scheme1(kmx_space* sp, double* e, double* h, double 
 /* Largest stable time step of the first scheme, 2 / sqrt(lambda_max) of
  * (M^1_eps)^{-1} K1^T D~^1 (M~^1_mu)^{-1} K~1^T D^1 by power iteration from the
  * same seeded start as kmx_cfl (stops when lambda changes by at most tol
- * relative), each mass solve to cg_tol.  Allocates two fields; synchronises. */
+ * relative), each mass solve to cg_tol.  Allocates two fields; synchronises.
+ * The space keeps the result for the checks of kmx_step_scheme1. */
 kmx_status kmx_cfl_scheme1(kmx_space* sp, int max_iter, double tol, double cg_tol, double* dt_max);
 
 /* ---- probes and the adjoint (gradient of a probe misfit in eps) ----------
@@ -385,7 +449,8 @@ kmx_status kmx_probe_eval(kmx_space* sp, const kmx_probes* pr, const double* e, 
 
 /* From zero fields, nsteps leapfrog steps driven by J (may be NULL); obs
  * (device, nsteps x 3n) receives P e^n for n = 1..nsteps.  Allocates two
- * fields of working memory; synchronises. */
+ * fields of working memory; synchronises.  Runs the tiled plan, like
+ * kmx_adjoint (a separable plan set on the space is restored afterwards). */
 kmx_status kmx_probe_forward(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, double dt, int nsteps,
                              double* obs, void* stream);
 
@@ -399,7 +464,11 @@ kmx_status kmx_probe_forward(kmx_space* sp, const kmx_probes* pr, const kmx_sour
  * The forward states are recomputed from checkpoints taken every
  * `checkpoint_every` steps.  data: device, nsteps x 3n.  loss_host: host
  * scalar.  grad: device, N^3 (x fastest), overwritten.  Allocates its working
- * memory (checkpoints, one segment of h, probe values); synchronises. */
+ * memory (checkpoints, one segment of h, probe values); synchronises.  The
+ * forward steps run the tiled plan (the operators the reverse sweep
+ * transposes; a separable plan set on the space is restored afterwards).  A
+ * failing forward step (e.g. KMX_E_UNSTABLE) ends the call with its status;
+ * loss_host and grad are then not valid. */
 kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, const double* data, double dt,
                        int nsteps, int checkpoint_every, double* loss_host, double* grad, void* stream);
 
@@ -424,6 +493,11 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
  * Arrays ms_total and launches (host) hold KMX_PROFILE_KINDS entries. */
 #define KMX_PROFILE_KINDS 12
 kmx_status kmx_profile_begin(kmx_space* sp, int capacity);
+/* Bracket only the kinds whose bit is set in mask (bit k: kind k; default all
+ * kinds) until kmx_profile_end.  Each bracketed launch is separated from
+ * its neighbours by two event records; bracketing one kind leaves the
+ * others' launches back to back. */
+kmx_status kmx_profile_select(kmx_space* sp, unsigned mask);
 kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches);
 
 const char* kmx_last_error(void);

@@ -42,6 +42,8 @@ EXPORTS = (
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
     "kmx_op_mass1", "kmx_solve_mass1", "kmx_half_step_scheme1", "kmx_step_scheme1", "kmx_cfl_scheme1",
     "kmx_init_split", "kmx_step_split", "kmx_project_E1", "kmx_graph_create_scheme1",
+    "kmx_profile_select", "kmx_sizes_full", "kmx_lift_boundary",
+    "kmx_set_lifting",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
                  "mode_fp32", "dense_fp64", "mass_1form", "cg_vector")
@@ -95,6 +97,7 @@ def load_library():
         "kmx_op_solve": ([vp, i, i, vp, vp, vp], i),
         "kmx_op_pairing": ([vp, i, vp, vp, vp], i),
         "kmx_profile_begin": ([vp, i], i),
+        "kmx_profile_select": ([vp, ctypes.c_uint], i),
         "kmx_profile_end": ([vp, vp, vp], i),
         "kmx_create_probes": ([vp, i, vp, ctypes.POINTER(vp)], i),
         "kmx_destroy_probes": ([vp], None),
@@ -120,6 +123,9 @@ def load_library():
         "kmx_project_E1": ([vp, vp, vp, d, vp], i),
         "kmx_graph_create_scheme1": ([vp, vp, vp, d, i, i, i, ctypes.POINTER(vp)], i),
         "kmx_step_split": ([vp, vp, vp, d, i, i, i, i, vp], i),
+        "kmx_sizes_full": ([vp, i64p], i),
+        "kmx_lift_boundary": ([vp, vp, vp, ctypes.POINTER(i)], i),
+        "kmx_set_lifting": ([vp, i, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -477,6 +483,13 @@ class Space:
     def profile_begin(self, capacity=100000):
         _check(load_library().kmx_profile_begin(self._h, int(capacity)))
 
+    def profile_select(self, kinds):
+        """Bracket only the named kernel kinds (names of PROFILE_KINDS)."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << PROFILE_KINDS.index(k)
+        _check(load_library().kmx_profile_select(self._h, mask))
+
     def profile_end(self) -> dict:
         """{kind: (total_ms, launches)} for the launches since profile_begin."""
         ms = np.zeros(len(PROFILE_KINDS))
@@ -484,6 +497,34 @@ class Space:
         _check(load_library().kmx_profile_end(self._h, ctypes.c_void_p(ms.ctypes.data),
                                               ctypes.c_void_p(cnt.ctypes.data)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_KINDS)}
+
+    # ---- non-homogeneous tangential data (Section 3.5) ---------------------
+    @property
+    def n_ef(self) -> int:
+        out = ctypes.c_int64()
+        _check(load_library().kmx_sizes_full(self._h, ctypes.byref(out)))
+        return out.value
+
+    def lift_boundary(self, Eh_faces) -> np.ndarray:
+        """Boundary coefficients (a vector of X^1_h) fitted to the pulled-back
+        tangential data at the face Gauss points (kmx_lift_boundary layout)."""
+        q = self.N * (self.p + 1)
+        a, ptr = _hptr(Eh_faces, 6 * q * q * 3, name="Eh_faces")
+        out = np.zeros(self.n_ef)
+        it = ctypes.c_int()
+        _check(load_library().kmx_lift_boundary(self._h, ptr, ctypes.c_void_p(out.ctypes.data), ctypes.byref(it)))
+        return out
+
+    def set_lifting(self, eb_full, amp, omega, phase):
+        """Lifting terms sum_j amp_j cos(omega_j t + phase_j) E_b^j (eb_full: one
+        vector of X^1_h per term); no terms removes it."""
+        eb = np.ascontiguousarray(np.asarray(eb_full, dtype=np.float64).reshape(-1))
+        n = len(np.atleast_1d(amp))
+        if n and eb.size != n * self.n_ef:
+            raise ValueError(f"eb_full has {eb.size} entries, needs {n} x {self.n_ef}")
+        arrs = [np.ascontiguousarray(np.atleast_1d(np.asarray(v, dtype=np.float64))) for v in (amp, omega, phase)]
+        ptr = lambda x: ctypes.c_void_p(x.ctypes.data) if x.size else None  # noqa: E731
+        _check(load_library().kmx_set_lifting(self._h, int(n), ptr(eb), *(ptr(x) for x in arrs)))
 
     def op_pairing(self, which: str, x, y):
         w = 1 if which == "K1" else 0

@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
+#include <unordered_set>
 #include <string>
 #include <vector>
 
@@ -19,10 +21,16 @@ namespace {
 
 thread_local std::string g_err;
 
+// Spaces that exist, so that destroying a graph after its space is harmless.
+std::mutex g_spaces_mu;
+std::unordered_set<const kmx_space*> g_spaces;
+
+
 kmx_status fail(kmx_status st, const std::string& msg) {
     g_err = msg;
     return st;
 }
+
 
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \
@@ -71,7 +79,7 @@ struct ProfScope {  // brackets one launch with events when profiling is on
     hipStream_t s;
     int slot = -1;
     ProfScope(kmx_space* sp_, hipStream_t s_, int kind) : sp(sp_), s(s_) {
-        if (sp->prof_on && sp->prof_used + 2 <= int(sp->prof_ev.size())) {
+        if (sp->prof_on && ((sp->prof_mask >> kind) & 1u) && sp->prof_used + 2 <= int(sp->prof_ev.size())) {
             slot = sp->prof_used;
             sp->prof_used += 2;
             sp->prof_kind[slot / 2] = kind;
@@ -246,6 +254,30 @@ void run_energy(kmx_space* sp, const double* E, const double* H, double dt, int 
     a.partial = sp->d_red;
     launch_energy_fused(sp->p, a, batch, s);
     launch_energy_final(sp->d_red, a.nb[0] + a.nb[1], dt, batch, out, out_stride, s);
+}
+
+// The forward model of the probe misfit and its adjoint run the tiled plan,
+// whose operators the reverse sweep transposes (a separable plan, chosen for
+// uniform materials, cannot serve per-element eps); the space's plan is
+// restored when the call returns.
+struct TiledPlanScope {
+    kmx_space* sp;
+    int saved;
+    explicit TiledPlanScope(kmx_space* s) : sp(s), saved(s->plan_kind) {
+        if (saved == KMX_PLAN_SEPARABLE || saved == KMX_PLAN_SEPARABLE_FUSED) sp->plan_kind = KMX_PLAN_TILED;
+    }
+    ~TiledPlanScope() { sp->plan_kind = saved; }
+};
+
+LiftTerms lift_terms(const kmx_space* sp) {
+    LiftTerms T{};
+    T.n = sp->lift_n;
+    for (int j = 0; j < sp->lift_n; ++j) {
+        T.amp[j] = sp->lift_amp[j];
+        T.omega[j] = sp->lift_omega[j];
+        T.phase[j] = sp->lift_phase[j];
+    }
+    return T;
 }
 
 kmx_status upload(double** dst, const std::vector<double>& v) {
@@ -541,6 +573,10 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
         kmx_destroy_space(sp);
         return fail(KMX_E_ARG, std::string("set-up failed: ") + ex.what());
     }
+    {
+        std::lock_guard<std::mutex> lk(g_spaces_mu);
+        g_spaces.insert(sp);
+    }
     *out = sp;
     return KMX_OK;
 }
@@ -553,6 +589,13 @@ kmx_status kmx_profile_begin(kmx_space* sp, int capacity) {
     for (auto& e : sp->prof_ev) HIP_TRY(hipEventCreate(&e));
     sp->prof_used = 0;
     sp->prof_on = true;
+    return KMX_OK;
+}
+
+kmx_status kmx_profile_select(kmx_space* sp, unsigned mask) {
+    if (!sp) return fail(KMX_E_ARG, "space is NULL");
+    if (mask == 0 || (mask >> KMX_PROFILE_KINDS) != 0) return fail(KMX_E_ARG, "mask must name kinds 0..KMX_PROFILE_KINDS-1");
+    sp->prof_mask = mask;
     return KMX_OK;
 }
 
@@ -583,11 +626,16 @@ kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches) {
     sp->prof_kind.clear();
     sp->prof_used = 0;
     sp->prof_on = false;
+    sp->prof_mask = ~0u;
     return st;
 }
 
 void kmx_destroy_space(kmx_space* sp) {
     if (!sp) return;
+    {
+        std::lock_guard<std::mutex> lk(g_spaces_mu);
+        g_spaces.erase(sp);
+    }
     for (auto& e : sp->prof_ev) (void)hipEventDestroy(e);
     for (auto& e : sp->s1_ev)
         if (e) (void)hipEventDestroy(e);
@@ -599,7 +647,8 @@ void kmx_destroy_space(kmx_space* sp) {
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_frag64,
-                    sp->d_eps, sp->d_mu, sp->d_metric1, sp->d_s1, sp->d_frag_pre};
+                    sp->d_eps, sp->d_mu, sp->d_metric1, sp->d_s1, sp->d_frag_pre, sp->d_lift_vh,
+                    sp->d_lift_ve};
     for (void* b : more)
         if (b) (void)hipFree(b);
     delete sp;
@@ -607,6 +656,9 @@ void kmx_destroy_space(kmx_space* sp) {
 
 kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double* mu_elem) {
     if (!sp) return fail(KMX_E_ARG, "space is NULL");
+    if (sp->live_graphs > 0)
+        return fail(KMX_E_STATE, "graphs of this space exist: they hold the material state they were captured "
+                                 "with; destroy them before changing the materials");
     const size_t ne3 = size_t(sp->N) * sp->N * sp->N;
     std::vector<double> ie(ne3, 1.0), im(ne3, 1.0);
     for (size_t i = 0; i < ne3; ++i) {
@@ -628,8 +680,62 @@ kmx_status kmx_set_materials(kmx_space* sp, const double* eps_elem, const double
     if (mu_elem) sp->mu_host.assign(mu_elem, mu_elem + ne3);
     else sp->mu_host.clear();
     sp->s1_ready = 0;
+    sp->dt_cfl = sp->dt_cfl1 = 0.0;  // the stable steps change with the materials
+    sp->lift_n = 0;                  // the lifting's v_h depends on mu: set it again
     note_uniform(sp);
     return upload_materials(sp);
+}
+
+kmx_status kmx_sizes_full(const kmx_space* sp, int64_t* n_ef) {
+    if (!sp || !n_ef) return fail(KMX_E_ARG, "NULL argument");
+    *n_ef = full_size(sp, 1);
+    return KMX_OK;
+}
+
+kmx_status kmx_lift_boundary(kmx_space* sp, const double* Eh_faces, double* eb_full, int* iters) {
+    if (!sp || !Eh_faces || !eb_full) return fail(KMX_E_ARG, "NULL argument");
+    const int64_t nq = int64_t(sp->N) * sp->nq;
+    for (int64_t i = 0; i < 6 * nq * nq * 3; ++i)
+        if (!std::isfinite(Eh_faces[i])) return fail(KMX_E_ARG, "face data not finite");
+    const int it = boundary_fit(sp, Eh_faces, eb_full, 1e-14, 5000);
+    if (iters) *iters = it;
+    if (it < 0) return fail(KMX_E_UNSTABLE, "the trace fit did not converge");
+    return KMX_OK;
+}
+
+kmx_status kmx_set_lifting(kmx_space* sp, int nterms, const double* eb_full, const double* amp, const double* omega,
+                           const double* phase) {
+    if (!sp || nterms < 0 || nterms > KMX_LIFT_MAX) return fail(KMX_E_ARG, "nterms must be 0..8");
+    if (nterms > 0 && (!eb_full || !amp || !omega || !phase)) return fail(KMX_E_ARG, "NULL argument");
+    if (sp->live_graphs > 0) return fail(KMX_E_STATE, "graphs of this space exist: destroy them first");
+    for (int j = 0; j < nterms; ++j)
+        if (!std::isfinite(amp[j]) || !std::isfinite(omega[j]) || !std::isfinite(phase[j]))
+            return fail(KMX_E_ARG, "time profile not finite");
+    sp->lift_n = 0;
+    if (nterms == 0) return KMX_OK;
+    const int64_t nf = full_size(sp, 1), nh = sp->n_h, ne = sp->n_e;
+    for (int64_t i = 0; i < nterms * nf; ++i)
+        if (!std::isfinite(eb_full[i])) return fail(KMX_E_ARG, "boundary coefficients not finite");
+    std::vector<double> vh_all(size_t(nterms) * nh), ve_all(size_t(nterms) * ne);
+    for (int j = 0; j < nterms; ++j) {
+        std::vector<double> vh, ve;
+        lifting_vectors(sp, eb_full + int64_t(j) * nf, vh, ve);
+        std::copy(vh.begin(), vh.end(), vh_all.begin() + int64_t(j) * nh);
+        std::copy(ve.begin(), ve.end(), ve_all.begin() + int64_t(j) * ne);
+    }
+    if (sp->d_lift_vh) { hipFree(sp->d_lift_vh); sp->d_lift_vh = nullptr; }
+    if (sp->d_lift_ve) { hipFree(sp->d_lift_ve); sp->d_lift_ve = nullptr; }
+    kmx_status st;
+    if ((st = upload(&sp->d_lift_vh, vh_all)) != KMX_OK) return st;
+    if ((st = upload(&sp->d_lift_ve, ve_all)) != KMX_OK) return st;
+    sp->lift_ve_host.swap(ve_all);
+    for (int j = 0; j < nterms; ++j) {
+        sp->lift_amp[j] = amp[j];
+        sp->lift_omega[j] = omega[j];
+        sp->lift_phase[j] = phase[j];
+    }
+    sp->lift_n = nterms;
+    return KMX_OK;
 }
 
 kmx_status kmx_sizes(const kmx_space* sp, int64_t* n_e, int64_t* n_h, int64_t* n_qp) {
@@ -651,6 +757,11 @@ kmx_status kmx_project_E(kmx_space* sp, const double* E_qp_host, double* e_dev, 
     std::vector<double> l;
     load_E(sp, E_qp_host, l);
     kron_solve_K1_host(sp, l);
+    // with a lifting: (K1)_0 e = l - (K1)_b e_b(0)
+    for (int j = 0; j < sp->lift_n; ++j) {
+        const double g0 = sp->lift_amp[j] * std::cos(sp->lift_phase[j]);
+        for (int64_t i = 0; i < sp->n_e; ++i) l[i] -= g0 * sp->lift_ve_host[size_t(j) * sp->n_e + i];
+    }
     HIP_TRY(hipMemcpyAsync(e_dev, l.data(), l.size() * sizeof(double), hipMemcpyHostToDevice,
                            static_cast<hipStream_t>(stream)));
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
@@ -756,6 +867,7 @@ kmx_status kmx_cfl(kmx_space* sp, int max_iter, double tol, double* dt_max) {
     hipFree(hb);
     if (result != KMX_OK) return result;
     *dt_max = 2.0 / std::sqrt(lam);
+    sp->dt_cfl = *dt_max;
     return KMX_OK;
 }
 
@@ -962,6 +1074,7 @@ kmx_status kmx_probe_forward(kmx_space* sp, const kmx_probes* pr, const kmx_sour
                              double* obs, void* stream) {
     if (!sp || !pr || !obs || nsteps < 1 || pr->sp != sp || (J && J->sp != sp)) return fail(KMX_E_ARG, "bad argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const TiledPlanScope tiled(sp);
     double *e = nullptr, *h = nullptr;
     if (hipMalloc(&e, sp->n_e * sizeof(double)) != hipSuccess || hipMalloc(&h, sp->n_h * sizeof(double)) != hipSuccess) {
         hipFree(e); hipFree(h);
@@ -988,7 +1101,9 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
     if (!sp || !pr || !data || !loss_host || !grad || nsteps < 1 || checkpoint_every < 1 || pr->sp != sp ||
         (J && J->sp != sp))
         return fail(KMX_E_ARG, "bad argument");
+    if (sp->lift_n) return fail(KMX_E_STATE, "the adjoint does not take a lifting");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const TiledPlanScope tiled(sp);
     const int64_t ne = sp->n_e, nh = sp->n_h, nobs = int64_t(3) * pr->n, NS = nsteps;
     const int K = std::min(checkpoint_every, nsteps), nseg = (nsteps + K - 1) / K;
     // working memory (this call allocates; the time step itself never does)
@@ -1019,14 +1134,16 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
         // ---- forward run with checkpoints of (e^n, h^{n-1/2}) every K steps ----
         hipMemsetAsync(e, 0, ne * sizeof(double), s);
         hipMemsetAsync(h, 0, nh * sizeof(double), s);
-        for (int n = 0; n < nsteps; ++n) {
+        for (int n = 0; n < nsteps && st == KMX_OK; ++n) {
             if (n % K == 0) {
                 hipMemcpyAsync(ck_e + int64_t(n / K) * ne, e, ne * sizeof(double), hipMemcpyDeviceToDevice, s);
                 hipMemcpyAsync(ck_h + int64_t(n / K) * nh, h, nh * sizeof(double), hipMemcpyDeviceToDevice, s);
             }
-            kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
+            st = kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
             launch_csr(pr->d_rowptr, pr->d_col, pr->d_val, e, obs + n * nobs, nullptr, int(nobs), 1.0, 0.0, s);
         }
+    }
+    if (st == KMX_OK) {
         // ---- misfit ----
         const int nb = int(std::min<int64_t>(1024, (NS * nobs + 255) / 256));
         launch_residual(obs, data, res, NS * nobs, sp->d_red, nb, s);
@@ -1055,14 +1172,15 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
         g.coef = -dt;
         g.grad = grad;
         g.lam = lam;
-        for (int seg = nseg - 1; seg >= 0; --seg) {
+        for (int seg = nseg - 1; seg >= 0 && st == KMX_OK; --seg) {
             const int n0 = seg * K, n1 = std::min(nsteps, n0 + K);
             hipMemcpyAsync(e, ck_e + int64_t(seg) * ne, ne * sizeof(double), hipMemcpyDeviceToDevice, s);
             hipMemcpyAsync(h, ck_h + int64_t(seg) * nh, nh * sizeof(double), hipMemcpyDeviceToDevice, s);
-            for (int n = n0; n < n1; ++n) {  // recompute the segment, keeping h^{n+1/2}
-                kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
+            for (int n = n0; n < n1 && st == KMX_OK; ++n) {  // recompute the segment, keeping h^{n+1/2}
+                st = kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
                 hipMemcpyAsync(seg_h + int64_t(n - n0) * nh, h, nh * sizeof(double), hipMemcpyDeviceToDevice, s);
             }
+            if (st != KMX_OK) break;
             for (int n = n1 - 1; n >= n0; --n) {
                 const double t = (n + 0.5) * dt;
                 // lam = K1^{-T} ebar
@@ -1089,8 +1207,8 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
         }
         double sumsq = 0.0;
         hipMemcpyAsync(&sumsq, sp->d_scal, sizeof(double), hipMemcpyDeviceToHost, s);
-        if (hipStreamSynchronize(s) != hipSuccess) st = fail(KMX_E_DEVICE, "adjoint run failed");
-        *loss_host = 0.5 * sumsq;
+        if (hipStreamSynchronize(s) != hipSuccess && st == KMX_OK) st = fail(KMX_E_DEVICE, "adjoint run failed");
+        if (st == KMX_OK) *loss_host = 0.5 * sumsq;
         if (st == KMX_OK && hipGetLastError() != hipSuccess) st = fail(KMX_E_DEVICE, "kernel launch failed");
     }
     hipStreamSynchronize(s);
@@ -1105,9 +1223,13 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
     const int track = flags & KMX_TRACK_DB;
     const int64_t es = sp->n_e * (1 + track), hs = sp->n_h * (1 + track);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (track && sp->lift_n) return fail(KMX_E_ARG, "tracking d and b with a lifting is not supported");
     if (track) run_curl(sp, 1, E, es, H + sp->n_h, hs, 0.5 * dt, 1.0, batch, s);
     run_mass(sp, SP_B, true, E, es, batch, s);
     run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, 0.5 * dt, 1, batch, nullptr, 0.0, 1, s);
+    // the lifting at t = 0: h += dt/2 sum_j g_j(0) v_h^j
+    if (sp->lift_n)
+        launch_lift(H, hs, sp->d_lift_vh, sp->n_h, lift_terms(sp), 0.0, 0.0, nullptr, -0.5 * dt, 0, batch, s);
     CHECK_LAUNCH();
     return KMX_OK;
 }
@@ -1197,7 +1319,7 @@ void dense_solve(kmx_space* sp, int which_K1, const double* y, double* out, int6
 // eps and mu the same in every element, no per-step energy output, lines that
 // fit the kernel's registers and component tensors that fit one workgroup's LDS.
 bool sep_eligible(const kmx_space* sp, const double* energy_dev) {
-    if (sp->map.kind != 0 || !sp->uniform_eps || !sp->uniform_mu || energy_dev) return false;
+    if (sp->map.kind != 0 || !sp->uniform_eps || !sp->uniform_mu || energy_dev || sp->lift_n) return false;
     if (sp->precision == KMX_MIXED) return false;
     if (sep_line_max(std::max(sp->n0, sp->n1)) == 0) return false;
     int ed[3][3], hd[3][3];
@@ -1250,9 +1372,11 @@ kmx_status run_sep(kmx_space* sp, double* E, double* H, const kmx_source* J, dou
 //   h -= ka K~1^{-1} M D^1 e   (b -= ka D^1 e when tracking)
 //   e += kb K1^{-1} (M~ D~^1 h - s(t_half))   (d += kb D~^1 h)
 // the leapfrog step with ka = kb = dt, a substep of a composition otherwise.
+// t_base + t_step (or *t_dev + t_step under graph replay) is the time at the
+// start of the substep, the lifting's t_n; t_half the source time.
 static void tiled_substep(kmx_space* sp, double* E, double* H, int64_t es, int64_t hs, double ka, double kb, int batch,
                    int track, bool dense, bool mixed, const kmx_source* J, double t_half, const double* t_dev,
-                   hipStream_t s) {
+                   hipStream_t s, double t_base = 0.0, double t_step = 0.0) {
     const int64_t nf = std::max(sp->n_e, sp->n_h);
     // M D^1 e (and b -= ka D^1 e), then h -= ka K~1^{-1} (.)
     run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -ka);
@@ -1265,6 +1389,9 @@ static void tiled_substep(kmx_space* sp, double* E, double* H, int64_t es, int64
     } else {
         run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -ka, 1, batch, nullptr, 0.0, 1, s);
     }
+    // the lifting: h -= ka sum_j g_j(t_n) v_h^j (t_n = t_half - ka / 2)
+    if (sp->lift_n)
+        launch_lift(H, hs, sp->d_lift_vh, sp->n_h, lift_terms(sp), t_base, t_step, t_dev, ka, 0, batch, s);
     // M~ D~^1 h (and d += kb D~^1 h), then e += kb K1^{-1} (. - s)
     run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, kb);
     if (dense && !mixed) {
@@ -1276,6 +1403,9 @@ static void tiled_substep(kmx_space* sp, double* E, double* H, int64_t es, int64
     } else {
         run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, kb, 1, batch, J, t_half, 1, s, nullptr, t_dev);
     }
+    // the lifting: e -= sum_j (g_j(t_n + kb) - g_j(t_n)) v_e^j
+    if (sp->lift_n)
+        launch_lift(E, es, sp->d_lift_ve, sp->n_e, lift_terms(sp), t_base, t_step, t_dev, kb, 1, batch, s);
 }
 
 kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start, const double* t_dev,
@@ -1284,9 +1414,11 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     if (batch < 1 || batch > sp->max_batch) return fail(KMX_E_ARG, "batch out of range");
     if (nsteps < 0) return fail(KMX_E_ARG, "nsteps < 0");
     if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt not finite");
+    if (sp->dt_cfl > 0.0 && std::fabs(dt) > sp->dt_cfl) return fail(KMX_E_UNSTABLE, "|dt| above the CFL limit");
     const int track = flags & KMX_TRACK_DB;
     if (J && J->sp != sp) return fail(KMX_E_ARG, "source belongs to another space");
     if (J && track) return fail(KMX_E_ARG, "tracking d and b needs J = NULL (d would need M~^{-1} s)");
+    if (sp->lift_n && track) return fail(KMX_E_ARG, "tracking d and b with a lifting is not supported");
     if (energy_dev && !track) return fail(KMX_E_ARG, "energy output needs KMX_TRACK_DB");
     const bool sep_ok = sep_eligible(sp, energy_dev);
     int kind = sp->plan_kind;
@@ -1309,7 +1441,8 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     sp->mass_waves4 = kind == KMX_PLAN_TILED_W4 ? 1 : 0;
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
-        tiled_substep(sp, E, H, es, hs, dt, dt, batch, track, dense, mixed, J, t_half, t_dev, s);
+        tiled_substep(sp, E, H, es, hs, dt, dt, batch, track, dense, mixed, J, t_half, t_dev, s, t_dev ? 0.0 : t_start,
+                      n * dt);
         if (energy_dev) run_energy(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, 1, s);
     }
     if (t_dev) launch_advance_time(const_cast<double*>(t_dev), nsteps * dt, s);
@@ -1351,6 +1484,12 @@ kmx_status kmx_step_split(kmx_space* sp, double* E, double* H, double dt, int ns
     if (batch < 1 || batch > sp->max_batch) return fail(KMX_E_ARG, "batch out of range");
     if (nsteps < 0) return fail(KMX_E_ARG, "nsteps < 0");
     if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt not finite");
+    if (sp->lift_n) return fail(KMX_E_STATE, "composed steps do not take a lifting");
+    const std::vector<double> c = composition_weights(order);
+    double cmax = 0.0;
+    for (double w : c) cmax = std::max(cmax, std::fabs(w));
+    if (sp->dt_cfl > 0.0 && cmax * std::fabs(dt) > sp->dt_cfl)
+        return fail(KMX_E_UNSTABLE, "the largest substep |c_j dt| is above the CFL limit");
     int kind = sp->plan_kind;
     if (kind == KMX_PLAN_SEPARABLE || kind == KMX_PLAN_SEPARABLE_FUSED)
         return fail(KMX_E_STATE, "composed steps run the tiled plans only");
@@ -1360,7 +1499,6 @@ kmx_status kmx_step_split(kmx_space* sp, double* E, double* H, double dt, int ns
     const bool mixed = sp->precision == KMX_MIXED;
     const bool dense = kind == KMX_PLAN_TILED_DENSE;
     sp->mass_waves4 = kind == KMX_PLAN_TILED_W4 ? 1 : 0;
-    const std::vector<double> c = composition_weights(order);
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int n = 0; n < nsteps; ++n)
         for (size_t j = 0; j < c.size(); ++j) {
@@ -1499,6 +1637,7 @@ kmx_status kmx_graph_create(kmx_space* sp, double* E, double* H, const kmx_sourc
         return fail(KMX_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
     }
     kmx_graph* g = new kmx_graph();
+    ++sp->live_graphs;
     g->sp = sp;
     g->graph = graph;
     g->exec = exec;
@@ -1515,6 +1654,10 @@ kmx_status kmx_graph_launch(kmx_graph* g, void* stream) {
 
 void kmx_graph_destroy(kmx_graph* g) {
     if (!g) return;
+    {
+        std::lock_guard<std::mutex> lk(g_spaces_mu);
+        if (g->sp && g_spaces.count(g->sp)) --g->sp->live_graphs;
+    }
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
@@ -1685,10 +1828,14 @@ kmx_status s1_build_precond(kmx_space* sp) {
                 dense_fragments(inv.data(), n, frag.data() + sp->frag_pre_off[s][c][a]);
             }
     }
-    if (sp->d_frag_pre) {
-        HIP_TRY(hipFree(sp->d_frag_pre));
-        sp->d_frag_pre = nullptr;
+    // rebuilt into the same allocation (its size depends on p and N only), so
+    // device pointers taken earlier stay valid
+    if (sp->d_frag_pre && sp->frag_pre_len == int64_t(frag.size())) {
+        HIP_TRY(hipMemcpy(sp->d_frag_pre, frag.data(), frag.size() * sizeof(double), hipMemcpyHostToDevice));
+        return KMX_OK;
     }
+    if (sp->d_frag_pre) return fail(KMX_E_STATE, "preconditioner size changed");
+    sp->frag_pre_len = int64_t(frag.size());
     return upload(&sp->d_frag_pre, frag);
 }
 
@@ -1920,6 +2067,7 @@ kmx_status s1_check(kmx_space* sp, double tol, int max_iter) {
     if (!(tol > 0.0) || !(tol < 1.0)) return fail(KMX_E_ARG, "tol must be in (0, 1)");
     if (max_iter < 1) return fail(KMX_E_ARG, "max_iter must be >= 1");
     if (sp->precision == KMX_MIXED) return fail(KMX_E_STATE, "the first scheme runs in FP64 spaces only");
+    if (sp->lift_n) return fail(KMX_E_STATE, "the first scheme does not take a lifting");
     return s1_prepare(sp);
 }
 
@@ -1986,6 +2134,8 @@ kmx_status kmx_step_scheme1(kmx_space* sp, double* e, double* h, double dt, int 
     if (nsteps < 0) return fail(KMX_E_ARG, "nsteps must be >= 0");
     if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt must be finite");
     kmx_status st = s1_check(sp, tol, max_iter);
+    if (st == KMX_OK && sp->dt_cfl1 > 0.0 && std::fabs(dt) > sp->dt_cfl1)
+        st = fail(KMX_E_UNSTABLE, "|dt| above the first scheme's CFL limit");
     if (st != KMX_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int it[2] = {0, 0};
@@ -2008,6 +2158,8 @@ kmx_status kmx_graph_create_scheme1(kmx_space* sp, double* e, double* h, double 
     if (!std::isfinite(dt)) return fail(KMX_E_ARG, "dt must be finite");
     kmx_status st = s1_check(sp, 0.5, 1);  // set-up (allocations) before the capture
     if (st != KMX_OK) return st;
+    if (sp->dt_cfl1 > 0.0 && std::fabs(dt) > sp->dt_cfl1)
+        return fail(KMX_E_UNSTABLE, "|dt| above the first scheme's CFL limit");
     if (sp->prof_on) return fail(KMX_E_STATE, "profiling is on; graphs are captured without timing events");
     *out = nullptr;
     if (!sp->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&sp->capture_stream, hipStreamNonBlocking));
@@ -2034,6 +2186,7 @@ kmx_status kmx_graph_create_scheme1(kmx_space* sp, double* e, double* h, double 
         return fail(KMX_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
     }
     kmx_graph* g = new kmx_graph();
+    ++sp->live_graphs;
     g->sp = sp;
     g->graph = graph;
     g->exec = exec;
@@ -2091,6 +2244,7 @@ kmx_status kmx_cfl_scheme1(kmx_space* sp, int max_iter, double tol, double cg_to
     hipFree(hb);
     if (st != KMX_OK) return st;
     *dt_max = 2.0 / std::sqrt(lam);
+    sp->dt_cfl1 = *dt_max;
     return KMX_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "patch.hpp"
 
 namespace kmx {
 
@@ -55,29 +56,12 @@ struct MassCfg {
     static constexpr int NT = ((Q * Q + 63) / 64) * 64;   // one thread per point of a plane
 };
 
-template <int P, int SPACE, int C>
-struct Lay {  // window layout of component C of a form space inside one tile
-    static constexpr int tx = space_tag(SPACE, C, 0), ty = space_tag(SPACE, C, 1), tz = space_tag(SPACE, C, 2);
-    static constexpr int Kx = tag_support(P, tx), Ky = tag_support(P, ty), Kz = tag_support(P, tz);
-    static constexpr int Wx = TILE + Kx - 1, Wy = TILE + Ky - 1, Wz = TILE + Kz - 1;
-    static constexpr int plane = Wx * Wy;
-    static constexpr int size = plane * Wz;
-};
-
 int mass_threads(int p) {
     switch (p) {
         case 2: return MassCfg<2>::NT;
         case 3: return MassCfg<3>::NT;
         default: return MassCfg<4>::NT;
     }
-}
-
-// Patch layout of one component: [tz][ty][lz][ly][tx][lx], the x rows of the
-// tiles along x side by side, so that a row of outputs gathers from
-// contiguous memory.
-template <class L>
-__host__ __device__ inline int64_t patch_at(int nt, int tx, int ty, int tz, int lx, int ly, int lz) {
-    return ((((int64_t(tz) * nt + ty) * L::Wz + lz) * L::Wy + ly) * nt + tx) * L::Wx + lx;
 }
 
 template <int P, int SPACE>
@@ -809,47 +793,6 @@ void launch_mass(int p, int space, bool curl, const MassArgs& a, int batch, hipS
 // fixed order (tiles by increasing z, y, x).  One thread per output; the
 // windows are compile-time per component, the candidate tiles come from shifts.
 // ===========================================================================
-template <int P, int SPACE, int C>
-__device__ inline double gather_one(const double* __restrict__ patch, int nt, int gz, int gy, int gx) {
-    using L = Lay<P, SPACE, C>;
-    const int rx = gx - tag_offset(L::tx), ry = gy - tag_offset(L::ty), rz = gz - tag_offset(L::tz);
-    int hx = rx / TILE, hy = ry / TILE, hz = rz / TILE;
-    hx = hx > nt - 1 ? nt - 1 : hx;
-    hy = hy > nt - 1 ? nt - 1 : hy;
-    hz = hz > nt - 1 ? nt - 1 : hz;
-    // the candidate tiles h - 1 and h per axis, in a fixed order; a candidate
-    // that does not cover the entry is read at a clamped (valid) position and
-    // contributes zero, so the eight reads are issued without branches
-    bool vx[2], vy[2], vz[2];
-    int tx[2], ty[2], tz[2], lx[2], ly[2], lz[2];
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-        const int ax = hx - 1 + d, ay = hy - 1 + d, az = hz - 1 + d;
-        vx[d] = ax >= 0 && rx - ax * TILE < L::Wx;
-        vy[d] = ay >= 0 && ry - ay * TILE < L::Wy;
-        vz[d] = az >= 0 && rz - az * TILE < L::Wz;
-        tx[d] = vx[d] ? ax : hx;
-        ty[d] = vy[d] ? ay : hy;
-        tz[d] = vz[d] ? az : hz;
-        lx[d] = vx[d] ? rx - tx[d] * TILE : 0;
-        ly[d] = vy[d] ? ry - ty[d] * TILE : 0;
-        lz[d] = vz[d] ? rz - tz[d] * TILE : 0;
-    }
-    double v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int dz = k >> 2, dy = (k >> 1) & 1, dx = k & 1;
-        v[k] = patch[patch_at<L>(nt, tx[dx], ty[dy], tz[dz], lx[dx], ly[dy], lz[dz])];
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int dz = k >> 2, dy = (k >> 1) & 1, dx = k & 1;
-        s += (vz[dz] && vy[dy] && vx[dx]) ? v[k] : 0.0;
-    }
-    return s;
-}
-
 // q = n / d and r = n % d for 0 <= n < 2^24, d > 0, without the software
 // integer division: the hardware reciprocal, refined by one Newton step, gives
 // a quotient that is off by at most one, which one comparison corrects.

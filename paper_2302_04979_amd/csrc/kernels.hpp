@@ -241,6 +241,26 @@ void launch_cg_update(double* x, double* r, double* pdir, const double* Ap, cons
                       int64_t n, const double* scal, int phase, hipStream_t s);
 
 void launch_advance_time(double* t, double dt, hipStream_t s);
+// Lifting terms of non-homogeneous tangential data: g_j(t) = amp_j cos(omega_j t + phase_j)
+constexpr int KMX_LIFT_MAX = 8;
+struct LiftTerms {
+    int n;
+    double amp[KMX_LIFT_MAX], omega[KMX_LIFT_MAX], phase[KMX_LIFT_MAX];
+};
+// whole primal spaces X^1_h (form 1) and X^2_h (form 2): component dims,
+// offsets and sizes
+void full_dims(const kmx_space* sp, int form, int c, int d[3]);
+int64_t full_offset(const kmx_space* sp, int form, int c);
+int64_t full_size(const kmx_space* sp, int form);
+// v_h = K~1^{-1} M_{0,f} D^1_f e_b and v_e = K1^{-1} (K1)_b e_b (host, FP64)
+void lifting_vectors(const kmx_space* sp, const double* eb_full, std::vector<double>& vh, std::vector<double>& ve);
+// least-squares trace fit of the boundary coefficients; returns the CG
+// iterations, or -1 when tol was not reached within max_iter
+int boundary_fit(const kmx_space* sp, const double* Eh_faces, double* eb_full, double tol, int max_iter);
+// out += the lifting's contribution to one half step (mode 0: h, 1: e)
+void launch_lift(double* out, int64_t out_stride, const double* v, int64_t n, const LiftTerms& T, double t_base,
+                 double t_step, const double* t_dev, double dt, int mode, int batch, hipStream_t s);
+
 
 int mass_threads(int p);
 int64_t patch_size(int p, int space, int ntile, int64_t comp_off[3]);

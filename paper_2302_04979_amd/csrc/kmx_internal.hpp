@@ -20,10 +20,13 @@ constexpr int TILE = 4;
 //   DV dual value, B-splines of S_{p-1}(Xi') (dim n1)
 //   DD dual derivative, Curry-Schoenberg basis of S_{p-2}(Xi'') (dim n0)
 enum Tag { PV = 0, PD = 1, DV = 2, DD = 3 };
+// The whole S_p(Xi) basis (Pv with its two boundary functions kept), only for
+// non-homogeneous boundary data; N + p functions, e .. e + p nonzero on element e.
+constexpr int PF = 4;
 
 // Number of basis functions of a tag that are nonzero on one element.
 __host__ __device__ constexpr int tag_support(int p, int tag) {
-    return tag == PV ? p + 1 : (tag == DD ? p - 1 : p);
+    return (tag == PV || tag == PF) ? p + 1 : (tag == DD ? p - 1 : p);
 }
 // Global index of local function j on element e is e + j + tag_offset.
 __host__ __device__ constexpr int tag_offset(int tag) { return tag == PV ? -1 : 0; }
@@ -66,6 +69,8 @@ struct Tables {        // host-side 1D data
     int p = 0, N = 0, nq = 0, n0 = 0, n1 = 0, npad = 0;
     std::vector<double> xq, wq;                 // global Gauss points / weights (N*nq)
     std::vector<double> tab[4];                 // [npad][nq][K(tag)] values at Gauss points
+    std::vector<double> tab_pf;                 // [N][nq][p+1] the whole S_p basis (Pv with its
+                                                // boundary functions), for boundary data
     std::vector<double> G, M;                   // dense n0 x n0 and n1 x n1
     BandLU lu[4];                               // factors of G, M, G^T, M^T
 };
@@ -164,8 +169,19 @@ struct kmx_space {
     double* h_rr = nullptr;            // pinned host copies of the CG residual norms (ring of 2)
     hipEvent_t s1_ev[2] = {nullptr, nullptr};  // marks the copies
     hipStream_t capture_stream = nullptr;
+    int live_graphs = 0;               // graphs captured on this space and not yet destroyed
+    // lifting of non-homogeneous tangential E data (kmx_set_lifting)
+    int lift_n = 0;
+    double *d_lift_vh = nullptr, *d_lift_ve = nullptr;  // [term][n_h], [term][n_e]
+    double lift_amp[8] = {}, lift_omega[8] = {}, lift_phase[8] = {};
+    std::vector<double> lift_ve_host;  // v_e of every term (the initial Hodge)
+    // last stable steps computed by kmx_cfl / kmx_cfl_scheme1 for the current
+    // materials (0: not computed); steps with a larger |dt| are refused
+    double dt_cfl = 0.0, dt_cfl1 = 0.0;
+    int64_t frag_pre_len = 0;          // doubles in d_frag_pre (fixed by p and N)
     // optional per-kernel timing with HIP events (kmx_profile_begin/end)
     bool prof_on = false;
+    unsigned prof_mask = ~0u;          // kinds bracketed with events (bit k: kind k)
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_kind;
     int prof_used = 0;

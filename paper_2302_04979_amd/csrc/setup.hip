@@ -91,6 +91,11 @@ void eval_tag_on_element(const Tables& tb, int tag, int e, double x, double* val
             }
             break;
         }
+        case PF: {
+            auto t = knots_for(p, N, 0);
+            nonzero_bsplines(t, p + e, p, x, vals);  // full indices e..e+p, none removed
+            break;
+        }
         case PD:
         case DV: {
             auto t = knots_for(p, N, 1);
@@ -194,6 +199,10 @@ void build_tables(Tables& tb, int p, int N) {
             for (int q = 0; q < tb.nq; ++q)
                 eval_tag_on_element(tb, tag, e, tb.xq[e * tb.nq + q], &tb.tab[tag][(e * tb.nq + q) * K]);
     }
+    tb.tab_pf.assign(size_t(N) * tb.nq * (p + 1), 0.0);
+    for (int e = 0; e < N; ++e)
+        for (int q = 0; q < tb.nq; ++q)
+            eval_tag_on_element(tb, PF, e, tb.xq[e * tb.nq + q], &tb.tab_pf[(e * tb.nq + q) * (p + 1)]);
     // 1D pairing matrices G^ = int Dd^T Pv (n0 x n0), M^ = int Dv^T Pd (n1 x n1)
     const int n0 = tb.n0, n1 = tb.n1;
     tb.G.assign(size_t(n0) * n0, 0.0);

@@ -46,3 +46,11 @@ def qp_param_points(p, N):
     Y = np.broadcast_to(x[None, :, None, None, :, None], (N, N, N, p + 1, p + 1, p + 1))
     Z = np.broadcast_to(x[:, None, None, :, None, None], (N, N, N, p + 1, p + 1, p + 1))
     return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def maxrel(a, b):
+    """Element-wise bound: max |a - b| over max |b|."""
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    mb = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / (mb if mb > 0 else 1.0)) if b.size else 0.0

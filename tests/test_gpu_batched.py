@@ -187,7 +187,7 @@ def test_batched_256_sources_p3_n24():
     orientations, identity map, eps = mu = 1, zero initial fields, 400 steps
     in one persistent launch under a captured graph: members equal their own
     single-source runs, and a sampled member matches the oracle over the
-    first 130 steps (past the Gaussian's peak at 100 dt)."""
+    whole run of 400 steps."""
     import time
     import torch
     import paper_2302_04979_amd as K
@@ -225,7 +225,7 @@ def test_batched_256_sources_p3_n24():
         H1 = torch.zeros(G1.n_h, dtype=torch.float64, device="cuda")
         G1.step(E1, H1, dt, nsteps=nsteps, J=J1)
         assert np.array_equal(Eb[k * G.n_e:(k + 1) * G.n_e], to_host(E1))
-    k, n_or = 97, 130
+    k, n_or = 97, nsteps
     S = Scheme(p, N)
     e, h = _oracle_member(S, dip, k, np.zeros(S.n_e), np.zeros(S.n_h), dt, n_or)
     G1 = K.Space(p, N)

@@ -1,0 +1,125 @@
+"""GPU parity of the non-homogeneous tangential data (Section 3.5) on the
+quarter coax with the TEM mode's data (Section 5.1.2): the trace fit, the
+lifted steps of both solve plans and their graph form, against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from _helpers import qp_param_points, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _coax(p, N):
+    from oracle.geometry import Map
+    from oracle.lifting import LiftedScheme
+    import paper_2302_04979_amd as K
+    S = LiftedScheme(p, N, Map("annulus"))
+    _, DF = W.quarter_annulus_jacobian(qp_param_points(p, N))
+    G = K.Space(p, N, map_kind=2, dF_qp=DF.reshape(-1))
+    return S, G
+
+
+def _face_data(p, N, t=0.0):
+    """E^ = DF^T (E o F) of the TEM field at the face Gauss points."""
+    P = W.face_gauss_points(p, N)
+    F, J = W.quarter_annulus_jacobian(P)
+    E = W.tem_coax_E(F, t)
+    return np.einsum("...ki,...k->...i", J, E)
+
+
+def _tem_on_quad(G):
+    """The TEM field at the mapped Gauss points (map kind 2 returns the
+    parametric points: the map is the caller's)."""
+    F, _ = W.quarter_annulus_jacobian(G.quad_points())
+    return W.tem_coax_E(F, 0.0)
+
+
+@pytest.mark.parametrize("p,N", [(2, 4), (3, 5)])
+def test_trace_fit_matches_oracle(p, N):
+    print(f"\n[case] trace fit p={p} N={N}", flush=True)
+    S, G = _coax(p, N)
+    eb_ref = S.lift(lambda x: W.tem_coax_E(x, 0.0))
+    eb = G.lift_boundary(_face_data(p, N))
+    assert eb.size == eb_ref.size
+    assert rel(eb, eb_ref) < 1e-12
+    assert np.all(eb[~S.boundary_mask()] == 0)
+
+
+@pytest.mark.parametrize("plan", ["tiled", "tiled-dense"])
+def test_lifted_steps_match_oracle(plan):
+    """Projection with the lifting, the staggered start and 15 lifted steps
+    (g(t) = cos(pi t)) match the oracle's lifted leapfrog."""
+    import torch
+    import paper_2302_04979_amd as K
+    p, N, dt, nsteps = 3, 5, 0.01, 15
+    print(f"\n[case] lifted steps p={p} N={N} plan={plan}", flush=True)
+    S, G = _coax(p, N)
+    G.set_plan(K.PLAN_TILED if plan == "tiled" else K.PLAN_TILED_DENSE)
+    eb = G.lift_boundary(_face_data(p, N))
+    G.set_lifting(eb, [1.0], [math.pi], [0.0])
+    E = torch.zeros(G.n_e, dtype=torch.float64, device="cuda")
+    H = torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+    G.project_E(_tem_on_quad(G), E)
+    G.init_stagger(E, H, dt)
+    e_start, h_start = to_host(E), to_host(H)
+    G.step(E, H, dt, nsteps=nsteps)
+    g = lambda t: math.cos(math.pi * t)  # noqa: E731
+    v_h, v_e = S.lifting_vectors(S.lift(lambda x: W.tem_coax_E(x, 0.0)))
+    terms = [(v_h, v_e, g)]
+    e0, h0 = S.init_lifted(lambda x: W.tem_coax_E(x, 0.0), terms, dt)
+    assert rel(e_start, e0) < 1e-12 and rel(h_start, h0) < 1e-12
+    e, h = S.step_lifted(e0, h0, dt, nsteps, terms)
+    assert rel(to_host(E), e) < 1e-12 and rel(to_host(H), h) < 1e-12
+
+
+def test_lifted_graph_replays_equal_eager_steps():
+    import torch
+    p, N, dt, K_ = 2, 4, 0.01, 6
+    S, G = _coax(p, N)
+    eb = G.lift_boundary(_face_data(p, N))
+    G.set_lifting(np.concatenate([eb, -0.5 * eb]), [0.7, 0.2], [math.pi, 2.0], [0.0, 0.3])
+    E0 = to_dev(W.random_vector(G.n_e, 3, 90) * 0.1)
+    H0 = to_dev(W.random_vector(G.n_h, 3, 91) * 0.1)
+    Ee, He = E0.clone(), H0.clone()
+    ref = []
+    t = 0.0
+    for c in range(3):
+        # the start times the graph's device clock reaches (sums of K dt)
+        G.step(Ee, He, dt, nsteps=K_, t_start=t)
+        t += K_ * dt
+        ref.append((to_host(Ee), to_host(He)))
+    Eg, Hg = E0.clone(), H0.clone()
+    gr = G.graph(Eg, Hg, dt, K_)
+    G.set_time(0.0)
+    for c in range(3):
+        gr.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(Eg), ref[c][0]) and np.array_equal(to_host(Hg), ref[c][1])
+    gr.close()
+
+
+def test_lifting_state_rules():
+    import torch
+    import paper_2302_04979_amd as K
+    p, N = 2, 3
+    S, G = _coax(p, N)
+    eb = G.lift_boundary(_face_data(p, N))
+    G.set_lifting(eb, [1.0], [math.pi], [0.0])
+    E = torch.zeros(2 * G.n_e, dtype=torch.float64, device="cuda")
+    H = torch.zeros(2 * G.n_h, dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KMXError) as ex:
+        G.step(E, H, 0.01, 1, flags=K.TRACK_DB)
+    assert ex.value.status == 1
+    with pytest.raises(K.KMXError) as ex:
+        G.step_split(E[:G.n_e], H[:G.n_h], 0.01, 1, 4)
+    assert ex.value.status == 7
+    # new materials remove the lifting: a zero state stays zero again
+    G.set_materials(eps=np.full(N ** 3, 2.0))
+    e, h = E[:G.n_e].clone(), H[:G.n_h].clone()
+    G.step(e, h, 0.01, 3)
+    assert float(e.abs().max()) == 0.0 and float(h.abs().max()) == 0.0
+    with pytest.raises(ValueError):
+        G.set_lifting(eb[:-1], [1.0], [1.0], [0.0])

@@ -1,0 +1,152 @@
+"""State rules of the C-ABI on the device: steps above the computed CFL limit
+are refused, materials cannot change under live graphs, the adjoint runs the
+operators its reverse sweep transposes whatever plan the space carries, and
+a failing forward step ends the adjoint with its status."""
+import numpy as np
+import pytest
+
+import workloads as W
+from _helpers import make_pair, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+UNSTABLE, STATE = 6, 7
+
+
+def test_steps_above_the_cfl_limit_are_refused():
+    import torch
+    import paper_2302_04979_amd as K
+    S, G = make_pair(2, 5, deformed=True)
+    E = torch.zeros(G.n_e, dtype=torch.float64, device="cuda")
+    H = torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+    G.step(E, H, 1.0, nsteps=1)  # no CFL computed yet: not checked
+    c = G.cfl(max_iter=500, tol=1e-8)
+    G.step(E, H, 0.99 * c, nsteps=1)
+    G.step(E, H, -0.99 * c, nsteps=1)
+    for dt in (1.01 * c, -1.01 * c):
+        with pytest.raises(K.KMXError) as ex:
+            G.step(E, H, dt, nsteps=1)
+        assert ex.value.status == UNSTABLE
+    with pytest.raises(K.KMXError) as ex:
+        G.graph(E, H, 1.01 * c, 2)
+    assert ex.value.status == UNSTABLE
+    # composed steps: the largest substep |c_j| dt counts (1.70 at order 4)
+    G.step_split(E, H, 0.5 * c, 1, 4)
+    with pytest.raises(K.KMXError) as ex:
+        G.step_split(E, H, 0.7 * c, 1, 4)
+    assert ex.value.status == UNSTABLE
+    # new materials forget the limit
+    G.set_materials(eps=np.full(125, 3.0))
+    G.step(E, H, 1.01 * c, nsteps=1)
+
+
+def test_scheme1_steps_above_its_cfl_limit_are_refused():
+    import torch
+    import paper_2302_04979_amd as K
+    S, G = make_pair(2, 4, deformed=True)
+    e = to_dev(W.random_vector(G.n_e, 1, 80))
+    h = torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+    c1 = G.cfl_scheme1(max_iter=500, tol=1e-8, cg_tol=1e-12)
+    G.step_scheme1(e, h, 0.9 * c1, 1, tol=1e-12)
+    with pytest.raises(K.KMXError) as ex:
+        G.step_scheme1(e, h, 1.1 * c1, 1, tol=1e-12)
+    assert ex.value.status == UNSTABLE
+    with pytest.raises(K.KMXError) as ex:
+        G.graph_scheme1(e, h, 1.1 * c1, 1, 5, 5)
+    assert ex.value.status == UNSTABLE
+
+
+def test_materials_cannot_change_under_live_graphs():
+    """A graph holds the material state it was captured with: set_materials
+    is refused until every graph of the space is destroyed; a graph may be
+    destroyed after its space."""
+    import torch
+    import paper_2302_04979_amd as K
+    S, G = make_pair(2, 4, deformed=True)
+    n3 = 4 ** 3
+    E = torch.zeros(G.n_e, dtype=torch.float64, device="cuda")
+    H = torch.zeros(G.n_h, dtype=torch.float64, device="cuda")
+    g1 = G.graph(E, H, 0.01, 2)
+    g2 = G.graph(E, H, 0.01, 3)
+    with pytest.raises(K.KMXError) as ex:
+        G.set_materials(eps=np.full(n3, 2.0))
+    assert ex.value.status == STATE
+    g1.close()
+    with pytest.raises(K.KMXError):
+        G.set_materials(eps=np.full(n3, 2.0))
+    g2.close()
+    G.set_materials(eps=np.full(n3, 2.0))
+    g3 = G.graph(E, H, 0.01, 1)
+    G.close()
+    g3.close()
+
+
+def test_scheme1_graph_sees_rebuilt_preconditioner_in_place():
+    """After a graph of the first scheme is destroyed and the materials
+    change, a new graph and the eager steps use the rebuilt preconditioner
+    (rebuilt in its old allocation) and agree with the oracle."""
+    import torch
+    from oracle.geometry import Map
+    from oracle.scheme1 import Scheme1
+    p, N, dt, nsteps = 2, 4, 0.02, 2
+    S, G = make_pair(p, N, deformed=True)
+    e0 = W.random_vector(G.n_e, 2, 81)
+    h0 = np.zeros(G.n_h)
+    e, h = to_dev(e0), to_dev(h0)
+    gr = G.graph_scheme1(e, h, dt, nsteps, 60, 40)
+    gr.launch()
+    torch.cuda.synchronize()
+    gr.close()
+    eps2 = W.eps_elements(N, 5)
+    G.set_materials(eps=eps2)
+    S2 = Scheme1(p, N, Map("sine", W.DEFORMED_AMPLITUDE), eps=eps2)
+    e, h = to_dev(e0), to_dev(h0)
+    gr = G.graph_scheme1(e, h, dt, nsteps, 80, 60)
+    gr.launch()
+    torch.cuda.synchronize()
+    gr.close()
+    e_o, h_o, _, _ = S2.step1(e0, h0, dt, nsteps)
+    assert rel(to_host(e), e_o) < 1e-10 and rel(to_host(h), h_o) < 1e-10
+
+
+def test_adjoint_runs_the_tiled_operators_under_a_separable_plan():
+    """A space tuned to the separable plan at uniform eps, then given
+    per-element eps by the misfit problem: the adjoint still returns the loss
+    and gradient of a space without that plan (bitwise), and the plan is kept."""
+    import torch
+    import paper_2302_04979_amd as K
+    p, N, nsteps, dt = 2, 5, 20, 0.01
+    dip = W.dipoles(1, seed=3, dt=dt)
+    dip["t0"], dip["sigma"] = np.array([6 * dt]), np.array([3 * dt])
+    probes = W.probes(4, seed=2)
+    data = torch.zeros(nsteps * 12, dtype=torch.float64, device="cuda")
+    eps = W.eps_elements(N, 0)
+    out = []
+    for plan in (None, K.PLAN_SEPARABLE):
+        G = K.Space(p, N)
+        if plan is not None:
+            G.set_plan(plan, 256)
+        prob = K.ProbeMisfitProblem(G, dip, probes, data, dt, nsteps, checkpoint_every=7)
+        data.copy_(prob.observe(eps * 0.5 + 1.0).reshape(-1))
+        L, g = prob.loss_and_grad(eps)
+        out.append((L, to_host(g)))
+        if plan is not None:
+            assert G.plan()[0] == plan
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
+    assert out[0][0] > 0
+
+
+def test_adjoint_reports_a_failing_forward_step():
+    """dt above the space's computed CFL limit: the forward step fails and the
+    adjoint returns its status instead of a loss and gradient."""
+    import torch
+    import paper_2302_04979_amd as K
+    p, N, nsteps = 2, 4, 5
+    G = K.Space(p, N)
+    c = G.cfl(max_iter=500, tol=1e-8)
+    pr = G.probes(W.probes(3, seed=1))
+    data = torch.zeros(nsteps * 9, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KMXError) as ex:
+        G.adjoint(pr, None, data, 1.5 * c, nsteps, 2, grad)
+    assert ex.value.status == UNSTABLE

@@ -67,3 +67,17 @@ def test_argument_errors_of_the_added_entry_points():
     assert L.kmx_step_split(None, None, None, d(0.1), 1, 4, 1, 0, None) == 1
     assert L.kmx_init_split(None, None, None, d(0.1), 3, 1, 0, None) == 1  # order 3 does not exist
     assert L.kmx_last_error().decode()
+
+
+def test_argument_errors_of_the_lifting_and_profiling_entry_points():
+    """The lifting and the profile selection refuse NULL or out-of-range
+    arguments before any device work."""
+    K, L = _lib()
+    d = ctypes.c_double
+    n = ctypes.c_int64()
+    assert L.kmx_sizes_full(None, ctypes.byref(n)) == 1
+    assert L.kmx_lift_boundary(None, None, None, None) == 1
+    assert L.kmx_set_lifting(None, 1, None, None, None, None) == 1
+    assert L.kmx_profile_select(None, 1) == 1
+    assert L.kmx_last_error().decode()
+
