@@ -454,6 +454,20 @@ kmx_status kmx_probe_eval(kmx_space* sp, const kmx_probes* pr, const double* e, 
 kmx_status kmx_probe_forward(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, double dt, int nsteps,
                              double* obs, void* stream);
 
+/* kmx_probe_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same steps and probe values, with the two working fields
+ * held in a fixed device array of the library (KMX_NOALLOC_FIELD_MAX doubles
+ * per field, 32 MiB per GPU, held until the process ends) instead of memory
+ * allocated per call.  Allocates nothing and does not synchronise (stream
+ * ordered; errors of the launches are reported, those of the kernels at the
+ * caller's next synchronisation).  KMX_E_ARG when n_e or n_h exceeds
+ * KMX_NOALLOC_FIELD_MAX.  All calls on one GPU share that array: calls that
+ * overlap on one GPU (e.g. on two streams) race. */
+#define KMX_NOALLOC_FIELD_MAX (1 << 21)
+kmx_status kmx_probe_forward_noalloc(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, double dt,
+                                     int nsteps, double* obs, void* stream);
+
 /* Loss L = 1/2 sum_n |P e^n - data_n|^2 over the run of kmx_probe_forward and
  * its gradient with respect to the per-element eps of the space (the eps set
  * by kmx_set_materials; create J after setting them: the tested dipole carries

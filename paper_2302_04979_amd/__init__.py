@@ -42,7 +42,7 @@ EXPORTS = (
     "kmx_graph_destroy", "kmx_set_time", "kmx_get_time", "kmx_last_error",
     "kmx_op_mass1", "kmx_solve_mass1", "kmx_half_step_scheme1", "kmx_step_scheme1", "kmx_cfl_scheme1",
     "kmx_init_split", "kmx_step_split", "kmx_project_E1", "kmx_graph_create_scheme1",
-    "kmx_profile_select", "kmx_sizes_full", "kmx_lift_boundary",
+    "kmx_probe_forward_noalloc", "kmx_profile_select", "kmx_sizes_full", "kmx_lift_boundary",
     "kmx_set_lifting",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
@@ -103,6 +103,7 @@ def load_library():
         "kmx_destroy_probes": ([vp], None),
         "kmx_probe_eval": ([vp, vp, vp, vp, vp], i),
         "kmx_probe_forward": ([vp, vp, vp, d, i, vp, vp], i),
+        "kmx_probe_forward_noalloc": ([vp, vp, vp, d, i, vp, vp], i),
         "kmx_adjoint": ([vp, vp, vp, vp, d, i, i, ctypes.POINTER(d), vp, vp], i),
         "kmx_set_plan": ([vp, i, i], i),
         "kmx_set_refinement": ([vp, i], i),
@@ -471,6 +472,11 @@ class Space:
     def probe_forward(self, pr: Probes, J: "Source | None", dt, nsteps, obs):
         _check(load_library().kmx_probe_forward(self._h, pr._h, None if J is None else J._h, float(dt), int(nsteps),
                                                 _dptr(obs, nsteps * 3 * pr.n, "obs"), _stream()))
+
+    def probe_forward_noalloc(self, pr: Probes, J: "Source | None", dt, nsteps, obs):
+        _check(load_library().kmx_probe_forward_noalloc(self._h, pr._h, None if J is None else J._h, float(dt),
+                                                        int(nsteps), _dptr(obs, nsteps * 3 * pr.n, "obs"),
+                                                        _stream()))
 
     def adjoint(self, pr: Probes, J: "Source | None", data, dt, nsteps, checkpoint_every, grad) -> float:
         loss = ctypes.c_double()

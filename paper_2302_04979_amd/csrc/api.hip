@@ -17,6 +17,12 @@
 
 using namespace kmx;
 
+// Working fields of kmx_probe_forward_noalloc (e, then h; KMX_NOALLOC_FIELD_MAX
+// doubles each) in a fixed device array: every GPU the library runs on holds
+// its own copy until the process ends.  Host code reaches it only through the
+// per-device address from hipGetSymbolAddress (scratch_ptr below).
+static __device__ __align__(256) double scratch[2 * KMX_NOALLOC_FIELD_MAX];
+
 namespace {
 
 thread_local std::string g_err;
@@ -31,6 +37,28 @@ kmx_status fail(kmx_status st, const std::string& msg) {
     return st;
 }
 
+// Device address of `scratch` per HIP device, resolved once per device by
+// the first kmx_create_space on it (that device current).
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;
+
+kmx_status resolve_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0) return fail(KMX_E_DEVICE, "bad device");
+    if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+    if (g_scratch_ptr[dev]) return KMX_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(KMX_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    return KMX_OK;
+}
+
+double* scratch_ptr(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return dev >= 0 && size_t(dev) < g_scratch_ptr.size() ? g_scratch_ptr[dev] : nullptr;
+}
 
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \
@@ -466,6 +494,8 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             if ((st = upload(&sp->d_gram, gb)) != KMX_OK) { kmx_destroy_space(sp); return st; }
             int dev = 0;
             HIP_TRY(hipGetDevice(&dev));
+            sp->device = dev;
+            if ((st = resolve_scratch(dev)) != KMX_OK) { kmx_destroy_space(sp); return st; }
             HIP_TRY(hipDeviceGetAttribute(&sp->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
             int ed[3][3], hd[3][3];
             int64_t o[3];
@@ -1091,6 +1121,31 @@ kmx_status kmx_probe_forward(kmx_space* sp, const kmx_probes* pr, const kmx_sour
     hipStreamSynchronize(s);
     hipFree(e);
     hipFree(h);
+    if (st != KMX_OK) return st;
+    CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_probe_forward_noalloc(kmx_space* sp, const kmx_probes* pr, const kmx_source* J, double dt,
+                                     int nsteps, double* obs, void* stream) {
+    if (!sp || !pr || !obs || nsteps < 1 || pr->sp != sp || (J && J->sp != sp)) return fail(KMX_E_ARG, "bad argument");
+    if (sp->n_e > KMX_NOALLOC_FIELD_MAX || sp->n_h > KMX_NOALLOC_FIELD_MAX)
+        return fail(KMX_E_ARG, "fields larger than KMX_NOALLOC_FIELD_MAX entries: use kmx_probe_forward");
+    double* base = scratch_ptr(sp->device);
+    if (!base) return fail(KMX_E_STATE, "the fixed working array of this device is not resolved");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const TiledPlanScope tiled(sp);
+    double* e = base;
+    double* h = base + KMX_NOALLOC_FIELD_MAX;
+    // the array keeps the previous call's values: start from zero fields
+    launch_fill(e, sp->n_e, 0.0, s);
+    launch_fill(h, sp->n_h, 0.0, s);
+    kmx_status st = KMX_OK;
+    for (int n = 0; n < nsteps && st == KMX_OK; ++n) {
+        st = kmx_step(sp, e, h, J, n * dt, dt, 1, 1, 0, nullptr, stream);
+        launch_csr(pr->d_rowptr, pr->d_col, pr->d_val, e, obs + int64_t(n) * 3 * pr->n, nullptr, 3 * pr->n, 1.0,
+                   0.0, s);
+    }
     if (st != KMX_OK) return st;
     CHECK_LAUNCH();
     return KMX_OK;

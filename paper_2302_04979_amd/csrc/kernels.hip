@@ -1802,6 +1802,15 @@ void launch_advance_time(double* t, double dt, hipStream_t s) {
     hipLaunchKernelGGL(advance_time_kernel, dim3(1), dim3(64), 0, s, t, dt);
 }
 
+__global__ void fill_kernel(double* x, int64_t n, double v) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+}
+
 void launch_axpby(const double* x, double* y, int64_t n, double ka, const double* sa, double kb, hipStream_t s) {
     hipLaunchKernelGGL(axpby_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, x, y, n, ka, sa, kb);
 }

@@ -260,7 +260,8 @@ int boundary_fit(const kmx_space* sp, const double* Eh_faces, double* eb_full, d
 // out += the lifting's contribution to one half step (mode 0: h, 1: e)
 void launch_lift(double* out, int64_t out_stride, const double* v, int64_t n, const LiftTerms& T, double t_base,
                  double t_step, const double* t_dev, double dt, int mode, int batch, hipStream_t s);
-
+// x[0..n) = v (a kernel, so that graph captures hold no memset node)
+void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 
 int mass_threads(int p);
 int64_t patch_size(int p, int space, int ntile, int64_t comp_off[3]);

@@ -112,6 +112,7 @@ struct kmx_space {
     int npad = 0, ntile = 0;           // padded element count and tiles per axis
     int max_batch = 1;
     int precision = 0;
+    int device = 0;                    // HIP device the space was created on
     int64_t n_e = 0, n_h = 0, n_qp = 0;
     kmx::Tables tb;
     kmx_map map{};

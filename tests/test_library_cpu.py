@@ -70,8 +70,8 @@ def test_argument_errors_of_the_added_entry_points():
 
 
 def test_argument_errors_of_the_lifting_and_profiling_entry_points():
-    """The lifting and the profile selection refuse NULL or out-of-range
-    arguments before any device work."""
+    """The lifting, the profile selection and the allocation-free probe run
+    refuse NULL or out-of-range arguments before any device work."""
     K, L = _lib()
     d = ctypes.c_double
     n = ctypes.c_int64()
@@ -79,5 +79,6 @@ def test_argument_errors_of_the_lifting_and_profiling_entry_points():
     assert L.kmx_lift_boundary(None, None, None, None) == 1
     assert L.kmx_set_lifting(None, 1, None, None, None, None) == 1
     assert L.kmx_profile_select(None, 1) == 1
+    assert L.kmx_probe_forward_noalloc(None, None, None, d(0.1), 1, None, None) == 1
     assert L.kmx_last_error().decode()
 
