@@ -527,7 +527,9 @@ def profile_run(K, W, torch, p, N, steps):
     """A short run for the profiler: a device copy of known size (512 MiB read,
     512 MiB written: the reference for the HBM byte counters), then `steps`
     steps of the metric workload's kernels from a seeded random state under
-    each of the three tiled plans, then two steps of the first scheme."""
+    each of the three tiled plans, then two steps of the first scheme, two
+    steps with mixed-precision solves, and 10 steps of the batched separable
+    plan (256 members, 24^3)."""
     import numpy as np
     n = 64 * 1024 * 1024  # doubles: 512 MiB
     src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -549,7 +551,23 @@ def profile_run(K, W, torch, p, N, steps):
     # two steps of the first scheme (1-form mass kernels, PCG)
     G.step_scheme1(E[:G.n_e], H[:G.n_h], 1e-3, 2, tol=1e-10)
     torch.cuda.synchronize()
-    return {"profile_run": {"copy_bytes_each_way": n * 8, "copies": 3, "steps": steps, "p": p, "N": N}}
+    del G
+    # two steps with mixed-precision solves (FP32 mode products + FP64 refinement)
+    Gm = K.Space(p, N, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE, precision=K.MIXED)
+    Gm.set_materials(eps=W.eps_elements(N, 0))
+    Gm.step(E, H, 1e-3, nsteps=2, flags=K.TRACK_DB, energy=en[:2])
+    torch.cuda.synchronize()
+    del Gm, E, H
+    # the batched separable plan: p=3, 24^3, 256 members, 10 steps
+    B, Nb = 256, 24
+    Gb = K.Space(p, Nb, max_batch=B)
+    Gb.set_plan(K.PLAN_SEPARABLE, 768)
+    Eb = torch.tensor(np.tile(W.random_vector(Gb.n_e, 0, 43), B), dtype=torch.float64, device="cuda")
+    Hb = torch.zeros(B * Gb.n_h, dtype=torch.float64, device="cuda")
+    Gb.step(Eb, Hb, 1e-3, nsteps=10, batch=B)
+    torch.cuda.synchronize()
+    return {"profile_run": {"copy_bytes_each_way": n * 8, "copies": 3, "steps": steps, "p": p, "N": N,
+                            "mixed_steps": 2, "batched": {"members": B, "N": Nb, "steps": 10}}}
 
 
 def batched_timing(K, W, torch, steps=400):

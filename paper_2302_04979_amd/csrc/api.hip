@@ -102,20 +102,28 @@ void fill_fac(const kmx_space* sp, const double** fac, int64_t fac_off[8]) {
 enum { PK_MASS_B = 0, PK_MASS_D = 1, PK_XY = 2, PK_Z = 3, PK_CURL = 4, PK_ENERGY = 5, PK_GATHER = 6, PK_SEP = 7,
        PK_MODE = 8, PK_DENSE = 9, PK_MASS_1 = 10, PK_VEC = 11 };
 
-struct ProfScope {  // brackets one launch with events when profiling is on
+// Brackets one launch with events when profiling is on.  `by_launch`: the
+// launcher takes the two events (start(), stop()) and hands them to
+// hipExtLaunchKernelGGL, which stamps them when the kernel itself starts and
+// ends, instead of recording them around the launch.
+struct ProfScope {
     kmx_space* sp;
     hipStream_t s;
     int slot = -1;
-    ProfScope(kmx_space* sp_, hipStream_t s_, int kind) : sp(sp_), s(s_) {
+    bool by_launch;
+    ProfScope(kmx_space* sp_, hipStream_t s_, int kind, bool by_launch_ = false)
+        : sp(sp_), s(s_), by_launch(by_launch_) {
         if (sp->prof_on && ((sp->prof_mask >> kind) & 1u) && sp->prof_used + 2 <= int(sp->prof_ev.size())) {
             slot = sp->prof_used;
             sp->prof_used += 2;
             sp->prof_kind[slot / 2] = kind;
-            (void)hipEventRecord(sp->prof_ev[slot], s);
+            if (!by_launch) (void)hipEventRecord(sp->prof_ev[slot], s);
         }
     }
+    hipEvent_t start() const { return slot >= 0 ? sp->prof_ev[slot] : nullptr; }
+    hipEvent_t stop() const { return slot >= 0 ? sp->prof_ev[slot + 1] : nullptr; }
     ~ProfScope() {
-        if (slot >= 0) (void)hipEventRecord(sp->prof_ev[slot + 1], s);
+        if (slot >= 0 && !by_launch) (void)hipEventRecord(sp->prof_ev[slot + 1], s);
     }
 };
 
@@ -149,7 +157,9 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
     space_dims(sp, src_space, a.src_dims, a.src_comp_off);
     patch_size(sp->p, space, sp->ntile, a.patch_comp_off);
     a.waves4 = sp->mass_waves4;
-    ProfScope ps(sp, s, space == SP_B ? PK_MASS_B : space == SP_D ? PK_MASS_D : PK_MASS_1);
+    ProfScope ps(sp, s, space == SP_B ? PK_MASS_B : space == SP_D ? PK_MASS_D : PK_MASS_1, true);
+    a.prof_start = ps.start();
+    a.prof_stop = ps.stop();
     launch_mass(sp->p, space, curl, a, batch, s);
 }
 

@@ -1,6 +1,7 @@
 // HIP kernels (gfx950) of the scheme-2 leapfrog: fused curl + sum-factorised
 // 2-form mass apply, Kronecker pairing solves one axis at a time, curls,
 // pairing applies and FP64 deterministic reductions.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -197,28 +198,25 @@ __device__ inline int owner_tile(int g, int nt) {
 // The entries of the y column (lx, ., lz) of a component window that this tile
 // owns: their offsets in the tracked component (-1 where not owned) and their
 // current values, requested at the start of the tile so that the update in
-// the y pass does not wait for them.
+// the y pass does not wait for them.  Branch-free (a lane that owns nothing
+// reads index 0 and keeps -1): nested early exits would make the compiler
+// rebuild the two arrays' initial values at every exit.
 template <class L, int NY>
 __device__ inline void track_column_load(const double* __restrict__ tr, const int dims[3], int tx, int ty, int tz,
                                          int nt, int lane, int (&k)[NY], double (&v)[NY]) {
-#pragma unroll
-    for (int ly = 0; ly < NY; ++ly) {
-        k[ly] = -1;
-        v[ly] = 0.0;
-    }
-    if (lane >= L::Wz * L::Wx) return;
     const int lz = lane / L::Wx, lx = lane - lz * L::Wx;
     const int gx = tx * TILE + tag_offset(L::tx) + lx;
     const int gz = tz * TILE + tag_offset(L::tz) + lz;
-    if (gx < 0 || gx >= dims[2] || gz < 0 || gz >= dims[0]) return;
-    if (owner_tile<L::tx>(gx, nt) != tx || owner_tile<L::tz>(gz, nt) != tz) return;
+    const bool ok = lane < L::Wz * L::Wx && gx >= 0 && gx < dims[2] && gz >= 0 && gz < dims[0] &&
+                    owner_tile<L::tx>(gx, nt) == tx && owner_tile<L::tz>(gz, nt) == tz;
 #pragma unroll
-    for (int ly = 0; ly < L::Wy; ++ly) {
+    for (int ly = 0; ly < NY; ++ly) {
         const int gy = ty * TILE + tag_offset(L::ty) + ly;
-        if (gy >= 0 && gy < dims[1] && owner_tile<L::ty>(gy, nt) == ty) {
-            k[ly] = (gz * dims[1] + gy) * dims[2] + gx;
-            v[ly] = tr[k[ly]];
-        }
+        const bool own = ok && ly < L::Wy && gy >= 0 && gy < dims[1] && owner_tile<L::ty>(gy, nt) == ty;
+        const int off = own ? (gz * dims[1] + gy) * dims[2] + gx : 0;
+        const double t = tr[off];
+        k[ly] = own ? off : -1;
+        v[ly] = own ? t : 0.0;
     }
 }
 
@@ -430,8 +428,11 @@ __device__ inline void integrate_y_col(const double* xi, double* __restrict__ ou
 #pragma unroll
         for (int j = 0; j < L::Ky; ++j) o[le + j] = fma(tyt[q * L::Ky + j], c[q], o[le + j]);
     }
+    // consecutive ly are nt * Wx apart in the patch
+    double* dst = out + patch_at<L>(nt, tx, ty, tz, lx, 0, cz);
+    const int pitch = nt * L::Wx;
 #pragma unroll
-    for (int ly = 0; ly < L::Wy; ++ly) out[patch_at<L>(nt, tx, ty, tz, lx, ly, cz)] = o[ly];
+    for (int ly = 0; ly < L::Wy; ++ly) dst[ly * pitch] = o[ly];
 }
 
 // MET = 0: the metric w_q DF^T DF / det DF is streamed from memory (any map);
@@ -751,18 +752,28 @@ mass_kernel(const MassArgs A, const double* __restrict__ tabg, const double* __r
                                    lane, nt, tx, ty, tz);
 }
 
+// One launch of a mass kernel; with profiling events, through
+// hipExtLaunchKernelGGL, which stamps them with the kernel's own start and
+// end (profiling runs are never captured into graphs)
+template <class K>
+static void launch_mass_k(K kernel, const MassArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    if (a.prof_start && a.prof_stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a.prof_start, a.prof_stop, 0, a, a.tab, a.axis_tab);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, a, a.tab, a.axis_tab);
+}
+
 template <int P, int SPACE, bool CURL>
 static void launch_mass_t(const MassArgs& a, dim3 grid, hipStream_t s) {
     // the four-wave variant exists for p <= 3 (p = 4 would spill)
     const bool w4 = a.waves4 && P <= 3;
+    const dim3 block(MassCfg<P>::NT);
     if (a.metric_mode == 1) {
-        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a,
-                                   a.tab, a.axis_tab);
-        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 1, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a, a.tab, a.axis_tab);
+        if (w4) launch_mass_k(mass_kernel<P, SPACE, CURL, 1, (P <= 3 ? 4 : 1)>, a, grid, block, s);
+        else launch_mass_k(mass_kernel<P, SPACE, CURL, 1, 1>, a, grid, block, s);
     } else {
-        if (w4) hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, (P <= 3 ? 4 : 1)>), grid, dim3(MassCfg<P>::NT), 0, s, a,
-                                   a.tab, a.axis_tab);
-        else hipLaunchKernelGGL((mass_kernel<P, SPACE, CURL, 0, 1>), grid, dim3(MassCfg<P>::NT), 0, s, a, a.tab, a.axis_tab);
+        if (w4) launch_mass_k(mass_kernel<P, SPACE, CURL, 0, (P <= 3 ? 4 : 1)>, a, grid, block, s);
+        else launch_mass_k(mass_kernel<P, SPACE, CURL, 0, 1>, a, grid, block, s);
     }
 }
 

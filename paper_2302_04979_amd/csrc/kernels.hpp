@@ -15,6 +15,8 @@ struct MassArgs {
     const double* metric;       // w_q DF^T DF / det DF, tile layout (metric_mode 0)
     int metric_mode;            // 0 stored metric, 1 recomputed for the sine map
     int waves4;                 // 1: the variant compiled for four waves per SIMD (p <= 3)
+    hipEvent_t prof_start;      // profiling: stamped when the kernel starts / ends, or nullptr
+    hipEvent_t prof_stop;
     double amp;                 // map amplitude a (metric_mode 1)
     const double* axis_tab;     // [sin | cos | weight] at the npad*nq Gauss points of an axis
     const double* inv_gamma;    // [npad^3] per-element 1/eps or 1/mu, or nullptr

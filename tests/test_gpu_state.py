@@ -150,3 +150,34 @@ def test_adjoint_reports_a_failing_forward_step():
     with pytest.raises(K.KMXError) as ex:
         G.adjoint(pr, None, data, 1.5 * c, nsteps, 2, grad)
     assert ex.value.status == UNSTABLE
+
+
+def test_profiled_mass_launches_are_timed_by_the_kernels():
+    """Profiling a step: the mass applies are timed by events that the launch
+    stamps with the kernel's own start and end (one pair per launch, two
+    launches per step), the other kinds by events around their launches; a
+    selection leaves the rest untimed; the profiled steps give the same fields
+    as unprofiled ones."""
+    import torch
+    import paper_2302_04979_amd as K
+    p, N, nsteps, dt = 3, 9, 4, 0.01
+    S, G = make_pair(p, N, deformed=True)
+    e0 = to_dev(W.random_vector(S.n_e, 7, 1))
+    h0 = to_dev(W.random_vector(S.n_h, 7, 2))
+    e, h = e0.clone(), h0.clone()
+    G.step(e, h, dt, nsteps=nsteps)
+    ep, hp = e0.clone(), h0.clone()
+    G.profile_begin(capacity=256)
+    G.step(ep, hp, dt, nsteps=nsteps)
+    prof = G.profile_end()
+    assert torch.equal(ep, e) and torch.equal(hp, h)
+    for kind in ("mass_B", "mass_D"):
+        ms, n = prof[kind]
+        assert n == nsteps and ms > 0.0
+    assert prof["solve_xy"][1] > 0 or prof["dense_fp64"][1] > 0
+    G.profile_begin(capacity=256)
+    G.profile_select(["mass_B"])
+    G.step(ep, hp, dt, nsteps=nsteps)
+    prof = G.profile_end()
+    assert prof["mass_B"][1] == nsteps and prof["mass_B"][0] > 0.0
+    assert all(n == 0 for k, (ms, n) in prof.items() if k != "mass_B")
