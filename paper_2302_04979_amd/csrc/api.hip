@@ -167,10 +167,13 @@ void run_mass(kmx_space* sp, int space, bool curl, const double* src, int64_t sr
 // (from_patch) or read from `in`; op = K^{-1} (solve = 1), K (solve = 2, the
 // banded pairing apply) or the identity (solve = 0, plain gather of the mass
 // output).
+// acc (optional, with from_patch): acc += acc_alpha * (the gathered field),
+// acc with the layout of `out` and member stride acc_stride.
 void run_solve(kmx_space* sp, int which_K1, int transpose, int from_patch, int gather_space, const double* in,
                int64_t in_stride, double* out, int64_t out_stride, double alpha, int accumulate, int batch,
                const kmx_source* J, double t_src, int solve, hipStream_t s, const int* fac_override = nullptr,
-               const double* t_dev = nullptr) {
+               const double* t_dev = nullptr, double* acc = nullptr, int64_t acc_stride = 0,
+               double acc_alpha = 0.0) {
     const int64_t nfield = std::max(sp->n_e, sp->n_h);
     const int layout = which_K1 ? SP_D : SP_B;  // dims of K1 (= e, d) or K~1 (= h, b) vectors
     if (from_patch) {
@@ -184,6 +187,9 @@ void run_solve(kmx_space* sp, int which_K1, int transpose, int from_patch, int g
         const bool direct = solve == 0 && !accumulate && alpha == 1.0 && !J;
         g.out = direct ? out : sp->d_tmp2;
         g.out_stride = direct ? out_stride : nfield;
+        g.acc = acc;
+        g.acc_stride = acc_stride;
+        g.acc_alpha = acc_alpha;
         {
             ProfScope ps(sp, s, PK_GATHER);
             launch_gather(sp->p, gather_space == SP_B ? SP_B : SP_D, g, which_K1 ? sp->n_e : sp->n_h, batch, s);
@@ -292,6 +298,25 @@ void run_energy(kmx_space* sp, const double* E, const double* H, double dt, int 
     a.partial = sp->d_red;
     launch_energy_fused(sp->p, a, batch, s);
     launch_energy_final(sp->d_red, a.nb[0] + a.nb[1], dt, batch, out, out_stride, s);
+}
+
+// Per-step energy of tracked states from the kept images w_e = K1 e and
+// w_h = K~1 h (updated by the substeps) and the fields themselves.
+void run_energy_dots(kmx_space* sp, const double* E, const double* H, double dt, int batch, double* out,
+                     hipStream_t s) {
+    ProfScope ps(sp, s, PK_ENERGY);
+    EnergyDotsArgs a{};
+    a.E = E;
+    a.H = H;
+    a.we = sp->d_we;
+    a.wh = sp->d_wh;
+    a.n_e = sp->n_e;
+    a.n_h = sp->n_h;
+    space_dims(sp, SP_E, a.e_dims, a.e_comp_off);
+    space_dims(sp, SP_B, a.h_dims, a.h_comp_off);
+    a.partial = sp->d_red;
+    launch_energy_dots(a, batch, s);
+    launch_energy_final(sp->d_red, ENERGY_DOT_BLOCKS, dt, batch, out, 1, s);
 }
 
 // The forward model of the probe misfit and its adjoint run the tiled plan,
@@ -603,6 +628,8 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
         if (hipMalloc(&sp->d_patch, size_t(sp->patch_per_field) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_tmp, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_tmp2, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_we, size_t(sp->n_e) * max_batch * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sp->d_wh, size_t(sp->n_h) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_red, size_t(sp->red_len) * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_scal, size_t(64 + 2 * max_batch) * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_time, sizeof(double)) != hipSuccess) {
@@ -683,7 +710,7 @@ void kmx_destroy_space(kmx_space* sp) {
     if (sp->capture_stream) (void)hipStreamDestroy(sp->capture_stream);
     if (sp->d_time) (void)hipFree(sp->d_time);
     double* bufs[] = {sp->d_tab, sp->d_metric, sp->d_axis_tab, sp->d_inv_eps, sp->d_inv_mu, sp->d_fac,
-                      sp->d_gram, sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_red, sp->d_scal};
+                      sp->d_gram, sp->d_patch, sp->d_tmp, sp->d_tmp2, sp->d_we, sp->d_wh, sp->d_red, sp->d_scal};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     void* more[] = {sp->d_inv32, sp->d_mx, sp->d_mr, sp->d_my, sp->d_m32a, sp->d_m32b, sp->d_frag64,
@@ -1439,20 +1466,27 @@ kmx_status run_sep(kmx_space* sp, double* E, double* H, const kmx_source* J, dou
 // the leapfrog step with ka = kb = dt, a substep of a composition otherwise.
 // t_base + t_step (or *t_dev + t_step under graph replay) is the time at the
 // start of the substep, the lifting's t_n; t_half the source time.
+// keep_w: also update the kept images K~1 h (d_wh) and K1 e (d_we) of the
+// per-step energy with the gathered mass applies.
 static void tiled_substep(kmx_space* sp, double* E, double* H, int64_t es, int64_t hs, double ka, double kb, int batch,
                    int track, bool dense, bool mixed, const kmx_source* J, double t_half, const double* t_dev,
-                   hipStream_t s, double t_base = 0.0, double t_step = 0.0) {
+                   hipStream_t s, double t_base = 0.0, double t_step = 0.0, bool keep_w = false) {
     const int64_t nf = std::max(sp->n_e, sp->n_h);
+    double* wh = keep_w ? sp->d_wh : nullptr;
+    double* we = keep_w ? sp->d_we : nullptr;
     // M D^1 e (and b -= ka D^1 e), then h -= ka K~1^{-1} (.)
     run_mass(sp, SP_B, true, E, es, batch, s, track ? H + sp->n_h : nullptr, hs, -ka);
     if (dense && !mixed) {
-        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s, nullptr, nullptr,
+                  wh, sp->n_h, -ka);
         dense_solve(sp, 0, sp->d_tmp2, H, hs, -ka, batch, nullptr, 0.0, nullptr, s);
     } else if (mixed) {
-        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, nullptr, 0.0, 0, s, nullptr, nullptr, wh,
+                  sp->n_h, -ka);
         mixed_solve(sp, 0, 0, sp->d_my, H, hs, -ka, 1, batch, s);
     } else {
-        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -ka, 1, batch, nullptr, 0.0, 1, s);
+        run_solve(sp, 0, 0, 1, SP_B, nullptr, 0, H, hs, -ka, 1, batch, nullptr, 0.0, 1, s, nullptr, nullptr, wh, sp->n_h,
+                  -ka);
     }
     // the lifting: h -= ka sum_j g_j(t_n) v_h^j (t_n = t_half - ka / 2)
     if (sp->lift_n)
@@ -1460,13 +1494,15 @@ static void tiled_substep(kmx_space* sp, double* E, double* H, int64_t es, int64
     // M~ D~^1 h (and d += kb D~^1 h), then e += kb K1^{-1} (. - s)
     run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, kb);
     if (dense && !mixed) {
-        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s, nullptr, nullptr,
+                  we, sp->n_e, kb);
         dense_solve(sp, 1, sp->d_tmp2, E, es, kb, batch, J, t_half, t_dev, s);
     } else if (mixed) {
-        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev);
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev, we,
+                  sp->n_e, kb);
         mixed_solve(sp, 1, 0, sp->d_my, E, es, kb, 1, batch, s);
     } else {
-        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, kb, 1, batch, J, t_half, 1, s, nullptr, t_dev);
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, kb, 1, batch, J, t_half, 1, s, nullptr, t_dev, we, sp->n_e, kb);
     }
     // the lifting: e -= sum_j (g_j(t_n + kb) - g_j(t_n)) v_e^j
     if (sp->lift_n)
@@ -1504,11 +1540,17 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     const bool mixed = sp->precision == KMX_MIXED;
     const bool dense = kind == KMX_PLAN_TILED_DENSE;
     sp->mass_waves4 = kind == KMX_PLAN_TILED_W4 ? 1 : 0;
+    // per-step energy: the images K1 e and K~1 h of the call's first state,
+    // then kept up to date by the substeps with the mass applies they gather
+    if (energy_dev && nsteps > 0) {
+        run_solve(sp, 1, 0, 0, SP_D, E, es, sp->d_we, sp->n_e, 1.0, 0, batch, nullptr, 0.0, 2, s);
+        run_solve(sp, 0, 0, 0, SP_B, H, hs, sp->d_wh, sp->n_h, 1.0, 0, batch, nullptr, 0.0, 2, s);
+    }
     for (int n = 0; n < nsteps; ++n) {
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
         tiled_substep(sp, E, H, es, hs, dt, dt, batch, track, dense, mixed, J, t_half, t_dev, s, t_dev ? 0.0 : t_start,
-                      n * dt);
-        if (energy_dev) run_energy(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, 1, s);
+                      n * dt, energy_dev != nullptr);
+        if (energy_dev) run_energy_dots(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, s);
     }
     if (t_dev) launch_advance_time(const_cast<double*>(t_dev), nsteps * dt, s);
     CHECK_LAUNCH();

@@ -840,6 +840,10 @@ __global__ void __launch_bounds__(256) gather_kernel(const GatherArgs A, int64_t
     else if (c == 1) v = gather_one<P, SPACE, 1>(patch, A.ntile, z, y, x);
     else v = gather_one<P, SPACE, 2>(patch, A.ntile, z, y, x);
     A.out[int64_t(b) * A.out_stride + i] = v;
+    if (A.acc) {
+        double* w = A.acc + int64_t(b) * A.acc_stride + i;
+        *w = fma(A.acc_alpha, v, *w);
+    }
 }
 
 void launch_gather(int p, int space, const GatherArgs& a, int64_t n, int batch, hipStream_t s) {
@@ -1463,6 +1467,50 @@ int energy_fused_blocks(const int dims[3][3], int cb[3]) {
         tot += cb[c];
     }
     return tot;
+}
+
+// Energy terms from the kept images w_e = K1 e and w_h = K~1 h (the step
+// updates them with the gathered mass applies: K~1 h^{n+1/2} = K~1 h^{n-1/2}
+// - dt M D^1 e^n and K1 e^{n+1} = K1 e^n + dt M~ D~^1 h^{n+1/2}, the Hodge
+// relations of eqs. (3.11) and (3.13) applied to the increments): per block
+// the partial sums of d . w_e, b . w_h and w_h . D^1 e, in a fixed order
+// (grid-stride loops over a fixed grid, then block_sum3).
+__global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A) {
+    const int bm = blockIdx.y;
+    const double* E = A.E + int64_t(bm) * 2 * A.n_e;
+    const double* H = A.H + int64_t(bm) * 2 * A.n_h;
+    const double* we = A.we + int64_t(bm) * A.n_e;
+    const double* wh = A.wh + int64_t(bm) * A.n_h;
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_e; i += stride) s0 = fma(E[A.n_e + i], we[i], s0);
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_h; i += stride) {
+        const double w = wh[i];
+        s1 = fma(H[A.n_h + i], w, s1);
+        // D^1 e at entry i of the 2-form: component c = d_{c+1} e_{c+2} - d_{c+2} e_{c+1}
+        const int c = i >= A.h_comp_off[2] ? 2 : (i >= A.h_comp_off[1] ? 1 : 0);
+        const int li = int(i - A.h_comp_off[c]);
+        const int nx = A.h_dims[c][2], ny = A.h_dims[c][1];
+        int x, y;
+        const int row = fast_divmod(li, nx, x);
+        const int z = fast_divmod(row, ny, y);
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        const double de = diff1_primal(E + A.e_comp_off[a2], A.e_dims[a2], a1, z, y, x) -
+                          diff1_primal(E + A.e_comp_off[a1], A.e_dims[a1], a2, z, y, x);
+        s2 = fma(w, de, s2);
+    }
+    __shared__ double r[3];
+    block_sum3<256>(s0, s1, s2, r);
+    if (threadIdx.x == 0) {
+        double* o = A.partial + (int64_t(bm) * gridDim.x + blockIdx.x) * 3;
+        o[0] = r[0];
+        o[1] = r[1];
+        o[2] = r[2];
+    }
+}
+
+void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(energy_dots_kernel, dim3(ENERGY_DOT_BLOCKS, batch), dim3(256), 0, s, a);
 }
 
 __global__ void __launch_bounds__(256) energy_final_kernel(const double* partial, int nblocks, double dt,

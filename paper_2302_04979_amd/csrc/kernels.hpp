@@ -45,6 +45,10 @@ struct GatherArgs {
     int64_t comp_off[3];
     int dims[3][3];
     int ntile;
+    // optional: acc += acc_alpha * (the gathered field), same layout
+    double* acc;
+    int64_t acc_stride;
+    double acc_alpha;
 };
 
 // Read a field, subtract point sources, solve (or apply) along x and y.
@@ -108,6 +112,19 @@ struct EnergyFusedArgs {
     int nb[2];                  // blocks of the first term and of the other two
     int cb[2][3];               // blocks per component
     double* partial;            // [batch][nb0 + nb1][3]
+};
+
+// Energy terms of tracked states from the images w_e = K1 e and w_h = K~1 h
+// that the step keeps: per block d . w_e, b . w_h and w_h . D^1 e.
+struct EnergyDotsArgs {
+    const double* E;            // [e | d] per batch member
+    const double* H;            // [h | b]
+    const double* we;           // K1 e per member (stride n_e)
+    const double* wh;           // K~1 h per member (stride n_h)
+    int64_t n_e, n_h;
+    int64_t e_comp_off[3], h_comp_off[3];
+    int e_dims[3][3], h_dims[3][3];
+    double* partial;            // [batch][gridDim.x][3]
 };
 
 struct PairGradArgs {           // per-element metric pairing of lam and D~^1 h
@@ -222,6 +239,8 @@ void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s);
 void launch_z(int p, const ZArgs& a, int batch, hipStream_t s);
 void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
 void launch_energy_fused(int p, const EnergyFusedArgs& a, int batch, hipStream_t s);
+constexpr int ENERGY_DOT_BLOCKS = 1024;  // blocks per member of the dot kernel
+void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s);
 int energy_fused_blocks(const int dims[3][3], int cb[3]);
 // out[b*out_stride] (+ step offset) from the energy partials
 void launch_energy_final(const double* partial, int nblocks, double dt, int batch, double* out,

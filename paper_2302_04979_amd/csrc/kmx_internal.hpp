@@ -132,6 +132,8 @@ struct kmx_space {
     int64_t patch_per_field = 0;
     double* d_tmp = nullptr;           // field-sized scratch [max_batch][max(n_e,n_h)]
     double* d_tmp2 = nullptr;          // second field-sized scratch
+    double* d_we = nullptr;            // per-step energy: K1 e per member [max_batch][n_e]
+    double* d_wh = nullptr;            // per-step energy: K~1 h per member [max_batch][n_h]
     double* d_red = nullptr;           // reduction partials
     int64_t red_len = 0;
     double* d_scal = nullptr;          // small device scalars
