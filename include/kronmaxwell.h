@@ -179,7 +179,11 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
  * state is advanced by nsteps.  J: NULL or a source of this space (not allowed
  * together with KMX_TRACK_DB).  energy_dev: NULL, or device array of
  * nsteps * batch doubles receiving the leapfrog invariant after every step
- * (requires KMX_TRACK_DB).  Never allocates and never synchronises.
+ * (requires KMX_TRACK_DB), evaluated as 1/2 (d.w_e + b.w_h - dt w_h.D^1 e)
+ * with w_e = K1 e and w_h = K~1 h formed once per call (one banded pairing
+ * apply each) and then updated with the mass applies of the steps (eqs.
+ * (3.11), (3.13) on the increments); it equals kmx_energy's first value to
+ * rounding.  Never allocates and never synchronises.
  * KMX_E_UNSTABLE when |dt| exceeds the last kmx_cfl result of the space. */
 kmx_status kmx_step(kmx_space* sp, double* E, double* H, const kmx_source* J, double t_start,
                     double dt, int nsteps, int batch, int flags, double* energy_dev, void* stream);

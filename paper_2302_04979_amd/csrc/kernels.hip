@@ -1482,22 +1482,50 @@ __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A
     const double* we = A.we + int64_t(bm) * A.n_e;
     const double* wh = A.wh + int64_t(bm) * A.n_h;
     const int64_t stride = int64_t(gridDim.x) * 256;
+    const int64_t i0 = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    // U entries per thread and round, all loads requested before the sums
+    constexpr int U = 4;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_e; i += stride) s0 = fma(E[A.n_e + i], we[i], s0);
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < A.n_h; i += stride) {
-        const double w = wh[i];
-        s1 = fma(H[A.n_h + i], w, s1);
-        // D^1 e at entry i of the 2-form: component c = d_{c+1} e_{c+2} - d_{c+2} e_{c+1}
-        const int c = i >= A.h_comp_off[2] ? 2 : (i >= A.h_comp_off[1] ? 1 : 0);
-        const int li = int(i - A.h_comp_off[c]);
-        const int nx = A.h_dims[c][2], ny = A.h_dims[c][1];
-        int x, y;
-        const int row = fast_divmod(li, nx, x);
-        const int z = fast_divmod(row, ny, y);
-        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-        const double de = diff1_primal(E + A.e_comp_off[a2], A.e_dims[a2], a1, z, y, x) -
-                          diff1_primal(E + A.e_comp_off[a1], A.e_dims[a1], a2, z, y, x);
-        s2 = fma(w, de, s2);
+    for (int64_t ib = i0; ib < A.n_e; ib += U * stride) {
+        double dv[U], wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = ib + u * stride;
+            const bool ok = i < A.n_e;
+            const double a = E[A.n_e + (ok ? i : 0)], b = we[ok ? i : 0];
+            dv[u] = ok ? a : 0.0;
+            wv[u] = ok ? b : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) s0 = fma(dv[u], wv[u], s0);
+    }
+    for (int64_t ib = i0; ib < A.n_h; ib += U * stride) {
+        double wv[U], bv[U], de[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = ib + u * stride;
+            const bool ok = i < A.n_h;
+            const int64_t j = ok ? i : 0;
+            const double w = wh[j], bb = H[A.n_h + j];
+            // D^1 e at entry j of the 2-form: component c = d_{c+1} e_{c+2} - d_{c+2} e_{c+1}
+            const int c = j >= A.h_comp_off[2] ? 2 : (j >= A.h_comp_off[1] ? 1 : 0);
+            const int li = int(j - A.h_comp_off[c]);
+            const int nx = A.h_dims[c][2], ny = A.h_dims[c][1];
+            int x, y;
+            const int row = fast_divmod(li, nx, x);
+            const int z = fast_divmod(row, ny, y);
+            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+            const double d = diff1_primal(E + A.e_comp_off[a2], A.e_dims[a2], a1, z, y, x) -
+                             diff1_primal(E + A.e_comp_off[a1], A.e_dims[a1], a2, z, y, x);
+            wv[u] = ok ? w : 0.0;
+            bv[u] = ok ? bb : 0.0;
+            de[u] = ok ? d : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s1 = fma(bv[u], wv[u], s1);
+            s2 = fma(wv[u], de[u], s2);
+        }
     }
     __shared__ double r[3];
     block_sum3<256>(s0, s1, s2, r);
