@@ -24,10 +24,17 @@ struct Lay {  // window layout of component C of a form space inside one tile
 
 // Patch layout of one component: [tz][ty][lz][ly][tx][lx], the x rows of the
 // tiles along x side by side, so that a row of outputs gathers from
-// contiguous memory.
+// contiguous memory.  One component's patches hold nt^3 Wx Wy Wz entries
+// (N <= 72 elements per axis: nt <= 18, windows <= 8 per axis), far below
+// 2^31, so offsets inside a component are 32-bit.
+template <class L>
+__host__ __device__ inline int patch_row(int nt, int ty, int tz, int ly, int lz) {
+    return (((tz * nt + ty) * L::Wz + lz) * L::Wy + ly) * nt * L::Wx;
+}
+
 template <class L>
 __host__ __device__ inline int64_t patch_at(int nt, int tx, int ty, int tz, int lx, int ly, int lz) {
-    return ((((int64_t(tz) * nt + ty) * L::Wz + lz) * L::Wy + ly) * nt + tx) * L::Wx + lx;
+    return patch_row<L>(nt, ty, tz, ly, lz) + tx * L::Wx + lx;
 }
 
 // Patch gather: the sum of the tile patches covering basis function (gx, gy,
@@ -58,12 +65,15 @@ __device__ inline double gather_one(const double* __restrict__ patch, int nt, in
         ly[d] = vy[d] ? ry - ty[d] * TILE : 0;
         lz[d] = vz[d] ? rz - tz[d] * TILE : 0;
     }
+    // the four (z, y) row offsets and the two x offsets, then the eight reads
+    int row[4], col[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) row[k] = patch_row<L>(nt, ty[k & 1], tz[k >> 1], ly[k & 1], lz[k >> 1]);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) col[d] = tx[d] * L::Wx + lx[d];
     double v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int dz = k >> 2, dy = (k >> 1) & 1, dx = k & 1;
-        v[k] = patch[patch_at<L>(nt, tx[dx], ty[dy], tz[dz], lx[dx], ly[dy], lz[dz])];
-    }
+    for (int k = 0; k < 8; ++k) v[k] = patch[row[k >> 1] + col[k & 1]];
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
