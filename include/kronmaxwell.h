@@ -168,6 +168,21 @@ kmx_status kmx_create_source(kmx_space* sp, int n, const double* pos, const doub
                              const int* batch_of, kmx_source** out);
 void kmx_destroy_source(kmx_source* src);
 
+/* The other source form: s(t) = g(t) P, a dense time-independent pattern P
+ * in the dual 2-form space X~^2 (the tested source vector itself, n_e entries
+ * in the layout of d) times a sampled time series g.  pattern (host): npat x
+ * n_e doubles, npat = 1 (every batch member) or one pattern per member
+ * (steps then need batch <= npat).  series (host): nsamples >= 2 values at
+ * t0 + k dt_sample; g(t) is their linear interpolation, zero outside
+ * [t0, t0 + (nsamples - 1) dt_sample].  The step subtracts s(t_{n+1/2}) from
+ * M~ D~^1 h before the K1 solve, as for point dipoles (Section 3.4).  The
+ * arrays are copied; the source keeps no host reference.  Runs with the
+ * tiled plans (a forced separable plan: KMX_E_STATE) and not in kmx_adjoint
+ * (KMX_E_STATE); KMX_E_ARG for non-finite data, npat outside 1..max_batch,
+ * fewer than two samples or dt_sample <= 0. */
+kmx_status kmx_create_source_pattern(kmx_space* sp, int npat, const double* pattern, int nsamples, double t0,
+                                     double dt_sample, const double* series, kmx_source** out);
+
 /* Backward half kick from t = 0 data: h <- h + dt/2 K~1^{-1} M D^1 e, and with
  * KMX_TRACK_DB also b <- b + dt/2 D^1 e.  E, H: device, batch members of
  * stride n_e*(1+track) and n_h*(1+track). */

@@ -34,6 +34,7 @@ PLAN_NAMES = {PLAN_AUTO: "auto", PLAN_TILED: "tiled", PLAN_SEPARABLE: "separable
 EXPORTS = (
     "kmx_create_space", "kmx_destroy_space", "kmx_set_materials", "kmx_sizes", "kmx_quad_points",
     "kmx_project_E", "kmx_project_D", "kmx_cfl", "kmx_create_source", "kmx_destroy_source",
+    "kmx_create_source_pattern",
     "kmx_init_stagger", "kmx_step", "kmx_energy", "kmx_op_curl", "kmx_op_mass", "kmx_op_solve",
     "kmx_op_pairing", "kmx_profile_begin", "kmx_profile_end", "kmx_create_probes", "kmx_destroy_probes",
     "kmx_probe_eval", "kmx_probe_forward", "kmx_adjoint", "kmx_set_plan", "kmx_get_plan", "kmx_tune",
@@ -88,6 +89,7 @@ def load_library():
         "kmx_project_D": ([vp, vp, vp, d, vp], i),
         "kmx_cfl": ([vp, i, d, ctypes.POINTER(d)], i),
         "kmx_create_source": ([vp, i, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)], i),
+        "kmx_create_source_pattern": ([vp, i, vp, i, d, d, vp, ctypes.POINTER(vp)], i),
         "kmx_destroy_source": ([vp], None),
         "kmx_init_stagger": ([vp, vp, vp, d, i, i, vp], i),
         "kmx_step": ([vp, vp, vp, vp, d, d, i, i, i, vp, vp], i),
@@ -164,10 +166,23 @@ def _stream():
 
 
 class Source:
-    """Point dipoles (see kmx_create_source)."""
+    """Point dipoles (see kmx_create_source), or with `pattern` a dense pattern
+    times a sampled time series (kmx_create_source_pattern)."""
 
-    def __init__(self, space: "Space", pos, moment, t0, sigma, amp, batch_of=None):
+    def __init__(self, space: "Space", pos=None, moment=None, t0=None, sigma=None, amp=None, batch_of=None,
+                 pattern=None, series=None, series_t0=0.0, series_dt=None):
         L = load_library()
+        if pattern is not None:
+            pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.float64).reshape(-1, space.n_e))
+            ser = np.ascontiguousarray(np.asarray(series, dtype=np.float64).ravel())
+            h = ctypes.c_void_p()
+            _check(L.kmx_create_source_pattern(space._h, int(pat.shape[0]), ctypes.c_void_p(pat.ctypes.data),
+                                               int(ser.size), float(series_t0), float(series_dt),
+                                               ctypes.c_void_p(ser.ctypes.data), ctypes.byref(h)))
+            self._h = h
+            self.space = space
+            self.n = 0
+            return
         n = int(np.asarray(pos).shape[0])
         self._keep = [_hptr(pos, 3 * n), _hptr(moment, 3 * n), _hptr(t0, n), _hptr(sigma, n), _hptr(amp, n)]
         bo = None if batch_of is None else _hptr(batch_of, n, np.int32)
@@ -316,6 +331,10 @@ class Space:
         out = ctypes.c_double()
         _check(load_library().kmx_cfl(self._h, int(max_iter), float(tol), ctypes.byref(out)))
         return out.value
+
+    def source_pattern(self, pattern, series, t0, dt_sample) -> Source:
+        """s(t) = g(t) P: pattern (npat x n_e, host), g sampled at t0 + k dt_sample."""
+        return Source(self, pattern=pattern, series=series, series_t0=t0, series_dt=dt_sample)
 
     def source(self, pos, moment, t0, sigma, amp, batch_of=None) -> Source:
         return Source(self, pos, moment, t0, sigma, amp, batch_of)

@@ -1016,8 +1016,45 @@ kmx_status kmx_create_source(kmx_space* sp, int n, const double* pos, const doub
     return KMX_OK;
 }
 
+kmx_status kmx_create_source_pattern(kmx_space* sp, int npat, const double* pattern, int nsamples, double t0,
+                                     double dt_sample, const double* series, kmx_source** out) {
+    if (!sp || !out || !pattern || !series) return fail(KMX_E_ARG, "NULL argument");
+    *out = nullptr;
+    if (npat < 1 || npat > sp->max_batch) return fail(KMX_E_ARG, "npat must be 1..max_batch");
+    if (nsamples < 2) return fail(KMX_E_ARG, "the time series needs at least two samples");
+    if (!std::isfinite(t0) || !(dt_sample > 0.0) || !std::isfinite(dt_sample))
+        return fail(KMX_E_ARG, "t0 must be finite and dt_sample > 0");
+    const int64_t n = int64_t(npat) * sp->n_e;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(pattern[i])) return fail(KMX_E_ARG, "pattern entry not finite");
+    for (int k = 0; k < nsamples; ++k)
+        if (!std::isfinite(series[k])) return fail(KMX_E_ARG, "series sample not finite");
+    kmx_source* src = new kmx_source();
+    src->sp = sp;
+    src->kind = 1;
+    src->npat = npat;
+    src->nsamples = nsamples;
+    src->ts0 = t0;
+    src->tsh = dt_sample;
+    src->batch_max = npat;
+    if (hipMalloc(&src->d_pattern, size_t(n) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&src->d_series, size_t(nsamples) * sizeof(double)) != hipSuccess) {
+        kmx_destroy_source(src);
+        return fail(KMX_E_OOM, "device allocation failed (source pattern)");
+    }
+    if (hipMemcpy(src->d_pattern, pattern, size_t(n) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(src->d_series, series, size_t(nsamples) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        kmx_destroy_source(src);
+        return fail(KMX_E_DEVICE, "copy of the source pattern failed");
+    }
+    *out = src;
+    return KMX_OK;
+}
+
 void kmx_destroy_source(kmx_source* src) {
     if (!src) return;
+    if (src->d_pattern) (void)hipFree(src->d_pattern);
+    if (src->d_series) (void)hipFree(src->d_series);
     if (src->d_entries) (void)hipFree(src->d_entries);
     if (src->d_prof) (void)hipFree(src->d_prof);
     if (src->d_elem) (void)hipFree(src->d_elem);
@@ -1194,6 +1231,7 @@ kmx_status kmx_adjoint(kmx_space* sp, const kmx_probes* pr, const kmx_source* J,
         (J && J->sp != sp))
         return fail(KMX_E_ARG, "bad argument");
     if (sp->lift_n) return fail(KMX_E_STATE, "the adjoint does not take a lifting");
+    if (J && J->kind == 1) return fail(KMX_E_STATE, "the adjoint takes point dipoles only");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const TiledPlanScope tiled(sp);
     const int64_t ne = sp->n_e, nh = sp->n_h, nobs = int64_t(3) * pr->n, NS = nsteps;
@@ -1491,16 +1529,30 @@ static void tiled_substep(kmx_space* sp, double* E, double* H, int64_t es, int64
     // the lifting: h -= ka sum_j g_j(t_n) v_h^j (t_n = t_half - ka / 2)
     if (sp->lift_n)
         launch_lift(H, hs, sp->d_lift_vh, sp->n_h, lift_terms(sp), t_base, t_step, t_dev, ka, 0, batch, s);
-    // M~ D~^1 h (and d += kb D~^1 h), then e += kb K1^{-1} (. - s)
+    // M~ D~^1 h (and d += kb D~^1 h), then e += kb K1^{-1} (. - s); a pattern
+    // source is subtracted from the gathered field, point dipoles inside the
+    // solve's first pass
     run_mass(sp, SP_D, true, H, hs, batch, s, track ? E + sp->n_e : nullptr, es, kb);
+    const bool pattern = J && J->kind == 1;
+    const kmx_source* Jd = pattern ? nullptr : J;
+    auto sub_pattern = [&](double* y) {
+        launch_pattern_source(y, nf, J->d_pattern, J->npat > 1 ? sp->n_e : 0, sp->n_e, J->d_series, J->nsamples,
+                              J->ts0, J->tsh, t_dev, t_half, batch, s);
+    };
     if (dense && !mixed) {
         run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s, nullptr, nullptr,
                   we, sp->n_e, kb);
-        dense_solve(sp, 1, sp->d_tmp2, E, es, kb, batch, J, t_half, t_dev, s);
+        if (pattern) sub_pattern(sp->d_tmp2);
+        dense_solve(sp, 1, sp->d_tmp2, E, es, kb, batch, Jd, t_half, t_dev, s);
     } else if (mixed) {
-        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, J, t_half, 0, s, nullptr, t_dev, we,
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_my, nf, 1.0, 0, batch, Jd, t_half, 0, s, nullptr, t_dev, we,
                   sp->n_e, kb);
+        if (pattern) sub_pattern(sp->d_my);
         mixed_solve(sp, 1, 0, sp->d_my, E, es, kb, 1, batch, s);
+    } else if (pattern) {
+        run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, sp->d_tmp2, nf, 1.0, 0, batch, nullptr, 0.0, 0, s);
+        sub_pattern(sp->d_tmp2);
+        run_solve(sp, 1, 0, 0, SP_D, sp->d_tmp2, nf, E, es, kb, 1, batch, nullptr, 0.0, 1, s);
     } else {
         run_solve(sp, 1, 0, 1, SP_D, nullptr, 0, E, es, kb, 1, batch, J, t_half, 1, s, nullptr, t_dev, we, sp->n_e, kb);
     }
@@ -1521,11 +1573,14 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
     if (J && track) return fail(KMX_E_ARG, "tracking d and b needs J = NULL (d would need M~^{-1} s)");
     if (sp->lift_n && track) return fail(KMX_E_ARG, "tracking d and b with a lifting is not supported");
     if (energy_dev && !track) return fail(KMX_E_ARG, "energy output needs KMX_TRACK_DB");
-    const bool sep_ok = sep_eligible(sp, energy_dev);
+    if (J && J->kind == 1 && J->npat > 1 && batch > J->npat)
+        return fail(KMX_E_ARG, "the source has fewer patterns than the batch has members");
+    // (the separable plan takes point dipoles only)
+    const bool sep_ok = sep_eligible(sp, energy_dev) && !(J && J->kind == 1);
     int kind = sp->plan_kind;
     if ((kind == KMX_PLAN_SEPARABLE || kind == KMX_PLAN_SEPARABLE_FUSED) && !sep_ok)
-        return fail(KMX_E_STATE, "separable plan needs the identity map, uniform eps and mu, no energy output "
-                                 "and component tensors that fit one workgroup's LDS");
+        return fail(KMX_E_STATE, "separable plan needs the identity map, uniform eps and mu, no energy output, "
+                                 "point-dipole sources only and component tensors that fit one workgroup's LDS");
     if (kind == KMX_PLAN_AUTO) kind = (sep_ok && batch >= SEP_AUTO_MIN_BATCH) ? KMX_PLAN_SEPARABLE : KMX_PLAN_TILED;
     if (kind == KMX_PLAN_SEPARABLE || kind == KMX_PLAN_SEPARABLE_FUSED) {
         if (nsteps > 0) {

@@ -4,6 +4,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "patch.hpp"
 
@@ -1539,6 +1541,35 @@ __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A
 
 void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s) {
     hipLaunchKernelGGL(energy_dots_kernel, dim3(ENERGY_DOT_BLOCKS, batch), dim3(256), 0, s, a);
+}
+
+// A dense source pattern times a sampled time series: g(t) by linear
+// interpolation of the samples at t0 + k h (zero outside the sampled span),
+// then y -= g(t) P over the field.
+__global__ void __launch_bounds__(256) pattern_source_kernel(double* y, int64_t y_stride, const double* P,
+                                                             int64_t p_stride, int64_t n, const double* series, int m,
+                                                             double t0, double h, const double* t_dev, double t_src) {
+    const int b = blockIdx.y;
+    const double t = (t_dev ? *t_dev : 0.0) + t_src;
+    const double u = (t - t0) / h;
+    double g = 0.0;
+    if (u >= 0.0 && u <= double(m - 1)) {
+        const int k = min(int(u), m - 2);
+        const double f = u - k;
+        g = fma(f, series[k + 1] - series[k], series[k]);
+    }
+    double* yb = y + int64_t(b) * y_stride;
+    const double* pb = P + int64_t(b) * p_stride;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        yb[i] = fma(-g, pb[i], yb[i]);
+}
+
+void launch_pattern_source(double* y, int64_t y_stride, const double* P, int64_t p_stride, int64_t n,
+                           const double* series, int m, double t0, double h, const double* t_dev, double t_src,
+                           int batch, hipStream_t s) {
+    const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 2048));
+    hipLaunchKernelGGL(pattern_source_kernel, dim3(blocks, batch), dim3(256), 0, s, y, y_stride, P, p_stride, n,
+                       series, m, t0, h, t_dev, t_src);
 }
 
 __global__ void __launch_bounds__(256) energy_final_kernel(const double* partial, int nblocks, double dt,

@@ -239,6 +239,11 @@ void launch_xy(int p, const XYArgs& a, int batch, hipStream_t s);
 void launch_z(int p, const ZArgs& a, int batch, hipStream_t s);
 void launch_curl(const CurlArgs& a, int64_t n_out, int batch, hipStream_t s);
 void launch_energy_fused(int p, const EnergyFusedArgs& a, int batch, hipStream_t s);
+// y -= g(t) P for every batch member (stride y_stride; pattern stride p_stride,
+// 0 when all members share one), g the sampled series at t = (*t_dev or 0) + t_src
+void launch_pattern_source(double* y, int64_t y_stride, const double* P, int64_t p_stride, int64_t n,
+                           const double* series, int m, double t0, double h, const double* t_dev, double t_src,
+                           int batch, hipStream_t s);
 constexpr int ENERGY_DOT_BLOCKS = 1024;  // blocks per member of the dot kernel
 void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s);
 int energy_fused_blocks(const int dims[3][3], int cb[3]);

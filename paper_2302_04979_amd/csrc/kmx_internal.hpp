@@ -88,6 +88,13 @@ struct kmx_source {
     double* d_inv_eps = nullptr;       // device: 1/eps of that element at creation
     int64_t* d_comp_off = nullptr;     // device: component offsets of the dual 2-form space
     int* d_dims = nullptr;             // device: [3][3] dims of the dual 2-form space
+    // kind 1: a dense pattern s (npat patterns of n_e entries: one for every
+    // member, or one per member) times a sampled time series g
+    int kind = 0;
+    int npat = 0, nsamples = 0;
+    double ts0 = 0.0, tsh = 0.0;       // sample k at ts0 + k tsh
+    double* d_pattern = nullptr;
+    double* d_series = nullptr;
 };
 
 struct kmx_graph {

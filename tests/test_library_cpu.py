@@ -79,6 +79,7 @@ def test_argument_errors_of_the_lifting_and_profiling_entry_points():
     assert L.kmx_lift_boundary(None, None, None, None) == 1
     assert L.kmx_set_lifting(None, 1, None, None, None, None) == 1
     assert L.kmx_profile_select(None, 1) == 1
+    assert L.kmx_create_source_pattern(None, 1, None, 2, d(0.0), d(0.1), None, None) == 1
     assert L.kmx_probe_forward_noalloc(None, None, None, d(0.1), 1, None, None) == 1
     assert L.kmx_last_error().decode()
 
