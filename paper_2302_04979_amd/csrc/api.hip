@@ -623,7 +623,7 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
             space_dims(sp, SP_E, ed, o);
             space_dims(sp, SP_B, hd, o);
             const int64_t nbe = energy_fused_blocks(ed, cb) + energy_fused_blocks(hd, cb);
-            sp->red_len = int64_t(max_batch) * std::max<int64_t>(1024, nbe) * 3 + 64;
+            sp->red_len = int64_t(max_batch) * std::max<int64_t>(std::max(1024, ENERGY_DOT_BLOCKS), nbe) * 3 + 64;
         }
         if (hipMalloc(&sp->d_patch, size_t(sp->patch_per_field) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_tmp, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||

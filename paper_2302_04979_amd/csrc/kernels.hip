@@ -1476,23 +1476,27 @@ int energy_fused_blocks(const int dims[3][3], int cb[3]) {
 // - dt M D^1 e^n and K1 e^{n+1} = K1 e^n + dt M~ D~^1 h^{n+1/2}, the Hodge
 // relations of eqs. (3.11) and (3.13) applied to the increments): per block
 // the partial sums of d . w_e, b . w_h and w_h . D^1 e, in a fixed order
-// (grid-stride loops over a fixed grid, then block_sum3).
+// (grid-stride loops over a fixed grid, then block_sum3).  The first EB
+// blocks take the d . w_e items, the others the b . w_h and w_h . D^1 e items
+// (EB = 0: every block takes items of both kinds).
+template <int U, int EB>
 __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A) {
     const int bm = blockIdx.y;
     const double* E = A.E + int64_t(bm) * 2 * A.n_e;
     const double* H = A.H + int64_t(bm) * 2 * A.n_h;
     const double* we = A.we + int64_t(bm) * A.n_e;
     const double* wh = A.wh + int64_t(bm) * A.n_h;
-    const int64_t stride = int64_t(gridDim.x) * 256;
-    const int64_t i0 = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int bx = blockIdx.x;
+    const bool do_e = EB == 0 || bx < EB, do_h = EB == 0 || bx >= EB;
+    const int64_t se = int64_t(EB == 0 ? gridDim.x : EB) * 256, sh = int64_t(gridDim.x - EB) * 256;
+    const int64_t ie = int64_t(bx) * 256 + threadIdx.x, ih = int64_t(bx - (EB == 0 ? 0 : EB)) * 256 + threadIdx.x;
     // U entries per thread and round, all loads requested before the sums
-    constexpr int U = 4;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int64_t ib = i0; ib < A.n_e; ib += U * stride) {
+    for (int64_t ib = ie; do_e && ib < A.n_e; ib += U * se) {
         double dv[U], wv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t i = ib + u * stride;
+            const int64_t i = ib + u * se;
             const bool ok = i < A.n_e;
             const double a = E[A.n_e + (ok ? i : 0)], b = we[ok ? i : 0];
             dv[u] = ok ? a : 0.0;
@@ -1501,11 +1505,11 @@ __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A
 #pragma unroll
         for (int u = 0; u < U; ++u) s0 = fma(dv[u], wv[u], s0);
     }
-    for (int64_t ib = i0; ib < A.n_h; ib += U * stride) {
+    for (int64_t ib = ih; do_h && ib < A.n_h; ib += U * sh) {
         double wv[U], bv[U], de[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t i = ib + u * stride;
+            const int64_t i = ib + u * sh;
             const bool ok = i < A.n_h;
             const int64_t j = ok ? i : 0;
             const double w = wh[j], bb = H[A.n_h + j];
@@ -1540,7 +1544,8 @@ __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A
 }
 
 void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(energy_dots_kernel, dim3(ENERGY_DOT_BLOCKS, batch), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((energy_dots_kernel<ENERGY_DOT_UNROLL, ENERGY_DOT_EBLOCKS>), dim3(ENERGY_DOT_BLOCKS, batch),
+                       dim3(256), 0, s, a);
 }
 
 // A dense source pattern times a sampled time series: g(t) by linear

@@ -244,7 +244,9 @@ void launch_energy_fused(int p, const EnergyFusedArgs& a, int batch, hipStream_t
 void launch_pattern_source(double* y, int64_t y_stride, const double* P, int64_t p_stride, int64_t n,
                            const double* series, int m, double t0, double h, const double* t_dev, double t_src,
                            int batch, hipStream_t s);
-constexpr int ENERGY_DOT_BLOCKS = 1024;  // blocks per member of the dot kernel
+constexpr int ENERGY_DOT_BLOCKS = 2048;  // blocks per member of the dot kernel
+constexpr int ENERGY_DOT_UNROLL = 1;     // entries per thread and loop round
+constexpr int ENERGY_DOT_EBLOCKS = 512;  // of the blocks, those that take the d . w_e items alone (0: all take both)
 void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s);
 int energy_fused_blocks(const int dims[3][3], int cb[3]);
 // out[b*out_stride] (+ step offset) from the energy partials
