@@ -9,7 +9,8 @@ it: the two sides meet only through the seeded input generators in
 The oracle is written plainly from the paper, in FP64 with NumPy/SciPy
 primitives (matrix products, dense LU), with no blocking or fusion:
 
-* ``splines``   - knot vectors, B-spline and Curry-Schoenberg bases, Gauss rules,
+* ``splines``   - knot vectors (uniform or with given breakpoints), B-spline and
+                  Curry-Schoenberg bases, Gauss rules,
                   1D incidence matrices, 1D pairing matrices G^ and M^
                   (Section 2.3; Section 4.1).
 * ``geometry``  - maps F of the unit cube (identity, the deformed cube, the
@@ -29,6 +30,9 @@ primitives (matrix products, dense LU), with no blocking or fusion:
                   mass solves, the (e, h) leapfrog with the transposed pairings,
                   its energies and CFL.
 * ``adjoint``   - the discrete adjoint of the scheme-2 leapfrog.
+* ``tensor``    - the scheme with a degree, a knot vector and an element count
+                  per direction (Section 4.1, per-direction factors of (4.2),
+                  (4.3)), with level-0 counterparts of its pairings and masses.
 * ``lifting``   - non-homogeneous tangential data for E (Section 3.5): the
                   whole primal spaces, the least-squares trace fit of the
                   lifting, the lifted leapfrog with separable-in-time data

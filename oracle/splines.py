@@ -63,17 +63,35 @@ def bspline_basis(knots: np.ndarray, deg: int, x) -> np.ndarray:
     return B
 
 
-class Axis:
-    """The four 1D bases on one parametric axis with N elements and degree p."""
+def open_knots_from_breaks(breaks: np.ndarray, p: int) -> np.ndarray:
+    """p-open knot vector on [0, 1] whose interior knots are the given
+    breakpoints, each simple (maximal regularity; Section 2.3 with a general
+    knot vector Xi, Section 4.1 with one per direction)."""
+    return np.concatenate([np.zeros(p + 1), np.asarray(breaks, float), np.ones(p + 1)])
 
-    def __init__(self, n_elem: int, p: int):
+
+class Axis:
+    """The four 1D bases on one parametric axis with N elements and degree p.
+
+    breaks: None for N uniform elements, else the N - 1 interior breakpoints
+    (strictly increasing inside (0, 1)) of a non-uniform knot vector."""
+
+    def __init__(self, n_elem: int, p: int, breaks=None):
         if p < 2:
             raise ValueError("the dual complex needs p >= 2 (Section 2.3, p > 1)")
         if n_elem < 1:
             raise ValueError("need at least one element")
         self.N = n_elem
         self.p = p
-        self.xi = open_knots(n_elem, p)
+        self.breaks = None
+        if breaks is None:
+            self.xi = open_knots(n_elem, p)
+        else:
+            b = np.asarray(breaks, dtype=float)
+            if b.shape != (n_elem - 1,) or not np.all(np.diff(np.concatenate([[0.0], b, [1.0]])) > 0):
+                raise ValueError("breaks must be N - 1 increasing points inside (0, 1)")
+            self.breaks = b
+            self.xi = open_knots_from_breaks(b, p)
         self.xi1 = self.xi[1:-1]
         self.xi2 = self.xi[2:-2]
         self.n0 = n_elem + p - 2
@@ -106,10 +124,22 @@ class Axis:
         ordered element by element: arrays of length N*nq."""
         nq = self.p + 1 if nq is None else nq
         g, w = np.polynomial.legendre.leggauss(nq)
-        h = 1.0 / self.N
-        x = np.concatenate([(e + 0.5 * (g + 1.0)) * h for e in range(self.N)])
-        wt = np.concatenate([0.5 * w * h for _ in range(self.N)])
+        if self.breaks is None:
+            h = 1.0 / self.N
+            x = np.concatenate([(e + 0.5 * (g + 1.0)) * h for e in range(self.N)])
+            wt = np.concatenate([0.5 * w * h for _ in range(self.N)])
+            return x, wt
+        nodes = np.concatenate([[0.0], self.breaks, [1.0]])
+        lo, hi = nodes[:-1], nodes[1:]
+        x = np.concatenate([lo[e] + 0.5 * (g + 1.0) * (hi[e] - lo[e]) for e in range(self.N)])
+        wt = np.concatenate([0.5 * w * (hi[e] - lo[e]) for e in range(self.N)])
         return x, wt
+
+    def nodes(self) -> np.ndarray:
+        """The N + 1 element boundaries."""
+        if self.breaks is None:
+            return np.arange(self.N + 1) / self.N
+        return np.concatenate([[0.0], self.breaks, [1.0]])
 
     # ---- incidence matrices (Section 2.4, +-1 with Curry-Schoenberg bases) --
     def d_primal(self) -> np.ndarray:

@@ -46,6 +46,31 @@ def eps_elements(n_elem: int, seed: int = 0, lo: float = 1.0, hi: float = 4.0,
     return rng(seed, purpose).uniform(lo, hi, size=(n_elem, n_elem, n_elem))
 
 
+def eps_elements_aniso(n_elem, seed: int = 0, lo: float = 1.0, hi: float = 4.0,
+                       purpose: str = "eps") -> np.ndarray:
+    """Per-element permittivity on an (Nx, Ny, Nz) mesh, uniform in [lo, hi],
+    shape (Nz, Ny, Nx) indexed [ez, ey, ex]."""
+    nx, ny, nz = (int(v) for v in n_elem)
+    return rng(seed, purpose).uniform(lo, hi, size=(nz, ny, nx))
+
+
+def graded_breaks(n_elem: int, ratio: float):
+    """Interior breakpoints of a geometrically graded mesh of [0, 1]: element
+    sizes proportional to ratio^k, k = 0..N-1 (ratio 1: uniform).  None for one
+    element."""
+    if n_elem < 2:
+        return None
+    w = np.asarray(ratio, float) ** np.arange(n_elem)
+    return np.cumsum(w)[:-1] / w.sum()
+
+
+# The anisotropic workload of the per-direction path: degrees (p_x, p_y, p_z),
+# elements (N_x, N_y, N_z) and the grading ratio of each direction (the finest
+# direction first, as the remark after eq. (4.5) recommends).
+ANISO_SMALL = {"p": (3, 2, 4), "n": (6, 5, 3), "ratio": (1.3, 1.0, 0.8)}
+ANISO_FULL = {"p": (3, 3, 2), "n": (64, 48, 32), "ratio": (1.02, 1.0, 0.97)}
+
+
 def random_vector(n: int, seed: int = 0, salt: int = 0) -> np.ndarray:
     """Standard-normal coefficient vector (operator tests)."""
     g = np.random.default_rng([int(seed), PURPOSE["field"], int(salt)])
