@@ -533,6 +533,49 @@ kmx_status kmx_profile_begin(kmx_space* sp, int capacity);
 kmx_status kmx_profile_select(kmx_space* sp, unsigned mask);
 kmx_status kmx_profile_end(kmx_space* sp, double* ms_total, int* launches);
 
+/* ---- per-direction degrees, knot vectors and element counts -------------
+ * Section 4.1: with a degree p_i and a knot vector Xi_i per direction i the
+ * pairing blocks keep the Kronecker form of eqs. (4.2)/(4.3), each 1D factor
+ * G^i, M^i built from the bases of direction i, and a solve stays one banded
+ * 1D solve per axis (eqs. (4.4)-(4.5)).  A kmx_tspace holds the spaces of the
+ * second scheme for such a mesh: direction a (0 = x, 1 = y, 2 = z) has degree
+ * p[a] (2..4), n_elem[a] elements (n_elem[a] + p[a] - 1 <= 76) and a p-open
+ * knot vector with the n_elem[a] - 1 interior breakpoints breaks_a (host,
+ * strictly increasing inside (0, 1); NULL: uniform).  Map kinds 0 and 1 only
+ * (host struct; kind 1 as for kmx_create_space).  Unknowns are laid out as in
+ * the single-degree spaces: the three components one after the other, x
+ * fastest inside; component c of a form space has, along direction a, the
+ * univariate space of its tag (Section 2.3): for X^1_{h,0} (and X~^2) the
+ * derivative space along c (dimension N_a + p_a - 1) and the value space across
+ * it (N_a + p_a - 2); for X^2_{h,0} (and X~^1) the other way round.  Gauss
+ * rules: p_a + 1 points per element and direction.  The metric factor is
+ * streamed (6 doubles per quadrature point).  Errors: KMX_E_ARG (sizes,
+ * degrees, breakpoints, map kind, a pairing factor that needs pivoting),
+ * KMX_E_GEOMETRY, KMX_E_OOM, KMX_E_DEVICE.  Calls on one space must not
+ * overlap (they share its scratch). */
+typedef struct kmx_tspace kmx_tspace;
+kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* breaks_x, const double* breaks_y,
+                             const double* breaks_z, const kmx_map* map, int max_batch, kmx_tspace** out);
+void kmx_destroy_tspace(kmx_tspace* ts);
+/* n_e = dim X^1_{h,0} = dim X~^2, n_h = dim X~^1 = dim X^2_{h,0} (either may be NULL). */
+kmx_status kmx_tspace_sizes(const kmx_tspace* ts, int64_t* n_e, int64_t* n_h);
+/* Per-element eps and mu (host, N_x N_y N_z each, x fastest; NULL = 1).
+ * Errors: KMX_E_MATERIAL (nothing changed), KMX_E_DEVICE. */
+kmx_status kmx_tspace_set_materials(kmx_tspace* ts, const double* eps_elem, const double* mu_elem);
+/* The operators of one field (device vectors, as kmx_op_curl, kmx_op_mass
+ * without the fused curl, kmx_op_solve and kmx_op_pairing). */
+kmx_status kmx_tspace_op_curl(kmx_tspace* ts, int which, const double* x, double* y, void* stream);
+kmx_status kmx_tspace_op_mass(kmx_tspace* ts, int which, const double* x, double* y, void* stream);
+kmx_status kmx_tspace_op_solve(kmx_tspace* ts, int which, int transpose, const double* y, double* x,
+                               void* stream);
+kmx_status kmx_tspace_op_pairing(kmx_tspace* ts, int which, const double* x, double* y, void* stream);
+/* nsteps source-free leapfrog steps (Section 3.4, as kmx_step):
+ *   h -= dt K~1^{-1} M^2_{1/mu} D^1 e,  e += dt K1^{-1} M~^2_{1/eps} D~^1 h,
+ * with b -= dt D^1 e and d += dt D~^1 h when flags has KMX_TRACK_DB (E holds
+ * [e | d], H holds [h | b] per member); batch members back to back. */
+kmx_status kmx_tspace_step(kmx_tspace* ts, double* E, double* H, double dt, int nsteps, int batch, int flags,
+                           void* stream);
+
 const char* kmx_last_error(void);
 
 #ifdef __cplusplus

@@ -16,7 +16,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Space", "Source", "load_library", "EXPORTS", "TRACK_DB", "KMXError"]
+__all__ = ["Space", "TSpace", "Source", "load_library", "EXPORTS", "TRACK_DB", "KMXError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkronmaxwell.so")
@@ -45,6 +45,9 @@ EXPORTS = (
     "kmx_init_split", "kmx_step_split", "kmx_project_E1", "kmx_graph_create_scheme1",
     "kmx_probe_forward_noalloc", "kmx_profile_select", "kmx_sizes_full", "kmx_lift_boundary",
     "kmx_set_lifting",
+    "kmx_create_tspace", "kmx_destroy_tspace", "kmx_tspace_sizes", "kmx_tspace_set_materials",
+    "kmx_tspace_op_curl", "kmx_tspace_op_mass", "kmx_tspace_op_solve", "kmx_tspace_op_pairing",
+    "kmx_tspace_step",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
                  "mode_fp32", "dense_fp64", "mass_1form", "cg_vector")
@@ -129,6 +132,15 @@ def load_library():
         "kmx_sizes_full": ([vp, i64p], i),
         "kmx_lift_boundary": ([vp, vp, vp, ctypes.POINTER(i)], i),
         "kmx_set_lifting": ([vp, i, vp, vp, vp, vp], i),
+        "kmx_create_tspace": ([vp, vp, vp, vp, vp, ctypes.POINTER(_Map), i, ctypes.POINTER(vp)], i),
+        "kmx_destroy_tspace": ([vp], None),
+        "kmx_tspace_sizes": ([vp, i64p, i64p], i),
+        "kmx_tspace_set_materials": ([vp, vp, vp], i),
+        "kmx_tspace_op_curl": ([vp, i, vp, vp, vp], i),
+        "kmx_tspace_op_mass": ([vp, i, vp, vp, vp], i),
+        "kmx_tspace_op_solve": ([vp, i, i, vp, vp, vp], i),
+        "kmx_tspace_op_pairing": ([vp, i, vp, vp, vp], i),
+        "kmx_tspace_step": ([vp, vp, vp, d, i, i, i, vp], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -272,6 +284,86 @@ class GraphScheme1(Graph):
         self._keep = (e, h)  # bound at capture
         self.space = space
         self.nsteps = nsteps
+
+
+class TSpace:
+    """Spaces with a degree, a knot vector and an element count per direction
+    (kmx_create_tspace): p and n_elem are (x, y, z) triples, breaks the
+    interior breakpoints of each direction (None: uniform)."""
+
+    def __init__(self, p, n_elem, breaks=(None, None, None), map_kind: int = 0, amplitude: float = 0.0,
+                 max_batch: int = 1):
+        L = load_library()
+        self.p = tuple(int(v) for v in p)
+        self.N = tuple(int(v) for v in n_elem)
+        pa = (ctypes.c_int * 3)(*self.p)
+        na = (ctypes.c_int * 3)(*self.N)
+        self._breaks = []
+        ptrs = []
+        for a in range(3):
+            if breaks[a] is None:
+                ptrs.append(None)
+            else:
+                arr, ptr = _hptr(breaks[a], self.N[a] - 1, name="breaks")
+                self._breaks.append(arr)
+                ptrs.append(ptr)
+        m = _Map(int(map_kind), float(amplitude), None)
+        h = ctypes.c_void_p()
+        _check(L.kmx_create_tspace(pa, na, ptrs[0], ptrs[1], ptrs[2], ctypes.byref(m), int(max_batch),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.max_batch = max_batch
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(L.kmx_tspace_sizes(h, ctypes.byref(a), ctypes.byref(b)))
+        self.n_e, self.n_h = a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().kmx_destroy_tspace(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_materials(self, eps=None, mu=None):
+        n = self.N[0] * self.N[1] * self.N[2]
+        e = None if eps is None else _hptr(np.asarray(eps).ravel(), n, name="eps")
+        m = None if mu is None else _hptr(np.asarray(mu).ravel(), n, name="mu")
+        _check(load_library().kmx_tspace_set_materials(self._h, None if e is None else e[1],
+                                                       None if m is None else m[1]))
+
+    def op_curl(self, primal: bool, x, y):
+        n_in, n_out = (self.n_e, self.n_h) if primal else (self.n_h, self.n_e)
+        _check(load_library().kmx_tspace_op_curl(self._h, 0 if primal else 1, _dptr(x, n_in, "x"),
+                                                 _dptr(y, n_out, "y"), _stream()))
+
+    def op_mass(self, which: str, x, y):
+        """which 'B' (M^2_{1/mu}) or 'D' (M~^2_{1/eps})."""
+        w = 0 if which == "B" else 1
+        n = self.n_h if w == 0 else self.n_e
+        _check(load_library().kmx_tspace_op_mass(self._h, w, _dptr(x, n, "x"), _dptr(y, n, "y"), _stream()))
+
+    def op_solve(self, which: str, y, x, transpose=False):
+        """which 'K1' or 'K1t': x = K^{-1} y (or K^{-T} y)."""
+        w = 1 if which == "K1" else 0
+        n = self.n_e if w else self.n_h
+        _check(load_library().kmx_tspace_op_solve(self._h, w, int(bool(transpose)), _dptr(y, n, "y"),
+                                                  _dptr(x, n, "x"), _stream()))
+
+    def op_pairing(self, which: str, x, y):
+        """y = K x, which 'K1' or 'K1t'."""
+        w = 1 if which == "K1" else 0
+        n = self.n_e if w else self.n_h
+        _check(load_library().kmx_tspace_op_pairing(self._h, w, _dptr(x, n, "x"), _dptr(y, n, "y"), _stream()))
+
+    def step(self, E, H, dt, nsteps=1, batch=1, flags=0):
+        k = 1 + (flags & TRACK_DB)
+        _check(load_library().kmx_tspace_step(self._h, _dptr(E, batch * k * self.n_e, "E"),
+                                              _dptr(H, batch * k * self.n_h, "H"), float(dt), int(nsteps),
+                                              int(batch), int(flags), _stream()))
 
 
 class Space:

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkronmaxwell.so")
-SOURCES = ["setup.hip", "kernels.hip", "sep.hip", "mixed.hip", "dense.hip", "lifting.hip", "api.hip"]
+SOURCES = ["setup.hip", "kernels.hip", "sep.hip", "mixed.hip", "dense.hip", "lifting.hip", "tensor.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -429,6 +429,11 @@ std::vector<double> gram(const Tables& tb, int tag) {
 
 }  // namespace
 
+namespace kmx {
+// Error reporting for the entry points of other sources (last error message).
+kmx_status report_error(kmx_status st, const std::string& msg) { return fail(st, msg); }
+}  // namespace kmx
+
 extern "C" {
 
 const char* kmx_last_error(void) { return g_err.c_str(); }

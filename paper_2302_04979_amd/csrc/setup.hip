@@ -62,7 +62,7 @@ static std::vector<double> knots_for(int p, int N, int trim) {
 // Values of the deg+1 B-splines of degree `deg` that are nonzero on knot span
 // s (t[s] <= x <= t[s+1]), i.e. B_{s-deg}, ..., B_s, by the triangular
 // Cox-de Boor recurrence.
-static void nonzero_bsplines(const std::vector<double>& t, int s, int deg, double x, double* out) {
+void nonzero_bsplines(const std::vector<double>& t, int s, int deg, double x, double* out) {
     double left[8], right[8];
     out[0] = 1.0;
     for (int j = 1; j <= deg; ++j) {

@@ -8,6 +8,8 @@
 namespace kmx {
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+// the deg + 1 B-splines of degree deg on knots t nonzero on span s, at x
+void nonzero_bsplines(const std::vector<double>& t, int s, int deg, double x, double* out);
 void eval_tag_on_element(const Tables& tb, int tag, int e, double x, double* vals);
 BandLU band_lu(const std::vector<double>& A, int n, int w);
 void band_solve_host(const BandLU& f, double* x, int64_t stride);

@@ -1,0 +1,736 @@
+// Spaces with a degree, a knot vector and an element count per direction
+// (Section 4.1: with p_i and Xi_i per direction the pairing blocks keep the
+// Kronecker form of eqs. (4.2)/(4.3), each 1D factor built from the bases of
+// its own direction, and each solve stays one banded 1D solve per axis,
+// eqs. (4.4)-(4.5)).  The spaces are the tensor products of the univariate
+// spaces of Section 2.3, now per direction; the curls are the same index
+// differences (Section 2.4); the 2-form masses (Section 3.4) integrate over
+// per-direction Gauss rules with p_i + 1 points per element.
+//
+// Device layout: fields as in the single-degree spaces (three components one
+// after the other, x fastest inside); the 1D basis tables per direction and
+// tag, element-major [e][q][k]; the metric factor w_q DF^T DF / det DF per
+// element as [element][6][point]; the mass apply writes one patch per element
+// (its window of every component) and a gather sums, for each output, the
+// patches of the elements in its support in a fixed order.  The pairing
+// solves run the banded line kernels of the single-degree spaces, with the
+// factors of every direction padded to the half bandwidth of the largest
+// degree (the padding holds zeros, so the substitutions are unchanged).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "kmx_internal.hpp"
+#include "setup.hpp"
+
+namespace kmx {
+
+kmx_status report_error(kmx_status st, const std::string& msg);  // api.hip
+
+namespace {
+
+constexpr int TP_MAX = 4;                            // largest degree per direction
+constexpr int TK = TP_MAX + 1;                       // functions per element and direction (at most)
+constexpr int TQ = TP_MAX + 1;                       // Gauss points per element and direction (at most)
+constexpr int TCUBE = TK * TK * TK;                  // one window or one point block
+constexpr int TLINE_MAX = 76;                        // longest 1D space the line kernels hold
+
+// Arguments of the per-element mass apply (one workgroup per element).
+struct TMassArgs {
+    const double* x;
+    int64_t x_stride;
+    double* patch;
+    int64_t patch_stride;        // per member
+    const double* tab;
+    int64_t tab_off[3][4];       // [direction][tag] -> [N][nq][K]
+    int p[3], N[3], nq[3];
+    int space;                   // SP_B or SP_D
+    int64_t comp_off[3];
+    int dims[3][3];              // [c][z, y, x]
+    int64_t pcomp_off[3];        // per-element patch: component offsets
+    int psize;                   // patch doubles per element
+    const double* metric;        // [element][6][point]
+    int npts;
+    const double* inv_gamma;     // per element (x fastest)
+};
+
+struct TGatherArgs {
+    const double* patch;
+    int64_t patch_stride;
+    double* out;
+    int64_t out_stride;
+    int p[3], N[3];
+    int space;
+    int64_t comp_off[3];
+    int dims[3][3];
+    int64_t pcomp_off[3];
+    int psize;
+};
+
+// Window size of component c along direction a.
+__host__ __device__ inline int t_support(const int p[3], int space, int c, int a) {
+    return tag_support(p[a], space_tag(space, c, a));
+}
+
+__global__ void __launch_bounds__(64) tmass_kernel(const TMassArgs A) {
+    __shared__ double X[TCUBE], T1[TCUBE], T2[TCUBE];
+    __shared__ double V[3][TCUBE];
+    __shared__ double tb[3][2][TQ * TK];  // per direction: the along and across tags, [q][k]
+    const int tid = threadIdx.x;
+    const int b = blockIdx.y;
+    const int elem = blockIdx.x;
+    const int e3[3] = {elem % A.N[0], (elem / A.N[0]) % A.N[1], elem / (A.N[0] * A.N[1])};
+    const int nqx = A.nq[0], nqy = A.nq[1], nqz = A.nq[2];
+
+    // the 1D tables of this element, both tags of the space per direction
+    for (int i = tid; i < 3 * 2 * TQ * TK; i += 64) {
+        const int a = i / (2 * TQ * TK), s = (i / (TQ * TK)) % 2, q = (i / TK) % TQ, k = i % TK;
+        const int tag = space_tag(A.space, s == 0 ? a : (a + 1) % 3, a);
+        const int K = tag_support(A.p[a], tag);
+        double v = 0.0;
+        if (q < A.nq[a] && k < K) v = A.tab[A.tab_off[a][tag] + (int64_t(e3[a]) * A.nq[a] + q) * K + k];
+        tb[a][s][q * TK + k] = v;
+    }
+    const double* x = A.x + int64_t(b) * A.x_stride;
+
+    // interpolation to the Gauss points, one component at a time: x, y, z passes
+    for (int c = 0; c < 3; ++c) {
+        const int Kx = t_support(A.p, A.space, c, 0), Ky = t_support(A.p, A.space, c, 1),
+                  Kz = t_support(A.p, A.space, c, 2);
+        const double* Tx = tb[0][c == 0 ? 0 : 1];
+        const double* Ty = tb[1][c == 1 ? 0 : 1];
+        const double* Tz = tb[2][c == 2 ? 0 : 1];
+        const int ox = tag_offset(space_tag(A.space, c, 0)), oy = tag_offset(space_tag(A.space, c, 1)),
+                  oz = tag_offset(space_tag(A.space, c, 2));
+        const int nx = A.dims[c][2], ny = A.dims[c][1], nz = A.dims[c][0];
+        __syncthreads();  // earlier readers of X, T1, T2 are done
+        for (int i = tid; i < Kx * Ky * Kz; i += 64) {
+            const int kx = i % Kx, ky = (i / Kx) % Ky, kz = i / (Kx * Ky);
+            const int gx = e3[0] + ox + kx, gy = e3[1] + oy + ky, gz = e3[2] + oz + kz;
+            const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+            X[i] = ok ? x[A.comp_off[c] + (int64_t(gz) * ny + gy) * nx + gx] : 0.0;
+        }
+        __syncthreads();
+        for (int i = tid; i < Kz * Ky * nqx; i += 64) {
+            const int qx = i % nqx, r = i / nqx;  // r = kz * Ky + ky
+            double s = 0.0;
+            for (int k = 0; k < Kx; ++k) s += Tx[qx * TK + k] * X[r * Kx + k];
+            T1[i] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < Kz * nqy * nqx; i += 64) {
+            const int qx = i % nqx, qy = (i / nqx) % nqy, kz = i / (nqx * nqy);
+            double s = 0.0;
+            for (int k = 0; k < Ky; ++k) s += Ty[qy * TK + k] * T1[(kz * Ky + k) * nqx + qx];
+            T2[i] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < nqz * nqy * nqx; i += 64) {
+            const int r = i % (nqy * nqx), qz = i / (nqy * nqx);
+            double s = 0.0;
+            for (int k = 0; k < Kz; ++k) s += Tz[qz * TK + k] * T2[k * nqy * nqx + r];
+            V[c][i] = s;
+        }
+    }
+    __syncthreads();
+    // the metric and the material at every point: u = (1 / gamma) G v
+    {
+        const double ig = A.inv_gamma[elem];
+        const double* g = A.metric + int64_t(elem) * 6 * A.npts;
+        for (int q = tid; q < A.npts; q += 64) {
+            const double g0 = g[q], g1 = g[A.npts + q], g2 = g[2 * A.npts + q], g3 = g[3 * A.npts + q],
+                         g4 = g[4 * A.npts + q], g5 = g[5 * A.npts + q];
+            const double v0 = V[0][q], v1 = V[1][q], v2 = V[2][q];
+            V[0][q] = ig * (g0 * v0 + g3 * v1 + g4 * v2);
+            V[1][q] = ig * (g3 * v0 + g1 * v1 + g5 * v2);
+            V[2][q] = ig * (g4 * v0 + g5 * v1 + g2 * v2);
+        }
+    }
+    // integration against the test functions: z, y, x passes, into the patch
+    double* patch = A.patch + int64_t(b) * A.patch_stride + int64_t(elem) * A.psize;
+    for (int c = 0; c < 3; ++c) {
+        const int Kx = t_support(A.p, A.space, c, 0), Ky = t_support(A.p, A.space, c, 1),
+                  Kz = t_support(A.p, A.space, c, 2);
+        const double* Tx = tb[0][c == 0 ? 0 : 1];
+        const double* Ty = tb[1][c == 1 ? 0 : 1];
+        const double* Tz = tb[2][c == 2 ? 0 : 1];
+        __syncthreads();
+        for (int i = tid; i < Kz * nqy * nqx; i += 64) {
+            const int r = i % (nqy * nqx), kz = i / (nqy * nqx);
+            double s = 0.0;
+            for (int q = 0; q < nqz; ++q) s += Tz[q * TK + kz] * V[c][q * nqy * nqx + r];
+            T2[i] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < Kz * Ky * nqx; i += 64) {
+            const int qx = i % nqx, ky = (i / nqx) % Ky, kz = i / (nqx * Ky);
+            double s = 0.0;
+            for (int q = 0; q < nqy; ++q) s += Ty[q * TK + ky] * T2[(kz * nqy + q) * nqx + qx];
+            T1[i] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < Kz * Ky * Kx; i += 64) {
+            const int kx = i % Kx, r = i / Kx;  // r = kz * Ky + ky
+            double s = 0.0;
+            for (int q = 0; q < nqx; ++q) s += Tx[q * TK + kx] * T1[r * nqx + q];
+            patch[A.pcomp_off[c] + i] = s;
+        }
+    }
+}
+
+// out_i = sum of the patch entries of the elements whose window holds
+// function i, by increasing z, y, x element index.
+__global__ void __launch_bounds__(256) tgather_kernel(const TGatherArgs A, int64_t n) {
+    const int b = blockIdx.y;
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int c = i >= A.comp_off[2] ? 2 : (i >= A.comp_off[1] ? 1 : 0);
+    const int64_t li = i - A.comp_off[c];
+    const int nx = A.dims[c][2], ny = A.dims[c][1];
+    const int g[3] = {int(li % nx), int((li / nx) % ny), int(li / (int64_t(nx) * ny))};
+    int K[3], o[3], lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        const int tag = space_tag(A.space, c, a);
+        K[a] = tag_support(A.p[a], tag);
+        o[a] = tag_offset(tag);
+        lo[a] = max(0, g[a] - o[a] - K[a] + 1);
+        hi[a] = min(A.N[a] - 1, g[a] - o[a]);
+    }
+    const double* patch = A.patch + int64_t(b) * A.patch_stride + A.pcomp_off[c];
+    double s = 0.0;
+    for (int ez = lo[2]; ez <= hi[2]; ++ez)
+        for (int ey = lo[1]; ey <= hi[1]; ++ey)
+            for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+                const int64_t elem = (int64_t(ez) * A.N[1] + ey) * A.N[0] + ex;
+                const int k = ((g[2] - o[2] - ez) * K[1] + (g[1] - o[1] - ey)) * K[0] + (g[0] - o[0] - ex);
+                s += patch[elem * A.psize + k];
+            }
+    A.out[int64_t(b) * A.out_stride + i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// host set-up
+// ---------------------------------------------------------------------------
+struct TAxis {
+    int p = 0, N = 0, nq = 0, n0 = 0, n1 = 0;
+    std::vector<double> t;                   // p-open knot vector
+    std::vector<double> xq, wq;              // Gauss points and weights, element by element
+    std::vector<double> tab[4];              // [N][nq][K(tag)]
+    std::vector<double> G, M;                // dense 1D pairing matrices
+};
+
+// Values of the functions of `tag` nonzero on element e at x (knot vector t of
+// degree p; trimmed vectors Xi', Xi'' for the lower degrees).
+void t_eval(const TAxis& ax, int tag, int e, double x, double* vals) {
+    const int p = ax.p;
+    const std::vector<double>& t = ax.t;
+    if (tag == PV) {
+        nonzero_bsplines(t, p + e, p, x, vals);  // functions e .. e + p of the whole basis
+        for (int j = 0; j <= p; ++j) {
+            const int gidx = e + j - 1;  // index without the first boundary function
+            if (gidx < 0 || gidx >= ax.n0) vals[j] = 0.0;
+        }
+    } else if (tag == PD || tag == DV) {
+        const std::vector<double> t1(t.begin() + 1, t.end() - 1);
+        nonzero_bsplines(t1, p - 1 + e, p - 1, x, vals);  // e .. e + p - 1
+        if (tag == PD)
+            for (int j = 0; j < p; ++j) vals[j] *= p / (t1[e + j + p] - t1[e + j]);  // unit integrals
+    } else {
+        const std::vector<double> t2(t.begin() + 2, t.end() - 2);
+        nonzero_bsplines(t2, p - 2 + e, p - 2, x, vals);  // e .. e + p - 2
+        for (int j = 0; j < p - 1; ++j) vals[j] *= (p - 1) / (t2[e + j + p - 1] - t2[e + j]);
+    }
+}
+
+void t_build_axis(TAxis& ax, int p, int N, const double* breaks) {
+    ax.p = p;
+    ax.N = N;
+    ax.nq = p + 1;
+    ax.n0 = N + p - 2;
+    ax.n1 = N + p - 1;
+    std::vector<double> nodes(N + 1);
+    for (int k = 0; k <= N; ++k) nodes[k] = breaks && k > 0 && k < N ? breaks[k - 1] : double(k) / N;
+    nodes[0] = 0.0;
+    nodes[N] = 1.0;
+    for (int k = 0; k < N; ++k)
+        if (!(nodes[k + 1] > nodes[k])) throw std::invalid_argument("breakpoints must increase inside (0, 1)");
+    ax.t.assign(p + 1, 0.0);
+    for (int k = 1; k < N; ++k) ax.t.push_back(nodes[k]);
+    for (int k = 0; k <= p; ++k) ax.t.push_back(1.0);
+    std::vector<double> g, gw;
+    gauss_legendre(ax.nq, g, gw);
+    ax.xq.resize(size_t(N) * ax.nq);
+    ax.wq.resize(size_t(N) * ax.nq);
+    for (int e = 0; e < N; ++e)
+        for (int q = 0; q < ax.nq; ++q) {
+            const double h = nodes[e + 1] - nodes[e];
+            ax.xq[e * ax.nq + q] = nodes[e] + 0.5 * (g[q] + 1.0) * h;
+            ax.wq[e * ax.nq + q] = 0.5 * gw[q] * h;
+        }
+    for (int tag = 0; tag < 4; ++tag) {
+        const int K = tag_support(p, tag);
+        ax.tab[tag].assign(size_t(N) * ax.nq * K, 0.0);
+        for (int e = 0; e < N; ++e)
+            for (int q = 0; q < ax.nq; ++q) t_eval(ax, tag, e, ax.xq[e * ax.nq + q], &ax.tab[tag][(e * ax.nq + q) * K]);
+    }
+    // G^ = int Dd^T Pv (n0 x n0), M^ = int Dv^T Pd (n1 x n1), Section 4.1
+    const int n0 = ax.n0, n1 = ax.n1;
+    ax.G.assign(size_t(n0) * n0, 0.0);
+    ax.M.assign(size_t(n1) * n1, 0.0);
+    const int Kpv = p + 1, Kpd = p, Kdv = p, Kdd = p - 1;
+    for (int e = 0; e < N; ++e)
+        for (int q = 0; q < ax.nq; ++q) {
+            const double w = ax.wq[e * ax.nq + q];
+            const double* dd = &ax.tab[DD][(e * ax.nq + q) * Kdd];
+            const double* pv = &ax.tab[PV][(e * ax.nq + q) * Kpv];
+            const double* dv = &ax.tab[DV][(e * ax.nq + q) * Kdv];
+            const double* pd = &ax.tab[PD][(e * ax.nq + q) * Kpd];
+            for (int i = 0; i < Kdd; ++i)
+                for (int j = 0; j < Kpv; ++j) {
+                    const int r = e + i, cidx = e + j - 1;
+                    if (cidx >= 0 && cidx < n0) ax.G[r * n0 + cidx] += w * dd[i] * pv[j];
+                }
+            for (int i = 0; i < Kdv; ++i)
+                for (int j = 0; j < Kpd; ++j) ax.M[(e + i) * n1 + (e + j)] += w * dv[i] * pd[j];
+        }
+}
+
+std::vector<double> transpose_sq(const std::vector<double>& A, int n) {
+    std::vector<double> T(A.size());
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) T[j * n + i] = A[i * n + j];
+    return T;
+}
+
+}  // namespace
+}  // namespace kmx
+
+using namespace kmx;
+
+struct kmx_tspace {
+    int p[3] = {0, 0, 0}, N[3] = {0, 0, 0};
+    int pmax = 0, max_batch = 1;
+    int map_kind = 0;
+    double amplitude = 0.0;
+    int64_t n_e = 0, n_h = 0, nfield = 0, nelem = 0;
+    int npts = 0;
+    TAxis ax[3];
+    int dims[4][3][3];          // per space (SP_E..SP_D): [c][z, y, x]
+    int64_t comp_off[4][3];
+    int64_t pcomp_off[4][3];    // SP_B and SP_D patches
+    int psize[4] = {0, 0, 0, 0};
+    int psize_max = 0;
+    int64_t tab_off[3][4];
+    int64_t fac_off[3][4];      // [direction][F_G, F_M, F_GT, F_MT]
+    double* d_tab = nullptr;
+    double* d_fac = nullptr;
+    double* d_metric = nullptr;
+    double* d_inv_eps = nullptr;
+    double* d_inv_mu = nullptr;
+    double* d_patch = nullptr;
+    double* d_u = nullptr;      // curl output
+    double* d_y = nullptr;      // gathered mass output
+    double* d_t = nullptr;      // between the xy and z passes of a solve
+};
+
+namespace {
+
+kmx_status t_fail(kmx_status st, const std::string& msg) { return report_error(st, msg); }
+
+#define T_TRY(expr)                                                                          \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return t_fail(KMX_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define T_CHECK_LAUNCH()                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess) return t_fail(KMX_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+kmx_status t_upload(double** dst, const std::vector<double>& v) {
+    if (hipMalloc(dst, std::max<size_t>(v.size(), 1) * sizeof(double)) != hipSuccess)
+        return t_fail(KMX_E_OOM, "device allocation failed");
+    if (!v.empty()) T_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    return KMX_OK;
+}
+
+// the 2-form metric factor w DF^T DF / det DF per element and point
+kmx_status t_build_metric(kmx_tspace* ts, std::vector<double>& out) {
+    const TAxis &X = ts->ax[0], &Y = ts->ax[1], &Z = ts->ax[2];
+    const int npts = ts->npts;
+    out.assign(size_t(ts->nelem) * 6 * npts, 0.0);
+    for (int ez = 0; ez < Z.N; ++ez)
+        for (int ey = 0; ey < Y.N; ++ey)
+            for (int ex = 0; ex < X.N; ++ex) {
+                const int64_t elem = (int64_t(ez) * Y.N + ey) * X.N + ex;
+                for (int iz = 0; iz < Z.nq; ++iz)
+                    for (int iy = 0; iy < Y.nq; ++iy)
+                        for (int ix = 0; ix < X.nq; ++ix) {
+                            const double xh[3] = {X.xq[ex * X.nq + ix], Y.xq[ey * Y.nq + iy], Z.xq[ez * Z.nq + iz]};
+                            const double w = X.wq[ex * X.nq + ix] * Y.wq[ey * Y.nq + iy] * Z.wq[ez * Z.nq + iz];
+                            double J[9];
+                            for (int k = 0; k < 9; ++k) J[k] = (k % 4 == 0) ? 1.0 : 0.0;
+                            if (ts->map_kind == 1) {
+                                const double a = ts->amplitude;
+                                const double sx = std::sin(M_PI * xh[0]), sy = std::sin(M_PI * xh[1]),
+                                             sz = std::sin(M_PI * xh[2]);
+                                const double cx = std::cos(M_PI * xh[0]), cy = std::cos(M_PI * xh[1]),
+                                             cz = std::cos(M_PI * xh[2]);
+                                const double grad[3] = {M_PI * cx * sy * sz, M_PI * sx * cy * sz, M_PI * sx * sy * cz};
+                                for (int r = 0; r < 3; ++r)
+                                    for (int k = 0; k < 3; ++k) J[3 * r + k] += a * grad[k];
+                            }
+                            const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) -
+                                               J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                                               J[2] * (J[3] * J[7] - J[4] * J[6]);
+                            if (!(det > 0.0) || !std::isfinite(det))
+                                return t_fail(KMX_E_GEOMETRY, "det DF <= 0 at a quadrature point");
+                            const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+                            const int q = (iz * Y.nq + iy) * X.nq + ix;
+                            for (int k = 0; k < 6; ++k) {
+                                double s = 0.0;
+                                for (int r = 0; r < 3; ++r) s += J[3 * r + ii[k]] * J[3 * r + jj[k]];
+                                out[(size_t(elem) * 6 + k) * npts + q] = w * s / det;
+                            }
+                        }
+            }
+    return KMX_OK;
+}
+
+// 1/gamma per element (host values gamma, x fastest; NULL = 1)
+kmx_status t_upload_inverse(kmx_tspace* ts, const double* g, double* dst) {
+    std::vector<double> v(size_t(ts->nelem), 1.0);
+    if (g)
+        for (int64_t k = 0; k < ts->nelem; ++k) {
+            if (!(g[k] > 0.0) || !std::isfinite(g[k])) return t_fail(KMX_E_MATERIAL, "eps and mu must be positive");
+            v[k] = 1.0 / g[k];
+        }
+    T_TRY(hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    return KMX_OK;
+}
+
+// which_K1 = 1: K1 (blocks of eq. (4.2)); 0: K~1 (eq. (4.3)).  The factor of
+// direction a for component c.
+int t_pair_kind(int which_K1, int transpose, int c, int a) {
+    if (which_K1) return transpose ? (a == c ? F_MT : F_GT) : (a == c ? F_M : F_G);
+    return transpose ? (a == c ? F_G : F_M) : (a == c ? F_GT : F_MT);
+}
+
+// x = K^{-1} y (solve = 1) or K y (solve = 2), then out = (acc ? out : 0) + alpha x;
+// y and out hold `batch` fields of the layout of K's rows (= columns).
+void t_solve(kmx_tspace* ts, int which_K1, int transpose, const double* y, int64_t y_stride, double* out,
+             int64_t out_stride, double alpha, int accumulate, int solve, int batch, hipStream_t s) {
+    const int layout = which_K1 ? SP_D : SP_B;
+    XYArgs a{};
+    a.in = y;
+    a.in_stride = y_stride;
+    a.out = ts->d_t;
+    a.out_stride = ts->nfield;
+    for (int c = 0; c < 3; ++c) {
+        a.comp_off[c] = ts->comp_off[layout][c];
+        for (int k = 0; k < 3; ++k) a.dims[c][k] = ts->dims[layout][c][k];
+    }
+    // six factor sets per call: direction a's "along" (slot 2a) and "across" (2a + 1)
+    a.fac = ts->d_fac;
+    for (int ax = 0; ax < 3; ++ax) {
+        a.fac_off[2 * ax] = ts->fac_off[ax][t_pair_kind(which_K1, transpose, ax, ax)];
+        a.fac_off[2 * ax + 1] = ts->fac_off[ax][t_pair_kind(which_K1, transpose, (ax + 1) % 3, ax)];
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int ax = 0; ax < 3; ++ax) a.fac_id[c][ax] = 2 * ax + (ax == c ? 0 : 1);
+    a.n_src = 0;
+    a.solve = solve;
+    launch_xy(ts->pmax, a, batch, s);
+    ZArgs z{};
+    z.in = ts->d_t;
+    z.in_stride = ts->nfield;
+    z.out = out;
+    z.out_stride = out_stride;
+    for (int c = 0; c < 3; ++c) {
+        z.comp_off[c] = a.comp_off[c];
+        for (int k = 0; k < 3; ++k) z.dims[c][k] = a.dims[c][k];
+        z.fac_id[c] = a.fac_id[c][2];
+    }
+    z.fac = ts->d_fac;
+    for (int k = 0; k < 8; ++k) z.fac_off[k] = a.fac_off[k];
+    z.alpha = alpha;
+    z.accumulate = accumulate;
+    z.solve = solve;
+    launch_z(ts->pmax, z, batch, s);
+}
+
+// y = M x (space SP_B: M^2_{1/mu}; SP_D: M~^2_{1/eps}) for `batch` fields
+void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double* y, int64_t y_stride, int batch,
+            hipStream_t s) {
+    TMassArgs m{};
+    m.x = x;
+    m.x_stride = x_stride;
+    m.patch = ts->d_patch;
+    m.patch_stride = int64_t(ts->psize_max) * ts->nelem;
+    m.tab = ts->d_tab;
+    for (int a = 0; a < 3; ++a) {
+        for (int t = 0; t < 4; ++t) m.tab_off[a][t] = ts->tab_off[a][t];
+        m.p[a] = ts->p[a];
+        m.N[a] = ts->N[a];
+        m.nq[a] = ts->ax[a].nq;
+    }
+    m.space = space;
+    for (int c = 0; c < 3; ++c) {
+        m.comp_off[c] = ts->comp_off[space][c];
+        m.pcomp_off[c] = ts->pcomp_off[space][c];
+        for (int k = 0; k < 3; ++k) m.dims[c][k] = ts->dims[space][c][k];
+    }
+    m.psize = ts->psize[space];
+    m.metric = ts->d_metric;
+    m.npts = ts->npts;
+    m.inv_gamma = space == SP_B ? ts->d_inv_mu : ts->d_inv_eps;
+    hipLaunchKernelGGL(tmass_kernel, dim3(unsigned(ts->nelem), batch), dim3(64), 0, s, m);
+    TGatherArgs g{};
+    g.patch = ts->d_patch;
+    g.patch_stride = m.patch_stride;
+    g.out = y;
+    g.out_stride = y_stride;
+    for (int a = 0; a < 3; ++a) {
+        g.p[a] = ts->p[a];
+        g.N[a] = ts->N[a];
+    }
+    g.space = space;
+    for (int c = 0; c < 3; ++c) {
+        g.comp_off[c] = m.comp_off[c];
+        g.pcomp_off[c] = m.pcomp_off[c];
+        for (int k = 0; k < 3; ++k) g.dims[c][k] = m.dims[c][k];
+    }
+    g.psize = m.psize;
+    const int64_t n = space == SP_B ? ts->n_h : ts->n_e;
+    hipLaunchKernelGGL(tgather_kernel, dim3(unsigned((n + 255) / 256), batch), dim3(256), 0, s, g, n);
+}
+
+// out = beta out + alpha D^1 in (primal) or D~^1 in (dual)
+void t_curl(kmx_tspace* ts, int primal, const double* in, int64_t in_stride, double* out, int64_t out_stride,
+            double alpha, double beta, int batch, hipStream_t s) {
+    CurlArgs a{};
+    a.in = in;
+    a.in_stride = in_stride;
+    a.out = out;
+    a.out_stride = out_stride;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.primal = primal;
+    const int si = primal ? SP_E : SP_H, so = primal ? SP_B : SP_D;
+    for (int c = 0; c < 3; ++c) {
+        a.in_comp_off[c] = ts->comp_off[si][c];
+        a.out_comp_off[c] = ts->comp_off[so][c];
+        for (int k = 0; k < 3; ++k) {
+            a.in_dims[c][k] = ts->dims[si][c][k];
+            a.out_dims[c][k] = ts->dims[so][c][k];
+        }
+    }
+    launch_curl(a, primal ? ts->n_h : ts->n_e, batch, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* breaks_x, const double* breaks_y,
+                             const double* breaks_z, const kmx_map* map, int max_batch, kmx_tspace** out) {
+    if (!out || !p || !n_elem) return t_fail(KMX_E_ARG, "NULL argument");
+    *out = nullptr;
+    if (max_batch < 1) return t_fail(KMX_E_ARG, "max_batch < 1");
+    const int kind = map ? map->kind : 0;
+    if (kind != 0 && kind != 1) return t_fail(KMX_E_ARG, "per-direction spaces take map kinds 0 and 1");
+    for (int a = 0; a < 3; ++a) {
+        if (p[a] < 2 || p[a] > TP_MAX) return t_fail(KMX_E_ARG, "degree per direction must be 2..4");
+        if (n_elem[a] < 1 || n_elem[a] + p[a] - 1 > TLINE_MAX)
+            return t_fail(KMX_E_ARG, "elements per direction: 1 .. 77 - p");
+    }
+    kmx_tspace* ts = new kmx_tspace();
+    const double* br[3] = {breaks_x, breaks_y, breaks_z};
+    try {
+        for (int a = 0; a < 3; ++a) {
+            ts->p[a] = p[a];
+            ts->N[a] = n_elem[a];
+            t_build_axis(ts->ax[a], p[a], n_elem[a], br[a]);
+        }
+    } catch (const std::exception& ex) {
+        delete ts;
+        return t_fail(KMX_E_ARG, ex.what());
+    }
+    ts->pmax = std::max(p[0], std::max(p[1], p[2]));
+    ts->max_batch = max_batch;
+    ts->map_kind = kind;
+    ts->amplitude = map ? map->amplitude : 0.0;
+    ts->nelem = int64_t(n_elem[0]) * n_elem[1] * n_elem[2];
+    ts->npts = ts->ax[0].nq * ts->ax[1].nq * ts->ax[2].nq;
+    // per space: component dims (z, y, x), offsets, and patch windows
+    for (int sp = 0; sp < 4; ++sp) {
+        int64_t off = 0, poff = 0;
+        for (int c = 0; c < 3; ++c) {
+            ts->comp_off[sp][c] = off;
+            ts->pcomp_off[sp][c] = poff;
+            int64_t n = 1, w = 1;
+            for (int a = 0; a < 3; ++a) {
+                const int tag = space_tag(sp, c, a);
+                const int d = (tag == PV || tag == DD) ? ts->ax[a].n0 : ts->ax[a].n1;
+                ts->dims[sp][c][2 - a] = d;
+                n *= d;
+                w *= tag_support(p[a], tag);
+            }
+            off += n;
+            poff += w;
+        }
+        ts->psize[sp] = int(poff);
+        if (sp == SP_E) ts->n_e = off;
+        if (sp == SP_H) ts->n_h = off;
+    }
+    ts->psize_max = std::max(ts->psize[SP_B], ts->psize[SP_D]);
+    ts->nfield = std::max(ts->n_e, ts->n_h);
+    kmx_status st;
+    std::vector<double> tabs;
+    for (int a = 0; a < 3; ++a)
+        for (int t = 0; t < 4; ++t) {
+            ts->tab_off[a][t] = int64_t(tabs.size());
+            tabs.insert(tabs.end(), ts->ax[a].tab[t].begin(), ts->ax[a].tab[t].end());
+        }
+    if ((st = t_upload(&ts->d_tab, tabs)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
+    // banded LU factors of G^, M^ and their transposes per direction, all with
+    // the half bandwidth of the largest degree
+    std::vector<double> facs;
+    try {
+        for (int a = 0; a < 3; ++a) {
+            const TAxis& A = ts->ax[a];
+            const BandLU sets[4] = {band_lu(A.G, A.n0, ts->pmax - 1), band_lu(A.M, A.n1, ts->pmax - 1),
+                                    band_lu(transpose_sq(A.G, A.n0), A.n0, ts->pmax - 1),
+                                    band_lu(transpose_sq(A.M, A.n1), A.n1, ts->pmax - 1)};
+            for (int k = 0; k < 4; ++k) {
+                ts->fac_off[a][k] = int64_t(facs.size());
+                facs.insert(facs.end(), sets[k].L.begin(), sets[k].L.end());
+                facs.insert(facs.end(), sets[k].U.begin(), sets[k].U.end());
+                facs.insert(facs.end(), sets[k].dinv.begin(), sets[k].dinv.end());
+                facs.insert(facs.end(), sets[k].band.begin(), sets[k].band.end());
+            }
+        }
+    } catch (const std::exception& ex) {
+        kmx_destroy_tspace(ts);
+        return t_fail(KMX_E_ARG, std::string("pairing factors: ") + ex.what());
+    }
+    if ((st = t_upload(&ts->d_fac, facs)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
+    {
+        std::vector<double> met;
+        if ((st = t_build_metric(ts, met)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
+        if ((st = t_upload(&ts->d_metric, met)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
+    }
+    const size_t nf = size_t(ts->nfield) * max_batch;
+    if (hipMalloc(&ts->d_inv_eps, size_t(ts->nelem) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ts->d_inv_mu, size_t(ts->nelem) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ts->d_patch, size_t(ts->psize_max) * ts->nelem * max_batch * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ts->d_u, nf * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ts->d_y, nf * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ts->d_t, nf * sizeof(double)) != hipSuccess) {
+        kmx_destroy_tspace(ts);
+        return t_fail(KMX_E_OOM, "device allocation failed (scratch)");
+    }
+    if ((st = t_upload_inverse(ts, nullptr, ts->d_inv_eps)) != KMX_OK ||
+        (st = t_upload_inverse(ts, nullptr, ts->d_inv_mu)) != KMX_OK) {
+        kmx_destroy_tspace(ts);
+        return st;
+    }
+    *out = ts;
+    return KMX_OK;
+}
+
+void kmx_destroy_tspace(kmx_tspace* ts) {
+    if (!ts) return;
+    double* bufs[] = {ts->d_tab, ts->d_fac, ts->d_metric, ts->d_inv_eps, ts->d_inv_mu,
+                      ts->d_patch, ts->d_u, ts->d_y, ts->d_t};
+    for (double* b : bufs)
+        if (b) (void)hipFree(b);
+    delete ts;
+}
+
+kmx_status kmx_tspace_sizes(const kmx_tspace* ts, int64_t* n_e, int64_t* n_h) {
+    if (!ts) return t_fail(KMX_E_ARG, "space is NULL");
+    if (n_e) *n_e = ts->n_e;
+    if (n_h) *n_h = ts->n_h;
+    return KMX_OK;
+}
+
+kmx_status kmx_tspace_set_materials(kmx_tspace* ts, const double* eps_elem, const double* mu_elem) {
+    if (!ts) return t_fail(KMX_E_ARG, "space is NULL");
+    // validate both before changing either
+    for (const double* g : {eps_elem, mu_elem})
+        if (g)
+            for (int64_t k = 0; k < ts->nelem; ++k)
+                if (!(g[k] > 0.0) || !std::isfinite(g[k])) return t_fail(KMX_E_MATERIAL, "eps and mu must be positive");
+    kmx_status st;
+    if ((st = t_upload_inverse(ts, eps_elem, ts->d_inv_eps)) != KMX_OK) return st;
+    return t_upload_inverse(ts, mu_elem, ts->d_inv_mu);
+}
+
+kmx_status kmx_tspace_op_curl(kmx_tspace* ts, int which, const double* x, double* y, void* stream) {
+    if (!ts || !x || !y || (which != 0 && which != 1)) return t_fail(KMX_E_ARG, "bad argument");
+    const int primal = which == 0;
+    t_curl(ts, primal, x, primal ? ts->n_e : ts->n_h, y, primal ? ts->n_h : ts->n_e, 1.0, 0.0, 1,
+           static_cast<hipStream_t>(stream));
+    T_CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_tspace_op_mass(kmx_tspace* ts, int which, const double* x, double* y, void* stream) {
+    if (!ts || !x || !y || (which != 0 && which != 1)) return t_fail(KMX_E_ARG, "bad argument");
+    const int space = which == 0 ? SP_B : SP_D;
+    const int64_t n = which == 0 ? ts->n_h : ts->n_e;
+    t_mass(ts, space, x, n, y, n, 1, static_cast<hipStream_t>(stream));
+    T_CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_tspace_op_solve(kmx_tspace* ts, int which, int transpose, const double* y, double* x, void* stream) {
+    if (!ts || !x || !y || (which != 0 && which != 1)) return t_fail(KMX_E_ARG, "bad argument");
+    const int64_t n = which ? ts->n_e : ts->n_h;
+    t_solve(ts, which, transpose ? 1 : 0, y, n, x, n, 1.0, 0, 1, 1, static_cast<hipStream_t>(stream));
+    T_CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_tspace_op_pairing(kmx_tspace* ts, int which, const double* x, double* y, void* stream) {
+    if (!ts || !x || !y || (which != 0 && which != 1)) return t_fail(KMX_E_ARG, "bad argument");
+    const int64_t n = which ? ts->n_e : ts->n_h;
+    t_solve(ts, which, 0, x, n, y, n, 1.0, 0, 2, 1, static_cast<hipStream_t>(stream));
+    T_CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+kmx_status kmx_tspace_step(kmx_tspace* ts, double* E, double* H, double dt, int nsteps, int batch, int flags,
+                           void* stream) {
+    if (!ts || !E || !H) return t_fail(KMX_E_ARG, "NULL argument");
+    if (batch < 1 || batch > ts->max_batch) return t_fail(KMX_E_ARG, "batch out of range");
+    if (nsteps < 0) return t_fail(KMX_E_ARG, "nsteps < 0");
+    if (!std::isfinite(dt)) return t_fail(KMX_E_ARG, "dt not finite");
+    const int track = flags & KMX_TRACK_DB;
+    const int64_t es = ts->n_e * (1 + track), hs = ts->n_h * (1 + track);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int n = 0; n < nsteps; ++n) {
+        // h -= dt K~1^{-1} M D^1 e   (b -= dt D^1 e)
+        t_curl(ts, 1, E, es, ts->d_u, ts->nfield, 1.0, 0.0, batch, s);
+        if (track) t_curl(ts, 1, E, es, H + ts->n_h, hs, -dt, 1.0, batch, s);
+        t_mass(ts, SP_B, ts->d_u, ts->nfield, ts->d_y, ts->nfield, batch, s);
+        t_solve(ts, 0, 0, ts->d_y, ts->nfield, H, hs, -dt, 1, 1, batch, s);
+        // e += dt K1^{-1} M~ D~^1 h   (d += dt D~^1 h)
+        t_curl(ts, 0, H, hs, ts->d_u, ts->nfield, 1.0, 0.0, batch, s);
+        if (track) t_curl(ts, 0, H, hs, E + ts->n_e, es, dt, 1.0, batch, s);
+        t_mass(ts, SP_D, ts->d_u, ts->nfield, ts->d_y, ts->nfield, batch, s);
+        t_solve(ts, 1, 0, ts->d_y, ts->nfield, E, es, dt, 1, 1, batch, s);
+    }
+    T_CHECK_LAUNCH();
+    return KMX_OK;
+}
+
+}  // extern "C"

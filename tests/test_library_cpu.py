@@ -83,3 +83,34 @@ def test_argument_errors_of_the_lifting_and_profiling_entry_points():
     assert L.kmx_probe_forward_noalloc(None, None, None, d(0.1), 1, None, None) == 1
     assert L.kmx_last_error().decode()
 
+
+
+def test_argument_errors_of_the_per_direction_spaces():
+    """kmx_create_tspace refuses degrees, element counts, breakpoints and map
+    kinds it does not take before any device work; the other per-direction
+    entry points refuse a NULL space."""
+    K, L = _lib()
+    h = ctypes.c_void_p()
+    m = K._Map(0, 0.0, None)
+    I3 = ctypes.c_int * 3
+
+    def create(p, n, bx=None, mp=m):
+        return L.kmx_create_tspace(I3(*p), I3(*n), bx, None, None, ctypes.byref(mp), 1, ctypes.byref(h))
+
+    for p, n in (((1, 3, 3), (4, 4, 4)), ((3, 5, 3), (4, 4, 4)), ((3, 3, 3), (4, 0, 4)),
+                 ((3, 3, 4), (4, 4, 74))):
+        assert create(p, n) == 1, (p, n)
+        assert L.kmx_last_error().decode()
+    bad = (ctypes.c_double * 3)(0.2, 0.6, 0.5)  # not increasing
+    assert create((3, 3, 3), (4, 4, 4), ctypes.cast(bad, ctypes.c_void_p)) == 1
+    edge = (ctypes.c_double * 3)(0.0, 0.5, 0.7)  # a breakpoint on the boundary
+    assert create((3, 3, 3), (4, 4, 4), ctypes.cast(edge, ctypes.c_void_p)) == 1
+    assert create((3, 3, 3), (4, 4, 4), mp=K._Map(2, 0.0, None)) == 1
+    assert L.kmx_create_tspace(None, None, None, None, None, None, 1, ctypes.byref(h)) == 1
+    a = ctypes.c_int64()
+    assert L.kmx_tspace_sizes(None, ctypes.byref(a), None) == 1
+    assert L.kmx_tspace_step(None, None, None, 0.1, 1, 1, 0, None) == 1
+    assert L.kmx_tspace_set_materials(None, None, None) == 1
+    assert L.kmx_tspace_op_mass(None, 0, None, None, None) == 1
+    assert L.kmx_tspace_op_solve(None, 0, 0, None, None, None) == 1
+    L.kmx_destroy_tspace(None)  # accepted

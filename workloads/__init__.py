@@ -28,6 +28,7 @@ PURPOSE = {
     "fd": 5,
     "field": 6,
     "eps_true": 7,
+    "mu": 8,
 }
 
 #: amplitude of the deformed-cube map x -> x + a*sin(pi x)sin(pi y)sin(pi z)
