@@ -566,8 +566,97 @@ def profile_run(K, W, torch, p, N, steps):
     Hb = torch.zeros(B * Gb.n_h, dtype=torch.float64, device="cuda")
     Gb.step(Eb, Hb, 1e-3, nsteps=10, batch=B)
     torch.cuda.synchronize()
+    del Gb, Eb, Hb
+    # two steps of the per-direction workload (degrees (3, 3, 2), 64 x 48 x 32 graded)
+    cfg = W.ANISO_FULL
+    br = tuple(W.graded_breaks(cfg["n"][a], cfg["ratio"][a]) for a in range(3))
+    Ga = K.TSpace(cfg["p"], cfg["n"], br, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+    Ga.set_materials(eps=W.eps_elements_aniso(cfg["n"], 60))
+    Ea = torch.tensor(W.random_vector(2 * Ga.n_e, 62, 1), dtype=torch.float64, device="cuda")
+    Ha = torch.tensor(W.random_vector(2 * Ga.n_h, 62, 2), dtype=torch.float64, device="cuda")
+    Ga.step(Ea, Ha, 1e-4, nsteps=2, flags=K.TRACK_DB)
+    torch.cuda.synchronize()
     return {"profile_run": {"copy_bytes_each_way": n * 8, "copies": 3, "steps": steps, "p": p, "N": N,
-                            "mixed_steps": 2, "batched": {"members": B, "N": Nb, "steps": 10}}}
+                            "mixed_steps": 2, "batched": {"members": B, "N": Nb, "steps": 10},
+                            "aniso_steps": 2}}
+
+
+def aniso_support(p, space, c, a):
+    """Functions of component c nonzero on one element along direction a: the
+    2-form space B has the degree-p value basis (p + 1) along c and the
+    derivative basis (p) across; D has p along c and p - 1 across."""
+    if space == "B":
+        return p[a] + 1 if a == c else p[a]
+    return p[a] if a == c else p[a] - 1
+
+
+def aniso_window(p, space):
+    """Doubles of one element's window of all three components."""
+    return sum(aniso_support(p, space, c, 0) * aniso_support(p, space, c, 1) * aniso_support(p, space, c, 2)
+               for c in range(3))
+
+
+def aniso_flops_per_element(p, space):
+    """FLOPs of the per-element mass kernel for one element: per component the
+    three interpolation passes and the three integration passes (2 flops per
+    multiply-add), plus 18 flops per Gauss point for u = (1/gamma) G v."""
+    nq = [pa + 1 for pa in p]
+    tot = 0
+    for c in range(3):
+        Kx, Ky, Kz = (aniso_support(p, space, c, a) for a in range(3))
+        fwd = Kz * Ky * nq[0] * Kx + Kz * nq[1] * nq[0] * Ky + nq[2] * nq[1] * nq[0] * Kz
+        tot += 2 * 2 * fwd
+    return tot + 18 * nq[0] * nq[1] * nq[2]
+
+
+def aniso_timing(K, W, torch, steps=50, reps=20):
+    """Per-direction degrees, knot vectors and element counts (Section 4.1):
+    degrees (3, 3, 2), 64 x 48 x 32 geometrically graded elements (size ratios
+    1.02, 1, 0.97 between neighbours), the deformed cube, eps in [1, 4] and mu
+    in [1, 2] per element, b/d tracking, dt = 1e-4; `steps` eager steps, then
+    `reps` mass applies of each 2-form space timed alone."""
+    cfg = W.ANISO_FULL
+    br = tuple(W.graded_breaks(cfg["n"][a], cfg["ratio"][a]) for a in range(3))
+    G = K.TSpace(cfg["p"], cfg["n"], br, map_kind=1, amplitude=W.DEFORMED_AMPLITUDE)
+    G.set_materials(eps=W.eps_elements_aniso(cfg["n"], 60), mu=W.eps_elements_aniso(cfg["n"], 61, 1.0, 2.0, "mu"))
+    dt = 1e-4
+    E = torch.tensor(W.random_vector(2 * G.n_e, 62, 1), dtype=torch.float64, device="cuda")
+    H = torch.tensor(W.random_vector(2 * G.n_h, 62, 2), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    G.step(E, H, dt, nsteps=3, flags=K.TRACK_DB)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    G.step(E, H, dt, nsteps=steps, flags=K.TRACK_DB)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    nel = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+    npts = (cfg["p"][0] + 1) * (cfg["p"][1] + 1) * (cfg["p"][2] + 1)
+    mass = {}
+    for which, n in (("B", G.n_h), ("D", G.n_e)):
+        x = torch.tensor(W.random_vector(n, 63, 0), dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        G.op_mass(which, x, y)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            G.op_mass(which, x, y)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) / reps * 1e3
+        # algorithmic bytes of one apply (element kernel + gather): the metric
+        # (6 doubles per point), 1/gamma per element, the input field, the
+        # per-element windows written and read back once, the output field
+        win = aniso_window(cfg["p"], which)
+        flops = aniso_flops_per_element(cfg["p"], which) * nel
+        bytes_ = 8.0 * (6 * npts * nel + nel + 2 * n + 2 * win * nel)
+        mass[which] = {"us_per_apply": round(us, 2), "algorithmic_bytes": int(bytes_),
+                       "GBps": round(bytes_ / (us * 1e-6) / 1e9, 1), "flops": int(flops),
+                       "TFLOPs": round(flops / (us * 1e-6) / 1e12, 2)}
+    return {"workload": "p=(3,3,2), 64x48x32 graded elements, deformed cube, eps/mu per element, tracking",
+            "n_e": G.n_e, "n_h": G.n_h, "ms_per_step": round(ms, 4),
+            "value": (G.n_e + G.n_h) / (ms * 1e-3), "unit": "DOF-updates/s", "mass_apply": mass}
 
 
 def batched_timing(K, W, torch, steps=400):
@@ -641,6 +730,8 @@ def main():
     ap.add_argument("--only-scheme1", action="store_true")
     ap.add_argument("--no-time-order", action="store_true")
     ap.add_argument("--no-coax", action="store_true")
+    ap.add_argument("--no-aniso", action="store_true")
+    ap.add_argument("--only-aniso", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -661,6 +752,9 @@ def main():
         return
     if args.only_batched:
         print(json.dumps({"batched": batched_timing(K, W, torch)}), flush=True)
+        return
+    if args.only_aniso:
+        print(json.dumps({"aniso": aniso_timing(K, W, torch)}), flush=True)
         return
     if args.only_mixed:
         print(json.dumps({"mixed": mixed_vs_fp64(K, W, torch, p, N, args.steps, W.eps_elements(N, 0)),
@@ -851,6 +945,11 @@ def main():
         log("quarter coax with the TEM data lifted")
         coax["tem_lifted"] = guarded("coax_tem", coax_tem_timing, K, W, torch)
 
+    aniso = None
+    if not args.no_aniso:
+        log("per-direction degrees, knots and element counts")
+        aniso = guarded("aniso", aniso_timing, K, W, torch)
+
     scheme1 = None
     if not args.no_scheme1:
         log("first scheme")
@@ -902,6 +1001,7 @@ def main():
         "scheme1": scheme1,
         "time_order": time_order,
         "coax": coax,
+        "aniso": aniso,
     }
     print(json.dumps(out), flush=True)
 

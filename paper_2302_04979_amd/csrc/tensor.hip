@@ -55,7 +55,6 @@ struct TMassArgs {
     int64_t pcomp_off[3];        // per-element patch: component offsets
     int psize;                   // patch doubles per element
     const double* metric;        // [element][6][point]
-    int npts;
     const double* inv_gamma;     // per element (x fastest)
 };
 
@@ -77,126 +76,240 @@ __host__ __device__ inline int t_support(const int p[3], int space, int c, int a
     return tag_support(p[a], space_tag(space, c, a));
 }
 
+// Block index -> work item so that each of the 8 XCDs (which take blocks
+// round robin) walks one contiguous range: neighbouring elements, which share
+// window entries and patch lines, then meet in the same L2.
+__device__ inline int t_xcd_order(int block, int nblocks) {
+    constexpr int XCD = 8;
+    const int per = nblocks / XCD;
+    return block < per * XCD ? (block % XCD) * per + block / XCD : block;
+}
+
+// Window of component C of a 2-form space on one element, per direction:
+// sizes and the offset of local index 0 in the global numbering.
+template <int PX, int PY, int PZ, int SPACE, int C>
+struct TWin {
+    static constexpr int Kx = tag_support(PX, space_tag(SPACE, C, 0));
+    static constexpr int Ky = tag_support(PY, space_tag(SPACE, C, 1));
+    static constexpr int Kz = tag_support(PZ, space_tag(SPACE, C, 2));
+    static constexpr int size = Kx * Ky * Kz;
+    static constexpr int ox = tag_offset(space_tag(SPACE, C, 0));
+    static constexpr int oy = tag_offset(space_tag(SPACE, C, 1));
+    static constexpr int oz = tag_offset(space_tag(SPACE, C, 2));
+};
+
+// One output of each sum-factorisation pass for component C (tables [q][k]
+// with row length TK).  Interpolation: x pass T1[kz][ky][qx], y pass
+// T2[kz][qy][qx], z pass V[qz][qy][qx]; integration: z pass T2[kz][qy][qx],
+// y pass T1[kz][ky][qx], x pass out[kz][ky][kx].
+template <int PX, int PY, int PZ, int SPACE, int C>
+struct TPass {
+    using Wn = TWin<PX, PY, PZ, SPACE, C>;
+    static constexpr int NQX = PX + 1, NQY = PY + 1, NQZ = PZ + 1;
+    static constexpr int N1 = Wn::Kz * Wn::Ky * NQX;   // T1 entries
+    static constexpr int N2 = Wn::Kz * NQY * NQX;      // T2 entries
+    static constexpr int NP = NQZ * NQY * NQX;         // points
+    __device__ static double fx(int i, const double* X, const double* Tx) {
+        const int qx = i % NQX, r = i / NQX;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < Wn::Kx; ++k) s += Tx[qx * TK + k] * X[r * Wn::Kx + k];
+        return s;
+    }
+    __device__ static double fy(int i, const double* T1, const double* Ty) {
+        const int qx = i % NQX, qy = (i / NQX) % NQY, kz = i / (NQX * NQY);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < Wn::Ky; ++k) s += Ty[qy * TK + k] * T1[(kz * Wn::Ky + k) * NQX + qx];
+        return s;
+    }
+    __device__ static double fz(int i, const double* T2, const double* Tz) {
+        const int r = i % (NQY * NQX), qz = i / (NQY * NQX);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < Wn::Kz; ++k) s += Tz[qz * TK + k] * T2[k * NQY * NQX + r];
+        return s;
+    }
+    __device__ static double bz(int i, const double* V, const double* Tz) {
+        const int r = i % (NQY * NQX), kz = i / (NQY * NQX);
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQZ; ++q) s += Tz[q * TK + kz] * V[q * NQY * NQX + r];
+        return s;
+    }
+    __device__ static double by(int i, const double* T2, const double* Ty) {
+        const int qx = i % NQX, ky = (i / NQX) % Wn::Ky, kz = i / (NQX * Wn::Ky);
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQY; ++q) s += Ty[q * TK + ky] * T2[(kz * NQY + q) * NQX + qx];
+        return s;
+    }
+    __device__ static double bx(int i, const double* T1, const double* Tx) {
+        const int kx = i % Wn::Kx, r = i / Wn::Kx;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQX; ++q) s += Tx[q * TK + kx] * T1[r * NQX + q];
+        return s;
+    }
+};
+
+// Interpolation of one component at the Gauss points (x, y, z passes) and
+// integration against its test functions (z, y, x passes, into `out`).
+template <class Qc>
+__device__ inline void t_interp(const double* X, const double* Tx, const double* Ty, const double* Tz, double* T1,
+                                double* T2, double* V, int tid) {
+    for (int i = tid; i < Qc::N1; i += 64) T1[i] = Qc::fx(i, X, Tx);
+    __syncthreads();
+    for (int i = tid; i < Qc::N2; i += 64) T2[i] = Qc::fy(i, T1, Ty);
+    __syncthreads();
+    for (int i = tid; i < Qc::NP; i += 64) V[i] = Qc::fz(i, T2, Tz);
+    __syncthreads();
+}
+
+template <class Qc>
+__device__ inline void t_integrate(const double* V, const double* Tx, const double* Ty, const double* Tz, double* T1,
+                                   double* T2, double* out, int tid) {
+    for (int i = tid; i < Qc::N2; i += 64) T2[i] = Qc::bz(i, V, Tz);
+    __syncthreads();
+    for (int i = tid; i < Qc::N1; i += 64) T1[i] = Qc::by(i, T2, Ty);
+    __syncthreads();
+    for (int i = tid; i < Qc::Wn::size; i += 64) out[i] = Qc::bx(i, T1, Tx);
+    __syncthreads();  // T1 and T2 are reused
+}
+
+// The window of component C: requested into registers (two entries per lane).
+template <int PX, int PY, int PZ, int SPACE, int C>
+__device__ inline void t_window_load(const double* x, const TMassArgs& A, const int e3[3], int tid, double (&r)[2]) {
+    using Wn = TWin<PX, PY, PZ, SPACE, C>;
+    static_assert(Wn::size <= 128, "two window entries per lane");
+    const int nx = A.dims[C][2], ny = A.dims[C][1], nz = A.dims[C][0];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = tid + 64 * j;
+        const int kx = i % Wn::Kx, ky = (i / Wn::Kx) % Wn::Ky, kz = i / (Wn::Kx * Wn::Ky);
+        const int gx = e3[0] + Wn::ox + kx, gy = e3[1] + Wn::oy + ky, gz = e3[2] + Wn::oz + kz;
+        const bool ok = i < Wn::size && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+        r[j] = ok ? x[A.comp_off[C] + (int64_t(gz) * ny + gy) * nx + gx] : 0.0;
+    }
+}
+
+// One workgroup (one wave) per element: every global load (the 1D tables, the
+// three input windows, the metric, 1/gamma) is requested in one round; the
+// sum-factorised passes run out of LDS with compile-time sizes, one component
+// at a time; the metric stays in registers (two points per lane).
+template <int PX, int PY, int PZ, int SPACE>
 __global__ void __launch_bounds__(64) tmass_kernel(const TMassArgs A) {
-    __shared__ double X[TCUBE], T1[TCUBE], T2[TCUBE];
-    __shared__ double V[3][TCUBE];
+    constexpr int NQX = PX + 1, NQY = PY + 1, NQZ = PZ + 1, NPTS = NQX * NQY * NQZ;
+    static_assert(NPTS <= 128, "two points per lane");
+    constexpr int TBN = 3 * 2 * TQ * TK;  // table entries
+    constexpr int TBR = (TBN + 63) / 64;
+    using W0 = TWin<PX, PY, PZ, SPACE, 0>;
+    using W1 = TWin<PX, PY, PZ, SPACE, 1>;
+    using W2 = TWin<PX, PY, PZ, SPACE, 2>;
+    // LDS sized for these degrees: the windows, the two pass buffers, the
+    // point values and the tables
+    constexpr int WMAX = W0::size > W1::size ? (W0::size > W2::size ? W0::size : W2::size)
+                                             : (W1::size > W2::size ? W1::size : W2::size);
+    using Q0 = TPass<PX, PY, PZ, SPACE, 0>;
+    using Q1 = TPass<PX, PY, PZ, SPACE, 1>;
+    using Q2 = TPass<PX, PY, PZ, SPACE, 2>;
+    // the pass buffers, reused by the three components
+    constexpr int T1N = Q0::N1 > Q1::N1 ? (Q0::N1 > Q2::N1 ? Q0::N1 : Q2::N1) : (Q1::N1 > Q2::N1 ? Q1::N1 : Q2::N1);
+    constexpr int T2N = Q0::N2 > Q1::N2 ? (Q0::N2 > Q2::N2 ? Q0::N2 : Q2::N2) : (Q1::N2 > Q2::N2 ? Q1::N2 : Q2::N2);
+    __shared__ double X[3][WMAX], T1[T1N], T2[T2N];
+    __shared__ double V[3][NPTS];
     __shared__ double tb[3][2][TQ * TK];  // per direction: the along and across tags, [q][k]
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
-    const int elem = blockIdx.x;
+    const int elem = t_xcd_order(blockIdx.x, gridDim.x);
     const int e3[3] = {elem % A.N[0], (elem / A.N[0]) % A.N[1], elem / (A.N[0] * A.N[1])};
-    const int nqx = A.nq[0], nqy = A.nq[1], nqz = A.nq[2];
-
-    // the 1D tables of this element, both tags of the space per direction
-    for (int i = tid; i < 3 * 2 * TQ * TK; i += 64) {
-        const int a = i / (2 * TQ * TK), s = (i / (TQ * TK)) % 2, q = (i / TK) % TQ, k = i % TK;
-        const int tag = space_tag(A.space, s == 0 ? a : (a + 1) % 3, a);
-        const int K = tag_support(A.p[a], tag);
-        double v = 0.0;
-        if (q < A.nq[a] && k < K) v = A.tab[A.tab_off[a][tag] + (int64_t(e3[a]) * A.nq[a] + q) * K + k];
-        tb[a][s][q * TK + k] = v;
-    }
     const double* x = A.x + int64_t(b) * A.x_stride;
+    constexpr int PD[3] = {PX, PY, PZ};
+    constexpr int NQ[3] = {NQX, NQY, NQZ};
 
-    // interpolation to the Gauss points, one component at a time: x, y, z passes
-    for (int c = 0; c < 3; ++c) {
-        const int Kx = t_support(A.p, A.space, c, 0), Ky = t_support(A.p, A.space, c, 1),
-                  Kz = t_support(A.p, A.space, c, 2);
-        const double* Tx = tb[0][c == 0 ? 0 : 1];
-        const double* Ty = tb[1][c == 1 ? 0 : 1];
-        const double* Tz = tb[2][c == 2 ? 0 : 1];
-        const int ox = tag_offset(space_tag(A.space, c, 0)), oy = tag_offset(space_tag(A.space, c, 1)),
-                  oz = tag_offset(space_tag(A.space, c, 2));
-        const int nx = A.dims[c][2], ny = A.dims[c][1], nz = A.dims[c][0];
-        __syncthreads();  // earlier readers of X, T1, T2 are done
-        for (int i = tid; i < Kx * Ky * Kz; i += 64) {
-            const int kx = i % Kx, ky = (i / Kx) % Ky, kz = i / (Kx * Ky);
-            const int gx = e3[0] + ox + kx, gy = e3[1] + oy + ky, gz = e3[2] + oz + kz;
-            const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-            X[i] = ok ? x[A.comp_off[c] + (int64_t(gz) * ny + gy) * nx + gx] : 0.0;
+    // ---- one round of loads ----
+    double rt[TBR], rw0[2], rw1[2], rw2[2], rg[2][6];
+#pragma unroll
+    for (int j = 0; j < TBR; ++j) {
+        const int i = tid + 64 * j;
+        const int a = i / (2 * TQ * TK), s = (i / (TQ * TK)) % 2, q = (i / TK) % TQ, k = i % TK;
+        double v = 0.0;
+        if (i < TBN) {
+            const int tag = space_tag(SPACE, s == 0 ? a : (a + 1) % 3, a);
+            const int K = tag_support(PD[a], tag);
+            if (q < NQ[a] && k < K) v = A.tab[A.tab_off[a][tag] + (int64_t(e3[a]) * NQ[a] + q) * K + k];
         }
-        __syncthreads();
-        for (int i = tid; i < Kz * Ky * nqx; i += 64) {
-            const int qx = i % nqx, r = i / nqx;  // r = kz * Ky + ky
-            double s = 0.0;
-            for (int k = 0; k < Kx; ++k) s += Tx[qx * TK + k] * X[r * Kx + k];
-            T1[i] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < Kz * nqy * nqx; i += 64) {
-            const int qx = i % nqx, qy = (i / nqx) % nqy, kz = i / (nqx * nqy);
-            double s = 0.0;
-            for (int k = 0; k < Ky; ++k) s += Ty[qy * TK + k] * T1[(kz * Ky + k) * nqx + qx];
-            T2[i] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < nqz * nqy * nqx; i += 64) {
-            const int r = i % (nqy * nqx), qz = i / (nqy * nqx);
-            double s = 0.0;
-            for (int k = 0; k < Kz; ++k) s += Tz[qz * TK + k] * T2[k * nqy * nqx + r];
-            V[c][i] = s;
+        rt[j] = v;
+    }
+    t_window_load<PX, PY, PZ, SPACE, 0>(x, A, e3, tid, rw0);
+    t_window_load<PX, PY, PZ, SPACE, 1>(x, A, e3, tid, rw1);
+    t_window_load<PX, PY, PZ, SPACE, 2>(x, A, e3, tid, rw2);
+    const double* gm = A.metric + int64_t(elem) * 6 * NPTS;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int q = tid + 64 * j;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) rg[j][k] = q < NPTS ? gm[k * NPTS + q] : 0.0;
+    }
+    const double ig = A.inv_gamma[elem];
+    // ---- into LDS ----
+#pragma unroll
+    for (int j = 0; j < TBR; ++j) {
+        const int i = tid + 64 * j;
+        if (i < TBN) (&tb[0][0][0])[i] = rt[j];
+    }
+
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = tid + 64 * j;
+        if (i < WMAX) {
+            X[0][i] = rw0[j];
+            X[1][i] = rw1[j];
+            X[2][i] = rw2[j];
         }
     }
     __syncthreads();
-    // the metric and the material at every point: u = (1 / gamma) G v
-    {
-        const double ig = A.inv_gamma[elem];
-        const double* g = A.metric + int64_t(elem) * 6 * A.npts;
-        for (int q = tid; q < A.npts; q += 64) {
-            const double g0 = g[q], g1 = g[A.npts + q], g2 = g[2 * A.npts + q], g3 = g[3 * A.npts + q],
-                         g4 = g[4 * A.npts + q], g5 = g[5 * A.npts + q];
+    // ---- interpolation to the Gauss points, one component at a time
+    // (component c's tables: tb[a][a == c ? 0 : 1]) ----
+    t_interp<Q0>(X[0], tb[0][0], tb[1][1], tb[2][1], T1, T2, V[0], tid);
+    t_interp<Q1>(X[1], tb[0][1], tb[1][0], tb[2][1], T1, T2, V[1], tid);
+    t_interp<Q2>(X[2], tb[0][1], tb[1][1], tb[2][0], T1, T2, V[2], tid);
+    // ---- u = (1 / gamma) G v at every point ----
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int q = tid + 64 * j;
+        if (q < NPTS) {
             const double v0 = V[0][q], v1 = V[1][q], v2 = V[2][q];
-            V[0][q] = ig * (g0 * v0 + g3 * v1 + g4 * v2);
-            V[1][q] = ig * (g3 * v0 + g1 * v1 + g5 * v2);
-            V[2][q] = ig * (g4 * v0 + g5 * v1 + g2 * v2);
+            V[0][q] = ig * (rg[j][0] * v0 + rg[j][3] * v1 + rg[j][4] * v2);
+            V[1][q] = ig * (rg[j][3] * v0 + rg[j][1] * v1 + rg[j][5] * v2);
+            V[2][q] = ig * (rg[j][4] * v0 + rg[j][5] * v1 + rg[j][2] * v2);
         }
     }
-    // integration against the test functions: z, y, x passes, into the patch
+    __syncthreads();
     double* patch = A.patch + int64_t(b) * A.patch_stride + int64_t(elem) * A.psize;
-    for (int c = 0; c < 3; ++c) {
-        const int Kx = t_support(A.p, A.space, c, 0), Ky = t_support(A.p, A.space, c, 1),
-                  Kz = t_support(A.p, A.space, c, 2);
-        const double* Tx = tb[0][c == 0 ? 0 : 1];
-        const double* Ty = tb[1][c == 1 ? 0 : 1];
-        const double* Tz = tb[2][c == 2 ? 0 : 1];
-        __syncthreads();
-        for (int i = tid; i < Kz * nqy * nqx; i += 64) {
-            const int r = i % (nqy * nqx), kz = i / (nqy * nqx);
-            double s = 0.0;
-            for (int q = 0; q < nqz; ++q) s += Tz[q * TK + kz] * V[c][q * nqy * nqx + r];
-            T2[i] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < Kz * Ky * nqx; i += 64) {
-            const int qx = i % nqx, ky = (i / nqx) % Ky, kz = i / (nqx * Ky);
-            double s = 0.0;
-            for (int q = 0; q < nqy; ++q) s += Ty[q * TK + ky] * T2[(kz * nqy + q) * nqx + qx];
-            T1[i] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < Kz * Ky * Kx; i += 64) {
-            const int kx = i % Kx, r = i / Kx;  // r = kz * Ky + ky
-            double s = 0.0;
-            for (int q = 0; q < nqx; ++q) s += Tx[q * TK + kx] * T1[r * nqx + q];
-            patch[A.pcomp_off[c] + i] = s;
-        }
-    }
+    // ---- integration against the test functions, into the patch ----
+    t_integrate<Q0>(V[0], tb[0][0], tb[1][1], tb[2][1], T1, T2, patch + A.pcomp_off[0], tid);
+    t_integrate<Q1>(V[1], tb[0][1], tb[1][0], tb[2][1], T1, T2, patch + A.pcomp_off[1], tid);
+    t_integrate<Q2>(V[2], tb[0][1], tb[1][1], tb[2][0], T1, T2, patch + A.pcomp_off[2], tid);
 }
 
 // out_i = sum of the patch entries of the elements whose window holds
 // function i, by increasing z, y, x element index.
+template <int PX, int PY, int PZ, int SPACE>
 __global__ void __launch_bounds__(256) tgather_kernel(const TGatherArgs A, int64_t n) {
     const int b = blockIdx.y;
-    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t i = int64_t(t_xcd_order(blockIdx.x, gridDim.x)) * 256 + threadIdx.x;
     if (i >= n) return;
     const int c = i >= A.comp_off[2] ? 2 : (i >= A.comp_off[1] ? 1 : 0);
     const int64_t li = i - A.comp_off[c];
     const int nx = A.dims[c][2], ny = A.dims[c][1];
     const int g[3] = {int(li % nx), int((li / nx) % ny), int(li / (int64_t(nx) * ny))};
+    constexpr int PD[3] = {PX, PY, PZ};
     int K[3], o[3], lo[3], hi[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int tag = space_tag(A.space, c, a);
-        K[a] = tag_support(A.p[a], tag);
+        const int tag = space_tag(SPACE, c, a);
+        K[a] = tag_support(PD[a], tag);
         o[a] = tag_offset(tag);
         lo[a] = max(0, g[a] - o[a] - K[a] + 1);
         hi[a] = min(A.N[a] - 1, g[a] - o[a]);
@@ -211,6 +324,36 @@ __global__ void __launch_bounds__(256) tgather_kernel(const TGatherArgs A, int64
                 s += patch[elem * A.psize + k];
             }
     A.out[int64_t(b) * A.out_stride + i] = s;
+}
+
+template <int PX, int PY, int PZ>
+void t_launch_p(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int64_t nelem) {
+    const dim3 gm(unsigned(nelem), batch), gg(unsigned((n + 255) / 256), batch);
+    if (m.space == SP_B) {
+        hipLaunchKernelGGL((tmass_kernel<PX, PY, PZ, SP_B>), gm, dim3(64), 0, s, m);
+        hipLaunchKernelGGL((tgather_kernel<PX, PY, PZ, SP_B>), gg, dim3(256), 0, s, g, n);
+    } else {
+        hipLaunchKernelGGL((tmass_kernel<PX, PY, PZ, SP_D>), gm, dim3(64), 0, s, m);
+        hipLaunchKernelGGL((tgather_kernel<PX, PY, PZ, SP_D>), gg, dim3(256), 0, s, g, n);
+    }
+}
+
+// the mass kernel and the gather for the space's degrees (2..4 each)
+void t_launch_mass(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int64_t nelem) {
+    const int code = (m.p[0] - 2) * 9 + (m.p[1] - 2) * 3 + (m.p[2] - 2);
+#define TL(PX, PY, PZ)                                                       \
+    case (PX - 2) * 9 + (PY - 2) * 3 + (PZ - 2):                             \
+        t_launch_p<PX, PY, PZ>(m, g, n, batch, s, nelem);                    \
+        return;
+#define TL3(PX, PY) TL(PX, PY, 2) TL(PX, PY, 3) TL(PX, PY, 4)
+    switch (code) {
+        TL3(2, 2) TL3(2, 3) TL3(2, 4)
+        TL3(3, 2) TL3(3, 3) TL3(3, 4)
+        TL3(4, 2) TL3(4, 3) TL3(4, 4)
+        default: return;
+    }
+#undef TL3
+#undef TL
 }
 
 // ---------------------------------------------------------------------------
@@ -361,7 +504,9 @@ kmx_status t_upload(double** dst, const std::vector<double>& v) {
     return KMX_OK;
 }
 
-// the 2-form metric factor w DF^T DF / det DF per element and point
+// the 2-form metric factor w DF^T DF / det DF per element and point, for the
+// identity and the deformed cube F(x) = x + a s(x) (1, 1, 1),
+// s = sin(pi x) sin(pi y) sin(pi z): DF = I + a 1 (grad s)^T
 kmx_status t_build_metric(kmx_tspace* ts, std::vector<double>& out) {
     const TAxis &X = ts->ax[0], &Y = ts->ax[1], &Z = ts->ax[2];
     const int npts = ts->npts;
@@ -395,9 +540,9 @@ kmx_status t_build_metric(kmx_tspace* ts, std::vector<double>& out) {
                             const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
                             const int q = (iz * Y.nq + iy) * X.nq + ix;
                             for (int k = 0; k < 6; ++k) {
-                                double s = 0.0;
-                                for (int r = 0; r < 3; ++r) s += J[3 * r + ii[k]] * J[3 * r + jj[k]];
-                                out[(size_t(elem) * 6 + k) * npts + q] = w * s / det;
+                                double sum = 0.0;
+                                for (int r = 0; r < 3; ++r) sum += J[3 * r + ii[k]] * J[3 * r + jj[k]];
+                                out[(size_t(elem) * 6 + k) * npts + q] = w * sum / det;
                             }
                         }
             }
@@ -489,9 +634,7 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
     }
     m.psize = ts->psize[space];
     m.metric = ts->d_metric;
-    m.npts = ts->npts;
     m.inv_gamma = space == SP_B ? ts->d_inv_mu : ts->d_inv_eps;
-    hipLaunchKernelGGL(tmass_kernel, dim3(unsigned(ts->nelem), batch), dim3(64), 0, s, m);
     TGatherArgs g{};
     g.patch = ts->d_patch;
     g.patch_stride = m.patch_stride;
@@ -509,7 +652,7 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
     }
     g.psize = m.psize;
     const int64_t n = space == SP_B ? ts->n_h : ts->n_e;
-    hipLaunchKernelGGL(tgather_kernel, dim3(unsigned((n + 255) / 256), batch), dim3(256), 0, s, g, n);
+    t_launch_mass(m, g, n, batch, s, ts->nelem);
 }
 
 // out = beta out + alpha D^1 in (primal) or D~^1 in (dual)
