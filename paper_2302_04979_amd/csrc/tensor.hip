@@ -10,9 +10,12 @@
 // Device layout: fields as in the single-degree spaces (three components one
 // after the other, x fastest inside); the 1D basis tables per direction and
 // tag, element-major [e][q][k]; the metric factor w_q DF^T DF / det DF per
-// element as [element][6][point]; the mass apply writes one patch per element
-// (its window of every component) and a gather sums, for each output, the
-// patches of the elements in its support in a fixed order.  The pairing
+// element as [element][6][point]; the mass apply writes each element's window
+// of every component into a patch held component by component and, inside a
+// component, entry by entry ([component][window entry][element]: a wave of the
+// gather reads one entry of 64 neighbouring elements at once), and the gather
+// sums, for each output, the window entries of the elements in its support in
+// a fixed order.  The pairing
 // solves run the banded line kernels of the single-degree spaces, with the
 // factors of every direction padded to the half bandwidth of the largest
 // degree (the padding holds zeros, so the substitutions are unchanged).
@@ -52,8 +55,7 @@ struct TMassArgs {
     int space;                   // SP_B or SP_D
     int64_t comp_off[3];
     int dims[3][3];              // [c][z, y, x]
-    int64_t pcomp_off[3];        // per-element patch: component offsets
-    int psize;                   // patch doubles per element
+    int64_t pcomp_off[3];        // patch region of each component: [window entry][element]
     const double* metric;        // [element][6][point]
     const double* inv_gamma;     // per element (x fastest)
 };
@@ -68,7 +70,6 @@ struct TGatherArgs {
     int64_t comp_off[3];
     int dims[3][3];
     int64_t pcomp_off[3];
-    int psize;
 };
 
 // Window size of component c along direction a.
@@ -168,12 +169,12 @@ __device__ inline void t_interp(const double* X, const double* Tx, const double*
 
 template <class Qc>
 __device__ inline void t_integrate(const double* V, const double* Tx, const double* Ty, const double* Tz, double* T1,
-                                   double* T2, double* out, int tid) {
+                                   double* T2, double* out, int64_t stride, int tid) {
     for (int i = tid; i < Qc::N2; i += 64) T2[i] = Qc::bz(i, V, Tz);
     __syncthreads();
     for (int i = tid; i < Qc::N1; i += 64) T1[i] = Qc::by(i, T2, Ty);
     __syncthreads();
-    for (int i = tid; i < Qc::Wn::size; i += 64) out[i] = Qc::bx(i, T1, Tx);
+    for (int i = tid; i < Qc::Wn::size; i += 64) out[i * stride] = Qc::bx(i, T1, Tx);
     __syncthreads();  // T1 and T2 are reused
 }
 
@@ -286,11 +287,12 @@ __global__ void __launch_bounds__(64) tmass_kernel(const TMassArgs A) {
         }
     }
     __syncthreads();
-    double* patch = A.patch + int64_t(b) * A.patch_stride + int64_t(elem) * A.psize;
+    double* patch = A.patch + int64_t(b) * A.patch_stride;
     // ---- integration against the test functions, into the patch ----
-    t_integrate<Q0>(V[0], tb[0][0], tb[1][1], tb[2][1], T1, T2, patch + A.pcomp_off[0], tid);
-    t_integrate<Q1>(V[1], tb[0][1], tb[1][0], tb[2][1], T1, T2, patch + A.pcomp_off[1], tid);
-    t_integrate<Q2>(V[2], tb[0][1], tb[1][1], tb[2][0], T1, T2, patch + A.pcomp_off[2], tid);
+    const int64_t ne = int64_t(A.N[0]) * A.N[1] * A.N[2];
+    t_integrate<Q0>(V[0], tb[0][0], tb[1][1], tb[2][1], T1, T2, patch + A.pcomp_off[0] + elem, ne, tid);
+    t_integrate<Q1>(V[1], tb[0][1], tb[1][0], tb[2][1], T1, T2, patch + A.pcomp_off[1] + elem, ne, tid);
+    t_integrate<Q2>(V[2], tb[0][1], tb[1][1], tb[2][0], T1, T2, patch + A.pcomp_off[2] + elem, ne, tid);
 }
 
 // out_i = sum of the patch entries of the elements whose window holds
@@ -315,13 +317,14 @@ __global__ void __launch_bounds__(256) tgather_kernel(const TGatherArgs A, int64
         hi[a] = min(A.N[a] - 1, g[a] - o[a]);
     }
     const double* patch = A.patch + int64_t(b) * A.patch_stride + A.pcomp_off[c];
+    const int64_t ne = int64_t(A.N[0]) * A.N[1] * A.N[2];
     double s = 0.0;
     for (int ez = lo[2]; ez <= hi[2]; ++ez)
         for (int ey = lo[1]; ey <= hi[1]; ++ey)
             for (int ex = lo[0]; ex <= hi[0]; ++ex) {
                 const int64_t elem = (int64_t(ez) * A.N[1] + ey) * A.N[0] + ex;
                 const int k = ((g[2] - o[2] - ez) * K[1] + (g[1] - o[1] - ey)) * K[0] + (g[0] - o[0] - ex);
-                s += patch[elem * A.psize + k];
+                s += patch[k * ne + elem];
             }
     A.out[int64_t(b) * A.out_stride + i] = s;
 }
@@ -465,8 +468,8 @@ struct kmx_tspace {
     TAxis ax[3];
     int dims[4][3][3];          // per space (SP_E..SP_D): [c][z, y, x]
     int64_t comp_off[4][3];
-    int64_t pcomp_off[4][3];    // SP_B and SP_D patches
-    int psize[4] = {0, 0, 0, 0};
+    int64_t pcomp_off[4][3];    // patch regions of the components: window x nelem each
+    int psize[4] = {0, 0, 0, 0};  // window doubles of one element, all components
     int psize_max = 0;
     int64_t tab_off[3][4];
     int64_t fac_off[3][4];      // [direction][F_G, F_M, F_GT, F_MT]
@@ -632,7 +635,6 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
         m.pcomp_off[c] = ts->pcomp_off[space][c];
         for (int k = 0; k < 3; ++k) m.dims[c][k] = ts->dims[space][c][k];
     }
-    m.psize = ts->psize[space];
     m.metric = ts->d_metric;
     m.inv_gamma = space == SP_B ? ts->d_inv_mu : ts->d_inv_eps;
     TGatherArgs g{};
@@ -650,7 +652,6 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
         g.pcomp_off[c] = m.pcomp_off[c];
         for (int k = 0; k < 3; ++k) g.dims[c][k] = m.dims[c][k];
     }
-    g.psize = m.psize;
     const int64_t n = space == SP_B ? ts->n_h : ts->n_e;
     t_launch_mass(m, g, n, batch, s, ts->nelem);
 }
@@ -717,7 +718,7 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
         int64_t off = 0, poff = 0;
         for (int c = 0; c < 3; ++c) {
             ts->comp_off[sp][c] = off;
-            ts->pcomp_off[sp][c] = poff;
+            ts->pcomp_off[sp][c] = poff * ts->nelem;
             int64_t n = 1, w = 1;
             for (int a = 0; a < 3; ++a) {
                 const int tag = space_tag(sp, c, a);
