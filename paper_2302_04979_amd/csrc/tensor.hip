@@ -9,16 +9,16 @@
 //
 // Device layout: fields as in the single-degree spaces (three components one
 // after the other, x fastest inside); the 1D basis tables per direction and
-// tag, element-major [e][q][k]; the metric factor w_q DF^T DF / det DF per
-// element as [element][6][point]; the mass apply writes each element's window
-// of every component into a patch held component by component and, inside a
-// component, entry by entry ([component][window entry][element]: a wave of the
-// gather reads one entry of 64 neighbouring elements at once), and the gather
-// sums, for each output, the window entries of the elements in its support in
-// a fixed order.  The pairing
-// solves run the banded line kernels of the single-degree spaces, with the
-// factors of every direction padded to the half bandwidth of the largest
-// degree (the padding holds zeros, so the substitutions are unchanged).
+// tag, element-major [e][q][k] and zero past the last element up to a whole
+// tile; the metric factor w_q DF^T DF / det DF per tile of TT^3 elements as
+// [tile][qz][6][qy][qx]; the mass apply writes, per tile and component, the
+// tile's window of basis functions (TT + K - 1 per direction) with the x rows
+// of the tiles side by side ([tz][ty][wz][wy][tx][wx]), and the gather sums
+// for each output the (at most eight) tile windows that hold it in a fixed
+// order.  The pairing solves run the banded line kernels of the single-degree
+// spaces, with the factors of every direction padded to the half bandwidth of
+// the largest degree (the padding holds zeros, so the substitutions are
+// unchanged).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,24 +39,24 @@ namespace {
 
 constexpr int TP_MAX = 4;                            // largest degree per direction
 constexpr int TK = TP_MAX + 1;                       // functions per element and direction (at most)
-constexpr int TQ = TP_MAX + 1;                       // Gauss points per element and direction (at most)
-constexpr int TCUBE = TK * TK * TK;                  // one window or one point block
 constexpr int TLINE_MAX = 76;                        // longest 1D space the line kernels hold
 
-// Arguments of the per-element mass apply (one workgroup per element).
+constexpr int TT = 4;                                // elements per tile edge of the mass apply
+
+// Arguments of the tiled mass apply (one workgroup per tile of TT^3 elements).
 struct TMassArgs {
     const double* x;
     int64_t x_stride;
     double* patch;
     int64_t patch_stride;        // per member
     const double* tab;
-    int64_t tab_off[3][4];       // [direction][tag] -> [N][nq][K]
-    int p[3], N[3], nq[3];
-    int space;                   // SP_B or SP_D
+    int64_t tab_off[3][4];       // [direction][tag] -> [nt TT elements][nq][K], zero past N
+    int nt[3];                   // tiles per direction
+    int N[3];
     int64_t comp_off[3];
     int dims[3][3];              // [c][z, y, x]
-    int64_t pcomp_off[3];        // patch region of each component: [window entry][element]
-    const double* metric;        // [element][6][point]
+    int64_t pcomp_off[3];        // patch region of each component
+    const double* metric;        // [tile][qz][6][qy][qx], zero at padded points
     const double* inv_gamma;     // per element (x fastest)
 };
 
@@ -65,20 +65,14 @@ struct TGatherArgs {
     int64_t patch_stride;
     double* out;
     int64_t out_stride;
-    int p[3], N[3];
-    int space;
+    int nt[3];
     int64_t comp_off[3];
     int dims[3][3];
     int64_t pcomp_off[3];
 };
 
-// Window size of component c along direction a.
-__host__ __device__ inline int t_support(const int p[3], int space, int c, int a) {
-    return tag_support(p[a], space_tag(space, c, a));
-}
-
 // Block index -> work item so that each of the 8 XCDs (which take blocks
-// round robin) walks one contiguous range: neighbouring elements, which share
+// round robin) walks one contiguous range: neighbouring tiles, which share
 // window entries and patch lines, then meet in the same L2.
 __device__ inline int t_xcd_order(int block, int nblocks) {
     constexpr int XCD = 8;
@@ -86,267 +80,316 @@ __device__ inline int t_xcd_order(int block, int nblocks) {
     return block < per * XCD ? (block % XCD) * per + block / XCD : block;
 }
 
-// Window of component C of a 2-form space on one element, per direction:
-// sizes and the offset of local index 0 in the global numbering.
+// Window of component C of a 2-form space over one tile, per direction: the
+// functions nonzero on one element (K), the tile window W = TT + K - 1 and the
+// offset of local index 0 in the global numbering.
 template <int PX, int PY, int PZ, int SPACE, int C>
 struct TWin {
     static constexpr int Kx = tag_support(PX, space_tag(SPACE, C, 0));
     static constexpr int Ky = tag_support(PY, space_tag(SPACE, C, 1));
     static constexpr int Kz = tag_support(PZ, space_tag(SPACE, C, 2));
-    static constexpr int size = Kx * Ky * Kz;
     static constexpr int ox = tag_offset(space_tag(SPACE, C, 0));
     static constexpr int oy = tag_offset(space_tag(SPACE, C, 1));
     static constexpr int oz = tag_offset(space_tag(SPACE, C, 2));
+    static constexpr int Wx = TT + Kx - 1, Wy = TT + Ky - 1, Wz = TT + Kz - 1;
+    static constexpr int size = Wx * Wy * Wz;
+    // the table slot (0: the tag along the component, 1: across) per direction
+    static constexpr int sx = C == 0 ? 0 : 1, sy = C == 1 ? 0 : 1, sz = C == 2 ? 0 : 1;
 };
 
-// One output of each sum-factorisation pass for component C (tables [q][k]
-// with row length TK).  Interpolation: x pass T1[kz][ky][qx], y pass
-// T2[kz][qy][qx], z pass V[qz][qy][qx]; integration: z pass T2[kz][qy][qx],
-// y pass T1[kz][ky][qx], x pass out[kz][ky][kx].
-template <int PX, int PY, int PZ, int SPACE, int C>
-struct TPass {
-    using Wn = TWin<PX, PY, PZ, SPACE, C>;
+// Patch layout of one component: [tz][ty][wz][wy][tx][wx], the x rows of the
+// tiles along x side by side (a gather wave reading a row of outputs touches
+// contiguous memory).
+template <class Wn>
+__device__ inline int64_t t_patch_at(const int nt[3], int tx, int ty, int tz, int wx, int wy, int wz) {
+    return ((((int64_t(tz) * nt[1] + ty) * Wn::Wz + wz) * Wn::Wy + wy) * nt[0] + tx) * Wn::Wx + wx;
+}
+
+constexpr int t_max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+// threads of a tiled mass workgroup: one per (qy, qx) column of the tile
+constexpr int tt_threads(int px, int py) { return ((TT * (px + 1) * TT * (py + 1) + 63) / 64) * 64; }
+
+template <int PX, int PY, int PZ>
+struct TTile {
     static constexpr int NQX = PX + 1, NQY = PY + 1, NQZ = PZ + 1;
-    static constexpr int N1 = Wn::Kz * Wn::Ky * NQX;   // T1 entries
-    static constexpr int N2 = Wn::Kz * NQY * NQX;      // T2 entries
-    static constexpr int NP = NQZ * NQY * NQX;         // points
-    __device__ static double fx(int i, const double* X, const double* Tx) {
-        const int qx = i % NQX, r = i / NQX;
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < Wn::Kx; ++k) s += Tx[qx * TK + k] * X[r * Wn::Kx + k];
-        return s;
-    }
-    __device__ static double fy(int i, const double* T1, const double* Ty) {
-        const int qx = i % NQX, qy = (i / NQX) % NQY, kz = i / (NQX * NQY);
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < Wn::Ky; ++k) s += Ty[qy * TK + k] * T1[(kz * Wn::Ky + k) * NQX + qx];
-        return s;
-    }
-    __device__ static double fz(int i, const double* T2, const double* Tz) {
-        const int r = i % (NQY * NQX), qz = i / (NQY * NQX);
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < Wn::Kz; ++k) s += Tz[qz * TK + k] * T2[k * NQY * NQX + r];
-        return s;
-    }
-    __device__ static double bz(int i, const double* V, const double* Tz) {
-        const int r = i % (NQY * NQX), kz = i / (NQY * NQX);
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < NQZ; ++q) s += Tz[q * TK + kz] * V[q * NQY * NQX + r];
-        return s;
-    }
-    __device__ static double by(int i, const double* T2, const double* Ty) {
-        const int qx = i % NQX, ky = (i / NQX) % Wn::Ky, kz = i / (NQX * Wn::Ky);
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < NQY; ++q) s += Ty[q * TK + ky] * T2[(kz * NQY + q) * NQX + qx];
-        return s;
-    }
-    __device__ static double bx(int i, const double* T1, const double* Tx) {
-        const int kx = i % Wn::Kx, r = i / Wn::Kx;
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < NQX; ++q) s += Tx[q * TK + kx] * T1[r * NQX + q];
-        return s;
-    }
+    static constexpr int QX = TT * NQX, QY = TT * NQY, QZ = TT * NQZ;
+    static constexpr int NT = tt_threads(PX, PY);
+    static constexpr int QM = t_max3(QX, QY, QZ);
 };
 
-// Interpolation of one component at the Gauss points (x, y, z passes) and
-// integration against its test functions (z, y, x passes, into `out`).
-template <class Qc>
-__device__ inline void t_interp(const double* X, const double* Tx, const double* Ty, const double* Tz, double* T1,
-                                double* T2, double* V, int tid) {
-    for (int i = tid; i < Qc::N1; i += 64) T1[i] = Qc::fx(i, X, Tx);
-    __syncthreads();
-    for (int i = tid; i < Qc::N2; i += 64) T2[i] = Qc::fy(i, T1, Ty);
-    __syncthreads();
-    for (int i = tid; i < Qc::NP; i += 64) V[i] = Qc::fz(i, T2, Tz);
-    __syncthreads();
-}
-
-template <class Qc>
-__device__ inline void t_integrate(const double* V, const double* Tx, const double* Ty, const double* Tz, double* T1,
-                                   double* T2, double* out, int64_t stride, int tid) {
-    for (int i = tid; i < Qc::N2; i += 64) T2[i] = Qc::bz(i, V, Tz);
-    __syncthreads();
-    for (int i = tid; i < Qc::N1; i += 64) T1[i] = Qc::by(i, T2, Ty);
-    __syncthreads();
-    for (int i = tid; i < Qc::Wn::size; i += 64) out[i * stride] = Qc::bx(i, T1, Tx);
-    __syncthreads();  // T1 and T2 are reused
-}
-
-// The window of component C: requested into registers (two entries per lane).
-template <int PX, int PY, int PZ, int SPACE, int C>
-__device__ inline void t_window_load(const double* x, const TMassArgs& A, const int e3[3], int tid, double (&r)[2]) {
+// Interpolation of component C along x and y: the tile window into LDS, the x
+// pass into LDS, the y pass into the thread's register column A[wz] (the
+// window's z planes at the thread's (qy, qx)).
+template <int PX, int PY, int PZ, int SPACE, int C, int WZM>
+__device__ inline void tt_forward_xy(const TMassArgs& A, const double* x, double (*tab)[2][TTile<PX, PY, PZ>::QM * TK],
+                                     double* X, double* AX, const int t3[3], int tid, int qy, int qx, bool active,
+                                     double (&col)[WZM]) {
     using Wn = TWin<PX, PY, PZ, SPACE, C>;
-    static_assert(Wn::size <= 128, "two window entries per lane");
+    using T = TTile<PX, PY, PZ>;
     const int nx = A.dims[C][2], ny = A.dims[C][1], nz = A.dims[C][0];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int i = tid + 64 * j;
-        const int kx = i % Wn::Kx, ky = (i / Wn::Kx) % Wn::Ky, kz = i / (Wn::Kx * Wn::Ky);
-        const int gx = e3[0] + Wn::ox + kx, gy = e3[1] + Wn::oy + ky, gz = e3[2] + Wn::oz + kz;
-        const bool ok = i < Wn::size && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-        r[j] = ok ? x[A.comp_off[C] + (int64_t(gz) * ny + gy) * nx + gx] : 0.0;
+    const int gx0 = t3[0] * TT + Wn::ox, gy0 = t3[1] * TT + Wn::oy, gz0 = t3[2] * TT + Wn::oz;
+    const double* xc = x + A.comp_off[C];
+    for (int i = tid; i < Wn::size; i += T::NT) {
+        const int wx = i % Wn::Wx, wy = (i / Wn::Wx) % Wn::Wy, wz = i / (Wn::Wx * Wn::Wy);
+        const int gx = gx0 + wx, gy = gy0 + wy, gz = gz0 + wz;
+        const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+        X[i] = ok ? xc[(int64_t(gz) * ny + gy) * nx + gx] : 0.0;
     }
+    __syncthreads();
+    const double* tx = tab[0][Wn::sx];
+    for (int i = tid; i < Wn::Wz * Wn::Wy * T::QX; i += T::NT) {
+        const int q = i % T::QX, r = i / T::QX;  // r = wz * Wy + wy
+        const int ex = q / T::NQX;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < Wn::Kx; ++k) s += tx[q * TK + k] * X[r * Wn::Wx + ex + k];
+        AX[i] = s;
+    }
+    __syncthreads();
+    if (active) {
+        const double* ty = tab[1][Wn::sy];
+        const int ey = qy / T::NQY;
+#pragma unroll
+        for (int wz = 0; wz < Wn::Wz; ++wz) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < Wn::Ky; ++k) s += ty[qy * TK + k] * AX[(wz * Wn::Wy + ey + k) * T::QX + qx];
+            col[wz] = s;
+        }
+    }
+    __syncthreads();  // X and AX are reused by the next component
 }
 
-// One workgroup (one wave) per element: every global load (the 1D tables, the
-// three input windows, the metric, 1/gamma) is requested in one round; the
-// sum-factorised passes run out of LDS with compile-time sizes, one component
-// at a time; the metric stays in registers (two points per lane).
+// Integration of component C along y and x: the thread's column R[wz] into
+// LDS, the y pass (sum over the elements of the tile whose window holds wy and
+// their points), the x pass likewise, into the tile's patch.
+template <int PX, int PY, int PZ, int SPACE, int C, int WZM>
+__device__ inline void tt_backward_xy(const TMassArgs& A, double* patch, double (*tab)[2][TTile<PX, PY, PZ>::QM * TK],
+                                      double* RB, double* BY, const int t3[3], int tid, int qy, int qx, bool active,
+                                      const double (&col)[WZM]) {
+    using Wn = TWin<PX, PY, PZ, SPACE, C>;
+    using T = TTile<PX, PY, PZ>;
+    if (active) {
+#pragma unroll
+        for (int wz = 0; wz < Wn::Wz; ++wz) RB[(wz * T::QY + qy) * T::QX + qx] = col[wz];
+    }
+    __syncthreads();
+    const double* ty = tab[1][Wn::sy];
+    for (int i = tid; i < Wn::Wz * Wn::Wy * T::QX; i += T::NT) {
+        const int q = i % T::QX, wy = (i / T::QX) % Wn::Wy, wz = i / (T::QX * Wn::Wy);
+        double s = 0.0;
+#pragma unroll
+        for (int ey = 0; ey < TT; ++ey) {
+            const int k = wy - ey;
+            if (k >= 0 && k < Wn::Ky) {
+#pragma unroll
+                for (int iy = 0; iy < T::NQY; ++iy) {
+                    const int qq = ey * T::NQY + iy;
+                    s += ty[qq * TK + k] * RB[(wz * T::QY + qq) * T::QX + q];
+                }
+            }
+        }
+        BY[i] = s;
+    }
+    __syncthreads();
+    const double* tx = tab[0][Wn::sx];
+    double* pc = patch + A.pcomp_off[C];
+    for (int i = tid; i < Wn::size; i += T::NT) {
+        const int wx = i % Wn::Wx, r = i / Wn::Wx;  // r = wz * Wy + wy
+        double s = 0.0;
+#pragma unroll
+        for (int ex = 0; ex < TT; ++ex) {
+            const int k = wx - ex;
+            if (k >= 0 && k < Wn::Kx) {
+#pragma unroll
+                for (int ix = 0; ix < T::NQX; ++ix) {
+                    const int qq = ex * T::NQX + ix;
+                    s += tx[qq * TK + k] * BY[r * T::QX + qq];
+                }
+            }
+        }
+        pc[t_patch_at<Wn>(A.nt, t3[0], t3[1], t3[2], wx, r % Wn::Wy, r / Wn::Wy)] = s;
+    }
+    __syncthreads();  // RB and BY are reused by the next component
+}
+
+// One workgroup per tile of TT^3 elements, one thread per (qy, qx) Gauss
+// column of the tile: the x and y contractions of each component through LDS
+// into register columns, then a walk over the tile's Gauss planes (z
+// interpolation, the metric streamed per point, 1/gamma of the point's
+// element, the z integration back into register columns), then the y and x
+// integrations into the tile's patch.  Specialised on the three degrees.
 template <int PX, int PY, int PZ, int SPACE>
-__global__ void __launch_bounds__(64) tmass_kernel(const TMassArgs A) {
-    constexpr int NQX = PX + 1, NQY = PY + 1, NQZ = PZ + 1, NPTS = NQX * NQY * NQZ;
-    static_assert(NPTS <= 128, "two points per lane");
-    constexpr int TBN = 3 * 2 * TQ * TK;  // table entries
-    constexpr int TBR = (TBN + 63) / 64;
+__global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TMassArgs A) {
+    using T = TTile<PX, PY, PZ>;
     using W0 = TWin<PX, PY, PZ, SPACE, 0>;
     using W1 = TWin<PX, PY, PZ, SPACE, 1>;
     using W2 = TWin<PX, PY, PZ, SPACE, 2>;
-    // LDS sized for these degrees: the windows, the two pass buffers, the
-    // point values and the tables
-    constexpr int WMAX = W0::size > W1::size ? (W0::size > W2::size ? W0::size : W2::size)
-                                             : (W1::size > W2::size ? W1::size : W2::size);
-    using Q0 = TPass<PX, PY, PZ, SPACE, 0>;
-    using Q1 = TPass<PX, PY, PZ, SPACE, 1>;
-    using Q2 = TPass<PX, PY, PZ, SPACE, 2>;
-    // the pass buffers, reused by the three components
-    constexpr int T1N = Q0::N1 > Q1::N1 ? (Q0::N1 > Q2::N1 ? Q0::N1 : Q2::N1) : (Q1::N1 > Q2::N1 ? Q1::N1 : Q2::N1);
-    constexpr int T2N = Q0::N2 > Q1::N2 ? (Q0::N2 > Q2::N2 ? Q0::N2 : Q2::N2) : (Q1::N2 > Q2::N2 ? Q1::N2 : Q2::N2);
-    __shared__ double X[3][WMAX], T1[T1N], T2[T2N];
-    __shared__ double V[3][NPTS];
-    __shared__ double tb[3][2][TQ * TK];  // per direction: the along and across tags, [q][k]
+    constexpr int WSZ = t_max3(W0::size, W1::size, W2::size);
+    constexpr int WZM = t_max3(W0::Wz, W1::Wz, W2::Wz);
+    constexpr int AXN = t_max3(W0::Wz * W0::Wy, W1::Wz * W1::Wy, W2::Wz * W2::Wy) * T::QX;
+    constexpr int RBN = WZM * T::QY * T::QX;
+    __shared__ double tab[3][2][T::QM * TK];
+    __shared__ double X[WSZ];
+    __shared__ double AX[AXN];   // x pass (forward), y pass (backward)
+    __shared__ double RB[RBN];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
-    const int elem = t_xcd_order(blockIdx.x, gridDim.x);
-    const int e3[3] = {elem % A.N[0], (elem / A.N[0]) % A.N[1], elem / (A.N[0] * A.N[1])};
+    const int ntile = A.nt[0] * A.nt[1] * A.nt[2];
+    const int tile = t_xcd_order(blockIdx.x, ntile);
+    const int t3[3] = {tile % A.nt[0], (tile / A.nt[0]) % A.nt[1], tile / (A.nt[0] * A.nt[1])};
+    const int qy = tid / T::QX, qx = tid % T::QX;
+    const bool active = tid < T::QX * T::QY;
     const double* x = A.x + int64_t(b) * A.x_stride;
-    constexpr int PD[3] = {PX, PY, PZ};
-    constexpr int NQ[3] = {NQX, NQY, NQZ};
 
-    // ---- one round of loads ----
-    double rt[TBR], rw0[2], rw1[2], rw2[2], rg[2][6];
-#pragma unroll
-    for (int j = 0; j < TBR; ++j) {
-        const int i = tid + 64 * j;
-        const int a = i / (2 * TQ * TK), s = (i / (TQ * TK)) % 2, q = (i / TK) % TQ, k = i % TK;
-        double v = 0.0;
-        if (i < TBN) {
+    // the tile's 1D tables, both tags of the space per direction
+    {
+        constexpr int NQ[3] = {T::NQX, T::NQY, T::NQZ};
+        constexpr int PD[3] = {PX, PY, PZ};
+        for (int i = tid; i < 3 * 2 * T::QM * TK; i += T::NT) {
+            const int a = i / (2 * T::QM * TK), s = (i / (T::QM * TK)) % 2, q = (i / TK) % T::QM, k = i % TK;
             const int tag = space_tag(SPACE, s == 0 ? a : (a + 1) % 3, a);
             const int K = tag_support(PD[a], tag);
-            if (q < NQ[a] && k < K) v = A.tab[A.tab_off[a][tag] + (int64_t(e3[a]) * NQ[a] + q) * K + k];
+            double v = 0.0;
+            if (q < TT * NQ[a] && k < K) v = A.tab[A.tab_off[a][tag] + (int64_t(t3[a]) * TT * NQ[a] + q) * K + k];
+            tab[a][s][q * TK + k] = v;
         }
-        rt[j] = v;
     }
-    t_window_load<PX, PY, PZ, SPACE, 0>(x, A, e3, tid, rw0);
-    t_window_load<PX, PY, PZ, SPACE, 1>(x, A, e3, tid, rw1);
-    t_window_load<PX, PY, PZ, SPACE, 2>(x, A, e3, tid, rw2);
-    const double* gm = A.metric + int64_t(elem) * 6 * NPTS;
+    // 1/gamma of the elements of this thread's column (padded elements: the
+    // metric is zero there)
+    double ig[TT];
+    {
+        const int ex = min(t3[0] * TT + qx / T::NQX, A.N[0] - 1), ey = min(t3[1] * TT + qy / T::NQY, A.N[1] - 1);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int q = tid + 64 * j;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) rg[j][k] = q < NPTS ? gm[k * NPTS + q] : 0.0;
+        for (int ez = 0; ez < TT; ++ez) {
+            const int gz = min(t3[2] * TT + ez, A.N[2] - 1);
+            ig[ez] = active ? A.inv_gamma[(int64_t(gz) * A.N[1] + ey) * A.N[0] + ex] : 0.0;
+        }
     }
-    const double ig = A.inv_gamma[elem];
-    // ---- into LDS ----
-#pragma unroll
-    for (int j = 0; j < TBR; ++j) {
-        const int i = tid + 64 * j;
-        if (i < TBN) (&tb[0][0][0])[i] = rt[j];
-    }
+    __syncthreads();
 
+    double a0[WZM], a1[WZM], a2[WZM];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int i = tid + 64 * j;
-        if (i < WMAX) {
-            X[0][i] = rw0[j];
-            X[1][i] = rw1[j];
-            X[2][i] = rw2[j];
+    for (int k = 0; k < WZM; ++k) a0[k] = a1[k] = a2[k] = 0.0;
+    tt_forward_xy<PX, PY, PZ, SPACE, 0, WZM>(A, x, tab, X, AX, t3, tid, qy, qx, active, a0);
+    tt_forward_xy<PX, PY, PZ, SPACE, 1, WZM>(A, x, tab, X, AX, t3, tid, qy, qx, active, a1);
+    tt_forward_xy<PX, PY, PZ, SPACE, 2, WZM>(A, x, tab, X, AX, t3, tid, qy, qx, active, a2);
+
+    // the walk over the tile's Gauss planes
+    double r0[WZM], r1[WZM], r2[WZM];
+#pragma unroll
+    for (int k = 0; k < WZM; ++k) r0[k] = r1[k] = r2[k] = 0.0;
+    if (active) {
+        const double* tz0 = tab[2][W0::sz];
+        const double* tz1 = tab[2][W1::sz];
+        const double* tz2 = tab[2][W2::sz];
+        const double* gm = A.metric + int64_t(tile) * T::QZ * 6 * T::QY * T::QX + qy * T::QX + qx;
+#pragma unroll
+        for (int qz = 0; qz < T::QZ; ++qz) {
+            constexpr int PL = T::QY * T::QX;
+            const int ez = qz / T::NQZ;
+            double g[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) g[k] = gm[(qz * 6 + k) * PL];
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < W0::Kz; ++k) v0 += tz0[qz * TK + k] * a0[ez + k];
+#pragma unroll
+            for (int k = 0; k < W1::Kz; ++k) v1 += tz1[qz * TK + k] * a1[ez + k];
+#pragma unroll
+            for (int k = 0; k < W2::Kz; ++k) v2 += tz2[qz * TK + k] * a2[ez + k];
+            const double s = ig[ez];
+            const double u0 = s * (g[0] * v0 + g[3] * v1 + g[4] * v2);
+            const double u1 = s * (g[3] * v0 + g[1] * v1 + g[5] * v2);
+            const double u2 = s * (g[4] * v0 + g[5] * v1 + g[2] * v2);
+#pragma unroll
+            for (int k = 0; k < W0::Kz; ++k) r0[ez + k] += tz0[qz * TK + k] * u0;
+#pragma unroll
+            for (int k = 0; k < W1::Kz; ++k) r1[ez + k] += tz1[qz * TK + k] * u1;
+#pragma unroll
+            for (int k = 0; k < W2::Kz; ++k) r2[ez + k] += tz2[qz * TK + k] * u2;
         }
     }
-    __syncthreads();
-    // ---- interpolation to the Gauss points, one component at a time
-    // (component c's tables: tb[a][a == c ? 0 : 1]) ----
-    t_interp<Q0>(X[0], tb[0][0], tb[1][1], tb[2][1], T1, T2, V[0], tid);
-    t_interp<Q1>(X[1], tb[0][1], tb[1][0], tb[2][1], T1, T2, V[1], tid);
-    t_interp<Q2>(X[2], tb[0][1], tb[1][1], tb[2][0], T1, T2, V[2], tid);
-    // ---- u = (1 / gamma) G v at every point ----
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int q = tid + 64 * j;
-        if (q < NPTS) {
-            const double v0 = V[0][q], v1 = V[1][q], v2 = V[2][q];
-            V[0][q] = ig * (rg[j][0] * v0 + rg[j][3] * v1 + rg[j][4] * v2);
-            V[1][q] = ig * (rg[j][3] * v0 + rg[j][1] * v1 + rg[j][5] * v2);
-            V[2][q] = ig * (rg[j][4] * v0 + rg[j][5] * v1 + rg[j][2] * v2);
-        }
-    }
-    __syncthreads();
     double* patch = A.patch + int64_t(b) * A.patch_stride;
-    // ---- integration against the test functions, into the patch ----
-    const int64_t ne = int64_t(A.N[0]) * A.N[1] * A.N[2];
-    t_integrate<Q0>(V[0], tb[0][0], tb[1][1], tb[2][1], T1, T2, patch + A.pcomp_off[0] + elem, ne, tid);
-    t_integrate<Q1>(V[1], tb[0][1], tb[1][0], tb[2][1], T1, T2, patch + A.pcomp_off[1] + elem, ne, tid);
-    t_integrate<Q2>(V[2], tb[0][1], tb[1][1], tb[2][0], T1, T2, patch + A.pcomp_off[2] + elem, ne, tid);
+    tt_backward_xy<PX, PY, PZ, SPACE, 0, WZM>(A, patch, tab, RB, AX, t3, tid, qy, qx, active, r0);
+    tt_backward_xy<PX, PY, PZ, SPACE, 1, WZM>(A, patch, tab, RB, AX, t3, tid, qy, qx, active, r1);
+    tt_backward_xy<PX, PY, PZ, SPACE, 2, WZM>(A, patch, tab, RB, AX, t3, tid, qy, qx, active, r2);
 }
 
-// out_i = sum of the patch entries of the elements whose window holds
-// function i, by increasing z, y, x element index.
+// out_i = sum of the patch entries of the (at most eight) tiles whose window
+// holds function i, by increasing z, y, x tile index.
+template <int PX, int PY, int PZ, int SPACE, int C>
+__device__ inline double tt_gather_one(const TGatherArgs& A, const double* patch, int gx, int gy, int gz) {
+    using Wn = TWin<PX, PY, PZ, SPACE, C>;
+    const int r[3] = {gx - Wn::ox, gy - Wn::oy, gz - Wn::oz};
+    const int W[3] = {Wn::Wx, Wn::Wy, Wn::Wz};
+    int t[3][2], w[3][2];
+    bool v[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int h = r[a] / TT;
+        h = h > A.nt[a] - 1 ? A.nt[a] - 1 : h;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const int c = h - 1 + d;
+            v[a][d] = c >= 0 && r[a] - c * TT < W[a];
+            t[a][d] = v[a][d] ? c : h;
+            w[a][d] = v[a][d] ? r[a] - c * TT : 0;
+        }
+    }
+    const double* pc = patch + A.pcomp_off[C];
+    double s = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const double val = pc[t_patch_at<Wn>(A.nt, t[0][dx], t[1][dy], t[2][dz], w[0][dx], w[1][dy], w[2][dz])];
+                s += (v[2][dz] && v[1][dy] && v[0][dx]) ? val : 0.0;
+            }
+    return s;
+}
+
 template <int PX, int PY, int PZ, int SPACE>
-__global__ void __launch_bounds__(256) tgather_kernel(const TGatherArgs A, int64_t n) {
+__global__ void __launch_bounds__(256) ttile_gather_kernel(const TGatherArgs A, int64_t n) {
     const int b = blockIdx.y;
     const int64_t i = int64_t(t_xcd_order(blockIdx.x, gridDim.x)) * 256 + threadIdx.x;
     if (i >= n) return;
     const int c = i >= A.comp_off[2] ? 2 : (i >= A.comp_off[1] ? 1 : 0);
     const int64_t li = i - A.comp_off[c];
     const int nx = A.dims[c][2], ny = A.dims[c][1];
-    const int g[3] = {int(li % nx), int((li / nx) % ny), int(li / (int64_t(nx) * ny))};
-    constexpr int PD[3] = {PX, PY, PZ};
-    int K[3], o[3], lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int tag = space_tag(SPACE, c, a);
-        K[a] = tag_support(PD[a], tag);
-        o[a] = tag_offset(tag);
-        lo[a] = max(0, g[a] - o[a] - K[a] + 1);
-        hi[a] = min(A.N[a] - 1, g[a] - o[a]);
-    }
-    const double* patch = A.patch + int64_t(b) * A.patch_stride + A.pcomp_off[c];
-    const int64_t ne = int64_t(A.N[0]) * A.N[1] * A.N[2];
-    double s = 0.0;
-    for (int ez = lo[2]; ez <= hi[2]; ++ez)
-        for (int ey = lo[1]; ey <= hi[1]; ++ey)
-            for (int ex = lo[0]; ex <= hi[0]; ++ex) {
-                const int64_t elem = (int64_t(ez) * A.N[1] + ey) * A.N[0] + ex;
-                const int k = ((g[2] - o[2] - ez) * K[1] + (g[1] - o[1] - ey)) * K[0] + (g[0] - o[0] - ex);
-                s += patch[k * ne + elem];
-            }
+    const int gx = int(li % nx), gy = int((li / nx) % ny), gz = int(li / (int64_t(nx) * ny));
+    const double* patch = A.patch + int64_t(b) * A.patch_stride;
+    double s;
+    if (c == 0) s = tt_gather_one<PX, PY, PZ, SPACE, 0>(A, patch, gx, gy, gz);
+    else if (c == 1) s = tt_gather_one<PX, PY, PZ, SPACE, 1>(A, patch, gx, gy, gz);
+    else s = tt_gather_one<PX, PY, PZ, SPACE, 2>(A, patch, gx, gy, gz);
     A.out[int64_t(b) * A.out_stride + i] = s;
 }
 
 template <int PX, int PY, int PZ>
-void t_launch_p(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int64_t nelem) {
-    const dim3 gm(unsigned(nelem), batch), gg(unsigned((n + 255) / 256), batch);
-    if (m.space == SP_B) {
-        hipLaunchKernelGGL((tmass_kernel<PX, PY, PZ, SP_B>), gm, dim3(64), 0, s, m);
-        hipLaunchKernelGGL((tgather_kernel<PX, PY, PZ, SP_B>), gg, dim3(256), 0, s, g, n);
+void t_launch_p(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int space) {
+    const int ntile = m.nt[0] * m.nt[1] * m.nt[2];
+    const dim3 gm(unsigned(ntile), batch), gg(unsigned((n + 255) / 256), batch);
+    const dim3 bm(TTile<PX, PY, PZ>::NT);
+    if (space == SP_B) {
+        hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_B>), gm, bm, 0, s, m);
+        hipLaunchKernelGGL((ttile_gather_kernel<PX, PY, PZ, SP_B>), gg, dim3(256), 0, s, g, n);
     } else {
-        hipLaunchKernelGGL((tmass_kernel<PX, PY, PZ, SP_D>), gm, dim3(64), 0, s, m);
-        hipLaunchKernelGGL((tgather_kernel<PX, PY, PZ, SP_D>), gg, dim3(256), 0, s, g, n);
+        hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_D>), gm, bm, 0, s, m);
+        hipLaunchKernelGGL((ttile_gather_kernel<PX, PY, PZ, SP_D>), gg, dim3(256), 0, s, g, n);
     }
 }
 
 // the mass kernel and the gather for the space's degrees (2..4 each)
-void t_launch_mass(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int64_t nelem) {
-    const int code = (m.p[0] - 2) * 9 + (m.p[1] - 2) * 3 + (m.p[2] - 2);
+void t_launch_mass(const int p[3], const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s,
+                   int space) {
+    const int code = (p[0] - 2) * 9 + (p[1] - 2) * 3 + (p[2] - 2);
 #define TL(PX, PY, PZ)                                                       \
     case (PX - 2) * 9 + (PY - 2) * 3 + (PZ - 2):                             \
-        t_launch_p<PX, PY, PZ>(m, g, n, batch, s, nelem);                    \
+        t_launch_p<PX, PY, PZ>(m, g, n, batch, s, space);                    \
         return;
 #define TL3(PX, PY) TL(PX, PY, 2) TL(PX, PY, 3) TL(PX, PY, 4)
     switch (code) {
@@ -366,7 +409,7 @@ struct TAxis {
     int p = 0, N = 0, nq = 0, n0 = 0, n1 = 0;
     std::vector<double> t;                   // p-open knot vector
     std::vector<double> xq, wq;              // Gauss points and weights, element by element
-    std::vector<double> tab[4];              // [N][nq][K(tag)]
+    std::vector<double> tab[4];              // [nt TT][nq][K(tag)], zero past the N elements
     std::vector<double> G, M;                // dense 1D pairing matrices
 };
 
@@ -420,7 +463,8 @@ void t_build_axis(TAxis& ax, int p, int N, const double* breaks) {
         }
     for (int tag = 0; tag < 4; ++tag) {
         const int K = tag_support(p, tag);
-        ax.tab[tag].assign(size_t(N) * ax.nq * K, 0.0);
+        const int npad = ((N + TT - 1) / TT) * TT;
+        ax.tab[tag].assign(size_t(npad) * ax.nq * K, 0.0);
         for (int e = 0; e < N; ++e)
             for (int q = 0; q < ax.nq; ++q) t_eval(ax, tag, e, ax.xq[e * ax.nq + q], &ax.tab[tag][(e * ax.nq + q) * K]);
     }
@@ -468,9 +512,10 @@ struct kmx_tspace {
     TAxis ax[3];
     int dims[4][3][3];          // per space (SP_E..SP_D): [c][z, y, x]
     int64_t comp_off[4][3];
-    int64_t pcomp_off[4][3];    // patch regions of the components: window x nelem each
-    int psize[4] = {0, 0, 0, 0};  // window doubles of one element, all components
-    int psize_max = 0;
+    int nt[3] = {0, 0, 0};      // tiles of TT elements per direction
+    int64_t pcomp_off[4][3];    // patch regions of the components (tile windows)
+    int64_t psize[4] = {0, 0, 0, 0};  // patch doubles of one field, all components
+    int64_t psize_max = 0;
     int64_t tab_off[3][4];
     int64_t fac_off[3][4];      // [direction][F_G, F_M, F_GT, F_MT]
     double* d_tab = nullptr;
@@ -507,17 +552,19 @@ kmx_status t_upload(double** dst, const std::vector<double>& v) {
     return KMX_OK;
 }
 
-// the 2-form metric factor w DF^T DF / det DF per element and point, for the
+// the 2-form metric factor w DF^T DF / det DF per tile and point, for the
 // identity and the deformed cube F(x) = x + a s(x) (1, 1, 1),
 // s = sin(pi x) sin(pi y) sin(pi z): DF = I + a 1 (grad s)^T
 kmx_status t_build_metric(kmx_tspace* ts, std::vector<double>& out) {
     const TAxis &X = ts->ax[0], &Y = ts->ax[1], &Z = ts->ax[2];
-    const int npts = ts->npts;
-    out.assign(size_t(ts->nelem) * 6 * npts, 0.0);
+    const int QX = TT * X.nq, QY = TT * Y.nq, QZ = TT * Z.nq;
+    const int* nt = ts->nt;
+    // [tile][qz][6][qy][qx]; points of padded elements stay zero
+    out.assign(size_t(nt[0]) * nt[1] * nt[2] * QZ * 6 * QY * QX, 0.0);
     for (int ez = 0; ez < Z.N; ++ez)
         for (int ey = 0; ey < Y.N; ++ey)
             for (int ex = 0; ex < X.N; ++ex) {
-                const int64_t elem = (int64_t(ez) * Y.N + ey) * X.N + ex;
+                const int64_t tile = (int64_t(ez / TT) * nt[1] + ey / TT) * nt[0] + ex / TT;
                 for (int iz = 0; iz < Z.nq; ++iz)
                     for (int iy = 0; iy < Y.nq; ++iy)
                         for (int ix = 0; ix < X.nq; ++ix) {
@@ -541,11 +588,12 @@ kmx_status t_build_metric(kmx_tspace* ts, std::vector<double>& out) {
                             if (!(det > 0.0) || !std::isfinite(det))
                                 return t_fail(KMX_E_GEOMETRY, "det DF <= 0 at a quadrature point");
                             const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
-                            const int q = (iz * Y.nq + iy) * X.nq + ix;
+                            const int qz = (ez % TT) * Z.nq + iz, qy = (ey % TT) * Y.nq + iy,
+                                      qx = (ex % TT) * X.nq + ix;
                             for (int k = 0; k < 6; ++k) {
                                 double sum = 0.0;
                                 for (int r = 0; r < 3; ++r) sum += J[3 * r + ii[k]] * J[3 * r + jj[k]];
-                                out[(size_t(elem) * 6 + k) * npts + q] = w * sum / det;
+                                out[((size_t(tile) * QZ + qz) * 6 + k) * QY * QX + size_t(qy) * QX + qx] = w * sum / det;
                             }
                         }
             }
@@ -621,15 +669,13 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
     m.x = x;
     m.x_stride = x_stride;
     m.patch = ts->d_patch;
-    m.patch_stride = int64_t(ts->psize_max) * ts->nelem;
+    m.patch_stride = ts->psize_max;
     m.tab = ts->d_tab;
     for (int a = 0; a < 3; ++a) {
         for (int t = 0; t < 4; ++t) m.tab_off[a][t] = ts->tab_off[a][t];
-        m.p[a] = ts->p[a];
+        m.nt[a] = ts->nt[a];
         m.N[a] = ts->N[a];
-        m.nq[a] = ts->ax[a].nq;
     }
-    m.space = space;
     for (int c = 0; c < 3; ++c) {
         m.comp_off[c] = ts->comp_off[space][c];
         m.pcomp_off[c] = ts->pcomp_off[space][c];
@@ -642,18 +688,14 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
     g.patch_stride = m.patch_stride;
     g.out = y;
     g.out_stride = y_stride;
-    for (int a = 0; a < 3; ++a) {
-        g.p[a] = ts->p[a];
-        g.N[a] = ts->N[a];
-    }
-    g.space = space;
+    for (int a = 0; a < 3; ++a) g.nt[a] = ts->nt[a];
     for (int c = 0; c < 3; ++c) {
         g.comp_off[c] = m.comp_off[c];
         g.pcomp_off[c] = m.pcomp_off[c];
         for (int k = 0; k < 3; ++k) g.dims[c][k] = m.dims[c][k];
     }
     const int64_t n = space == SP_B ? ts->n_h : ts->n_e;
-    t_launch_mass(m, g, n, batch, s, ts->nelem);
+    t_launch_mass(ts->p, m, g, n, batch, s, space);
 }
 
 // out = beta out + alpha D^1 in (primal) or D~^1 in (dual)
@@ -714,23 +756,24 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
     ts->nelem = int64_t(n_elem[0]) * n_elem[1] * n_elem[2];
     ts->npts = ts->ax[0].nq * ts->ax[1].nq * ts->ax[2].nq;
     // per space: component dims (z, y, x), offsets, and patch windows
+    for (int a = 0; a < 3; ++a) ts->nt[a] = (n_elem[a] + TT - 1) / TT;
     for (int sp = 0; sp < 4; ++sp) {
         int64_t off = 0, poff = 0;
         for (int c = 0; c < 3; ++c) {
             ts->comp_off[sp][c] = off;
-            ts->pcomp_off[sp][c] = poff * ts->nelem;
+            ts->pcomp_off[sp][c] = poff;
             int64_t n = 1, w = 1;
             for (int a = 0; a < 3; ++a) {
                 const int tag = space_tag(sp, c, a);
                 const int d = (tag == PV || tag == DD) ? ts->ax[a].n0 : ts->ax[a].n1;
                 ts->dims[sp][c][2 - a] = d;
                 n *= d;
-                w *= tag_support(p[a], tag);
+                w *= int64_t(ts->nt[a]) * (TT + tag_support(p[a], tag) - 1);  // tile windows along a
             }
             off += n;
             poff += w;
         }
-        ts->psize[sp] = int(poff);
+        ts->psize[sp] = poff;
         if (sp == SP_E) ts->n_e = off;
         if (sp == SP_H) ts->n_h = off;
     }
@@ -774,7 +817,7 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
     const size_t nf = size_t(ts->nfield) * max_batch;
     if (hipMalloc(&ts->d_inv_eps, size_t(ts->nelem) * sizeof(double)) != hipSuccess ||
         hipMalloc(&ts->d_inv_mu, size_t(ts->nelem) * sizeof(double)) != hipSuccess ||
-        hipMalloc(&ts->d_patch, size_t(ts->psize_max) * ts->nelem * max_batch * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ts->d_patch, size_t(ts->psize_max) * max_batch * sizeof(double)) != hipSuccess ||
         hipMalloc(&ts->d_u, nf * sizeof(double)) != hipSuccess ||
         hipMalloc(&ts->d_y, nf * sizeof(double)) != hipSuccess ||
         hipMalloc(&ts->d_t, nf * sizeof(double)) != hipSuccess) {
