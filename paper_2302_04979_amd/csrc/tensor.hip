@@ -10,8 +10,10 @@
 // Device layout: fields as in the single-degree spaces (three components one
 // after the other, x fastest inside); the 1D basis tables per direction and
 // tag, element-major [e][q][k] and zero past the last element up to a whole
-// tile; the metric factor w_q DF^T DF / det DF per tile of TT^3 elements as
-// [tile][qz][6][qy][qx]; the mass apply writes, per tile and component, the
+// tile; per direction and Gauss point (sin(pi x), cos(pi x), w), from which
+// the mass kernel forms the metric factor w_q DF^T DF / det DF of the map at
+// every point (the identity and the deformed cube are the maps taken; points
+// of padded elements have w = 0); the mass apply writes, per tile and component, the
 // tile's window of basis functions (TT + K - 1 per direction) with the x rows
 // of the tiles side by side ([tz][ty][wz][wy][tx][wx]), and the gather sums
 // for each output the (at most eight) tile windows that hold it in a fixed
@@ -56,7 +58,9 @@ struct TMassArgs {
     int64_t comp_off[3];
     int dims[3][3];              // [c][z, y, x]
     int64_t pcomp_off[3];        // patch region of each component
-    const double* metric;        // [tile][qz][6][qy][qx], zero at padded points
+    const double* geo;           // per direction: [nt TT][nq][3] = sin(pi x), cos(pi x), w
+    int64_t geo_off[3];
+    double amp;                  // map amplitude a (0: the identity)
     const double* inv_gamma;     // per element (x fastest)
 };
 
@@ -217,7 +221,7 @@ __device__ inline void tt_backward_xy(const TMassArgs& A, double* patch, double 
 // One workgroup per tile of TT^3 elements, one thread per (qy, qx) Gauss
 // column of the tile: the x and y contractions of each component through LDS
 // into register columns, then a walk over the tile's Gauss planes (z
-// interpolation, the metric streamed per point, 1/gamma of the point's
+// interpolation, the metric factor formed per point, 1/gamma of the point's
 // element, the z integration back into register columns), then the y and x
 // integrations into the tile's patch.  Specialised on the three degrees.
 template <int PX, int PY, int PZ, int SPACE>
@@ -256,8 +260,17 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
             tab[a][s][q * TK + k] = v;
         }
     }
-    // 1/gamma of the elements of this thread's column (padded elements: the
-    // metric is zero there)
+    // the map values of the tile's Gauss points, per direction
+    __shared__ double geo[3][T::QM][3];
+    {
+        constexpr int NQ[3] = {T::NQX, T::NQY, T::NQZ};
+        for (int i = tid; i < 3 * T::QM * 3; i += T::NT) {
+            const int a = i / (T::QM * 3), q = (i / 3) % T::QM, k = i % 3;
+            geo[a][q][k] = q < TT * NQ[a] ? A.geo[A.geo_off[a] + (int64_t(t3[a]) * TT * NQ[a] + q) * 3 + k] : 0.0;
+        }
+    }
+    // 1/gamma of the elements of this thread's column (padded elements: their
+    // weights are zero)
     double ig[TT];
     {
         const int ex = min(t3[0] * TT + qx / T::NQX, A.N[0] - 1), ey = min(t3[1] * TT + qy / T::NQY, A.N[1] - 1);
@@ -284,14 +297,26 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
         const double* tz0 = tab[2][W0::sz];
         const double* tz1 = tab[2][W1::sz];
         const double* tz2 = tab[2][W2::sz];
-        const double* gm = A.metric + int64_t(tile) * T::QZ * 6 * T::QY * T::QX + qy * T::QX + qx;
+        // G = w DF^T DF / det DF of F(x) = x + a s(x) (1, 1, 1),
+        // s = sin(pi x) sin(pi y) sin(pi z): DF = I + a 1 g^T with g = grad s,
+        // det DF = 1 + a (g_x + g_y + g_z), DF^T DF = I + a (g 1^T + 1 g^T) + 3 a^2 g g^T
+        const double am = A.amp, a3 = 3.0 * am * am;
+        const double sx = geo[0][qx][0], cx = geo[0][qx][1], wx = geo[0][qx][2];
+        const double sy = geo[1][qy][0], cy = geo[1][qy][1], wy = geo[1][qy][2];
+        const double sxy = sx * sy, pcs = M_PI * cx * sy, psc = M_PI * sx * cy, wxy = wx * wy;
 #pragma unroll
         for (int qz = 0; qz < T::QZ; ++qz) {
-            constexpr int PL = T::QY * T::QX;
             const int ez = qz / T::NQZ;
+            const double sz = geo[2][qz][0], cz = geo[2][qz][1], wz = geo[2][qz][2];
+            const double gx = pcs * sz, gy = psc * sz, gzz = M_PI * sxy * cz;
+            const double f = wxy * wz / fma(am, gx + gy + gzz, 1.0);
             double g[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) g[k] = gm[(qz * 6 + k) * PL];
+            g[0] = f * fma(a3 * gx, gx, fma(2.0 * am, gx, 1.0));
+            g[1] = f * fma(a3 * gy, gy, fma(2.0 * am, gy, 1.0));
+            g[2] = f * fma(a3 * gzz, gzz, fma(2.0 * am, gzz, 1.0));
+            g[3] = f * fma(a3 * gx, gy, am * (gx + gy));
+            g[4] = f * fma(a3 * gx, gzz, am * (gx + gzz));
+            g[5] = f * fma(a3 * gy, gzz, am * (gy + gzz));
             double v0 = 0.0, v1 = 0.0, v2 = 0.0;
 #pragma unroll
             for (int k = 0; k < W0::Kz; ++k) v0 += tz0[qz * TK + k] * a0[ez + k];
@@ -508,7 +533,6 @@ struct kmx_tspace {
     int map_kind = 0;
     double amplitude = 0.0;
     int64_t n_e = 0, n_h = 0, nfield = 0, nelem = 0;
-    int npts = 0;
     TAxis ax[3];
     int dims[4][3][3];          // per space (SP_E..SP_D): [c][z, y, x]
     int64_t comp_off[4][3];
@@ -520,7 +544,8 @@ struct kmx_tspace {
     int64_t fac_off[3][4];      // [direction][F_G, F_M, F_GT, F_MT]
     double* d_tab = nullptr;
     double* d_fac = nullptr;
-    double* d_metric = nullptr;
+    double* d_geo = nullptr;
+    int64_t geo_off[3] = {0, 0, 0};
     double* d_inv_eps = nullptr;
     double* d_inv_mu = nullptr;
     double* d_patch = nullptr;
@@ -552,50 +577,21 @@ kmx_status t_upload(double** dst, const std::vector<double>& v) {
     return KMX_OK;
 }
 
-// the 2-form metric factor w DF^T DF / det DF per tile and point, for the
-// identity and the deformed cube F(x) = x + a s(x) (1, 1, 1),
-// s = sin(pi x) sin(pi y) sin(pi z): DF = I + a 1 (grad s)^T
-kmx_status t_build_metric(kmx_tspace* ts, std::vector<double>& out) {
+// det DF > 0 at every Gauss point of the map (F(x) = x + a s(x) (1, 1, 1):
+// det DF = 1 + a (s_x + s_y + s_z))
+kmx_status t_check_map(const kmx_tspace* ts) {
+    if (ts->map_kind != 1) return KMX_OK;
     const TAxis &X = ts->ax[0], &Y = ts->ax[1], &Z = ts->ax[2];
-    const int QX = TT * X.nq, QY = TT * Y.nq, QZ = TT * Z.nq;
-    const int* nt = ts->nt;
-    // [tile][qz][6][qy][qx]; points of padded elements stay zero
-    out.assign(size_t(nt[0]) * nt[1] * nt[2] * QZ * 6 * QY * QX, 0.0);
-    for (int ez = 0; ez < Z.N; ++ez)
-        for (int ey = 0; ey < Y.N; ++ey)
-            for (int ex = 0; ex < X.N; ++ex) {
-                const int64_t tile = (int64_t(ez / TT) * nt[1] + ey / TT) * nt[0] + ex / TT;
-                for (int iz = 0; iz < Z.nq; ++iz)
-                    for (int iy = 0; iy < Y.nq; ++iy)
-                        for (int ix = 0; ix < X.nq; ++ix) {
-                            const double xh[3] = {X.xq[ex * X.nq + ix], Y.xq[ey * Y.nq + iy], Z.xq[ez * Z.nq + iz]};
-                            const double w = X.wq[ex * X.nq + ix] * Y.wq[ey * Y.nq + iy] * Z.wq[ez * Z.nq + iz];
-                            double J[9];
-                            for (int k = 0; k < 9; ++k) J[k] = (k % 4 == 0) ? 1.0 : 0.0;
-                            if (ts->map_kind == 1) {
-                                const double a = ts->amplitude;
-                                const double sx = std::sin(M_PI * xh[0]), sy = std::sin(M_PI * xh[1]),
-                                             sz = std::sin(M_PI * xh[2]);
-                                const double cx = std::cos(M_PI * xh[0]), cy = std::cos(M_PI * xh[1]),
-                                             cz = std::cos(M_PI * xh[2]);
-                                const double grad[3] = {M_PI * cx * sy * sz, M_PI * sx * cy * sz, M_PI * sx * sy * cz};
-                                for (int r = 0; r < 3; ++r)
-                                    for (int k = 0; k < 3; ++k) J[3 * r + k] += a * grad[k];
-                            }
-                            const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) -
-                                               J[1] * (J[3] * J[8] - J[5] * J[6]) +
-                                               J[2] * (J[3] * J[7] - J[4] * J[6]);
-                            if (!(det > 0.0) || !std::isfinite(det))
-                                return t_fail(KMX_E_GEOMETRY, "det DF <= 0 at a quadrature point");
-                            const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
-                            const int qz = (ez % TT) * Z.nq + iz, qy = (ey % TT) * Y.nq + iy,
-                                      qx = (ex % TT) * X.nq + ix;
-                            for (int k = 0; k < 6; ++k) {
-                                double sum = 0.0;
-                                for (int r = 0; r < 3; ++r) sum += J[3 * r + ii[k]] * J[3 * r + jj[k]];
-                                out[((size_t(tile) * QZ + qz) * 6 + k) * QY * QX + size_t(qy) * QX + qx] = w * sum / det;
-                            }
-                        }
+    const double a = ts->amplitude;
+    for (int kz = 0; kz < Z.N * Z.nq; ++kz)
+        for (int ky = 0; ky < Y.N * Y.nq; ++ky)
+            for (int kx = 0; kx < X.N * X.nq; ++kx) {
+                const double sx = std::sin(M_PI * X.xq[kx]), sy = std::sin(M_PI * Y.xq[ky]),
+                             sz = std::sin(M_PI * Z.xq[kz]);
+                const double cx = std::cos(M_PI * X.xq[kx]), cy = std::cos(M_PI * Y.xq[ky]),
+                             cz = std::cos(M_PI * Z.xq[kz]);
+                const double det = 1.0 + a * M_PI * (cx * sy * sz + sx * cy * sz + sx * sy * cz);
+                if (!(det > 0.0) || !std::isfinite(det)) return t_fail(KMX_E_GEOMETRY, "det DF <= 0 at a quadrature point");
             }
     return KMX_OK;
 }
@@ -681,7 +677,9 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
         m.pcomp_off[c] = ts->pcomp_off[space][c];
         for (int k = 0; k < 3; ++k) m.dims[c][k] = ts->dims[space][c][k];
     }
-    m.metric = ts->d_metric;
+    m.geo = ts->d_geo;
+    for (int a = 0; a < 3; ++a) m.geo_off[a] = ts->geo_off[a];
+    m.amp = ts->map_kind == 1 ? ts->amplitude : 0.0;
     m.inv_gamma = space == SP_B ? ts->d_inv_mu : ts->d_inv_eps;
     TGatherArgs g{};
     g.patch = ts->d_patch;
@@ -754,7 +752,6 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
     ts->map_kind = kind;
     ts->amplitude = map ? map->amplitude : 0.0;
     ts->nelem = int64_t(n_elem[0]) * n_elem[1] * n_elem[2];
-    ts->npts = ts->ax[0].nq * ts->ax[1].nq * ts->ax[2].nq;
     // per space: component dims (z, y, x), offsets, and patch windows
     for (int a = 0; a < 3; ++a) ts->nt[a] = (n_elem[a] + TT - 1) / TT;
     for (int sp = 0; sp < 4; ++sp) {
@@ -810,9 +807,22 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
     }
     if ((st = t_upload(&ts->d_fac, facs)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
     {
-        std::vector<double> met;
-        if ((st = t_build_metric(ts, met)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
-        if ((st = t_upload(&ts->d_metric, met)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
+        if ((st = t_check_map(ts)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
+        // per direction (sin(pi x), cos(pi x), w) at the Gauss points, zero
+        // past the last element up to a whole tile
+        std::vector<double> geo;
+        for (int a = 0; a < 3; ++a) {
+            ts->geo_off[a] = int64_t(geo.size());
+            const TAxis& A = ts->ax[a];
+            const int npad = ts->nt[a] * TT;
+            for (int k = 0; k < npad * A.nq; ++k) {
+                const bool in = k < A.N * A.nq;
+                geo.push_back(in ? std::sin(M_PI * A.xq[k]) : 0.0);
+                geo.push_back(in ? std::cos(M_PI * A.xq[k]) : 0.0);
+                geo.push_back(in ? A.wq[k] : 0.0);
+            }
+        }
+        if ((st = t_upload(&ts->d_geo, geo)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
     }
     const size_t nf = size_t(ts->nfield) * max_batch;
     if (hipMalloc(&ts->d_inv_eps, size_t(ts->nelem) * sizeof(double)) != hipSuccess ||
@@ -835,7 +845,7 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
 
 void kmx_destroy_tspace(kmx_tspace* ts) {
     if (!ts) return;
-    double* bufs[] = {ts->d_tab, ts->d_fac, ts->d_metric, ts->d_inv_eps, ts->d_inv_mu,
+    double* bufs[] = {ts->d_tab, ts->d_fac, ts->d_geo, ts->d_inv_eps, ts->d_inv_mu,
                       ts->d_patch, ts->d_u, ts->d_y, ts->d_t};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
