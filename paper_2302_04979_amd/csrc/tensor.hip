@@ -394,6 +394,42 @@ __global__ void __launch_bounds__(256) ttile_gather_kernel(const TGatherArgs A, 
     A.out[int64_t(b) * A.out_stride + i] = s;
 }
 
+// One difference of the incidence matrices (Section 2.4) along `axis` at
+// (z, y, x): primal v[k] - v[k-1], dual v[k+1] - v[k], zero outside 0..n-1.
+__device__ inline double t_diff(const double* u, const int d[3], int primal, int axis, int z, int y, int x) {
+    const int n = d[2 - axis];
+    const int k = axis == 0 ? x : (axis == 1 ? y : z);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? d[2] : int64_t(d[1]) * d[2]);
+    const int64_t base = (int64_t(z) * d[1] + y) * d[2] + x;
+    const int hi = primal ? k : k + 1, lo = hi - 1;
+    const double a = (hi >= 0 && hi < n) ? u[base + (hi - k) * stride] : 0.0;
+    const double b = (lo >= 0 && lo < n) ? u[base + (lo - k) * stride] : 0.0;
+    return a - b;
+}
+
+// out = D^1 in (primal) or D~^1 in (dual), component c = d_{c+1} in_{c+2} -
+// d_{c+2} in_{c+1}; with `track`, also track += talpha (the same curl): the
+// tracked 2-form's update from the differences already formed.
+__global__ void __launch_bounds__(256) t_curl_kernel(const CurlArgs A, double* track, int64_t track_stride,
+                                                     double talpha, int64_t n_out) {
+    const int b = blockIdx.y;
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n_out) return;
+    const int c = i >= A.out_comp_off[2] ? 2 : (i >= A.out_comp_off[1] ? 1 : 0);
+    const int64_t li = i - A.out_comp_off[c];
+    const int* od = A.out_dims[c];
+    const int x = int(li % od[2]), y = int((li / od[2]) % od[1]), z = int(li / (int64_t(od[2]) * od[1]));
+    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+    const double* in = A.in + int64_t(b) * A.in_stride;
+    const double v = t_diff(in + A.in_comp_off[a2], A.in_dims[a2], A.primal, a1, z, y, x) -
+                     t_diff(in + A.in_comp_off[a1], A.in_dims[a1], A.primal, a2, z, y, x);
+    A.out[int64_t(b) * A.out_stride + i] = v;
+    if (track) {
+        double* t = track + int64_t(b) * track_stride + i;
+        *t = *t + talpha * v;
+    }
+}
+
 template <int PX, int PY, int PZ>
 void t_launch_p(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int space) {
     const int ntile = m.nt[0] * m.nt[1] * m.nt[2];
@@ -696,16 +732,16 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
     t_launch_mass(ts->p, m, g, n, batch, s, space);
 }
 
-// out = beta out + alpha D^1 in (primal) or D~^1 in (dual)
+// out = D^1 in (primal) or D~^1 in (dual); track (optional) += talpha (the curl)
 void t_curl(kmx_tspace* ts, int primal, const double* in, int64_t in_stride, double* out, int64_t out_stride,
-            double alpha, double beta, int batch, hipStream_t s) {
+            double* track, int64_t track_stride, double talpha, int batch, hipStream_t s) {
     CurlArgs a{};
     a.in = in;
     a.in_stride = in_stride;
     a.out = out;
     a.out_stride = out_stride;
-    a.alpha = alpha;
-    a.beta = beta;
+    a.alpha = 1.0;
+    a.beta = 0.0;
     a.primal = primal;
     const int si = primal ? SP_E : SP_H, so = primal ? SP_B : SP_D;
     for (int c = 0; c < 3; ++c) {
@@ -716,7 +752,9 @@ void t_curl(kmx_tspace* ts, int primal, const double* in, int64_t in_stride, dou
             a.out_dims[c][k] = ts->dims[so][c][k];
         }
     }
-    launch_curl(a, primal ? ts->n_h : ts->n_e, batch, s);
+    const int64_t n = primal ? ts->n_h : ts->n_e;
+    hipLaunchKernelGGL(t_curl_kernel, dim3(unsigned((n + 255) / 256), batch), dim3(256), 0, s, a, track, track_stride,
+                       talpha, n);
 }
 
 }  // namespace
@@ -874,7 +912,7 @@ kmx_status kmx_tspace_set_materials(kmx_tspace* ts, const double* eps_elem, cons
 kmx_status kmx_tspace_op_curl(kmx_tspace* ts, int which, const double* x, double* y, void* stream) {
     if (!ts || !x || !y || (which != 0 && which != 1)) return t_fail(KMX_E_ARG, "bad argument");
     const int primal = which == 0;
-    t_curl(ts, primal, x, primal ? ts->n_e : ts->n_h, y, primal ? ts->n_h : ts->n_e, 1.0, 0.0, 1,
+    t_curl(ts, primal, x, primal ? ts->n_e : ts->n_h, y, primal ? ts->n_h : ts->n_e, nullptr, 0, 0.0, 1,
            static_cast<hipStream_t>(stream));
     T_CHECK_LAUNCH();
     return KMX_OK;
@@ -916,13 +954,11 @@ kmx_status kmx_tspace_step(kmx_tspace* ts, double* E, double* H, double dt, int 
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int n = 0; n < nsteps; ++n) {
         // h -= dt K~1^{-1} M D^1 e   (b -= dt D^1 e)
-        t_curl(ts, 1, E, es, ts->d_u, ts->nfield, 1.0, 0.0, batch, s);
-        if (track) t_curl(ts, 1, E, es, H + ts->n_h, hs, -dt, 1.0, batch, s);
+        t_curl(ts, 1, E, es, ts->d_u, ts->nfield, track ? H + ts->n_h : nullptr, hs, -dt, batch, s);
         t_mass(ts, SP_B, ts->d_u, ts->nfield, ts->d_y, ts->nfield, batch, s);
         t_solve(ts, 0, 0, ts->d_y, ts->nfield, H, hs, -dt, 1, 1, batch, s);
         // e += dt K1^{-1} M~ D~^1 h   (d += dt D~^1 h)
-        t_curl(ts, 0, H, hs, ts->d_u, ts->nfield, 1.0, 0.0, batch, s);
-        if (track) t_curl(ts, 0, H, hs, E + ts->n_e, es, dt, 1.0, batch, s);
+        t_curl(ts, 0, H, hs, ts->d_u, ts->nfield, track ? E + ts->n_e : nullptr, es, dt, batch, s);
         t_mass(ts, SP_D, ts->d_u, ts->nfield, ts->d_y, ts->nfield, batch, s);
         t_solve(ts, 1, 0, ts->d_y, ts->nfield, E, es, dt, 1, 1, batch, s);
     }
