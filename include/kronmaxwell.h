@@ -562,6 +562,12 @@ kmx_status kmx_tspace_sizes(const kmx_tspace* ts, int64_t* n_e, int64_t* n_h);
 /* Per-element eps and mu (host, N_x N_y N_z each, x fastest; NULL = 1).
  * Errors: KMX_E_MATERIAL (nothing changed), KMX_E_DEVICE. */
 kmx_status kmx_tspace_set_materials(kmx_tspace* ts, const double* eps_elem, const double* mu_elem);
+/* The form of the pairing solves (eqs. (4.4)-(4.5)): dense = 1 applies the
+ * dense FP64 inverses of the 1D factors on the matrix cores (the default when
+ * every line has at most 80 entries), dense = 0 the banded LU substitutions.
+ * Same results up to rounding.  Errors: KMX_E_ARG; KMX_E_STATE for dense = 1
+ * on a space with a longer line. */
+kmx_status kmx_tspace_set_solver(kmx_tspace* ts, int dense);
 /* The operators of one field (device vectors, as kmx_op_curl, kmx_op_mass
  * without the fused curl, kmx_op_solve and kmx_op_pairing). */
 kmx_status kmx_tspace_op_curl(kmx_tspace* ts, int which, const double* x, double* y, void* stream);

@@ -47,7 +47,7 @@ EXPORTS = (
     "kmx_set_lifting",
     "kmx_create_tspace", "kmx_destroy_tspace", "kmx_tspace_sizes", "kmx_tspace_set_materials",
     "kmx_tspace_op_curl", "kmx_tspace_op_mass", "kmx_tspace_op_solve", "kmx_tspace_op_pairing",
-    "kmx_tspace_step",
+    "kmx_tspace_step", "kmx_tspace_set_solver",
 )
 PROFILE_KINDS = ("mass_B", "mass_D", "solve_xy", "solve_z", "curl", "energy", "gather", "separable",
                  "mode_fp32", "dense_fp64", "mass_1form", "cg_vector")
@@ -141,6 +141,7 @@ def load_library():
         "kmx_tspace_op_solve": ([vp, i, i, vp, vp, vp], i),
         "kmx_tspace_op_pairing": ([vp, i, vp, vp, vp], i),
         "kmx_tspace_step": ([vp, vp, vp, d, i, i, i, vp], i),
+        "kmx_tspace_set_solver": ([vp, i], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -334,6 +335,10 @@ class TSpace:
         m = None if mu is None else _hptr(np.asarray(mu).ravel(), n, name="mu")
         _check(load_library().kmx_tspace_set_materials(self._h, None if e is None else e[1],
                                                        None if m is None else m[1]))
+
+    def set_solver(self, dense: bool):
+        """Dense inverse factors on the matrix cores (True) or banded LU (False)."""
+        _check(load_library().kmx_tspace_set_solver(self._h, int(bool(dense))))
 
     def op_curl(self, primal: bool, x, y):
         n_in, n_out = (self.n_e, self.n_h) if primal else (self.n_h, self.n_e)

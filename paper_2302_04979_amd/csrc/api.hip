@@ -432,6 +432,8 @@ std::vector<double> gram(const Tables& tb, int tag) {
 namespace kmx {
 // Error reporting for the entry points of other sources (last error message).
 kmx_status report_error(kmx_status st, const std::string& msg) { return fail(st, msg); }
+// The dense inverse of a 1D pairing factor for other sources (Gauss-Jordan, FP64).
+std::vector<double> pairing_inverse(const std::vector<double>& A, int n) { return dense_inverse(A, n); }
 }  // namespace kmx
 
 extern "C" {

@@ -344,13 +344,18 @@ hipError_t raise_z(size_t shm) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
 }
 
+// The kernels' LDS grant only ever grows: spaces created later with smaller
+// planes must not shrink what an earlier space's launches need.
 hipError_t dense_prepare(size_t shm) {
+    static size_t granted = 0;
+    if (shm <= granted) return hipSuccess;
     hipError_t e = hipSuccess;
 #define RAISE(K) \
     if (e == hipSuccess) e = raise_xy<K>(shm); \
     if (e == hipSuccess) e = raise_z<K>(shm);
     DENSE_KB_CASES(RAISE)
 #undef RAISE
+    if (e == hipSuccess) granted = shm;
     return e;
 }
 

@@ -36,6 +36,7 @@
 namespace kmx {
 
 kmx_status report_error(kmx_status st, const std::string& msg);  // api.hip
+std::vector<double> pairing_inverse(const std::vector<double>& A, int n);  // api.hip
 
 namespace {
 
@@ -578,6 +579,12 @@ struct kmx_tspace {
     int64_t psize_max = 0;
     int64_t tab_off[3][4];
     int64_t fac_off[3][4];      // [direction][F_G, F_M, F_GT, F_MT]
+    // dense FP64 inverses of the 1D factors in the matrix cores' operand
+    // order (lines of at most DENSE_NMAX entries): the solves' dense form
+    double* d_frag = nullptr;
+    int64_t frag_off[3][4];     // [direction][F_G, F_M, F_GT, F_MT]
+    int dense_ok = 0;           // the dense inverses exist
+    int dense = 0;              // the solves use them (kmx_tspace_set_solver)
     double* d_tab = nullptr;
     double* d_fac = nullptr;
     double* d_geo = nullptr;
@@ -656,6 +663,29 @@ int t_pair_kind(int which_K1, int transpose, int c, int a) {
 void t_solve(kmx_tspace* ts, int which_K1, int transpose, const double* y, int64_t y_stride, double* out,
              int64_t out_stride, double alpha, int accumulate, int solve, int batch, hipStream_t s) {
     const int layout = which_K1 ? SP_D : SP_B;
+    if (solve == 1 && ts->dense) {
+        // B_y Y B_x^T per z plane, then B_z along z, with the dense inverses
+        DenseArgs d{};
+        for (int c = 0; c < 3; ++c) {
+            d.comp_off[c] = ts->comp_off[layout][c];
+            for (int k = 0; k < 3; ++k) d.dims[c][k] = ts->dims[layout][c][k];
+            for (int ax = 0; ax < 3; ++ax) d.frag_off[c][ax] = ts->frag_off[ax][t_pair_kind(which_K1, transpose, c, ax)];
+        }
+        d.frag = ts->d_frag;
+        d.in = y;
+        d.in_stride = y_stride;
+        d.out = ts->d_t;
+        d.out_stride = ts->nfield;
+        launch_dense_xy(d, batch, s);
+        d.in = ts->d_t;
+        d.in_stride = ts->nfield;
+        d.out = out;
+        d.out_stride = out_stride;
+        d.alpha = alpha;
+        d.accumulate = accumulate;
+        launch_dense_z(d, batch, s);
+        return;
+    }
     XYArgs a{};
     a.in = y;
     a.in_stride = y_stride;
@@ -845,6 +875,47 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
     }
     if ((st = t_upload(&ts->d_fac, facs)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
     {
+        // the dense form of the solves when every line fits the dense kernels
+        // and their planes fit the LDS
+        int nmax = 0;
+        for (int a = 0; a < 3; ++a) nmax = std::max(nmax, ts->ax[a].n1);
+        int dev = 0, max_lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            kmx_destroy_tspace(ts);
+            return t_fail(KMX_E_DEVICE, "device attributes");
+        }
+        const size_t shm = std::max(dense_lds_bytes(ts->dims[SP_B]), dense_lds_bytes(ts->dims[SP_D]));
+        if (nmax <= DENSE_NMAX && shm <= size_t(max_lds)) {
+            std::vector<double> frag;
+            try {
+                for (int a = 0; a < 3; ++a)
+                    for (int k = 0; k < 4; ++k) {
+                        const TAxis& A = ts->ax[a];
+                        const int n = (k == F_G || k == F_GT) ? A.n0 : A.n1;
+                        const std::vector<double> Ai = pairing_inverse((k == F_G || k == F_GT) ? A.G : A.M, n);
+                        std::vector<double> B(size_t(n) * n);
+                        const bool tr = k == F_GT || k == F_MT;
+                        for (int i = 0; i < n; ++i)
+                            for (int j = 0; j < n; ++j) B[size_t(i) * n + j] = tr ? Ai[size_t(j) * n + i] : Ai[size_t(i) * n + j];
+                        ts->frag_off[a][k] = int64_t(frag.size());
+                        frag.resize(frag.size() + size_t(dense_frag_doubles(n)));
+                        dense_fragments(B.data(), n, frag.data() + ts->frag_off[a][k]);
+                    }
+            } catch (const std::exception& ex) {
+                kmx_destroy_tspace(ts);
+                return t_fail(KMX_E_ARG, std::string("pairing inverses: ") + ex.what());
+            }
+            if ((st = t_upload(&ts->d_frag, frag)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
+            if (dense_prepare(shm) != hipSuccess) {
+                kmx_destroy_tspace(ts);
+                return t_fail(KMX_E_DEVICE, "dense solve kernels: LDS grant failed");
+            }
+            ts->dense_ok = 1;
+            ts->dense = 1;
+        }
+    }
+    {
         if ((st = t_check_map(ts)) != KMX_OK) { kmx_destroy_tspace(ts); return st; }
         // per direction (sin(pi x), cos(pi x), w) at the Gauss points, zero
         // past the last element up to a whole tile
@@ -883,7 +954,7 @@ kmx_status kmx_create_tspace(const int* p, const int* n_elem, const double* brea
 
 void kmx_destroy_tspace(kmx_tspace* ts) {
     if (!ts) return;
-    double* bufs[] = {ts->d_tab, ts->d_fac, ts->d_geo, ts->d_inv_eps, ts->d_inv_mu,
+    double* bufs[] = {ts->d_tab, ts->d_fac, ts->d_frag, ts->d_geo, ts->d_inv_eps, ts->d_inv_mu,
                       ts->d_patch, ts->d_u, ts->d_y, ts->d_t};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
@@ -907,6 +978,13 @@ kmx_status kmx_tspace_set_materials(kmx_tspace* ts, const double* eps_elem, cons
     kmx_status st;
     if ((st = t_upload_inverse(ts, eps_elem, ts->d_inv_eps)) != KMX_OK) return st;
     return t_upload_inverse(ts, mu_elem, ts->d_inv_mu);
+}
+
+kmx_status kmx_tspace_set_solver(kmx_tspace* ts, int dense) {
+    if (!ts || (dense != 0 && dense != 1)) return t_fail(KMX_E_ARG, "bad argument");
+    if (dense && !ts->dense_ok) return t_fail(KMX_E_STATE, "no dense factors for this space (a line above 80 entries)");
+    ts->dense = dense;
+    return KMX_OK;
 }
 
 kmx_status kmx_tspace_op_curl(kmx_tspace* ts, int which, const double* x, double* y, void* stream) {

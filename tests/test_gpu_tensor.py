@@ -2,9 +2,10 @@
 (Section 4.1: per-direction factors of eqs. (4.2)/(4.3), eqs. (4.4)-(4.5)
 solves; Section 3.4 masses over per-direction Gauss rules) against the
 oracle's TensorScheme on the same seeded inputs: curls bit for bit, mass
-applies, pairing applies and solves, and leapfrog runs with and without b/d
-tracking; batch members equal single runs; a full-size anisotropic graded
-step; the calls it refuses."""
+applies, pairing applies and solves (dense inverses on the matrix cores and
+banded LU), and leapfrog runs with and without b/d tracking; batch members
+equal single runs; a full-size anisotropic graded step; the calls it
+refuses."""
 import numpy as np
 import pytest
 
@@ -18,7 +19,7 @@ def _breaks(cfg):
     return tuple(W.graded_breaks(cfg["n"][a], cfg["ratio"][a]) for a in range(3))
 
 
-def _pair(cfg, seed=3, max_batch=1, deformed=True):
+def _pair(cfg, seed=3, max_batch=1, deformed=True, solver="dense"):
     import paper_2302_04979_amd as K
     from oracle.geometry import Map
     from oracle.tensor import TensorScheme
@@ -29,6 +30,7 @@ def _pair(cfg, seed=3, max_batch=1, deformed=True):
     G = K.TSpace(cfg["p"], cfg["n"], _breaks(cfg), map_kind=1 if deformed else 0,
                  amplitude=W.DEFORMED_AMPLITUDE if deformed else 0.0, max_batch=max_batch)
     G.set_materials(eps=eps, mu=mu)
+    G.set_solver(solver == "dense")
     assert (G.n_e, G.n_h) == (S.n_e, S.n_h)
     return S, G
 
@@ -44,12 +46,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+@pytest.mark.parametrize("solver", ["dense", "banded"])
 @pytest.mark.parametrize("k", range(len(CASES)))
-def test_operators_match_oracle(k):
+def test_operators_match_oracle(k, solver):
     import torch
     cfg = CASES[k]
-    print(f"\n[case] per-direction operators {cfg}", flush=True)
-    S, G = _pair(cfg)
+    print(f"\n[case] per-direction operators {cfg} {solver}", flush=True)
+    S, G = _pair(cfg, solver=solver)
     e = W.random_vector(S.n_e, k, 1)
     h = W.random_vector(S.n_h, k, 2)
     # curls: the same index differences, bit for bit
@@ -77,12 +80,13 @@ def test_operators_match_oracle(k):
             assert np.abs(to_host(out) - ref).max() < 1e-11 * np.abs(ref).max(), (which, tr)
 
 
+@pytest.mark.parametrize("solver", ["dense", "banded"])
 @pytest.mark.parametrize("k", range(len(CASES)))
-def test_leapfrog_matches_oracle(k):
+def test_leapfrog_matches_oracle(k, solver):
     import paper_2302_04979_amd as K
     cfg = CASES[k]
-    print(f"\n[case] per-direction leapfrog {cfg}", flush=True)
-    S, G = _pair(cfg, seed=10 + k)
+    print(f"\n[case] per-direction leapfrog {cfg} {solver}", flush=True)
+    S, G = _pair(cfg, seed=10 + k, solver=solver)
     e0 = W.random_vector(S.n_e, 20 + k, 1)
     h0 = W.random_vector(S.n_h, 20 + k, 2)
     d0 = W.random_vector(S.n_e, 20 + k, 3)
@@ -136,17 +140,19 @@ def test_batch_members_equal_single_runs():
 def test_full_size_graded_anisotropic_step_matches_oracle():
     """The measured workload (degrees (3, 3, 2), 64 x 48 x 32 graded
     elements, deformed cube, eps and mu per element): one step against the
-    oracle, every entry."""
+    oracle, every entry, with the dense (default) and the banded solves."""
     cfg = W.ANISO_FULL
     print(f"\n[case] per-direction full size {cfg}", flush=True)
     S, G = _pair(cfg, seed=60)
     e0 = W.random_vector(S.n_e, 61, 1)
     h0 = W.random_vector(S.n_h, 61, 2)
-    E, H = to_dev(e0), to_dev(h0)
-    G.step(E, H, 1e-3, nsteps=1)
     e, h = S.step(e0, h0, 1e-3, nsteps=1)[:2]
-    assert np.abs(to_host(E) - e).max() < 1e-12 * np.abs(e).max()
-    assert np.abs(to_host(H) - h).max() < 1e-12 * np.abs(h).max()
+    for dense in (True, False):
+        G.set_solver(dense)
+        E, H = to_dev(e0), to_dev(h0)
+        G.step(E, H, 1e-3, nsteps=1)
+        assert np.abs(to_host(E) - e).max() < 1e-12 * np.abs(e).max(), dense
+        assert np.abs(to_host(H) - h).max() < 1e-12 * np.abs(h).max(), dense
 
 
 def test_refusals():
@@ -164,3 +170,4 @@ def test_refusals():
     with pytest.raises(K.KMXError) as ex:
         K.TSpace((2, 3, 2), (3, 3, 3), map_kind=1, amplitude=5.0)  # folds the cube: det DF < 0
     assert ex.value.status == 2
+    assert K.load_library().kmx_tspace_set_solver(G._h, 2) == 1

@@ -113,4 +113,5 @@ def test_argument_errors_of_the_per_direction_spaces():
     assert L.kmx_tspace_set_materials(None, None, None) == 1
     assert L.kmx_tspace_op_mass(None, 0, None, None, None) == 1
     assert L.kmx_tspace_op_solve(None, 0, 0, None, None, None) == 1
+    assert L.kmx_tspace_set_solver(None, 1) == 1
     L.kmx_destroy_tspace(None)  # accepted
