@@ -63,6 +63,14 @@ struct TMassArgs {
     int64_t geo_off[3];
     double amp;                  // map amplitude a (0: the identity)
     const double* inv_gamma;     // per element (x fastest)
+    // with the curl fused: x is the 1-form (layout src_*), the windows are
+    // formed from its differences; track (optional) += talpha (the curl) on
+    // the 2-form entries the tile owns
+    int64_t src_comp_off[3];
+    int src_dims[3][3];
+    double* track;
+    int64_t track_stride;
+    double talpha;
 };
 
 struct TGatherArgs {
@@ -83,6 +91,19 @@ __device__ inline int t_xcd_order(int block, int nblocks) {
     constexpr int XCD = 8;
     const int per = nblocks / XCD;
     return block < per * XCD ? (block % XCD) * per + block / XCD : block;
+}
+
+// One difference of the incidence matrices (Section 2.4) along `axis` at
+// (z, y, x): primal v[k] - v[k-1], dual v[k+1] - v[k], zero outside 0..n-1.
+__device__ inline double t_diff(const double* u, const int d[3], int primal, int axis, int z, int y, int x) {
+    const int n = d[2 - axis];
+    const int k = axis == 0 ? x : (axis == 1 ? y : z);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? d[2] : int64_t(d[1]) * d[2]);
+    const int64_t base = (int64_t(z) * d[1] + y) * d[2] + x;
+    const int hi = primal ? k : k + 1, lo = hi - 1;
+    const double a = (hi >= 0 && hi < n) ? u[base + (hi - k) * stride] : 0.0;
+    const double b = (lo >= 0 && lo < n) ? u[base + (lo - k) * stride] : 0.0;
+    return a - b;
 }
 
 // Window of component C of a 2-form space over one tile, per direction: the
@@ -126,20 +147,40 @@ struct TTile {
 // Interpolation of component C along x and y: the tile window into LDS, the x
 // pass into LDS, the y pass into the thread's register column A[wz] (the
 // window's z planes at the thread's (qy, qx)).
-template <int PX, int PY, int PZ, int SPACE, int C, int WZM>
-__device__ inline void tt_forward_xy(const TMassArgs& A, const double* x, double (*tab)[2][TTile<PX, PY, PZ>::QM * TK],
-                                     double* X, double* AX, const int t3[3], int tid, int qy, int qx, bool active,
-                                     double (&col)[WZM]) {
+template <int PX, int PY, int PZ, int SPACE, bool CURL, int C, int WZM>
+__device__ inline void tt_forward_xy(const TMassArgs& A, const double* x, double* track,
+                                     double (*tab)[2][TTile<PX, PY, PZ>::QM * TK], double* X, double* AX,
+                                     const int t3[3], int tid, int qy, int qx, bool active, double (&col)[WZM]) {
     using Wn = TWin<PX, PY, PZ, SPACE, C>;
     using T = TTile<PX, PY, PZ>;
     const int nx = A.dims[C][2], ny = A.dims[C][1], nz = A.dims[C][0];
     const int gx0 = t3[0] * TT + Wn::ox, gy0 = t3[1] * TT + Wn::oy, gz0 = t3[2] * TT + Wn::oz;
     const double* xc = x + A.comp_off[C];
+    constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
     for (int i = tid; i < Wn::size; i += T::NT) {
         const int wx = i % Wn::Wx, wy = (i / Wn::Wx) % Wn::Wy, wz = i / (Wn::Wx * Wn::Wy);
         const int gx = gx0 + wx, gy = gy0 + wy, gz = gz0 + wz;
         const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-        X[i] = ok ? xc[(int64_t(gz) * ny + gy) * nx + gx] : 0.0;
+        double v = 0.0;
+        if (CURL) {
+            // component C of the curl of the 1-form at this entry
+            if (ok) {
+                constexpr int primal = SPACE == SP_B ? 1 : 0;
+                v = t_diff(x + A.src_comp_off[A2], A.src_dims[A2], primal, A1, gz, gy, gx) -
+                    t_diff(x + A.src_comp_off[A1], A.src_dims[A1], primal, A2, gz, gy, gx);
+                // the tracked 2-form's update on the entries this tile owns
+                // (local index below TT, or any in the last tile of a direction)
+                const bool own = (wx < TT || t3[0] == A.nt[0] - 1) && (wy < TT || t3[1] == A.nt[1] - 1) &&
+                                 (wz < TT || t3[2] == A.nt[2] - 1);
+                if (track && own) {
+                    double* t = track + A.comp_off[C] + (int64_t(gz) * ny + gy) * nx + gx;
+                    *t = *t + A.talpha * v;
+                }
+            }
+        } else {
+            v = ok ? xc[(int64_t(gz) * ny + gy) * nx + gx] : 0.0;
+        }
+        X[i] = v;
     }
     __syncthreads();
     const double* tx = tab[0][Wn::sx];
@@ -225,7 +266,7 @@ __device__ inline void tt_backward_xy(const TMassArgs& A, double* patch, double 
 // interpolation, the metric factor formed per point, 1/gamma of the point's
 // element, the z integration back into register columns), then the y and x
 // integrations into the tile's patch.  Specialised on the three degrees.
-template <int PX, int PY, int PZ, int SPACE>
+template <int PX, int PY, int PZ, int SPACE, bool CURL>
 __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TMassArgs A) {
     using T = TTile<PX, PY, PZ>;
     using W0 = TWin<PX, PY, PZ, SPACE, 0>;
@@ -247,6 +288,7 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
     const int qy = tid / T::QX, qx = tid % T::QX;
     const bool active = tid < T::QX * T::QY;
     const double* x = A.x + int64_t(b) * A.x_stride;
+    double* track = A.track ? A.track + int64_t(b) * A.track_stride : nullptr;
 
     // the tile's 1D tables, both tags of the space per direction
     {
@@ -286,9 +328,9 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
     double a0[WZM], a1[WZM], a2[WZM];
 #pragma unroll
     for (int k = 0; k < WZM; ++k) a0[k] = a1[k] = a2[k] = 0.0;
-    tt_forward_xy<PX, PY, PZ, SPACE, 0, WZM>(A, x, tab, X, AX, t3, tid, qy, qx, active, a0);
-    tt_forward_xy<PX, PY, PZ, SPACE, 1, WZM>(A, x, tab, X, AX, t3, tid, qy, qx, active, a1);
-    tt_forward_xy<PX, PY, PZ, SPACE, 2, WZM>(A, x, tab, X, AX, t3, tid, qy, qx, active, a2);
+    tt_forward_xy<PX, PY, PZ, SPACE, CURL, 0, WZM>(A, x, track, tab, X, AX, t3, tid, qy, qx, active, a0);
+    tt_forward_xy<PX, PY, PZ, SPACE, CURL, 1, WZM>(A, x, track, tab, X, AX, t3, tid, qy, qx, active, a1);
+    tt_forward_xy<PX, PY, PZ, SPACE, CURL, 2, WZM>(A, x, track, tab, X, AX, t3, tid, qy, qx, active, a2);
 
     // the walk over the tile's Gauss planes
     double r0[WZM], r1[WZM], r2[WZM];
@@ -395,19 +437,6 @@ __global__ void __launch_bounds__(256) ttile_gather_kernel(const TGatherArgs A, 
     A.out[int64_t(b) * A.out_stride + i] = s;
 }
 
-// One difference of the incidence matrices (Section 2.4) along `axis` at
-// (z, y, x): primal v[k] - v[k-1], dual v[k+1] - v[k], zero outside 0..n-1.
-__device__ inline double t_diff(const double* u, const int d[3], int primal, int axis, int z, int y, int x) {
-    const int n = d[2 - axis];
-    const int k = axis == 0 ? x : (axis == 1 ? y : z);
-    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? d[2] : int64_t(d[1]) * d[2]);
-    const int64_t base = (int64_t(z) * d[1] + y) * d[2] + x;
-    const int hi = primal ? k : k + 1, lo = hi - 1;
-    const double a = (hi >= 0 && hi < n) ? u[base + (hi - k) * stride] : 0.0;
-    const double b = (lo >= 0 && lo < n) ? u[base + (lo - k) * stride] : 0.0;
-    return a - b;
-}
-
 // out = D^1 in (primal) or D~^1 in (dual), component c = d_{c+1} in_{c+2} -
 // d_{c+2} in_{c+1}; with `track`, also track += talpha (the same curl): the
 // tracked 2-form's update from the differences already formed.
@@ -432,26 +461,28 @@ __global__ void __launch_bounds__(256) t_curl_kernel(const CurlArgs A, double* t
 }
 
 template <int PX, int PY, int PZ>
-void t_launch_p(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int space) {
+void t_launch_p(const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s, int space, bool curl) {
     const int ntile = m.nt[0] * m.nt[1] * m.nt[2];
     const dim3 gm(unsigned(ntile), batch), gg(unsigned((n + 255) / 256), batch);
     const dim3 bm(TTile<PX, PY, PZ>::NT);
     if (space == SP_B) {
-        hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_B>), gm, bm, 0, s, m);
+        if (curl) hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_B, true>), gm, bm, 0, s, m);
+        else hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_B, false>), gm, bm, 0, s, m);
         hipLaunchKernelGGL((ttile_gather_kernel<PX, PY, PZ, SP_B>), gg, dim3(256), 0, s, g, n);
     } else {
-        hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_D>), gm, bm, 0, s, m);
+        if (curl) hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_D, true>), gm, bm, 0, s, m);
+        else hipLaunchKernelGGL((ttile_mass_kernel<PX, PY, PZ, SP_D, false>), gm, bm, 0, s, m);
         hipLaunchKernelGGL((ttile_gather_kernel<PX, PY, PZ, SP_D>), gg, dim3(256), 0, s, g, n);
     }
 }
 
 // the mass kernel and the gather for the space's degrees (2..4 each)
 void t_launch_mass(const int p[3], const TMassArgs& m, const TGatherArgs& g, int64_t n, int batch, hipStream_t s,
-                   int space) {
+                   int space, bool curl) {
     const int code = (p[0] - 2) * 9 + (p[1] - 2) * 3 + (p[2] - 2);
 #define TL(PX, PY, PZ)                                                       \
     case (PX - 2) * 9 + (PY - 2) * 3 + (PZ - 2):                             \
-        t_launch_p<PX, PY, PZ>(m, g, n, batch, s, space);                    \
+        t_launch_p<PX, PY, PZ>(m, g, n, batch, s, space, curl);              \
         return;
 #define TL3(PX, PY) TL(PX, PY, 2) TL(PX, PY, 3) TL(PX, PY, 4)
     switch (code) {
@@ -724,10 +755,22 @@ void t_solve(kmx_tspace* ts, int which_K1, int transpose, const double* y, int64
     launch_z(ts->pmax, z, batch, s);
 }
 
-// y = M x (space SP_B: M^2_{1/mu}; SP_D: M~^2_{1/eps}) for `batch` fields
+// y = M x (space SP_B: M^2_{1/mu}; SP_D: M~^2_{1/eps}) for `batch` fields;
+// with `curl`, y = M D x for the 1-form x (D^1 for B, D~^1 for D) and, when
+// track is given, track += talpha D x
 void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double* y, int64_t y_stride, int batch,
-            hipStream_t s) {
+            hipStream_t s, bool curl = false, double* track = nullptr, int64_t track_stride = 0, double talpha = 0.0) {
     TMassArgs m{};
+    if (curl) {
+        const int src = space == SP_B ? SP_E : SP_H;
+        for (int c = 0; c < 3; ++c) {
+            m.src_comp_off[c] = ts->comp_off[src][c];
+            for (int k = 0; k < 3; ++k) m.src_dims[c][k] = ts->dims[src][c][k];
+        }
+        m.track = track;
+        m.track_stride = track_stride;
+        m.talpha = talpha;
+    }
     m.x = x;
     m.x_stride = x_stride;
     m.patch = ts->d_patch;
@@ -759,7 +802,7 @@ void t_mass(kmx_tspace* ts, int space, const double* x, int64_t x_stride, double
         for (int k = 0; k < 3; ++k) g.dims[c][k] = m.dims[c][k];
     }
     const int64_t n = space == SP_B ? ts->n_h : ts->n_e;
-    t_launch_mass(ts->p, m, g, n, batch, s, space);
+    t_launch_mass(ts->p, m, g, n, batch, s, space, curl);
 }
 
 // out = D^1 in (primal) or D~^1 in (dual); track (optional) += talpha (the curl)
@@ -1032,12 +1075,10 @@ kmx_status kmx_tspace_step(kmx_tspace* ts, double* E, double* H, double dt, int 
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int n = 0; n < nsteps; ++n) {
         // h -= dt K~1^{-1} M D^1 e   (b -= dt D^1 e)
-        t_curl(ts, 1, E, es, ts->d_u, ts->nfield, track ? H + ts->n_h : nullptr, hs, -dt, batch, s);
-        t_mass(ts, SP_B, ts->d_u, ts->nfield, ts->d_y, ts->nfield, batch, s);
+        t_mass(ts, SP_B, E, es, ts->d_y, ts->nfield, batch, s, true, track ? H + ts->n_h : nullptr, hs, -dt);
         t_solve(ts, 0, 0, ts->d_y, ts->nfield, H, hs, -dt, 1, 1, batch, s);
         // e += dt K1^{-1} M~ D~^1 h   (d += dt D~^1 h)
-        t_curl(ts, 0, H, hs, ts->d_u, ts->nfield, track ? E + ts->n_e : nullptr, es, dt, batch, s);
-        t_mass(ts, SP_D, ts->d_u, ts->nfield, ts->d_y, ts->nfield, batch, s);
+        t_mass(ts, SP_D, H, hs, ts->d_y, ts->nfield, batch, s, true, track ? E + ts->n_e : nullptr, es, dt);
         t_solve(ts, 1, 0, ts->d_y, ts->nfield, E, es, dt, 1, 1, batch, s);
     }
     T_CHECK_LAUNCH();
