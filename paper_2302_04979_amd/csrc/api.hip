@@ -302,7 +302,14 @@ void run_energy(kmx_space* sp, const double* E, const double* H, double dt, int 
 
 // Per-step energy of tracked states from the kept images w_e = K1 e and
 // w_h = K~1 h (updated by the substeps) and the fields themselves.
-void run_energy_dots(kmx_space* sp, const double* E, const double* H, double dt, int batch, double* out,
+// Step n writes its partials to half n % 2 of the reduction buffer, and its
+// launch finishes step n - 1's energy from the other half (out[-batch..-1]);
+// finish_energy_dots sums the last step's.
+static double* energy_half(kmx_space* sp, int n, int batch) {
+    return sp->d_red + int64_t(n & 1) * batch * ENERGY_DOT_WORKERS * 3;
+}
+
+void run_energy_dots(kmx_space* sp, const double* E, const double* H, double dt, int batch, int n, double* out,
                      hipStream_t s) {
     ProfScope ps(sp, s, PK_ENERGY);
     EnergyDotsArgs a{};
@@ -314,9 +321,18 @@ void run_energy_dots(kmx_space* sp, const double* E, const double* H, double dt,
     a.n_h = sp->n_h;
     space_dims(sp, SP_E, a.e_dims, a.e_comp_off);
     space_dims(sp, SP_B, a.h_dims, a.h_comp_off);
-    a.partial = sp->d_red;
+    a.partial = energy_half(sp, n, batch);
+    if (n > 0) {
+        a.prev_partial = energy_half(sp, n - 1, batch);
+        a.prev_out = out - batch;
+        a.prev_dt = dt;
+    }
     launch_energy_dots(a, batch, s);
-    launch_energy_final(sp->d_red, ENERGY_DOT_BLOCKS, dt, batch, out, 1, s);
+}
+
+void finish_energy_dots(kmx_space* sp, double dt, int batch, int n, double* out, hipStream_t s) {
+    ProfScope ps(sp, s, PK_ENERGY);
+    launch_energy_final(energy_half(sp, n, batch), ENERGY_DOT_WORKERS, dt, batch, out, 1, s);
 }
 
 // The forward model of the probe misfit and its adjoint run the tiled plan,
@@ -624,13 +640,14 @@ kmx_status kmx_create_space(int p, int n_elem, const kmx_map* map, int precision
         const int64_t nfield = std::max(sp->n_e, sp->n_h);
         {
             // reduction partials: the CG and dot kernels use up to 1024 blocks per
-            // member, the fused energy kernel one per (component, plane, row block)
+            // member, the per-step energy dots two halves of ENERGY_DOT_BLOCKS,
+            // the fused energy kernel one per (component, plane, row block)
             int ed[3][3], hd[3][3], cb[3];
             int64_t o[3];
             space_dims(sp, SP_E, ed, o);
             space_dims(sp, SP_B, hd, o);
             const int64_t nbe = energy_fused_blocks(ed, cb) + energy_fused_blocks(hd, cb);
-            sp->red_len = int64_t(max_batch) * std::max<int64_t>(std::max(1024, ENERGY_DOT_BLOCKS), nbe) * 3 + 64;
+            sp->red_len = int64_t(max_batch) * std::max<int64_t>(std::max(1024, 2 * ENERGY_DOT_BLOCKS), nbe) * 3 + 64;
         }
         if (hipMalloc(&sp->d_patch, size_t(sp->patch_per_field) * max_batch * sizeof(double)) != hipSuccess ||
             hipMalloc(&sp->d_tmp, size_t(nfield) * max_batch * sizeof(double)) != hipSuccess ||
@@ -1612,8 +1629,10 @@ kmx_status step_loop(kmx_space* sp, double* E, double* H, const kmx_source* J, d
         const double t_half = (t_dev ? 0.0 : t_start) + (n + 0.5) * dt;
         tiled_substep(sp, E, H, es, hs, dt, dt, batch, track, dense, mixed, J, t_half, t_dev, s, t_dev ? 0.0 : t_start,
                       n * dt, energy_dev != nullptr);
-        if (energy_dev) run_energy_dots(sp, E, H, dt, batch, energy_dev + int64_t(n) * batch, s);
+        if (energy_dev) run_energy_dots(sp, E, H, dt, batch, n, energy_dev + int64_t(n) * batch, s);
     }
+    if (energy_dev && nsteps > 0)
+        finish_energy_dots(sp, dt, batch, nsteps - 1, energy_dev + int64_t(nsteps - 1) * batch, s);
     if (t_dev) launch_advance_time(const_cast<double*>(t_dev), nsteps * dt, s);
     CHECK_LAUNCH();
     return KMX_OK;

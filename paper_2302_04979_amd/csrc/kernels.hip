@@ -1478,17 +1478,39 @@ int energy_fused_blocks(const int dims[3][3], int cb[3]) {
 // the partial sums of d . w_e, b . w_h and w_h . D^1 e, in a fixed order
 // (grid-stride loops over a fixed grid, then block_sum3).  The first EB
 // blocks take the d . w_e items, the others the b . w_h and w_h . D^1 e items
-// (EB = 0: every block takes items of both kinds).
+// (EB = 0: every block takes items of both kinds).  Block 0 takes no items:
+// with A.prev_out set it sums the previous step's partials into that step's
+// energy (what energy_final_kernel does), so that a run of steps needs the
+// separate final launch only after its last step.  The grid stays at
+// ENERGY_DOT_BLOCKS, which fills the chip's workgroup slots in one wave.
+__device__ inline void energy_finish(const double* partial, int nblocks, double dt, double* out) {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += 256) {
+        t0 += partial[int64_t(k) * 3];
+        t1 += partial[int64_t(k) * 3 + 1];
+        t2 += partial[int64_t(k) * 3 + 2];
+    }
+    __shared__ double r[3];
+    block_sum3<256>(t0, t1, t2, r);
+    __syncthreads();
+    if (threadIdx.x == 0) *out = 0.5 * (r[0] + r[1]) - 0.5 * dt * r[2];
+}
+
 template <int U, int EB>
 __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A) {
     const int bm = blockIdx.y;
+    constexpr int NB = ENERGY_DOT_WORKERS;
+    if (blockIdx.x == 0) {
+        if (A.prev_out) energy_finish(A.prev_partial + int64_t(bm) * NB * 3, NB, A.prev_dt, A.prev_out + bm);
+        return;
+    }
     const double* E = A.E + int64_t(bm) * 2 * A.n_e;
     const double* H = A.H + int64_t(bm) * 2 * A.n_h;
     const double* we = A.we + int64_t(bm) * A.n_e;
     const double* wh = A.wh + int64_t(bm) * A.n_h;
-    const int bx = blockIdx.x;
+    const int bx = int(blockIdx.x) - 1;
     const bool do_e = EB == 0 || bx < EB, do_h = EB == 0 || bx >= EB;
-    const int64_t se = int64_t(EB == 0 ? gridDim.x : EB) * 256, sh = int64_t(gridDim.x - EB) * 256;
+    const int64_t se = int64_t(EB == 0 ? NB : EB) * 256, sh = int64_t(NB - EB) * 256;
     const int64_t ie = int64_t(bx) * 256 + threadIdx.x, ih = int64_t(bx - (EB == 0 ? 0 : EB)) * 256 + threadIdx.x;
     // U entries per thread and round, all loads requested before the sums
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -1536,7 +1558,7 @@ __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A
     __shared__ double r[3];
     block_sum3<256>(s0, s1, s2, r);
     if (threadIdx.x == 0) {
-        double* o = A.partial + (int64_t(bm) * gridDim.x + blockIdx.x) * 3;
+        double* o = A.partial + (int64_t(bm) * NB + bx) * 3;
         o[0] = r[0];
         o[1] = r[1];
         o[2] = r[2];
@@ -1544,8 +1566,8 @@ __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A
 }
 
 void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s) {
-    hipLaunchKernelGGL((energy_dots_kernel<ENERGY_DOT_UNROLL, ENERGY_DOT_EBLOCKS>), dim3(ENERGY_DOT_BLOCKS, batch),
-                       dim3(256), 0, s, a);
+    hipLaunchKernelGGL((energy_dots_kernel<ENERGY_DOT_UNROLL, ENERGY_DOT_EBLOCKS>),
+                       dim3(ENERGY_DOT_BLOCKS, batch), dim3(256), 0, s, a);
 }
 
 // A dense source pattern times a sampled time series: g(t) by linear

@@ -124,7 +124,12 @@ struct EnergyDotsArgs {
     int64_t n_e, n_h;
     int64_t e_comp_off[3], h_comp_off[3];
     int e_dims[3][3], h_dims[3][3];
-    double* partial;            // [batch][gridDim.x][3]
+    double* partial;            // [batch][ENERGY_DOT_WORKERS][3]
+    // optional: the previous step's partials, finished into prev_out[batch]
+    // by one extra workgroup of the same launch (NULL: none)
+    const double* prev_partial;
+    double* prev_out;
+    double prev_dt;
 };
 
 struct PairGradArgs {           // per-element metric pairing of lam and D~^1 h
@@ -245,6 +250,7 @@ void launch_pattern_source(double* y, int64_t y_stride, const double* P, int64_t
                            const double* series, int m, double t0, double h, const double* t_dev, double t_src,
                            int batch, hipStream_t s);
 constexpr int ENERGY_DOT_BLOCKS = 2048;  // blocks per member of the dot kernel
+constexpr int ENERGY_DOT_WORKERS = ENERGY_DOT_BLOCKS - 1;  // the first block finishes the previous step
 constexpr int ENERGY_DOT_UNROLL = 1;     // entries per thread and loop round
 constexpr int ENERGY_DOT_EBLOCKS = 512;  // of the blocks, those that take the d . w_e items alone (0: all take both)
 void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s);

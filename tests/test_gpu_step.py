@@ -127,6 +127,42 @@ def test_batch_members_equal_single_runs_bitwise():
         assert np.array_equal(Hb[k * S.n_h:(k + 1) * S.n_h], to_host(H1))
 
 
+def test_batched_per_step_energies():
+    """The per-step energies of a batch of tracked runs: each member's series
+    equals its single run's bit for bit and the oracle's, for runs of one
+    step and of several (a step's energy is summed inside the next step's
+    launch, the last one by a launch of its own), and the same run made as
+    two calls gives the oracle's series too."""
+    import torch
+    S, G = make_pair(3, 5, deformed=True, max_batch=3)
+    dt = 0.01
+    states = [_state(S, 60 + k) for k in range(3)]
+    for nsteps in (1, 2, 7):
+        print(f"\n[case] batched energies nsteps={nsteps}", flush=True)
+        E = to_dev(np.concatenate([np.concatenate([st[0], st[1]]) for st in states]))
+        H = to_dev(np.concatenate([np.concatenate([st[2], st[3]]) for st in states]))
+        en = torch.full((nsteps, 3), float("nan"), dtype=torch.float64, device="cuda")
+        G.step(E, H, dt, nsteps=nsteps, batch=3, flags=1, energy=en)
+        en = to_host(en)
+        for k, (e0, d0, h0, b0) in enumerate(states):
+            E1 = to_dev(np.concatenate([e0, d0]))
+            H1 = to_dev(np.concatenate([h0, b0]))
+            single = torch.full((nsteps,), float("nan"), dtype=torch.float64, device="cuda")
+            G.step(E1, H1, dt, nsteps=nsteps, flags=1, energy=single)
+            assert np.array_equal(en[:, k], to_host(single)), (nsteps, k)
+            ref = np.array(S.step(e0, h0, dt, nsteps=nsteps, d=d0, b=b0, energy_every=1)[4])
+            assert np.abs(en[:, k] - ref).max() < 1e-12 * np.abs(ref).max(), (nsteps, k)
+            if nsteps > 1:  # the same run as two calls (the second re-forms K1 e and K~1 h)
+                E1 = to_dev(np.concatenate([e0, d0]))
+                H1 = to_dev(np.concatenate([h0, b0]))
+                first = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+                rest = torch.full((nsteps - 1,), float("nan"), dtype=torch.float64, device="cuda")
+                G.step(E1, H1, dt, nsteps=1, flags=1, energy=first)
+                G.step(E1, H1, dt, nsteps=nsteps - 1, flags=1, energy=rest)
+                two = np.concatenate([to_host(first), to_host(rest)])
+                assert np.abs(two - ref).max() < 1e-12 * np.abs(ref).max(), (nsteps, k)
+
+
 def test_run_to_run_bitwise_determinism():
     S, G = make_pair(3, 8, deformed=True)
     e0, _, h0, _ = _state(S, 5)
