@@ -1477,8 +1477,8 @@ int energy_fused_blocks(const int dims[3][3], int cb[3]) {
 // relations of eqs. (3.11) and (3.13) applied to the increments): per block
 // the partial sums of d . w_e, b . w_h and w_h . D^1 e, in a fixed order
 // (grid-stride loops over a fixed grid, then block_sum3).  The first EB
-// blocks take the d . w_e items, the others the b . w_h and w_h . D^1 e items
-// (EB = 0: every block takes items of both kinds).  Block 0 takes no items:
+// working blocks take the d . w_e items, the others the b . w_h and
+// w_h . D^1 e items by 2-form positions.  Block 0 takes no items:
 // with A.prev_out set it sums the previous step's partials into that step's
 // energy (what energy_final_kernel does), so that a run of steps needs the
 // separate final launch only after its last step.  The grid stays at
@@ -1496,6 +1496,28 @@ __device__ inline void energy_finish(const double* partial, int nblocks, double 
     if (threadIdx.x == 0) *out = 0.5 * (r[0] + r[1]) - 0.5 * dt * r[2];
 }
 
+// One e component's value at (z, y, x) and at the positions one step back
+// along its two other axes (zero outside the component: e is zero on the
+// boundary), the three loads issued together.
+template <int A_>
+__device__ inline void e_star(const double* u, const int d[3], int z, int y, int x, double& c, double& m1,
+                              double& m2) {
+    constexpr int a1 = (A_ + 1) % 3, a2 = (A_ + 2) % 3;  // the axes it is differenced along
+    const int nz = d[0], ny = d[1], nx = d[2];
+    const int base = (z * ny + y) * nx + x;
+    auto back = [&](int ax) { return ax == 0 ? 1 : (ax == 1 ? nx : nx * ny); };
+    auto coord = [&](int ax) { return ax == 0 ? x : (ax == 1 ? y : z); };
+    const bool in = z < nz && y < ny && x < nx;
+    const bool in1 = coord(a1) >= 1 && coord(a1) - 1 < d[2 - a1] && (a1 == 2 || z < nz) &&
+                     (a1 == 1 || y < ny) && (a1 == 0 || x < nx);
+    const bool in2 = coord(a2) >= 1 && coord(a2) - 1 < d[2 - a2] && (a2 == 2 || z < nz) &&
+                     (a2 == 1 || y < ny) && (a2 == 0 || x < nx);
+    const double v = u[in ? base : 0], v1 = u[in1 ? base - back(a1) : 0], v2 = u[in2 ? base - back(a2) : 0];
+    c = in ? v : 0.0;
+    m1 = in1 ? v1 : 0.0;
+    m2 = in2 ? v2 : 0.0;
+}
+
 template <int U, int EB>
 __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A) {
     const int bm = blockIdx.y;
@@ -1504,55 +1526,71 @@ __global__ void __launch_bounds__(256) energy_dots_kernel(const EnergyDotsArgs A
         if (A.prev_out) energy_finish(A.prev_partial + int64_t(bm) * NB * 3, NB, A.prev_dt, A.prev_out + bm);
         return;
     }
+    static_assert(EB > 0 && EB < NB, "the d . w_e items and the 2-form positions take blocks of their own");
     const double* E = A.E + int64_t(bm) * 2 * A.n_e;
     const double* H = A.H + int64_t(bm) * 2 * A.n_h;
     const double* we = A.we + int64_t(bm) * A.n_e;
     const double* wh = A.wh + int64_t(bm) * A.n_h;
     const int bx = int(blockIdx.x) - 1;
-    const bool do_e = EB == 0 || bx < EB, do_h = EB == 0 || bx >= EB;
-    const int64_t se = int64_t(EB == 0 ? NB : EB) * 256, sh = int64_t(NB - EB) * 256;
-    const int64_t ie = int64_t(bx) * 256 + threadIdx.x, ih = int64_t(bx - (EB == 0 ? 0 : EB)) * 256 + threadIdx.x;
-    // U entries per thread and round, all loads requested before the sums
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int64_t ib = ie; do_e && ib < A.n_e; ib += U * se) {
-        double dv[U], wv[U];
+    if (bx < EB) {
+        // d . w_e, U entries per thread and round, all loads requested before the sums
+        const int64_t se = int64_t(EB) * 256;
+        for (int64_t ib = int64_t(bx) * 256 + threadIdx.x; ib < A.n_e; ib += U * se) {
+            double dv[U], wv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = ib + u * se;
-            const bool ok = i < A.n_e;
-            const double a = E[A.n_e + (ok ? i : 0)], b = we[ok ? i : 0];
-            dv[u] = ok ? a : 0.0;
-            wv[u] = ok ? b : 0.0;
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = ib + u * se;
+                const bool ok = i < A.n_e;
+                const double a = E[A.n_e + (ok ? i : 0)], b = we[ok ? i : 0];
+                dv[u] = ok ? a : 0.0;
+                wv[u] = ok ? b : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) s0 = fma(dv[u], wv[u], s0);
         }
+    } else {
+        // b . w_h and w_h . D^1 e by positions (z, y, x) of the box that holds
+        // the three 2-form components: at each, the components whose dims
+        // contain it, (D^1 e)_c = d_{c+1} e_{c+2} - d_{c+2} e_{c+1} from the
+        // nine e values around the position, each e value loaded once
+        int bz = 0, by = 0, bxn = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) s0 = fma(dv[u], wv[u], s0);
-    }
-    for (int64_t ib = ih; do_h && ib < A.n_h; ib += U * sh) {
-        double wv[U], bv[U], de[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = ib + u * sh;
-            const bool ok = i < A.n_h;
-            const int64_t j = ok ? i : 0;
-            const double w = wh[j], bb = H[A.n_h + j];
-            // D^1 e at entry j of the 2-form: component c = d_{c+1} e_{c+2} - d_{c+2} e_{c+1}
-            const int c = j >= A.h_comp_off[2] ? 2 : (j >= A.h_comp_off[1] ? 1 : 0);
-            const int li = int(j - A.h_comp_off[c]);
-            const int nx = A.h_dims[c][2], ny = A.h_dims[c][1];
+        for (int c = 0; c < 3; ++c) {
+            bz = max(bz, A.h_dims[c][0]);
+            by = max(by, A.h_dims[c][1]);
+            bxn = max(bxn, A.h_dims[c][2]);
+        }
+        const int npos = bz * by * bxn;
+        const int sh = (NB - EB) * 256;
+        for (int ip = (bx - EB) * 256 + int(threadIdx.x); ip < npos; ip += sh) {
             int x, y;
-            const int row = fast_divmod(li, nx, x);
-            const int z = fast_divmod(row, ny, y);
-            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            const double d = diff1_primal(E + A.e_comp_off[a2], A.e_dims[a2], a1, z, y, x) -
-                             diff1_primal(E + A.e_comp_off[a1], A.e_dims[a1], a2, z, y, x);
-            wv[u] = ok ? w : 0.0;
-            bv[u] = ok ? bb : 0.0;
-            de[u] = ok ? d : 0.0;
-        }
+            const int row = fast_divmod(ip, bxn, x);
+            const int z = fast_divmod(row, by, y);
+            double w[3], bb[3];
+            bool ok[3];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            s1 = fma(bv[u], wv[u], s1);
-            s2 = fma(wv[u], de[u], s2);
+            for (int c = 0; c < 3; ++c) {
+                const int* d = A.h_dims[c];
+                ok[c] = z < d[0] && y < d[1] && x < d[2];
+                const int64_t j = A.h_comp_off[c] + (ok[c] ? (z * d[1] + y) * d[2] + x : 0);
+                w[c] = wh[j];
+                bb[c] = H[A.n_h + j];
+            }
+            // e_a at the position (c) and one step back along a + 1 (m1) and a + 2 (m2)
+            double ec[3], m1[3], m2[3];
+            e_star<0>(E + A.e_comp_off[0], A.e_dims[0], z, y, x, ec[0], m1[0], m2[0]);
+            e_star<1>(E + A.e_comp_off[1], A.e_dims[1], z, y, x, ec[1], m1[1], m2[1]);
+            e_star<2>(E + A.e_comp_off[2], A.e_dims[2], z, y, x, ec[2], m1[2], m2[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+                // d_{a1} e_{a2}: e_{a2} back along a1, which is a2 + 2; d_{a2} e_{a1}: e_{a1} back along a2 = a1 + 1
+                const double dv = (ec[a2] - m2[a2]) - (ec[a1] - m1[a1]);
+                const double wv = ok[c] ? w[c] : 0.0, bv = ok[c] ? bb[c] : 0.0;
+                s1 = fma(bv, wv, s1);
+                s2 = fma(wv, ok[c] ? dv : 0.0, s2);
+            }
         }
     }
     __shared__ double r[3];

@@ -252,7 +252,7 @@ void launch_pattern_source(double* y, int64_t y_stride, const double* P, int64_t
 constexpr int ENERGY_DOT_BLOCKS = 2048;  // blocks per member of the dot kernel
 constexpr int ENERGY_DOT_WORKERS = ENERGY_DOT_BLOCKS - 1;  // the first block finishes the previous step
 constexpr int ENERGY_DOT_UNROLL = 1;     // entries per thread and loop round
-constexpr int ENERGY_DOT_EBLOCKS = 512;  // of the blocks, those that take the d . w_e items alone (0: all take both)
+constexpr int ENERGY_DOT_EBLOCKS = 768;  // of the working blocks, those that take the d . w_e items
 void launch_energy_dots(const EnergyDotsArgs& a, int batch, hipStream_t s);
 int energy_fused_blocks(const int dims[3][3], int cb[3]);
 // out[b*out_stride] (+ step offset) from the energy partials
