@@ -106,6 +106,15 @@ __device__ inline double t_diff(const double* u, const int d[3], int primal, int
     return a - b;
 }
 
+// 1/d by the hardware's reciprocal estimate and two Newton-Raphson steps
+// r <- r + r (1 - d r), each of which squares the relative error.
+__device__ inline double t_recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
 // Window of component C of a 2-form space over one tile, per direction: the
 // functions nonzero on one element (K), the tile window W = TT + K - 1 and the
 // offset of local index 0 in the global numbering.
@@ -341,25 +350,21 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
         const double* tz1 = tab[2][W1::sz];
         const double* tz2 = tab[2][W2::sz];
         // G = w DF^T DF / det DF of F(x) = x + a s(x) (1, 1, 1),
-        // s = sin(pi x) sin(pi y) sin(pi z): DF = I + a 1 g^T with g = grad s,
-        // det DF = 1 + a (g_x + g_y + g_z), DF^T DF = I + a (g 1^T + 1 g^T) + 3 a^2 g g^T
-        const double am = A.amp, a3 = 3.0 * am * am;
+        // s = sin(pi x) sin(pi y) sin(pi z): with q = a grad s, DF = I + 1 q^T,
+        // det DF = 1 + q . 1 and DF^T DF = I + q 1^T + 1 q^T + 3 q q^T, so
+        // G v = f (v + (S + 3 Q) q + Q 1) with f = w / det DF, S = sum v and
+        // Q = q . v: a rank-2 update of the identity, f scaled by 1/gamma
+        const double am = A.amp;
         const double sx = geo[0][qx][0], cx = geo[0][qx][1], wx = geo[0][qx][2];
         const double sy = geo[1][qy][0], cy = geo[1][qy][1], wy = geo[1][qy][2];
-        const double sxy = sx * sy, pcs = M_PI * cx * sy, psc = M_PI * sx * cy, wxy = wx * wy;
+        const double pcs = am * M_PI * cx * sy, psc = am * M_PI * sx * cy, pss = am * M_PI * sx * sy;
+        const double wxy = wx * wy;
 #pragma unroll
         for (int qz = 0; qz < T::QZ; ++qz) {
             const int ez = qz / T::NQZ;
             const double sz = geo[2][qz][0], cz = geo[2][qz][1], wz = geo[2][qz][2];
-            const double gx = pcs * sz, gy = psc * sz, gzz = M_PI * sxy * cz;
-            const double f = wxy * wz / fma(am, gx + gy + gzz, 1.0);
-            double g[6];
-            g[0] = f * fma(a3 * gx, gx, fma(2.0 * am, gx, 1.0));
-            g[1] = f * fma(a3 * gy, gy, fma(2.0 * am, gy, 1.0));
-            g[2] = f * fma(a3 * gzz, gzz, fma(2.0 * am, gzz, 1.0));
-            g[3] = f * fma(a3 * gx, gy, am * (gx + gy));
-            g[4] = f * fma(a3 * gx, gzz, am * (gx + gzz));
-            g[5] = f * fma(a3 * gy, gzz, am * (gy + gzz));
+            const double q1 = pcs * sz, q2 = psc * sz, q3 = pss * cz;
+            const double sf = (ig[ez] * (wxy * wz)) * t_recip(1.0 + (q1 + q2 + q3));
             double v0 = 0.0, v1 = 0.0, v2 = 0.0;
 #pragma unroll
             for (int k = 0; k < W0::Kz; ++k) v0 += tz0[qz * TK + k] * a0[ez + k];
@@ -367,10 +372,11 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
             for (int k = 0; k < W1::Kz; ++k) v1 += tz1[qz * TK + k] * a1[ez + k];
 #pragma unroll
             for (int k = 0; k < W2::Kz; ++k) v2 += tz2[qz * TK + k] * a2[ez + k];
-            const double s = ig[ez];
-            const double u0 = s * (g[0] * v0 + g[3] * v1 + g[4] * v2);
-            const double u1 = s * (g[3] * v0 + g[1] * v1 + g[5] * v2);
-            const double u2 = s * (g[4] * v0 + g[5] * v1 + g[2] * v2);
+            const double Qv = fma(q1, v0, fma(q2, v1, q3 * v2));
+            const double cq = sf * fma(3.0, Qv, v0 + v1 + v2), bq = sf * Qv;
+            const double u0 = fma(sf, v0, fma(cq, q1, bq));
+            const double u1 = fma(sf, v1, fma(cq, q2, bq));
+            const double u2 = fma(sf, v2, fma(cq, q3, bq));
 #pragma unroll
             for (int k = 0; k < W0::Kz; ++k) r0[ez + k] += tz0[qz * TK + k] * u0;
 #pragma unroll
