@@ -163,6 +163,44 @@ def test_batched_per_step_energies():
                 assert np.abs(two - ref).max() < 1e-12 * np.abs(ref).max(), (nsteps, k)
 
 
+def test_graph_replays_of_tracked_steps_with_energy_equal_eager():
+    """A captured run of tracked steps with per-step energies (a step's
+    energy summed inside the next step's launch, the last one by a launch of
+    its own) for a batch of two, replayed three times from the same state
+    with eager work in between: fields and energies equal the eager run's
+    bit for bit on every replay."""
+    import torch
+    S, G = make_pair(3, 6, deformed=True, max_batch=2)
+    dt, n = 0.01, 9
+    states = [_state(S, 70 + k) for k in range(2)]
+    E0 = to_dev(np.concatenate([np.concatenate([st[0], st[1]]) for st in states]))
+    H0 = to_dev(np.concatenate([np.concatenate([st[2], st[3]]) for st in states]))
+    E, H = E0.clone(), H0.clone()
+    en = torch.zeros((n, 2), dtype=torch.float64, device="cuda")
+    G.step(E, H, dt, nsteps=n, batch=2, flags=1, energy=en)
+    Eg, Hg = E0.clone(), H0.clone()
+    en_g = torch.full((n, 2), float("nan"), dtype=torch.float64, device="cuda")
+    gr = G.graph(Eg, Hg, dt, n, batch=2, flags=1, energy=en_g)
+    try:
+        for rep in range(3):
+            print(f"\n[case] graph replay {rep}", flush=True)
+            Eg.copy_(E0)
+            Hg.copy_(H0)
+            en_g.fill_(float("nan"))
+            G.set_time(0.0)
+            gr.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(Eg, E) and torch.equal(Hg, H), rep
+            assert torch.equal(en_g, en), rep
+            # eager work on the same space between the replays
+            e2, h2 = E0.clone(), H0.clone()
+            G.step(e2, h2, dt, nsteps=2, batch=2, flags=1,
+                   energy=torch.zeros((2, 2), dtype=torch.float64, device="cuda"))
+            torch.cuda.synchronize()
+    finally:
+        gr.close()
+
+
 def test_run_to_run_bitwise_determinism():
     S, G = make_pair(3, 8, deformed=True)
     e0, _, h0, _ = _state(S, 5)
