@@ -194,7 +194,9 @@ kmx_status kmx_init_stagger(kmx_space* sp, const double* E, double* H, double dt
  * state is advanced by nsteps.  J: NULL or a source of this space (not allowed
  * together with KMX_TRACK_DB).  energy_dev: NULL, or device array of
  * nsteps * batch doubles receiving the leapfrog invariant after every step
- * (requires KMX_TRACK_DB), evaluated as 1/2 (d.w_e + b.w_h - dt w_h.D^1 e)
+ * (requires KMX_TRACK_DB; entry k * batch + m is member m's value after step
+ * k + 1, all written by the call's work on the stream), evaluated as
+ * 1/2 (d.w_e + b.w_h - dt w_h.D^1 e)
  * with w_e = K1 e and w_h = K~1 h formed once per call (one banded pairing
  * apply each) and then updated with the mass applies of the steps (eqs.
  * (3.11), (3.13) on the increments); it equals kmx_energy's first value to
