@@ -163,6 +163,28 @@ def test_batched_per_step_energies():
                 assert np.abs(two - ref).max() < 1e-12 * np.abs(ref).max(), (nsteps, k)
 
 
+@pytest.mark.parametrize("p,N", [(2, 7), (4, 5), (3, 9)])
+def test_per_step_energies_match_oracle_across_degrees(p, N):
+    """Per-step energies of a tracked batch of two against the oracle's, at
+    degrees whose 1- and 2-form components differ in shape (every position
+    of the box of the three 2-form components and the e values around it).
+    The random b and h are not each other's Hodge images, so the series
+    is not constant: it is compared entry by entry."""
+    import torch
+    print(f"\n[case] energies p={p} N={N}", flush=True)
+    S, G = make_pair(p, N, deformed=True, max_batch=2)
+    dt, n = 0.01 / p, 6
+    states = [_state(S, 80 + k) for k in range(2)]
+    E = to_dev(np.concatenate([np.concatenate([st[0], st[1]]) for st in states]))
+    H = to_dev(np.concatenate([np.concatenate([st[2], st[3]]) for st in states]))
+    en = torch.full((n, 2), float("nan"), dtype=torch.float64, device="cuda")
+    G.step(E, H, dt, nsteps=n, batch=2, flags=1, energy=en)
+    en = to_host(en)
+    for k, (e0, d0, h0, b0) in enumerate(states):
+        ref = np.array(S.step(e0, h0, dt, nsteps=n, d=d0, b=b0, energy_every=1)[4])
+        assert np.abs(en[:, k] - ref).max() < 1e-12 * np.abs(ref).max(), k
+
+
 def test_graph_replays_of_tracked_steps_with_energy_equal_eager():
     """A captured run of tracked steps with per-step energies (a step's
     energy summed inside the next step's launch, the last one by a launch of
