@@ -48,6 +48,12 @@ def qp_param_points(p, N):
     return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
 
 
+def relmax(a, b):
+    """The larger of the relative 2-norm error and the element-wise error
+    (max |a - b| over max |b|): a parity bound on both."""
+    return max(rel(a, b), maxrel(a, b))
+
+
 def maxrel(a, b):
     """Element-wise bound: max |a - b| over max |b|."""
     a = np.asarray(a, dtype=float)

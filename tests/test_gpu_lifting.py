@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from _helpers import qp_param_points, rel, to_dev, to_host
+from _helpers import maxrel, qp_param_points, rel, relmax, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +44,7 @@ def test_trace_fit_matches_oracle(p, N):
     eb_ref = S.lift(lambda x: W.tem_coax_E(x, 0.0))
     eb = G.lift_boundary(_face_data(p, N))
     assert eb.size == eb_ref.size
-    assert rel(eb, eb_ref) < 1e-12
+    assert relmax(eb, eb_ref) < 1e-12
     assert np.all(eb[~S.boundary_mask()] == 0)
 
 
@@ -70,9 +70,11 @@ def test_lifted_steps_match_oracle(plan):
     v_h, v_e = S.lifting_vectors(S.lift(lambda x: W.tem_coax_E(x, 0.0)))
     terms = [(v_h, v_e, g)]
     e0, h0 = S.init_lifted(lambda x: W.tem_coax_E(x, 0.0), terms, dt)
-    assert rel(e_start, e0) < 1e-12 and rel(h_start, h0) < 1e-12
+    assert relmax(e_start, e0) < 1e-12 and rel(h_start, h0) < 1e-12 and maxrel(h_start, h0) < 1e-11
     e, h = S.step_lifted(e0, h0, dt, nsteps, terms)
-    assert rel(to_host(E), e) < 1e-12 and rel(to_host(H), h) < 1e-12
+    # h entry by entry at ten times the norm-wise bound (its entries span
+    # many orders of magnitude below max |h|), as the other element-wise bounds
+    assert relmax(to_host(E), e) < 1e-12 and rel(to_host(H), h) < 1e-12 and maxrel(to_host(H), h) < 1e-11
 
 
 def test_lifted_graph_replays_equal_eager_steps():
