@@ -48,8 +48,8 @@ __device__ inline double gather_one(const double* __restrict__ patch, int nt, in
     hy = hy > nt - 1 ? nt - 1 : hy;
     hz = hz > nt - 1 ? nt - 1 : hz;
     // the candidate tiles h - 1 and h per axis, in a fixed order; a candidate
-    // that does not cover the entry is read at a clamped (valid) position and
-    // contributes zero, so the eight reads are issued without branches
+    // that does not cover the entry contributes zero and is not read (the
+    // lanes whose candidate covers it read, the others are masked off)
     bool vx[2], vy[2], vz[2];
     int tx[2], ty[2], tz[2], lx[2], ly[2], lz[2];
 #pragma unroll
@@ -65,7 +65,7 @@ __device__ inline double gather_one(const double* __restrict__ patch, int nt, in
         ly[d] = vy[d] ? ry - ty[d] * TILE : 0;
         lz[d] = vz[d] ? rz - tz[d] * TILE : 0;
     }
-    // the four (z, y) row offsets and the two x offsets, then the eight reads
+    // the four (z, y) row offsets and the two x offsets, then the reads
     int row[4], col[2];
 #pragma unroll
     for (int k = 0; k < 4; ++k) row[k] = patch_row<L>(nt, ty[k & 1], tz[k >> 1], ly[k & 1], lz[k >> 1]);
@@ -73,13 +73,14 @@ __device__ inline double gather_one(const double* __restrict__ patch, int nt, in
     for (int d = 0; d < 2; ++d) col[d] = tx[d] * L::Wx + lx[d];
     double v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = patch[row[k >> 1] + col[k & 1]];
-    double s = 0.0;
-#pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int dz = k >> 2, dy = (k >> 1) & 1, dx = k & 1;
-        s += (vz[dz] && vy[dy] && vx[dx]) ? v[k] : 0.0;
+        v[k] = 0.0;
+        if (vz[dz] && vy[dy] && vx[dx]) v[k] = patch[row[k >> 1] + col[k & 1]];
     }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
     return s;
 }
 

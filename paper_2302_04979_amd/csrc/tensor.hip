@@ -420,8 +420,11 @@ __device__ inline double tt_gather_one(const TGatherArgs& A, const double* patch
         for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
-                const double val = pc[t_patch_at<Wn>(A.nt, t[0][dx], t[1][dy], t[2][dz], w[0][dx], w[1][dy], w[2][dz])];
-                s += (v[2][dz] && v[1][dy] && v[0][dx]) ? val : 0.0;
+                // only the lanes whose candidate covers the entry read it
+                double val = 0.0;
+                if (v[2][dz] && v[1][dy] && v[0][dx])
+                    val = pc[t_patch_at<Wn>(A.nt, t[0][dx], t[1][dy], t[2][dz], w[0][dx], w[1][dy], w[2][dz])];
+                s += val;
             }
     return s;
 }
