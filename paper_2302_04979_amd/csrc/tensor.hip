@@ -216,57 +216,65 @@ __device__ inline void tt_forward_xy(const TMassArgs& A, const double* x, double
     __syncthreads();  // X and AX are reused by the next component
 }
 
-// Integration of component C along y and x: the thread's column R[wz] into
-// LDS, the y pass (sum over the elements of the tile whose window holds wy and
-// their points), the x pass likewise, into the tile's patch.
+// Integration of component C along x and y: the thread's column R[wz] into
+// LDS; a thread per (wz, qy) row integrates it along x against the x table
+// (each Gauss point qx feeds the K_x functions of its element, no masked
+// terms) into XI[wz][wx][qy]; a thread per (wz, wx) column integrates that
+// along y likewise and writes the column of the tile's patch.
 template <int PX, int PY, int PZ, int SPACE, int C, int WZM>
 __device__ inline void tt_backward_xy(const TMassArgs& A, double* patch, double (*tab)[2][TTile<PX, PY, PZ>::QM * TK],
-                                      double* RB, double* BY, const int t3[3], int tid, int qy, int qx, bool active,
+                                      double* RB, double* XI, const int t3[3], int tid, int qy, int qx, bool active,
                                       const double (&col)[WZM]) {
     using Wn = TWin<PX, PY, PZ, SPACE, C>;
     using T = TTile<PX, PY, PZ>;
+    constexpr int XP = T::QY + 1;  // odd pitch of the XI columns
+    static_assert(Wn::Wz * T::QY <= T::NT && Wn::Wz * Wn::Wx <= T::NT, "a thread per row and per column");
     if (active) {
 #pragma unroll
         for (int wz = 0; wz < Wn::Wz; ++wz) RB[(wz * T::QY + qy) * T::QX + qx] = col[wz];
     }
     __syncthreads();
-    const double* ty = tab[1][Wn::sy];
-    for (int i = tid; i < Wn::Wz * Wn::Wy * T::QX; i += T::NT) {
-        const int q = i % T::QX, wy = (i / T::QX) % Wn::Wy, wz = i / (T::QX * Wn::Wy);
-        double s = 0.0;
+    if (tid < Wn::Wz * T::QY) {
+        const double* tx = tab[0][Wn::sx];
+        const int wz = tid / T::QY, y = tid - wz * T::QY;
+        const double* row = RB + (wz * T::QY + y) * T::QX;
+        double r[T::QX];
 #pragma unroll
-        for (int ey = 0; ey < TT; ++ey) {
-            const int k = wy - ey;
-            if (k >= 0 && k < Wn::Ky) {
+        for (int q = 0; q < T::QX; ++q) r[q] = row[q];
+        double c[Wn::Wx];
 #pragma unroll
-                for (int iy = 0; iy < T::NQY; ++iy) {
-                    const int qq = ey * T::NQY + iy;
-                    s += ty[qq * TK + k] * RB[(wz * T::QY + qq) * T::QX + q];
-                }
-            }
+        for (int w = 0; w < Wn::Wx; ++w) c[w] = 0.0;
+#pragma unroll
+        for (int q = 0; q < T::QX; ++q) {
+            const int le = q / T::NQX;
+#pragma unroll
+            for (int k = 0; k < Wn::Kx; ++k) c[le + k] = fma(tx[q * TK + k], r[q], c[le + k]);
         }
-        BY[i] = s;
+#pragma unroll
+        for (int w = 0; w < Wn::Wx; ++w) XI[(wz * Wn::Wx + w) * XP + y] = c[w];
     }
     __syncthreads();
-    const double* tx = tab[0][Wn::sx];
-    double* pc = patch + A.pcomp_off[C];
-    for (int i = tid; i < Wn::size; i += T::NT) {
-        const int wx = i % Wn::Wx, r = i / Wn::Wx;  // r = wz * Wy + wy
-        double s = 0.0;
+    if (tid < Wn::Wz * Wn::Wx) {
+        const double* ty = tab[1][Wn::sy];
+        const int wz = tid / Wn::Wx, wx = tid - wz * Wn::Wx;
+        const double* cl = XI + tid * XP;
+        double cq[T::QY];
 #pragma unroll
-        for (int ex = 0; ex < TT; ++ex) {
-            const int k = wx - ex;
-            if (k >= 0 && k < Wn::Kx) {
+        for (int q = 0; q < T::QY; ++q) cq[q] = cl[q];
+        double o[Wn::Wy];
 #pragma unroll
-                for (int ix = 0; ix < T::NQX; ++ix) {
-                    const int qq = ex * T::NQX + ix;
-                    s += tx[qq * TK + k] * BY[r * T::QX + qq];
-                }
-            }
+        for (int w = 0; w < Wn::Wy; ++w) o[w] = 0.0;
+#pragma unroll
+        for (int q = 0; q < T::QY; ++q) {
+            const int le = q / T::NQY;
+#pragma unroll
+            for (int k = 0; k < Wn::Ky; ++k) o[le + k] = fma(ty[q * TK + k], cq[q], o[le + k]);
         }
-        pc[t_patch_at<Wn>(A.nt, t3[0], t3[1], t3[2], wx, r % Wn::Wy, r / Wn::Wy)] = s;
+        double* pc = patch + A.pcomp_off[C];
+#pragma unroll
+        for (int w = 0; w < Wn::Wy; ++w) pc[t_patch_at<Wn>(A.nt, t3[0], t3[1], t3[2], wx, w, wz)] = o[w];
     }
-    __syncthreads();  // RB and BY are reused by the next component
+    __syncthreads();  // RB and XI are reused by the next component
 }
 
 // One workgroup per tile of TT^3 elements, one thread per (qy, qx) Gauss
@@ -283,11 +291,14 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
     using W2 = TWin<PX, PY, PZ, SPACE, 2>;
     constexpr int WSZ = t_max3(W0::size, W1::size, W2::size);
     constexpr int WZM = t_max3(W0::Wz, W1::Wz, W2::Wz);
-    constexpr int AXN = t_max3(W0::Wz * W0::Wy, W1::Wz * W1::Wy, W2::Wz * W2::Wy) * T::QX;
+    // x passes (forward) and the x integrals XI[wz][wx][qy] (backward, pitch QY + 1)
+    constexpr int AXF = t_max3(W0::Wz * W0::Wy, W1::Wz * W1::Wy, W2::Wz * W2::Wy) * T::QX;
+    constexpr int AXB = t_max3(W0::Wz * W0::Wx, W1::Wz * W1::Wx, W2::Wz * W2::Wx) * (T::QY + 1);
+    constexpr int AXN = AXF > AXB ? AXF : AXB;
     constexpr int RBN = WZM * T::QY * T::QX;
     __shared__ double tab[3][2][T::QM * TK];
     __shared__ double X[WSZ];
-    __shared__ double AX[AXN];   // x pass (forward), y pass (backward)
+    __shared__ double AX[AXN];   // x pass (forward), x integrals (backward)
     __shared__ double RB[RBN];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
