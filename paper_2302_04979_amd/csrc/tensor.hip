@@ -228,16 +228,17 @@ __device__ inline void tt_backward_xy(const TMassArgs& A, double* patch, double 
     using Wn = TWin<PX, PY, PZ, SPACE, C>;
     using T = TTile<PX, PY, PZ>;
     constexpr int XP = T::QY + 1;  // odd pitch of the XI columns
+    constexpr int RP = T::QX + 1;  // odd pitch of the RB rows (the x integration reads one row per lane)
     static_assert(Wn::Wz * T::QY <= T::NT && Wn::Wz * Wn::Wx <= T::NT, "a thread per row and per column");
     if (active) {
 #pragma unroll
-        for (int wz = 0; wz < Wn::Wz; ++wz) RB[(wz * T::QY + qy) * T::QX + qx] = col[wz];
+        for (int wz = 0; wz < Wn::Wz; ++wz) RB[(wz * T::QY + qy) * RP + qx] = col[wz];
     }
     __syncthreads();
     if (tid < Wn::Wz * T::QY) {
         const double* tx = tab[0][Wn::sx];
         const int wz = tid / T::QY, y = tid - wz * T::QY;
-        const double* row = RB + (wz * T::QY + y) * T::QX;
+        const double* row = RB + (wz * T::QY + y) * RP;
         double r[T::QX];
 #pragma unroll
         for (int q = 0; q < T::QX; ++q) r[q] = row[q];
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(tt_threads(PX, PY)) ttile_mass_kernel(const TM
     constexpr int AXF = t_max3(W0::Wz * W0::Wy, W1::Wz * W1::Wy, W2::Wz * W2::Wy) * T::QX;
     constexpr int AXB = t_max3(W0::Wz * W0::Wx, W1::Wz * W1::Wx, W2::Wz * W2::Wx) * (T::QY + 1);
     constexpr int AXN = AXF > AXB ? AXF : AXB;
-    constexpr int RBN = WZM * T::QY * T::QX;
+    constexpr int RBN = WZM * T::QY * (T::QX + 1);
     __shared__ double tab[3][2][T::QM * TK];
     __shared__ double X[WSZ];
     __shared__ double AX[AXN];   // x pass (forward), x integrals (backward)
